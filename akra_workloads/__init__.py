@@ -1,0 +1,238 @@
+"""Seeded synthetic inputs shaped like the paper's DES Y3 workload (Sec. III).
+
+These stand in for the DES Y3 shear catalog, which is not available: every
+input is drawn from a seeded numpy generator with the shapes, sizes and value
+distributions of the five benchmark configurations.  The module holds none of
+the method's arithmetic (no harmonic transform, no kernel, no operator):
+callers turn the convergence coefficients it returns into shear with their own
+synthesis.  It serves both the oracle and the HIP path.
+
+Per-pixel quantities follow the paper's pixelisation (Sec. III.B):
+  counts n_p ~ Poisson(mu_p) stand in for N_eff (eq. Neff_pixel),
+  N^-1_p = n_p / sigma_e^2 with sigma_e = 0.26 (eq. noise_var),
+  M_p = footprint_p and n_p >= 1 (eq. mask with N_th in (0, 1]),
+  per-component shape noise eps ~ N(0, sigma_e^2 / n_p).
+Footprint: union of 3 spherical caps in a DES-like southern area, the common
+radius bisected to f_sky, minus small circular holes of radius 2'-10'.
+"""
+import math
+
+import numpy as np
+
+SIGMA_E = 0.26
+
+# name -> parameters (sizes and distributions of the benchmark configurations)
+CONFIGS = {
+    # plain FP64 CG, one cap with f_sky = 0.1, Poisson mean 5
+    "C1": dict(nside=32, lmax=64, mask="cap", fsky=0.1, mu=5.0, amp=[1e-7], nrhs=1, holes=0),
+    # mixed precision vs FP64: 3-cap footprint minus 200 holes, Poisson mean 3
+    "C2": dict(nside=512, lmax=1024, mask="footprint", fsky=0.1, mu=3.0, amp=[1e-7], nrhs=1, holes=200),
+    # headline single RHS: 2000 holes, mean 2 with a smooth x U[0.5,1.5] depth modulation
+    "C3": dict(nside=2048, lmax=4096, mask="footprint", fsky=0.1, mu=2.0, amp=[1e-7], nrhs=1, holes=2000,
+               depth=True),
+    # batched: 4 tomographic bins x (1 signal + 3 noise realisations) = 16 RHS, shared footprint
+    "C4": dict(nside=1024, lmax=2048, mask="footprint", fsky=0.1, mu=15.34, amp=[0.5e-7, 1e-7, 1.5e-7, 2e-7],
+               nrhs=16, holes=2000),
+    # differentiable solve
+    "C5": dict(nside=256, lmax=512, mask="footprint", fsky=0.1, mu=5.0, amp=[1e-7], nrhs=1, holes=200),
+}
+_CFG_NUM = {"C1": 1, "C2": 2, "C3": 3, "C4": 4, "C5": 5}
+
+# random-stream ids inside one configuration
+S_KAPPA, S_FOOT, S_COUNTS, S_NOISE, S_DEPTH, S_ROT = 1, 2, 3, 4, 5, 6
+
+
+def rng(seed_base, stream):
+    return np.random.default_rng(1000 * int(seed_base) + int(stream))
+
+
+# ---------------------------------------------------------------------------------------------
+# pixel centres (HEALPix RING order) -- used only to place caps and holes
+# ---------------------------------------------------------------------------------------------
+def ring_layout(nside):
+    """Per ring: z, pixel count, phi0, first pixel."""
+    nside = int(nside)
+    zs, ns, p0, ofs = [], [], [], []
+    o = 0
+    for i in range(1, 4 * nside):
+        if i < nside:
+            z, n, ph = 1 - i * i / (3.0 * nside * nside), 4 * i, math.pi / (4 * i)
+        elif i <= 3 * nside:
+            z, n = 4.0 / 3.0 - 2.0 * i / (3.0 * nside), 4 * nside
+            ph = math.pi / (4 * nside) * ((i - nside + 1) % 2)
+        else:
+            ii = 4 * nside - i
+            z, n, ph = -(1 - ii * ii / (3.0 * nside * nside)), 4 * ii, math.pi / (4 * ii)
+        zs.append(z); ns.append(n); p0.append(ph); ofs.append(o)
+        o += n
+    return np.array(zs), np.array(ns, np.int64), np.array(p0), np.array(ofs, np.int64)
+
+
+def pixel_vectors(nside):
+    """Unit vectors of all pixel centres, shape (3, Npix), RING order."""
+    zs, ns, p0, ofs = ring_layout(nside)
+    npix = int(ns.sum())
+    z = np.repeat(zs, ns)
+    ring = np.repeat(np.arange(len(ns)), ns)
+    j = np.arange(npix) - ofs[ring]
+    phi = p0[ring] + 2 * np.pi * j / ns[ring]
+    s = np.sqrt(np.maximum(0.0, 1 - z * z))
+    return np.stack([s * np.cos(phi), s * np.sin(phi), z])
+
+
+def _unit(theta, phi):
+    return np.array([math.sin(theta) * math.cos(phi), math.sin(theta) * math.sin(phi), math.cos(theta)])
+
+
+def cap_mask(nside, centre_theta, centre_phi, fsky, vec=None):
+    """Boolean mask of one spherical cap covering the fraction fsky (cos rho = 1 - 2 fsky)."""
+    vec = pixel_vectors(nside) if vec is None else vec
+    c = _unit(centre_theta, centre_phi)
+    return (c @ vec) >= 1.0 - 2.0 * fsky
+
+
+def footprint(nside, fsky, nholes, seed_base, vec=None):
+    """Union of 3 caps (centres in theta in [95, 130] deg, phi in [0, 90] deg) with the common
+    radius bisected so that the union covers fsky, minus nholes holes of radius U[2', 10']
+    centred uniformly inside the union.  A pixel is inside when its centre is."""
+    g = rng(seed_base, S_FOOT)
+    vec = pixel_vectors(nside) if vec is None else vec
+    th = np.radians(g.uniform(95.0, 130.0, 3))
+    ph = np.radians(g.uniform(0.0, 90.0, 3))
+    dots = np.stack([_unit(t, p) @ vec for t, p in zip(th, ph)])
+    best = dots.max(axis=0)                      # union covers cos(angle) >= cos(rho)
+    lo, hi = -1.0, 1.0                            # bisection on cos(rho)
+    for _ in range(60):
+        mid = 0.5 * (lo + hi)
+        if np.mean(best >= mid) > fsky:
+            lo = mid
+        else:
+            hi = mid
+    mask = best >= hi
+    if nholes:
+        inside = np.flatnonzero(mask)
+        centres = inside[g.integers(0, len(inside), nholes)]
+        radii = np.radians(g.uniform(2.0, 10.0, nholes) / 60.0)
+        _punch_holes(nside, mask, vec, centres, radii)
+    return mask
+
+
+def _punch_holes(nside, mask, vec, centres, radii):
+    zs, ns, p0, ofs = ring_layout(nside)
+    th_r = np.arccos(np.clip(zs, -1, 1))
+    for cpix, rad in zip(centres, radii):
+        c = vec[:, cpix]
+        tc = math.acos(max(-1.0, min(1.0, c[2])))
+        rings = np.flatnonzero(np.abs(th_r - tc) <= rad + 2.0 / nside)
+        if len(rings) == 0:
+            continue
+        lo, hi = int(ofs[rings[0]]), int(ofs[rings[-1]] + ns[rings[-1]])
+        sub = c @ vec[:, lo:hi] >= math.cos(rad)
+        mask[lo:hi] &= ~sub
+
+
+def depth_modulation(nside, seed_base, vec=None, nwaves=64, kscale=20.0):
+    """Smooth multiplicative depth u_p = 0.5 + Phi(g_p) in [0.5, 1.5]; g is a unit-variance smooth
+    field made of random plane waves exp(i k.n) with |k| ~ kscale evaluated on the sphere."""
+    g = rng(seed_base, S_DEPTH)
+    vec = pixel_vectors(nside) if vec is None else vec
+    k = g.normal(size=(nwaves, 3))
+    k *= (kscale * g.uniform(0.5, 1.0, nwaves) / np.linalg.norm(k, axis=1))[:, None]
+    phase = g.uniform(0, 2 * np.pi, nwaves)
+    field = np.zeros(vec.shape[1])
+    for i in range(nwaves):
+        field += np.cos(k[i] @ vec + phase[i])
+    field = (field - field.mean()) / field.std()
+    from scipy.special import ndtr
+    return 0.5 + ndtr(field)
+
+
+# ---------------------------------------------------------------------------------------------
+# harmonic-space draws
+# ---------------------------------------------------------------------------------------------
+def alm_size(lmax):
+    return (lmax + 1) * (lmax + 2) // 2
+
+
+def _l_of(lmax):
+    return np.concatenate([np.arange(m, lmax + 1) for m in range(lmax + 1)])
+
+
+def cl_kappa(lmax, amp=1e-7):
+    """C_l = amp (l + 10)^-1.2 for l >= 2, zero below."""
+    l = np.arange(lmax + 1, dtype=np.float64)
+    cl = amp * (l + 10.0) ** -1.2
+    cl[:2] = 0.0
+    return cl
+
+
+def gaussian_alm(lmax, cl, g):
+    """Real-field Gaussian coefficients (m >= 0 healpy order): a_l0 ~ N(0, C_l); Re, Im ~ N(0, C_l/2)."""
+    l = _l_of(lmax)
+    n = alm_size(lmax)
+    sd = np.sqrt(np.asarray(cl)[l])
+    re = g.normal(size=n)
+    im = g.normal(size=n)
+    a = sd * (re + 1j * im) / math.sqrt(2.0)
+    a[: lmax + 1] = sd[: lmax + 1] * re[: lmax + 1]
+    return a
+
+
+def random_alm(lmax, seed, lmin=2):
+    """Unit-variance random coefficients for operator tests (zero below lmin, Im(a_l0) = 0)."""
+    g = np.random.default_rng(seed)
+    n = alm_size(lmax)
+    a = g.normal(size=n) + 1j * g.normal(size=n)
+    a[: lmax + 1] = a[: lmax + 1].real
+    a[_l_of(lmax) < lmin] = 0
+    return a
+
+
+def random_maps(npix, seed):
+    g = np.random.default_rng(seed)
+    return g.normal(size=npix), g.normal(size=npix)
+
+
+# ---------------------------------------------------------------------------------------------
+# configurations
+# ---------------------------------------------------------------------------------------------
+def make_config(name, nside=None, lmax=None):
+    """Inputs of one benchmark configuration (optionally at other sizes, same distributions).
+
+    Returns dict with: nside, lmax, nrhs, mask (uint8, Npix), ninv (float64, (nrhs_bins, Npix)),
+    kappa (complex128, (nrhs, nalm)) -- E-mode convergence coefficients, B = 0 --,
+    eps1/eps2 (float64, (nrhs, Npix)) -- shape noise, zero outside the mask --, and bin (int per RHS).
+    The observed shear is gamma_obs = M (Y(K kappa) + eps); callers apply Y and K themselves."""
+    p = dict(CONFIGS[name])
+    c = _CFG_NUM[name]
+    nside = int(nside or p["nside"])
+    lmax = int(lmax or p["lmax"])
+    vec = pixel_vectors(nside)
+    npix = vec.shape[1]
+    if p["mask"] == "cap":
+        foot = cap_mask(nside, math.radians(60.0), math.radians(45.0), p["fsky"], vec)
+    else:
+        foot = footprint(nside, p["fsky"], p["holes"], c, vec)
+    mu = np.full(npix, p["mu"])
+    if p.get("depth"):
+        mu = mu * depth_modulation(nside, c, vec)
+    nb = len(p["amp"])
+    nrhs = p["nrhs"]
+    gc = rng(c, S_COUNTS)
+    counts = np.stack([gc.poisson(mu) for _ in range(nb)])
+    mask = (foot[None, :] & (counts >= 1)).all(axis=0) if nb > 1 else (foot & (counts[0] >= 1))
+    ninv = counts / SIGMA_E ** 2
+    gk = rng(c, S_KAPPA)
+    kap = [gaussian_alm(lmax, cl_kappa(lmax, a), gk) for a in p["amp"]]
+    gn = rng(c, S_NOISE)
+    per_bin = nrhs // nb
+    kappa, e1, e2, bins = [], [], [], []
+    for k in range(nrhs):
+        b = k // per_bin
+        sd = np.where(counts[b] > 0, SIGMA_E / np.sqrt(np.maximum(counts[b], 1)), 0.0)
+        kappa.append(kap[b])
+        e1.append(sd * gn.normal(size=npix) * mask)
+        e2.append(sd * gn.normal(size=npix) * mask)
+        bins.append(b)
+    return dict(name=name, nside=nside, lmax=lmax, nrhs=nrhs, mask=mask.astype(np.uint8), ninv=ninv,
+                kappa=np.stack(kappa), eps1=np.stack(e1), eps2=np.stack(e2), bin=np.array(bins))
