@@ -1,0 +1,154 @@
+/*
+ * akra.h -- C ABI of libakra: the matrix-free normal-equation operator of AKRA 3.0
+ * (Shi, Zhang, Cui, Qin, Yao) on an AMD Instinct MI355X (gfx950).
+ *
+ * The method (paper Sec. II.B, "AKRA 3.0: matrix-free inversion framework"):
+ *   convergence harmonics x = (kappa_E, kappa_B)  --  joint E/B unknowns, App. A eq. joint_forward
+ *   A = Y o K : harmonic diagonal K_l = sigma_D D_l (eq. Dl_kernel), then the inverse spin-2
+ *               transform Y to shear gamma = gamma_1 + i gamma_2 at HEALPix RING pixel centres
+ *               (shear expansion eq. shear_SH with 2a = -(a_E + i a_B), eq. EB_decomp)
+ *   N^-1, M  : per-pixel inverse noise and binary mask, folded once into W_p = M_p N^-1_p
+ *              (pixel-space diagonal of the storage problem; eq. noise_var, eq. mask)
+ *   H v = K Y^H ( W (Y (K v)) ) + lambda_eff v                  (eq. normal_eq, eq. ML_estimator_reg)
+ *   b   = K Y^H ( W gamma_obs )
+ *   solved by preconditioned conjugate gradient with P = (<M^2 N^-1> + lambda_eff)^-1 I
+ *   (eq. precond), x0 = 0 by default, stopping at ||r_k|| / ||b|| < tol (Sec. III.C).
+ * Y^H is the exact adjoint of Y for the pixel product <g,h> = sum_p Omega Re(conj(g_p) h_p),
+ * Omega = 4 pi / Npix, and the full-m harmonic product
+ *   <a,b> = sum_l [ Re(a_l0* b_l0) + 2 sum_{m>0} Re(a_lm* b_lm) ].
+ * lambda_eff = lambda <N^-1>_M (mean of N^-1 over unmasked pixels), lambda = 1e-3 by default.
+ *
+ * Data layout (all arrays are DEVICE pointers owned by the caller unless stated):
+ *   alm   complex128 interleaved (re, im), m >= 0 only, index i(l,m) = m (2 lmax + 1 - m)/2 + l,
+ *         n_alm = (lmax+1)(lmax+2)/2 entries per field.  A real field has a_{l,-m} = (-1)^m conj(a_lm).
+ *         On input, entries with l < 2 are ignored by Y and Im(a_l0) is ignored everywhere;
+ *         on output Im(a_l0) = 0 and Y^H / b have zero entries at l < 2.
+ *   maps  float64 [Npix] in HEALPix RING order, Npix = 12 nside^2 (gamma_1 and gamma_2 separate).
+ *   ninv  float64 [Npix] (>= 0, finite), mask uint8 [Npix] (0 = masked, nonzero = observed).
+ *   Batched plans (nrhs > 1): alm, maps and ninv carry a leading [nrhs] dimension, contiguous;
+ *   the mask is shared by all right-hand sides.
+ *
+ * Streams and ownership: every call is ordered on the plan's HIP stream.  The plan owns all
+ * tables and scratch; calls allocate no device memory after akra_plan_create, except that
+ * akra_cg_solve* allocate nothing either (all solver vectors live in the plan).  Outputs must
+ * not alias inputs, except x in akra_cg_solve*, which is both the start vector (opts->use_x0)
+ * and the result.  Calls on one plan must not overlap from several host threads.
+ *
+ * Errors: every call returns an akra_status; nothing throws across the ABI and nothing aborts.
+ * akra_last_error() returns a thread-local message for the last failing call on this thread.
+ */
+#ifndef AKRA_H
+#define AKRA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct akra_plan_s *akra_plan;
+
+typedef enum {
+    AKRA_OK = 0,
+    AKRA_ERR_ARG = 1,        /* invalid argument (sizes, null pointers, negative weights)        */
+    AKRA_ERR_ALLOC = 2,      /* device or host allocation failed                                 */
+    AKRA_ERR_HIP = 3,        /* a HIP runtime call or kernel launch failed                        */
+    AKRA_ERR_NUMERIC = 4,    /* NaN/Inf in the inputs, or CG breakdown (p^T H p <= 0)             */
+    AKRA_NOT_CONVERGED = 5   /* maxiter reached; x holds the last iterate                         */
+} akra_status;
+
+typedef enum {
+    AKRA_FP64 = 0,           /* transforms in FP64                                                */
+    AKRA_FP32 = 1            /* transforms in FP32 (recurrence seeds and rescaling in FP64);      */
+                             /* solves refine in FP64 to the requested tolerance                  */
+} akra_precision;
+
+typedef struct {
+    double lambda;           /* regulariser lambda (default 1e-3, Sec. II.B)                      */
+    double tol;              /* ||r|| / ||b|| target (default 1e-3, Sec. III.C)                  */
+    int maxiter;             /* iteration cap (default 1000)                                      */
+    int use_x0;              /* nonzero: x holds the start vector on entry (default 0: x0 = 0)   */
+    const double *kernel_l;  /* HOST array [lmax+1]: harmonic kernel K_l; NULL = sigma_D D_l     */
+                             /* with sigma_D = -1 (eq. Dl_kernel)                                  */
+    double reliable_delta;   /* FP32 plans: replace the residual by the FP64 true residual once  */
+                             /* ||r|| drops by this factor (default 0.1)                         */
+    double *resid_hist;      /* HOST, optional: relative residual after each iteration           */
+    int resid_hist_len;
+} akra_cg_opts;
+
+typedef struct {
+    int iters;               /* CG iterations (operator applies in the iteration's precision)    */
+    int fp64_applies;        /* FP64 applies used for true residuals (FP32 plans)                */
+    double rel_resid;        /* last recursive ||r|| / ||b||                                      */
+    double rel_resid_true;   /* ||b - H x|| / ||b|| recomputed in FP64 at exit                    */
+    double lambda_eff;       /* lambda <N^-1>_M actually used                                     */
+    double precond;          /* scalar P actually used                                            */
+    double ms_total;         /* wall time of the call                                             */
+    int status;              /* akra_status of the solve                                          */
+} akra_cg_info;
+
+/* Default options (lambda 1e-3, tol 1e-3, maxiter 1000, x0 = 0, kernel sigma_D D_l). */
+void akra_cg_opts_default(akra_cg_opts *opts);
+
+/*
+ * Create a plan for HEALPix nside with band limit lmax (2 <= lmax <= 4 nside, nside <= 2048 for FP64
+ * plans, 1 <= nrhs <= 64), on the HIP stream `hip_stream` (hipStream_t, NULL = default stream) of the
+ * current device.  Builds the ring geometry, the Wigner-d recurrence tables and per-(m, ring) seeds
+ * (scaled-exponent FP64), FFT twiddles and all workspaces.  Errors: AKRA_ERR_ARG, AKRA_ERR_ALLOC,
+ * AKRA_ERR_HIP.  The plan is released with akra_plan_destroy.
+ */
+akra_status akra_plan_create(int nside, int lmax, int nrhs, int precision, void *hip_stream, akra_plan *out);
+void akra_plan_destroy(akra_plan plan);
+const char *akra_last_error(void);
+
+/* Device bytes held by the plan (tables + workspaces). */
+int64_t akra_plan_device_bytes(akra_plan plan);
+
+/*
+ * Y: spin-2 synthesis (shear expansion eq. shear_SH, eq. EB_decomp), no harmonic kernel:
+ *   g1 + i g2 = sum_{l>=2} sum_{m=-l..l} 2a_lm 2Y_lm(pixel centre),  2a_lm = -(almE_lm + i almB_lm).
+ * In: almE, almB (alm layout).  Out: g1, g2 (maps).
+ */
+akra_status akra_synth2(akra_plan plan, const double *almE, const double *almB, double *g1, double *g2);
+
+/*
+ * Y^H: exact adjoint of akra_synth2 (pixel product with Omega = 4 pi/Npix, full-m harmonic product):
+ *   2h_lm = sum_p Omega conj(2Y_lm(p)) h_p,  -2h_lm = sum_p Omega conj(-2Y_lm(p)) conj(h_p),
+ *   almE = -(2h + -2h)/2,  almB = (i/2)(2h - -2h)   (eq. EB_decomp), h = g1 + i g2.
+ * In: g1, g2 (maps).  Out: almE, almB (alm layout).
+ */
+akra_status akra_adjoint2(akra_plan plan, const double *g1, const double *g2, double *almE, double *almB);
+
+/*
+ * H v = K Y^H (W (Y (K v))) + lambda_eff v with W_p = mask_p * ninv_p (eq. normal_eq; the operator
+ * chain diagonal -> SHT^-1 -> diagonal -> SHT of the storage problem).  kernel_l: HOST [lmax+1] or
+ * NULL (sigma_D D_l).  lambda_eff is used as given.  In: ninv, mask, xE, xB.  Out: yE, yB.
+ * Errors: AKRA_ERR_NUMERIC when ninv holds NaN/Inf, AKRA_ERR_ARG when a weight is negative.
+ */
+akra_status akra_apply_H(akra_plan plan, const double *ninv, const uint8_t *mask, const double *kernel_l,
+                         double lambda_eff, const double *xE, const double *xB, double *yE, double *yB);
+
+/* b = K Y^H (W gamma_obs) (right-hand side of eq. normal_eq).  In: g1, g2, ninv, mask.  Out: bE, bB. */
+akra_status akra_rhs(akra_plan plan, const double *g1, const double *g2, const double *ninv, const uint8_t *mask,
+                     const double *kernel_l, double *bE, double *bB);
+
+/*
+ * Regularised ML estimate x = (H)^-1 b for the shear maps g1, g2 (eq. ML_estimator_reg) by PCG
+ * (Sec. II.B inversion problem).  FP64 plans iterate in FP64; FP32 plans iterate with the FP32
+ * operator and replace the residual by the FP64 true residual b - H x whenever it has dropped by
+ * opts->reliable_delta (reliable updates), so the result meets tol in FP64.
+ * Out: xE, xB (alm layout), info (HOST, may be NULL).  Returns AKRA_NOT_CONVERGED (x valid) at maxiter,
+ * AKRA_ERR_NUMERIC on breakdown.  ||b|| = 0 gives x = 0 after 0 iterations.
+ */
+akra_status akra_cg_solve(akra_plan plan, const double *g1, const double *g2, const double *ninv,
+                          const uint8_t *mask, const akra_cg_opts *opts, double *xE, double *xB, akra_cg_info *info);
+
+/* As akra_cg_solve for a given right-hand side (bE, bB) in alm layout (used by the adjoint solve of the
+ * differentiable form). */
+akra_status akra_cg_solve_b(akra_plan plan, const double *ninv, const uint8_t *mask, const double *bE,
+                            const double *bB, const akra_cg_opts *opts, double *xE, double *xB, akra_cg_info *info);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AKRA_H */

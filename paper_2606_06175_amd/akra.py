@@ -1,0 +1,248 @@
+"""ctypes binding of libakra (include/akra.h) on torch device tensors.
+
+Argument marshalling only: every step of the operator and the solver runs in libakra's HIP
+kernels.  There is no fallback: without the built library every call raises.
+
+Tensors: alm are complex128 with n_alm = (lmax+1)(lmax+2)/2 entries (m >= 0, healpy order)
+and an optional leading [nrhs] dimension; maps are float64 [.., Npix] in HEALPix RING order;
+the mask is uint8 [Npix].  Calls run on the plan's HIP stream, which defaults to torch's
+current stream, so they are ordered with surrounding torch work.
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libakra.so")
+_lib = None
+
+AKRA_OK, AKRA_ERR_ARG, AKRA_ERR_ALLOC, AKRA_ERR_HIP, AKRA_ERR_NUMERIC, AKRA_NOT_CONVERGED = range(6)
+STATUS_NAMES = {0: "AKRA_OK", 1: "AKRA_ERR_ARG", 2: "AKRA_ERR_ALLOC", 3: "AKRA_ERR_HIP", 4: "AKRA_ERR_NUMERIC",
+                5: "AKRA_NOT_CONVERGED"}
+PRECISIONS = {"fp64": 0, "fp32": 1}
+
+
+class AkraError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), msg))
+        self.status = status
+
+
+class CgOpts(ctypes.Structure):
+    _fields_ = [("lambda_", ctypes.c_double), ("tol", ctypes.c_double), ("maxiter", ctypes.c_int),
+                ("use_x0", ctypes.c_int), ("kernel_l", ctypes.POINTER(ctypes.c_double)),
+                ("reliable_delta", ctypes.c_double), ("resid_hist", ctypes.POINTER(ctypes.c_double)),
+                ("resid_hist_len", ctypes.c_int)]
+
+
+class CgInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("fp64_applies", ctypes.c_int), ("rel_resid", ctypes.c_double),
+                ("rel_resid_true", ctypes.c_double), ("lambda_eff", ctypes.c_double), ("precond", ctypes.c_double),
+                ("ms_total", ctypes.c_double), ("status", ctypes.c_int)]
+
+
+def lib():
+    """Load libakra.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libakra.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+    L = ctypes.CDLL(LIB_PATH)
+    vp, dp, i64 = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int64
+    L.akra_plan_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, ctypes.POINTER(vp)]
+    L.akra_plan_destroy.argtypes = [vp]
+    L.akra_plan_destroy.restype = None
+    L.akra_last_error.restype = ctypes.c_char_p
+    L.akra_plan_device_bytes.argtypes = [vp]
+    L.akra_plan_device_bytes.restype = i64
+    L.akra_cg_opts_default.argtypes = [ctypes.POINTER(CgOpts)]
+    L.akra_cg_opts_default.restype = None
+    L.akra_synth2.argtypes = [vp, vp, vp, vp, vp]
+    L.akra_adjoint2.argtypes = [vp, vp, vp, vp, vp]
+    L.akra_apply_H.argtypes = [vp, vp, vp, dp, ctypes.c_double, vp, vp, vp, vp]
+    L.akra_rhs.argtypes = [vp, vp, vp, vp, vp, dp, vp, vp]
+    L.akra_cg_solve.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(CgOpts), vp, vp, ctypes.POINTER(CgInfo)]
+    L.akra_cg_solve_b.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(CgOpts), vp, vp, ctypes.POINTER(CgInfo)]
+    for f in ("akra_plan_create", "akra_synth2", "akra_adjoint2", "akra_apply_H", "akra_rhs", "akra_cg_solve",
+              "akra_cg_solve_b"):
+        getattr(L, f).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(st):
+    if st != AKRA_OK:
+        raise AkraError(st, lib().akra_last_error().decode())
+
+
+def alm_size(lmax):
+    return (lmax + 1) * (lmax + 2) // 2
+
+
+def _kernel_arg(kernel):
+    if kernel is None:
+        return None, None
+    import numpy as np
+    k = np.ascontiguousarray(kernel, dtype=np.float64)
+    return k, k.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+class Plan:
+    """A libakra plan: HEALPix nside, band limit lmax, nrhs right-hand sides, FP64 or FP32 transforms."""
+
+    def __init__(self, nside, lmax, nrhs=1, precision="fp64", device=None, stream=None):
+        L = lib()
+        self.nside, self.lmax, self.nrhs = int(nside), int(lmax), int(nrhs)
+        self.precision = precision
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        if self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        self.npix = 12 * self.nside * self.nside
+        self.nalm = alm_size(self.lmax)
+        with torch.cuda.device(self.device):
+            s = stream if stream is not None else torch.cuda.current_stream(self.device)
+            self.stream = s
+            h = ctypes.c_void_p()
+            _check(L.akra_plan_create(self.nside, self.lmax, self.nrhs, PRECISIONS[precision],
+                                      ctypes.c_void_p(s.cuda_stream), ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().akra_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def device_bytes(self):
+        return lib().akra_plan_device_bytes(self._h)
+
+    # -- helpers ------------------------------------------------------------------------------
+    def _alm(self, a, name):
+        if a.dtype != torch.complex128 or a.device != self.device:
+            raise TypeError("%s must be complex128 on %s" % (name, self.device))
+        if a.shape[-1] != self.nalm or a.numel() != self.nrhs * self.nalm:
+            raise ValueError("%s must hold nrhs x n_alm = %d x %d entries" % (name, self.nrhs, self.nalm))
+        return a.contiguous()
+
+    def _map(self, g, name, dtype=torch.float64, per_rhs=True):
+        if g.dtype != dtype or g.device != self.device:
+            raise TypeError("%s must be %s on %s" % (name, dtype, self.device))
+        n = (self.nrhs if per_rhs else 1) * self.npix
+        if g.numel() != n:
+            raise ValueError("%s must hold %d entries" % (name, n))
+        return g.contiguous()
+
+    def _alm_out(self):
+        shape = (self.nalm,) if self.nrhs == 1 else (self.nrhs, self.nalm)
+        return torch.empty(shape, dtype=torch.complex128, device=self.device)
+
+    def _map_out(self):
+        shape = (self.npix,) if self.nrhs == 1 else (self.nrhs, self.npix)
+        return torch.empty(shape, dtype=torch.float64, device=self.device)
+
+    # -- operator -----------------------------------------------------------------------------
+    def synth2(self, almE, almB):
+        almE, almB = self._alm(almE, "almE"), self._alm(almB, "almB")
+        g1, g2 = self._map_out(), self._map_out()
+        with torch.cuda.device(self.device):
+            _check(lib().akra_synth2(self._h, almE.data_ptr(), almB.data_ptr(), g1.data_ptr(), g2.data_ptr()))
+        return g1, g2
+
+    def adjoint2(self, g1, g2):
+        g1, g2 = self._map(g1, "g1"), self._map(g2, "g2")
+        aE, aB = self._alm_out(), self._alm_out()
+        with torch.cuda.device(self.device):
+            _check(lib().akra_adjoint2(self._h, g1.data_ptr(), g2.data_ptr(), aE.data_ptr(), aB.data_ptr()))
+        return aE, aB
+
+    def apply_H(self, ninv, mask, xE, xB, lambda_eff, kernel=None):
+        ninv = self._map(ninv, "ninv")
+        mask = self._map(mask, "mask", torch.uint8, per_rhs=False)
+        xE, xB = self._alm(xE, "xE"), self._alm(xB, "xB")
+        yE, yB = self._alm_out(), self._alm_out()
+        keep, kp = _kernel_arg(kernel)
+        with torch.cuda.device(self.device):
+            _check(lib().akra_apply_H(self._h, ninv.data_ptr(), mask.data_ptr(), kp, float(lambda_eff),
+                                      xE.data_ptr(), xB.data_ptr(), yE.data_ptr(), yB.data_ptr()))
+        return yE, yB
+
+    def rhs(self, g1, g2, ninv, mask, kernel=None):
+        g1, g2 = self._map(g1, "g1"), self._map(g2, "g2")
+        ninv = self._map(ninv, "ninv")
+        mask = self._map(mask, "mask", torch.uint8, per_rhs=False)
+        bE, bB = self._alm_out(), self._alm_out()
+        keep, kp = _kernel_arg(kernel)
+        with torch.cuda.device(self.device):
+            _check(lib().akra_rhs(self._h, g1.data_ptr(), g2.data_ptr(), ninv.data_ptr(), mask.data_ptr(), kp,
+                                  bE.data_ptr(), bB.data_ptr()))
+        return bE, bB
+
+    def _opts(self, tol, maxiter, lam, x0, kernel, reliable_delta, hist_len):
+        o = CgOpts()
+        lib().akra_cg_opts_default(ctypes.byref(o))
+        o.lambda_, o.tol, o.maxiter = float(lam), float(tol), int(maxiter)
+        o.use_x0 = 1 if x0 is not None else 0
+        o.reliable_delta = float(reliable_delta)
+        keep = []
+        if kernel is not None:
+            k, kp = _kernel_arg(kernel)
+            keep.append(k)
+            o.kernel_l = kp
+        if hist_len:
+            import numpy as np
+            h = np.zeros(hist_len)
+            keep.append(h)
+            o.resid_hist = h.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            o.resid_hist_len = hist_len
+        return o, keep
+
+    @staticmethod
+    def _info(inf, keep, hist_len):
+        d = {k: getattr(inf, k) for k, _ in CgInfo._fields_}
+        if hist_len:
+            d["hist"] = keep[-1][: inf.iters].copy()
+        return d
+
+    def cg_solve(self, g1, g2, ninv, mask, tol=1e-3, maxiter=1000, lam=1e-3, x0=None, kernel=None,
+                 reliable_delta=0.1, hist_len=0, raise_not_converged=True):
+        g1, g2 = self._map(g1, "g1"), self._map(g2, "g2")
+        ninv = self._map(ninv, "ninv")
+        mask = self._map(mask, "mask", torch.uint8, per_rhs=False)
+        xE, xB = self._alm_out(), self._alm_out()
+        if x0 is not None:
+            xE.copy_(x0[0].reshape(xE.shape))
+            xB.copy_(x0[1].reshape(xB.shape))
+        o, keep = self._opts(tol, maxiter, lam, x0, kernel, reliable_delta, hist_len)
+        inf = CgInfo()
+        with torch.cuda.device(self.device):
+            st = lib().akra_cg_solve(self._h, g1.data_ptr(), g2.data_ptr(), ninv.data_ptr(), mask.data_ptr(),
+                                     ctypes.byref(o), xE.data_ptr(), xB.data_ptr(), ctypes.byref(inf))
+        if st != AKRA_OK and (st != AKRA_NOT_CONVERGED or raise_not_converged):
+            _check(st)
+        return xE, xB, self._info(inf, keep, hist_len)
+
+    def cg_solve_b(self, bE, bB, ninv, mask, tol=1e-3, maxiter=1000, lam=1e-3, x0=None, kernel=None,
+                   reliable_delta=0.1, hist_len=0, raise_not_converged=True):
+        bE, bB = self._alm(bE, "bE"), self._alm(bB, "bB")
+        ninv = self._map(ninv, "ninv")
+        mask = self._map(mask, "mask", torch.uint8, per_rhs=False)
+        xE, xB = self._alm_out(), self._alm_out()
+        if x0 is not None:
+            xE.copy_(x0[0].reshape(xE.shape))
+            xB.copy_(x0[1].reshape(xB.shape))
+        o, keep = self._opts(tol, maxiter, lam, x0, kernel, reliable_delta, hist_len)
+        inf = CgInfo()
+        with torch.cuda.device(self.device):
+            st = lib().akra_cg_solve_b(self._h, ninv.data_ptr(), mask.data_ptr(), bE.data_ptr(), bB.data_ptr(),
+                                       ctypes.byref(o), xE.data_ptr(), xB.data_ptr(), ctypes.byref(inf))
+        if st != AKRA_OK and (st != AKRA_NOT_CONVERGED or raise_not_converged):
+            _check(st)
+        return xE, xB, self._info(inf, keep, hist_len)

@@ -1,0 +1,118 @@
+// Internal declarations of libakra (HIP, gfx950).  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/akra.h"
+
+namespace akra {
+
+// ------------------------------------------------------------------------------------------------
+// Scaled-exponent representation of the Wigner-d recurrence values.
+// A value is mant * 2^(UNIT * k) with an integer k <= 0.  While k < 0 the value is below
+// 2^-(UNIT/2) and contributes nothing; the mantissa is rescaled by 2^-UNIT whenever it exceeds
+// 2^(UNIT/2), and k then grows by one.  Once k == 0 the mantissa is the value itself.
+// ------------------------------------------------------------------------------------------------
+template <typename T> struct Scale;
+template <> struct Scale<double> {
+    static constexpr int UNIT = 512;
+};
+template <> struct Scale<float> {
+    static constexpr int UNIT = 64;
+};
+
+// Per-(l, m) recurrence coefficients of the normalised spin-weighted functions
+//   2lambda_{l+1} = (a x + b) 2lambda_l - g 2lambda_{l-1},   -2lambda_{l+1} = (a x - b) -2lambda_l - g -2lambda_{l-1}
+// stored at the alm index i(l, m) (entries at l = lmax are zero).
+struct alignas(32) Coef64 {
+    double a, b, g, pad;
+};
+struct alignas(16) Coef32 {
+    float a, b, g, pad;
+};
+
+// One iso-latitude ring of the pixelisation.
+struct RingInfo {
+    double z;      // cos(theta): the ring is defined by this double value
+    int64_t ofs;   // first pixel (RING order)
+    int nphi;      // pixels on the ring, N = 4 * sub
+    int sub;       // N / 4: length of the four interleaved sub-transforms
+    int shift;     // phi0 = pi * shift / N
+    int M;         // Bluestein FFT length for the sub-transform (0: sub is a power of two)
+};
+
+struct Plan {
+    int nside = 0, lmax = 0, nrhs = 1, prec = AKRA_FP64;
+    int dev = 0;
+    hipStream_t stream = nullptr;
+    int nrings = 0, npairs = 0;
+    int64_t npix = 0, nalm = 0;
+    double omega = 0;
+
+    // tables
+    RingInfo *d_rings = nullptr;
+    double *d_pair_z = nullptr;
+    Coef64 *d_coef64 = nullptr;
+    Coef32 *d_coef32 = nullptr;
+    double *d_seed2 = nullptr, *d_seedm2 = nullptr;  // [m][pair]
+    int *d_seedk = nullptr;
+    void *d_tw64 = nullptr, *d_tw32 = nullptr;  // e^{-2 pi i k / twn}, k < twn/2
+    int twn = 1;
+    int *d_lof = nullptr;  // l of every alm index
+    int *d_order_p2 = nullptr, *d_order_bl = nullptr;
+    int n_p2 = 0, n_bl = 0, maxM_p2 = 1, maxM_bl = 1;
+    std::vector<RingInfo> h_rings;
+
+    // Legendre launch shapes
+    int syn_R = 1, syn_groups = 1;
+    int adj_R = 1, adj_W = 1, adj_nrb = 1;
+
+    // workspaces (sized for FP64; FP32 views reuse them)
+    void *d_FG = nullptr;       // [nrhs][nrings][lmax+1][2] complex
+    void *d_part = nullptr;     // [nrb][nalm][4] adjoint partial sums
+    void *d_tE = nullptr, *d_tB = nullptr;  // [nrhs][nalm] complex, kernel-scaled input
+    double *d_W = nullptr;      // [nrhs][npix] weights
+    double *d_kern = nullptr;   // [lmax+1]
+    double *d_kuser = nullptr;  // [lmax+1] caller-supplied kernel
+    double *d_red = nullptr;    // reduction partials
+    double *d_scal = nullptr;   // device scalars
+    int *d_flag = nullptr;
+    // solver vectors [nrhs][2][nalm] complex FP64
+    double *d_x = nullptr, *d_r = nullptr, *d_p = nullptr, *d_w = nullptr, *d_b = nullptr, *d_xs = nullptr;
+    double *h_pin = nullptr;    // pinned host scalars
+    int64_t device_bytes = 0;
+};
+
+// error handling
+void set_error(const std::string &msg);
+akra_status hip_fail(hipError_t e, const char *what);
+
+// ---- kernel launchers (akra_kernels.hip) -------------------------------------------------------
+// kernel-scaled prologue: out = K_l * x (Im(a_l0) dropped), converted to the transform precision
+void launch_prologue(Plan &P, bool fp32, const double *xE, const double *xB, const double *kern, int nrhs);
+// Legendre synthesis of the prologue buffers (d_tE, d_tB) or of user FP64 input into d_FG
+void launch_leg_synth(Plan &P, bool fp32, const void *aE, const void *aB, int64_t alm_stride, int nrhs);
+// ring stage: mode 0 = F -> maps, 1 = maps -> G, 2 = F -> W -> G (in place)
+void launch_ring(Plan &P, bool fp32, int mode, const double *g1, const double *g2, double *o1, double *o2,
+                 const double *W, int nrhs);
+// Legendre adjoint of d_FG into the partial sums d_part
+void launch_leg_adj(Plan &P, bool fp32, int rhs);
+// epilogue: sum partials, E/B combination, out = K_l * c + lam * x
+void launch_epilogue(Plan &P, bool fp32, const double *kern, double lam, const double *xE, const double *xB,
+                     double *outE, double *outB);
+// weights W = mask * ninv, plus the sums needed for lambda_eff / P and input validation
+void launch_weights(Plan &P, const double *ninv, const uint8_t *mask, int nrhs);
+
+// full-m dot products and CG vector updates on [2][nalm] complex FP64 vectors
+void launch_dot(Plan &P, const double *a, const double *b, double *out_dev, int64_t n_complex);
+void launch_cg_xr(Plan &P, double *x, double *r, const double *p, const double *w, const double *alpha_dev,
+                  int64_t n_complex);
+void launch_cg_p(Plan &P, double *p, const double *r, const double *beta_dev, double precond, int64_t n_complex);
+void launch_axpby(Plan &P, double *y, double a, const double *x, double b, int64_t n_complex);
+void launch_scalar_div(Plan &P, double *out, const double *num, const double *den);
+bool pow2(int n);
+
+}  // namespace akra

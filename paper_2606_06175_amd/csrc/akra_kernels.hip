@@ -1,0 +1,903 @@
+// Device kernels of libakra for CDNA4 (gfx950).
+//
+// Operator chain of the matrix-free H v (paper Sec. II.B, storage problem):
+//   prologue      x -> K_l x                                   (harmonic diagonal, eq. Dl_kernel)
+//   leg_synth     alm -> F_r(+-m) per ring                      (inverse SHT, Legendre stage)
+//   ring          F -> fold -> inverse DFT -> x W -> DFT -> unfold -> G     (SHT ring stage + N^-1 M)
+//   leg_adj       G -> partial sums of 2h_lm, -2h_lm            (adjoint SHT, Legendre stage)
+//   epilogue      E/B combination (eq. EB_decomp), K_l, + lambda_eff x   (eq. ML_estimator_reg)
+#include <type_traits>
+
+#include "akra_internal.h"
+
+namespace akra {
+
+template <typename T> struct V2;
+template <> struct V2<double> { using type = double2; };
+template <> struct V2<float> { using type = float2; };
+template <typename T> using cplx = typename V2<T>::type;
+template <typename T> struct CoefT;
+template <> struct CoefT<double> { using type = Coef64; };
+template <> struct CoefT<float> { using type = Coef32; };
+
+template <typename T> __device__ __forceinline__ cplx<T> mk(T a, T b) { cplx<T> r; r.x = a; r.y = b; return r; }
+template <typename T> __device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> b)
+{
+    return mk<T>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+template <typename T> __device__ __forceinline__ cplx<T> cadd(cplx<T> a, cplx<T> b) { return mk<T>(a.x + b.x, a.y + b.y); }
+template <typename T> __device__ __forceinline__ cplx<T> csub(cplx<T> a, cplx<T> b) { return mk<T>(a.x - b.x, a.y - b.y); }
+template <typename T> __device__ __forceinline__ cplx<T> cconj(cplx<T> a) { return mk<T>(a.x, -a.y); }
+template <typename T> __device__ __forceinline__ cplx<T> cmuli(cplx<T> a) { return mk<T>(-a.y, a.x); }  // i a
+template <typename T> __device__ __forceinline__ cplx<T> cscale(cplx<T> a, T s) { return mk<T>(a.x * s, a.y * s); }
+
+// e^{i pi k / den} for an integer k (reduced exactly modulo 2 den), evaluated in FP64.
+template <typename T> __device__ __forceinline__ cplx<T> cis_pi(int64_t k, int64_t den)
+{
+    int64_t p = 2 * den;
+    k %= p;
+    if (k < 0) k += p;
+    double s, c;
+    sincospi((double)k / (double)den, &s, &c);
+    return mk<T>((T)c, (T)s);
+}
+
+// ------------------------------------------------------------------------------------------------
+// Seeds: stored in FP64 as mant * 2^(512 k).  FP32 kernels re-express them in their own unit.
+// ------------------------------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void load_seed(const double *__restrict__ s2, const double *__restrict__ sm,
+                                          const int *__restrict__ sk, int64_t idx, T &v2, T &vm, int &k)
+{
+    double a = s2[idx], b = sm[idx];
+    int k64 = sk[idx];
+    if constexpr (std::is_same<T, double>::value) {
+        v2 = a;
+        vm = b;
+        k = k64;
+    } else {
+        double big = fmax(fabs(a), fabs(b));
+        if (big == 0.0) {
+            v2 = vm = 0.0f;
+            k = 0;
+            return;
+        }
+        int e = ilogb(big) + 512 * k64;
+        int k32 = (e >= -40) ? 0 : -((20 - e) / 64);
+        int sh = 512 * k64 - 64 * k32;
+        v2 = (float)ldexp(a, sh);
+        vm = (float)ldexp(b, sh);
+        k = k32;
+    }
+}
+
+template <typename T> __device__ __forceinline__ T scale_hi();
+template <> __device__ __forceinline__ double scale_hi<double>() { return 0x1p256; }
+template <> __device__ __forceinline__ float scale_hi<float>() { return 0x1p32f; }
+template <typename T> __device__ __forceinline__ T scale_down();
+template <> __device__ __forceinline__ double scale_down<double>() { return 0x1p-512; }
+template <> __device__ __forceinline__ float scale_down<float>() { return 0x1p-64f; }
+
+__device__ __forceinline__ bool wave_any(bool p) { return __ballot(p) != 0ull; }
+
+// ================================================================================================
+// Legendre synthesis: for every (m, ring pair) accumulate
+//   P2[par] += 2lambda_lm * (aE, aB),  Pm[par] += -2lambda_lm * (aE, aB)       par = (l + m) mod 2
+// over l = max(m,2) .. lmax, with the recurrence values of the north ring in registers.  The south
+// ring follows from 2lambda_lm(pi - theta) = (-1)^(l+m) -2lambda_lm(theta).  Then
+//   F(m) = -(sum 2lambda (aE + i aB)),  F(-m) = -(sum -2lambda (conj aE + i conj aB)).
+// One wave handles 64*R ring pairs of one m; per-l data (alm, coefficients) are wave-uniform.
+// ================================================================================================
+template <typename T, int R, bool MASK>
+__device__ __forceinline__ void syn_step(const T *__restrict__ aE, const T *__restrict__ aB,
+                                         const typename CoefT<T>::type *__restrict__ cf, int l, bool m0, T (&x)[R],
+                                         T (&c2)[R], T (&p2)[R], T (&cm)[R], T (&pm)[R], const int (&k)[R],
+                                         T (&acc)[8][R])
+{
+    const T er = aE[2 * l], br = aB[2 * l];
+    const T ei = m0 ? (T)0 : aE[2 * l + 1], bi = m0 ? (T)0 : aB[2 * l + 1];
+    const auto c = cf[l];
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        T v2 = c2[j], vm = cm[j];
+        if (MASK) {
+            if (k[j] != 0) v2 = vm = (T)0;
+        }
+        acc[0][j] = fma(v2, er, acc[0][j]);
+        acc[1][j] = fma(v2, ei, acc[1][j]);
+        acc[2][j] = fma(v2, br, acc[2][j]);
+        acc[3][j] = fma(v2, bi, acc[3][j]);
+        acc[4][j] = fma(vm, er, acc[4][j]);
+        acc[5][j] = fma(vm, ei, acc[5][j]);
+        acc[6][j] = fma(vm, br, acc[6][j]);
+        acc[7][j] = fma(vm, bi, acc[7][j]);
+        const T u = c.a * x[j];
+        const T n2 = fma(u + c.b, c2[j], -(c.g * p2[j]));
+        const T nm = fma(u - c.b, cm[j], -(c.g * pm[j]));
+        p2[j] = c2[j];
+        c2[j] = n2;
+        pm[j] = cm[j];
+        cm[j] = nm;
+    }
+}
+
+template <typename T, int R>
+__device__ __forceinline__ bool rescale(T (&c2)[R], T (&p2)[R], T (&cm)[R], T (&pm)[R], int (&k)[R])
+{
+    bool any_neg = false;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        if (k[j] < 0) {
+            T big = fmax(fabs(c2[j]), fabs(cm[j]));
+            if (big > scale_hi<T>()) {
+                const T d = scale_down<T>();
+                c2[j] *= d;
+                p2[j] *= d;
+                cm[j] *= d;
+                pm[j] *= d;
+                k[j] += 1;
+            }
+            any_neg |= (k[j] < 0);
+        }
+    }
+    return wave_any(any_neg);
+}
+
+template <typename T, int R>
+__global__ __launch_bounds__(256) void k_leg_synth(const T *__restrict__ almE, const T *__restrict__ almB,
+                                                   int64_t alm_stride, cplx<T> *__restrict__ FG, int64_t fg_stride,
+                                                   const typename CoefT<T>::type *__restrict__ coef,
+                                                   const double *__restrict__ seed2, const double *__restrict__ seedm2,
+                                                   const int *__restrict__ seedk, const double *__restrict__ pair_z,
+                                                   int lmax, int npairs, int nrings, int ngroups)
+{
+    const int rhs = blockIdx.y;
+    const int lane = threadIdx.x & 63;
+    const int gw = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
+    const int m = gw / ngroups;
+    if (m > lmax) return;
+    const int grp = gw - m * ngroups;
+    const int l0 = m > 2 ? m : 2;
+    const int64_t base = (int64_t)m * (2 * lmax + 1 - m) / 2;
+    const T *aE = almE + 2 * (rhs * alm_stride + base);
+    const T *aB = almB + 2 * (rhs * alm_stride + base);
+    const auto *cf = coef + base;
+    const bool m0 = (m == 0);
+
+    T x[R], c2[R], p2[R], cm[R], pm[R];
+    int k[R], pr[R];
+    T acc0[8][R], acc1[8][R];
+    bool neg = false;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        const int p = grp * 64 * R + j * 64 + lane;
+        pr[j] = p;
+        if (p < npairs) {
+            x[j] = (T)pair_z[p];
+            load_seed<T>(seed2, seedm2, seedk, (int64_t)m * npairs + p, c2[j], cm[j], k[j]);
+        } else {
+            x[j] = (T)0;
+            c2[j] = cm[j] = (T)0;
+            k[j] = 0;
+        }
+        p2[j] = pm[j] = (T)0;
+        neg |= (k[j] < 0);
+#pragma unroll
+        for (int c = 0; c < 8; ++c) acc0[c][j] = acc1[c][j] = (T)0;
+    }
+    bool ramp = wave_any(neg);
+    int l = l0;
+    while (ramp && l < lmax) {
+        syn_step<T, R, true>(aE, aB, cf, l, m0, x, c2, p2, cm, pm, k, acc0);
+        syn_step<T, R, true>(aE, aB, cf, l + 1, m0, x, c2, p2, cm, pm, k, acc1);
+        l += 2;
+        ramp = rescale<T, R>(c2, p2, cm, pm, k);
+    }
+    for (; l < lmax; l += 2) {
+        syn_step<T, R, false>(aE, aB, cf, l, m0, x, c2, p2, cm, pm, k, acc0);
+        syn_step<T, R, false>(aE, aB, cf, l + 1, m0, x, c2, p2, cm, pm, k, acc1);
+    }
+    if (l == lmax) syn_step<T, R, true>(aE, aB, cf, l, m0, x, c2, p2, cm, pm, k, acc0);
+
+    const bool odd0 = ((l0 + m) & 1) != 0;  // acc0 holds l + m odd terms when true
+    cplx<T> *Fb = FG + rhs * fg_stride;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        if (pr[j] >= npairs) continue;
+        T E[8], O[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            E[c] = odd0 ? acc1[c][j] : acc0[c][j];
+            O[c] = odd0 ? acc0[c][j] : acc1[c][j];
+        }
+        const int rn = pr[j], rs = nrings - 1 - pr[j];
+        {
+            T S2[4], Sm[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                S2[c] = E[c] + O[c];
+                Sm[c] = E[4 + c] + O[4 + c];
+            }
+            cplx<T> *f = Fb + ((int64_t)rn * (lmax + 1) + m) * 2;
+            f[0] = mk<T>(-(S2[0] - S2[3]), -(S2[1] + S2[2]));
+            f[1] = mk<T>(-(Sm[0] + Sm[3]), -(Sm[2] - Sm[1]));
+        }
+        if (rs != rn) {
+            T S2[4], Sm[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                S2[c] = E[4 + c] - O[4 + c];
+                Sm[c] = E[c] - O[c];
+            }
+            cplx<T> *f = Fb + ((int64_t)rs * (lmax + 1) + m) * 2;
+            f[0] = mk<T>(-(S2[0] - S2[3]), -(S2[1] + S2[2]));
+            f[1] = mk<T>(-(Sm[0] + Sm[3]), -(Sm[2] - Sm[1]));
+        }
+    }
+}
+
+// ================================================================================================
+// Legendre adjoint: for one m and a block of ring pairs, the partial sums
+//   2h_lm  = sum_r 2lambda_lm(theta_r) G_r(m),      -2h_lm = sum_r -2lambda_lm(theta_r) conj(G_r(-m))
+// (south rings through the reflection symmetry).  Each lane sums its R ring pairs in registers;
+// every L steps of l the per-lane partials go through LDS and are reduced over the workgroup.
+// ================================================================================================
+template <typename T, int R, bool MASK, bool ODD>
+__device__ __forceinline__ void adj_step(const typename CoefT<T>::type *__restrict__ cf, int l, T (&x)[R], T (&c2)[R],
+                                         T (&p2)[R], T (&cm)[R], T (&pm)[R], const int (&k)[R],
+                                         const cplx<T> (&GN)[R], const cplx<T> (&GS)[R], const cplx<T> (&HN)[R],
+                                         const cplx<T> (&HS)[R], T (&out)[4])
+{
+    const auto c = cf[l];
+    T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        T v2 = c2[j], vm = cm[j];
+        if (MASK) {
+            if (k[j] != 0) v2 = vm = (T)0;
+        }
+        const T s = ODD ? (T)-1 : (T)1;
+        a0 = fma(v2, GN[j].x, a0);
+        a1 = fma(v2, GN[j].y, a1);
+        a2 = fma(vm, HN[j].x, a2);
+        a3 = fma(vm, HN[j].y, a3);
+        a0 = fma(s * vm, GS[j].x, a0);
+        a1 = fma(s * vm, GS[j].y, a1);
+        a2 = fma(s * v2, HS[j].x, a2);
+        a3 = fma(s * v2, HS[j].y, a3);
+        const T u = c.a * x[j];
+        const T n2 = fma(u + c.b, c2[j], -(c.g * p2[j]));
+        const T nm = fma(u - c.b, cm[j], -(c.g * pm[j]));
+        p2[j] = c2[j];
+        c2[j] = n2;
+        pm[j] = cm[j];
+        cm[j] = nm;
+    }
+    out[0] = a0;
+    out[1] = a1;
+    out[2] = a2;
+    out[3] = a3;
+}
+
+template <typename T, int R, int W, int L>
+__global__ __launch_bounds__(64 * W) void k_leg_adj(const cplx<T> *__restrict__ FG,
+                                                    const typename CoefT<T>::type *__restrict__ coef,
+                                                    const double *__restrict__ seed2, const double *__restrict__ seedm2,
+                                                    const int *__restrict__ seedk, const double *__restrict__ pair_z,
+                                                    T *__restrict__ part, int64_t nalm, int lmax, int npairs,
+                                                    int nrings, int nrb)
+{
+    __shared__ T red[W * L * 4 * 64];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int b = blockIdx.x;
+    const int m = b / nrb;
+    const int rb = b - m * nrb;
+    const int l0 = m > 2 ? m : 2;
+    const int64_t base = (int64_t)m * (2 * lmax + 1 - m) / 2;
+    const auto *cf = coef + base;
+    const T sgn0 = ((l0 + m) & 1) ? (T)-1 : (T)1;
+
+    T x[R], c2[R], p2[R], cm[R], pm[R];
+    int k[R];
+    cplx<T> GN[R], GS[R], HN[R], HS[R];
+    bool neg = false;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        const int p = rb * (64 * W * R) + (wave * R + j) * 64 + lane;
+        const cplx<T> z = mk<T>(0, 0);
+        GN[j] = GS[j] = HN[j] = HS[j] = z;
+        x[j] = c2[j] = cm[j] = p2[j] = pm[j] = (T)0;
+        k[j] = 0;
+        if (p < npairs) {
+            x[j] = (T)pair_z[p];
+            load_seed<T>(seed2, seedm2, seedk, (int64_t)m * npairs + p, c2[j], cm[j], k[j]);
+            const int rn = p, rs = nrings - 1 - p;
+            const cplx<T> *fn = FG + ((int64_t)rn * (lmax + 1) + m) * 2;
+            GN[j] = fn[0];
+            HN[j] = cconj<T>(fn[1]);
+            if (rs != rn) {
+                const cplx<T> *fs = FG + ((int64_t)rs * (lmax + 1) + m) * 2;
+                GS[j] = cscale<T>(fs[0], sgn0);
+                HS[j] = cscale<T>(cconj<T>(fs[1]), sgn0);
+            }
+        }
+        neg |= (k[j] < 0);
+    }
+    bool ramp = wave_any(neg);
+    const int NT = 64 * W, NO = 4 * L, G = NT / NO;
+    const int t = threadIdx.x, o = t / G, gi = t - o * G;
+    const int oli = o >> 2, oc = o & 3;
+
+    for (int lc = l0; lc <= lmax; lc += L) {
+#pragma unroll
+        for (int li = 0; li < L; li += 2) {
+            T out[4];
+            const int l = lc + li;
+            if (l <= lmax) {
+                if (ramp) adj_step<T, R, true, false>(cf, l, x, c2, p2, cm, pm, k, GN, GS, HN, HS, out);
+                else adj_step<T, R, false, false>(cf, l, x, c2, p2, cm, pm, k, GN, GS, HN, HS, out);
+            } else {
+                out[0] = out[1] = out[2] = out[3] = (T)0;
+            }
+#pragma unroll
+            for (int c = 0; c < 4; ++c) red[((wave * L + li) * 4 + c) * 64 + lane] = out[c];
+            if (l + 1 <= lmax) {
+                if (ramp) adj_step<T, R, true, true>(cf, l + 1, x, c2, p2, cm, pm, k, GN, GS, HN, HS, out);
+                else adj_step<T, R, false, true>(cf, l + 1, x, c2, p2, cm, pm, k, GN, GS, HN, HS, out);
+            } else {
+                out[0] = out[1] = out[2] = out[3] = (T)0;
+            }
+#pragma unroll
+            for (int c = 0; c < 4; ++c) red[((wave * L + li + 1) * 4 + c) * 64 + lane] = out[c];
+            if (ramp) ramp = rescale<T, R>(c2, p2, cm, pm, k);
+        }
+        __syncthreads();
+        T s = 0;
+        for (int q = gi; q < NT; q += G) s += red[(((q >> 6) * L + oli) * 4 + oc) * 64 + (q & 63)];
+        for (int off = G >> 1; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+        if (gi == 0 && lc + oli <= lmax) part[((int64_t)rb * nalm + base + lc + oli) * 4 + oc] = s;
+        __syncthreads();
+    }
+}
+
+// ================================================================================================
+// prologue / epilogue / weights
+// ================================================================================================
+template <typename T>
+__global__ void k_prologue(const double *__restrict__ xE, const double *__restrict__ xB, const double *__restrict__ kern,
+                           const int *__restrict__ lof, int lmax, int64_t nalm, T *__restrict__ oE, T *__restrict__ oB)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int rhs = blockIdx.y;
+    if (i >= nalm) return;
+    const int64_t o = rhs * nalm + i;
+    const double K = kern ? kern[lof[i]] : 1.0;
+    const bool m0 = i <= lmax;
+    oE[2 * o] = (T)(K * xE[2 * o]);
+    oE[2 * o + 1] = m0 ? (T)0 : (T)(K * xE[2 * o + 1]);
+    oB[2 * o] = (T)(K * xB[2 * o]);
+    oB[2 * o + 1] = m0 ? (T)0 : (T)(K * xB[2 * o + 1]);
+}
+
+template <typename T>
+__global__ void k_epilogue(const T *__restrict__ part, int nrb, int64_t nalm, const int *__restrict__ lof, int lmax,
+                           const double *__restrict__ kern, double lam, const double *__restrict__ xE,
+                           const double *__restrict__ xB, double *__restrict__ outE, double *__restrict__ outB)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nalm) return;
+    const int l = lof[i];
+    const bool m0 = i <= lmax;
+    double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+    if (l >= 2) {
+        for (int rb = 0; rb < nrb; ++rb) {
+            const T *q = part + ((int64_t)rb * nalm + i) * 4;
+            s0 += (double)q[0];
+            s1 += (double)q[1];
+            s2 += (double)q[2];
+            s3 += (double)q[3];
+        }
+    }
+    // cE = -(2h + -2h)/2,  cB = (i/2)(2h - -2h)
+    double eR = -0.5 * (s0 + s2), eI = -0.5 * (s1 + s3);
+    double bR = -0.5 * (s1 - s3), bI = 0.5 * (s0 - s2);
+    if (m0) eI = bI = 0.0;
+    const double K = kern ? kern[l] : 1.0;
+    eR *= K; eI *= K; bR *= K; bI *= K;
+    if (xE) {
+        eR += lam * xE[2 * i];
+        bR += lam * xB[2 * i];
+        if (!m0) {
+            eI += lam * xE[2 * i + 1];
+            bI += lam * xB[2 * i + 1];
+        }
+    }
+    outE[2 * i] = eR;
+    outE[2 * i + 1] = eI;
+    outB[2 * i] = bR;
+    outB[2 * i + 1] = bI;
+}
+
+// W = mask * ninv; block partials of sum(M N^-1), sum(M), #non-finite, #negative, sum over all pixels
+__global__ void k_weights(const double *__restrict__ ninv, const uint8_t *__restrict__ mask, double *__restrict__ W,
+                          int64_t npix, double *__restrict__ red)
+{
+    const int rhs = blockIdx.y;
+    __shared__ double sh[5][256];
+    double a = 0, b = 0, c = 0, d = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < npix; i += (int64_t)gridDim.x * blockDim.x) {
+        const double v = ninv[rhs * npix + i];
+        const bool obs = mask[i] != 0;
+        if (!isfinite(v)) c += 1;
+        if (v < 0) d += 1;
+        const double w = obs ? v : 0.0;
+        W[rhs * npix + i] = w;
+        a += w;
+        b += obs ? 1.0 : 0.0;
+    }
+    sh[0][threadIdx.x] = a;
+    sh[1][threadIdx.x] = b;
+    sh[2][threadIdx.x] = c;
+    sh[3][threadIdx.x] = d;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int q = 0; q < 4; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int q = 0; q < 4; ++q) red[((int64_t)rhs * gridDim.x + blockIdx.x) * 4 + q] = sh[q][0];
+}
+
+// ================================================================================================
+// Ring stage.  One workgroup per ring of N = 4L pixels.  The length-N DFTs are split into four
+// interleaved length-L sub-transforms (radix-4 step in registers); a sub-transform is a radix-2
+// FFT in LDS when L is a power of two, else Bluestein's chirp-z with a power-of-two FFT of length
+// M >= 2L - 1.  Synthesis direction: fold F(m), |m| <= lmax, into the N bins (phase e^{i m phi0}),
+// inverse DFT -> gamma at the pixels.  Adjoint direction: weight, forward DFT, unfold into every
+// |m| <= lmax (phase e^{-i m phi0}) and multiply by the pixel area.
+// ================================================================================================
+constexpr int RT = 256;  // threads per ring workgroup
+constexpr int RU = 8;    // sub-transform elements per thread: L <= RT * RU
+
+__device__ __forceinline__ unsigned brev(unsigned n, int logM) { return logM ? (__builtin_bitreverse32(n) >> (32 - logM)) : 0u; }
+
+// e^{-i pi n^2 / L}
+template <typename T> __device__ __forceinline__ cplx<T> chirp(int n, int L)
+{
+    return cconj<T>(cis_pi<T>(((int64_t)n * n) % (2 * (int64_t)L), L));
+}
+
+// in-place radix-2 FFT, bit-reversed input -> natural output; sign -1: e^{-2 pi i/M}
+template <typename T>
+__device__ void fft_dit(cplx<T> *buf, int M, const cplx<T> *__restrict__ tw, int twn, int sign)
+{
+    for (int h = 1; h < M; h <<= 1) {
+        const int stride = twn / (2 * h);
+        for (int bI = threadIdx.x; bI < M / 2; bI += RT) {
+            const int pos = bI & (h - 1);
+            const int i0 = ((bI - pos) << 1) + pos, i1 = i0 + h;
+            cplx<T> w = tw[pos * stride];
+            if (sign > 0) w.y = -w.y;
+            const cplx<T> t = cmul<T>(w, buf[i1]);
+            const cplx<T> a = buf[i0];
+            buf[i0] = cadd<T>(a, t);
+            buf[i1] = csub<T>(a, t);
+        }
+        __syncthreads();
+    }
+}
+
+// in-place radix-2 FFT, natural input -> bit-reversed output
+template <typename T>
+__device__ void fft_dif(cplx<T> *buf, int M, const cplx<T> *__restrict__ tw, int twn, int sign)
+{
+    for (int h = M >> 1; h >= 1; h >>= 1) {
+        const int stride = twn / (2 * h);
+        for (int bI = threadIdx.x; bI < M / 2; bI += RT) {
+            const int pos = bI & (h - 1);
+            const int i0 = ((bI - pos) << 1) + pos, i1 = i0 + h;
+            cplx<T> w = tw[pos * stride];
+            if (sign > 0) w.y = -w.y;
+            const cplx<T> a = buf[i0], c = buf[i1];
+            buf[i0] = cadd<T>(a, c);
+            buf[i1] = cmul<T>(csub<T>(a, c), w);
+        }
+        __syncthreads();
+    }
+}
+
+// Forward DFT of length L: y_k = sum_n x_n e^{-2 pi i n k / L}; x_n = get(u) for n = tid + RT u,
+// y_k delivered as put(u, y) for k = tid + RT u.
+template <typename T, class Get, class Put>
+__device__ __forceinline__ void dft_forward(cplx<T> *buf, const cplx<T> *bhat, int L, int M, int logM, bool blu,
+                                            const cplx<T> *__restrict__ tw, int twn, Get &&get, Put &&put)
+{
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int u = 0; u < RU; ++u) {
+        const int n = tid + RT * u;
+        if (n < L) {
+            cplx<T> v = get(u);
+            if (blu) v = cmul<T>(v, chirp<T>(n, L));
+            buf[brev(n, logM)] = v;
+        }
+    }
+    for (int n = L + tid; n < M; n += RT) buf[brev(n, logM)] = mk<T>(0, 0);
+    __syncthreads();
+    fft_dit<T>(buf, M, tw, twn, -1);
+    if (blu) {
+        for (int n = tid; n < M; n += RT) buf[n] = cmul<T>(buf[n], bhat[n]);
+        __syncthreads();
+        fft_dif<T>(buf, M, tw, twn, +1);
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            const int kk = tid + RT * u;
+            if (kk < L) put(u, cmul<T>(buf[brev(kk, logM)], chirp<T>(kk, L)));
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            const int kk = tid + RT * u;
+            if (kk < L) put(u, buf[kk]);
+        }
+    }
+    __syncthreads();
+}
+
+// sum over m = bin (mod N), |m| <= lmax, of F(m) e^{i m phi0}, phi0 = pi shift / N
+template <typename T>
+__device__ __forceinline__ cplx<T> fold_bin(const cplx<T> *__restrict__ F, int bin, int N, int shift, int lmax)
+{
+    // m = bin + N t,  t in [tlo, thi]
+    const int tlo = -((lmax + bin) / N);
+    const int thi = (lmax >= bin) ? (lmax - bin) / N : -1;
+    T sr = 0, si = 0;
+    for (int t = tlo; t <= thi; ++t) {
+        const int m = bin + N * t;
+        cplx<T> f = (m >= 0) ? F[2 * m] : F[2 * (-m) + 1];
+        if (shift && (t & 1)) f = mk<T>(-f.x, -f.y);  // e^{i pi (N t) shift / N} = (-1)^(t shift)
+        sr += f.x;
+        si += f.y;
+    }
+    cplx<T> s = mk<T>(sr, si);
+    if (shift) s = cmul<T>(s, cis_pi<T>(bin, N));
+    return s;
+}
+
+template <typename T>
+__device__ __forceinline__ void unfold_bin(cplx<T> *__restrict__ G, int bin, int N, int shift, int lmax, cplx<T> y)
+{
+    if (shift) y = cmul<T>(y, cconj<T>(cis_pi<T>(bin, N)));
+    const int tlo = -((lmax + bin) / N);
+    const int thi = (lmax >= bin) ? (lmax - bin) / N : -1;
+    for (int t = tlo; t <= thi; ++t) {
+        const int m = bin + N * t;
+        const cplx<T> g = (shift && (t & 1)) ? mk<T>(-y.x, -y.y) : y;
+        if (m > 0) G[2 * m] = g;
+        else if (m < 0) G[2 * (-m) + 1] = g;
+        else {
+            G[0] = g;
+            G[1] = g;
+        }
+    }
+}
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(RT) void k_ring(cplx<T> *__restrict__ FG, int64_t fg_stride, const double *__restrict__ g1,
+                                             const double *__restrict__ g2, double *__restrict__ o1,
+                                             double *__restrict__ o2, int64_t map_stride, const double *__restrict__ Wt,
+                                             const RingInfo *__restrict__ rings, const int *__restrict__ order,
+                                             const cplx<T> *__restrict__ tw, int twn, int lmax, double omega)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cplx<T> *buf = reinterpret_cast<cplx<T> *>(smem_raw);
+    const int r = order[blockIdx.x];
+    const int rhs = blockIdx.y;
+    const RingInfo ri = rings[r];
+    const int N = ri.nphi, L = ri.sub, shift = ri.shift;
+    const bool blu = ri.M > 0;
+    const int M = blu ? ri.M : L;
+    const int logM = 31 - __builtin_clz(M);
+    cplx<T> *bhat = buf + M;
+    cplx<T> *F = FG + rhs * fg_stride + (int64_t)r * (lmax + 1) * 2;
+    const int tid = threadIdx.x;
+    const int64_t pofs = rhs * map_stride + ri.ofs;
+
+    if (blu) {  // FFT of the chirp b_n = e^{+i pi n^2/L} (n in (-L, L), wrapped), scaled by 1/M
+        for (int n = tid; n < M; n += RT) {
+            cplx<T> v = mk<T>(0, 0);
+            if (n < L) v = cconj<T>(chirp<T>(n, L));
+            else if (n > M - L) v = cconj<T>(chirp<T>(M - n, L));
+            bhat[brev(n, logM)] = v;
+        }
+        __syncthreads();
+        fft_dit<T>(bhat, M, tw, twn, -1);
+        const T inv = (T)1 / (T)M;
+        for (int n = tid; n < M; n += RT) bhat[n] = cscale<T>(bhat[n], inv);
+        __syncthreads();
+    }
+
+    cplx<T> v[RU][4];
+    if (MODE != 1) {
+        // gamma[j1 + L j2] = sum_q i^(q j2) e^{2 pi i q j1/N} X_q[j1],  X_q = inverse DFT_L of bins 4k'+q
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            dft_forward<T>(
+                buf, bhat, L, M, logM, blu, tw, twn,
+                [&](int u) { return cconj<T>(fold_bin<T>(F, 4 * (tid + RT * u) + q, N, shift, lmax)); },
+                [&](int u, cplx<T> y) { v[u][q] = cconj<T>(y); });
+        }
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            const int j1 = tid + RT * u;
+            if (j1 >= L) continue;
+            const cplx<T> t0 = v[u][0];
+            const cplx<T> t1 = cmul<T>(cis_pi<T>(2 * (int64_t)j1, N), v[u][1]);
+            const cplx<T> t2 = cmul<T>(cis_pi<T>(4 * (int64_t)j1, N), v[u][2]);
+            const cplx<T> t3 = cmul<T>(cis_pi<T>(6 * (int64_t)j1, N), v[u][3]);
+            const cplx<T> a = cadd<T>(t0, t2), b = csub<T>(t0, t2), c = cadd<T>(t1, t3), d = cmuli<T>(csub<T>(t1, t3));
+            v[u][0] = cadd<T>(a, c);
+            v[u][1] = cadd<T>(b, d);
+            v[u][2] = csub<T>(a, c);
+            v[u][3] = csub<T>(b, d);
+        }
+    }
+    if (MODE == 0) {
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            const int j1 = tid + RT * u;
+            if (j1 >= L) continue;
+#pragma unroll
+            for (int j2 = 0; j2 < 4; ++j2) {
+                o1[pofs + j1 + L * j2] = (double)v[u][j2].x;
+                o2[pofs + j1 + L * j2] = (double)v[u][j2].y;
+            }
+        }
+        return;
+    }
+#pragma unroll
+    for (int u = 0; u < RU; ++u) {
+        const int j1 = tid + RT * u;
+        if (j1 >= L) continue;
+#pragma unroll
+        for (int j2 = 0; j2 < 4; ++j2) {
+            const int64_t pix = pofs + j1 + L * j2;
+            if (MODE == 1) {
+                const T w = Wt ? (T)Wt[pix] : (T)1;
+                v[u][j2] = mk<T>((T)g1[pix] * w, (T)g2[pix] * w);
+            } else {
+                const T w = (T)Wt[pix];
+                v[u][j2] = cscale<T>(v[u][j2], w);
+            }
+        }
+        // u_q = e^{-2 pi i q j1/N} sum_j2 (-i)^(j2 q) h[j1 + L j2]
+        const cplx<T> h0 = v[u][0], h1 = v[u][1], h2 = v[u][2], h3 = v[u][3];
+        const cplx<T> a = cadd<T>(h0, h2), b = csub<T>(h0, h2), c = cadd<T>(h1, h3), d = cmuli<T>(csub<T>(h1, h3));
+        v[u][0] = cadd<T>(a, c);
+        v[u][1] = cmul<T>(cconj<T>(cis_pi<T>(2 * (int64_t)j1, N)), csub<T>(b, d));
+        v[u][2] = cmul<T>(cconj<T>(cis_pi<T>(4 * (int64_t)j1, N)), csub<T>(a, c));
+        v[u][3] = cmul<T>(cconj<T>(cis_pi<T>(6 * (int64_t)j1, N)), cadd<T>(b, d));
+    }
+    const T om = (T)omega;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        dft_forward<T>(
+            buf, bhat, L, M, logM, blu, tw, twn, [&](int u) { return v[u][q]; },
+            [&](int u, cplx<T> y) { unfold_bin<T>(F, 4 * (tid + RT * u) + q, N, shift, lmax, cscale<T>(y, om)); });
+    }
+}
+
+// ================================================================================================
+// vector kernels (FP64): full-m inner product and the CG updates
+// ================================================================================================
+constexpr int RED_BLOCKS = 512;
+
+__global__ void k_dot_part(const double *__restrict__ a, const double *__restrict__ b, int64_t n, int64_t nalm, int lmax,
+                           double *__restrict__ red)
+{
+    __shared__ double sh[256];
+    double s = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double w = ((i % nalm) <= lmax) ? 1.0 : 2.0;
+        s += w * (a[2 * i] * b[2 * i] + a[2 * i + 1] * b[2 * i + 1]);
+    }
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int q = 128; q > 0; q >>= 1) {
+        if ((int)threadIdx.x < q) sh[threadIdx.x] += sh[threadIdx.x + q];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) red[blockIdx.x] = sh[0];
+}
+
+__global__ void k_sum_part(const double *__restrict__ red, int n, int stride, int ncomp, double *__restrict__ out)
+{
+    // deterministic: one thread per component sums the block partials in order
+    const int c = threadIdx.x;
+    if (c >= ncomp) return;
+    double s = 0;
+    for (int i = 0; i < n; ++i) s += red[(int64_t)i * stride + c];
+    out[c] = s;
+}
+
+__global__ void k_cg_xr(double *__restrict__ x, double *__restrict__ r, const double *__restrict__ p,
+                        const double *__restrict__ w, const double *__restrict__ alpha, int64_t n2)
+{
+    const double a = *alpha;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += (int64_t)gridDim.x * blockDim.x) {
+        x[i] = fma(a, p[i], x[i]);
+        r[i] = fma(-a, w[i], r[i]);
+    }
+}
+
+__global__ void k_cg_p(double *__restrict__ p, const double *__restrict__ r, const double *__restrict__ beta,
+                       double precond, int64_t n2)
+{
+    const double bt = *beta;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = fma(bt, p[i], precond * r[i]);
+}
+
+__global__ void k_axpby(double *__restrict__ y, double a, const double *__restrict__ x, double b, int64_t n2)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = a * x[i] + b * y[i];
+}
+
+__global__ void k_scalar_div(double *out, const double *num, const double *den) { *out = *num / *den; }
+
+// ================================================================================================
+// launchers
+// ================================================================================================
+bool pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
+
+static int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+void launch_prologue(Plan &P, bool fp32, const double *xE, const double *xB, const double *kern, int nrhs)
+{
+    dim3 g((unsigned)cdiv(P.nalm, 256), nrhs);
+    if (fp32)
+        k_prologue<float><<<g, 256, 0, P.stream>>>(xE, xB, kern, P.d_lof, P.lmax, P.nalm, (float *)P.d_tE,
+                                                   (float *)P.d_tB);
+    else
+        k_prologue<double><<<g, 256, 0, P.stream>>>(xE, xB, kern, P.d_lof, P.lmax, P.nalm, (double *)P.d_tE,
+                                                    (double *)P.d_tB);
+}
+
+template <typename T, int R>
+static void syn_launch(Plan &P, const void *aE, const void *aB, int64_t alm_stride, int nrhs, int64_t fg_stride)
+{
+    const int ngroups = (int)cdiv(P.npairs, 64 * R);
+    const int64_t waves = (int64_t)(P.lmax + 1) * ngroups;
+    dim3 g((unsigned)cdiv(waves, 4), nrhs);
+    const void *coef = std::is_same<T, double>::value ? (const void *)P.d_coef64 : (const void *)P.d_coef32;
+    k_leg_synth<T, R><<<g, 256, 0, P.stream>>>((const T *)aE, (const T *)aB, alm_stride, (cplx<T> *)P.d_FG, fg_stride,
+                                               (const typename CoefT<T>::type *)coef, P.d_seed2, P.d_seedm2, P.d_seedk,
+                                               P.d_pair_z, P.lmax, P.npairs, P.nrings, ngroups);
+}
+
+void launch_leg_synth(Plan &P, bool fp32, const void *aE, const void *aB, int64_t alm_stride, int nrhs)
+{
+    const int64_t fg_stride = (int64_t)P.nrings * (P.lmax + 1) * 2;
+    if (fp32) {
+        if (P.syn_R == 1) syn_launch<float, 1>(P, aE, aB, alm_stride, nrhs, fg_stride);
+        else syn_launch<float, 2>(P, aE, aB, alm_stride, nrhs, fg_stride);
+    } else {
+        if (P.syn_R == 1) syn_launch<double, 1>(P, aE, aB, alm_stride, nrhs, fg_stride);
+        else syn_launch<double, 2>(P, aE, aB, alm_stride, nrhs, fg_stride);
+    }
+}
+
+template <typename T, int R, int W>
+static void adj_launch(Plan &P, int rhs)
+{
+    constexpr int L = 8;
+    const int64_t fg_stride = (int64_t)P.nrings * (P.lmax + 1) * 2;
+    const void *coef = std::is_same<T, double>::value ? (const void *)P.d_coef64 : (const void *)P.d_coef32;
+    dim3 g((unsigned)((P.lmax + 1) * P.adj_nrb));
+    k_leg_adj<T, R, W, L><<<g, 64 * W, 0, P.stream>>>((const cplx<T> *)P.d_FG + rhs * fg_stride,
+                                                      (const typename CoefT<T>::type *)coef, P.d_seed2, P.d_seedm2,
+                                                      P.d_seedk, P.d_pair_z, (T *)P.d_part, P.nalm, P.lmax, P.npairs,
+                                                      P.nrings, P.adj_nrb);
+}
+
+template <typename T>
+static void adj_dispatch(Plan &P, int rhs)
+{
+    const int R = P.adj_R, W = P.adj_W;
+    if (R == 1 && W == 1) adj_launch<T, 1, 1>(P, rhs);
+    else if (R == 1 && W == 2) adj_launch<T, 1, 2>(P, rhs);
+    else if (R == 1 && W == 4) adj_launch<T, 1, 4>(P, rhs);
+    else if (R == 2 && W == 4) adj_launch<T, 2, 4>(P, rhs);
+    else adj_launch<T, 4, 4>(P, rhs);
+}
+
+void launch_leg_adj(Plan &P, bool fp32, int rhs)
+{
+    if (fp32) adj_dispatch<float>(P, rhs);
+    else adj_dispatch<double>(P, rhs);
+}
+
+void launch_epilogue(Plan &P, bool fp32, const double *kern, double lam, const double *xE, const double *xB,
+                     double *outE, double *outB)
+{
+    dim3 g((unsigned)cdiv(P.nalm, 256));
+    if (fp32)
+        k_epilogue<float><<<g, 256, 0, P.stream>>>((const float *)P.d_part, P.adj_nrb, P.nalm, P.d_lof, P.lmax, kern,
+                                                   lam, xE, xB, outE, outB);
+    else
+        k_epilogue<double><<<g, 256, 0, P.stream>>>((const double *)P.d_part, P.adj_nrb, P.nalm, P.d_lof, P.lmax,
+                                                    kern, lam, xE, xB, outE, outB);
+}
+
+template <typename T, int MODE>
+static void ring_launch_t(Plan &P, const double *g1, const double *g2, double *o1, double *o2, const double *W,
+                          int nrhs)
+{
+    const int64_t fg_stride = (int64_t)P.nrings * (P.lmax + 1) * 2;
+    const void *tw = std::is_same<T, double>::value ? P.d_tw64 : P.d_tw32;
+    if (P.n_p2) {
+        size_t sm = sizeof(cplx<T>) * (size_t)P.maxM_p2;
+        k_ring<T, MODE><<<dim3(P.n_p2, nrhs), RT, sm, P.stream>>>((cplx<T> *)P.d_FG, fg_stride, g1, g2, o1, o2, P.npix,
+                                                                  W, P.d_rings, P.d_order_p2, (const cplx<T> *)tw,
+                                                                  P.twn, P.lmax, P.omega);
+    }
+    if (P.n_bl) {
+        size_t sm = sizeof(cplx<T>) * (size_t)P.maxM_bl * 2;
+        k_ring<T, MODE><<<dim3(P.n_bl, nrhs), RT, sm, P.stream>>>((cplx<T> *)P.d_FG, fg_stride, g1, g2, o1, o2, P.npix,
+                                                                  W, P.d_rings, P.d_order_bl, (const cplx<T> *)tw,
+                                                                  P.twn, P.lmax, P.omega);
+    }
+}
+
+void launch_ring(Plan &P, bool fp32, int mode, const double *g1, const double *g2, double *o1, double *o2,
+                 const double *W, int nrhs)
+{
+    if (fp32) {
+        if (mode == 0) ring_launch_t<float, 0>(P, g1, g2, o1, o2, W, nrhs);
+        else if (mode == 1) ring_launch_t<float, 1>(P, g1, g2, o1, o2, W, nrhs);
+        else ring_launch_t<float, 2>(P, g1, g2, o1, o2, W, nrhs);
+    } else {
+        if (mode == 0) ring_launch_t<double, 0>(P, g1, g2, o1, o2, W, nrhs);
+        else if (mode == 1) ring_launch_t<double, 1>(P, g1, g2, o1, o2, W, nrhs);
+        else ring_launch_t<double, 2>(P, g1, g2, o1, o2, W, nrhs);
+    }
+}
+
+void launch_weights(Plan &P, const double *ninv, const uint8_t *mask, int nrhs)
+{
+    k_weights<<<dim3(RED_BLOCKS, nrhs), 256, 0, P.stream>>>(ninv, mask, P.d_W, P.npix, P.d_red);
+    for (int r = 0; r < nrhs; ++r)
+        k_sum_part<<<1, 64, 0, P.stream>>>(P.d_red + (int64_t)r * RED_BLOCKS * 4, RED_BLOCKS, 4, 4, P.d_scal + 8 + 4 * r);
+}
+
+void launch_dot(Plan &P, const double *a, const double *b, double *out_dev, int64_t n_complex)
+{
+    k_dot_part<<<RED_BLOCKS, 256, 0, P.stream>>>(a, b, n_complex, P.nalm, P.lmax, P.d_red);
+    k_sum_part<<<1, 64, 0, P.stream>>>(P.d_red, RED_BLOCKS, 1, 1, out_dev);
+}
+
+void launch_cg_xr(Plan &P, double *x, double *r, const double *p, const double *w, const double *alpha_dev,
+                  int64_t n_complex)
+{
+    k_cg_xr<<<1024, 256, 0, P.stream>>>(x, r, p, w, alpha_dev, 2 * n_complex);
+}
+
+void launch_cg_p(Plan &P, double *p, const double *r, const double *beta_dev, double precond, int64_t n_complex)
+{
+    k_cg_p<<<1024, 256, 0, P.stream>>>(p, r, beta_dev, precond, 2 * n_complex);
+}
+
+void launch_axpby(Plan &P, double *y, double a, const double *x, double b, int64_t n_complex)
+{
+    k_axpby<<<1024, 256, 0, P.stream>>>(y, a, x, b, 2 * n_complex);
+}
+
+void launch_scalar_div(Plan &P, double *out, const double *num, const double *den)
+{
+    k_scalar_div<<<1, 1, 0, P.stream>>>(out, num, den);
+}
+
+}  // namespace akra

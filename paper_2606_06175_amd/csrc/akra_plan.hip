@@ -1,0 +1,827 @@
+// Host side of libakra: plan (geometry, recurrence tables, seeds, workspaces), the C ABI and
+// the conjugate-gradient drivers (paper Sec. II.B, inversion problem; eq. ML_estimator_reg,
+// eq. precond).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "akra_internal.h"
+
+namespace akra {
+
+static thread_local std::string g_err;
+void set_error(const std::string &msg) { g_err = msg; }
+akra_status hip_fail(hipError_t e, const char *what)
+{
+    set_error(std::string(what) + ": " + hipGetErrorString(e));
+    return AKRA_ERR_HIP;
+}
+
+#define AK_HIP(call, what)                         \
+    do {                                           \
+        hipError_t e_ = (call);                    \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+template <class F> static void parallel_for(int n, F f)
+{
+    int nt = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    nt = std::min(nt, std::max(1, n));
+    std::vector<std::thread> th;
+    for (int t = 0; t < nt; ++t)
+        th.emplace_back([=]() {
+            for (int i = t; i < n; i += nt) f(i);
+        });
+    for (auto &x : th) x.join();
+}
+
+// ---------------------------------------------------------------------------------------------
+// HEALPix RING geometry (Gorski et al. 2005; the pixelisation of Sec. III.B).  A ring is defined
+// by its double-precision z computed exactly as below.
+// ---------------------------------------------------------------------------------------------
+static void build_rings(Plan &P)
+{
+    const int ns = P.nside;
+    P.nrings = 4 * ns - 1;
+    P.npairs = 2 * ns;
+    P.npix = 12LL * ns * ns;
+    P.omega = 4.0 * M_PI / (double)P.npix;
+    P.h_rings.resize(P.nrings);
+    int64_t ofs = 0;
+    for (int k = 0; k < P.nrings; ++k) {
+        const int i = k + 1;
+        RingInfo r{};
+        if (i < ns || i > 3 * ns) {
+            const int ii = (i < ns) ? i : 4 * ns - i;
+            const double d = (double)((int64_t)ii * ii) / (3.0 * ns * ns);
+            r.z = (i < ns) ? (1.0 - d) : -(1.0 - d);
+            r.nphi = 4 * ii;
+            r.shift = 1;
+        } else {
+            r.z = 4.0 / 3.0 - 2.0 * i / (3.0 * ns);
+            r.nphi = 4 * ns;
+            r.shift = (i - ns + 1) % 2;
+        }
+        r.ofs = ofs;
+        r.sub = r.nphi / 4;
+        r.M = 0;
+        if (!pow2(r.sub)) {
+            int M = 1;
+            while (M < 2 * r.sub - 1) M <<= 1;
+            r.M = M;
+        }
+        ofs += r.nphi;
+        P.h_rings[k] = r;
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Recurrence coefficients of lambda_l = sqrt((2l+1)/(4pi)) d^l_{m,mp}(theta), mp = -+2, from the
+// three-term recurrence of the Wigner d-functions:
+//   a_l = (l+1) sqrt((2l+1)(2l+3)) / R_{l+1},  b_l = 2m sqrt((2l+1)(2l+3)) / (l R_{l+1}),
+//   g_l = (l+1) R_l sqrt((2l+3)/(2l-1)) / (l R_{l+1}),   R_l = sqrt((l^2 - m^2)(l^2 - 4)).
+// ---------------------------------------------------------------------------------------------
+static void build_coef(int lmax, std::vector<Coef64> &c64, std::vector<Coef32> &c32)
+{
+    const int64_t nalm = (int64_t)(lmax + 1) * (lmax + 2) / 2;
+    c64.assign(nalm, Coef64{0, 0, 0, 0});
+    c32.assign(nalm, Coef32{0, 0, 0, 0});
+    parallel_for(lmax + 1, [&](int m) {
+        const int64_t base = (int64_t)m * (2 * lmax + 1 - m) / 2;
+        const int l0 = std::max(m, 2);
+        typedef long double ld;
+        auto R = [&](int l) { return sqrtl(((ld)l * l - (ld)m * m) * ((ld)l * l - 4.0L)); };
+        for (int l = l0; l < lmax; ++l) {
+            const ld L = l;
+            const ld r1 = R(l + 1), r0 = R(l);
+            const ld q = sqrtl((2 * L + 1) * (2 * L + 3));
+            const ld a = (L + 1) * q / r1;
+            const ld b = 2.0L * m * q / (L * r1);
+            const ld g = (L + 1) * r0 * sqrtl((2 * L + 3) / (2 * L - 1)) / (L * r1);
+            c64[base + l] = Coef64{(double)a, (double)b, (double)g, 0.0};
+            c32[base + l] = Coef32{(float)a, (float)b, (float)g, 0.0f};
+        }
+    });
+}
+
+// ---------------------------------------------------------------------------------------------
+// Seeds lambda_{l0,m}, l0 = max(m,2), for the north ring of every pair, by a recurrence in m:
+//   t_2 = d^2_{22} = c^4,  t_{m+1} = -t_m sqrt((2m+2)(2m+1)/((m+3)(m-1))) c s   (t_m = d^m_{m,2}),
+//   d^m_{m,-2} = t_m (s/c)^4;  for m < 2: d^2_{0,+-2} = sqrt6 c^2 s^2, d^2_{1,2} = 2 c^3 s, d^2_{1,-2} = -2 c s^3.
+// c = cos(theta/2), s = sin(theta/2).  Long double with explicit binary exponents; stored as
+// mant * 2^(512 k) (see Scale<double>).
+// ---------------------------------------------------------------------------------------------
+static void build_seeds(Plan &P, std::vector<double> &s2, std::vector<double> &sm, std::vector<int> &sk)
+{
+    typedef long double ld;
+    const int lmax = P.lmax, np = P.npairs;
+    s2.assign((size_t)(lmax + 1) * np, 0.0);
+    sm.assign((size_t)(lmax + 1) * np, 0.0);
+    sk.assign((size_t)(lmax + 1) * np, 0);
+    std::vector<ld> fac(lmax + 2, 0.0L);
+    for (int m = 2; m <= lmax; ++m) fac[m] = sqrtl((ld)(2 * m + 2) * (2 * m + 1) / ((ld)(m + 3) * (m - 1)));
+    const ld inv4pi = 1.0L / (4.0L * 3.141592653589793238462643383279502884L);
+    parallel_for(np, [&](int p) {
+        const ld z = P.h_rings[p].z;
+        const ld c = sqrtl((1 + z) / 2), s = sqrtl((1 - z) / 2);
+        const ld cs = c * s, t4 = (s / c) * (s / c) * (s / c) * (s / c);
+        auto store = [&](int m, ld mant_m2, int e_m2, ld mant_2, int e_2) {
+            // value_m2 = mant_m2 2^e_m2 is -2lambda (mp = +2), value_2 = 2lambda (mp = -2)
+            const int l0 = std::max(m, 2);
+            const ld nrm = sqrtl((2 * l0 + 1) * inv4pi);
+            int ea, eb;
+            ld fa = frexpl(mant_m2 * nrm, &ea), fb = frexpl(mant_2 * nrm, &eb);
+            ea += e_m2;
+            eb += e_2;
+            if (fa == 0) ea = -1000000;
+            if (fb == 0) eb = -1000000;
+            const int ebig = std::max(ea, eb);
+            int k = 0;
+            if (ebig < -400) k = (int)std::floor((ebig + 300) / 512.0);
+            const size_t idx = (size_t)m * np + p;
+            sm[idx] = (double)ldexpl(fa, ea - 512 * k);
+            s2[idx] = (double)ldexpl(fb, eb - 512 * k);
+            sk[idx] = k;
+        };
+        store(0, sqrtl(6.0L) * c * c * s * s, 0, sqrtl(6.0L) * c * c * s * s, 0);
+        if (lmax >= 1) store(1, 2.0L * c * c * c * s, 0, -2.0L * c * s * s * s, 0);
+        int e = 0;
+        ld t = frexpl(c * c * c * c, &e);  // t_2
+        for (int m = 2; m <= lmax; ++m) {
+            if (m > 2) {
+                int de;
+                t = frexpl(-t * fac[m - 1] * cs, &de);
+                e += de;
+            }
+            int de2;
+            ld u = frexpl(t * t4, &de2);
+            store(m, t, e, u, e + de2);
+        }
+    });
+}
+
+static akra_status upload(void **dst, const void *src, size_t bytes, Plan &P)
+{
+    AK_HIP(hipMalloc(dst, std::max<size_t>(bytes, 16)), "hipMalloc");
+    P.device_bytes += (int64_t)bytes;
+    if (src) AK_HIP(hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice), "hipMemcpy");
+    return AKRA_OK;
+}
+
+static akra_status alloc(void **dst, size_t bytes, Plan &P)
+{
+    AK_HIP(hipMalloc(dst, std::max<size_t>(bytes, 16)), "hipMalloc");
+    P.device_bytes += (int64_t)bytes;
+    return AKRA_OK;
+}
+
+static void default_kernel(int lmax, std::vector<double> &k)
+{
+    // K_l = sigma_D D_l, sigma_D = -1, D_l = -sqrt((l-1)(l+2)/(l(l+1))) (eq. Dl_kernel), K_0 = K_1 = 0
+    k.assign(lmax + 1, 0.0);
+    for (int l = 2; l <= lmax; ++l) k[l] = std::sqrt((double)(l - 1) * (l + 2) / ((double)l * (l + 1)));
+}
+
+static void free_plan(Plan *P)
+{
+    void *ptrs[] = {P->d_rings, P->d_pair_z, P->d_coef64, P->d_coef32, P->d_seed2, P->d_seedm2, P->d_seedk,
+                    P->d_tw64, P->d_tw32, P->d_lof, P->d_order_p2, P->d_order_bl, P->d_FG, P->d_part, P->d_tE,
+                    P->d_tB, P->d_W, P->d_kern, P->d_kuser, P->d_red, P->d_scal, P->d_flag, P->d_x, P->d_r,
+                    P->d_p, P->d_w, P->d_b, P->d_xs};
+    for (void *q : ptrs)
+        if (q) (void)hipFree(q);
+    if (P->h_pin) (void)hipHostFree(P->h_pin);
+    delete P;
+}
+
+static akra_status create(int nside, int lmax, int nrhs, int prec, void *stream, Plan **out)
+{
+    if (nside < 1 || nside > 2048) {
+        set_error("nside must be in [1, 2048]");
+        return AKRA_ERR_ARG;
+    }
+    if (lmax < 2 || lmax > 4 * nside) {
+        set_error("lmax must be in [2, 4 nside]");
+        return AKRA_ERR_ARG;
+    }
+    if (nrhs < 1 || nrhs > 64) {
+        set_error("nrhs must be in [1, 64]");
+        return AKRA_ERR_ARG;
+    }
+    if (prec != AKRA_FP64 && prec != AKRA_FP32) {
+        set_error("precision must be AKRA_FP64 or AKRA_FP32");
+        return AKRA_ERR_ARG;
+    }
+    Plan *P = new Plan();
+    P->nside = nside;
+    P->lmax = lmax;
+    P->nrhs = nrhs;
+    P->prec = prec;
+    P->stream = (hipStream_t)stream;
+    (void)hipGetDevice(&P->dev);
+    P->nalm = (int64_t)(lmax + 1) * (lmax + 2) / 2;
+    build_rings(*P);
+
+    // ring launch lists (power-of-two sub-transforms / Bluestein), largest first
+    std::vector<int> p2, bl;
+    int maxp2 = 1, maxbl = 1;
+    for (int r = 0; r < P->nrings; ++r) {
+        if (P->h_rings[r].M) {
+            bl.push_back(r);
+            maxbl = std::max(maxbl, P->h_rings[r].M);
+        } else {
+            p2.push_back(r);
+            maxp2 = std::max(maxp2, P->h_rings[r].sub);
+        }
+    }
+    auto bysize = [&](int a, int b) { return P->h_rings[a].nphi > P->h_rings[b].nphi; };
+    std::stable_sort(p2.begin(), p2.end(), bysize);
+    std::stable_sort(bl.begin(), bl.end(), bysize);
+    P->n_p2 = (int)p2.size();
+    P->n_bl = (int)bl.size();
+    P->maxM_p2 = maxp2;
+    P->maxM_bl = maxbl;
+    P->twn = std::max(2, std::max(maxp2, maxbl));
+
+    // Legendre launch shapes
+    P->syn_R = P->npairs >= 256 ? 2 : 1;
+    P->syn_groups = (P->npairs + 64 * P->syn_R - 1) / (64 * P->syn_R);
+    const int caps[5][2] = {{1, 1}, {1, 2}, {1, 4}, {2, 4}, {4, 4}};
+    int ci = 4;
+    for (int i = 0; i < 5; ++i)
+        if (64 * caps[i][0] * caps[i][1] >= P->npairs) {
+            ci = i;
+            break;
+        }
+    P->adj_R = caps[ci][0];
+    P->adj_W = caps[ci][1];
+    P->adj_nrb = (P->npairs + 64 * P->adj_R * P->adj_W - 1) / (64 * P->adj_R * P->adj_W);
+
+    akra_status st;
+#define AK_TRY(x)                \
+    do {                         \
+        st = (x);                \
+        if (st != AKRA_OK) {     \
+            free_plan(P);        \
+            return st;           \
+        }                        \
+    } while (0)
+
+    // tables
+    {
+        std::vector<Coef64> c64;
+        std::vector<Coef32> c32;
+        build_coef(lmax, c64, c32);
+        AK_TRY(upload((void **)&P->d_coef64, c64.data(), c64.size() * sizeof(Coef64), *P));
+        AK_TRY(upload((void **)&P->d_coef32, c32.data(), c32.size() * sizeof(Coef32), *P));
+    }
+    {
+        std::vector<double> s2, sm;
+        std::vector<int> sk;
+        build_seeds(*P, s2, sm, sk);
+        AK_TRY(upload((void **)&P->d_seed2, s2.data(), s2.size() * sizeof(double), *P));
+        AK_TRY(upload((void **)&P->d_seedm2, sm.data(), sm.size() * sizeof(double), *P));
+        AK_TRY(upload((void **)&P->d_seedk, sk.data(), sk.size() * sizeof(int), *P));
+    }
+    {
+        std::vector<double> pz(P->npairs);
+        for (int p = 0; p < P->npairs; ++p) pz[p] = P->h_rings[p].z;
+        AK_TRY(upload((void **)&P->d_pair_z, pz.data(), pz.size() * sizeof(double), *P));
+        AK_TRY(upload((void **)&P->d_rings, P->h_rings.data(), P->h_rings.size() * sizeof(RingInfo), *P));
+        AK_TRY(upload((void **)&P->d_order_p2, p2.data(), p2.size() * sizeof(int), *P));
+        AK_TRY(upload((void **)&P->d_order_bl, bl.data(), bl.size() * sizeof(int), *P));
+    }
+    {
+        const int n = P->twn / 2;
+        std::vector<double2> t64(n);
+        std::vector<float2> t32(n);
+        for (int k = 0; k < n; ++k) {
+            long double a = -2.0L * 3.141592653589793238462643383279502884L * k / P->twn;
+            t64[k] = make_double2((double)cosl(a), (double)sinl(a));
+            t32[k] = make_float2((float)cosl(a), (float)sinl(a));
+        }
+        AK_TRY(upload(&P->d_tw64, t64.data(), n * sizeof(double2), *P));
+        AK_TRY(upload(&P->d_tw32, t32.data(), n * sizeof(float2), *P));
+    }
+    {
+        std::vector<int> lof(P->nalm);
+        for (int m = 0; m <= lmax; ++m)
+            for (int l = m; l <= lmax; ++l) lof[(int64_t)m * (2 * lmax + 1 - m) / 2 + l] = l;
+        AK_TRY(upload((void **)&P->d_lof, lof.data(), lof.size() * sizeof(int), *P));
+        std::vector<double> kd, ones(lmax + 1, 1.0);
+        default_kernel(lmax, kd);
+        AK_TRY(upload((void **)&P->d_kern, kd.data(), kd.size() * sizeof(double), *P));
+        AK_TRY(upload((void **)&P->d_kuser, ones.data(), ones.size() * sizeof(double), *P));
+    }
+    // workspaces
+    const size_t fg = (size_t)nrhs * P->nrings * (lmax + 1) * 2 * sizeof(double2);
+    AK_TRY(alloc(&P->d_FG, fg, *P));
+    AK_TRY(alloc(&P->d_part, (size_t)P->adj_nrb * P->nalm * 4 * sizeof(double), *P));
+    AK_TRY(alloc(&P->d_tE, (size_t)nrhs * P->nalm * sizeof(double2), *P));
+    AK_TRY(alloc(&P->d_tB, (size_t)nrhs * P->nalm * sizeof(double2), *P));
+    AK_TRY(alloc((void **)&P->d_W, (size_t)nrhs * P->npix * sizeof(double), *P));
+    AK_TRY(alloc((void **)&P->d_red, (size_t)512 * 4 * nrhs * sizeof(double), *P));
+    AK_TRY(alloc((void **)&P->d_scal, (size_t)(64 + 4 * nrhs) * sizeof(double), *P));
+    AK_TRY(alloc((void **)&P->d_flag, 64 * sizeof(int), *P));
+    const size_t vb = (size_t)nrhs * 2 * P->nalm * sizeof(double2);
+    AK_TRY(alloc((void **)&P->d_x, vb, *P));
+    AK_TRY(alloc((void **)&P->d_r, vb, *P));
+    AK_TRY(alloc((void **)&P->d_p, vb, *P));
+    AK_TRY(alloc((void **)&P->d_w, vb, *P));
+    AK_TRY(alloc((void **)&P->d_b, vb, *P));
+    AK_TRY(alloc((void **)&P->d_xs, vb, *P));
+    if (hipHostMalloc((void **)&P->h_pin, 256 * sizeof(double)) != hipSuccess) {
+        P->h_pin = nullptr;
+        free_plan(P);
+        set_error("hipHostMalloc failed");
+        return AKRA_ERR_ALLOC;
+    }
+#undef AK_TRY
+    *out = P;
+    return AKRA_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// operator pieces
+// ---------------------------------------------------------------------------------------------
+static bool plan_fp32(const Plan &P) { return P.prec == AKRA_FP32; }
+
+static akra_status check_launch(const char *what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, what);
+    return AKRA_OK;
+}
+
+// y = K Y^H (W (Y (K x))) + lam x for the single right-hand side `rhs` of stacked [2][nalm] vectors
+// (x, y device, FP64).  W must already be in P.d_W.
+static akra_status apply_H_core(Plan &P, bool fp32, const double *kern_dev, double lam, const double *xE,
+                                const double *xB, double *yE, double *yB, int rhs)
+{
+    launch_prologue(P, fp32, xE, xB, kern_dev, 1);
+    launch_leg_synth(P, fp32, P.d_tE, P.d_tB, P.nalm, 1);
+    launch_ring(P, fp32, 2, nullptr, nullptr, nullptr, nullptr, P.d_W + (int64_t)rhs * P.npix, 1);
+    launch_leg_adj(P, fp32, 0);
+    launch_epilogue(P, fp32, kern_dev, lam, xE, xB, yE, yB);
+    return check_launch("apply_H");
+}
+
+// W from ninv/mask, validated; returns lambda_eff and P for every rhs (host)
+static akra_status setup_weights(Plan &P, const double *ninv, const uint8_t *mask, double lam, std::vector<double> &lam_eff,
+                                 std::vector<double> &pc)
+{
+    if (!ninv || !mask) {
+        set_error("ninv and mask must be device pointers");
+        return AKRA_ERR_ARG;
+    }
+    launch_weights(P, ninv, mask, P.nrhs);
+    akra_status st = check_launch("weights");
+    if (st) return st;
+    AK_HIP(hipMemcpyAsync(P.h_pin, P.d_scal + 8, sizeof(double) * 4 * P.nrhs, hipMemcpyDeviceToHost, P.stream),
+           "hipMemcpyAsync");
+    AK_HIP(hipStreamSynchronize(P.stream), "hipStreamSynchronize");
+    lam_eff.resize(P.nrhs);
+    pc.resize(P.nrhs);
+    for (int r = 0; r < P.nrhs; ++r) {
+        const double sw = P.h_pin[4 * r], sm = P.h_pin[4 * r + 1], nonfin = P.h_pin[4 * r + 2], negs = P.h_pin[4 * r + 3];
+        if (nonfin > 0) {
+            set_error("ninv holds NaN or Inf");
+            return AKRA_ERR_NUMERIC;
+        }
+        if (negs > 0) {
+            set_error("ninv holds negative weights");
+            return AKRA_ERR_ARG;
+        }
+        lam_eff[r] = (sm > 0) ? lam * sw / sm : 0.0;  // lambda <N^-1>_M
+        pc[r] = 1.0 / (sw / (double)P.npix + lam_eff[r]);  // (<M^2 N^-1> + lambda_eff)^-1
+    }
+    return AKRA_OK;
+}
+
+static akra_status kernel_to_device(Plan &P, const double *kernel_l, const double **kdev)
+{
+    if (!kernel_l) {
+        *kdev = P.d_kern;
+        return AKRA_OK;
+    }
+    // a caller-supplied kernel goes into the plan's second kernel table
+    AK_HIP(hipMemcpyAsync(P.d_kuser, kernel_l, sizeof(double) * (P.lmax + 1), hipMemcpyHostToDevice, P.stream),
+           "hipMemcpyAsync");
+    *kdev = P.d_kuser;
+    return AKRA_OK;
+}
+
+static double read_scalar(Plan &P, const double *dev, hipError_t *err)
+{
+    *err = hipMemcpyAsync(P.h_pin, dev, sizeof(double), hipMemcpyDeviceToHost, P.stream);
+    if (*err == hipSuccess) *err = hipStreamSynchronize(P.stream);
+    return P.h_pin[0];
+}
+
+__global__ void k_cg_alpha(double *scal, int *flag)
+{
+    // scal[0] = rz, scal[1] = pw, scal[2] = alpha
+    const double pw = scal[1];
+    if (!(pw > 0.0) || !isfinite(pw)) {
+        flag[0] = 1;
+        scal[2] = 0.0;
+    } else {
+        scal[2] = scal[0] / pw;
+    }
+}
+
+__global__ void k_cg_beta(double *scal, double pc)
+{
+    // scal[3] = rr (new), scal[0] = rz (old) -> scal[4] = beta, scal[0] = rz new
+    const double rz = pc * scal[3];
+    scal[4] = (scal[0] > 0.0) ? rz / scal[0] : 0.0;
+    scal[0] = rz;
+}
+
+__global__ void k_set(double *p, double v) { *p = v; }
+
+// PCG on the stacked [2][nalm] vectors of right-hand side `rhs`.  b must be in P.d_b.
+static akra_status cg_core(Plan &P, const akra_cg_opts &o, const double *kern_dev, double lam_eff, double pc, int rhs,
+                           akra_cg_info *info)
+{
+    const int64_t nc = 2 * P.nalm;
+    double *b = P.d_b, *x = P.d_x, *r = P.d_r, *p = P.d_p, *w = P.d_w;
+    double *bE = b, *bB = b + 2 * P.nalm;
+    auto E = [&](double *v) { return v; };
+    auto B = [&](double *v) { return v + 2 * P.nalm; };
+    hipError_t he;
+    const bool fp32 = plan_fp32(P);
+    info->lambda_eff = lam_eff;
+    info->precond = pc;
+    info->iters = 0;
+    info->fp64_applies = 0;
+
+    launch_dot(P, b, b, P.d_scal + 5, nc);
+    const double bn2 = read_scalar(P, P.d_scal + 5, &he);
+    if (he != hipSuccess) return hip_fail(he, "cg");
+    if (!std::isfinite(bn2)) {
+        set_error("right-hand side is not finite");
+        return AKRA_ERR_NUMERIC;
+    }
+    if (bn2 == 0.0) {
+        AK_HIP(hipMemsetAsync(x, 0, sizeof(double2) * nc, P.stream), "hipMemsetAsync");
+        AK_HIP(hipStreamSynchronize(P.stream), "sync");
+        info->rel_resid = info->rel_resid_true = 0.0;
+        return AKRA_OK;
+    }
+    const double bn = std::sqrt(bn2);
+    // x0, r0 = b - H x0
+    if (o.use_x0) {
+        akra_status st = apply_H_core(P, false, kern_dev, lam_eff, E(x), B(x), E(w), B(w), rhs);
+        if (st) return st;
+        info->fp64_applies++;
+        AK_HIP(hipMemcpyAsync(r, b, sizeof(double2) * nc, hipMemcpyDeviceToDevice, P.stream), "copy");
+        launch_axpby(P, r, -1.0, w, 1.0, nc);
+    } else {
+        AK_HIP(hipMemsetAsync(x, 0, sizeof(double2) * nc, P.stream), "memset");
+        AK_HIP(hipMemcpyAsync(r, b, sizeof(double2) * nc, hipMemcpyDeviceToDevice, P.stream), "copy");
+    }
+    (void)bE;
+    (void)bB;
+    AK_HIP(hipMemsetAsync(P.d_flag, 0, sizeof(int), P.stream), "memset");
+    launch_dot(P, r, r, P.d_scal + 3, nc);
+    double rr = read_scalar(P, P.d_scal + 3, &he);
+    if (he != hipSuccess) return hip_fail(he, "cg");
+    // p = P r, rz = P <r, r>
+    AK_HIP(hipMemsetAsync(p, 0, sizeof(double2) * nc, P.stream), "memset");
+    k_set<<<1, 1, 0, P.stream>>>(P.d_scal + 0, 0.0);
+    k_cg_beta<<<1, 1, 0, P.stream>>>(P.d_scal, pc);
+    k_set<<<1, 1, 0, P.stream>>>(P.d_scal + 4, 0.0);
+    launch_cg_p(P, p, r, P.d_scal + 4, pc, nc);
+
+    double rel = std::sqrt(rr) / bn;
+    double rmax = std::sqrt(rr);
+    bool fresh = true;  // r is a true (FP64) residual
+    int it = 0;
+    akra_status result = AKRA_NOT_CONVERGED;
+    while (true) {
+        if (rel < o.tol) {
+            if (!fp32 || fresh) {
+                result = AKRA_OK;
+                break;
+            }
+            // recursive FP32 residual says converged: confirm with the true residual
+            akra_status st = apply_H_core(P, false, kern_dev, lam_eff, E(x), B(x), E(w), B(w), rhs);
+            if (st) return st;
+            info->fp64_applies++;
+            AK_HIP(hipMemcpyAsync(r, b, sizeof(double2) * nc, hipMemcpyDeviceToDevice, P.stream), "copy");
+            launch_axpby(P, r, -1.0, w, 1.0, nc);
+            launch_dot(P, r, r, P.d_scal + 3, nc);
+            rr = read_scalar(P, P.d_scal + 3, &he);
+            if (he != hipSuccess) return hip_fail(he, "cg");
+            rel = std::sqrt(rr) / bn;
+            rmax = std::sqrt(rr);
+            fresh = true;
+            if (rel < o.tol) {
+                result = AKRA_OK;
+                break;
+            }
+            k_cg_beta<<<1, 1, 0, P.stream>>>(P.d_scal, pc);
+            launch_cg_p(P, p, r, P.d_scal + 4, pc, nc);
+        }
+        if (it >= o.maxiter) break;
+        // w = H p
+        akra_status st = apply_H_core(P, fp32, kern_dev, lam_eff, E(p), B(p), E(w), B(w), rhs);
+        if (st) return st;
+        launch_dot(P, p, w, P.d_scal + 1, nc);
+        k_cg_alpha<<<1, 1, 0, P.stream>>>(P.d_scal, P.d_flag);
+        launch_cg_xr(P, x, r, p, w, P.d_scal + 2, nc);
+        launch_dot(P, r, r, P.d_scal + 3, nc);
+        AK_HIP(hipMemcpyAsync(P.h_pin, P.d_scal + 3, sizeof(double), hipMemcpyDeviceToHost, P.stream), "copy");
+        AK_HIP(hipMemcpyAsync(P.h_pin + 1, P.d_flag, sizeof(int), hipMemcpyDeviceToHost, P.stream), "copy");
+        AK_HIP(hipStreamSynchronize(P.stream), "sync");
+        rr = P.h_pin[0];
+        int flag;
+        std::memcpy(&flag, P.h_pin + 1, sizeof(int));
+        ++it;
+        fresh = false;
+        if (flag || !std::isfinite(rr)) {
+            set_error("CG breakdown: p^T H p <= 0 or non-finite scalar");
+            info->iters = it;
+            return AKRA_ERR_NUMERIC;
+        }
+        rel = std::sqrt(rr) / bn;
+        if (fp32 && std::sqrt(rr) < o.reliable_delta * rmax && rel >= o.tol) {
+            // reliable update: replace the recursive residual by b - H64 x
+            st = apply_H_core(P, false, kern_dev, lam_eff, E(x), B(x), E(w), B(w), rhs);
+            if (st) return st;
+            info->fp64_applies++;
+            AK_HIP(hipMemcpyAsync(r, b, sizeof(double2) * nc, hipMemcpyDeviceToDevice, P.stream), "copy");
+            launch_axpby(P, r, -1.0, w, 1.0, nc);
+            launch_dot(P, r, r, P.d_scal + 3, nc);
+            rr = read_scalar(P, P.d_scal + 3, &he);
+            if (he != hipSuccess) return hip_fail(he, "cg");
+            rel = std::sqrt(rr) / bn;
+            rmax = std::sqrt(rr);
+            fresh = true;
+        }
+        if (o.resid_hist && it - 1 < o.resid_hist_len) o.resid_hist[it - 1] = rel;
+        if (rel < o.tol && (!fp32 || fresh)) {
+            result = AKRA_OK;
+            break;
+        }
+        if (rel < o.tol) continue;  // FP32: confirm at the top of the loop
+        k_cg_beta<<<1, 1, 0, P.stream>>>(P.d_scal, pc);
+        launch_cg_p(P, p, r, P.d_scal + 4, pc, nc);
+    }
+    info->iters = it;
+    info->rel_resid = rel;
+    // true residual in FP64
+    {
+        akra_status st = apply_H_core(P, false, kern_dev, lam_eff, E(x), B(x), E(w), B(w), rhs);
+        if (st) return st;
+        info->fp64_applies++;
+        AK_HIP(hipMemcpyAsync(P.d_xs, b, sizeof(double2) * nc, hipMemcpyDeviceToDevice, P.stream), "copy");
+        launch_axpby(P, P.d_xs, -1.0, w, 1.0, nc);
+        launch_dot(P, P.d_xs, P.d_xs, P.d_scal + 6, nc);
+        const double tr = read_scalar(P, P.d_scal + 6, &he);
+        if (he != hipSuccess) return hip_fail(he, "cg");
+        info->rel_resid_true = std::sqrt(tr) / bn;
+    }
+    AK_HIP(hipStreamSynchronize(P.stream), "sync");
+    if (result == AKRA_NOT_CONVERGED) set_error("maxiter reached");
+    return result;
+}
+
+}  // namespace akra
+
+using namespace akra;
+
+// =================================================================================================
+// C ABI
+// =================================================================================================
+extern "C" {
+
+struct akra_plan_s {
+    Plan *P;
+};
+
+const char *akra_last_error(void) { return g_err.c_str(); }
+
+void akra_cg_opts_default(akra_cg_opts *o)
+{
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->lambda = 1e-3;
+    o->tol = 1e-3;
+    o->maxiter = 1000;
+    o->use_x0 = 0;
+    o->kernel_l = nullptr;
+    o->reliable_delta = 0.1;
+}
+
+akra_status akra_plan_create(int nside, int lmax, int nrhs, int precision, void *hip_stream, akra_plan *out)
+{
+    if (!out) {
+        set_error("out is NULL");
+        return AKRA_ERR_ARG;
+    }
+    *out = nullptr;
+    Plan *P = nullptr;
+    akra_status st;
+    try {
+        st = create(nside, lmax, nrhs, precision, hip_stream, &P);
+    } catch (const std::bad_alloc &) {
+        set_error("host allocation failed");
+        return AKRA_ERR_ALLOC;
+    }
+    if (st != AKRA_OK) return st;
+    *out = new akra_plan_s{P};
+    return AKRA_OK;
+}
+
+void akra_plan_destroy(akra_plan plan)
+{
+    if (!plan) return;
+    (void)hipStreamSynchronize(plan->P->stream);
+    free_plan(plan->P);
+    delete plan;
+}
+
+int64_t akra_plan_device_bytes(akra_plan plan) { return plan ? plan->P->device_bytes : 0; }
+
+#define AK_PLAN()                          \
+    if (!plan) {                           \
+        set_error("plan is NULL");         \
+        return AKRA_ERR_ARG;               \
+    }                                      \
+    Plan &P = *plan->P
+
+akra_status akra_synth2(akra_plan plan, const double *almE, const double *almB, double *g1, double *g2)
+{
+    AK_PLAN();
+    if (!almE || !almB || !g1 || !g2) {
+        set_error("null pointer argument");
+        return AKRA_ERR_ARG;
+    }
+    const bool fp32 = plan_fp32(P);
+    if (fp32) {
+        launch_prologue(P, true, almE, almB, nullptr, P.nrhs);
+        launch_leg_synth(P, true, P.d_tE, P.d_tB, P.nalm, P.nrhs);
+    } else {
+        launch_leg_synth(P, false, almE, almB, P.nalm, P.nrhs);
+    }
+    launch_ring(P, fp32, 0, nullptr, nullptr, g1, g2, nullptr, P.nrhs);
+    return check_launch("synth2");
+}
+
+akra_status akra_adjoint2(akra_plan plan, const double *g1, const double *g2, double *almE, double *almB)
+{
+    AK_PLAN();
+    if (!almE || !almB || !g1 || !g2) {
+        set_error("null pointer argument");
+        return AKRA_ERR_ARG;
+    }
+    const bool fp32 = plan_fp32(P);
+    launch_ring(P, fp32, 1, g1, g2, nullptr, nullptr, nullptr, P.nrhs);
+    for (int r = 0; r < P.nrhs; ++r) {
+        launch_leg_adj(P, fp32, r);
+        launch_epilogue(P, fp32, nullptr, 0.0, nullptr, nullptr, almE + (int64_t)r * 2 * P.nalm,
+                        almB + (int64_t)r * 2 * P.nalm);
+    }
+    return check_launch("adjoint2");
+}
+
+akra_status akra_apply_H(akra_plan plan, const double *ninv, const uint8_t *mask, const double *kernel_l,
+                         double lambda_eff, const double *xE, const double *xB, double *yE, double *yB)
+{
+    AK_PLAN();
+    if (!xE || !xB || !yE || !yB) {
+        set_error("null pointer argument");
+        return AKRA_ERR_ARG;
+    }
+    std::vector<double> le, pc;
+    akra_status st = setup_weights(P, ninv, mask, 0.0, le, pc);
+    if (st) return st;
+    const double *kd;
+    st = kernel_to_device(P, kernel_l, &kd);
+    if (st) return st;
+    const bool fp32 = plan_fp32(P);
+    for (int r = 0; r < P.nrhs; ++r) {
+        const int64_t o = (int64_t)r * 2 * P.nalm;
+        st = apply_H_core(P, fp32, kd, lambda_eff, xE + o, xB + o, yE + o, yB + o, r);
+        if (st) return st;
+    }
+    return AKRA_OK;
+}
+
+static akra_status rhs_core(Plan &P, const double *g1, const double *g2, const double *kd, double *bE, double *bB)
+{
+    const bool fp32 = plan_fp32(P);
+    // W gamma_obs, adjoint ring stage in the plan precision would lose FP64 accuracy of b for the
+    // refined solve: the right-hand side is always formed in FP64.
+    (void)fp32;
+    launch_ring(P, false, 1, g1, g2, nullptr, nullptr, P.d_W, P.nrhs);
+    for (int r = 0; r < P.nrhs; ++r) {
+        launch_leg_adj(P, false, r);
+        launch_epilogue(P, false, kd, 0.0, nullptr, nullptr, bE + (int64_t)r * 2 * P.nalm, bB + (int64_t)r * 2 * P.nalm);
+    }
+    return check_launch("rhs");
+}
+
+akra_status akra_rhs(akra_plan plan, const double *g1, const double *g2, const double *ninv, const uint8_t *mask,
+                     const double *kernel_l, double *bE, double *bB)
+{
+    AK_PLAN();
+    if (!g1 || !g2 || !bE || !bB) {
+        set_error("null pointer argument");
+        return AKRA_ERR_ARG;
+    }
+    std::vector<double> le, pc;
+    akra_status st = setup_weights(P, ninv, mask, 0.0, le, pc);
+    if (st) return st;
+    const double *kd;
+    st = kernel_to_device(P, kernel_l, &kd);
+    if (st) return st;
+    return rhs_core(P, g1, g2, kd, bE, bB);
+}
+
+static akra_status solve_common(Plan &P, const double *g1, const double *g2, const double *ninv, const uint8_t *mask,
+                                const double *bE, const double *bB, const akra_cg_opts *opts, double *xE, double *xB,
+                                akra_cg_info *info_out)
+{
+    auto t0 = std::chrono::steady_clock::now();
+    akra_cg_opts o;
+    akra_cg_opts_default(&o);
+    if (opts) o = *opts;
+    if (!(o.tol > 0) || o.maxiter < 0 || !(o.lambda >= 0) || !(o.reliable_delta > 0 && o.reliable_delta < 1)) {
+        set_error("invalid solver options");
+        return AKRA_ERR_ARG;
+    }
+    akra_cg_info info{};
+    std::vector<double> le, pc;
+    akra_status st = setup_weights(P, ninv, mask, o.lambda, le, pc);
+    if (st) return st;
+    const double *kd;
+    st = kernel_to_device(P, o.kernel_l, &kd);
+    if (st) return st;
+    akra_status worst = AKRA_OK;
+    for (int r = 0; r < P.nrhs; ++r) {
+        const int64_t off = (int64_t)r * 2 * P.nalm;
+        // b into the solver's stacked [E | B] buffer
+        if (g1) {
+            launch_ring(P, false, 1, g1 + r * P.npix, g2 + r * P.npix, nullptr, nullptr, P.d_W + r * P.npix, 1);
+            launch_leg_adj(P, false, 0);
+            launch_epilogue(P, false, kd, 0.0, nullptr, nullptr, P.d_b, P.d_b + 2 * P.nalm);
+        } else {
+            AK_HIP(hipMemcpyAsync(P.d_b, bE + off, sizeof(double2) * P.nalm, hipMemcpyDeviceToDevice, P.stream), "copy");
+            AK_HIP(hipMemcpyAsync(P.d_b + 2 * P.nalm, bB + off, sizeof(double2) * P.nalm, hipMemcpyDeviceToDevice,
+                                  P.stream),
+                   "copy");
+        }
+        // x in and out through the solver's stacked [E | B] iterate d_x
+        if (o.use_x0) {
+            AK_HIP(hipMemcpyAsync(P.d_x, xE + off, sizeof(double2) * P.nalm, hipMemcpyDeviceToDevice, P.stream), "copy");
+            AK_HIP(hipMemcpyAsync(P.d_x + 2 * P.nalm, xB + off, sizeof(double2) * P.nalm, hipMemcpyDeviceToDevice,
+                                  P.stream),
+                   "copy");
+        }
+        st = cg_core(P, o, kd, le[r], pc[r], r, &info);
+        if (st == AKRA_OK || st == AKRA_NOT_CONVERGED) {
+            AK_HIP(hipMemcpyAsync(xE + off, P.d_x, sizeof(double2) * P.nalm, hipMemcpyDeviceToDevice, P.stream), "copy");
+            AK_HIP(hipMemcpyAsync(xB + off, P.d_x + 2 * P.nalm, sizeof(double2) * P.nalm, hipMemcpyDeviceToDevice,
+                                  P.stream),
+                   "copy");
+            AK_HIP(hipStreamSynchronize(P.stream), "sync");
+        }
+        if (st != AKRA_OK && st != AKRA_NOT_CONVERGED) return st;
+        if (st == AKRA_NOT_CONVERGED) worst = st;
+    }
+    info.status = worst;
+    info.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (info_out) *info_out = info;
+    return worst;
+}
+
+akra_status akra_cg_solve(akra_plan plan, const double *g1, const double *g2, const double *ninv, const uint8_t *mask,
+                          const akra_cg_opts *opts, double *xE, double *xB, akra_cg_info *info)
+{
+    AK_PLAN();
+    if (!g1 || !g2 || !xE || !xB) {
+        set_error("null pointer argument");
+        return AKRA_ERR_ARG;
+    }
+    return solve_common(P, g1, g2, ninv, mask, nullptr, nullptr, opts, xE, xB, info);
+}
+
+akra_status akra_cg_solve_b(akra_plan plan, const double *ninv, const uint8_t *mask, const double *bE, const double *bB,
+                            const akra_cg_opts *opts, double *xE, double *xB, akra_cg_info *info)
+{
+    AK_PLAN();
+    if (!bE || !bB || !xE || !xB) {
+        set_error("null pointer argument");
+        return AKRA_ERR_ARG;
+    }
+    return solve_common(P, nullptr, nullptr, ninv, mask, bE, bB, opts, xE, xB, info);
+}
+
+}  // extern "C"
