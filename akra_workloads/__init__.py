@@ -131,7 +131,7 @@ def _punch_holes(nside, mask, vec, centres, radii):
         mask[lo:hi] &= ~sub
 
 
-def depth_modulation(nside, seed_base, vec=None, nwaves=64, kscale=20.0):
+def depth_modulation(nside, seed_base, vec=None, nwaves=16, kscale=20.0):
     """Smooth multiplicative depth u_p = 0.5 + Phi(g_p) in [0.5, 1.5]; g is a unit-variance smooth
     field made of random plane waves exp(i k.n) with |k| ~ kscale evaluated on the sphere."""
     g = rng(seed_base, S_DEPTH)
@@ -139,9 +139,11 @@ def depth_modulation(nside, seed_base, vec=None, nwaves=64, kscale=20.0):
     k = g.normal(size=(nwaves, 3))
     k *= (kscale * g.uniform(0.5, 1.0, nwaves) / np.linalg.norm(k, axis=1))[:, None]
     phase = g.uniform(0, 2 * np.pi, nwaves)
-    field = np.zeros(vec.shape[1])
+    v32 = vec.astype(np.float32)
+    field = np.zeros(vec.shape[1], np.float32)
     for i in range(nwaves):
-        field += np.cos(k[i] @ vec + phase[i])
+        field += np.cos(k[i].astype(np.float32) @ v32 + np.float32(phase[i]))
+    field = field.astype(np.float64)
     field = (field - field.mean()) / field.std()
     from scipy.special import ndtr
     return 0.5 + ndtr(field)

@@ -148,6 +148,49 @@ akra_status akra_cg_solve(akra_plan plan, const double *g1, const double *g2, co
 akra_status akra_cg_solve_b(akra_plan plan, const double *ninv, const uint8_t *mask, const double *bE,
                             const double *bB, const akra_cg_opts *opts, double *xE, double *xB, akra_cg_info *info);
 
+/*
+ * Step-wise PCG on the plan's device-resident solver state (first right-hand side of the plan):
+ *   akra_cg_start  forms b = K Y^H (W gamma_obs), lambda_eff and P as akra_cg_solve does, sets x0 = 0,
+ *                  r0 = b, p0 = P r0 (one host synchronisation).  opts->use_x0 must be 0.
+ *   akra_cg_step   runs nsteps PCG iterations (Sec. II.B inversion problem) in the plan precision,
+ *                  stream-ordered with no host synchronisation and no convergence test:
+ *                  w = H p, alpha = rz/<p,w>, x += alpha p, r -= alpha w, beta = P<r,r>/rz, p = P r + beta p.
+ *   akra_cg_state  synchronises and returns ||r||/||b|| of the recursive residual, the iteration count,
+ *                  and (if xE, xB are non-NULL device pointers) copies the iterate.  AKRA_ERR_NUMERIC on
+ *                  breakdown.
+ */
+akra_status akra_cg_start(akra_plan plan, const double *g1, const double *g2, const double *ninv, const uint8_t *mask,
+                          const akra_cg_opts *opts);
+akra_status akra_cg_step(akra_plan plan, int nsteps);
+akra_status akra_cg_state(akra_plan plan, double *rel_resid, int *iters, double *xE, double *xB);
+
+/*
+ * Stage timing: when on, every operator apply records HIP events on the plan stream around its
+ * stages; akra_plan_stage_times synchronises, returns the summed milliseconds and launch counts per
+ * stage in HOST arrays of AKRA_NSTAGES entries, and resets the counters.
+ * Stages: 0 prologue (K_l), 1 Legendre synthesis, 2 ring stage (DFTs and weights), 3 Legendre
+ * adjoint, 4 epilogue (E/B combination, K_l, lambda_eff), 5 CG vector updates.
+ */
+#define AKRA_NSTAGES 6
+
+/*
+ * Launch shapes of the Legendre kernels (chosen by the autotuner; results do not depend on them
+ * beyond the rounding order of the adjoint's ring sums):
+ *   syn_variant  0 two steps per trip, 1 four steps per trip with look-ahead loads
+ *   syn_rings    ring pairs per lane of the synthesis (1, 2, 4)
+ *   adj_rings, adj_waves, adj_chunk   ring pairs per lane, waves per workgroup and l-chunk of the
+ *                adjoint: (1,1,8) (1,2,8) (1,4,8) (2,2,8) (2,4,8) (4,2,8) (4,4,8) (8,1,8) (8,2,8)
+ *                (2,4,4) (4,2,4) (4,4,4) (8,1,4).  A shape covering fewer ring pairs per workgroup than
+ *                the plan's partial-sum buffer allows (at least 512 pairs per workgroup when
+ *                Nside > 512) is rejected with AKRA_ERR_ARG.
+ * akra_plan_get_tuning writes the five current values to out5 (HOST).
+ */
+akra_status akra_plan_set_tuning(akra_plan plan, int syn_variant, int syn_rings, int adj_rings, int adj_waves,
+                                 int adj_chunk);
+akra_status akra_plan_get_tuning(akra_plan plan, int *out5);
+akra_status akra_plan_set_timing(akra_plan plan, int on);
+akra_status akra_plan_stage_times(akra_plan plan, double *ms, int *calls);
+
 #ifdef __cplusplus
 }
 #endif

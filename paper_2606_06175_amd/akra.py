@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libakra.so")
 _lib = None
 
 AKRA_OK, AKRA_ERR_ARG, AKRA_ERR_ALLOC, AKRA_ERR_HIP, AKRA_ERR_NUMERIC, AKRA_NOT_CONVERGED = range(6)
+STAGES = ("prologue", "leg_synth", "ring", "leg_adj", "epilogue", "cg_vec")
 STATUS_NAMES = {0: "AKRA_OK", 1: "AKRA_ERR_ARG", 2: "AKRA_ERR_ALLOC", 3: "AKRA_ERR_HIP", 4: "AKRA_ERR_NUMERIC",
                 5: "AKRA_NOT_CONVERGED"}
 PRECISIONS = {"fp64": 0, "fp32": 1}
@@ -65,8 +66,16 @@ def lib():
     L.akra_rhs.argtypes = [vp, vp, vp, vp, vp, dp, vp, vp]
     L.akra_cg_solve.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(CgOpts), vp, vp, ctypes.POINTER(CgInfo)]
     L.akra_cg_solve_b.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(CgOpts), vp, vp, ctypes.POINTER(CgInfo)]
+    L.akra_cg_start.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(CgOpts)]
+    L.akra_cg_step.argtypes = [vp, ctypes.c_int]
+    L.akra_cg_state.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int), vp, vp]
+    L.akra_plan_set_timing.argtypes = [vp, ctypes.c_int]
+    L.akra_plan_set_tuning.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    L.akra_plan_get_tuning.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
+    L.akra_plan_stage_times.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int)]
     for f in ("akra_plan_create", "akra_synth2", "akra_adjoint2", "akra_apply_H", "akra_rhs", "akra_cg_solve",
-              "akra_cg_solve_b"):
+              "akra_cg_solve_b", "akra_cg_start", "akra_cg_step", "akra_cg_state", "akra_plan_set_timing",
+              "akra_plan_stage_times", "akra_plan_set_tuning", "akra_plan_get_tuning"):
         getattr(L, f).restype = ctypes.c_int
     _lib = L
     return L
@@ -92,7 +101,8 @@ def _kernel_arg(kernel):
 class Plan:
     """A libakra plan: HEALPix nside, band limit lmax, nrhs right-hand sides, FP64 or FP32 transforms."""
 
-    def __init__(self, nside, lmax, nrhs=1, precision="fp64", device=None, stream=None):
+    def __init__(self, nside, lmax, nrhs=1, precision="fp64", device=None, stream=None, tuned=True):
+        """tuned: apply the launch shapes cached by the autotuner (tune.py) for this size, if any."""
         L = lib()
         self.nside, self.lmax, self.nrhs = int(nside), int(lmax), int(nrhs)
         self.precision = precision
@@ -108,6 +118,12 @@ class Plan:
             _check(L.akra_plan_create(self.nside, self.lmax, self.nrhs, PRECISIONS[precision],
                                       ctypes.c_void_p(s.cuda_stream), ctypes.byref(h)))
         self._h = h
+        if tuned:
+            from .tune import lookup
+            e = lookup(self.nside, self.lmax, precision)
+            if e:
+                self.set_tuning(e["syn_variant"], e["syn_rings"], e["adj_rings"], e["adj_waves"],
+                                e.get("adj_chunk", 8))
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -246,3 +262,52 @@ class Plan:
         if st != AKRA_OK and (st != AKRA_NOT_CONVERGED or raise_not_converged):
             _check(st)
         return xE, xB, self._info(inf, keep, hist_len)
+
+    # -- step-wise PCG ------------------------------------------------------------------------
+    def cg_start(self, g1, g2, ninv, mask, lam=1e-3, kernel=None):
+        """Form b, lambda_eff and P and set x0 = 0 (first right-hand side of the plan)."""
+        g1, g2 = self._map(g1, "g1"), self._map(g2, "g2")
+        ninv = self._map(ninv, "ninv")
+        mask = self._map(mask, "mask", torch.uint8, per_rhs=False)
+        o, keep = self._opts(1e-3, 0, lam, None, kernel, 0.1, 0)
+        with torch.cuda.device(self.device):
+            _check(lib().akra_cg_start(self._h, g1.data_ptr(), g2.data_ptr(), ninv.data_ptr(), mask.data_ptr(),
+                                       ctypes.byref(o)))
+
+    def cg_step(self, n=1):
+        """n PCG iterations, stream-ordered, no host synchronisation."""
+        with torch.cuda.device(self.device):
+            _check(lib().akra_cg_step(self._h, int(n)))
+
+    def cg_state(self, copy_x=False):
+        rel = ctypes.c_double()
+        it = ctypes.c_int()
+        xE = xB = None
+        if copy_x:
+            xE, xB = torch.empty(self.nalm, dtype=torch.complex128, device=self.device), \
+                torch.empty(self.nalm, dtype=torch.complex128, device=self.device)
+        with torch.cuda.device(self.device):
+            _check(lib().akra_cg_state(self._h, ctypes.byref(rel), ctypes.byref(it),
+                                       xE.data_ptr() if copy_x else None, xB.data_ptr() if copy_x else None))
+        return (rel.value, it.value, xE, xB) if copy_x else (rel.value, it.value)
+
+    # -- stage timing -------------------------------------------------------------------------
+    def set_timing(self, on=True):
+        _check(lib().akra_plan_set_timing(self._h, 1 if on else 0))
+
+    def stage_times(self):
+        """{stage: (total_ms, launches)} since the last call; synchronises the plan stream."""
+        ms = (ctypes.c_double * len(STAGES))()
+        calls = (ctypes.c_int * len(STAGES))()
+        _check(lib().akra_plan_stage_times(self._h, ms, calls))
+        return {s: (ms[i], calls[i]) for i, s in enumerate(STAGES)}
+
+    # -- launch shapes ------------------------------------------------------------------------
+    def set_tuning(self, syn_variant, syn_rings, adj_rings, adj_waves, adj_chunk=8):
+        _check(lib().akra_plan_set_tuning(self._h, int(syn_variant), int(syn_rings), int(adj_rings),
+                                          int(adj_waves), int(adj_chunk)))
+
+    def get_tuning(self):
+        v = (ctypes.c_int * 5)()
+        _check(lib().akra_plan_get_tuning(self._h, v))
+        return tuple(v)

@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -16,6 +17,9 @@ namespace akra {
 // 2^-(UNIT/2) and contributes nothing; the mantissa is rescaled by 2^-UNIT whenever it exceeds
 // 2^(UNIT/2), and k then grows by one.  Once k == 0 the mantissa is the value itself.
 // ------------------------------------------------------------------------------------------------
+// padding (in entries) after the coefficient table and the kernel-scaled alm buffers
+constexpr int ALM_PAD = 64;
+
 template <typename T> struct Scale;
 template <> struct Scale<double> {
     static constexpr int UNIT = 512;
@@ -67,13 +71,15 @@ struct Plan {
     std::vector<RingInfo> h_rings;
 
     // Legendre launch shapes
-    int syn_R = 1, syn_groups = 1;
-    int adj_R = 1, adj_W = 1, adj_nrb = 1;
+    int syn_R = 1, syn_V = 1, syn_groups = 1;
+    int adj_R = 1, adj_W = 1, adj_L = 8, adj_nrb = 1;
+    size_t part_rb_cap = 1;  // ring blocks the partial-sum buffer holds
 
     // workspaces (sized for FP64; FP32 views reuse them)
     void *d_FG = nullptr;       // [nrhs][nrings][lmax+1][2] complex
     void *d_part = nullptr;     // [nrb][nalm][4] adjoint partial sums
-    void *d_tE = nullptr, *d_tB = nullptr;  // [nrhs][nalm] complex, kernel-scaled input
+    void *d_rec = nullptr;      // [nrhs][nalm + ALM_PAD] synthesis records (64 B in FP64)
+    int64_t rec_stride = 0;     // records per right-hand side
     double *d_W = nullptr;      // [nrhs][npix] weights
     double *d_kern = nullptr;   // [lmax+1]
     double *d_kuser = nullptr;  // [lmax+1] caller-supplied kernel
@@ -84,6 +90,18 @@ struct Plan {
     double *d_x = nullptr, *d_r = nullptr, *d_p = nullptr, *d_w = nullptr, *d_b = nullptr, *d_xs = nullptr;
     double *h_pin = nullptr;    // pinned host scalars
     int64_t device_bytes = 0;
+
+    // solver state of the right-hand side in progress
+    bool cg_ready = false;
+    int cg_rhs = 0, cg_iters = 0, cg_fp64_applies = 0;
+    double cg_bn = 0, cg_rr = 0, cg_lam = 0, cg_pc = 1;
+    const double *cg_kern = nullptr;
+
+    // stage timing with HIP events on the plan stream
+    bool timing = false;
+    std::vector<std::array<hipEvent_t, 2>> ev_pool;
+    std::vector<int> ev_stage;
+    int ev_used = 0;
 };
 
 // error handling
@@ -91,10 +109,10 @@ void set_error(const std::string &msg);
 akra_status hip_fail(hipError_t e, const char *what);
 
 // ---- kernel launchers (akra_kernels.hip) -------------------------------------------------------
-// kernel-scaled prologue: out = K_l * x (Im(a_l0) dropped), converted to the transform precision
+// prologue: records {a, b, g, 0, K_l x_E, K_l x_B} per (l, m) in the transform precision (Im(a_l0) dropped)
 void launch_prologue(Plan &P, bool fp32, const double *xE, const double *xB, const double *kern, int nrhs);
-// Legendre synthesis of the prologue buffers (d_tE, d_tB) or of user FP64 input into d_FG
-void launch_leg_synth(Plan &P, bool fp32, const void *aE, const void *aB, int64_t alm_stride, int nrhs);
+// Legendre synthesis of the prologue's records (d_rec) into d_FG
+void launch_leg_synth(Plan &P, bool fp32, int nrhs);
 // ring stage: mode 0 = F -> maps, 1 = maps -> G, 2 = F -> W -> G (in place)
 void launch_ring(Plan &P, bool fp32, int mode, const double *g1, const double *g2, double *o1, double *o2,
                  const double *W, int nrhs);
@@ -114,5 +132,6 @@ void launch_cg_p(Plan &P, double *p, const double *r, const double *beta_dev, do
 void launch_axpby(Plan &P, double *y, double a, const double *x, double b, int64_t n_complex);
 void launch_scalar_div(Plan &P, double *out, const double *num, const double *den);
 bool pow2(int n);
+bool adj_shape_supported(int r, int w, int l);
 
 }  // namespace akra

@@ -78,6 +78,19 @@ template <typename T> __device__ __forceinline__ T scale_down();
 template <> __device__ __forceinline__ double scale_down<double>() { return 0x1p-512; }
 template <> __device__ __forceinline__ float scale_down<float>() { return 0x1p-64f; }
 
+// A read-only pointer that is the same in every lane, made explicit for the compiler: the value is
+// taken from the first lane and the result lives in the constant address space, so uniform loads
+// through it become scalar loads.
+template <typename P> using const_as = const __attribute__((address_space(4))) P;
+template <typename P> __device__ __forceinline__ const_as<P> *uniform_ptr(const P *p)
+{
+    const uint64_t v = (uint64_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (const_as<P> *)(((uint64_t)hi << 32) | lo);
+}
+
+// wave-uniform "any lane"
 __device__ __forceinline__ bool wave_any(bool p) { return __ballot(p) != 0ull; }
 
 // ================================================================================================
@@ -88,32 +101,66 @@ __device__ __forceinline__ bool wave_any(bool p) { return __ballot(p) != 0ull; }
 //   F(m) = -(sum 2lambda (aE + i aB)),  F(-m) = -(sum -2lambda (conj aE + i conj aB)).
 // One wave handles 64*R ring pairs of one m; per-l data (alm, coefficients) are wave-uniform.
 // ================================================================================================
-template <typename T, int R, bool MASK>
-__device__ __forceinline__ void syn_step(const T *__restrict__ aE, const T *__restrict__ aB,
-                                         const typename CoefT<T>::type *__restrict__ cf, int l, bool m0, T (&x)[R],
-                                         T (&c2)[R], T (&p2)[R], T (&cm)[R], T (&pm)[R], const int (&k)[R],
-                                         T (&acc)[8][R])
+// Per-(l, m) wave-uniform input of the synthesis, written by the prologue: the recurrence
+// coefficients next to the kernel-scaled alm (Im(a_l0) zeroed), one record of 8 values so that a
+// step is a single scalar load.  The record buffer is padded so look-ahead loads stay in bounds.
+template <typename T> struct alignas(8 * sizeof(T)) SynRec {
+    T a, b, g, pad, er, ei, br, bi;
+};
+template <typename T> using SynIn = SynRec<T>;
+
+template <typename T> __device__ __forceinline__ SynRec<T> ld_rec(const_as<SynRec<T>> *p)
 {
-    const T er = aE[2 * l], br = aB[2 * l];
-    const T ei = m0 ? (T)0 : aE[2 * l + 1], bi = m0 ? (T)0 : aB[2 * l + 1];
-    const auto c = cf[l];
+    SynRec<T> r;
+    r.a = p->a;
+    r.b = p->b;
+    r.g = p->g;
+    r.pad = (T)0;
+    r.er = p->er;
+    r.ei = p->ei;
+    r.br = p->br;
+    r.bi = p->bi;
+    return r;
+}
+
+
+template <typename T>
+__device__ __forceinline__ SynIn<T> syn_load(const SynRec<T> *__restrict__ rec, int l)
+{
+    return rec[l];
+}
+
+// XCD-aware placement: workgroups are dealt to the 8 XCDs round-robin, so all blocks of one m
+// are mapped to blocks with the same index mod 8 (they share that XCD's L2 for the per-m data),
+// and each XCD walks its m values in increasing order (decreasing work).
+__device__ __forceinline__ void xcd_map(int b, int nbm, int &m, int &blk)
+{
+    const int xcd = b & 7, local = b >> 3;
+    m = xcd + 8 * (local / nbm);
+    blk = local - (local / nbm) * nbm;
+}
+
+template <typename T, int R, bool MASK, typename In>
+__device__ __forceinline__ void syn_step(const In &in, T (&x)[R], T (&c2)[R], T (&p2)[R], T (&cm)[R],
+                                         T (&pm)[R], const int (&k)[R], T (&acc)[8][R])
+{
 #pragma unroll
     for (int j = 0; j < R; ++j) {
         T v2 = c2[j], vm = cm[j];
         if (MASK) {
             if (k[j] != 0) v2 = vm = (T)0;
         }
-        acc[0][j] = fma(v2, er, acc[0][j]);
-        acc[1][j] = fma(v2, ei, acc[1][j]);
-        acc[2][j] = fma(v2, br, acc[2][j]);
-        acc[3][j] = fma(v2, bi, acc[3][j]);
-        acc[4][j] = fma(vm, er, acc[4][j]);
-        acc[5][j] = fma(vm, ei, acc[5][j]);
-        acc[6][j] = fma(vm, br, acc[6][j]);
-        acc[7][j] = fma(vm, bi, acc[7][j]);
-        const T u = c.a * x[j];
-        const T n2 = fma(u + c.b, c2[j], -(c.g * p2[j]));
-        const T nm = fma(u - c.b, cm[j], -(c.g * pm[j]));
+        acc[0][j] = fma(v2, in.er, acc[0][j]);
+        acc[1][j] = fma(v2, in.ei, acc[1][j]);
+        acc[2][j] = fma(v2, in.br, acc[2][j]);
+        acc[3][j] = fma(v2, in.bi, acc[3][j]);
+        acc[4][j] = fma(vm, in.er, acc[4][j]);
+        acc[5][j] = fma(vm, in.ei, acc[5][j]);
+        acc[6][j] = fma(vm, in.br, acc[6][j]);
+        acc[7][j] = fma(vm, in.bi, acc[7][j]);
+        const T u = in.a * x[j];
+        const T n2 = fma(u + in.b, c2[j], -(in.g * p2[j]));
+        const T nm = fma(u - in.b, cm[j], -(in.g * pm[j]));
         p2[j] = c2[j];
         c2[j] = n2;
         pm[j] = cm[j];
@@ -143,26 +190,23 @@ __device__ __forceinline__ bool rescale(T (&c2)[R], T (&p2)[R], T (&cm)[R], T (&
     return wave_any(any_neg);
 }
 
-template <typename T, int R>
-__global__ __launch_bounds__(256) void k_leg_synth(const T *__restrict__ almE, const T *__restrict__ almB,
-                                                   int64_t alm_stride, cplx<T> *__restrict__ FG, int64_t fg_stride,
-                                                   const typename CoefT<T>::type *__restrict__ coef,
+template <typename T, int R, int V>
+__global__ __launch_bounds__(256) void k_leg_synth(const SynRec<T> *__restrict__ recs, int64_t rec_stride,
+                                                   cplx<T> *__restrict__ FG, int64_t fg_stride,
                                                    const double *__restrict__ seed2, const double *__restrict__ seedm2,
                                                    const int *__restrict__ seedk, const double *__restrict__ pair_z,
-                                                   int lmax, int npairs, int nrings, int ngroups)
+                                                   int lmax, int npairs, int nrings, int ngroups, int nbm)
 {
     const int rhs = blockIdx.y;
     const int lane = threadIdx.x & 63;
-    const int gw = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
-    const int m = gw / ngroups;
-    if (m > lmax) return;
-    const int grp = gw - m * ngroups;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    int m, blk;
+    xcd_map((int)blockIdx.x, nbm, m, blk);
+    const int grp = blk * 4 + wave;
+    if (m > lmax || grp >= ngroups) return;
     const int l0 = m > 2 ? m : 2;
     const int64_t base = (int64_t)m * (2 * lmax + 1 - m) / 2;
-    const T *aE = almE + 2 * (rhs * alm_stride + base);
-    const T *aB = almB + 2 * (rhs * alm_stride + base);
-    const auto *cf = coef + base;
-    const bool m0 = (m == 0);
+    const SynRec<T> *rec = recs + rhs * rec_stride + base;
 
     T x[R], c2[R], p2[R], cm[R], pm[R];
     int k[R], pr[R];
@@ -187,17 +231,52 @@ __global__ __launch_bounds__(256) void k_leg_synth(const T *__restrict__ almE, c
     }
     bool ramp = wave_any(neg);
     int l = l0;
-    while (ramp && l < lmax) {
-        syn_step<T, R, true>(aE, aB, cf, l, m0, x, c2, p2, cm, pm, k, acc0);
-        syn_step<T, R, true>(aE, aB, cf, l + 1, m0, x, c2, p2, cm, pm, k, acc1);
-        l += 2;
-        ramp = rescale<T, R>(c2, p2, cm, pm, k);
+    SynIn<T> i0;
+    if constexpr (V == 0) {
+        // plain: two steps per trip, loads issued inside the step
+        while (ramp && l < lmax) {
+            syn_step<T, R, true>(syn_load<T>(rec, l), x, c2, p2, cm, pm, k, acc0);
+            syn_step<T, R, true>(syn_load<T>(rec, l + 1), x, c2, p2, cm, pm, k, acc1);
+            l += 2;
+            ramp = rescale<T, R>(c2, p2, cm, pm, k);
+        }
+        l = __builtin_amdgcn_readfirstlane(l);
+        const_as<SynRec<T>> *rp = uniform_ptr(rec + l);  // keep the record address scalar
+        for (; l < lmax; l += 2, rp += 2) {
+            syn_step<T, R, false>(ld_rec<T>(rp), x, c2, p2, cm, pm, k, acc0);
+            syn_step<T, R, false>(ld_rec<T>(rp + 1), x, c2, p2, cm, pm, k, acc1);
+        }
+        i0 = syn_load<T>(rec, l);
+    } else {
+        // ramp loop, then four steps per trip whose loads are issued one pair ahead into ping-pong
+        // registers (no copies of loaded registers)
+        while (ramp && l < lmax) {
+            syn_step<T, R, true>(syn_load<T>(rec, l), x, c2, p2, cm, pm, k, acc0);
+            syn_step<T, R, true>(syn_load<T>(rec, l + 1), x, c2, p2, cm, pm, k, acc1);
+            l += 2;
+            ramp = rescale<T, R>(c2, p2, cm, pm, k);
+        }
+        l = __builtin_amdgcn_readfirstlane(l);
+        const_as<SynRec<T>> *rp = uniform_ptr(rec + l);
+        SynRec<T> a0 = ld_rec<T>(rp), a1 = ld_rec<T>(rp + 1), b0, b1;
+        for (; l + 3 <= lmax; l += 4, rp += 4) {
+            b0 = ld_rec<T>(rp + 2);
+            b1 = ld_rec<T>(rp + 3);
+            syn_step<T, R, false>(a0, x, c2, p2, cm, pm, k, acc0);
+            syn_step<T, R, false>(a1, x, c2, p2, cm, pm, k, acc1);
+            a0 = ld_rec<T>(rp + 4);
+            a1 = ld_rec<T>(rp + 5);
+            syn_step<T, R, false>(b0, x, c2, p2, cm, pm, k, acc0);
+            syn_step<T, R, false>(b1, x, c2, p2, cm, pm, k, acc1);
+        }
+        if (l < lmax) {
+            syn_step<T, R, false>(a0, x, c2, p2, cm, pm, k, acc0);
+            syn_step<T, R, false>(a1, x, c2, p2, cm, pm, k, acc1);
+            l += 2;
+        }
+        i0 = syn_load<T>(rec, l);
     }
-    for (; l < lmax; l += 2) {
-        syn_step<T, R, false>(aE, aB, cf, l, m0, x, c2, p2, cm, pm, k, acc0);
-        syn_step<T, R, false>(aE, aB, cf, l + 1, m0, x, c2, p2, cm, pm, k, acc1);
-    }
-    if (l == lmax) syn_step<T, R, true>(aE, aB, cf, l, m0, x, c2, p2, cm, pm, k, acc0);
+    if (l == lmax) syn_step<T, R, true>(i0, x, c2, p2, cm, pm, k, acc0);
 
     const bool odd0 = ((l0 + m) & 1) != 0;  // acc0 holds l + m odd terms when true
     cplx<T> *Fb = FG + rhs * fg_stride;
@@ -242,13 +321,12 @@ __global__ __launch_bounds__(256) void k_leg_synth(const T *__restrict__ almE, c
 // (south rings through the reflection symmetry).  Each lane sums its R ring pairs in registers;
 // every L steps of l the per-lane partials go through LDS and are reduced over the workgroup.
 // ================================================================================================
-template <typename T, int R, bool MASK, bool ODD>
-__device__ __forceinline__ void adj_step(const typename CoefT<T>::type *__restrict__ cf, int l, T (&x)[R], T (&c2)[R],
+template <typename T, int R, bool MASK, bool ODD, typename C>
+__device__ __forceinline__ void adj_step(const C &c, T (&x)[R], T (&c2)[R],
                                          T (&p2)[R], T (&cm)[R], T (&pm)[R], const int (&k)[R],
                                          const cplx<T> (&GN)[R], const cplx<T> (&GS)[R], const cplx<T> (&HN)[R],
                                          const cplx<T> (&HS)[R], T (&out)[4])
 {
-    const auto c = cf[l];
     T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
 #pragma unroll
     for (int j = 0; j < R; ++j) {
@@ -290,9 +368,9 @@ __global__ __launch_bounds__(64 * W) void k_leg_adj(const cplx<T> *__restrict__ 
     __shared__ T red[W * L * 4 * 64];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int b = blockIdx.x;
-    const int m = b / nrb;
-    const int rb = b - m * nrb;
+    int m, rb;
+    xcd_map((int)blockIdx.x, nrb, m, rb);
+    if (m > lmax) return;
     const int l0 = m > 2 ? m : 2;
     const int64_t base = (int64_t)m * (2 * lmax + 1 - m) / 2;
     const auto *cf = coef + base;
@@ -329,32 +407,48 @@ __global__ __launch_bounds__(64 * W) void k_leg_adj(const cplx<T> *__restrict__ 
     const int t = threadIdx.x, o = t / G, gi = t - o * G;
     const int oli = o >> 2, oc = o & 3;
 
+    using C = typename CoefT<T>::type;
+    // the coefficient table is padded past its last column, so the look-ahead loads stay in bounds
+    C c0 = cf[l0], c1 = cf[l0 + 1];
     for (int lc = l0; lc <= lmax; lc += L) {
 #pragma unroll
         for (int li = 0; li < L; li += 2) {
             T out[4];
             const int l = lc + li;
+            const C n0 = cf[l + 2], n1 = cf[l + 3];  // prefetch the next pair
             if (l <= lmax) {
-                if (ramp) adj_step<T, R, true, false>(cf, l, x, c2, p2, cm, pm, k, GN, GS, HN, HS, out);
-                else adj_step<T, R, false, false>(cf, l, x, c2, p2, cm, pm, k, GN, GS, HN, HS, out);
+                if (ramp) adj_step<T, R, true, false>(c0, x, c2, p2, cm, pm, k, GN, GS, HN, HS, out);
+                else adj_step<T, R, false, false>(c0, x, c2, p2, cm, pm, k, GN, GS, HN, HS, out);
             } else {
                 out[0] = out[1] = out[2] = out[3] = (T)0;
             }
 #pragma unroll
             for (int c = 0; c < 4; ++c) red[((wave * L + li) * 4 + c) * 64 + lane] = out[c];
             if (l + 1 <= lmax) {
-                if (ramp) adj_step<T, R, true, true>(cf, l + 1, x, c2, p2, cm, pm, k, GN, GS, HN, HS, out);
-                else adj_step<T, R, false, true>(cf, l + 1, x, c2, p2, cm, pm, k, GN, GS, HN, HS, out);
+                if (ramp) adj_step<T, R, true, true>(c1, x, c2, p2, cm, pm, k, GN, GS, HN, HS, out);
+                else adj_step<T, R, false, true>(c1, x, c2, p2, cm, pm, k, GN, GS, HN, HS, out);
             } else {
                 out[0] = out[1] = out[2] = out[3] = (T)0;
             }
 #pragma unroll
             for (int c = 0; c < 4; ++c) red[((wave * L + li + 1) * 4 + c) * 64 + lane] = out[c];
+            c0 = n0;
+            c1 = n1;
             if (ramp) ramp = rescale<T, R>(c2, p2, cm, pm, k);
         }
         __syncthreads();
-        T s = 0;
-        for (int q = gi; q < NT; q += G) s += red[(((q >> 6) * L + oli) * 4 + oc) * 64 + (q & 63)];
+        // column sums over the workgroup's lanes: four independent partial sums per thread, then
+        // a butterfly over the G threads sharing the output
+        T s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+        int q = gi;
+        for (; q + 3 * G < NT; q += 4 * G) {
+            s0 += red[(((q >> 6) * L + oli) * 4 + oc) * 64 + (q & 63)];
+            s1 += red[((((q + G) >> 6) * L + oli) * 4 + oc) * 64 + ((q + G) & 63)];
+            s2 += red[((((q + 2 * G) >> 6) * L + oli) * 4 + oc) * 64 + ((q + 2 * G) & 63)];
+            s3 += red[((((q + 3 * G) >> 6) * L + oli) * 4 + oc) * 64 + ((q + 3 * G) & 63)];
+        }
+        for (; q < NT; q += G) s0 += red[(((q >> 6) * L + oli) * 4 + oc) * 64 + (q & 63)];
+        T s = (s0 + s1) + (s2 + s3);
         for (int off = G >> 1; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
         if (gi == 0 && lc + oli <= lmax) part[((int64_t)rb * nalm + base + lc + oli) * 4 + oc] = s;
         __syncthreads();
@@ -366,7 +460,8 @@ __global__ __launch_bounds__(64 * W) void k_leg_adj(const cplx<T> *__restrict__ 
 // ================================================================================================
 template <typename T>
 __global__ void k_prologue(const double *__restrict__ xE, const double *__restrict__ xB, const double *__restrict__ kern,
-                           const int *__restrict__ lof, int lmax, int64_t nalm, T *__restrict__ oE, T *__restrict__ oB)
+                           const int *__restrict__ lof, const typename CoefT<T>::type *__restrict__ coef, int lmax,
+                           int64_t nalm, int64_t rec_stride, SynRec<T> *__restrict__ rec)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int rhs = blockIdx.y;
@@ -374,10 +469,17 @@ __global__ void k_prologue(const double *__restrict__ xE, const double *__restri
     const int64_t o = rhs * nalm + i;
     const double K = kern ? kern[lof[i]] : 1.0;
     const bool m0 = i <= lmax;
-    oE[2 * o] = (T)(K * xE[2 * o]);
-    oE[2 * o + 1] = m0 ? (T)0 : (T)(K * xE[2 * o + 1]);
-    oB[2 * o] = (T)(K * xB[2 * o]);
-    oB[2 * o + 1] = m0 ? (T)0 : (T)(K * xB[2 * o + 1]);
+    const auto c = coef[i];
+    SynRec<T> r;
+    r.a = c.a;
+    r.b = c.b;
+    r.g = c.g;
+    r.pad = (T)0;
+    r.er = (T)(K * xE[2 * o]);
+    r.ei = m0 ? (T)0 : (T)(K * xE[2 * o + 1]);
+    r.br = (T)(K * xB[2 * o]);
+    r.bi = m0 ? (T)0 : (T)(K * xB[2 * o + 1]);
+    rec[rhs * rec_stride + i] = r;
 }
 
 template <typename T>
@@ -759,59 +861,83 @@ void launch_prologue(Plan &P, bool fp32, const double *xE, const double *xB, con
 {
     dim3 g((unsigned)cdiv(P.nalm, 256), nrhs);
     if (fp32)
-        k_prologue<float><<<g, 256, 0, P.stream>>>(xE, xB, kern, P.d_lof, P.lmax, P.nalm, (float *)P.d_tE,
-                                                   (float *)P.d_tB);
+        k_prologue<float><<<g, 256, 0, P.stream>>>(xE, xB, kern, P.d_lof, P.d_coef32, P.lmax, P.nalm, P.rec_stride,
+                                                   (SynRec<float> *)P.d_rec);
     else
-        k_prologue<double><<<g, 256, 0, P.stream>>>(xE, xB, kern, P.d_lof, P.lmax, P.nalm, (double *)P.d_tE,
-                                                    (double *)P.d_tB);
+        k_prologue<double><<<g, 256, 0, P.stream>>>(xE, xB, kern, P.d_lof, P.d_coef64, P.lmax, P.nalm, P.rec_stride,
+                                                    (SynRec<double> *)P.d_rec);
 }
 
-template <typename T, int R>
-static void syn_launch(Plan &P, const void *aE, const void *aB, int64_t alm_stride, int nrhs, int64_t fg_stride)
+template <typename T, int R, int V>
+static void syn_launch(Plan &P, int nrhs, int64_t fg_stride)
 {
     const int ngroups = (int)cdiv(P.npairs, 64 * R);
-    const int64_t waves = (int64_t)(P.lmax + 1) * ngroups;
-    dim3 g((unsigned)cdiv(waves, 4), nrhs);
-    const void *coef = std::is_same<T, double>::value ? (const void *)P.d_coef64 : (const void *)P.d_coef32;
-    k_leg_synth<T, R><<<g, 256, 0, P.stream>>>((const T *)aE, (const T *)aB, alm_stride, (cplx<T> *)P.d_FG, fg_stride,
-                                               (const typename CoefT<T>::type *)coef, P.d_seed2, P.d_seedm2, P.d_seedk,
-                                               P.d_pair_z, P.lmax, P.npairs, P.nrings, ngroups);
+    P.syn_groups = ngroups;
+    const int nbm = (int)cdiv(ngroups, 4);               // blocks of four waves per m
+    const int64_t blocks = 8 * nbm * cdiv(P.lmax + 1, 8);
+    dim3 g((unsigned)blocks, nrhs);
+    k_leg_synth<T, R, V><<<g, 256, 0, P.stream>>>((const SynRec<T> *)P.d_rec, P.rec_stride, (cplx<T> *)P.d_FG,
+                                                  fg_stride, P.d_seed2, P.d_seedm2, P.d_seedk, P.d_pair_z, P.lmax,
+                                                  P.npairs, P.nrings, ngroups, nbm);
 }
 
-void launch_leg_synth(Plan &P, bool fp32, const void *aE, const void *aB, int64_t alm_stride, int nrhs)
+template <typename T, int V>
+static void syn_dispatch_r(Plan &P, int nrhs, int64_t fg_stride)
+{
+    if (P.syn_R == 1) syn_launch<T, 1, V>(P, nrhs, fg_stride);
+    else if (P.syn_R == 2) syn_launch<T, 2, V>(P, nrhs, fg_stride);
+    else syn_launch<T, 4, V>(P, nrhs, fg_stride);
+}
+
+template <typename T>
+static void syn_dispatch(Plan &P, int nrhs, int64_t fg_stride)
+{
+    if (P.syn_V == 0) syn_dispatch_r<T, 0>(P, nrhs, fg_stride);
+    else syn_dispatch_r<T, 1>(P, nrhs, fg_stride);
+}
+
+void launch_leg_synth(Plan &P, bool fp32, int nrhs)
 {
     const int64_t fg_stride = (int64_t)P.nrings * (P.lmax + 1) * 2;
-    if (fp32) {
-        if (P.syn_R == 1) syn_launch<float, 1>(P, aE, aB, alm_stride, nrhs, fg_stride);
-        else syn_launch<float, 2>(P, aE, aB, alm_stride, nrhs, fg_stride);
-    } else {
-        if (P.syn_R == 1) syn_launch<double, 1>(P, aE, aB, alm_stride, nrhs, fg_stride);
-        else syn_launch<double, 2>(P, aE, aB, alm_stride, nrhs, fg_stride);
-    }
+    if (fp32) syn_dispatch<float>(P, nrhs, fg_stride);
+    else syn_dispatch<double>(P, nrhs, fg_stride);
 }
 
-template <typename T, int R, int W>
+template <typename T, int R, int W, int L>
 static void adj_launch(Plan &P, int rhs)
 {
-    constexpr int L = 8;
     const int64_t fg_stride = (int64_t)P.nrings * (P.lmax + 1) * 2;
     const void *coef = std::is_same<T, double>::value ? (const void *)P.d_coef64 : (const void *)P.d_coef32;
-    dim3 g((unsigned)((P.lmax + 1) * P.adj_nrb));
+    dim3 g((unsigned)(8 * P.adj_nrb * cdiv(P.lmax + 1, 8)));
     k_leg_adj<T, R, W, L><<<g, 64 * W, 0, P.stream>>>((const cplx<T> *)P.d_FG + rhs * fg_stride,
                                                       (const typename CoefT<T>::type *)coef, P.d_seed2, P.d_seedm2,
                                                       P.d_seedk, P.d_pair_z, (T *)P.d_part, P.nalm, P.lmax, P.npairs,
                                                       P.nrings, P.adj_nrb);
 }
 
+// supported adjoint shapes (ring pairs per lane, waves per workgroup, l-chunk)
+#define AKRA_ADJ_SHAPES(X) \
+    X(1, 1, 8) X(1, 2, 8) X(1, 4, 8) X(2, 2, 8) X(2, 4, 8) X(4, 2, 8) X(4, 4, 8) X(8, 1, 8) X(8, 2, 8) \
+    X(2, 4, 4) X(4, 2, 4) X(4, 4, 4) X(8, 1, 4)
+
 template <typename T>
 static void adj_dispatch(Plan &P, int rhs)
 {
-    const int R = P.adj_R, W = P.adj_W;
-    if (R == 1 && W == 1) adj_launch<T, 1, 1>(P, rhs);
-    else if (R == 1 && W == 2) adj_launch<T, 1, 2>(P, rhs);
-    else if (R == 1 && W == 4) adj_launch<T, 1, 4>(P, rhs);
-    else if (R == 2 && W == 4) adj_launch<T, 2, 4>(P, rhs);
-    else adj_launch<T, 4, 4>(P, rhs);
+    const int R = P.adj_R, W = P.adj_W, L = P.adj_L;
+#define AKRA_ADJ_CASE(r, w, l) \
+    if (R == r && W == w && L == l) return adj_launch<T, r, w, l>(P, rhs);
+    AKRA_ADJ_SHAPES(AKRA_ADJ_CASE)
+#undef AKRA_ADJ_CASE
+    adj_launch<T, 4, 4, 8>(P, rhs);
+}
+
+bool adj_shape_supported(int r, int w, int l)
+{
+#define AKRA_ADJ_SUP(a, b, c) \
+    if (r == a && w == b && l == c) return true;
+    AKRA_ADJ_SHAPES(AKRA_ADJ_SUP)
+#undef AKRA_ADJ_SUP
+    return false;
 }
 
 void launch_leg_adj(Plan &P, bool fp32, int rhs)

@@ -85,11 +85,12 @@ static void build_rings(Plan &P)
 //   a_l = (l+1) sqrt((2l+1)(2l+3)) / R_{l+1},  b_l = 2m sqrt((2l+1)(2l+3)) / (l R_{l+1}),
 //   g_l = (l+1) R_l sqrt((2l+3)/(2l-1)) / (l R_{l+1}),   R_l = sqrt((l^2 - m^2)(l^2 - 4)).
 // ---------------------------------------------------------------------------------------------
+// Entries past the last column (ALM_PAD) keep the kernels' look-ahead loads in bounds.
 static void build_coef(int lmax, std::vector<Coef64> &c64, std::vector<Coef32> &c32)
 {
     const int64_t nalm = (int64_t)(lmax + 1) * (lmax + 2) / 2;
-    c64.assign(nalm, Coef64{0, 0, 0, 0});
-    c32.assign(nalm, Coef32{0, 0, 0, 0});
+    c64.assign(nalm + ALM_PAD, Coef64{0, 0, 0, 0});
+    c32.assign(nalm + ALM_PAD, Coef32{0, 0, 0, 0});
     parallel_for(lmax + 1, [&](int m) {
         const int64_t base = (int64_t)m * (2 * lmax + 1 - m) / 2;
         const int l0 = std::max(m, 2);
@@ -189,12 +190,15 @@ static void default_kernel(int lmax, std::vector<double> &k)
 static void free_plan(Plan *P)
 {
     void *ptrs[] = {P->d_rings, P->d_pair_z, P->d_coef64, P->d_coef32, P->d_seed2, P->d_seedm2, P->d_seedk,
-                    P->d_tw64, P->d_tw32, P->d_lof, P->d_order_p2, P->d_order_bl, P->d_FG, P->d_part, P->d_tE,
-                    P->d_tB, P->d_W, P->d_kern, P->d_kuser, P->d_red, P->d_scal, P->d_flag, P->d_x, P->d_r,
+                    P->d_tw64, P->d_tw32, P->d_lof, P->d_order_p2, P->d_order_bl, P->d_FG, P->d_part, P->d_rec, P->d_W, P->d_kern, P->d_kuser, P->d_red, P->d_scal, P->d_flag, P->d_x, P->d_r,
                     P->d_p, P->d_w, P->d_b, P->d_xs};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     if (P->h_pin) (void)hipHostFree(P->h_pin);
+    for (auto &e : P->ev_pool) {
+        (void)hipEventDestroy(e[0]);
+        (void)hipEventDestroy(e[1]);
+    }
     delete P;
 }
 
@@ -320,9 +324,15 @@ static akra_status create(int nside, int lmax, int nrhs, int prec, void *stream,
     // workspaces
     const size_t fg = (size_t)nrhs * P->nrings * (lmax + 1) * 2 * sizeof(double2);
     AK_TRY(alloc(&P->d_FG, fg, *P));
-    AK_TRY(alloc(&P->d_part, (size_t)P->adj_nrb * P->nalm * 4 * sizeof(double), *P));
-    AK_TRY(alloc(&P->d_tE, (size_t)nrhs * P->nalm * sizeof(double2), *P));
-    AK_TRY(alloc(&P->d_tB, (size_t)nrhs * P->nalm * sizeof(double2), *P));
+    P->part_rb_cap = (size_t)std::max(P->adj_nrb, P->npairs <= 1024 ? (P->npairs + 63) / 64 : (P->npairs + 511) / 512);
+    AK_TRY(alloc(&P->d_part, P->part_rb_cap * P->nalm * 4 * sizeof(double), *P));
+    P->rec_stride = P->nalm + ALM_PAD;
+    AK_TRY(alloc(&P->d_rec, (size_t)nrhs * P->rec_stride * 64, *P));
+    if (hipMemset(P->d_rec, 0, (size_t)nrhs * P->rec_stride * 64) != hipSuccess) {
+        free_plan(P);
+        set_error("hipMemset failed");
+        return AKRA_ERR_HIP;
+    }
     AK_TRY(alloc((void **)&P->d_W, (size_t)nrhs * P->npix * sizeof(double), *P));
     AK_TRY(alloc((void **)&P->d_red, (size_t)512 * 4 * nrhs * sizeof(double), *P));
     AK_TRY(alloc((void **)&P->d_scal, (size_t)(64 + 4 * nrhs) * sizeof(double), *P));
@@ -355,19 +365,6 @@ static akra_status check_launch(const char *what)
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, what);
     return AKRA_OK;
-}
-
-// y = K Y^H (W (Y (K x))) + lam x for the single right-hand side `rhs` of stacked [2][nalm] vectors
-// (x, y device, FP64).  W must already be in P.d_W.
-static akra_status apply_H_core(Plan &P, bool fp32, const double *kern_dev, double lam, const double *xE,
-                                const double *xB, double *yE, double *yB, int rhs)
-{
-    launch_prologue(P, fp32, xE, xB, kern_dev, 1);
-    launch_leg_synth(P, fp32, P.d_tE, P.d_tB, P.nalm, 1);
-    launch_ring(P, fp32, 2, nullptr, nullptr, nullptr, nullptr, P.d_W + (int64_t)rhs * P.npix, 1);
-    launch_leg_adj(P, fp32, 0);
-    launch_epilogue(P, fp32, kern_dev, lam, xE, xB, yE, yB);
-    return check_launch("apply_H");
 }
 
 // W from ninv/mask, validated; returns lambda_eff and P for every rhs (host)
@@ -424,7 +421,7 @@ static double read_scalar(Plan &P, const double *dev, hipError_t *err)
 
 __global__ void k_cg_alpha(double *scal, int *flag)
 {
-    // scal[0] = rz, scal[1] = pw, scal[2] = alpha
+    // scal[0] = rz, scal[1] = pw -> scal[2] = alpha; breakdown when p^T H p <= 0
     const double pw = scal[1];
     if (!(pw > 0.0) || !isfinite(pw)) {
         flag[0] = 1;
@@ -436,7 +433,7 @@ __global__ void k_cg_alpha(double *scal, int *flag)
 
 __global__ void k_cg_beta(double *scal, double pc)
 {
-    // scal[3] = rr (new), scal[0] = rz (old) -> scal[4] = beta, scal[0] = rz new
+    // scal[3] = <r, r> (new), scal[0] = rz (old) -> scal[4] = beta, scal[0] = P <r, r>
     const double rz = pc * scal[3];
     scal[4] = (scal[0] > 0.0) ? rz / scal[0] : 0.0;
     scal[0] = rz;
@@ -444,150 +441,210 @@ __global__ void k_cg_beta(double *scal, double pc)
 
 __global__ void k_set(double *p, double v) { *p = v; }
 
-// PCG on the stacked [2][nalm] vectors of right-hand side `rhs`.  b must be in P.d_b.
-static akra_status cg_core(Plan &P, const akra_cg_opts &o, const double *kern_dev, double lam_eff, double pc, int rhs,
-                           akra_cg_info *info)
+// after a residual replacement: rz = P <r, r> for the next alpha; the search direction is kept
+__global__ void k_cg_rz(double *scal, double pc) { scal[0] = pc * scal[3]; }
+
+// ---- stage timing (HIP events on the plan stream) -------------------------------------------
+static void stage_mark(Plan &P, int stage, bool begin)
+{
+    if (!P.timing) return;
+    if (begin) {
+        if (P.ev_used == (int)P.ev_pool.size()) {
+            hipEvent_t a, b;
+            if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return;
+            P.ev_pool.push_back({a, b});
+            P.ev_stage.push_back(0);
+        }
+        P.ev_stage[P.ev_used] = stage;
+        (void)hipEventRecord(P.ev_pool[P.ev_used][0], P.stream);
+    } else {
+        (void)hipEventRecord(P.ev_pool[P.ev_used][1], P.stream);
+        P.ev_used++;
+    }
+}
+
+// w = H p style apply with timing marks; W of right-hand side `rhs` must be in P.d_W
+static akra_status apply_H_timed(Plan &P, bool fp32, const double *kern_dev, double lam, const double *xE,
+                                 const double *xB, double *yE, double *yB, int rhs)
+{
+    stage_mark(P, 0, true);
+    launch_prologue(P, fp32, xE, xB, kern_dev, 1);
+    stage_mark(P, 0, false);
+    stage_mark(P, 1, true);
+    launch_leg_synth(P, fp32, 1);
+    stage_mark(P, 1, false);
+    stage_mark(P, 2, true);
+    launch_ring(P, fp32, 2, nullptr, nullptr, nullptr, nullptr, P.d_W + (int64_t)rhs * P.npix, 1);
+    stage_mark(P, 2, false);
+    stage_mark(P, 3, true);
+    launch_leg_adj(P, fp32, 0);
+    stage_mark(P, 3, false);
+    stage_mark(P, 4, true);
+    launch_epilogue(P, fp32, kern_dev, lam, xE, xB, yE, yB);
+    stage_mark(P, 4, false);
+    return check_launch("apply_H");
+}
+
+// r = b - H64 x (true residual) and rr = <r, r> on the device
+static akra_status true_residual(Plan &P, double *rdst)
 {
     const int64_t nc = 2 * P.nalm;
-    double *b = P.d_b, *x = P.d_x, *r = P.d_r, *p = P.d_p, *w = P.d_w;
-    double *bE = b, *bB = b + 2 * P.nalm;
-    auto E = [&](double *v) { return v; };
-    auto B = [&](double *v) { return v + 2 * P.nalm; };
-    hipError_t he;
-    const bool fp32 = plan_fp32(P);
-    info->lambda_eff = lam_eff;
-    info->precond = pc;
-    info->iters = 0;
-    info->fp64_applies = 0;
+    double *x = P.d_x, *w = P.d_w;
+    akra_status st = apply_H_timed(P, false, P.cg_kern, P.cg_lam, x, x + 2 * P.nalm, w, w + 2 * P.nalm, P.cg_rhs);
+    if (st) return st;
+    P.cg_fp64_applies++;
+    AK_HIP(hipMemcpyAsync(rdst, P.d_b, sizeof(double2) * nc, hipMemcpyDeviceToDevice, P.stream), "copy");
+    launch_axpby(P, rdst, -1.0, w, 1.0, nc);
+    return AKRA_OK;
+}
 
-    launch_dot(P, b, b, P.d_scal + 5, nc);
+// Initialise PCG on the right-hand side already in P.d_b (x0 in P.d_x when use_x0):
+//   r0 = b - H x0, p0 = P r0, rz0 = P <r0, r0>.  One host synchronisation (||b||, ||r0||).
+static akra_status cg_begin(Plan &P, bool use_x0)
+{
+    const int64_t nc = 2 * P.nalm;
+    hipError_t he;
+    P.cg_ready = false;
+    P.cg_iters = 0;
+    P.cg_fp64_applies = 0;
+    launch_dot(P, P.d_b, P.d_b, P.d_scal + 5, nc);
     const double bn2 = read_scalar(P, P.d_scal + 5, &he);
     if (he != hipSuccess) return hip_fail(he, "cg");
     if (!std::isfinite(bn2)) {
         set_error("right-hand side is not finite");
         return AKRA_ERR_NUMERIC;
     }
-    if (bn2 == 0.0) {
-        AK_HIP(hipMemsetAsync(x, 0, sizeof(double2) * nc, P.stream), "hipMemsetAsync");
-        AK_HIP(hipStreamSynchronize(P.stream), "sync");
+    P.cg_bn = std::sqrt(bn2);
+    if (use_x0) {
+        akra_status st = true_residual(P, P.d_r);
+        if (st) return st;
+    } else {
+        AK_HIP(hipMemsetAsync(P.d_x, 0, sizeof(double2) * nc, P.stream), "memset");
+        AK_HIP(hipMemcpyAsync(P.d_r, P.d_b, sizeof(double2) * nc, hipMemcpyDeviceToDevice, P.stream), "copy");
+    }
+    AK_HIP(hipMemsetAsync(P.d_flag, 0, sizeof(int), P.stream), "memset");
+    launch_dot(P, P.d_r, P.d_r, P.d_scal + 3, nc);
+    AK_HIP(hipMemsetAsync(P.d_p, 0, sizeof(double2) * nc, P.stream), "memset");
+    k_set<<<1, 1, 0, P.stream>>>(P.d_scal + 0, 0.0);
+    k_cg_beta<<<1, 1, 0, P.stream>>>(P.d_scal, P.cg_pc);
+    k_set<<<1, 1, 0, P.stream>>>(P.d_scal + 4, 0.0);
+    launch_cg_p(P, P.d_p, P.d_r, P.d_scal + 4, P.cg_pc, nc);
+    const double rr = read_scalar(P, P.d_scal + 3, &he);
+    if (he != hipSuccess) return hip_fail(he, "cg");
+    P.cg_rr = rr;
+    P.cg_ready = true;
+    return check_launch("cg_begin");
+}
+
+// One PCG iteration on device-resident state, no host synchronisation:
+//   w = H p, alpha = rz / <p, w>, x += alpha p, r -= alpha w, rr = <r, r>,
+//   beta = P rr / rz, p = P r + beta p.
+static akra_status cg_iterate(Plan &P, bool fp32)
+{
+    const int64_t nc = 2 * P.nalm;
+    double *x = P.d_x, *r = P.d_r, *p = P.d_p, *w = P.d_w;
+    akra_status st = apply_H_timed(P, fp32, P.cg_kern, P.cg_lam, p, p + 2 * P.nalm, w, w + 2 * P.nalm, P.cg_rhs);
+    if (st) return st;
+    stage_mark(P, 5, true);
+    launch_dot(P, p, w, P.d_scal + 1, nc);
+    k_cg_alpha<<<1, 1, 0, P.stream>>>(P.d_scal, P.d_flag);
+    launch_cg_xr(P, x, r, p, w, P.d_scal + 2, nc);
+    launch_dot(P, r, r, P.d_scal + 3, nc);
+    k_cg_beta<<<1, 1, 0, P.stream>>>(P.d_scal, P.cg_pc);
+    launch_cg_p(P, p, r, P.d_scal + 4, P.cg_pc, nc);
+    stage_mark(P, 5, false);
+    P.cg_iters++;
+    return check_launch("cg_step");
+}
+
+// host view of <r, r> and the breakdown flag (one synchronisation)
+static akra_status cg_poll(Plan &P, double *rr, int *flag)
+{
+    AK_HIP(hipMemcpyAsync(P.h_pin, P.d_scal + 3, sizeof(double), hipMemcpyDeviceToHost, P.stream), "copy");
+    AK_HIP(hipMemcpyAsync(P.h_pin + 1, P.d_flag, sizeof(int), hipMemcpyDeviceToHost, P.stream), "copy");
+    AK_HIP(hipStreamSynchronize(P.stream), "sync");
+    *rr = P.h_pin[0];
+    std::memcpy(flag, P.h_pin + 1, sizeof(int));
+    return AKRA_OK;
+}
+
+// Full solve on the state prepared by cg_begin.  FP32 plans iterate with the FP32 operator and
+// replace the recursive residual by the FP64 true residual whenever it has dropped by
+// reliable_delta since the last replacement (reliable updates); convergence is only accepted
+// on a true residual.  The search direction is kept across replacements.
+static akra_status cg_run(Plan &P, const akra_cg_opts &o, akra_cg_info *info)
+{
+    const int64_t nc = 2 * P.nalm;
+    const bool fp32 = P.prec == AKRA_FP32;
+    hipError_t he;
+    info->lambda_eff = P.cg_lam;
+    info->precond = P.cg_pc;
+    if (P.cg_bn == 0.0) {
+        info->iters = 0;
         info->rel_resid = info->rel_resid_true = 0.0;
         return AKRA_OK;
     }
-    const double bn = std::sqrt(bn2);
-    // x0, r0 = b - H x0
-    if (o.use_x0) {
-        akra_status st = apply_H_core(P, false, kern_dev, lam_eff, E(x), B(x), E(w), B(w), rhs);
-        if (st) return st;
-        info->fp64_applies++;
-        AK_HIP(hipMemcpyAsync(r, b, sizeof(double2) * nc, hipMemcpyDeviceToDevice, P.stream), "copy");
-        launch_axpby(P, r, -1.0, w, 1.0, nc);
-    } else {
-        AK_HIP(hipMemsetAsync(x, 0, sizeof(double2) * nc, P.stream), "memset");
-        AK_HIP(hipMemcpyAsync(r, b, sizeof(double2) * nc, hipMemcpyDeviceToDevice, P.stream), "copy");
-    }
-    (void)bE;
-    (void)bB;
-    AK_HIP(hipMemsetAsync(P.d_flag, 0, sizeof(int), P.stream), "memset");
-    launch_dot(P, r, r, P.d_scal + 3, nc);
-    double rr = read_scalar(P, P.d_scal + 3, &he);
-    if (he != hipSuccess) return hip_fail(he, "cg");
-    // p = P r, rz = P <r, r>
-    AK_HIP(hipMemsetAsync(p, 0, sizeof(double2) * nc, P.stream), "memset");
-    k_set<<<1, 1, 0, P.stream>>>(P.d_scal + 0, 0.0);
-    k_cg_beta<<<1, 1, 0, P.stream>>>(P.d_scal, pc);
-    k_set<<<1, 1, 0, P.stream>>>(P.d_scal + 4, 0.0);
-    launch_cg_p(P, p, r, P.d_scal + 4, pc, nc);
-
-    double rel = std::sqrt(rr) / bn;
-    double rmax = std::sqrt(rr);
-    bool fresh = true;  // r is a true (FP64) residual
-    int it = 0;
+    const double bn = P.cg_bn;
+    double rr = P.cg_rr, rel = std::sqrt(rr) / bn, rmax = std::sqrt(rr);
+    bool fresh = true;
     akra_status result = AKRA_NOT_CONVERGED;
+    auto refresh = [&]() -> akra_status {
+        akra_status s2 = true_residual(P, P.d_r);
+        if (s2) return s2;
+        launch_dot(P, P.d_r, P.d_r, P.d_scal + 3, nc);
+        rr = read_scalar(P, P.d_scal + 3, &he);
+        if (he != hipSuccess) return hip_fail(he, "cg");
+        rel = std::sqrt(rr) / bn;
+        rmax = std::sqrt(rr);
+        fresh = true;
+        return AKRA_OK;
+    };
     while (true) {
         if (rel < o.tol) {
             if (!fp32 || fresh) {
                 result = AKRA_OK;
                 break;
             }
-            // recursive FP32 residual says converged: confirm with the true residual
-            akra_status st = apply_H_core(P, false, kern_dev, lam_eff, E(x), B(x), E(w), B(w), rhs);
+            akra_status st = refresh();
             if (st) return st;
-            info->fp64_applies++;
-            AK_HIP(hipMemcpyAsync(r, b, sizeof(double2) * nc, hipMemcpyDeviceToDevice, P.stream), "copy");
-            launch_axpby(P, r, -1.0, w, 1.0, nc);
-            launch_dot(P, r, r, P.d_scal + 3, nc);
-            rr = read_scalar(P, P.d_scal + 3, &he);
-            if (he != hipSuccess) return hip_fail(he, "cg");
-            rel = std::sqrt(rr) / bn;
-            rmax = std::sqrt(rr);
-            fresh = true;
             if (rel < o.tol) {
                 result = AKRA_OK;
                 break;
             }
-            k_cg_beta<<<1, 1, 0, P.stream>>>(P.d_scal, pc);
-            launch_cg_p(P, p, r, P.d_scal + 4, pc, nc);
+            // continue from the true residual with the kept direction
+            k_cg_rz<<<1, 1, 0, P.stream>>>(P.d_scal, P.cg_pc);
         }
-        if (it >= o.maxiter) break;
-        // w = H p
-        akra_status st = apply_H_core(P, fp32, kern_dev, lam_eff, E(p), B(p), E(w), B(w), rhs);
+        if (P.cg_iters >= o.maxiter) break;
+        akra_status st = cg_iterate(P, fp32);
         if (st) return st;
-        launch_dot(P, p, w, P.d_scal + 1, nc);
-        k_cg_alpha<<<1, 1, 0, P.stream>>>(P.d_scal, P.d_flag);
-        launch_cg_xr(P, x, r, p, w, P.d_scal + 2, nc);
-        launch_dot(P, r, r, P.d_scal + 3, nc);
-        AK_HIP(hipMemcpyAsync(P.h_pin, P.d_scal + 3, sizeof(double), hipMemcpyDeviceToHost, P.stream), "copy");
-        AK_HIP(hipMemcpyAsync(P.h_pin + 1, P.d_flag, sizeof(int), hipMemcpyDeviceToHost, P.stream), "copy");
-        AK_HIP(hipStreamSynchronize(P.stream), "sync");
-        rr = P.h_pin[0];
-        int flag;
-        std::memcpy(&flag, P.h_pin + 1, sizeof(int));
-        ++it;
+        int flag = 0;
+        st = cg_poll(P, &rr, &flag);
+        if (st) return st;
         fresh = false;
         if (flag || !std::isfinite(rr)) {
             set_error("CG breakdown: p^T H p <= 0 or non-finite scalar");
-            info->iters = it;
+            info->iters = P.cg_iters;
             return AKRA_ERR_NUMERIC;
         }
         rel = std::sqrt(rr) / bn;
+        if (o.resid_hist && P.cg_iters - 1 < o.resid_hist_len) o.resid_hist[P.cg_iters - 1] = rel;
         if (fp32 && std::sqrt(rr) < o.reliable_delta * rmax && rel >= o.tol) {
-            // reliable update: replace the recursive residual by b - H64 x
-            st = apply_H_core(P, false, kern_dev, lam_eff, E(x), B(x), E(w), B(w), rhs);
+            st = refresh();
             if (st) return st;
-            info->fp64_applies++;
-            AK_HIP(hipMemcpyAsync(r, b, sizeof(double2) * nc, hipMemcpyDeviceToDevice, P.stream), "copy");
-            launch_axpby(P, r, -1.0, w, 1.0, nc);
-            launch_dot(P, r, r, P.d_scal + 3, nc);
-            rr = read_scalar(P, P.d_scal + 3, &he);
-            if (he != hipSuccess) return hip_fail(he, "cg");
-            rel = std::sqrt(rr) / bn;
-            rmax = std::sqrt(rr);
-            fresh = true;
+            k_cg_rz<<<1, 1, 0, P.stream>>>(P.d_scal, P.cg_pc);
         }
-        if (o.resid_hist && it - 1 < o.resid_hist_len) o.resid_hist[it - 1] = rel;
-        if (rel < o.tol && (!fp32 || fresh)) {
-            result = AKRA_OK;
-            break;
-        }
-        if (rel < o.tol) continue;  // FP32: confirm at the top of the loop
-        k_cg_beta<<<1, 1, 0, P.stream>>>(P.d_scal, pc);
-        launch_cg_p(P, p, r, P.d_scal + 4, pc, nc);
     }
-    info->iters = it;
+    info->iters = P.cg_iters;
     info->rel_resid = rel;
-    // true residual in FP64
     {
-        akra_status st = apply_H_core(P, false, kern_dev, lam_eff, E(x), B(x), E(w), B(w), rhs);
+        akra_status st = true_residual(P, P.d_xs);
         if (st) return st;
-        info->fp64_applies++;
-        AK_HIP(hipMemcpyAsync(P.d_xs, b, sizeof(double2) * nc, hipMemcpyDeviceToDevice, P.stream), "copy");
-        launch_axpby(P, P.d_xs, -1.0, w, 1.0, nc);
         launch_dot(P, P.d_xs, P.d_xs, P.d_scal + 6, nc);
         const double tr = read_scalar(P, P.d_scal + 6, &he);
         if (he != hipSuccess) return hip_fail(he, "cg");
         info->rel_resid_true = std::sqrt(tr) / bn;
     }
-    AK_HIP(hipStreamSynchronize(P.stream), "sync");
+    info->fp64_applies = P.cg_fp64_applies;
     if (result == AKRA_NOT_CONVERGED) set_error("maxiter reached");
     return result;
 }
@@ -664,12 +721,8 @@ akra_status akra_synth2(akra_plan plan, const double *almE, const double *almB, 
         return AKRA_ERR_ARG;
     }
     const bool fp32 = plan_fp32(P);
-    if (fp32) {
-        launch_prologue(P, true, almE, almB, nullptr, P.nrhs);
-        launch_leg_synth(P, true, P.d_tE, P.d_tB, P.nalm, P.nrhs);
-    } else {
-        launch_leg_synth(P, false, almE, almB, P.nalm, P.nrhs);
-    }
+    launch_prologue(P, fp32, almE, almB, nullptr, P.nrhs);
+    launch_leg_synth(P, fp32, P.nrhs);
     launch_ring(P, fp32, 0, nullptr, nullptr, g1, g2, nullptr, P.nrhs);
     return check_launch("synth2");
 }
@@ -708,7 +761,7 @@ akra_status akra_apply_H(akra_plan plan, const double *ninv, const uint8_t *mask
     const bool fp32 = plan_fp32(P);
     for (int r = 0; r < P.nrhs; ++r) {
         const int64_t o = (int64_t)r * 2 * P.nalm;
-        st = apply_H_core(P, fp32, kd, lambda_eff, xE + o, xB + o, yE + o, yB + o, r);
+        st = apply_H_timed(P, fp32, kd, lambda_eff, xE + o, xB + o, yE + o, yB + o, r);
         if (st) return st;
     }
     return AKRA_OK;
@@ -745,21 +798,57 @@ akra_status akra_rhs(akra_plan plan, const double *g1, const double *g2, const d
     return rhs_core(P, g1, g2, kd, bE, bB);
 }
 
-static akra_status solve_common(Plan &P, const double *g1, const double *g2, const double *ninv, const uint8_t *mask,
-                                const double *bE, const double *bB, const akra_cg_opts *opts, double *xE, double *xB,
-                                akra_cg_info *info_out)
+// Load right-hand side `r` (from maps, or given b) and x0 into the solver state and run cg_begin.
+static akra_status cg_prepare(Plan &P, const double *g1, const double *g2, const double *bE, const double *bB,
+                              const double *xE, const double *xB, const akra_cg_opts &o, const double *kd,
+                              const std::vector<double> &le, const std::vector<double> &pc, int r)
 {
-    auto t0 = std::chrono::steady_clock::now();
-    akra_cg_opts o;
+    const int64_t off = (int64_t)r * 2 * P.nalm;
+    P.cg_kern = kd;
+    P.cg_lam = le[r];
+    P.cg_pc = pc[r];
+    P.cg_rhs = r;
+    if (g1) {
+        launch_ring(P, false, 1, g1 + r * P.npix, g2 + r * P.npix, nullptr, nullptr, P.d_W + r * P.npix, 1);
+        launch_leg_adj(P, false, 0);
+        launch_epilogue(P, false, kd, 0.0, nullptr, nullptr, P.d_b, P.d_b + 2 * P.nalm);
+    } else {
+        AK_HIP(hipMemcpyAsync(P.d_b, bE + off, sizeof(double2) * P.nalm, hipMemcpyDeviceToDevice, P.stream), "copy");
+        AK_HIP(hipMemcpyAsync(P.d_b + 2 * P.nalm, bB + off, sizeof(double2) * P.nalm, hipMemcpyDeviceToDevice,
+                              P.stream),
+               "copy");
+    }
+    if (o.use_x0) {
+        AK_HIP(hipMemcpyAsync(P.d_x, xE + off, sizeof(double2) * P.nalm, hipMemcpyDeviceToDevice, P.stream), "copy");
+        AK_HIP(hipMemcpyAsync(P.d_x + 2 * P.nalm, xB + off, sizeof(double2) * P.nalm, hipMemcpyDeviceToDevice,
+                              P.stream),
+               "copy");
+    }
+    return cg_begin(P, o.use_x0 != 0);
+}
+
+static akra_status read_opts(const akra_cg_opts *opts, akra_cg_opts &o)
+{
     akra_cg_opts_default(&o);
     if (opts) o = *opts;
     if (!(o.tol > 0) || o.maxiter < 0 || !(o.lambda >= 0) || !(o.reliable_delta > 0 && o.reliable_delta < 1)) {
         set_error("invalid solver options");
         return AKRA_ERR_ARG;
     }
+    return AKRA_OK;
+}
+
+static akra_status solve_common(Plan &P, const double *g1, const double *g2, const double *ninv, const uint8_t *mask,
+                                const double *bE, const double *bB, const akra_cg_opts *opts, double *xE, double *xB,
+                                akra_cg_info *info_out)
+{
+    auto t0 = std::chrono::steady_clock::now();
+    akra_cg_opts o;
+    akra_status st = read_opts(opts, o);
+    if (st) return st;
     akra_cg_info info{};
     std::vector<double> le, pc;
-    akra_status st = setup_weights(P, ninv, mask, o.lambda, le, pc);
+    st = setup_weights(P, ninv, mask, o.lambda, le, pc);
     if (st) return st;
     const double *kd;
     st = kernel_to_device(P, o.kernel_l, &kd);
@@ -767,25 +856,9 @@ static akra_status solve_common(Plan &P, const double *g1, const double *g2, con
     akra_status worst = AKRA_OK;
     for (int r = 0; r < P.nrhs; ++r) {
         const int64_t off = (int64_t)r * 2 * P.nalm;
-        // b into the solver's stacked [E | B] buffer
-        if (g1) {
-            launch_ring(P, false, 1, g1 + r * P.npix, g2 + r * P.npix, nullptr, nullptr, P.d_W + r * P.npix, 1);
-            launch_leg_adj(P, false, 0);
-            launch_epilogue(P, false, kd, 0.0, nullptr, nullptr, P.d_b, P.d_b + 2 * P.nalm);
-        } else {
-            AK_HIP(hipMemcpyAsync(P.d_b, bE + off, sizeof(double2) * P.nalm, hipMemcpyDeviceToDevice, P.stream), "copy");
-            AK_HIP(hipMemcpyAsync(P.d_b + 2 * P.nalm, bB + off, sizeof(double2) * P.nalm, hipMemcpyDeviceToDevice,
-                                  P.stream),
-                   "copy");
-        }
-        // x in and out through the solver's stacked [E | B] iterate d_x
-        if (o.use_x0) {
-            AK_HIP(hipMemcpyAsync(P.d_x, xE + off, sizeof(double2) * P.nalm, hipMemcpyDeviceToDevice, P.stream), "copy");
-            AK_HIP(hipMemcpyAsync(P.d_x + 2 * P.nalm, xB + off, sizeof(double2) * P.nalm, hipMemcpyDeviceToDevice,
-                                  P.stream),
-                   "copy");
-        }
-        st = cg_core(P, o, kd, le[r], pc[r], r, &info);
+        st = cg_prepare(P, g1, g2, bE, bB, xE, xB, o, kd, le, pc, r);
+        if (st) return st;
+        st = cg_run(P, o, &info);
         if (st == AKRA_OK || st == AKRA_NOT_CONVERGED) {
             AK_HIP(hipMemcpyAsync(xE + off, P.d_x, sizeof(double2) * P.nalm, hipMemcpyDeviceToDevice, P.stream), "copy");
             AK_HIP(hipMemcpyAsync(xB + off, P.d_x + 2 * P.nalm, sizeof(double2) * P.nalm, hipMemcpyDeviceToDevice,
@@ -822,6 +895,137 @@ akra_status akra_cg_solve_b(akra_plan plan, const double *ninv, const uint8_t *m
         return AKRA_ERR_ARG;
     }
     return solve_common(P, nullptr, nullptr, ninv, mask, bE, bB, opts, xE, xB, info);
+}
+
+akra_status akra_cg_start(akra_plan plan, const double *g1, const double *g2, const double *ninv, const uint8_t *mask,
+                          const akra_cg_opts *opts)
+{
+    AK_PLAN();
+    if (!g1 || !g2) {
+        set_error("null pointer argument");
+        return AKRA_ERR_ARG;
+    }
+    akra_cg_opts o;
+    akra_status st = read_opts(opts, o);
+    if (st) return st;
+    if (o.use_x0) {
+        set_error("akra_cg_start starts from x0 = 0");
+        return AKRA_ERR_ARG;
+    }
+    std::vector<double> le, pc;
+    st = setup_weights(P, ninv, mask, o.lambda, le, pc);
+    if (st) return st;
+    const double *kd;
+    st = kernel_to_device(P, o.kernel_l, &kd);
+    if (st) return st;
+    return cg_prepare(P, g1, g2, nullptr, nullptr, nullptr, nullptr, o, kd, le, pc, 0);
+}
+
+akra_status akra_cg_step(akra_plan plan, int nsteps)
+{
+    AK_PLAN();
+    if (!P.cg_ready) {
+        set_error("akra_cg_step before akra_cg_start");
+        return AKRA_ERR_ARG;
+    }
+    for (int i = 0; i < nsteps; ++i) {
+        akra_status st = cg_iterate(P, P.prec == AKRA_FP32);
+        if (st) return st;
+    }
+    return AKRA_OK;
+}
+
+akra_status akra_cg_state(akra_plan plan, double *rel_resid, int *iters, double *xE, double *xB)
+{
+    AK_PLAN();
+    if (!P.cg_ready) {
+        set_error("akra_cg_state before akra_cg_start");
+        return AKRA_ERR_ARG;
+    }
+    double rr;
+    int flag;
+    akra_status st = cg_poll(P, &rr, &flag);
+    if (st) return st;
+    if (rel_resid) *rel_resid = P.cg_bn > 0 ? std::sqrt(rr) / P.cg_bn : 0.0;
+    if (iters) *iters = P.cg_iters;
+    if (xE && xB) {
+        AK_HIP(hipMemcpyAsync(xE, P.d_x, sizeof(double2) * P.nalm, hipMemcpyDeviceToDevice, P.stream), "copy");
+        AK_HIP(hipMemcpyAsync(xB, P.d_x + 2 * P.nalm, sizeof(double2) * P.nalm, hipMemcpyDeviceToDevice, P.stream),
+               "copy");
+        AK_HIP(hipStreamSynchronize(P.stream), "sync");
+    }
+    if (flag || !std::isfinite(rr)) {
+        set_error("CG breakdown: p^T H p <= 0 or non-finite scalar");
+        return AKRA_ERR_NUMERIC;
+    }
+    return AKRA_OK;
+}
+
+akra_status akra_plan_set_tuning(akra_plan plan, int syn_variant, int syn_rings, int adj_rings, int adj_waves,
+                                 int adj_chunk)
+{
+    AK_PLAN();
+    const bool sv = syn_variant == 0 || syn_variant == 1;
+    const bool sr = syn_rings == 1 || syn_rings == 2 || syn_rings == 4;
+    if (!sv || !sr || !adj_shape_supported(adj_rings, adj_waves, adj_chunk)) {
+        set_error("unsupported tuning (see akra.h for the supported launch shapes)");
+        return AKRA_ERR_ARG;
+    }
+    const int cap = 64 * adj_rings * adj_waves;
+    const int nrb = (P.npairs + cap - 1) / cap;
+    if ((size_t)nrb > P.part_rb_cap) {
+        set_error("adjoint shape needs more ring blocks than the plan's partial-sum buffer holds");
+        return AKRA_ERR_ARG;
+    }
+    P.syn_V = syn_variant;
+    P.syn_R = syn_rings;
+    P.adj_R = adj_rings;
+    P.adj_W = adj_waves;
+    P.adj_L = adj_chunk;
+    P.adj_nrb = nrb;
+    return AKRA_OK;
+}
+
+akra_status akra_plan_get_tuning(akra_plan plan, int *out5)
+{
+    AK_PLAN();
+    if (!out5) {
+        set_error("null pointer argument");
+        return AKRA_ERR_ARG;
+    }
+    out5[0] = P.syn_V;
+    out5[1] = P.syn_R;
+    out5[2] = P.adj_R;
+    out5[3] = P.adj_W;
+    out5[4] = P.adj_L;
+    return AKRA_OK;
+}
+
+akra_status akra_plan_set_timing(akra_plan plan, int on)
+{
+    AK_PLAN();
+    P.timing = on != 0;
+    P.ev_used = 0;
+    return AKRA_OK;
+}
+
+akra_status akra_plan_stage_times(akra_plan plan, double *ms, int *calls)
+{
+    AK_PLAN();
+    AK_HIP(hipStreamSynchronize(P.stream), "sync");
+    for (int s = 0; s < AKRA_NSTAGES; ++s) {
+        if (ms) ms[s] = 0.0;
+        if (calls) calls[s] = 0;
+    }
+    for (int i = 0; i < P.ev_used; ++i) {
+        float t = 0;
+        AK_HIP(hipEventElapsedTime(&t, P.ev_pool[i][0], P.ev_pool[i][1]), "hipEventElapsedTime");
+        const int s = P.ev_stage[i];
+        if (ms) ms[s] += t;
+        if (calls) calls[s] += 1;
+    }
+    P.ev_used = 0;
+    return AKRA_OK;
 }
 
 }  // extern "C"

@@ -1,0 +1,108 @@
+"""Autotuner for the Legendre launch shapes.
+
+For one (Nside, lmax, precision) it times every supported synthesis variant / ring-pairs-per-lane
+choice and every adjoint (ring pairs per lane, waves per workgroup) shape with HIP events on the
+plan stream (stage times of PCG iterations on synthetic data), and stores the fastest in
+tuning.json next to this file.  Plan() applies the cached shapes automatically.
+
+    python -m paper_2606_06175_amd.tune --nside 2048 --lmax 4096 --precision fp64
+"""
+import argparse
+import json
+import os
+import sys
+
+CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning.json")
+SYN = [(v, r) for v in (0, 1) for r in (1, 2, 4)]
+ADJ = [(1, 1, 8), (1, 2, 8), (1, 4, 8), (2, 2, 8), (2, 4, 8), (4, 2, 8), (4, 4, 8), (8, 1, 8), (8, 2, 8),
+       (2, 4, 4), (4, 2, 4), (4, 4, 4), (8, 1, 4)]
+
+
+def key(nside, lmax, precision):
+    return "%d:%d:%s" % (nside, lmax, precision)
+
+
+def load_cache():
+    if os.path.exists(CACHE):
+        with open(CACHE) as f:
+            return json.load(f)
+    return {}
+
+
+def lookup(nside, lmax, precision):
+    return load_cache().get(key(nside, lmax, precision))
+
+
+def _time_stage(plan, stage, steps):
+    plan.cg_step(1)
+    plan.set_timing(True)
+    plan.stage_times()
+    plan.cg_step(steps)
+    st = plan.stage_times()
+    plan.set_timing(False)
+    ms, n = st[stage]
+    return ms / max(n, 1)
+
+
+def tune(nside, lmax, precision="fp64", steps=2, log=print):
+    import torch
+
+    from .akra import AkraError, Plan
+    dev = torch.device("cuda", 0)
+    plan = Plan(nside, lmax, precision=precision, device=dev, tuned=False)
+    npix = 12 * nside * nside
+    g = torch.Generator(device="cpu").manual_seed(7)
+    g1 = torch.randn(npix, generator=g, dtype=torch.float64).to(dev)
+    g2 = torch.randn(npix, generator=g, dtype=torch.float64).to(dev)
+    ninv = torch.ones(npix, dtype=torch.float64, device=dev)
+    mask = torch.ones(npix, dtype=torch.uint8, device=dev)
+    plan.cg_start(g1, g2, ninv, mask)
+    base = plan.get_tuning()
+    res = {"syn": {}, "adj": {}}
+    best_syn, best_t = (base[0], base[1]), float("inf")
+    for v, r in SYN:
+        plan.set_tuning(v, r, base[2], base[3], base[4])
+        t = _time_stage(plan, "leg_synth", steps)
+        res["syn"]["%d,%d" % (v, r)] = t
+        log("  synth variant %d rings/lane %d: %.3f ms" % (v, r, t))
+        if t < best_t:
+            best_syn, best_t = (v, r), t
+    best_adj, best_ta = (base[2], base[3], base[4]), float("inf")
+    for r, w, c in ADJ:
+        try:
+            plan.set_tuning(best_syn[0], best_syn[1], r, w, c)
+        except AkraError:
+            continue
+        t = _time_stage(plan, "leg_adj", steps)
+        res["adj"]["%d,%d,%d" % (r, w, c)] = t
+        log("  adjoint rings/lane %d waves %d chunk %d: %.3f ms" % (r, w, c, t))
+        if t < best_ta:
+            best_adj, best_ta = (r, w, c), t
+    plan.close()
+    entry = {"syn_variant": best_syn[0], "syn_rings": best_syn[1], "adj_rings": best_adj[0],
+             "adj_waves": best_adj[1], "adj_chunk": best_adj[2], "ms_syn": best_t, "ms_adj": best_ta, "sweep": res}
+    return entry
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--nside", type=int, required=True)
+    ap.add_argument("--lmax", type=int, required=True)
+    ap.add_argument("--precision", default="fp64")
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--out", default=CACHE)
+    a = ap.parse_args()
+    e = tune(a.nside, a.lmax, a.precision, a.steps, log=lambda *x: print(*x, flush=True))
+    cache = {}
+    if os.path.exists(a.out):
+        with open(a.out) as f:
+            cache = json.load(f)
+    cache[key(a.nside, a.lmax, a.precision)] = e
+    with open(a.out, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+    print(json.dumps({k: v for k, v in e.items() if k != "sweep"}), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
