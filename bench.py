@@ -118,9 +118,12 @@ def main():
     ap.add_argument("--lmax", type=int, default=None)
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-rings", type=int, default=24)
+    ap.add_argument("--cpu-sample-rings", type=int, default=192)
     ap.add_argument("--solve-tol", type=float, default=1e-8)
     ap.add_argument("--maxiter", type=int, default=3000)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only time a plain device-to-device copy of MIB MiB (4 launches) and exit; the HBM "
+                         "counters of that copy calibrate the counters of the operator's kernels")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -137,6 +140,19 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.copy_calibration:
+        n = args.copy_calibration << 20
+        src = torch.ones(n // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(4):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t) / 4
+        print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "ms_per_copy": dt * 1e3,
+                          "GB_per_s": 2 * n / dt / 1e9}), flush=True)
+        return
     p = wl.CONFIGS[args.workload]
     nside = args.nside or p["nside"]
     lmax = args.lmax or p["lmax"]

@@ -180,9 +180,9 @@ akra_status akra_cg_state(akra_plan plan, double *rel_resid, int *iters, double 
  *   syn_rings    ring pairs per lane of the synthesis (1, 2, 4)
  *   adj_rings, adj_waves, adj_chunk   ring pairs per lane, waves per workgroup and l-chunk of the
  *                adjoint: (1,1,8) (1,2,8) (1,4,8) (2,2,8) (2,4,8) (4,2,8) (4,4,8) (8,1,8) (8,2,8)
- *                (2,4,4) (4,2,4) (4,4,4) (8,1,4).  A shape covering fewer ring pairs per workgroup than
- *                the plan's partial-sum buffer allows (at least 512 pairs per workgroup when
- *                Nside > 512) is rejected with AKRA_ERR_ARG.
+ *                (2,4,4) (4,2,4) (4,4,4) (8,1,4) (2,1,8) (4,1,4) (4,1,8).  A shape covering fewer ring
+ *                pairs per workgroup than the plan's partial-sum buffer allows (at least 256 pairs
+ *                per workgroup when Nside > 512) is rejected with AKRA_ERR_ARG.
  * akra_plan_get_tuning writes the five current values to out5 (HOST).
  */
 akra_status akra_plan_set_tuning(akra_plan plan, int syn_variant, int syn_rings, int adj_rings, int adj_waves,

@@ -90,6 +90,16 @@ template <typename P> __device__ __forceinline__ const_as<P> *uniform_ptr(const 
     return (const_as<P> *)(((uint64_t)hi << 32) | lo);
 }
 
+template <typename C> __device__ __forceinline__ C ld_coef(const_as<C> *p)
+{
+    C c;
+    c.a = p->a;
+    c.b = p->b;
+    c.g = p->g;
+    c.pad = 0;
+    return c;
+}
+
 // wave-uniform "any lane"
 __device__ __forceinline__ bool wave_any(bool p) { return __ballot(p) != 0ull; }
 
@@ -408,34 +418,45 @@ __global__ __launch_bounds__(64 * W) void k_leg_adj(const cplx<T> *__restrict__ 
     const int oli = o >> 2, oc = o & 3;
 
     using C = typename CoefT<T>::type;
-    // the coefficient table is padded past its last column, so the look-ahead loads stay in bounds
-    C c0 = cf[l0], c1 = cf[l0 + 1];
-    for (int lc = l0; lc <= lmax; lc += L) {
+    // coefficient records through an explicitly uniform pointer (scalar loads); the table is padded
+    // past its last column, so the look-ahead loads stay in bounds
+    const_as<C> *cp = uniform_ptr(cf + l0);
+    C cc[L];
 #pragma unroll
-        for (int li = 0; li < L; li += 2) {
-            T out[4];
-            const int l = lc + li;
-            const C n0 = cf[l + 2], n1 = cf[l + 3];  // prefetch the next pair
-            if (l <= lmax) {
-                if (ramp) adj_step<T, R, true, false>(c0, x, c2, p2, cm, pm, k, GN, GS, HN, HS, out);
-                else adj_step<T, R, false, false>(c0, x, c2, p2, cm, pm, k, GN, GS, HN, HS, out);
-            } else {
-                out[0] = out[1] = out[2] = out[3] = (T)0;
+    for (int li = 0; li < L; ++li) cc[li] = ld_coef<C>(cp + li);
+    for (int lc = l0; lc <= lmax; lc += L, cp += L) {
+        if (ramp || lc + L - 1 > lmax) {
+            // ramp (masked contraction, rescaling) or the last, partial chunk
+#pragma unroll
+            for (int li = 0; li < L; li += 2) {
+                T out[4];
+                const int l = lc + li;
+                if (l <= lmax) adj_step<T, R, true, false>(cc[li], x, c2, p2, cm, pm, k, GN, GS, HN, HS, out);
+                else out[0] = out[1] = out[2] = out[3] = (T)0;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) red[((wave * L + li) * 4 + c) * 64 + lane] = out[c];
+                if (l + 1 <= lmax) adj_step<T, R, true, true>(cc[li + 1], x, c2, p2, cm, pm, k, GN, GS, HN, HS, out);
+                else out[0] = out[1] = out[2] = out[3] = (T)0;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) red[((wave * L + li + 1) * 4 + c) * 64 + lane] = out[c];
+                if (ramp) ramp = rescale<T, R>(c2, p2, cm, pm, k);
             }
+        } else {
 #pragma unroll
-            for (int c = 0; c < 4; ++c) red[((wave * L + li) * 4 + c) * 64 + lane] = out[c];
-            if (l + 1 <= lmax) {
-                if (ramp) adj_step<T, R, true, true>(c1, x, c2, p2, cm, pm, k, GN, GS, HN, HS, out);
-                else adj_step<T, R, false, true>(c1, x, c2, p2, cm, pm, k, GN, GS, HN, HS, out);
-            } else {
-                out[0] = out[1] = out[2] = out[3] = (T)0;
+            for (int li = 0; li < L; li += 2) {
+                T out[4];
+                adj_step<T, R, false, false>(cc[li], x, c2, p2, cm, pm, k, GN, GS, HN, HS, out);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) red[((wave * L + li) * 4 + c) * 64 + lane] = out[c];
+                adj_step<T, R, false, true>(cc[li + 1], x, c2, p2, cm, pm, k, GN, GS, HN, HS, out);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) red[((wave * L + li + 1) * 4 + c) * 64 + lane] = out[c];
             }
-#pragma unroll
-            for (int c = 0; c < 4; ++c) red[((wave * L + li + 1) * 4 + c) * 64 + lane] = out[c];
-            c0 = n0;
-            c1 = n1;
-            if (ramp) ramp = rescale<T, R>(c2, p2, cm, pm, k);
         }
+        // the next chunk's coefficients load while the chunk is reduced
+        C nc[L];
+#pragma unroll
+        for (int li = 0; li < L; ++li) nc[li] = ld_coef<C>(cp + L + li);
         __syncthreads();
         // column sums over the workgroup's lanes: four independent partial sums per thread, then
         // a butterfly over the G threads sharing the output
@@ -451,6 +472,8 @@ __global__ __launch_bounds__(64 * W) void k_leg_adj(const cplx<T> *__restrict__ 
         T s = (s0 + s1) + (s2 + s3);
         for (int off = G >> 1; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
         if (gi == 0 && lc + oli <= lmax) part[((int64_t)rb * nalm + base + lc + oli) * 4 + oc] = s;
+#pragma unroll
+        for (int li = 0; li < L; ++li) cc[li] = nc[li];
         __syncthreads();
     }
 }
@@ -918,7 +941,7 @@ static void adj_launch(Plan &P, int rhs)
 // supported adjoint shapes (ring pairs per lane, waves per workgroup, l-chunk)
 #define AKRA_ADJ_SHAPES(X) \
     X(1, 1, 8) X(1, 2, 8) X(1, 4, 8) X(2, 2, 8) X(2, 4, 8) X(4, 2, 8) X(4, 4, 8) X(8, 1, 8) X(8, 2, 8) \
-    X(2, 4, 4) X(4, 2, 4) X(4, 4, 4) X(8, 1, 4)
+    X(2, 4, 4) X(4, 2, 4) X(4, 4, 4) X(8, 1, 4) X(2, 1, 8) X(4, 1, 4) X(4, 1, 8)
 
 template <typename T>
 static void adj_dispatch(Plan &P, int rhs)

@@ -324,7 +324,7 @@ static akra_status create(int nside, int lmax, int nrhs, int prec, void *stream,
     // workspaces
     const size_t fg = (size_t)nrhs * P->nrings * (lmax + 1) * 2 * sizeof(double2);
     AK_TRY(alloc(&P->d_FG, fg, *P));
-    P->part_rb_cap = (size_t)std::max(P->adj_nrb, P->npairs <= 1024 ? (P->npairs + 63) / 64 : (P->npairs + 511) / 512);
+    P->part_rb_cap = (size_t)std::max(P->adj_nrb, P->npairs <= 1024 ? (P->npairs + 63) / 64 : (P->npairs + 255) / 256);
     AK_TRY(alloc(&P->d_part, P->part_rb_cap * P->nalm * 4 * sizeof(double), *P));
     P->rec_stride = P->nalm + ALM_PAD;
     AK_TRY(alloc(&P->d_rec, (size_t)nrhs * P->rec_stride * 64, *P));
