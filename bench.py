@@ -28,6 +28,24 @@ PEAK_FP64 = 78.6e12      # MI355X FP64 vector FMA, FLOP/s
 FLOP_PER_TRIPLE = 26     # per (l, m, ring pair) and direction: 2 recurrences (10) + 8 contraction FMAs (16)
 
 
+# HBM bytes per launch of the dominant kernel from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE at this
+# workload, each scaled by the same counter's reading for a device copy of known size; valid only for
+# the kernel source they were taken from (its SHA-256 is checked at run time).
+TRAFFIC = {}
+
+
+def traffic(stage):
+    import hashlib
+    rec = TRAFFIC.get(stage)
+    if not rec:
+        return None
+    src = os.path.join(ROOT, "paper_2606_06175_amd", "csrc", "akra_kernels.hip")
+    with open(src, "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != rec["kernels_sha256"]:
+            return None
+    return rec["bytes"]
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -184,15 +202,23 @@ def main():
         log("  stage %-9s %9.3f ms/launch (%d launches)" % (k, v["ms_avg"], v["launches"]))
 
     T = triples(nside, lmax)
+    work = plan.work()
+    assert work["all"] == T
+    evaluated = {"leg_synth": work["synth"], "leg_adj": work["adjoint"]}
     dom = max(("leg_synth", "leg_adj"), key=lambda k: stages[k]["ms_avg"])
-    flops = FLOP_PER_TRIPLE * T
+    flops = FLOP_PER_TRIPLE * evaluated[dom]
     achieved = flops / (stages[dom]["ms_avg"] * 1e-3)
     roofline = {"bound": "alu", "kernel": "k_leg_adj" if dom == "leg_adj" else "k_leg_synth",
                 "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP64, "traffic": None,
-                "algorithmic": "26 flop x T = %.4g flop per launch, T = %d (l, m, ring-pair) triples" % (flops, T)}
+                "frac": achieved / PEAK_FP64, "traffic": traffic(dom),
+                "algorithmic": "26 flop x %d evaluated (l, m, ring-pair) triples = %.4g flop per launch "
+                               "(all triples T = %d; below each ring group's entry degree the terms are zero "
+                               "and are skipped)" % (evaluated[dom], flops, T)}
     for k in ("leg_synth", "leg_adj"):
-        roofline["frac_" + k] = flops / (stages[k]["ms_avg"] * 1e-3) / PEAK_FP64
+        t = stages[k]["ms_avg"] * 1e-3
+        roofline["frac_" + k] = FLOP_PER_TRIPLE * evaluated[k] / t / PEAK_FP64
+        roofline["evaluated_fraction_" + k] = evaluated[k] / T
+        roofline["full_T_rate_TFLOPs_" + k] = FLOP_PER_TRIPLE * T / t / 1e12
 
     out = {"metric": METRIC, "value": 1e3 / ms_step, "unit": "H·v applies/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,

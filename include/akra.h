@@ -188,6 +188,15 @@ akra_status akra_cg_state(akra_plan plan, double *rel_resid, int *iters, double 
 akra_status akra_plan_set_tuning(akra_plan plan, int syn_variant, int syn_rings, int adj_rings, int adj_waves,
                                  int adj_chunk);
 akra_status akra_plan_get_tuning(akra_plan plan, int *out5);
+/*
+ * Work of one Legendre launch, in (l, m, ring pair) triples, written to out3 (HOST): [0] all triples
+ * with max(2, m) <= l <= lmax; [1] those the synthesis evaluates and [2] those the adjoint evaluates
+ * with the current launch shapes.  Below the degree where the recurrence values of a whole 64-pair
+ * ring group first exceed the transform precision's underflow bound (2^-256 in FP64, 2^-44 in FP32
+ * plans) their terms are masked to zero by the kernels anyway; they are skipped, and the kernels
+ * start from recurrence states stored at plan creation.
+ */
+akra_status akra_plan_work(akra_plan plan, int64_t *out3);
 akra_status akra_plan_set_timing(akra_plan plan, int on);
 akra_status akra_plan_stage_times(akra_plan plan, double *ms, int *calls);
 

@@ -1,6 +1,6 @@
 """Oracle operator, right-hand side and PCG (test infrastructure only).
 
-Definitions (paper Sec. II and App. A, with the readings listed in the design doc):
+Definitions (paper Sec. II and App. A; where the paper is ambiguous the reading taken is stated inline):
   * alm storage: m >= 0, healpy order i(l, m) = m (2 lmax + 1 - m)/2 + l, complex128.
     Fields are real, so a_{l,-m} = (-1)^m conj(a_lm) (Sec. II.A); Im(a_l0) is not a
     degree of freedom.

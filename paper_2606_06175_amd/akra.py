@@ -72,10 +72,11 @@ def lib():
     L.akra_plan_set_timing.argtypes = [vp, ctypes.c_int]
     L.akra_plan_set_tuning.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     L.akra_plan_get_tuning.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
+    L.akra_plan_work.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
     L.akra_plan_stage_times.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int)]
     for f in ("akra_plan_create", "akra_synth2", "akra_adjoint2", "akra_apply_H", "akra_rhs", "akra_cg_solve",
               "akra_cg_solve_b", "akra_cg_start", "akra_cg_step", "akra_cg_state", "akra_plan_set_timing",
-              "akra_plan_stage_times", "akra_plan_set_tuning", "akra_plan_get_tuning"):
+              "akra_plan_stage_times", "akra_plan_set_tuning", "akra_plan_get_tuning", "akra_plan_work"):
         getattr(L, f).restype = ctypes.c_int
     _lib = L
     return L
@@ -311,3 +312,9 @@ class Plan:
         v = (ctypes.c_int * 5)()
         _check(lib().akra_plan_get_tuning(self._h, v))
         return tuple(v)
+
+    def work(self):
+        """(l, m, ring-pair) triples per Legendre launch: all, evaluated by the synthesis, by the adjoint."""
+        v = (ctypes.c_int64 * 3)()
+        _check(lib().akra_plan_work(self._h, v))
+        return {"all": v[0], "synth": v[1], "adjoint": v[2]}

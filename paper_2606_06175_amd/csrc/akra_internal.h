@@ -38,6 +38,16 @@ struct alignas(16) Coef32 {
     float a, b, g, pad;
 };
 
+// State of the recurrence of one (m, ring pair) at the entry degree of the pair's 64-pair group:
+// lambda_l and lambda_{l-1} for spin +2 and -2, sharing one scale exponent (kept beside it).
+// Below the entry degree every value of the group is under the scale threshold and contributes
+// nothing, so the Legendre kernels start there instead of at l = max(m, 2).
+struct alignas(32) Ent64 {
+    double c2, p2, cm, pm;
+};
+// entry degree of a group whose values never reach the threshold up to lmax
+constexpr int ENT_SKIP = 0x3fffffff;
+
 // One iso-latitude ring of the pixelisation.
 struct RingInfo {
     double z;      // cos(theta): the ring is defined by this double value
@@ -61,8 +71,15 @@ struct Plan {
     double *d_pair_z = nullptr;
     Coef64 *d_coef64 = nullptr;
     Coef32 *d_coef32 = nullptr;
-    double *d_seed2 = nullptr, *d_seedm2 = nullptr;  // [m][pair]
+    double *d_seed2 = nullptr, *d_seedm2 = nullptr;  // [m][pair] seeds at l = max(m,2) (plan build only)
     int *d_seedk = nullptr;
+    Ent64 *d_ent = nullptr;     // [m][pair] entry states
+    int *d_entk = nullptr;      // [m][pair] their scale exponents
+    int *d_entl = nullptr;      // [m][group] entry degree of each 64-pair group (ENT_SKIP: none)
+    int ng64 = 0;               // 64-pair groups
+    std::vector<int> h_entl;
+    int *d_wgstart = nullptr;   // [m][adjoint ring block] first degree the block wrote
+    int64_t work[3] = {0, 0, 0};  // (l, m, pair) triples: all, evaluated by synthesis, by adjoint
     void *d_tw64 = nullptr, *d_tw32 = nullptr;  // e^{-2 pi i k / twn}, k < twn/2
     int twn = 1;
     int *d_lof = nullptr;  // l of every alm index
@@ -74,6 +91,9 @@ struct Plan {
     int syn_R = 1, syn_V = 1, syn_groups = 1;
     int adj_R = 1, adj_W = 1, adj_L = 8, adj_nrb = 1;
     size_t part_rb_cap = 1;  // ring blocks the partial-sum buffer holds
+    // FP32 plans: the 64-pair groups nearest the poles run the Legendre stages in FP64 arithmetic
+    // (FP32 storage); the adjoint covers them with adj_nrb_polar ring blocks of four groups
+    int polar_groups = 0, adj_nrb_polar = 0;
 
     // workspaces (sized for FP64; FP32 views reuse them)
     void *d_FG = nullptr;       // [nrhs][nrings][lmax+1][2] complex
@@ -111,6 +131,8 @@ akra_status hip_fail(hipError_t e, const char *what);
 // ---- kernel launchers (akra_kernels.hip) -------------------------------------------------------
 // prologue: records {a, b, g, 0, K_l x_E, K_l x_B} per (l, m) in the transform precision (Im(a_l0) dropped)
 void launch_prologue(Plan &P, bool fp32, const double *xE, const double *xB, const double *kern, int nrhs);
+// entry states of the recurrence from the seeds (plan build)
+void launch_entry(Plan &P);
 // Legendre synthesis of the prologue's records (d_rec) into d_FG
 void launch_leg_synth(Plan &P, bool fp32, int nrhs);
 // ring stage: mode 0 = F -> maps, 1 = maps -> G, 2 = F -> W -> G (in place)

@@ -43,30 +43,34 @@ template <typename T> __device__ __forceinline__ cplx<T> cis_pi(int64_t k, int64
 }
 
 // ------------------------------------------------------------------------------------------------
-// Seeds: stored in FP64 as mant * 2^(512 k).  FP32 kernels re-express them in their own unit.
+// Entry states: stored in FP64 as mant * 2^(512 k).  FP32 kernels re-express them in their own unit.
 // ------------------------------------------------------------------------------------------------
 template <typename T>
-__device__ __forceinline__ void load_seed(const double *__restrict__ s2, const double *__restrict__ sm,
-                                          const int *__restrict__ sk, int64_t idx, T &v2, T &vm, int &k)
+__device__ __forceinline__ void load_entry(const Ent64 *__restrict__ ent, const int *__restrict__ entk, int64_t idx,
+                                           T &c2, T &p2, T &cm, T &pm, int &k)
 {
-    double a = s2[idx], b = sm[idx];
-    int k64 = sk[idx];
+    const Ent64 e = ent[idx];
+    const int k64 = entk[idx];
     if constexpr (std::is_same<T, double>::value) {
-        v2 = a;
-        vm = b;
+        c2 = e.c2;
+        p2 = e.p2;
+        cm = e.cm;
+        pm = e.pm;
         k = k64;
     } else {
-        double big = fmax(fabs(a), fabs(b));
+        const double big = fmax(fmax(fabs(e.c2), fabs(e.cm)), fmax(fabs(e.p2), fabs(e.pm)));
         if (big == 0.0) {
-            v2 = vm = 0.0f;
+            c2 = p2 = cm = pm = 0.0f;
             k = 0;
             return;
         }
-        int e = ilogb(big) + 512 * k64;
-        int k32 = (e >= -40) ? 0 : -((20 - e) / 64);
-        int sh = 512 * k64 - 64 * k32;
-        v2 = (float)ldexp(a, sh);
-        vm = (float)ldexp(b, sh);
+        const int ex = ilogb(big) + 512 * k64;
+        const int k32 = (ex >= -40) ? 0 : -((20 - ex) / 64);
+        const int sh = 512 * k64 - 64 * k32;
+        c2 = (float)ldexp(e.c2, sh);
+        p2 = (float)ldexp(e.p2, sh);
+        cm = (float)ldexp(e.cm, sh);
+        pm = (float)ldexp(e.pm, sh);
         k = k32;
     }
 }
@@ -98,6 +102,24 @@ template <typename C> __device__ __forceinline__ C ld_coef(const_as<C> *p)
     c.g = p->g;
     c.pad = 0;
     return c;
+}
+
+// cos(theta) of a ring pair as the recurrences use it.  FP32 kernels carry it as an unevaluated sum
+// hi + lo of two floats: rounding cos(theta) itself to FP32 would move the ring by a fixed angle,
+// an error that grows linearly along the recurrence in l; with the split only the per-step
+// rounding of a x remains.
+struct XF {
+    float hi, lo;
+};
+template <typename T> struct XT { using type = T; };
+template <> struct XT<float> { using type = XF; };
+__device__ __forceinline__ double mulx(double a, double x) { return a * x; }
+__device__ __forceinline__ float mulx(float a, XF x) { return fmaf(a, x.hi, a * x.lo); }
+__device__ __forceinline__ void setx(double &x, double z) { x = z; }
+__device__ __forceinline__ void setx(XF &x, double z)
+{
+    x.hi = (float)z;
+    x.lo = (float)(z - (double)x.hi);
 }
 
 // wave-uniform "any lane"
@@ -140,6 +162,48 @@ __device__ __forceinline__ SynIn<T> syn_load(const SynRec<T> *__restrict__ rec, 
     return rec[l];
 }
 
+// Wave-uniform source of the synthesis records for compute type T from records stored as IO.  With
+// T = double and IO = float (the near-polar rings of an FP32 plan, computed in FP64) the recurrence
+// coefficients come from the FP64 table and the alm values from the FP32 records.
+template <typename T, typename IO> struct SynSrc;
+template <typename T> struct SynSrc<T, T> {
+    const_as<SynRec<T>> *r;
+    __device__ __forceinline__ SynSrc(const SynRec<T> *rec, const Coef64 *) : r(uniform_ptr(rec)) {}
+    __device__ __forceinline__ SynRec<T> at(int i) const { return ld_rec<T>(r + i); }
+    __device__ __forceinline__ void adv(int n) { r += n; }
+};
+template <> struct SynSrc<double, float> {
+    const_as<SynRec<float>> *r;
+    const_as<Coef64> *c;
+    __device__ __forceinline__ SynSrc(const SynRec<float> *rec, const Coef64 *cf)
+        : r(uniform_ptr(rec)), c(uniform_ptr(cf))
+    {
+    }
+    __device__ __forceinline__ SynRec<double> at(int i) const
+    {
+        SynRec<double> o;
+        o.a = c[i].a;
+        o.b = c[i].b;
+        o.g = c[i].g;
+        o.pad = 0.0;
+        o.er = r[i].er;
+        o.ei = r[i].ei;
+        o.br = r[i].br;
+        o.bi = r[i].bi;
+        return o;
+    }
+    __device__ __forceinline__ void adv(int n)
+    {
+        r += n;
+        c += n;
+    }
+};
+
+template <typename T, typename IO> __device__ __forceinline__ cplx<T> to_c(cplx<IO> v)
+{
+    return mk<T>((T)v.x, (T)v.y);
+}
+
 // XCD-aware placement: workgroups are dealt to the 8 XCDs round-robin, so all blocks of one m
 // are mapped to blocks with the same index mod 8 (they share that XCD's L2 for the per-m data),
 // and each XCD walks its m values in increasing order (decreasing work).
@@ -151,7 +215,7 @@ __device__ __forceinline__ void xcd_map(int b, int nbm, int &m, int &blk)
 }
 
 template <typename T, int R, bool MASK, typename In>
-__device__ __forceinline__ void syn_step(const In &in, T (&x)[R], T (&c2)[R], T (&p2)[R], T (&cm)[R],
+__device__ __forceinline__ void syn_step(const In &in, const typename XT<T>::type (&x)[R], T (&c2)[R], T (&p2)[R], T (&cm)[R],
                                          T (&pm)[R], const int (&k)[R], T (&acc)[8][R])
 {
 #pragma unroll
@@ -168,7 +232,7 @@ __device__ __forceinline__ void syn_step(const In &in, T (&x)[R], T (&c2)[R], T 
         acc[5][j] = fma(vm, in.ei, acc[5][j]);
         acc[6][j] = fma(vm, in.br, acc[6][j]);
         acc[7][j] = fma(vm, in.bi, acc[7][j]);
-        const T u = in.a * x[j];
+        const T u = mulx(in.a, x[j]);
         const T n2 = fma(u + in.b, c2[j], -(in.g * p2[j]));
         const T nm = fma(u - in.b, cm[j], -(in.g * pm[j]));
         p2[j] = c2[j];
@@ -200,82 +264,211 @@ __device__ __forceinline__ bool rescale(T (&c2)[R], T (&p2)[R], T (&cm)[R], T (&
     return wave_any(any_neg);
 }
 
-template <typename T, int R, int V>
-__global__ __launch_bounds__(256) void k_leg_synth(const SynRec<T> *__restrict__ recs, int64_t rec_stride,
-                                                   cplx<T> *__restrict__ FG, int64_t fg_stride,
-                                                   const double *__restrict__ seed2, const double *__restrict__ seedm2,
-                                                   const int *__restrict__ seedk, const double *__restrict__ pair_z,
-                                                   int lmax, int npairs, int nrings, int ngroups, int nbm)
+// ------------------------------------------------------------------------------------------------
+// Entry states (plan build).  One wave per (m, 64-pair group) runs the FP64 recurrence from the
+// seeds at l0 = max(m, 2) with the same steps and rescaling as the Legendre kernels' ramp (two
+// steps, then a rescale), and stops at the first degree where some pair of the group contributes:
+// it has left the scaled range and reaches `live` (0 for FP64 plans; for FP32 plans a bound below
+// which the FP32 kernels' scaled values are still masked).  The state at the last degree l0 + 8q
+// before it is stored with that degree; a group that never contributes up to lmax is marked
+// ENT_SKIP.
+// ------------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_entry(const double *__restrict__ seed2, const double *__restrict__ seedm2,
+                                               const int *__restrict__ seedk, const double *__restrict__ pair_z,
+                                               const Coef64 *__restrict__ coef, Ent64 *__restrict__ ent,
+                                               int *__restrict__ entk, int *__restrict__ entl, int lmax, int npairs,
+                                               int ng, int gpb, double live)
+{
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int m = blockIdx.x / gpb;
+    const int g = (blockIdx.x - m * gpb) * 4 + wave;
+    if (m > lmax || g >= ng) return;
+    const int p = g * 64 + lane;
+    const bool valid = p < npairs;
+    const int64_t idx = (int64_t)m * npairs + p;
+    double x = 0, c2 = 0, p2 = 0, cm = 0, pm = 0;
+    int k = 0;
+    if (valid) {
+        x = pair_z[p];
+        c2 = seed2[idx];
+        cm = seedm2[idx];
+        k = seedk[idx];
+    }
+    const int l0 = m > 2 ? m : 2;
+    const Coef64 *cf = coef + (int64_t)m * (2 * lmax + 1 - m) / 2;
+    double s2 = c2, sp2 = p2, sm = cm, spm = pm;
+    int sk = k, sl = l0, res = ENT_SKIP;
+    for (int l = l0; l <= lmax;) {
+        if (wave_any(valid && k == 0 && fmax(fabs(c2), fabs(cm)) >= live)) {
+            res = sl;
+            break;
+        }
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            const Coef64 c = cf[l + t];
+            const double u = c.a * x;
+            const double n2 = fma(u + c.b, c2, -(c.g * p2));
+            const double nm = fma(u - c.b, cm, -(c.g * pm));
+            p2 = c2;
+            c2 = n2;
+            pm = cm;
+            cm = nm;
+        }
+        l += 2;
+        if (k < 0) {
+            const double big = fmax(fabs(c2), fabs(cm));
+            if (big > scale_hi<double>()) {
+                const double d = scale_down<double>();
+                c2 *= d;
+                p2 *= d;
+                cm *= d;
+                pm *= d;
+                k += 1;
+            }
+        }
+        if (((l - l0) & 7) == 0) {
+            s2 = c2;
+            sp2 = p2;
+            sm = cm;
+            spm = pm;
+            sk = k;
+            sl = l;
+        }
+    }
+    if (valid) {
+        Ent64 e;
+        e.c2 = s2;
+        e.p2 = sp2;
+        e.cm = sm;
+        e.pm = spm;
+        ent[idx] = e;
+        entk[idx] = sk;
+    }
+    if (lane == 0) entl[(int64_t)m * ng + g] = res;
+}
+
+// Start of a slot j whose group enters later than the wave (its values are zero until then).
+template <typename T, int R>
+__device__ __forceinline__ void inject(int l, const int (&e)[R], const int (&pr)[R], const Ent64 *__restrict__ ent,
+                                       const int *__restrict__ entk, int64_t row, int npairs, T (&c2)[R], T (&p2)[R],
+                                       T (&cm)[R], T (&pm)[R], int (&k)[R])
+{
+#pragma unroll
+    for (int j = 0; j < R; ++j)
+        if (e[j] == l && pr[j] < npairs) load_entry<T>(ent, entk, row + pr[j], c2[j], p2[j], cm[j], pm[j], k[j]);
+}
+
+template <int R> __device__ __forceinline__ bool pending(int l, int lmax, const int (&e)[R])
+{
+    bool q = false;
+#pragma unroll
+    for (int j = 0; j < R; ++j) q |= (e[j] > l && e[j] <= lmax);
+    return q;
+}
+
+// Waves gbeg .. gend-1 (wave w holds the 64-pair groups w R .. w R + R - 1) of every m.
+template <typename T, int R, int V, typename IO = T>
+__global__ __launch_bounds__(256) void k_leg_synth(const SynRec<IO> *__restrict__ recs, int64_t rec_stride,
+                                                   const Coef64 *__restrict__ coef64, cplx<IO> *__restrict__ FG,
+                                                   int64_t fg_stride, const Ent64 *__restrict__ ent,
+                                                   const int *__restrict__ entk, const int *__restrict__ entl,
+                                                   int ng64, const double *__restrict__ pair_z, int lmax, int npairs,
+                                                   int nrings, int gbeg, int gend, int nbm)
 {
     const int rhs = blockIdx.y;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     int m, blk;
     xcd_map((int)blockIdx.x, nbm, m, blk);
-    const int grp = blk * 4 + wave;
-    if (m > lmax || grp >= ngroups) return;
+    const int grp = gbeg + blk * 4 + wave;
+    if (m > lmax || grp >= gend) return;
     const int l0 = m > 2 ? m : 2;
     const int64_t base = (int64_t)m * (2 * lmax + 1 - m) / 2;
-    const SynRec<T> *rec = recs + rhs * rec_stride + base;
+    const SynRec<IO> *rec = recs + rhs * rec_stride + base;
+    const Coef64 *cf64 = coef64 + base;
+    const SynSrc<T, IO> src(rec, cf64);
+    auto rload = [&](int i) -> SynRec<T> {
+        if constexpr (std::is_same<T, IO>::value) return rec[i];
+        else return src.at(i);
+    };
 
-    T x[R], c2[R], p2[R], cm[R], pm[R];
-    int k[R], pr[R];
+    typename XT<T>::type x[R];
+    T c2[R], p2[R], cm[R], pm[R];
+    int k[R], pr[R], e[R];
     T acc0[8][R], acc1[8][R];
+    // entry degree of each slot's 64-pair group; the wave starts at the earliest
+    const_as<int> *el = uniform_ptr(entl + (int64_t)m * ng64);
+    int ls = ENT_SKIP;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        const int g = grp * R + j;
+        e[j] = g < ng64 ? el[g] : ENT_SKIP;
+        ls = e[j] < ls ? e[j] : ls;
+    }
+    const int64_t row = (int64_t)m * npairs;
     bool neg = false;
 #pragma unroll
     for (int j = 0; j < R; ++j) {
         const int p = grp * 64 * R + j * 64 + lane;
         pr[j] = p;
+        setx(x[j], 0.0);
+        c2[j] = p2[j] = cm[j] = pm[j] = (T)0;
+        k[j] = 0;
         if (p < npairs) {
-            x[j] = (T)pair_z[p];
-            load_seed<T>(seed2, seedm2, seedk, (int64_t)m * npairs + p, c2[j], cm[j], k[j]);
-        } else {
-            x[j] = (T)0;
-            c2[j] = cm[j] = (T)0;
-            k[j] = 0;
+            setx(x[j], pair_z[p]);
+            if (e[j] == ls && ls <= lmax) load_entry<T>(ent, entk, row + p, c2[j], p2[j], cm[j], pm[j], k[j]);
         }
-        p2[j] = pm[j] = (T)0;
         neg |= (k[j] < 0);
 #pragma unroll
         for (int c = 0; c < 8; ++c) acc0[c][j] = acc1[c][j] = (T)0;
     }
-    bool ramp = wave_any(neg);
-    int l = l0;
+    bool pend = R > 1 && pending<R>(ls, lmax, e);
+    bool ramp = wave_any(neg) || pend;
+    int l = ls <= lmax ? ls : lmax + 1;
     SynIn<T> i0;
     if constexpr (V == 0) {
         // plain: two steps per trip, loads issued inside the step
         while (ramp && l < lmax) {
-            syn_step<T, R, true>(syn_load<T>(rec, l), x, c2, p2, cm, pm, k, acc0);
-            syn_step<T, R, true>(syn_load<T>(rec, l + 1), x, c2, p2, cm, pm, k, acc1);
+            if (pend) {
+                inject<T, R>(l, e, pr, ent, entk, row, npairs, c2, p2, cm, pm, k);
+                pend = pending<R>(l, lmax, e);
+            }
+            syn_step<T, R, true>(rload(l), x, c2, p2, cm, pm, k, acc0);
+            syn_step<T, R, true>(rload(l + 1), x, c2, p2, cm, pm, k, acc1);
             l += 2;
-            ramp = rescale<T, R>(c2, p2, cm, pm, k);
+            ramp = rescale<T, R>(c2, p2, cm, pm, k) || pend;
         }
         l = __builtin_amdgcn_readfirstlane(l);
-        const_as<SynRec<T>> *rp = uniform_ptr(rec + l);  // keep the record address scalar
-        for (; l < lmax; l += 2, rp += 2) {
-            syn_step<T, R, false>(ld_rec<T>(rp), x, c2, p2, cm, pm, k, acc0);
-            syn_step<T, R, false>(ld_rec<T>(rp + 1), x, c2, p2, cm, pm, k, acc1);
+        SynSrc<T, IO> rp(rec + l, cf64 + l);  // keep the record address scalar
+        for (; l < lmax; l += 2, rp.adv(2)) {
+            syn_step<T, R, false>(rp.at(0), x, c2, p2, cm, pm, k, acc0);
+            syn_step<T, R, false>(rp.at(1), x, c2, p2, cm, pm, k, acc1);
         }
-        i0 = syn_load<T>(rec, l);
+        i0 = rload(l);
     } else {
         // ramp loop, then four steps per trip whose loads are issued one pair ahead into ping-pong
         // registers (no copies of loaded registers)
         while (ramp && l < lmax) {
-            syn_step<T, R, true>(syn_load<T>(rec, l), x, c2, p2, cm, pm, k, acc0);
-            syn_step<T, R, true>(syn_load<T>(rec, l + 1), x, c2, p2, cm, pm, k, acc1);
+            if (pend) {
+                inject<T, R>(l, e, pr, ent, entk, row, npairs, c2, p2, cm, pm, k);
+                pend = pending<R>(l, lmax, e);
+            }
+            syn_step<T, R, true>(rload(l), x, c2, p2, cm, pm, k, acc0);
+            syn_step<T, R, true>(rload(l + 1), x, c2, p2, cm, pm, k, acc1);
             l += 2;
-            ramp = rescale<T, R>(c2, p2, cm, pm, k);
+            ramp = rescale<T, R>(c2, p2, cm, pm, k) || pend;
         }
         l = __builtin_amdgcn_readfirstlane(l);
-        const_as<SynRec<T>> *rp = uniform_ptr(rec + l);
-        SynRec<T> a0 = ld_rec<T>(rp), a1 = ld_rec<T>(rp + 1), b0, b1;
-        for (; l + 3 <= lmax; l += 4, rp += 4) {
-            b0 = ld_rec<T>(rp + 2);
-            b1 = ld_rec<T>(rp + 3);
+        SynSrc<T, IO> rp(rec + l, cf64 + l);
+        SynRec<T> a0 = rp.at(0), a1 = rp.at(1), b0, b1;
+        for (; l + 3 <= lmax; l += 4, rp.adv(4)) {
+            b0 = rp.at(2);
+            b1 = rp.at(3);
             syn_step<T, R, false>(a0, x, c2, p2, cm, pm, k, acc0);
             syn_step<T, R, false>(a1, x, c2, p2, cm, pm, k, acc1);
-            a0 = ld_rec<T>(rp + 4);
-            a1 = ld_rec<T>(rp + 5);
+            a0 = rp.at(4);
+            a1 = rp.at(5);
             syn_step<T, R, false>(b0, x, c2, p2, cm, pm, k, acc0);
             syn_step<T, R, false>(b1, x, c2, p2, cm, pm, k, acc1);
         }
@@ -284,12 +477,15 @@ __global__ __launch_bounds__(256) void k_leg_synth(const SynRec<T> *__restrict__
             syn_step<T, R, false>(a1, x, c2, p2, cm, pm, k, acc1);
             l += 2;
         }
-        i0 = syn_load<T>(rec, l);
+        i0 = rload(l);
     }
-    if (l == lmax) syn_step<T, R, true>(i0, x, c2, p2, cm, pm, k, acc0);
+    if (l == lmax) {
+        if (pend) inject<T, R>(l, e, pr, ent, entk, row, npairs, c2, p2, cm, pm, k);
+        syn_step<T, R, true>(i0, x, c2, p2, cm, pm, k, acc0);
+    }
 
     const bool odd0 = ((l0 + m) & 1) != 0;  // acc0 holds l + m odd terms when true
-    cplx<T> *Fb = FG + rhs * fg_stride;
+    cplx<IO> *Fb = FG + rhs * fg_stride;
 #pragma unroll
     for (int j = 0; j < R; ++j) {
         if (pr[j] >= npairs) continue;
@@ -307,9 +503,9 @@ __global__ __launch_bounds__(256) void k_leg_synth(const SynRec<T> *__restrict__
                 S2[c] = E[c] + O[c];
                 Sm[c] = E[4 + c] + O[4 + c];
             }
-            cplx<T> *f = Fb + ((int64_t)rn * (lmax + 1) + m) * 2;
-            f[0] = mk<T>(-(S2[0] - S2[3]), -(S2[1] + S2[2]));
-            f[1] = mk<T>(-(Sm[0] + Sm[3]), -(Sm[2] - Sm[1]));
+            cplx<IO> *f = Fb + ((int64_t)rn * (lmax + 1) + m) * 2;
+            f[0] = mk<IO>((IO)(-(S2[0] - S2[3])), (IO)(-(S2[1] + S2[2])));
+            f[1] = mk<IO>((IO)(-(Sm[0] + Sm[3])), (IO)(-(Sm[2] - Sm[1])));
         }
         if (rs != rn) {
             T S2[4], Sm[4];
@@ -318,9 +514,9 @@ __global__ __launch_bounds__(256) void k_leg_synth(const SynRec<T> *__restrict__
                 S2[c] = E[4 + c] - O[4 + c];
                 Sm[c] = E[c] - O[c];
             }
-            cplx<T> *f = Fb + ((int64_t)rs * (lmax + 1) + m) * 2;
-            f[0] = mk<T>(-(S2[0] - S2[3]), -(S2[1] + S2[2]));
-            f[1] = mk<T>(-(Sm[0] + Sm[3]), -(Sm[2] - Sm[1]));
+            cplx<IO> *f = Fb + ((int64_t)rs * (lmax + 1) + m) * 2;
+            f[0] = mk<IO>((IO)(-(S2[0] - S2[3])), (IO)(-(S2[1] + S2[2])));
+            f[1] = mk<IO>((IO)(-(Sm[0] + Sm[3])), (IO)(-(Sm[2] - Sm[1])));
         }
     }
 }
@@ -332,7 +528,7 @@ __global__ __launch_bounds__(256) void k_leg_synth(const SynRec<T> *__restrict__
 // every L steps of l the per-lane partials go through LDS and are reduced over the workgroup.
 // ================================================================================================
 template <typename T, int R, bool MASK, bool ODD, typename C>
-__device__ __forceinline__ void adj_step(const C &c, T (&x)[R], T (&c2)[R],
+__device__ __forceinline__ void adj_step(const C &c, const typename XT<T>::type (&x)[R], T (&c2)[R],
                                          T (&p2)[R], T (&cm)[R], T (&pm)[R], const int (&k)[R],
                                          const cplx<T> (&GN)[R], const cplx<T> (&GS)[R], const cplx<T> (&HN)[R],
                                          const cplx<T> (&HS)[R], T (&out)[4])
@@ -353,7 +549,7 @@ __device__ __forceinline__ void adj_step(const C &c, T (&x)[R], T (&c2)[R],
         a1 = fma(s * vm, GS[j].y, a1);
         a2 = fma(s * v2, HS[j].x, a2);
         a3 = fma(s * v2, HS[j].y, a3);
-        const T u = c.a * x[j];
+        const T u = mulx(c.a, x[j]);
         const T n2 = fma(u + c.b, c2[j], -(c.g * p2[j]));
         const T nm = fma(u - c.b, cm[j], -(c.g * pm[j]));
         p2[j] = c2[j];
@@ -367,52 +563,78 @@ __device__ __forceinline__ void adj_step(const C &c, T (&x)[R], T (&c2)[R],
     out[3] = a3;
 }
 
-template <typename T, int R, int W, int L>
-__global__ __launch_bounds__(64 * W) void k_leg_adj(const cplx<T> *__restrict__ FG,
+// Workgroups rb0 .. rb0 + nrbl - 1 of the nrb ring blocks of every m; this launch's workgroup rbl
+// holds the 64-pair groups g0 + rbl W R .. g0 + (rbl + 1) W R - 1, bounded by gend.
+template <typename T, int R, int W, int L, typename IO = T>
+__global__ __launch_bounds__(64 * W) void k_leg_adj(const cplx<IO> *__restrict__ FG,
                                                     const typename CoefT<T>::type *__restrict__ coef,
-                                                    const double *__restrict__ seed2, const double *__restrict__ seedm2,
-                                                    const int *__restrict__ seedk, const double *__restrict__ pair_z,
-                                                    T *__restrict__ part, int64_t nalm, int lmax, int npairs,
-                                                    int nrings, int nrb)
+                                                    const Ent64 *__restrict__ ent, const int *__restrict__ entk,
+                                                    const int *__restrict__ entl, int ng64,
+                                                    const double *__restrict__ pair_z, IO *__restrict__ part,
+                                                    int *__restrict__ wgstart, int64_t nalm, int lmax, int npairs,
+                                                    int nrings, int g0, int gend, int rb0, int nrbl, int nrb)
 {
     __shared__ T red[W * L * 4 * 64];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    int m, rb;
-    xcd_map((int)blockIdx.x, nrb, m, rb);
+    int m, rbl;
+    xcd_map((int)blockIdx.x, nrbl, m, rbl);
     if (m > lmax) return;
+    const int rb = rb0 + rbl;
+    const int gw = g0 + rbl * W * R;                            // first group of the workgroup
+    const int pb = npairs < 64 * gend ? npairs : 64 * gend;    // pairs of this launch end here
     const int l0 = m > 2 ? m : 2;
     const int64_t base = (int64_t)m * (2 * lmax + 1 - m) / 2;
     const auto *cf = coef + base;
     const T sgn0 = ((l0 + m) & 1) ? (T)-1 : (T)1;
 
-    T x[R], c2[R], p2[R], cm[R], pm[R];
+    // entry degrees of the workgroup's 64-pair groups: the workgroup starts at the earliest, a slot
+    // whose group enters later holds zeros until its entry (always at a chunk start: entries are
+    // l0 + 8q and chunks start at l0 + Lq)
+    const_as<int> *el = uniform_ptr(entl + (int64_t)m * ng64);
+    int ls = ENT_SKIP;
+    for (int g = gw; g < gw + W * R && g < gend; ++g) ls = el[g] < ls ? el[g] : ls;
+    if (threadIdx.x == 0) wgstart[(int64_t)m * nrb + rb] = ls;
+    if (ls > lmax) return;
+    int e[R], pr[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        const int g = gw + wave * R + j;
+        e[j] = g < gend ? el[g] : ENT_SKIP;
+    }
+    const int64_t row = (int64_t)m * npairs;
+
+    typename XT<T>::type x[R];
+    T c2[R], p2[R], cm[R], pm[R];
     int k[R];
     cplx<T> GN[R], GS[R], HN[R], HS[R];
     bool neg = false;
 #pragma unroll
     for (int j = 0; j < R; ++j) {
-        const int p = rb * (64 * W * R) + (wave * R + j) * 64 + lane;
+        const int p = (gw + wave * R + j) * 64 + lane;
+        pr[j] = p;
         const cplx<T> z = mk<T>(0, 0);
         GN[j] = GS[j] = HN[j] = HS[j] = z;
-        x[j] = c2[j] = cm[j] = p2[j] = pm[j] = (T)0;
+        setx(x[j], 0.0);
+        c2[j] = cm[j] = p2[j] = pm[j] = (T)0;
         k[j] = 0;
-        if (p < npairs) {
-            x[j] = (T)pair_z[p];
-            load_seed<T>(seed2, seedm2, seedk, (int64_t)m * npairs + p, c2[j], cm[j], k[j]);
+        if (p < pb) {
+            setx(x[j], pair_z[p]);
+            if (e[j] == ls) load_entry<T>(ent, entk, row + p, c2[j], p2[j], cm[j], pm[j], k[j]);
             const int rn = p, rs = nrings - 1 - p;
-            const cplx<T> *fn = FG + ((int64_t)rn * (lmax + 1) + m) * 2;
-            GN[j] = fn[0];
-            HN[j] = cconj<T>(fn[1]);
+            const cplx<IO> *fn = FG + ((int64_t)rn * (lmax + 1) + m) * 2;
+            GN[j] = to_c<T, IO>(fn[0]);
+            HN[j] = cconj<T>(to_c<T, IO>(fn[1]));
             if (rs != rn) {
-                const cplx<T> *fs = FG + ((int64_t)rs * (lmax + 1) + m) * 2;
-                GS[j] = cscale<T>(fs[0], sgn0);
-                HS[j] = cscale<T>(cconj<T>(fs[1]), sgn0);
+                const cplx<IO> *fs = FG + ((int64_t)rs * (lmax + 1) + m) * 2;
+                GS[j] = cscale<T>(to_c<T, IO>(fs[0]), sgn0);
+                HS[j] = cscale<T>(cconj<T>(to_c<T, IO>(fs[1])), sgn0);
             }
         }
         neg |= (k[j] < 0);
     }
     bool ramp = wave_any(neg);
+    bool pend = (R > 1 || W > 1) && pending<R>(ls, lmax, e);
     const int NT = 64 * W, NO = 4 * L, G = NT / NO;
     const int t = threadIdx.x, o = t / G, gi = t - o * G;
     const int oli = o >> 2, oc = o & 3;
@@ -420,11 +642,19 @@ __global__ __launch_bounds__(64 * W) void k_leg_adj(const cplx<T> *__restrict__ 
     using C = typename CoefT<T>::type;
     // coefficient records through an explicitly uniform pointer (scalar loads); the table is padded
     // past its last column, so the look-ahead loads stay in bounds
-    const_as<C> *cp = uniform_ptr(cf + l0);
+    const_as<C> *cp = uniform_ptr(cf + ls);
     C cc[L];
 #pragma unroll
     for (int li = 0; li < L; ++li) cc[li] = ld_coef<C>(cp + li);
-    for (int lc = l0; lc <= lmax; lc += L, cp += L) {
+    for (int lc = ls; lc <= lmax; lc += L, cp += L) {
+        if (pend) {
+            inject<T, R>(lc, e, pr, ent, entk, row, pb, c2, p2, cm, pm, k);
+            bool ng = false;
+#pragma unroll
+            for (int j = 0; j < R; ++j) ng |= (k[j] < 0);
+            ramp = ramp || wave_any(ng);
+            pend = pending<R>(lc, lmax, e);
+        }
         if (ramp || lc + L - 1 > lmax) {
             // ramp (masked contraction, rescaling) or the last, partial chunk
 #pragma unroll
@@ -471,7 +701,7 @@ __global__ __launch_bounds__(64 * W) void k_leg_adj(const cplx<T> *__restrict__ 
         for (; q < NT; q += G) s0 += red[(((q >> 6) * L + oli) * 4 + oc) * 64 + (q & 63)];
         T s = (s0 + s1) + (s2 + s3);
         for (int off = G >> 1; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-        if (gi == 0 && lc + oli <= lmax) part[((int64_t)rb * nalm + base + lc + oli) * 4 + oc] = s;
+        if (gi == 0 && lc + oli <= lmax) part[((int64_t)rb * nalm + base + lc + oli) * 4 + oc] = (IO)s;
 #pragma unroll
         for (int li = 0; li < L; ++li) cc[li] = nc[li];
         __syncthreads();
@@ -505,10 +735,24 @@ __global__ void k_prologue(const double *__restrict__ xE, const double *__restri
     rec[rhs * rec_stride + i] = r;
 }
 
+// m of the alm index i = m (2 lmax + 1 - m)/2 + l
+__device__ __forceinline__ int m_of(int64_t i, int l, int lmax)
+{
+    const int64_t b = i - l;
+    const double A = 2.0 * lmax + 1.0;
+    int m = (int)((A - sqrt(A * A - 8.0 * (double)b)) * 0.5);
+    if (m < 0) m = 0;
+    if (m > lmax) m = lmax;
+    while (m > 0 && (int64_t)m * (2 * lmax + 1 - m) / 2 > b) --m;
+    while (m < lmax && (int64_t)(m + 1) * (2 * lmax - m) / 2 <= b) ++m;
+    return m;
+}
+
 template <typename T>
-__global__ void k_epilogue(const T *__restrict__ part, int nrb, int64_t nalm, const int *__restrict__ lof, int lmax,
-                           const double *__restrict__ kern, double lam, const double *__restrict__ xE,
-                           const double *__restrict__ xB, double *__restrict__ outE, double *__restrict__ outB)
+__global__ void k_epilogue(const T *__restrict__ part, const int *__restrict__ wgstart, int nrb, int64_t nalm,
+                           const int *__restrict__ lof, int lmax, const double *__restrict__ kern, double lam,
+                           const double *__restrict__ xE, const double *__restrict__ xB, double *__restrict__ outE,
+                           double *__restrict__ outB)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nalm) return;
@@ -516,7 +760,10 @@ __global__ void k_epilogue(const T *__restrict__ part, int nrb, int64_t nalm, co
     const bool m0 = i <= lmax;
     double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
     if (l >= 2) {
+        // ring blocks that started above l wrote nothing for it
+        const int *ws = wgstart + (int64_t)m_of(i, l, lmax) * nrb;
         for (int rb = 0; rb < nrb; ++rb) {
+            if (l < ws[rb]) continue;
             const T *q = part + ((int64_t)rb * nalm + i) * 4;
             s0 += (double)q[0];
             s1 += (double)q[1];
@@ -891,51 +1138,69 @@ void launch_prologue(Plan &P, bool fp32, const double *xE, const double *xB, con
                                                     (SynRec<double> *)P.d_rec);
 }
 
-template <typename T, int R, int V>
-static void syn_launch(Plan &P, int nrhs, int64_t fg_stride)
+// synthesis waves over the 64-pair groups [g0, g1) (g0 a multiple of R)
+template <typename T, int R, int V, typename IO>
+static void syn_launch(Plan &P, int nrhs, int64_t fg_stride, int g0, int g1)
 {
-    const int ngroups = (int)cdiv(P.npairs, 64 * R);
-    P.syn_groups = ngroups;
-    const int nbm = (int)cdiv(ngroups, 4);               // blocks of four waves per m
+    const int gbeg = g0 / R, gend = (int)cdiv(g1, R);
+    if (gend <= gbeg) return;
+    const int nbm = (int)cdiv(gend - gbeg, 4);  // blocks of four waves per m
     const int64_t blocks = 8 * nbm * cdiv(P.lmax + 1, 8);
     dim3 g((unsigned)blocks, nrhs);
-    k_leg_synth<T, R, V><<<g, 256, 0, P.stream>>>((const SynRec<T> *)P.d_rec, P.rec_stride, (cplx<T> *)P.d_FG,
-                                                  fg_stride, P.d_seed2, P.d_seedm2, P.d_seedk, P.d_pair_z, P.lmax,
-                                                  P.npairs, P.nrings, ngroups, nbm);
+    k_leg_synth<T, R, V, IO><<<g, 256, 0, P.stream>>>((const SynRec<IO> *)P.d_rec, P.rec_stride, P.d_coef64,
+                                                      (cplx<IO> *)P.d_FG, fg_stride, P.d_ent, P.d_entk, P.d_entl,
+                                                      P.ng64, P.d_pair_z, P.lmax, P.npairs, P.nrings, gbeg, gend,
+                                                      nbm);
 }
 
 template <typename T, int V>
-static void syn_dispatch_r(Plan &P, int nrhs, int64_t fg_stride)
+static void syn_dispatch_r(Plan &P, int nrhs, int64_t fg_stride, int g0)
 {
-    if (P.syn_R == 1) syn_launch<T, 1, V>(P, nrhs, fg_stride);
-    else if (P.syn_R == 2) syn_launch<T, 2, V>(P, nrhs, fg_stride);
-    else syn_launch<T, 4, V>(P, nrhs, fg_stride);
+    if (P.syn_R == 1) syn_launch<T, 1, V, T>(P, nrhs, fg_stride, g0, P.ng64);
+    else if (P.syn_R == 2) syn_launch<T, 2, V, T>(P, nrhs, fg_stride, g0, P.ng64);
+    else syn_launch<T, 4, V, T>(P, nrhs, fg_stride, g0, P.ng64);
 }
 
 template <typename T>
-static void syn_dispatch(Plan &P, int nrhs, int64_t fg_stride)
+static void syn_dispatch(Plan &P, int nrhs, int64_t fg_stride, int g0)
 {
-    if (P.syn_V == 0) syn_dispatch_r<T, 0>(P, nrhs, fg_stride);
-    else syn_dispatch_r<T, 1>(P, nrhs, fg_stride);
+    if (P.syn_V == 0) syn_dispatch_r<T, 0>(P, nrhs, fg_stride, g0);
+    else syn_dispatch_r<T, 1>(P, nrhs, fg_stride, g0);
+}
+
+void launch_entry(Plan &P)
+{
+    const int gpb = (int)cdiv(P.ng64, 4);
+    k_entry<<<(unsigned)((int64_t)gpb * (P.lmax + 1)), 256, 0, P.stream>>>(
+        P.d_seed2, P.d_seedm2, P.d_seedk, P.d_pair_z, P.d_coef64, P.d_ent, P.d_entk, P.d_entl, P.lmax, P.npairs, P.ng64,
+        gpb, P.prec == AKRA_FP32 ? 0x1p-44 : 0.0);
 }
 
 void launch_leg_synth(Plan &P, bool fp32, int nrhs)
 {
     const int64_t fg_stride = (int64_t)P.nrings * (P.lmax + 1) * 2;
-    if (fp32) syn_dispatch<float>(P, nrhs, fg_stride);
-    else syn_dispatch<double>(P, nrhs, fg_stride);
+    if (fp32) {
+        // near-polar ring groups in FP64 arithmetic, the rest in FP32
+        if (P.polar_groups) syn_launch<double, 1, 1, float>(P, nrhs, fg_stride, 0, P.polar_groups);
+        syn_dispatch<float>(P, nrhs, fg_stride, P.polar_groups);
+    } else {
+        syn_dispatch<double>(P, nrhs, fg_stride, 0);
+    }
 }
 
-template <typename T, int R, int W, int L>
-static void adj_launch(Plan &P, int rhs)
+// adjoint workgroups over the 64-pair groups [g0, g1), ring blocks rb0 .. of the plan's adj_nrb
+template <typename T, int R, int W, int L, typename IO>
+static void adj_launch(Plan &P, int rhs, int g0, int g1, int rb0)
 {
+    const int nrbl = (int)cdiv(g1 - g0, W * R);
+    if (nrbl <= 0) return;
     const int64_t fg_stride = (int64_t)P.nrings * (P.lmax + 1) * 2;
     const void *coef = std::is_same<T, double>::value ? (const void *)P.d_coef64 : (const void *)P.d_coef32;
-    dim3 g((unsigned)(8 * P.adj_nrb * cdiv(P.lmax + 1, 8)));
-    k_leg_adj<T, R, W, L><<<g, 64 * W, 0, P.stream>>>((const cplx<T> *)P.d_FG + rhs * fg_stride,
-                                                      (const typename CoefT<T>::type *)coef, P.d_seed2, P.d_seedm2,
-                                                      P.d_seedk, P.d_pair_z, (T *)P.d_part, P.nalm, P.lmax, P.npairs,
-                                                      P.nrings, P.adj_nrb);
+    dim3 g((unsigned)(8 * nrbl * cdiv(P.lmax + 1, 8)));
+    k_leg_adj<T, R, W, L, IO><<<g, 64 * W, 0, P.stream>>>(
+        (const cplx<IO> *)P.d_FG + rhs * fg_stride, (const typename CoefT<T>::type *)coef, P.d_ent, P.d_entk,
+        P.d_entl, P.ng64, P.d_pair_z, (IO *)P.d_part, P.d_wgstart, P.nalm, P.lmax, P.npairs, P.nrings, g0, g1, rb0,
+        nrbl, P.adj_nrb);
 }
 
 // supported adjoint shapes (ring pairs per lane, waves per workgroup, l-chunk)
@@ -944,14 +1209,14 @@ static void adj_launch(Plan &P, int rhs)
     X(2, 4, 4) X(4, 2, 4) X(4, 4, 4) X(8, 1, 4) X(2, 1, 8) X(4, 1, 4) X(4, 1, 8)
 
 template <typename T>
-static void adj_dispatch(Plan &P, int rhs)
+static void adj_dispatch(Plan &P, int rhs, int g0, int rb0)
 {
     const int R = P.adj_R, W = P.adj_W, L = P.adj_L;
 #define AKRA_ADJ_CASE(r, w, l) \
-    if (R == r && W == w && L == l) return adj_launch<T, r, w, l>(P, rhs);
+    if (R == r && W == w && L == l) return adj_launch<T, r, w, l, T>(P, rhs, g0, P.ng64, rb0);
     AKRA_ADJ_SHAPES(AKRA_ADJ_CASE)
 #undef AKRA_ADJ_CASE
-    adj_launch<T, 4, 4, 8>(P, rhs);
+    adj_launch<T, 4, 4, 8, T>(P, rhs, g0, P.ng64, rb0);
 }
 
 bool adj_shape_supported(int r, int w, int l)
@@ -965,8 +1230,13 @@ bool adj_shape_supported(int r, int w, int l)
 
 void launch_leg_adj(Plan &P, bool fp32, int rhs)
 {
-    if (fp32) adj_dispatch<float>(P, rhs);
-    else adj_dispatch<double>(P, rhs);
+    if (fp32) {
+        // near-polar ring groups in FP64 arithmetic (four groups per workgroup), the rest in FP32
+        if (P.polar_groups) adj_launch<double, 4, 1, 4, float>(P, rhs, 0, P.polar_groups, 0);
+        adj_dispatch<float>(P, rhs, P.polar_groups, P.adj_nrb_polar);
+    } else {
+        adj_dispatch<double>(P, rhs, 0, 0);
+    }
 }
 
 void launch_epilogue(Plan &P, bool fp32, const double *kern, double lam, const double *xE, const double *xB,
@@ -974,11 +1244,11 @@ void launch_epilogue(Plan &P, bool fp32, const double *kern, double lam, const d
 {
     dim3 g((unsigned)cdiv(P.nalm, 256));
     if (fp32)
-        k_epilogue<float><<<g, 256, 0, P.stream>>>((const float *)P.d_part, P.adj_nrb, P.nalm, P.d_lof, P.lmax, kern,
-                                                   lam, xE, xB, outE, outB);
+        k_epilogue<float><<<g, 256, 0, P.stream>>>((const float *)P.d_part, P.d_wgstart, P.adj_nrb, P.nalm, P.d_lof,
+                                                   P.lmax, kern, lam, xE, xB, outE, outB);
     else
-        k_epilogue<double><<<g, 256, 0, P.stream>>>((const double *)P.d_part, P.adj_nrb, P.nalm, P.d_lof, P.lmax,
-                                                    kern, lam, xE, xB, outE, outB);
+        k_epilogue<double><<<g, 256, 0, P.stream>>>((const double *)P.d_part, P.d_wgstart, P.adj_nrb, P.nalm,
+                                                    P.d_lof, P.lmax, kern, lam, xE, xB, outE, outB);
 }
 
 template <typename T, int MODE>

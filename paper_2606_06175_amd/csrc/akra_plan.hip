@@ -11,6 +11,14 @@
 
 #include "akra_internal.h"
 
+// FP32 plans evaluate the spin-weighted recurrences of rings within AKRA_POLAR_K sqrt(lmax) radians
+// of a pole in FP64.  Near the poles the per-step phase advance of the recurrence is of the order of
+// theta, so the FP32 rounding of each step moves the phase by ~eps/theta and the error of the
+// transform grows like sqrt(l) eps / theta; at theta above this bound it stays below 1e-5.
+#ifndef AKRA_POLAR_K
+#define AKRA_POLAR_K 0.01
+#endif
+
 namespace akra {
 
 static thread_local std::string g_err;
@@ -165,6 +173,35 @@ static void build_seeds(Plan &P, std::vector<double> &s2, std::vector<double> &s
     });
 }
 
+// Triples (l, m, ring pair) the Legendre kernels evaluate with the current launch shapes: a wave of
+// the synthesis starts at the earliest entry degree of its slots' groups, a workgroup of the adjoint
+// at the earliest of its groups; every lane of a started wave or workgroup steps to lmax.
+static void compute_work(Plan &P)
+{
+    const int lmax = P.lmax, np = P.npairs, ng = P.ng64, gp = P.polar_groups;
+    auto pairs_in = [&](int g0, int g1) { return (int64_t)std::max(0, std::min(np, 64 * g1) - 64 * g0); };
+    int64_t all = 0, syn = 0, adj = 0;
+    // blocks of gs groups over [g0, g1): each starts at the earliest entry degree of its groups
+    auto seg = [&](const int *e, int g0, int g1, int gs) {
+        int64_t w = 0;
+        for (int b = g0; b < g1; b += gs) {
+            int ls = ENT_SKIP;
+            for (int g = b; g < std::min(g1, b + gs); ++g) ls = std::min(ls, e[g]);
+            if (ls <= lmax) w += pairs_in(b, std::min(g1, b + gs)) * (lmax - ls + 1);
+        }
+        return w;
+    };
+    for (int m = 0; m <= lmax; ++m) {
+        all += (int64_t)np * (lmax - std::max(m, 2) + 1);
+        const int *e = P.h_entl.data() + (size_t)m * ng;
+        syn += seg(e, 0, gp, 1) + seg(e, gp, ng, P.syn_R);
+        adj += seg(e, 0, gp, 4) + seg(e, gp, ng, P.adj_R * P.adj_W);
+    }
+    P.work[0] = all;
+    P.work[1] = syn;
+    P.work[2] = adj;
+}
+
 static akra_status upload(void **dst, const void *src, size_t bytes, Plan &P)
 {
     AK_HIP(hipMalloc(dst, std::max<size_t>(bytes, 16)), "hipMalloc");
@@ -190,6 +227,7 @@ static void default_kernel(int lmax, std::vector<double> &k)
 static void free_plan(Plan *P)
 {
     void *ptrs[] = {P->d_rings, P->d_pair_z, P->d_coef64, P->d_coef32, P->d_seed2, P->d_seedm2, P->d_seedk,
+                    P->d_ent, P->d_entk, P->d_entl, P->d_wgstart,
                     P->d_tw64, P->d_tw32, P->d_lof, P->d_order_p2, P->d_order_bl, P->d_FG, P->d_part, P->d_rec, P->d_W, P->d_kern, P->d_kuser, P->d_red, P->d_scal, P->d_flag, P->d_x, P->d_r,
                     P->d_p, P->d_w, P->d_b, P->d_xs};
     for (void *q : ptrs)
@@ -251,6 +289,16 @@ static akra_status create(int nside, int lmax, int nrhs, int prec, void *stream,
     P->maxM_bl = maxbl;
     P->twn = std::max(2, std::max(maxp2, maxbl));
 
+    // near-polar groups of FP32 plans: first pair of the group within theta_c of a pole
+    P->ng64 = (P->npairs + 63) / 64;
+    if (prec == AKRA_FP32) {
+        const double theta_c = AKRA_POLAR_K * std::sqrt((double)lmax);
+        int g = 0;
+        while (g < P->ng64 && std::acos(P->h_rings[64 * g].z) < theta_c) ++g;
+        P->polar_groups = std::min(P->ng64, (g + 3) / 4 * 4);
+        P->adj_nrb_polar = (P->polar_groups + 3) / 4;
+    }
+
     // Legendre launch shapes
     P->syn_R = P->npairs >= 256 ? 2 : 1;
     P->syn_groups = (P->npairs + 64 * P->syn_R - 1) / (64 * P->syn_R);
@@ -263,7 +311,7 @@ static akra_status create(int nside, int lmax, int nrhs, int prec, void *stream,
         }
     P->adj_R = caps[ci][0];
     P->adj_W = caps[ci][1];
-    P->adj_nrb = (P->npairs + 64 * P->adj_R * P->adj_W - 1) / (64 * P->adj_R * P->adj_W);
+    P->adj_nrb = P->adj_nrb_polar + (P->ng64 - P->polar_groups + P->adj_R * P->adj_W - 1) / (P->adj_R * P->adj_W);
 
     akra_status st;
 #define AK_TRY(x)                \
@@ -299,6 +347,26 @@ static akra_status create(int nside, int lmax, int nrhs, int prec, void *stream,
         AK_TRY(upload((void **)&P->d_order_p2, p2.data(), p2.size() * sizeof(int), *P));
         AK_TRY(upload((void **)&P->d_order_bl, bl.data(), bl.size() * sizeof(int), *P));
     }
+    // entry states of the recurrence (the seeds are only needed to build them)
+    {
+        const size_t nmp = (size_t)(lmax + 1) * P->npairs;
+        AK_TRY(alloc((void **)&P->d_ent, nmp * sizeof(Ent64), *P));
+        AK_TRY(alloc((void **)&P->d_entk, nmp * sizeof(int), *P));
+        AK_TRY(alloc((void **)&P->d_entl, (size_t)(lmax + 1) * P->ng64 * sizeof(int), *P));
+        launch_entry(*P);
+        P->h_entl.resize((size_t)(lmax + 1) * P->ng64);
+        if (hipGetLastError() != hipSuccess || hipStreamSynchronize(P->stream) != hipSuccess ||
+            hipMemcpy(P->h_entl.data(), P->d_entl, P->h_entl.size() * sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) {
+            free_plan(P);
+            set_error("entry-state kernel failed");
+            return AKRA_ERR_HIP;
+        }
+        for (void **q : {(void **)&P->d_seed2, (void **)&P->d_seedm2, (void **)&P->d_seedk}) {
+            (void)hipFree(*q);
+            *q = nullptr;
+        }
+        P->device_bytes -= (int64_t)nmp * (2 * sizeof(double) + sizeof(int));
+    }
     {
         const int n = P->twn / 2;
         std::vector<double2> t64(n);
@@ -324,8 +392,10 @@ static akra_status create(int nside, int lmax, int nrhs, int prec, void *stream,
     // workspaces
     const size_t fg = (size_t)nrhs * P->nrings * (lmax + 1) * 2 * sizeof(double2);
     AK_TRY(alloc(&P->d_FG, fg, *P));
-    P->part_rb_cap = (size_t)std::max(P->adj_nrb, P->npairs <= 1024 ? (P->npairs + 63) / 64 : (P->npairs + 255) / 256);
+    P->part_rb_cap = (size_t)std::max(P->adj_nrb, P->adj_nrb_polar + (P->npairs <= 1024 ? P->ng64 : (P->ng64 + 3) / 4));
     AK_TRY(alloc(&P->d_part, P->part_rb_cap * P->nalm * 4 * sizeof(double), *P));
+    AK_TRY(alloc((void **)&P->d_wgstart, P->part_rb_cap * (lmax + 1) * sizeof(int), *P));
+    compute_work(*P);
     P->rec_stride = P->nalm + ALM_PAD;
     AK_TRY(alloc(&P->d_rec, (size_t)nrhs * P->rec_stride * 64, *P));
     if (hipMemset(P->d_rec, 0, (size_t)nrhs * P->rec_stride * 64) != hipSuccess) {
@@ -971,8 +1041,8 @@ akra_status akra_plan_set_tuning(akra_plan plan, int syn_variant, int syn_rings,
         set_error("unsupported tuning (see akra.h for the supported launch shapes)");
         return AKRA_ERR_ARG;
     }
-    const int cap = 64 * adj_rings * adj_waves;
-    const int nrb = (P.npairs + cap - 1) / cap;
+    const int gpw = adj_rings * adj_waves;
+    const int nrb = P.adj_nrb_polar + (P.ng64 - P.polar_groups + gpw - 1) / gpw;
     if ((size_t)nrb > P.part_rb_cap) {
         set_error("adjoint shape needs more ring blocks than the plan's partial-sum buffer holds");
         return AKRA_ERR_ARG;
@@ -983,6 +1053,18 @@ akra_status akra_plan_set_tuning(akra_plan plan, int syn_variant, int syn_rings,
     P.adj_W = adj_waves;
     P.adj_L = adj_chunk;
     P.adj_nrb = nrb;
+    compute_work(P);
+    return AKRA_OK;
+}
+
+akra_status akra_plan_work(akra_plan plan, int64_t *out3)
+{
+    AK_PLAN();
+    if (!out3) {
+        set_error("out3 is NULL");
+        return AKRA_ERR_ARG;
+    }
+    for (int i = 0; i < 3; ++i) out3[i] = P.work[i];
     return AKRA_OK;
 }
 

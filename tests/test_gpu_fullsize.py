@@ -1,0 +1,117 @@
+"""GPU parity at the benchmark size (HEALPix Nside 2048, lmax 4096), in the launch configuration the
+benchmark times (autotuned shapes): outputs the oracle can compute one by one (the synthesis on
+sampled rings, the adjoint for sampled m) and properties that hold at any size (symmetry of H,
+FP32 against FP64)."""
+import numpy as np
+import pytest
+
+import akra_workloads as wl
+from oracle.core import Oracle
+from oracle.geometry import healpix_rings
+
+pytestmark = pytest.mark.gpu
+
+NSIDE, LMAX = 2048, 4096
+TOL = {"fp64": 1e-10, "fp32": 1e-5}
+# north pole, cap, last cap ring, belt, equator, south belt, south cap, south pole
+RINGS = [0, 5, 1500, 2046, 4095, 7000, 8190]
+MS = [0, 1, 2, 1000, 3333, 4096]
+
+
+def rel(a, b):
+    a = np.ravel(a)
+    b = np.ravel(b)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def big():
+    import torch
+    dev = torch.device("cuda", 0)
+    rings = healpix_rings(NSIDE)
+    o = Oracle(LMAX, rings)
+    aE = wl.random_alm(LMAX, 11)
+    aB = wl.random_alm(LMAX, 12)
+    h1, h2 = wl.random_maps(12 * NSIDE * NSIDE, 13)
+    print("oracle: synthesis on %d rings, adjoint for %d m" % (len(RINGS), len(MS)), flush=True)
+    syn = o.synth(aE, aB, ring_idx=RINGS)
+    adj = o.adjoint(h1, h2, mlist=MS)
+    return dict(torch=torch, dev=dev, rings=rings, o=o, aE=aE, aB=aB, h1=h1, h2=h2, syn=syn, adj=adj)
+
+
+def _plan(prec):
+    from paper_2606_06175_amd import Plan
+    print("plan nside=%d lmax=%d %s" % (NSIDE, LMAX, prec), flush=True)
+    return Plan(NSIDE, LMAX, precision=prec, device="cuda:0")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_synth_sampled_rings(big, prec):
+    torch, dev, o, rings = big["torch"], big["dev"], big["o"], big["rings"]
+    p = _plan(prec)
+    g1, g2 = p.synth2(torch.from_numpy(big["aE"]).to(dev), torch.from_numpy(big["aB"]).to(dev))
+    g1, g2 = g1.cpu().numpy(), g2.cpu().numpy()
+    p.close()
+    r1, r2 = big["syn"]
+    for r in RINGS:
+        a, n = int(rings.ofs[r]), int(rings.nphi[r])
+        got = np.r_[g1[a:a + n], g2[a:a + n]]
+        ref = np.r_[r1[a:a + n], r2[a:a + n]]
+        e = rel(got, ref)
+        print("ring %d rel %.3e" % (r, e), flush=True)
+        assert e < TOL[prec], (r, e)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_adjoint_sampled_m(big, prec):
+    torch, dev, o = big["torch"], big["dev"], big["o"]
+    p = _plan(prec)
+    cE, cB = p.adjoint2(torch.from_numpy(big["h1"]).to(dev), torch.from_numpy(big["h2"]).to(dev))
+    cE, cB = cE.cpu().numpy(), cB.cpu().numpy()
+    p.close()
+    rE, rB = big["adj"]
+    for m in MS:
+        sl = slice(m * (2 * LMAX + 1 - m) // 2 + m, m * (2 * LMAX + 1 - m) // 2 + LMAX + 1)
+        e = rel(np.r_[cE[sl], cB[sl]], np.r_[rE[sl], rB[sl]])
+        print("m %d rel %.3e" % (m, e), flush=True)
+        assert e < TOL[prec], (m, e)
+
+
+def test_work_accounting(big):
+    p = _plan("fp64")
+    w = p.work()
+    npairs = 2 * NSIDE
+    assert w["all"] == npairs * sum(LMAX - max(2, m) + 1 for m in range(LMAX + 1))
+    assert 0 < w["synth"] < w["all"] and 0 < w["adjoint"] < w["all"]
+    # the skipped terms are those of near-polar rings at high m: well below half of all
+    assert w["synth"] > 0.5 * w["all"]
+
+
+def test_apply_H_symmetric_and_fp32_agrees(big):
+    # <u, H v> = <H u, v> in the full-m product; FP32 operator within 1e-5 of FP64
+    torch, dev = big["torch"], big["dev"]
+    cfg_mask = wl.cap_mask(NSIDE, 2.0, 0.5, 0.1)
+    mask = torch.from_numpy(cfg_mask.astype(np.uint8)).to(dev)
+    ninv = torch.from_numpy(np.random.default_rng(3).uniform(5.0, 60.0, 12 * NSIDE * NSIDE)).to(dev)
+    u = [torch.from_numpy(a).to(dev) for a in (big["aE"], big["aB"])]
+    v = [torch.from_numpy(wl.random_alm(LMAX, s)).to(dev) for s in (21, 22)]
+    w = torch.full((u[0].numel(),), 2.0, dtype=torch.float64, device=dev)
+    w[: LMAX + 1] = 1.0
+
+    def dot(a, b):
+        return float((w * (a[0].conj() * b[0]).real).sum() + (w * (a[1].conj() * b[1]).real).sum())
+
+    out = {}
+    for prec in ("fp64", "fp32"):
+        p = _plan(prec)
+        Hv = p.apply_H(ninv, mask, v[0], v[1], 0.01)
+        Hu = p.apply_H(ninv, mask, u[0], u[1], 0.01)
+        out[prec] = (Hv, Hu)
+        lhs, rhs = dot(u, Hv), dot(Hu, v)
+        print("%s <u,Hv> %.15e <Hu,v> %.15e" % (prec, lhs, rhs), flush=True)
+        assert abs(lhs - rhs) < TOL[prec] * np.sqrt(dot(Hv, Hv) * dot(u, u))
+        p.close()
+    for i in range(2):
+        a = torch.stack([out["fp32"][i][0], out["fp32"][i][1]]).cpu().numpy()
+        b = torch.stack([out["fp64"][i][0], out["fp64"][i][1]]).cpu().numpy()
+        assert rel(a, b) < 1e-5
