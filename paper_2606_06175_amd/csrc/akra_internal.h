@@ -37,6 +37,14 @@ struct alignas(32) Coef64 {
 struct alignas(16) Coef32 {
     float a, b, g, pad;
 };
+// Near the poles FP32 kernels run the recurrence in difference form, with d_l = lambda_l - lambda_{l-1}
+// and y = 1 - x:
+//   d_{l+1} = (e - a y) lambda_l + g d_l,   lambda_{l+1} = lambda_l + d_{l+1},   e = a +- b - g - 1.
+// There a x + b - g - 1 is small while a x + b is close to 2 and the plain form loses its
+// information to rounding; e is formed in extended precision at plan creation.
+struct alignas(16) Coef32D {
+    float a, ep, em, g;  // a, e for spin +2, e for spin -2, g
+};
 
 // State of the recurrence of one (m, ring pair) at the entry degree of the pair's 64-pair group:
 // lambda_l and lambda_{l-1} for spin +2 and -2, sharing one scale exponent (kept beside it).
@@ -71,6 +79,7 @@ struct Plan {
     double *d_pair_z = nullptr;
     Coef64 *d_coef64 = nullptr;
     Coef32 *d_coef32 = nullptr;
+    Coef32D *d_coef32d = nullptr;
     double *d_seed2 = nullptr, *d_seedm2 = nullptr;  // [m][pair] seeds at l = max(m,2) (plan build only)
     int *d_seedk = nullptr;
     Ent64 *d_ent = nullptr;     // [m][pair] entry states
@@ -91,8 +100,8 @@ struct Plan {
     int syn_R = 1, syn_V = 1, syn_groups = 1;
     int adj_R = 1, adj_W = 1, adj_L = 8, adj_nrb = 1;
     size_t part_rb_cap = 1;  // ring blocks the partial-sum buffer holds
-    // FP32 plans: the 64-pair groups nearest the poles run the Legendre stages in FP64 arithmetic
-    // (FP32 storage); the adjoint covers them with adj_nrb_polar ring blocks of four groups
+    // FP32 plans: the 64-pair groups nearest the poles run the Legendre stages in the difference
+    // form; the adjoint covers them with adj_nrb_polar ring blocks of four groups
     int polar_groups = 0, adj_nrb_polar = 0;
 
     // workspaces (sized for FP64; FP32 views reuse them)

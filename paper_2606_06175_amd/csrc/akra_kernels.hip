@@ -16,9 +16,12 @@ template <typename T> struct V2;
 template <> struct V2<double> { using type = double2; };
 template <> struct V2<float> { using type = float2; };
 template <typename T> using cplx = typename V2<T>::type;
-template <typename T> struct CoefT;
-template <> struct CoefT<double> { using type = Coef64; };
-template <> struct CoefT<float> { using type = Coef32; };
+// Recurrence forms: 0 the plain three-term form (FP64, and FP32 away from the poles), 1 the
+// difference form of FP32 near the poles (see Coef32D).
+template <typename T, int F> struct CoefT;
+template <> struct CoefT<double, 0> { using type = Coef64; };
+template <> struct CoefT<float, 0> { using type = Coef32; };
+template <> struct CoefT<float, 1> { using type = Coef32D; };
 
 template <typename T> __device__ __forceinline__ cplx<T> mk(T a, T b) { cplx<T> r; r.x = a; r.y = b; return r; }
 template <typename T> __device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> b)
@@ -45,7 +48,7 @@ template <typename T> __device__ __forceinline__ cplx<T> cis_pi(int64_t k, int64
 // ------------------------------------------------------------------------------------------------
 // Entry states: stored in FP64 as mant * 2^(512 k).  FP32 kernels re-express them in their own unit.
 // ------------------------------------------------------------------------------------------------
-template <typename T>
+template <typename T, int F>
 __device__ __forceinline__ void load_entry(const Ent64 *__restrict__ ent, const int *__restrict__ entk, int64_t idx,
                                            T &c2, T &p2, T &cm, T &pm, int &k)
 {
@@ -58,7 +61,9 @@ __device__ __forceinline__ void load_entry(const Ent64 *__restrict__ ent, const 
         pm = e.pm;
         k = k64;
     } else {
-        const double big = fmax(fmax(fabs(e.c2), fabs(e.cm)), fmax(fabs(e.p2), fabs(e.pm)));
+        // difference form: p2, pm carry lambda_l - lambda_{l-1}
+        const double d2 = F ? e.c2 - e.p2 : e.p2, dm = F ? e.cm - e.pm : e.pm;
+        const double big = fmax(fmax(fabs(e.c2), fabs(e.cm)), fmax(fabs(d2), fabs(dm)));
         if (big == 0.0) {
             c2 = p2 = cm = pm = 0.0f;
             k = 0;
@@ -68,9 +73,9 @@ __device__ __forceinline__ void load_entry(const Ent64 *__restrict__ ent, const 
         const int k32 = (ex >= -40) ? 0 : -((20 - ex) / 64);
         const int sh = 512 * k64 - 64 * k32;
         c2 = (float)ldexp(e.c2, sh);
-        p2 = (float)ldexp(e.p2, sh);
+        p2 = (float)ldexp(d2, sh);
         cm = (float)ldexp(e.cm, sh);
-        pm = (float)ldexp(e.pm, sh);
+        pm = (float)ldexp(dm, sh);
         k = k32;
     }
 }
@@ -94,32 +99,94 @@ template <typename P> __device__ __forceinline__ const_as<P> *uniform_ptr(const 
     return (const_as<P> *)(((uint64_t)hi << 32) | lo);
 }
 
-template <typename C> __device__ __forceinline__ C ld_coef(const_as<C> *p)
+__device__ __forceinline__ Coef64 ld_coef(const_as<Coef64> *p)
 {
-    C c;
+    Coef64 c;
     c.a = p->a;
     c.b = p->b;
     c.g = p->g;
     c.pad = 0;
     return c;
 }
+__device__ __forceinline__ Coef32 ld_coef(const_as<Coef32> *p)
+{
+    Coef32 c;
+    c.a = p->a;
+    c.b = p->b;
+    c.g = p->g;
+    c.pad = 0;
+    return c;
+}
+__device__ __forceinline__ Coef32D ld_coef(const_as<Coef32D> *p)
+{
+    Coef32D c;
+    c.a = p->a;
+    c.ep = p->ep;
+    c.em = p->em;
+    c.g = p->g;
+    return c;
+}
 
-// cos(theta) of a ring pair as the recurrences use it.  FP32 kernels carry it as an unevaluated sum
-// hi + lo of two floats: rounding cos(theta) itself to FP32 would move the ring by a fixed angle,
-// an error that grows linearly along the recurrence in l; with the split only the per-step
-// rounding of a x remains.
+// The ring pair's position as the recurrences use it.  FP64: x = cos(theta).  FP32 carries its
+// coordinate as an unevaluated sum hi + lo of two floats, x = cos(theta) in the plain form and
+// y = 1 - cos(theta) (exact in double for the ring's defining z) in the difference form: rounding
+// it to one float would move the ring by a fixed angle, an error that grows linearly along l.
 struct XF {
     float hi, lo;
 };
-template <typename T> struct XT { using type = T; };
-template <> struct XT<float> { using type = XF; };
-__device__ __forceinline__ double mulx(double a, double x) { return a * x; }
-__device__ __forceinline__ float mulx(float a, XF x) { return fmaf(a, x.hi, a * x.lo); }
-__device__ __forceinline__ void setx(double &x, double z) { x = z; }
-__device__ __forceinline__ void setx(XF &x, double z)
+struct YF {
+    float hi, lo;
+};
+template <typename T, int F> struct PosT;
+template <> struct PosT<double, 0> { using type = double; };
+template <> struct PosT<float, 0> { using type = XF; };
+template <> struct PosT<float, 1> { using type = YF; };
+__device__ __forceinline__ void setpos(double &x, double z) { x = z; }
+__device__ __forceinline__ void setpos(XF &x, double z)
 {
     x.hi = (float)z;
     x.lo = (float)(z - (double)x.hi);
+}
+__device__ __forceinline__ void setpos(YF &y, double z)
+{
+    const double v = 1.0 - z;
+    y.hi = (float)v;
+    y.lo = (float)(v - (double)y.hi);
+}
+
+// One step l -> l+1 of the spin +2 and spin -2 recurrences.  Plain form: (c2, p2) = (lambda_l,
+// lambda_{l-1}).  Difference form: (c2, p2) = (lambda_l, lambda_l - lambda_{l-1}).
+template <class C>
+__device__ __forceinline__ void rstep(const C &c, double x, double &c2, double &p2, double &cm, double &pm)
+{
+    const double u = c.a * x;
+    const double n2 = fma(u + c.b, c2, -(c.g * p2));
+    const double nm = fma(u - c.b, cm, -(c.g * pm));
+    p2 = c2;
+    c2 = n2;
+    pm = cm;
+    cm = nm;
+}
+template <class C>
+__device__ __forceinline__ void rstep(const C &c, XF x, float &c2, float &p2, float &cm, float &pm)
+{
+    const float u = fmaf(c.a, x.hi, c.a * x.lo);
+    const float n2 = fmaf(u + c.b, c2, -(c.g * p2));
+    const float nm = fmaf(u - c.b, cm, -(c.g * pm));
+    p2 = c2;
+    c2 = n2;
+    pm = cm;
+    cm = nm;
+}
+template <class C>
+__device__ __forceinline__ void rstep(const C &c, YF y, float &c2, float &p2, float &cm, float &pm)
+{
+    const float t = c.a * y.lo;
+    const float kp = fmaf(-c.a, y.hi, c.ep - t), km = fmaf(-c.a, y.hi, c.em - t);
+    p2 = fmaf(kp, c2, c.g * p2);
+    pm = fmaf(km, cm, c.g * pm);
+    c2 += p2;
+    cm += pm;
 }
 
 // wave-uniform "any lane"
@@ -136,18 +203,39 @@ __device__ __forceinline__ bool wave_any(bool p) { return __ballot(p) != 0ull; }
 // Per-(l, m) wave-uniform input of the synthesis, written by the prologue: the recurrence
 // coefficients next to the kernel-scaled alm (Im(a_l0) zeroed), one record of 8 values so that a
 // step is a single scalar load.  The record buffer is padded so look-ahead loads stay in bounds.
-template <typename T> struct alignas(8 * sizeof(T)) SynRec {
-    T a, b, g, pad, er, ei, br, bi;
+template <typename T> struct SynRec;
+template <> struct alignas(64) SynRec<double> {
+    double a, b, g, pad, er, ei, br, bi;
+};
+template <> struct alignas(32) SynRec<float> {
+    float a, b, g, pad, er, ei, br, bi;
+};
+// record of the difference form, assembled from the coefficient table and the alm records
+struct SynRecD {
+    float a, ep, em, g, er, ei, br, bi;
 };
 template <typename T> using SynIn = SynRec<T>;
 
-template <typename T> __device__ __forceinline__ SynRec<T> ld_rec(const_as<SynRec<T>> *p)
+__device__ __forceinline__ SynRec<double> ld_rec(const_as<SynRec<double>> *p)
 {
-    SynRec<T> r;
+    SynRec<double> r;
     r.a = p->a;
     r.b = p->b;
     r.g = p->g;
-    r.pad = (T)0;
+    r.pad = 0.0;
+    r.er = p->er;
+    r.ei = p->ei;
+    r.br = p->br;
+    r.bi = p->bi;
+    return r;
+}
+__device__ __forceinline__ SynRec<float> ld_rec(const_as<SynRec<float>> *p)
+{
+    SynRec<float> r;
+    r.a = p->a;
+    r.b = p->b;
+    r.g = p->g;
+    r.pad = 0.0f;
     r.er = p->er;
     r.ei = p->ei;
     r.br = p->br;
@@ -162,30 +250,30 @@ __device__ __forceinline__ SynIn<T> syn_load(const SynRec<T> *__restrict__ rec, 
     return rec[l];
 }
 
-// Wave-uniform source of the synthesis records for compute type T from records stored as IO.  With
-// T = double and IO = float (the near-polar rings of an FP32 plan, computed in FP64) the recurrence
-// coefficients come from the FP64 table and the alm values from the FP32 records.
-template <typename T, typename IO> struct SynSrc;
-template <typename T> struct SynSrc<T, T> {
+// Wave-uniform source of the synthesis records of form F: the prologue's records for the plain form;
+// for the FP32 difference form the coefficients come from their own table and the alm values from
+// the records.
+template <typename T, int F> struct SynSrc;
+template <typename T> struct SynSrc<T, 0> {
     const_as<SynRec<T>> *r;
-    __device__ __forceinline__ SynSrc(const SynRec<T> *rec, const Coef64 *) : r(uniform_ptr(rec)) {}
-    __device__ __forceinline__ SynRec<T> at(int i) const { return ld_rec<T>(r + i); }
+    __device__ __forceinline__ SynSrc(const SynRec<T> *rec, const Coef32D *) : r(uniform_ptr(rec)) {}
+    __device__ __forceinline__ SynRec<T> at(int i) const { return ld_rec(r + i); }
     __device__ __forceinline__ void adv(int n) { r += n; }
 };
-template <> struct SynSrc<double, float> {
+template <> struct SynSrc<float, 1> {
     const_as<SynRec<float>> *r;
-    const_as<Coef64> *c;
-    __device__ __forceinline__ SynSrc(const SynRec<float> *rec, const Coef64 *cf)
+    const_as<Coef32D> *c;
+    __device__ __forceinline__ SynSrc(const SynRec<float> *rec, const Coef32D *cf)
         : r(uniform_ptr(rec)), c(uniform_ptr(cf))
     {
     }
-    __device__ __forceinline__ SynRec<double> at(int i) const
+    __device__ __forceinline__ SynRecD at(int i) const
     {
-        SynRec<double> o;
+        SynRecD o;
         o.a = c[i].a;
-        o.b = c[i].b;
+        o.ep = c[i].ep;
+        o.em = c[i].em;
         o.g = c[i].g;
-        o.pad = 0.0;
         o.er = r[i].er;
         o.ei = r[i].ei;
         o.br = r[i].br;
@@ -199,11 +287,6 @@ template <> struct SynSrc<double, float> {
     }
 };
 
-template <typename T, typename IO> __device__ __forceinline__ cplx<T> to_c(cplx<IO> v)
-{
-    return mk<T>((T)v.x, (T)v.y);
-}
-
 // XCD-aware placement: workgroups are dealt to the 8 XCDs round-robin, so all blocks of one m
 // are mapped to blocks with the same index mod 8 (they share that XCD's L2 for the per-m data),
 // and each XCD walks its m values in increasing order (decreasing work).
@@ -214,8 +297,8 @@ __device__ __forceinline__ void xcd_map(int b, int nbm, int &m, int &blk)
     blk = local - (local / nbm) * nbm;
 }
 
-template <typename T, int R, bool MASK, typename In>
-__device__ __forceinline__ void syn_step(const In &in, const typename XT<T>::type (&x)[R], T (&c2)[R], T (&p2)[R], T (&cm)[R],
+template <typename T, int R, bool MASK, typename In, typename X>
+__device__ __forceinline__ void syn_step(const In &in, const X (&x)[R], T (&c2)[R], T (&p2)[R], T (&cm)[R],
                                          T (&pm)[R], const int (&k)[R], T (&acc)[8][R])
 {
 #pragma unroll
@@ -232,13 +315,7 @@ __device__ __forceinline__ void syn_step(const In &in, const typename XT<T>::typ
         acc[5][j] = fma(vm, in.ei, acc[5][j]);
         acc[6][j] = fma(vm, in.br, acc[6][j]);
         acc[7][j] = fma(vm, in.bi, acc[7][j]);
-        const T u = mulx(in.a, x[j]);
-        const T n2 = fma(u + in.b, c2[j], -(in.g * p2[j]));
-        const T nm = fma(u - in.b, cm[j], -(in.g * pm[j]));
-        p2[j] = c2[j];
-        c2[j] = n2;
-        pm[j] = cm[j];
-        cm[j] = nm;
+        rstep(in, x[j], c2[j], p2[j], cm[j], pm[j]);
     }
 }
 
@@ -349,14 +426,14 @@ __global__ __launch_bounds__(256) void k_entry(const double *__restrict__ seed2,
 }
 
 // Start of a slot j whose group enters later than the wave (its values are zero until then).
-template <typename T, int R>
+template <typename T, int R, int F>
 __device__ __forceinline__ void inject(int l, const int (&e)[R], const int (&pr)[R], const Ent64 *__restrict__ ent,
                                        const int *__restrict__ entk, int64_t row, int npairs, T (&c2)[R], T (&p2)[R],
                                        T (&cm)[R], T (&pm)[R], int (&k)[R])
 {
 #pragma unroll
     for (int j = 0; j < R; ++j)
-        if (e[j] == l && pr[j] < npairs) load_entry<T>(ent, entk, row + pr[j], c2[j], p2[j], cm[j], pm[j], k[j]);
+        if (e[j] == l && pr[j] < npairs) load_entry<T, F>(ent, entk, row + pr[j], c2[j], p2[j], cm[j], pm[j], k[j]);
 }
 
 template <int R> __device__ __forceinline__ bool pending(int l, int lmax, const int (&e)[R])
@@ -368,9 +445,9 @@ template <int R> __device__ __forceinline__ bool pending(int l, int lmax, const 
 }
 
 // Waves gbeg .. gend-1 (wave w holds the 64-pair groups w R .. w R + R - 1) of every m.
-template <typename T, int R, int V, typename IO = T>
-__global__ __launch_bounds__(256) void k_leg_synth(const SynRec<IO> *__restrict__ recs, int64_t rec_stride,
-                                                   const Coef64 *__restrict__ coef64, cplx<IO> *__restrict__ FG,
+template <typename T, int R, int V, int F>
+__global__ __launch_bounds__(256) void k_leg_synth(const SynRec<T> *__restrict__ recs, int64_t rec_stride,
+                                                   const Coef32D *__restrict__ coefd, cplx<T> *__restrict__ FG,
                                                    int64_t fg_stride, const Ent64 *__restrict__ ent,
                                                    const int *__restrict__ entk, const int *__restrict__ entl,
                                                    int ng64, const double *__restrict__ pair_z, int lmax, int npairs,
@@ -385,15 +462,15 @@ __global__ __launch_bounds__(256) void k_leg_synth(const SynRec<IO> *__restrict_
     if (m > lmax || grp >= gend) return;
     const int l0 = m > 2 ? m : 2;
     const int64_t base = (int64_t)m * (2 * lmax + 1 - m) / 2;
-    const SynRec<IO> *rec = recs + rhs * rec_stride + base;
-    const Coef64 *cf64 = coef64 + base;
-    const SynSrc<T, IO> src(rec, cf64);
-    auto rload = [&](int i) -> SynRec<T> {
-        if constexpr (std::is_same<T, IO>::value) return rec[i];
+    const SynRec<T> *rec = recs + rhs * rec_stride + base;
+    const Coef32D *cfd = coefd + base;
+    const SynSrc<T, F> src(rec, cfd);
+    auto rload = [&](int i) {
+        if constexpr (F == 0) return rec[i];
         else return src.at(i);
     };
 
-    typename XT<T>::type x[R];
+    typename PosT<T, F>::type x[R];
     T c2[R], p2[R], cm[R], pm[R];
     int k[R], pr[R], e[R];
     T acc0[8][R], acc1[8][R];
@@ -412,12 +489,12 @@ __global__ __launch_bounds__(256) void k_leg_synth(const SynRec<IO> *__restrict_
     for (int j = 0; j < R; ++j) {
         const int p = grp * 64 * R + j * 64 + lane;
         pr[j] = p;
-        setx(x[j], 0.0);
+        setpos(x[j], 0.0);
         c2[j] = p2[j] = cm[j] = pm[j] = (T)0;
         k[j] = 0;
         if (p < npairs) {
-            setx(x[j], pair_z[p]);
-            if (e[j] == ls && ls <= lmax) load_entry<T>(ent, entk, row + p, c2[j], p2[j], cm[j], pm[j], k[j]);
+            setpos(x[j], pair_z[p]);
+            if (e[j] == ls && ls <= lmax) load_entry<T, F>(ent, entk, row + p, c2[j], p2[j], cm[j], pm[j], k[j]);
         }
         neg |= (k[j] < 0);
 #pragma unroll
@@ -426,12 +503,12 @@ __global__ __launch_bounds__(256) void k_leg_synth(const SynRec<IO> *__restrict_
     bool pend = R > 1 && pending<R>(ls, lmax, e);
     bool ramp = wave_any(neg) || pend;
     int l = ls <= lmax ? ls : lmax + 1;
-    SynIn<T> i0;
+    decltype(rload(0)) i0;
     if constexpr (V == 0) {
         // plain: two steps per trip, loads issued inside the step
         while (ramp && l < lmax) {
             if (pend) {
-                inject<T, R>(l, e, pr, ent, entk, row, npairs, c2, p2, cm, pm, k);
+                inject<T, R, F>(l, e, pr, ent, entk, row, npairs, c2, p2, cm, pm, k);
                 pend = pending<R>(l, lmax, e);
             }
             syn_step<T, R, true>(rload(l), x, c2, p2, cm, pm, k, acc0);
@@ -440,7 +517,7 @@ __global__ __launch_bounds__(256) void k_leg_synth(const SynRec<IO> *__restrict_
             ramp = rescale<T, R>(c2, p2, cm, pm, k) || pend;
         }
         l = __builtin_amdgcn_readfirstlane(l);
-        SynSrc<T, IO> rp(rec + l, cf64 + l);  // keep the record address scalar
+        SynSrc<T, F> rp(rec + l, cfd + l);  // keep the record address scalar
         for (; l < lmax; l += 2, rp.adv(2)) {
             syn_step<T, R, false>(rp.at(0), x, c2, p2, cm, pm, k, acc0);
             syn_step<T, R, false>(rp.at(1), x, c2, p2, cm, pm, k, acc1);
@@ -451,7 +528,7 @@ __global__ __launch_bounds__(256) void k_leg_synth(const SynRec<IO> *__restrict_
         // registers (no copies of loaded registers)
         while (ramp && l < lmax) {
             if (pend) {
-                inject<T, R>(l, e, pr, ent, entk, row, npairs, c2, p2, cm, pm, k);
+                inject<T, R, F>(l, e, pr, ent, entk, row, npairs, c2, p2, cm, pm, k);
                 pend = pending<R>(l, lmax, e);
             }
             syn_step<T, R, true>(rload(l), x, c2, p2, cm, pm, k, acc0);
@@ -460,8 +537,8 @@ __global__ __launch_bounds__(256) void k_leg_synth(const SynRec<IO> *__restrict_
             ramp = rescale<T, R>(c2, p2, cm, pm, k) || pend;
         }
         l = __builtin_amdgcn_readfirstlane(l);
-        SynSrc<T, IO> rp(rec + l, cf64 + l);
-        SynRec<T> a0 = rp.at(0), a1 = rp.at(1), b0, b1;
+        SynSrc<T, F> rp(rec + l, cfd + l);
+        auto a0 = rp.at(0), a1 = rp.at(1), b0 = a0, b1 = a1;
         for (; l + 3 <= lmax; l += 4, rp.adv(4)) {
             b0 = rp.at(2);
             b1 = rp.at(3);
@@ -480,12 +557,12 @@ __global__ __launch_bounds__(256) void k_leg_synth(const SynRec<IO> *__restrict_
         i0 = rload(l);
     }
     if (l == lmax) {
-        if (pend) inject<T, R>(l, e, pr, ent, entk, row, npairs, c2, p2, cm, pm, k);
+        if (pend) inject<T, R, F>(l, e, pr, ent, entk, row, npairs, c2, p2, cm, pm, k);
         syn_step<T, R, true>(i0, x, c2, p2, cm, pm, k, acc0);
     }
 
     const bool odd0 = ((l0 + m) & 1) != 0;  // acc0 holds l + m odd terms when true
-    cplx<IO> *Fb = FG + rhs * fg_stride;
+    cplx<T> *Fb = FG + rhs * fg_stride;
 #pragma unroll
     for (int j = 0; j < R; ++j) {
         if (pr[j] >= npairs) continue;
@@ -503,9 +580,9 @@ __global__ __launch_bounds__(256) void k_leg_synth(const SynRec<IO> *__restrict_
                 S2[c] = E[c] + O[c];
                 Sm[c] = E[4 + c] + O[4 + c];
             }
-            cplx<IO> *f = Fb + ((int64_t)rn * (lmax + 1) + m) * 2;
-            f[0] = mk<IO>((IO)(-(S2[0] - S2[3])), (IO)(-(S2[1] + S2[2])));
-            f[1] = mk<IO>((IO)(-(Sm[0] + Sm[3])), (IO)(-(Sm[2] - Sm[1])));
+            cplx<T> *f = Fb + ((int64_t)rn * (lmax + 1) + m) * 2;
+            f[0] = mk<T>(-(S2[0] - S2[3]), -(S2[1] + S2[2]));
+            f[1] = mk<T>(-(Sm[0] + Sm[3]), -(Sm[2] - Sm[1]));
         }
         if (rs != rn) {
             T S2[4], Sm[4];
@@ -514,9 +591,9 @@ __global__ __launch_bounds__(256) void k_leg_synth(const SynRec<IO> *__restrict_
                 S2[c] = E[4 + c] - O[4 + c];
                 Sm[c] = E[c] - O[c];
             }
-            cplx<IO> *f = Fb + ((int64_t)rs * (lmax + 1) + m) * 2;
-            f[0] = mk<IO>((IO)(-(S2[0] - S2[3])), (IO)(-(S2[1] + S2[2])));
-            f[1] = mk<IO>((IO)(-(Sm[0] + Sm[3])), (IO)(-(Sm[2] - Sm[1])));
+            cplx<T> *f = Fb + ((int64_t)rs * (lmax + 1) + m) * 2;
+            f[0] = mk<T>(-(S2[0] - S2[3]), -(S2[1] + S2[2]));
+            f[1] = mk<T>(-(Sm[0] + Sm[3]), -(Sm[2] - Sm[1]));
         }
     }
 }
@@ -527,8 +604,8 @@ __global__ __launch_bounds__(256) void k_leg_synth(const SynRec<IO> *__restrict_
 // (south rings through the reflection symmetry).  Each lane sums its R ring pairs in registers;
 // every L steps of l the per-lane partials go through LDS and are reduced over the workgroup.
 // ================================================================================================
-template <typename T, int R, bool MASK, bool ODD, typename C>
-__device__ __forceinline__ void adj_step(const C &c, const typename XT<T>::type (&x)[R], T (&c2)[R],
+template <typename T, int R, bool MASK, bool ODD, typename C, typename X>
+__device__ __forceinline__ void adj_step(const C &c, const X (&x)[R], T (&c2)[R],
                                          T (&p2)[R], T (&cm)[R], T (&pm)[R], const int (&k)[R],
                                          const cplx<T> (&GN)[R], const cplx<T> (&GS)[R], const cplx<T> (&HN)[R],
                                          const cplx<T> (&HS)[R], T (&out)[4])
@@ -549,13 +626,7 @@ __device__ __forceinline__ void adj_step(const C &c, const typename XT<T>::type 
         a1 = fma(s * vm, GS[j].y, a1);
         a2 = fma(s * v2, HS[j].x, a2);
         a3 = fma(s * v2, HS[j].y, a3);
-        const T u = mulx(c.a, x[j]);
-        const T n2 = fma(u + c.b, c2[j], -(c.g * p2[j]));
-        const T nm = fma(u - c.b, cm[j], -(c.g * pm[j]));
-        p2[j] = c2[j];
-        c2[j] = n2;
-        pm[j] = cm[j];
-        cm[j] = nm;
+        rstep(c, x[j], c2[j], p2[j], cm[j], pm[j]);
     }
     out[0] = a0;
     out[1] = a1;
@@ -565,12 +636,12 @@ __device__ __forceinline__ void adj_step(const C &c, const typename XT<T>::type 
 
 // Workgroups rb0 .. rb0 + nrbl - 1 of the nrb ring blocks of every m; this launch's workgroup rbl
 // holds the 64-pair groups g0 + rbl W R .. g0 + (rbl + 1) W R - 1, bounded by gend.
-template <typename T, int R, int W, int L, typename IO = T>
-__global__ __launch_bounds__(64 * W) void k_leg_adj(const cplx<IO> *__restrict__ FG,
-                                                    const typename CoefT<T>::type *__restrict__ coef,
+template <typename T, int R, int W, int L, int F>
+__global__ __launch_bounds__(64 * W) void k_leg_adj(const cplx<T> *__restrict__ FG,
+                                                    const typename CoefT<T, F>::type *__restrict__ coef,
                                                     const Ent64 *__restrict__ ent, const int *__restrict__ entk,
                                                     const int *__restrict__ entl, int ng64,
-                                                    const double *__restrict__ pair_z, IO *__restrict__ part,
+                                                    const double *__restrict__ pair_z, T *__restrict__ part,
                                                     int *__restrict__ wgstart, int64_t nalm, int lmax, int npairs,
                                                     int nrings, int g0, int gend, int rb0, int nrbl, int nrb)
 {
@@ -604,7 +675,7 @@ __global__ __launch_bounds__(64 * W) void k_leg_adj(const cplx<IO> *__restrict__
     }
     const int64_t row = (int64_t)m * npairs;
 
-    typename XT<T>::type x[R];
+    typename PosT<T, F>::type x[R];
     T c2[R], p2[R], cm[R], pm[R];
     int k[R];
     cplx<T> GN[R], GS[R], HN[R], HS[R];
@@ -615,20 +686,20 @@ __global__ __launch_bounds__(64 * W) void k_leg_adj(const cplx<IO> *__restrict__
         pr[j] = p;
         const cplx<T> z = mk<T>(0, 0);
         GN[j] = GS[j] = HN[j] = HS[j] = z;
-        setx(x[j], 0.0);
+        setpos(x[j], 0.0);
         c2[j] = cm[j] = p2[j] = pm[j] = (T)0;
         k[j] = 0;
         if (p < pb) {
-            setx(x[j], pair_z[p]);
-            if (e[j] == ls) load_entry<T>(ent, entk, row + p, c2[j], p2[j], cm[j], pm[j], k[j]);
+            setpos(x[j], pair_z[p]);
+            if (e[j] == ls) load_entry<T, F>(ent, entk, row + p, c2[j], p2[j], cm[j], pm[j], k[j]);
             const int rn = p, rs = nrings - 1 - p;
-            const cplx<IO> *fn = FG + ((int64_t)rn * (lmax + 1) + m) * 2;
-            GN[j] = to_c<T, IO>(fn[0]);
-            HN[j] = cconj<T>(to_c<T, IO>(fn[1]));
+            const cplx<T> *fn = FG + ((int64_t)rn * (lmax + 1) + m) * 2;
+            GN[j] = fn[0];
+            HN[j] = cconj<T>(fn[1]);
             if (rs != rn) {
-                const cplx<IO> *fs = FG + ((int64_t)rs * (lmax + 1) + m) * 2;
-                GS[j] = cscale<T>(to_c<T, IO>(fs[0]), sgn0);
-                HS[j] = cscale<T>(cconj<T>(to_c<T, IO>(fs[1])), sgn0);
+                const cplx<T> *fs = FG + ((int64_t)rs * (lmax + 1) + m) * 2;
+                GS[j] = cscale<T>(fs[0], sgn0);
+                HS[j] = cscale<T>(cconj<T>(fs[1]), sgn0);
             }
         }
         neg |= (k[j] < 0);
@@ -639,16 +710,16 @@ __global__ __launch_bounds__(64 * W) void k_leg_adj(const cplx<IO> *__restrict__
     const int t = threadIdx.x, o = t / G, gi = t - o * G;
     const int oli = o >> 2, oc = o & 3;
 
-    using C = typename CoefT<T>::type;
+    using C = typename CoefT<T, F>::type;
     // coefficient records through an explicitly uniform pointer (scalar loads); the table is padded
     // past its last column, so the look-ahead loads stay in bounds
     const_as<C> *cp = uniform_ptr(cf + ls);
     C cc[L];
 #pragma unroll
-    for (int li = 0; li < L; ++li) cc[li] = ld_coef<C>(cp + li);
+    for (int li = 0; li < L; ++li) cc[li] = ld_coef(cp + li);
     for (int lc = ls; lc <= lmax; lc += L, cp += L) {
         if (pend) {
-            inject<T, R>(lc, e, pr, ent, entk, row, pb, c2, p2, cm, pm, k);
+            inject<T, R, F>(lc, e, pr, ent, entk, row, pb, c2, p2, cm, pm, k);
             bool ng = false;
 #pragma unroll
             for (int j = 0; j < R; ++j) ng |= (k[j] < 0);
@@ -686,7 +757,7 @@ __global__ __launch_bounds__(64 * W) void k_leg_adj(const cplx<IO> *__restrict__
         // the next chunk's coefficients load while the chunk is reduced
         C nc[L];
 #pragma unroll
-        for (int li = 0; li < L; ++li) nc[li] = ld_coef<C>(cp + L + li);
+        for (int li = 0; li < L; ++li) nc[li] = ld_coef(cp + L + li);
         __syncthreads();
         // column sums over the workgroup's lanes: four independent partial sums per thread, then
         // a butterfly over the G threads sharing the output
@@ -701,7 +772,7 @@ __global__ __launch_bounds__(64 * W) void k_leg_adj(const cplx<IO> *__restrict__
         for (; q < NT; q += G) s0 += red[(((q >> 6) * L + oli) * 4 + oc) * 64 + (q & 63)];
         T s = (s0 + s1) + (s2 + s3);
         for (int off = G >> 1; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-        if (gi == 0 && lc + oli <= lmax) part[((int64_t)rb * nalm + base + lc + oli) * 4 + oc] = (IO)s;
+        if (gi == 0 && lc + oli <= lmax) part[((int64_t)rb * nalm + base + lc + oli) * 4 + oc] = s;
 #pragma unroll
         for (int li = 0; li < L; ++li) cc[li] = nc[li];
         __syncthreads();
@@ -713,7 +784,7 @@ __global__ __launch_bounds__(64 * W) void k_leg_adj(const cplx<IO> *__restrict__
 // ================================================================================================
 template <typename T>
 __global__ void k_prologue(const double *__restrict__ xE, const double *__restrict__ xB, const double *__restrict__ kern,
-                           const int *__restrict__ lof, const typename CoefT<T>::type *__restrict__ coef, int lmax,
+                           const int *__restrict__ lof, const typename CoefT<T, 0>::type *__restrict__ coef, int lmax,
                            int64_t nalm, int64_t rec_stride, SynRec<T> *__restrict__ rec)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1139,7 +1210,7 @@ void launch_prologue(Plan &P, bool fp32, const double *xE, const double *xB, con
 }
 
 // synthesis waves over the 64-pair groups [g0, g1) (g0 a multiple of R)
-template <typename T, int R, int V, typename IO>
+template <typename T, int R, int V, int F>
 static void syn_launch(Plan &P, int nrhs, int64_t fg_stride, int g0, int g1)
 {
     const int gbeg = g0 / R, gend = (int)cdiv(g1, R);
@@ -1147,8 +1218,8 @@ static void syn_launch(Plan &P, int nrhs, int64_t fg_stride, int g0, int g1)
     const int nbm = (int)cdiv(gend - gbeg, 4);  // blocks of four waves per m
     const int64_t blocks = 8 * nbm * cdiv(P.lmax + 1, 8);
     dim3 g((unsigned)blocks, nrhs);
-    k_leg_synth<T, R, V, IO><<<g, 256, 0, P.stream>>>((const SynRec<IO> *)P.d_rec, P.rec_stride, P.d_coef64,
-                                                      (cplx<IO> *)P.d_FG, fg_stride, P.d_ent, P.d_entk, P.d_entl,
+    k_leg_synth<T, R, V, F><<<g, 256, 0, P.stream>>>((const SynRec<T> *)P.d_rec, P.rec_stride, P.d_coef32d,
+                                                     (cplx<T> *)P.d_FG, fg_stride, P.d_ent, P.d_entk, P.d_entl,
                                                       P.ng64, P.d_pair_z, P.lmax, P.npairs, P.nrings, gbeg, gend,
                                                       nbm);
 }
@@ -1156,9 +1227,9 @@ static void syn_launch(Plan &P, int nrhs, int64_t fg_stride, int g0, int g1)
 template <typename T, int V>
 static void syn_dispatch_r(Plan &P, int nrhs, int64_t fg_stride, int g0)
 {
-    if (P.syn_R == 1) syn_launch<T, 1, V, T>(P, nrhs, fg_stride, g0, P.ng64);
-    else if (P.syn_R == 2) syn_launch<T, 2, V, T>(P, nrhs, fg_stride, g0, P.ng64);
-    else syn_launch<T, 4, V, T>(P, nrhs, fg_stride, g0, P.ng64);
+    if (P.syn_R == 1) syn_launch<T, 1, V, 0>(P, nrhs, fg_stride, g0, P.ng64);
+    else if (P.syn_R == 2) syn_launch<T, 2, V, 0>(P, nrhs, fg_stride, g0, P.ng64);
+    else syn_launch<T, 4, V, 0>(P, nrhs, fg_stride, g0, P.ng64);
 }
 
 template <typename T>
@@ -1180,8 +1251,8 @@ void launch_leg_synth(Plan &P, bool fp32, int nrhs)
 {
     const int64_t fg_stride = (int64_t)P.nrings * (P.lmax + 1) * 2;
     if (fp32) {
-        // near-polar ring groups in FP64 arithmetic, the rest in FP32
-        if (P.polar_groups) syn_launch<double, 1, 1, float>(P, nrhs, fg_stride, 0, P.polar_groups);
+        // near-polar ring groups in the difference form, the rest in the plain form
+        if (P.polar_groups) syn_launch<float, 1, 1, 1>(P, nrhs, fg_stride, 0, P.polar_groups);
         syn_dispatch<float>(P, nrhs, fg_stride, P.polar_groups);
     } else {
         syn_dispatch<double>(P, nrhs, fg_stride, 0);
@@ -1189,17 +1260,19 @@ void launch_leg_synth(Plan &P, bool fp32, int nrhs)
 }
 
 // adjoint workgroups over the 64-pair groups [g0, g1), ring blocks rb0 .. of the plan's adj_nrb
-template <typename T, int R, int W, int L, typename IO>
+template <typename T, int R, int W, int L, int F>
 static void adj_launch(Plan &P, int rhs, int g0, int g1, int rb0)
 {
     const int nrbl = (int)cdiv(g1 - g0, W * R);
     if (nrbl <= 0) return;
     const int64_t fg_stride = (int64_t)P.nrings * (P.lmax + 1) * 2;
-    const void *coef = std::is_same<T, double>::value ? (const void *)P.d_coef64 : (const void *)P.d_coef32;
+    const void *coef = std::is_same<T, double>::value ? (const void *)P.d_coef64
+                       : F                              ? (const void *)P.d_coef32d
+                                                        : (const void *)P.d_coef32;
     dim3 g((unsigned)(8 * nrbl * cdiv(P.lmax + 1, 8)));
-    k_leg_adj<T, R, W, L, IO><<<g, 64 * W, 0, P.stream>>>(
-        (const cplx<IO> *)P.d_FG + rhs * fg_stride, (const typename CoefT<T>::type *)coef, P.d_ent, P.d_entk,
-        P.d_entl, P.ng64, P.d_pair_z, (IO *)P.d_part, P.d_wgstart, P.nalm, P.lmax, P.npairs, P.nrings, g0, g1, rb0,
+    k_leg_adj<T, R, W, L, F><<<g, 64 * W, 0, P.stream>>>(
+        (const cplx<T> *)P.d_FG + rhs * fg_stride, (const typename CoefT<T, F>::type *)coef, P.d_ent, P.d_entk,
+        P.d_entl, P.ng64, P.d_pair_z, (T *)P.d_part, P.d_wgstart, P.nalm, P.lmax, P.npairs, P.nrings, g0, g1, rb0,
         nrbl, P.adj_nrb);
 }
 
@@ -1213,10 +1286,10 @@ static void adj_dispatch(Plan &P, int rhs, int g0, int rb0)
 {
     const int R = P.adj_R, W = P.adj_W, L = P.adj_L;
 #define AKRA_ADJ_CASE(r, w, l) \
-    if (R == r && W == w && L == l) return adj_launch<T, r, w, l, T>(P, rhs, g0, P.ng64, rb0);
+    if (R == r && W == w && L == l) return adj_launch<T, r, w, l, 0>(P, rhs, g0, P.ng64, rb0);
     AKRA_ADJ_SHAPES(AKRA_ADJ_CASE)
 #undef AKRA_ADJ_CASE
-    adj_launch<T, 4, 4, 8, T>(P, rhs, g0, P.ng64, rb0);
+    adj_launch<T, 4, 4, 8, 0>(P, rhs, g0, P.ng64, rb0);
 }
 
 bool adj_shape_supported(int r, int w, int l)
@@ -1231,8 +1304,8 @@ bool adj_shape_supported(int r, int w, int l)
 void launch_leg_adj(Plan &P, bool fp32, int rhs)
 {
     if (fp32) {
-        // near-polar ring groups in FP64 arithmetic (four groups per workgroup), the rest in FP32
-        if (P.polar_groups) adj_launch<double, 4, 1, 4, float>(P, rhs, 0, P.polar_groups, 0);
+        // near-polar ring groups in the difference form (four groups per workgroup), the rest plain
+        if (P.polar_groups) adj_launch<float, 4, 1, 4, 1>(P, rhs, 0, P.polar_groups, 0);
         adj_dispatch<float>(P, rhs, P.polar_groups, P.adj_nrb_polar);
     } else {
         adj_dispatch<double>(P, rhs, 0, 0);

@@ -11,12 +11,13 @@
 
 #include "akra_internal.h"
 
-// FP32 plans evaluate the spin-weighted recurrences of rings within AKRA_POLAR_K sqrt(lmax) radians
-// of a pole in FP64.  Near the poles the per-step phase advance of the recurrence is of the order of
-// theta, so the FP32 rounding of each step moves the phase by ~eps/theta and the error of the
-// transform grows like sqrt(l) eps / theta; at theta above this bound it stays below 1e-5.
-#ifndef AKRA_POLAR_K
-#define AKRA_POLAR_K 0.01
+// FP32 plans run the spin-weighted recurrences of ring pairs within AKRA_DIFF_THETA radians of a pole
+// in the difference form.  Near a pole the per-step phase advance of the recurrence is of the order
+// of theta; in the plain form the FP32 rounding of each step moves the phase by ~eps/theta, an
+// error that grows like sqrt(l) eps/theta.  The difference form keeps it at ~sqrt(l) eps there but
+// rounds more at large theta; the two errors cross near 0.45 rad.
+#ifndef AKRA_DIFF_THETA
+#define AKRA_DIFF_THETA 0.45
 #endif
 
 namespace akra {
@@ -94,11 +95,12 @@ static void build_rings(Plan &P)
 //   g_l = (l+1) R_l sqrt((2l+3)/(2l-1)) / (l R_{l+1}),   R_l = sqrt((l^2 - m^2)(l^2 - 4)).
 // ---------------------------------------------------------------------------------------------
 // Entries past the last column (ALM_PAD) keep the kernels' look-ahead loads in bounds.
-static void build_coef(int lmax, std::vector<Coef64> &c64, std::vector<Coef32> &c32)
+static void build_coef(int lmax, std::vector<Coef64> &c64, std::vector<Coef32> &c32, std::vector<Coef32D> &c32d)
 {
     const int64_t nalm = (int64_t)(lmax + 1) * (lmax + 2) / 2;
     c64.assign(nalm + ALM_PAD, Coef64{0, 0, 0, 0});
     c32.assign(nalm + ALM_PAD, Coef32{0, 0, 0, 0});
+    c32d.assign(nalm + ALM_PAD, Coef32D{0, 0, 0, 0});
     parallel_for(lmax + 1, [&](int m) {
         const int64_t base = (int64_t)m * (2 * lmax + 1 - m) / 2;
         const int l0 = std::max(m, 2);
@@ -113,6 +115,7 @@ static void build_coef(int lmax, std::vector<Coef64> &c64, std::vector<Coef32> &
             const ld g = (L + 1) * r0 * sqrtl((2 * L + 3) / (2 * L - 1)) / (L * r1);
             c64[base + l] = Coef64{(double)a, (double)b, (double)g, 0.0};
             c32[base + l] = Coef32{(float)a, (float)b, (float)g, 0.0f};
+            c32d[base + l] = Coef32D{(float)a, (float)(a + b - g - 1), (float)(a - b - g - 1), (float)g};
         }
     });
 }
@@ -227,7 +230,7 @@ static void default_kernel(int lmax, std::vector<double> &k)
 static void free_plan(Plan *P)
 {
     void *ptrs[] = {P->d_rings, P->d_pair_z, P->d_coef64, P->d_coef32, P->d_seed2, P->d_seedm2, P->d_seedk,
-                    P->d_ent, P->d_entk, P->d_entl, P->d_wgstart,
+                    P->d_ent, P->d_entk, P->d_entl, P->d_wgstart, P->d_coef32d,
                     P->d_tw64, P->d_tw32, P->d_lof, P->d_order_p2, P->d_order_bl, P->d_FG, P->d_part, P->d_rec, P->d_W, P->d_kern, P->d_kuser, P->d_red, P->d_scal, P->d_flag, P->d_x, P->d_r,
                     P->d_p, P->d_w, P->d_b, P->d_xs};
     for (void *q : ptrs)
@@ -292,7 +295,7 @@ static akra_status create(int nside, int lmax, int nrhs, int prec, void *stream,
     // near-polar groups of FP32 plans: first pair of the group within theta_c of a pole
     P->ng64 = (P->npairs + 63) / 64;
     if (prec == AKRA_FP32) {
-        const double theta_c = AKRA_POLAR_K * std::sqrt((double)lmax);
+        const double theta_c = AKRA_DIFF_THETA;
         int g = 0;
         while (g < P->ng64 && std::acos(P->h_rings[64 * g].z) < theta_c) ++g;
         P->polar_groups = std::min(P->ng64, (g + 3) / 4 * 4);
@@ -327,9 +330,11 @@ static akra_status create(int nside, int lmax, int nrhs, int prec, void *stream,
     {
         std::vector<Coef64> c64;
         std::vector<Coef32> c32;
-        build_coef(lmax, c64, c32);
+        std::vector<Coef32D> c32d;
+        build_coef(lmax, c64, c32, c32d);
         AK_TRY(upload((void **)&P->d_coef64, c64.data(), c64.size() * sizeof(Coef64), *P));
         AK_TRY(upload((void **)&P->d_coef32, c32.data(), c32.size() * sizeof(Coef32), *P));
+        AK_TRY(upload((void **)&P->d_coef32d, c32d.data(), c32d.size() * sizeof(Coef32D), *P));
     }
     {
         std::vector<double> s2, sm;
