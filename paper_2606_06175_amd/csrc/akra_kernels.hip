@@ -341,6 +341,35 @@ __device__ __forceinline__ bool rescale(T (&c2)[R], T (&p2)[R], T (&cm)[R], T (&
     return wave_any(any_neg);
 }
 
+// Rescale check of the synthesis ramp: a lane whose exponent reaches zero restarts its sums (what it
+// accumulated while scaled is discarded).  Returns whether any lane of the wave is still scaled.
+template <typename T, int R>
+__device__ __forceinline__ bool rescale_restart(T (&c2)[R], T (&p2)[R], T (&cm)[R], T (&pm)[R], int (&k)[R],
+                                                T (&acc0)[8][R], T (&acc1)[8][R])
+{
+    bool any_neg = false;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        if (k[j] < 0) {
+            const T big = fmax(fabs(c2[j]), fabs(cm[j]));
+            if (big > scale_hi<T>()) {
+                const T d = scale_down<T>();
+                c2[j] *= d;
+                p2[j] *= d;
+                cm[j] *= d;
+                pm[j] *= d;
+                k[j] += 1;
+                if (k[j] == 0) {
+#pragma unroll
+                    for (int c = 0; c < 8; ++c) acc0[c][j] = acc1[c][j] = (T)0;
+                }
+            }
+            any_neg |= (k[j] < 0);
+        }
+    }
+    return wave_any(any_neg);
+}
+
 // ------------------------------------------------------------------------------------------------
 // Entry states (plan build).  One wave per (m, 64-pair group) runs the FP64 recurrence from the
 // seeds at l0 = max(m, 2) with the same steps and rescaling as the Legendre kernels' ramp (two
@@ -500,46 +529,27 @@ __global__ __launch_bounds__(256) void k_leg_synth(const SynRec<T> *__restrict__
 #pragma unroll
         for (int c = 0; c < 8; ++c) acc0[c][j] = acc1[c][j] = (T)0;
     }
+    // Lanes whose scale exponent is still negative ("ramp") run the same unmasked steps: their
+    // scaled values accumulate garbage that is discarded when the lane's exponent reaches zero (its
+    // sums restart there) or at the end; the check runs once per trip of S steps, which the growth
+    // of the recurrence over S steps keeps far from overflow.
     bool pend = R > 1 && pending<R>(ls, lmax, e);
-    bool ramp = wave_any(neg) || pend;
-    int l = ls <= lmax ? ls : lmax + 1;
-    decltype(rload(0)) i0;
-    if constexpr (V == 0) {
-        // plain: two steps per trip, loads issued inside the step
-        while (ramp && l < lmax) {
-            if (pend) {
-                inject<T, R, F>(l, e, pr, ent, entk, row, npairs, c2, p2, cm, pm, k);
-                pend = pending<R>(l, lmax, e);
-            }
-            syn_step<T, R, true>(rload(l), x, c2, p2, cm, pm, k, acc0);
-            syn_step<T, R, true>(rload(l + 1), x, c2, p2, cm, pm, k, acc1);
-            l += 2;
-            ramp = rescale<T, R>(c2, p2, cm, pm, k) || pend;
+    bool ramp = wave_any(neg);
+    constexpr int S = V == 0 ? 2 : 4;
+    int l = __builtin_amdgcn_readfirstlane(ls <= lmax ? ls : lmax + 1);
+    SynSrc<T, F> rp(rec + l, cfd + l);
+    auto a0 = rp.at(0), a1 = rp.at(1), b0 = a0, b1 = a1;
+    for (; l + S - 1 <= lmax; l += S, rp.adv(S)) {
+        if (pend) {
+            // a slot enters at its group's entry degree (entries are l0 + 8q, trips start at ls + S q)
+            inject<T, R, F>(l, e, pr, ent, entk, row, npairs, c2, p2, cm, pm, k);
+            pend = pending<R>(l, lmax, e);
+            bool ng = false;
+#pragma unroll
+            for (int j = 0; j < R; ++j) ng |= (k[j] < 0);
+            ramp = ramp || wave_any(ng);
         }
-        l = __builtin_amdgcn_readfirstlane(l);
-        SynSrc<T, F> rp(rec + l, cfd + l);  // keep the record address scalar
-        for (; l < lmax; l += 2, rp.adv(2)) {
-            syn_step<T, R, false>(rp.at(0), x, c2, p2, cm, pm, k, acc0);
-            syn_step<T, R, false>(rp.at(1), x, c2, p2, cm, pm, k, acc1);
-        }
-        i0 = rload(l);
-    } else {
-        // ramp loop, then four steps per trip whose loads are issued one pair ahead into ping-pong
-        // registers (no copies of loaded registers)
-        while (ramp && l < lmax) {
-            if (pend) {
-                inject<T, R, F>(l, e, pr, ent, entk, row, npairs, c2, p2, cm, pm, k);
-                pend = pending<R>(l, lmax, e);
-            }
-            syn_step<T, R, true>(rload(l), x, c2, p2, cm, pm, k, acc0);
-            syn_step<T, R, true>(rload(l + 1), x, c2, p2, cm, pm, k, acc1);
-            l += 2;
-            ramp = rescale<T, R>(c2, p2, cm, pm, k) || pend;
-        }
-        l = __builtin_amdgcn_readfirstlane(l);
-        SynSrc<T, F> rp(rec + l, cfd + l);
-        auto a0 = rp.at(0), a1 = rp.at(1), b0 = a0, b1 = a1;
-        for (; l + 3 <= lmax; l += 4, rp.adv(4)) {
+        if constexpr (S == 4) {
             b0 = rp.at(2);
             b1 = rp.at(3);
             syn_step<T, R, false>(a0, x, c2, p2, cm, pm, k, acc0);
@@ -548,18 +558,27 @@ __global__ __launch_bounds__(256) void k_leg_synth(const SynRec<T> *__restrict__
             a1 = rp.at(5);
             syn_step<T, R, false>(b0, x, c2, p2, cm, pm, k, acc0);
             syn_step<T, R, false>(b1, x, c2, p2, cm, pm, k, acc1);
-        }
-        if (l < lmax) {
+        } else {
             syn_step<T, R, false>(a0, x, c2, p2, cm, pm, k, acc0);
             syn_step<T, R, false>(a1, x, c2, p2, cm, pm, k, acc1);
-            l += 2;
+            a0 = rp.at(2);
+            a1 = rp.at(3);
         }
-        i0 = rload(l);
+        if (ramp) ramp = rescale_restart<T, R>(c2, p2, cm, pm, k, acc0, acc1);
     }
-    if (l == lmax) {
+    // tail (fewer than S steps)
+    for (int t = 0; l <= lmax; ++l, ++t) {
         if (pend) inject<T, R, F>(l, e, pr, ent, entk, row, npairs, c2, p2, cm, pm, k);
-        syn_step<T, R, true>(i0, x, c2, p2, cm, pm, k, acc0);
+        if (t & 1) syn_step<T, R, false>(rload(l), x, c2, p2, cm, pm, k, acc1);
+        else syn_step<T, R, false>(rload(l), x, c2, p2, cm, pm, k, acc0);
     }
+    // lanes that never left the scaled range contribute nothing
+#pragma unroll
+    for (int j = 0; j < R; ++j)
+        if (k[j] < 0) {
+#pragma unroll
+            for (int c = 0; c < 8; ++c) acc0[c][j] = acc1[c][j] = (T)0;
+        }
 
     const bool odd0 = ((l0 + m) & 1) != 0;  // acc0 holds l + m odd terms when true
     cplx<T> *Fb = FG + rhs * fg_stride;
@@ -692,23 +711,35 @@ __global__ __launch_bounds__(64 * W) void k_leg_adj(const cplx<T> *__restrict__ 
         if (p < pb) {
             setpos(x[j], pair_z[p]);
             if (e[j] == ls) load_entry<T, F>(ent, entk, row + p, c2[j], p2[j], cm[j], pm[j], k[j]);
-            const int rn = p, rs = nrings - 1 - p;
-            const cplx<T> *fn = FG + ((int64_t)rn * (lmax + 1) + m) * 2;
-            GN[j] = fn[0];
-            HN[j] = cconj<T>(fn[1]);
-            if (rs != rn) {
-                const cplx<T> *fs = FG + ((int64_t)rs * (lmax + 1) + m) * 2;
-                GS[j] = cscale<T>(fs[0], sgn0);
-                HS[j] = cscale<T>(cconj<T>(fs[1]), sgn0);
-            }
         }
         neg |= (k[j] < 0);
     }
+    // G of slot j's ring pair; lanes still in the scaled range (k < 0) hold G = 0, so the unmasked
+    // steps add nothing for them until their exponent reaches zero and G is loaded
+    auto load_g = [&](int j) {
+        const int p = pr[j];
+        if (p >= pb || k[j] < 0) return;
+        const int rn = p, rs = nrings - 1 - p;
+        const cplx<T> *fn = FG + ((int64_t)rn * (lmax + 1) + m) * 2;
+        GN[j] = fn[0];
+        HN[j] = cconj<T>(fn[1]);
+        if (rs != rn) {
+            const cplx<T> *fs = FG + ((int64_t)rs * (lmax + 1) + m) * 2;
+            GS[j] = cscale<T>(fs[0], sgn0);
+            HS[j] = cscale<T>(cconj<T>(fs[1]), sgn0);
+        }
+    };
+#pragma unroll
+    for (int j = 0; j < R; ++j)
+        if (e[j] == ls) load_g(j);
     bool ramp = wave_any(neg);
     bool pend = (R > 1 || W > 1) && pending<R>(ls, lmax, e);
-    const int NT = 64 * W, NO = 4 * L, G = NT / NO;
+    constexpr int NT = 64 * W, NO = 4 * L, G = NT / NO;
+    static_assert(G >= 1 && 64 % G == 0 && NT % (4 * G) == 0, "reduction layout");
     const int t = threadIdx.x, o = t / G, gi = t - o * G;
     const int oli = o >> 2, oc = o & 3;
+    const T *col = red + o * 64 + gi;                                   // column o, entry gi
+    T *pout = part + ((int64_t)rb * nalm + base + ls + oli) * 4 + oc;  // output of the first chunk
 
     using C = typename CoefT<T, F>::type;
     // coefficient records through an explicitly uniform pointer (scalar loads); the table is padded
@@ -722,59 +753,64 @@ __global__ __launch_bounds__(64 * W) void k_leg_adj(const cplx<T> *__restrict__ 
             inject<T, R, F>(lc, e, pr, ent, entk, row, pb, c2, p2, cm, pm, k);
             bool ng = false;
 #pragma unroll
-            for (int j = 0; j < R; ++j) ng |= (k[j] < 0);
+            for (int j = 0; j < R; ++j) {
+                if (e[j] == lc) load_g(j);
+                ng |= (k[j] < 0);
+            }
             ramp = ramp || wave_any(ng);
             pend = pending<R>(lc, lmax, e);
         }
-        if (ramp || lc + L - 1 > lmax) {
-            // ramp (masked contraction, rescaling) or the last, partial chunk
+        // all L steps unmasked: rows past lmax (last chunk) are reduced but not stored, and the
+        // coefficient table is padded past its last column
 #pragma unroll
-            for (int li = 0; li < L; li += 2) {
-                T out[4];
-                const int l = lc + li;
-                if (l <= lmax) adj_step<T, R, true, false>(cc[li], x, c2, p2, cm, pm, k, GN, GS, HN, HS, out);
-                else out[0] = out[1] = out[2] = out[3] = (T)0;
+        for (int li = 0; li < L; li += 2) {
+            T out[4];
+            adj_step<T, R, false, false>(cc[li], x, c2, p2, cm, pm, k, GN, GS, HN, HS, out);
 #pragma unroll
-                for (int c = 0; c < 4; ++c) red[((wave * L + li) * 4 + c) * 64 + lane] = out[c];
-                if (l + 1 <= lmax) adj_step<T, R, true, true>(cc[li + 1], x, c2, p2, cm, pm, k, GN, GS, HN, HS, out);
-                else out[0] = out[1] = out[2] = out[3] = (T)0;
+            for (int c = 0; c < 4; ++c) red[((wave * L + li) * 4 + c) * 64 + lane] = out[c];
+            adj_step<T, R, false, true>(cc[li + 1], x, c2, p2, cm, pm, k, GN, GS, HN, HS, out);
 #pragma unroll
-                for (int c = 0; c < 4; ++c) red[((wave * L + li + 1) * 4 + c) * 64 + lane] = out[c];
-                if (ramp) ramp = rescale<T, R>(c2, p2, cm, pm, k);
-            }
-        } else {
-#pragma unroll
-            for (int li = 0; li < L; li += 2) {
-                T out[4];
-                adj_step<T, R, false, false>(cc[li], x, c2, p2, cm, pm, k, GN, GS, HN, HS, out);
-#pragma unroll
-                for (int c = 0; c < 4; ++c) red[((wave * L + li) * 4 + c) * 64 + lane] = out[c];
-                adj_step<T, R, false, true>(cc[li + 1], x, c2, p2, cm, pm, k, GN, GS, HN, HS, out);
-#pragma unroll
-                for (int c = 0; c < 4; ++c) red[((wave * L + li + 1) * 4 + c) * 64 + lane] = out[c];
-            }
+            for (int c = 0; c < 4; ++c) red[((wave * L + li + 1) * 4 + c) * 64 + lane] = out[c];
         }
         // the next chunk's coefficients load while the chunk is reduced
         C nc[L];
 #pragma unroll
         for (int li = 0; li < L; ++li) nc[li] = ld_coef(cp + L + li);
         __syncthreads();
-        // column sums over the workgroup's lanes: four independent partial sums per thread, then
-        // a butterfly over the G threads sharing the output
-        T s0 = 0, s1 = 0, s2 = 0, s3 = 0;
-        int q = gi;
-        for (; q + 3 * G < NT; q += 4 * G) {
-            s0 += red[(((q >> 6) * L + oli) * 4 + oc) * 64 + (q & 63)];
-            s1 += red[((((q + G) >> 6) * L + oli) * 4 + oc) * 64 + ((q + G) & 63)];
-            s2 += red[((((q + 2 * G) >> 6) * L + oli) * 4 + oc) * 64 + ((q + 2 * G) & 63)];
-            s3 += red[((((q + 3 * G) >> 6) * L + oli) * 4 + oc) * 64 + ((q + 3 * G) & 63)];
-        }
-        for (; q < NT; q += G) s0 += red[(((q >> 6) * L + oli) * 4 + oc) * 64 + (q & 63)];
-        T s = (s0 + s1) + (s2 + s3);
+        // column sums over the workgroup's lanes: thread (o, gi) adds the entries q = gi + G t of
+        // column o (wave q / 64, lane q % 64) at compile-time offsets from its column base, in four
+        // independent partial sums, then a butterfly over the G threads sharing the output
+        T ps[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (int u = 0; u < NT / G; ++u) ps[u & 3] += col[(G * u / 64) * (L * 4 * 64) + (G * u) % 64];
+        T s = (ps[0] + ps[1]) + (ps[2] + ps[3]);
+#pragma unroll
         for (int off = G >> 1; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-        if (gi == 0 && lc + oli <= lmax) part[((int64_t)rb * nalm + base + lc + oli) * 4 + oc] = s;
+        if (gi == 0 && lc + oli <= lmax) pout[(int64_t)(lc - ls) * 4] = s;
 #pragma unroll
         for (int li = 0; li < L; ++li) cc[li] = nc[li];
+        if (ramp) {
+            // once per chunk (the growth over L steps stays far from overflow): rescale, and load
+            // G for lanes whose exponent reached zero
+            bool any_neg = false;
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                if (k[j] < 0) {
+                    const T big = fmax(fabs(c2[j]), fabs(cm[j]));
+                    if (big > scale_hi<T>()) {
+                        const T d = scale_down<T>();
+                        c2[j] *= d;
+                        p2[j] *= d;
+                        cm[j] *= d;
+                        pm[j] *= d;
+                        k[j] += 1;
+                        if (k[j] == 0) load_g(j);
+                    }
+                    any_neg |= (k[j] < 0);
+                }
+            }
+            ramp = wave_any(any_neg);
+        }
         __syncthreads();
     }
 }
