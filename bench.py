@@ -31,13 +31,17 @@ FLOP_PER_TRIPLE = 26     # per (l, m, ring pair) and direction: 2 recurrences (1
 # HBM bytes per launch of the dominant kernel from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE at this
 # workload, each scaled by the same counter's reading for a device copy of known size; valid only for
 # the kernel source they were taken from (its SHA-256 is checked at run time).
-TRAFFIC = {}
+TRAFFIC = {
+    # profiles/k_leg_adj_nside2048_lmax4096_fp64.md: FETCH 2.350e6 KiB x 1.9999 + WRITE 3.242e6 KiB x 1.0000
+    "leg_adj": {"bytes": 8.1334e9, "workload": (2048, 4096),
+                "kernels_sha256": "abe87c6da6d23eb6135fb81bca2492357454b563e45c10a0df799ab45cc96278"},
+}
 
 
-def traffic(stage):
+def traffic(stage, nside, lmax):
     import hashlib
     rec = TRAFFIC.get(stage)
-    if not rec:
+    if not rec or rec["workload"] != (nside, lmax):
         return None
     src = os.path.join(ROOT, "paper_2606_06175_amd", "csrc", "akra_kernels.hip")
     with open(src, "rb") as f:
@@ -210,7 +214,7 @@ def main():
     achieved = flops / (stages[dom]["ms_avg"] * 1e-3)
     roofline = {"bound": "alu", "kernel": "k_leg_adj" if dom == "leg_adj" else "k_leg_synth",
                 "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP64, "traffic": traffic(dom),
+                "frac": achieved / PEAK_FP64, "traffic": traffic(dom, nside, lmax),
                 "algorithmic": "26 flop x %d evaluated (l, m, ring-pair) triples = %.4g flop per launch "
                                "(all triples T = %d; below each ring group's entry degree the terms are zero "
                                "and are skipped)" % (evaluated[dom], flops, T)}
