@@ -136,7 +136,12 @@ akra_status akra_rhs(akra_plan plan, const double *g1, const double *g2, const d
  * Regularised ML estimate x = (H)^-1 b for the shear maps g1, g2 (eq. ML_estimator_reg) by PCG
  * (Sec. II.B inversion problem).  FP64 plans iterate in FP64; FP32 plans iterate with the FP32
  * operator and replace the residual by the FP64 true residual b - H x whenever it has dropped by
- * opts->reliable_delta (reliable updates), so the result meets tol in FP64.
+ * opts->reliable_delta (reliable updates), so the result meets tol in FP64.  Should the FP32 operator
+ * no longer resolve a search direction (p^T H p <= 0, which can happen for tolerances near its
+ * accuracy on ill-conditioned systems), the solve restarts from the true residual and finishes
+ * with the FP64 operator; info->fp64_applies counts those iterations too.  If that stalls as well
+ * (tol below the attainable accuracy of the system), the call returns AKRA_NOT_CONVERGED with the
+ * last iterate and its true residual in info.
  * Out: xE, xB (alm layout), info (HOST, may be NULL).  Returns AKRA_NOT_CONVERGED (x valid) at maxiter,
  * AKRA_ERR_NUMERIC on breakdown.  ||b|| = 0 gives x = 0 after 0 iterations.
  */
@@ -147,6 +152,22 @@ akra_status akra_cg_solve(akra_plan plan, const double *g1, const double *g2, co
  * differentiable form). */
 akra_status akra_cg_solve_b(akra_plan plan, const double *ninv, const uint8_t *mask, const double *bE,
                             const double *bB, const akra_cg_opts *opts, double *xE, double *xB, akra_cg_info *info);
+
+/*
+ * Gradient of the solve (the differentiable form): for x = (xE, xB) returned by akra_cg_solve with
+ * the same g1, g2, ninv, mask and opts, and the gradient vE, vB of a real loss L with respect to the
+ * stored (Re, Im) of x (the convention of torch autograd), writes dL/dg1, dL/dg2 and dL/dninv
+ * (maps, layout of g1 / ninv).  x enters H^-1 b through eq. normal_eq; the backward pass is one more
+ * CG solve with the same self-adjoint H,
+ *   u = H^-1 (v / w)   (w = 1 for m = 0, 2 for m > 0: the full-m harmonic product; Im(v_l0) ignored),
+ *   dL/dg = Omega W (Y K u),   dL/dninv = M [Omega (Y K u).(g - Y K x) - (lambda / sum M) <u, x>]
+ * where the last term follows lambda_eff = lambda <ninv>_M.  opts->use_x0 must be 0.  info reports
+ * the backward solve.  Returns AKRA_NOT_CONVERGED (outputs valid) when that solve hits maxiter.
+ */
+akra_status akra_cg_solve_vjp(akra_plan plan, const double *g1, const double *g2, const double *ninv,
+                              const uint8_t *mask, const akra_cg_opts *opts, const double *xE, const double *xB,
+                              const double *vE, const double *vB, double *dg1, double *dg2, double *dninv,
+                              akra_cg_info *info);
 
 /*
  * Step-wise PCG on the plan's device-resident solver state (first right-hand side of the plan):

@@ -73,10 +73,13 @@ def lib():
     L.akra_plan_set_tuning.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     L.akra_plan_get_tuning.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
     L.akra_plan_work.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
+    L.akra_cg_solve_vjp.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(CgOpts), vp, vp, vp, vp, vp, vp, vp,
+                                    ctypes.POINTER(CgInfo)]
     L.akra_plan_stage_times.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int)]
     for f in ("akra_plan_create", "akra_synth2", "akra_adjoint2", "akra_apply_H", "akra_rhs", "akra_cg_solve",
               "akra_cg_solve_b", "akra_cg_start", "akra_cg_step", "akra_cg_state", "akra_plan_set_timing",
-              "akra_plan_stage_times", "akra_plan_set_tuning", "akra_plan_get_tuning", "akra_plan_work"):
+              "akra_plan_stage_times", "akra_plan_set_tuning", "akra_plan_get_tuning", "akra_plan_work",
+              "akra_cg_solve_vjp"):
         getattr(L, f).restype = ctypes.c_int
     _lib = L
     return L
@@ -246,6 +249,26 @@ class Plan:
             _check(st)
         return xE, xB, self._info(inf, keep, hist_len)
 
+    def cg_solve_vjp(self, g1, g2, ninv, mask, xE, xB, vE, vB, tol=1e-3, maxiter=1000, lam=1e-3, kernel=None,
+                     reliable_delta=0.1, raise_not_converged=True):
+        """dL/dg1, dL/dg2, dL/dninv for x = cg_solve(g1, g2, ninv, mask, ...) and the upstream
+        gradient (vE, vB) on the stored (Re, Im) of x (one more CG solve, see akra_cg_solve_vjp)."""
+        g1, g2 = self._map(g1, "g1"), self._map(g2, "g2")
+        ninv = self._map(ninv, "ninv")
+        mask = self._map(mask, "mask", torch.uint8, per_rhs=False)
+        xE, xB = self._alm(xE, "xE"), self._alm(xB, "xB")
+        vE, vB = self._alm(vE, "vE"), self._alm(vB, "vB")
+        dg1, dg2, dn = self._map_out(), self._map_out(), self._map_out()
+        o, keep = self._opts(tol, maxiter, lam, None, kernel, reliable_delta, 0)
+        inf = CgInfo()
+        with torch.cuda.device(self.device):
+            st = lib().akra_cg_solve_vjp(self._h, g1.data_ptr(), g2.data_ptr(), ninv.data_ptr(), mask.data_ptr(),
+                                         ctypes.byref(o), xE.data_ptr(), xB.data_ptr(), vE.data_ptr(), vB.data_ptr(),
+                                         dg1.data_ptr(), dg2.data_ptr(), dn.data_ptr(), ctypes.byref(inf))
+        if st != AKRA_OK and (st != AKRA_NOT_CONVERGED or raise_not_converged):
+            _check(st)
+        return dg1, dg2, dn, self._info(inf, keep, 0)
+
     def cg_solve_b(self, bE, bB, ninv, mask, tol=1e-3, maxiter=1000, lam=1e-3, x0=None, kernel=None,
                    reliable_delta=0.1, hist_len=0, raise_not_converged=True):
         bE, bB = self._alm(bE, "bE"), self._alm(bB, "bB")
@@ -318,3 +341,32 @@ class Plan:
         v = (ctypes.c_int64 * 3)()
         _check(lib().akra_plan_work(self._h, v))
         return {"all": v[0], "synth": v[1], "adjoint": v[2]}
+
+
+class AkraSolve(torch.autograd.Function):
+    """Differentiable regularised solve x = H^-1 b(g1, g2, ninv) on a plan.
+
+        xE, xB = AkraSolve.apply(g1, g2, ninv, mask, plan, dict(tol=1e-8))
+
+    Gradients flow to g1, g2 and ninv (not to the mask).  The backward pass is one more CG solve
+    with the same operator, run by akra_cg_solve_vjp; solver options apply to both solves."""
+
+    @staticmethod
+    def forward(ctx, g1, g2, ninv, mask, plan, opts=None):
+        opts = dict(opts or {})
+        xE, xB, info = plan.cg_solve(g1, g2, ninv, mask, **opts)
+        ctx.plan, ctx.opts = plan, opts
+        ctx.save_for_backward(g1, g2, ninv, mask, xE, xB)
+        ctx.mark_non_differentiable(mask)
+        return xE, xB
+
+    @staticmethod
+    def backward(ctx, vE, vB):
+        g1, g2, ninv, mask, xE, xB = ctx.saved_tensors
+        if vE is None:
+            vE = torch.zeros_like(xE)
+        if vB is None:
+            vB = torch.zeros_like(xB)
+        opts = {k: v for k, v in ctx.opts.items() if k not in ("x0", "hist_len")}
+        dg1, dg2, dn, _ = ctx.plan.cg_solve_vjp(g1, g2, ninv, mask, xE, xB, vE.contiguous(), vB.contiguous(), **opts)
+        return dg1, dg2, dn, None, None, None

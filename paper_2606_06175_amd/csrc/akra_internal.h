@@ -149,6 +149,13 @@ void launch_ring(Plan &P, bool fp32, int mode, const double *g1, const double *g
                  const double *W, int nrhs);
 // Legendre adjoint of d_FG into the partial sums d_part
 void launch_leg_adj(Plan &P, bool fp32, int rhs);
+// gradient of the solve (ring MODE 3, FP64): F = Y K x in d_FG, q = Y K u in (q1, q2) on entry;
+// dninv = M (Omega q . (g - Y K x) - c), (q1, q2) <- Omega W q
+void launch_ring_grad(Plan &P, const double *g1, const double *g2, double *q1, double *q2, const double *W,
+                      double *dninv, const uint8_t *mask, const double *cdev);
+// b = upstream alm gradient / full-m weight (Im(a_l0) dropped), for the backward solve
+void launch_vjp_rhs(Plan &P, const double *vE, const double *vB, double *bE, double *bB);
+void launch_scale_scalar(Plan &P, double *out, const double *in, double f);
 // epilogue: sum partials, E/B combination, out = K_l * c + lam * x
 void launch_epilogue(Plan &P, bool fp32, const double *kern, double lam, const double *xE, const double *xB,
                      double *outE, double *outB);

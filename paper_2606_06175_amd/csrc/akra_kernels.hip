@@ -1063,12 +1063,17 @@ __device__ __forceinline__ void unfold_bin(cplx<T> *__restrict__ G, int bin, int
     }
 }
 
+// MODE 0: F -> maps (o1, o2).  MODE 1: maps (g1, g2) x W -> G.  MODE 2: F -> maps x W -> G in place.
+// MODE 3 (gradient of the solve): F = Y K x as maps px; with o1, o2 holding q = Y K u, per pixel
+//   o3 = M (omega q . (g - px) - c),   (o1, o2) = omega W q.
 template <typename T, int MODE>
 __global__ __launch_bounds__(RT) void k_ring(cplx<T> *__restrict__ FG, int64_t fg_stride, const double *__restrict__ g1,
                                              const double *__restrict__ g2, double *__restrict__ o1,
                                              double *__restrict__ o2, int64_t map_stride, const double *__restrict__ Wt,
                                              const RingInfo *__restrict__ rings, const int *__restrict__ order,
-                                             const cplx<T> *__restrict__ tw, int twn, int lmax, double omega)
+                                             const cplx<T> *__restrict__ tw, int twn, int lmax, double omega,
+                                             double *__restrict__ o3, const uint8_t *__restrict__ mask,
+                                             const double *__restrict__ cdev)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cplx<T> *buf = reinterpret_cast<cplx<T> *>(smem_raw);
@@ -1132,6 +1137,26 @@ __global__ __launch_bounds__(RT) void k_ring(cplx<T> *__restrict__ FG, int64_t f
             for (int j2 = 0; j2 < 4; ++j2) {
                 o1[pofs + j1 + L * j2] = (double)v[u][j2].x;
                 o2[pofs + j1 + L * j2] = (double)v[u][j2].y;
+            }
+        }
+        return;
+    }
+    if (MODE == 3) {
+        const double c = *cdev;
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            const int j1 = tid + RT * u;
+            if (j1 >= L) continue;
+#pragma unroll
+            for (int j2 = 0; j2 < 4; ++j2) {
+                const int64_t pix = pofs + j1 + L * j2;
+                const int64_t pm = ri.ofs + j1 + L * j2;  // the mask is shared by all right-hand sides
+                const double q1 = o1[pix], q2 = o2[pix];
+                const double r1 = g1[pix] - (double)v[u][j2].x, r2 = g2[pix] - (double)v[u][j2].y;
+                o3[pix] = mask[pm] ? omega * (q1 * r1 + q2 * r2) - c : 0.0;
+                const double w = omega * Wt[pix];
+                o1[pix] = w * q1;
+                o2[pix] = w * q2;
             }
         }
         return;
@@ -1344,7 +1369,10 @@ void launch_leg_adj(Plan &P, bool fp32, int rhs)
         if (P.polar_groups) adj_launch<float, 4, 1, 4, 1>(P, rhs, 0, P.polar_groups, 0);
         adj_dispatch<float>(P, rhs, P.polar_groups, P.adj_nrb_polar);
     } else {
-        adj_dispatch<double>(P, rhs, 0, 0);
+        // the same ring-block layout as the plan's FP32 applies (the epilogue sums adj_nrb slabs):
+        // in FP32 plans the near-polar groups form their own blocks here too
+        if (P.polar_groups) adj_launch<double, 4, 1, 4, 0>(P, rhs, 0, P.polar_groups, 0);
+        adj_dispatch<double>(P, rhs, P.polar_groups, P.adj_nrb_polar);
     }
 }
 
@@ -1362,6 +1390,7 @@ void launch_epilogue(Plan &P, bool fp32, const double *kern, double lam, const d
 
 template <typename T, int MODE>
 static void ring_launch_t(Plan &P, const double *g1, const double *g2, double *o1, double *o2, const double *W,
+                          double *o3, const uint8_t *mask, const double *cdev,
                           int nrhs)
 {
     const int64_t fg_stride = (int64_t)P.nrings * (P.lmax + 1) * 2;
@@ -1370,13 +1399,13 @@ static void ring_launch_t(Plan &P, const double *g1, const double *g2, double *o
         size_t sm = sizeof(cplx<T>) * (size_t)P.maxM_p2;
         k_ring<T, MODE><<<dim3(P.n_p2, nrhs), RT, sm, P.stream>>>((cplx<T> *)P.d_FG, fg_stride, g1, g2, o1, o2, P.npix,
                                                                   W, P.d_rings, P.d_order_p2, (const cplx<T> *)tw,
-                                                                  P.twn, P.lmax, P.omega);
+                                                                  P.twn, P.lmax, P.omega, o3, mask, cdev);
     }
     if (P.n_bl) {
         size_t sm = sizeof(cplx<T>) * (size_t)P.maxM_bl * 2;
         k_ring<T, MODE><<<dim3(P.n_bl, nrhs), RT, sm, P.stream>>>((cplx<T> *)P.d_FG, fg_stride, g1, g2, o1, o2, P.npix,
                                                                   W, P.d_rings, P.d_order_bl, (const cplx<T> *)tw,
-                                                                  P.twn, P.lmax, P.omega);
+                                                                  P.twn, P.lmax, P.omega, o3, mask, cdev);
     }
 }
 
@@ -1384,14 +1413,47 @@ void launch_ring(Plan &P, bool fp32, int mode, const double *g1, const double *g
                  const double *W, int nrhs)
 {
     if (fp32) {
-        if (mode == 0) ring_launch_t<float, 0>(P, g1, g2, o1, o2, W, nrhs);
-        else if (mode == 1) ring_launch_t<float, 1>(P, g1, g2, o1, o2, W, nrhs);
-        else ring_launch_t<float, 2>(P, g1, g2, o1, o2, W, nrhs);
+        if (mode == 0) ring_launch_t<float, 0>(P, g1, g2, o1, o2, W, nullptr, nullptr, nullptr, nrhs);
+        else if (mode == 1) ring_launch_t<float, 1>(P, g1, g2, o1, o2, W, nullptr, nullptr, nullptr, nrhs);
+        else ring_launch_t<float, 2>(P, g1, g2, o1, o2, W, nullptr, nullptr, nullptr, nrhs);
     } else {
-        if (mode == 0) ring_launch_t<double, 0>(P, g1, g2, o1, o2, W, nrhs);
-        else if (mode == 1) ring_launch_t<double, 1>(P, g1, g2, o1, o2, W, nrhs);
-        else ring_launch_t<double, 2>(P, g1, g2, o1, o2, W, nrhs);
+        if (mode == 0) ring_launch_t<double, 0>(P, g1, g2, o1, o2, W, nullptr, nullptr, nullptr, nrhs);
+        else if (mode == 1) ring_launch_t<double, 1>(P, g1, g2, o1, o2, W, nullptr, nullptr, nullptr, nrhs);
+        else ring_launch_t<double, 2>(P, g1, g2, o1, o2, W, nullptr, nullptr, nullptr, nrhs);
     }
+}
+
+void launch_ring_grad(Plan &P, const double *g1, const double *g2, double *q1, double *q2, const double *W,
+                      double *dninv, const uint8_t *mask, const double *cdev)
+{
+    ring_launch_t<double, 3>(P, g1, g2, q1, q2, W, dninv, mask, cdev, 1);
+}
+
+// right-hand side of the backward solve: the upstream gradient on the stored (Re, Im) of the alm,
+// divided by the full-m weight (1 for m = 0, 2 for m > 0), Im(a_l0) dropped
+__global__ void k_vjp_rhs(const double *__restrict__ vE, const double *__restrict__ vB, double *__restrict__ bE,
+                          double *__restrict__ bB, int64_t nalm, int lmax)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nalm) return;
+    const bool m0 = i <= lmax;
+    const double s = m0 ? 1.0 : 0.5;
+    bE[2 * i] = s * vE[2 * i];
+    bE[2 * i + 1] = m0 ? 0.0 : s * vE[2 * i + 1];
+    bB[2 * i] = s * vB[2 * i];
+    bB[2 * i + 1] = m0 ? 0.0 : s * vB[2 * i + 1];
+}
+
+void launch_vjp_rhs(Plan &P, const double *vE, const double *vB, double *bE, double *bB)
+{
+    k_vjp_rhs<<<(unsigned)cdiv(P.nalm, 256), 256, 0, P.stream>>>(vE, vB, bE, bB, P.nalm, P.lmax);
+}
+
+__global__ void k_scale_scalar(double *out, const double *in, double f) { *out = f * *in; }
+
+void launch_scale_scalar(Plan &P, double *out, const double *in, double f)
+{
+    k_scale_scalar<<<1, 1, 0, P.stream>>>(out, in, f);
 }
 
 void launch_weights(Plan &P, const double *ninv, const uint8_t *mask, int nrhs)

@@ -444,7 +444,7 @@ static akra_status check_launch(const char *what)
 
 // W from ninv/mask, validated; returns lambda_eff and P for every rhs (host)
 static akra_status setup_weights(Plan &P, const double *ninv, const uint8_t *mask, double lam, std::vector<double> &lam_eff,
-                                 std::vector<double> &pc)
+                                 std::vector<double> &pc, std::vector<double> *msum = nullptr)
 {
     if (!ninv || !mask) {
         set_error("ninv and mask must be device pointers");
@@ -458,6 +458,7 @@ static akra_status setup_weights(Plan &P, const double *ninv, const uint8_t *mas
     AK_HIP(hipStreamSynchronize(P.stream), "hipStreamSynchronize");
     lam_eff.resize(P.nrhs);
     pc.resize(P.nrhs);
+    if (msum) msum->resize(P.nrhs);
     for (int r = 0; r < P.nrhs; ++r) {
         const double sw = P.h_pin[4 * r], sm = P.h_pin[4 * r + 1], nonfin = P.h_pin[4 * r + 2], negs = P.h_pin[4 * r + 3];
         if (nonfin > 0) {
@@ -469,6 +470,7 @@ static akra_status setup_weights(Plan &P, const double *ninv, const uint8_t *mas
             return AKRA_ERR_ARG;
         }
         lam_eff[r] = (sm > 0) ? lam * sw / sm : 0.0;  // lambda <N^-1>_M
+        if (msum) (*msum)[r] = sm;
         pc[r] = 1.0 / (sw / (double)P.npix + lam_eff[r]);  // (<M^2 N^-1> + lambda_eff)^-1
     }
     return AKRA_OK;
@@ -646,11 +648,13 @@ static akra_status cg_poll(Plan &P, double *rr, int *flag)
 // Full solve on the state prepared by cg_begin.  FP32 plans iterate with the FP32 operator and
 // replace the recursive residual by the FP64 true residual whenever it has dropped by
 // reliable_delta since the last replacement (reliable updates); convergence is only accepted
-// on a true residual.  The search direction is kept across replacements.
+// on a true residual.  The search direction is kept across replacements.  If the FP32 operator
+// can no longer resolve a search direction (p^T H p <= 0 near the tolerance of an ill-conditioned
+// system) the solve restarts from the true residual and finishes with the FP64 operator.
 static akra_status cg_run(Plan &P, const akra_cg_opts &o, akra_cg_info *info)
 {
     const int64_t nc = 2 * P.nalm;
-    const bool fp32 = P.prec == AKRA_FP32;
+    bool fp32 = P.prec == AKRA_FP32;
     hipError_t he;
     info->lambda_eff = P.cg_lam;
     info->precond = P.cg_pc;
@@ -692,10 +696,29 @@ static akra_status cg_run(Plan &P, const akra_cg_opts &o, akra_cg_info *info)
         if (P.cg_iters >= o.maxiter) break;
         akra_status st = cg_iterate(P, fp32);
         if (st) return st;
+        if (!fp32 && P.prec == AKRA_FP32) P.cg_fp64_applies++;
         int flag = 0;
         st = cg_poll(P, &rr, &flag);
         if (st) return st;
         fresh = false;
+        if ((flag || !std::isfinite(rr)) && fp32) {
+            // x is the last iterate (alpha was set to 0): restart p = P r from the true residual
+            fp32 = false;
+            AK_HIP(hipMemsetAsync(P.d_flag, 0, sizeof(int), P.stream), "memset");
+            st = refresh();
+            if (st) return st;
+            k_set<<<1, 1, 0, P.stream>>>(P.d_scal + 4, 0.0);
+            launch_cg_p(P, P.d_p, P.d_r, P.d_scal + 4, P.cg_pc, nc);
+            k_cg_rz<<<1, 1, 0, P.stream>>>(P.d_scal, P.cg_pc);
+            continue;
+        }
+        if ((flag || !std::isfinite(rr)) && P.prec == AKRA_FP32) {
+            // the FP64 iterations of an FP32 plan stalled too: tol is below the attainable accuracy
+            // of the system; x is the last iterate
+            AK_HIP(hipMemsetAsync(P.d_flag, 0, sizeof(int), P.stream), "memset");
+            set_error("CG stalled below the attainable accuracy (p^T H p <= 0 after the FP64 restart)");
+            break;
+        }
         if (flag || !std::isfinite(rr)) {
             set_error("CG breakdown: p^T H p <= 0 or non-finite scalar");
             info->iters = P.cg_iters;
@@ -720,7 +743,7 @@ static akra_status cg_run(Plan &P, const akra_cg_opts &o, akra_cg_info *info)
         info->rel_resid_true = std::sqrt(tr) / bn;
     }
     info->fp64_applies = P.cg_fp64_applies;
-    if (result == AKRA_NOT_CONVERGED) set_error("maxiter reached");
+    if (result == AKRA_NOT_CONVERGED && P.cg_iters >= o.maxiter) set_error("maxiter reached");
     return result;
 }
 
@@ -970,6 +993,77 @@ akra_status akra_cg_solve_b(akra_plan plan, const double *ninv, const uint8_t *m
         return AKRA_ERR_ARG;
     }
     return solve_common(P, nullptr, nullptr, ninv, mask, bE, bB, opts, xE, xB, info);
+}
+
+__global__ void k_sum2_scaled(double *out, const double *a, const double *b, double f) { *out = f * (*a + *b); }
+
+// Gradient of L(x(g, ninv)) for x = H^-1 b(g, ninv) (differentiable form of the solve).  With the
+// upstream gradient v on the stored (Re, Im) of x and the full-m product <,>_w under which H is
+// self-adjoint:
+//   u = H^-1 (v / w)                                   (one more solve with the same operator)
+//   dL/dg     = Omega W (Y K u)
+//   dL/dninv  = M [Omega (Y K u) . (g - Y K x) - (lambda / sum M) <u, x>_w]
+// the last term from lambda_eff = lambda <ninv>_M.  Y K u and Y K x are formed in FP64.
+akra_status akra_cg_solve_vjp(akra_plan plan, const double *g1, const double *g2, const double *ninv,
+                              const uint8_t *mask, const akra_cg_opts *opts, const double *xE, const double *xB,
+                              const double *vE, const double *vB, double *dg1, double *dg2, double *dninv,
+                              akra_cg_info *info_out)
+{
+    AK_PLAN();
+    if (!g1 || !g2 || !xE || !xB || !vE || !vB || !dg1 || !dg2 || !dninv) {
+        set_error("null pointer argument");
+        return AKRA_ERR_ARG;
+    }
+    if (opts && opts->use_x0) {
+        set_error("use_x0 is not supported by the gradient solve");
+        return AKRA_ERR_ARG;
+    }
+    auto t0 = std::chrono::steady_clock::now();
+    akra_cg_opts o;
+    akra_status st = read_opts(opts, o);
+    if (st) return st;
+    akra_cg_info info{};
+    std::vector<double> le, pc, ms;
+    st = setup_weights(P, ninv, mask, o.lambda, le, pc, &ms);
+    if (st) return st;
+    const double *kd;
+    st = kernel_to_device(P, o.kernel_l, &kd);
+    if (st) return st;
+    akra_status worst = AKRA_OK;
+    const int64_t na = P.nalm;
+    for (int r = 0; r < P.nrhs; ++r) {
+        const int64_t off = (int64_t)r * 2 * na, mo = (int64_t)r * P.npix;
+        launch_vjp_rhs(P, vE + off, vB + off, P.d_b, P.d_b + 2 * na);
+        P.cg_kern = kd;
+        P.cg_lam = le[r];
+        P.cg_pc = pc[r];
+        P.cg_rhs = r;
+        st = cg_begin(P, false);
+        if (st) return st;
+        st = cg_run(P, o, &info);
+        if (st != AKRA_OK && st != AKRA_NOT_CONVERGED) return st;
+        if (st == AKRA_NOT_CONVERGED) worst = st;
+        // c = lambda / sum M * <u, x>_w, in scalar slots past the per-rhs weight sums
+        double *sc = P.d_scal + 8 + 4 * P.nrhs;
+        launch_dot(P, P.d_x, xE + off, sc, na);
+        launch_dot(P, P.d_x + 2 * na, xB + off, sc + 1, na);
+        k_sum2_scaled<<<1, 1, 0, P.stream>>>(sc + 2, sc, sc + 1, ms[r] > 0 ? o.lambda / ms[r] : 0.0);
+        // q = Y K u into the gradient maps
+        launch_prologue(P, false, P.d_x, P.d_x + 2 * na, kd, 1);
+        launch_leg_synth(P, false, 1);
+        launch_ring(P, false, 0, nullptr, nullptr, dg1 + mo, dg2 + mo, nullptr, 1);
+        // Y K x, consumed per pixel together with q, g, W and the mask
+        launch_prologue(P, false, xE + off, xB + off, kd, 1);
+        launch_leg_synth(P, false, 1);
+        launch_ring_grad(P, g1 + mo, g2 + mo, dg1 + mo, dg2 + mo, P.d_W + mo, dninv + mo, mask, sc + 2);
+        st = check_launch("solve_vjp");
+        if (st) return st;
+    }
+    AK_HIP(hipStreamSynchronize(P.stream), "sync");
+    info.status = worst;
+    info.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (info_out) *info_out = info;
+    return worst;
 }
 
 akra_status akra_cg_start(akra_plan plan, const double *g1, const double *g2, const double *ninv, const uint8_t *mask,

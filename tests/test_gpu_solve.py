@@ -156,3 +156,30 @@ def test_invalid_weights_are_reported(c1, bad, status):
     with pytest.raises(AkraError) as e:
         p.apply_H(ninv, t["mask"], z, z, 1.0)
     assert e.value.status == status
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 8), (2, 4, 4)])
+def test_mixed_solve_with_polar_blocks(shape):
+    # FP32 plan whose near-polar ring groups form their own adjoint blocks; the FP64 applies of the
+    # refinement must use the same block layout.  The true residual is the oracle's.
+    import torch
+    nside, lmax = 256, 512
+    dev = torch.device("cuda", 0)
+    mask = wl.cap_mask(nside, 0.9, 0.7, 0.15).astype(np.uint8)
+    ninv = np.random.default_rng(31).uniform(10.0, 60.0, 12 * nside * nside)
+    g1, g2 = [m * mask for m in wl.random_maps(12 * nside * nside, 32)]
+    p = _plan(nside, lmax, "fp32")
+    p.set_tuning(1, 1, *shape)
+    assert p.work()["adjoint"] > 0
+    t = [torch.from_numpy(a).to(dev) for a in (g1, g2, ninv, mask)]
+    xE, xB, info = p.cg_solve(*t, tol=1e-8, maxiter=3000)
+    o = Oracle(lmax, healpix_rings(nside))
+    W = o.weights(ninv, mask)
+    lam = o.lambda_eff(ninv, mask)
+    b = o.rhs(g1, g2, W)
+    x = np.stack([xE.cpu().numpy(), xB.cpu().numpy()])
+    r = b - o.apply_H(x, W, lam)
+    rt = float(np.sqrt(o.dot(r, r) / o.dot(b, b)))
+    print("shape", shape, "iters", info["iters"], "true residual", rt, info["rel_resid_true"], flush=True)
+    assert rt <= 1.05e-8
+    assert abs(rt - info["rel_resid_true"]) <= 1e-11
