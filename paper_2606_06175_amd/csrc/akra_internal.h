@@ -108,6 +108,7 @@ struct Plan {
     void *d_FG = nullptr;       // [nrhs][nrings][lmax+1][2] complex
     void *d_part = nullptr;     // [nrb][nalm][4] adjoint partial sums
     void *d_rec = nullptr;      // [nrhs][nalm + ALM_PAD] synthesis records (64 B in FP64)
+    float *d_brec = nullptr;    // FP32 plans with nrhs > 1: [nalm + ALM_PAD][8 rhs][4] batched records
     int64_t rec_stride = 0;     // records per right-hand side
     double *d_W = nullptr;      // [nrhs][npix] weights
     double *d_kern = nullptr;   // [lmax+1]
@@ -142,6 +143,9 @@ akra_status hip_fail(hipError_t e, const char *what);
 void launch_prologue(Plan &P, bool fp32, const double *xE, const double *xB, const double *kern, int nrhs);
 // entry states of the recurrence from the seeds (plan build)
 void launch_entry(Plan &P);
+// FP32 plans with nrhs > 1: kernel-scaled records and matrix-core synthesis of all right-hand sides
+// (alm of right-hand side r at xE/xB + 2 r rstride doubles)
+void launch_synth_batched(Plan &P, const double *xE, const double *xB, int64_t rstride, const double *kern);
 // Legendre synthesis of the prologue's records (d_rec) into d_FG
 void launch_leg_synth(Plan &P, bool fp32, int nrhs);
 // ring stage: mode 0 = F -> maps, 1 = maps -> G, 2 = F -> W -> G (in place)

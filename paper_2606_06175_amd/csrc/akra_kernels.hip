@@ -1257,6 +1257,149 @@ __global__ void k_scalar_div(double *out, const double *num, const double *den) 
 // ================================================================================================
 bool pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
 
+// ================================================================================================
+// Batched synthesis (FP32 plans with several right-hand sides): for one m, 32 ring pairs and a group
+// of NB = 8 right-hand sides, the sums over l of lambda(l, pair) a(l, rhs, c) are a matrix product
+// [pairs x l] x [l x (rhs, c)] with the lambda generated on the fly, accumulated on the matrix cores
+// (v_mfma_f32_32x32x2_f32: D[32 x 32] += A[32 x 2] B[2 x 32]).
+//   A[i][k]  lambda of pair i at degree l0 + 2k (even-offset product) or l0 + 1 + 2k (odd), held by
+//            lane i + 32k: both halves of the wave run the recurrence of pair i
+//   B[k][j]  record value j = 4 rhs + c (c = Re/Im of aE, Re/Im of aB) at the same degree
+//   D        four accumulators: spin +2 / -2 times even / odd offsets from the start degree
+// Lane l, register r of D holds pair i = 8 (r/4) + 4 (l/32) + r%4 and column j = l%32.
+// ================================================================================================
+typedef float v16f __attribute__((ext_vector_type(16)));
+constexpr int NBR = 8;  // right-hand sides per batched group
+
+// per (l, m): the NBR x 4 kernel-scaled alm values of one group (Im(a_l0) zeroed), zero past nrhs
+__global__ void k_prologue_b(const double *__restrict__ xE, const double *__restrict__ xB, int64_t rstride,
+                             const double *__restrict__ kern, const int *__restrict__ lof, int lmax, int64_t nalm,
+                             int nrhs, int q, float *__restrict__ brec)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // (alm, rhs-in-group)
+    if (t >= nalm * NBR) return;
+    const int64_t i = t / NBR;
+    const int rr = (int)(t - i * NBR), rhs = q * NBR + rr;
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (rhs < nrhs) {
+        const int64_t o = (int64_t)rhs * rstride + i;  // rstride: complex elements between right-hand sides
+        const double K = kern ? kern[lof[i]] : 1.0;
+        const bool m0 = i <= lmax;
+        v.x = (float)(K * xE[2 * o]);
+        v.y = m0 ? 0.f : (float)(K * xE[2 * o + 1]);
+        v.z = (float)(K * xB[2 * o]);
+        v.w = m0 ? 0.f : (float)(K * xB[2 * o + 1]);
+    }
+    reinterpret_cast<float4 *>(brec)[t] = v;
+}
+
+// quad sum over the four lanes 4 rhs + (0..3) that hold c = 0..3 of one right-hand side
+__device__ __forceinline__ float quad_sum(float v)
+{
+    v += __shfl_xor(v, 1, 64);
+    v += __shfl_xor(v, 2, 64);
+    return v;
+}
+
+template <int F>
+__global__ __launch_bounds__(256) void k_leg_synth_b(const float *__restrict__ brec,
+                                                     const typename CoefT<float, F>::type *__restrict__ coef,
+                                                     float2 *__restrict__ FG, int64_t fg_stride,
+                                                     const Ent64 *__restrict__ ent, const int *__restrict__ entk,
+                                                     const int *__restrict__ entl, int ng64,
+                                                     const double *__restrict__ pair_z, int lmax, int npairs,
+                                                     int nrings, int nrhs, int q, int wbeg, int wend, int nbm)
+{
+    const int lane = threadIdx.x & 63, h = lane >> 5, i = lane & 31;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    int m, blk;
+    xcd_map((int)blockIdx.x, nbm, m, blk);
+    const int w = wbeg + blk * 4 + wave;  // 32 ring pairs 32 w .. 32 w + 31
+    if (m > lmax || w >= wend) return;
+    const int l0 = m > 2 ? m : 2;
+    const int64_t base = (int64_t)m * (2 * lmax + 1 - m) / 2;
+    const int p = 32 * w + i;
+    const int ls = __builtin_amdgcn_readfirstlane(uniform_ptr(entl + (int64_t)m * ng64)[w >> 1]);
+
+    typename PosT<float, F>::type x;
+    float c2 = 0.f, p2 = 0.f, cm = 0.f, pm = 0.f;
+    int k = 0;
+    setpos(x, 0.0);
+    if (p < npairs && ls <= lmax) {
+        setpos(x, pair_z[p]);
+        load_entry<float, F>(ent, entk, (int64_t)m * npairs + p, c2, p2, cm, pm, k);
+    }
+    v16f D2e, D2o, Dme, Dmo;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) D2e[r] = D2o[r] = Dme[r] = Dmo[r] = 0.f;
+    bool ramp = wave_any(k < 0);
+    using C = typename CoefT<float, F>::type;
+    const_as<C> *cp = uniform_ptr(coef + base);
+    const float *bl = brec + base * (NBR * 4) + i;  // column i of the group's records
+    for (int l = ls; l <= lmax; l += 4) {
+        // B rows l + 2h (even offsets) and l + 1 + 2h (odd), zero past lmax
+        const int re = l + 2 * h, ro = re + 1;
+        const float be = re <= lmax ? bl[(int64_t)re * (NBR * 4)] : 0.f;
+        const float bo = ro <= lmax ? bl[(int64_t)ro * (NBR * 4)] : 0.f;
+        float v2[4], vm[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const bool live = k == 0;
+            v2[t] = live ? c2 : 0.f;
+            vm[t] = live ? cm : 0.f;
+            rstep(ld_coef(cp + l + t), x, c2, p2, cm, pm);
+        }
+        const float a2e = h ? v2[2] : v2[0], a2o = h ? v2[3] : v2[1];
+        const float ame = h ? vm[2] : vm[0], amo = h ? vm[3] : vm[1];
+        D2e = __builtin_amdgcn_mfma_f32_32x32x2f32(a2e, be, D2e, 0, 0, 0);
+        D2o = __builtin_amdgcn_mfma_f32_32x32x2f32(a2o, bo, D2o, 0, 0, 0);
+        Dme = __builtin_amdgcn_mfma_f32_32x32x2f32(ame, be, Dme, 0, 0, 0);
+        Dmo = __builtin_amdgcn_mfma_f32_32x32x2f32(amo, bo, Dmo, 0, 0, 0);
+        if (ramp) {
+            // once per four steps (the growth over four steps stays far from overflow)
+            if (k < 0 && fmaxf(fabsf(c2), fabsf(cm)) > scale_hi<float>()) {
+                const float d = scale_down<float>();
+                c2 *= d;
+                p2 *= d;
+                cm *= d;
+                pm *= d;
+                k += 1;
+            }
+            ramp = wave_any(k < 0);
+        }
+    }
+    // F of the north and south ring of every (pair, rhs): quad sums over c, written by lane c = 0
+    const bool odd0 = ((l0 + m) & 1) != 0;
+    const int c = i & 3, rl = i >> 2, rhs = q * NBR + rl;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int pi = 32 * w + 8 * (r >> 2) + 4 * h + (r & 3);
+        const float E2 = odd0 ? D2o[r] : D2e[r], O2 = odd0 ? D2e[r] : D2o[r];
+        const float Em = odd0 ? Dmo[r] : Dme[r], Om = odd0 ? Dme[r] : Dmo[r];
+        // north: S2 = E2 + O2, Sm = Em + Om;  south: S2 = Em - Om, Sm = E2 - O2
+        const float S2n = E2 + O2, Smn = Em + Om, S2s = Em - Om, Sms = E2 - O2;
+        // f0 = -(S2[0] - S2[3], S2[1] + S2[2]),  f1 = -(Sm[0] + Sm[3], Sm[2] - Sm[1])
+        const float s0r = c == 0 ? -1.f : (c == 3 ? 1.f : 0.f), s0i = (c == 1 || c == 2) ? -1.f : 0.f;
+        const float s1r = (c == 0 || c == 3) ? -1.f : 0.f, s1i = c == 2 ? -1.f : (c == 1 ? 1.f : 0.f);
+        const float fn0r = quad_sum(s0r * S2n), fn0i = quad_sum(s0i * S2n);
+        const float fn1r = quad_sum(s1r * Smn), fn1i = quad_sum(s1i * Smn);
+        const float fs0r = quad_sum(s0r * S2s), fs0i = quad_sum(s0i * S2s);
+        const float fs1r = quad_sum(s1r * Sms), fs1i = quad_sum(s1i * Sms);
+        if (c == 0 && rhs < nrhs && pi < npairs) {
+            float2 *Fb = FG + (int64_t)rhs * fg_stride;
+            const int rn = pi, rs = nrings - 1 - pi;
+            float2 *f = Fb + ((int64_t)rn * (lmax + 1) + m) * 2;
+            f[0] = make_float2(fn0r, fn0i);
+            f[1] = make_float2(fn1r, fn1i);
+            if (rs != rn) {
+                float2 *g = Fb + ((int64_t)rs * (lmax + 1) + m) * 2;
+                g[0] = make_float2(fs0r, fs0i);
+                g[1] = make_float2(fs1r, fs1i);
+            }
+        }
+    }
+}
+
 static int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 void launch_prologue(Plan &P, bool fp32, const double *xE, const double *xB, const double *kern, int nrhs)
@@ -1298,6 +1441,30 @@ static void syn_dispatch(Plan &P, int nrhs, int64_t fg_stride, int g0)
 {
     if (P.syn_V == 0) syn_dispatch_r<T, 0>(P, nrhs, fg_stride, g0);
     else syn_dispatch_r<T, 1>(P, nrhs, fg_stride, g0);
+}
+
+// batched synthesis of FP32 plans: records and matrix-core sums per group of NBR right-hand sides
+void launch_synth_batched(Plan &P, const double *xE, const double *xB, int64_t rstride, const double *kern)
+{
+    const int64_t fg_stride = (int64_t)P.nrings * (P.lmax + 1) * 2;
+    const int nw = (int)cdiv(P.npairs, 32), wpol = 2 * P.polar_groups < nw ? 2 * P.polar_groups : nw;
+    const int64_t lblocks = cdiv(P.lmax + 1, 8);
+    for (int q = 0; q * NBR < P.nrhs; ++q) {
+        k_prologue_b<<<(unsigned)cdiv(P.nalm * NBR, 256), 256, 0, P.stream>>>(xE, xB, rstride, kern, P.d_lof, P.lmax,
+                                                                             P.nalm, P.nrhs, q, P.d_brec);
+        if (wpol > 0) {
+            const int nbm = (int)cdiv(wpol, 4);
+            k_leg_synth_b<1><<<(unsigned)(8 * nbm * lblocks), 256, 0, P.stream>>>(
+                P.d_brec, P.d_coef32d, (float2 *)P.d_FG, fg_stride, P.d_ent, P.d_entk, P.d_entl, P.ng64, P.d_pair_z,
+                P.lmax, P.npairs, P.nrings, P.nrhs, q, 0, wpol, nbm);
+        }
+        if (nw > wpol) {
+            const int nbm = (int)cdiv(nw - wpol, 4);
+            k_leg_synth_b<0><<<(unsigned)(8 * nbm * lblocks), 256, 0, P.stream>>>(
+                P.d_brec, P.d_coef32, (float2 *)P.d_FG, fg_stride, P.d_ent, P.d_entk, P.d_entl, P.ng64, P.d_pair_z,
+                P.lmax, P.npairs, P.nrings, P.nrhs, q, wpol, nw, nbm);
+        }
+    }
 }
 
 void launch_entry(Plan &P)

@@ -230,7 +230,7 @@ static void default_kernel(int lmax, std::vector<double> &k)
 static void free_plan(Plan *P)
 {
     void *ptrs[] = {P->d_rings, P->d_pair_z, P->d_coef64, P->d_coef32, P->d_seed2, P->d_seedm2, P->d_seedk,
-                    P->d_ent, P->d_entk, P->d_entl, P->d_wgstart, P->d_coef32d,
+                    P->d_ent, P->d_entk, P->d_entl, P->d_wgstart, P->d_coef32d, P->d_brec,
                     P->d_tw64, P->d_tw32, P->d_lof, P->d_order_p2, P->d_order_bl, P->d_FG, P->d_part, P->d_rec, P->d_W, P->d_kern, P->d_kuser, P->d_red, P->d_scal, P->d_flag, P->d_x, P->d_r,
                     P->d_p, P->d_w, P->d_b, P->d_xs};
     for (void *q : ptrs)
@@ -403,6 +403,7 @@ static akra_status create(int nside, int lmax, int nrhs, int prec, void *stream,
     compute_work(*P);
     P->rec_stride = P->nalm + ALM_PAD;
     AK_TRY(alloc(&P->d_rec, (size_t)nrhs * P->rec_stride * 64, *P));
+    if (prec == AKRA_FP32 && nrhs > 1) AK_TRY(alloc((void **)&P->d_brec, (size_t)P->rec_stride * 8 * 4 * sizeof(float), *P));
     if (hipMemset(P->d_rec, 0, (size_t)nrhs * P->rec_stride * 64) != hipSuccess) {
         free_plan(P);
         set_error("hipMemset failed");
@@ -410,7 +411,7 @@ static akra_status create(int nside, int lmax, int nrhs, int prec, void *stream,
     }
     AK_TRY(alloc((void **)&P->d_W, (size_t)nrhs * P->npix * sizeof(double), *P));
     AK_TRY(alloc((void **)&P->d_red, (size_t)512 * 4 * nrhs * sizeof(double), *P));
-    AK_TRY(alloc((void **)&P->d_scal, (size_t)(64 + 4 * nrhs) * sizeof(double), *P));
+    AK_TRY(alloc((void **)&P->d_scal, (size_t)(64 + 16 * nrhs) * sizeof(double), *P));
     AK_TRY(alloc((void **)&P->d_flag, 64 * sizeof(int), *P));
     const size_t vb = (size_t)nrhs * 2 * P->nalm * sizeof(double2);
     AK_TRY(alloc((void **)&P->d_x, vb, *P));
@@ -563,6 +564,30 @@ static akra_status apply_H_timed(Plan &P, bool fp32, const double *kern_dev, dou
 }
 
 // r = b - H64 x (true residual) and rr = <r, r> on the device
+// H applied to all right-hand sides of an FP32 plan at once: batched matrix-core synthesis, ring
+// stage of every right-hand side with its own W, then the adjoint and epilogue of each.  lam_dev
+// (device, per rhs) overrides lam when given.
+static akra_status apply_H_batched(Plan &P, const double *kern_dev, const double *lam_host, double lam,
+                                   const double *xE, const double *xB, double *yE, double *yB, int64_t rstride)
+{
+    stage_mark(P, 1, true);
+    launch_synth_batched(P, xE, xB, rstride, kern_dev);
+    stage_mark(P, 1, false);
+    stage_mark(P, 2, true);
+    launch_ring(P, true, 2, nullptr, nullptr, nullptr, nullptr, P.d_W, P.nrhs);
+    stage_mark(P, 2, false);
+    for (int r = 0; r < P.nrhs; ++r) {
+        const int64_t o = (int64_t)r * 2 * rstride;
+        stage_mark(P, 3, true);
+        launch_leg_adj(P, true, r);
+        stage_mark(P, 3, false);
+        stage_mark(P, 4, true);
+        launch_epilogue(P, true, kern_dev, lam_host ? lam_host[r] : lam, xE + o, xB + o, yE + o, yB + o);
+        stage_mark(P, 4, false);
+    }
+    return check_launch("apply_H_batched");
+}
+
 static akra_status true_residual(Plan &P, double *rdst)
 {
     const int64_t nc = 2 * P.nalm;
@@ -819,8 +844,12 @@ akra_status akra_synth2(akra_plan plan, const double *almE, const double *almB, 
         return AKRA_ERR_ARG;
     }
     const bool fp32 = plan_fp32(P);
-    launch_prologue(P, fp32, almE, almB, nullptr, P.nrhs);
-    launch_leg_synth(P, fp32, P.nrhs);
+    if (fp32 && P.nrhs > 1) {
+        launch_synth_batched(P, almE, almB, P.nalm, nullptr);
+    } else {
+        launch_prologue(P, fp32, almE, almB, nullptr, P.nrhs);
+        launch_leg_synth(P, fp32, P.nrhs);
+    }
     launch_ring(P, fp32, 0, nullptr, nullptr, g1, g2, nullptr, P.nrhs);
     return check_launch("synth2");
 }
@@ -857,6 +886,7 @@ akra_status akra_apply_H(akra_plan plan, const double *ninv, const uint8_t *mask
     st = kernel_to_device(P, kernel_l, &kd);
     if (st) return st;
     const bool fp32 = plan_fp32(P);
+    if (fp32 && P.nrhs > 1) return apply_H_batched(P, kd, nullptr, lambda_eff, xE, xB, yE, yB, P.nalm);
     for (int r = 0; r < P.nrhs; ++r) {
         const int64_t o = (int64_t)r * 2 * P.nalm;
         st = apply_H_timed(P, fp32, kd, lambda_eff, xE + o, xB + o, yE + o, yB + o, r);
@@ -936,6 +966,205 @@ static akra_status read_opts(const akra_cg_opts *opts, akra_cg_opts &o)
     return AKRA_OK;
 }
 
+// Lockstep PCG of all right-hand sides of an FP32 plan with nrhs > 1: one batched operator apply per
+// iteration (matrix-core synthesis shared by all right-hand sides), per-right-hand-side scalars on
+// the device, reliable updates and convergence tests per right-hand side.  A right-hand side that
+// has converged keeps its iterate and takes no further updates.
+static akra_status solve_batched(Plan &P, const double *g1, const double *g2, const double *bE, const double *bB,
+                                 const akra_cg_opts &o, const double *kd, const std::vector<double> &le,
+                                 const std::vector<double> &pc, double *xE, double *xB, akra_cg_info &info)
+{
+    const int nr = P.nrhs;
+    const int64_t na = P.nalm, nc = 2 * na;
+    hipError_t he;
+    auto V = [&](double *base, int r) { return base + (int64_t)r * 2 * nc; };  // [rhs][E, B][nalm] complex
+    double *scb = P.d_scal + 16 + 4 * nr;
+    auto S = [&](int r) { return scb + 8 * r; };
+    // right-hand sides (FP64) and starting residuals
+    for (int r = 0; r < nr; ++r) {
+        const int64_t off = (int64_t)r * 2 * na;
+        if (g1) {
+            launch_ring(P, false, 1, g1 + r * P.npix, g2 + r * P.npix, nullptr, nullptr, P.d_W + r * P.npix, 1);
+            launch_leg_adj(P, false, 0);
+            launch_epilogue(P, false, kd, 0.0, nullptr, nullptr, V(P.d_b, r), V(P.d_b, r) + 2 * na);
+        } else {
+            AK_HIP(hipMemcpyAsync(V(P.d_b, r), bE + off, sizeof(double2) * na, hipMemcpyDeviceToDevice, P.stream), "copy");
+            AK_HIP(hipMemcpyAsync(V(P.d_b, r) + 2 * na, bB + off, sizeof(double2) * na, hipMemcpyDeviceToDevice,
+                                  P.stream),
+                   "copy");
+        }
+        if (o.use_x0) {
+            AK_HIP(hipMemcpyAsync(V(P.d_x, r), xE + off, sizeof(double2) * na, hipMemcpyDeviceToDevice, P.stream), "copy");
+            AK_HIP(hipMemcpyAsync(V(P.d_x, r) + 2 * na, xB + off, sizeof(double2) * na, hipMemcpyDeviceToDevice,
+                                  P.stream),
+                   "copy");
+        } else {
+            AK_HIP(hipMemsetAsync(V(P.d_x, r), 0, sizeof(double2) * nc, P.stream), "memset");
+        }
+    }
+    // true residual of right-hand side r (FP64 apply): r_r = b_r - H x_r
+    auto true_res = [&](int r, double *dst) -> akra_status {
+        akra_status s2 = apply_H_timed(P, false, kd, le[r], V(P.d_x, r), V(P.d_x, r) + 2 * na, V(P.d_w, r),
+                                       V(P.d_w, r) + 2 * na, r);
+        if (s2) return s2;
+        P.cg_fp64_applies++;
+        AK_HIP(hipMemcpyAsync(dst, V(P.d_b, r), sizeof(double2) * nc, hipMemcpyDeviceToDevice, P.stream), "copy");
+        launch_axpby(P, dst, -1.0, V(P.d_w, r), 1.0, nc);
+        return AKRA_OK;
+    };
+    std::vector<double> bn(nr), rel(nr), rmax(nr), rr(nr);
+    std::vector<char> active(nr, 1), fresh(nr, 1), restarted(nr, 0);
+    std::vector<int> status(nr, AKRA_NOT_CONVERGED);
+    P.cg_fp64_applies = 0;
+    AK_HIP(hipMemsetAsync(P.d_flag, 0, sizeof(int) * nr, P.stream), "memset");
+    for (int r = 0; r < nr; ++r) {
+        launch_dot(P, V(P.d_b, r), V(P.d_b, r), S(r) + 5, nc);
+        if (o.use_x0) {
+            akra_status st = true_res(r, V(P.d_r, r));
+            if (st) return st;
+        } else {
+            AK_HIP(hipMemcpyAsync(V(P.d_r, r), V(P.d_b, r), sizeof(double2) * nc, hipMemcpyDeviceToDevice, P.stream),
+                   "copy");
+        }
+        launch_dot(P, V(P.d_r, r), V(P.d_r, r), S(r) + 3, nc);
+        k_set<<<1, 1, 0, P.stream>>>(S(r) + 0, 0.0);
+        k_cg_beta<<<1, 1, 0, P.stream>>>(S(r), pc[r]);
+        k_set<<<1, 1, 0, P.stream>>>(S(r) + 4, 0.0);
+        AK_HIP(hipMemsetAsync(V(P.d_p, r), 0, sizeof(double2) * nc, P.stream), "memset");
+        launch_cg_p(P, V(P.d_p, r), V(P.d_r, r), S(r) + 4, pc[r], nc);
+    }
+    std::vector<double> hs(8 * nr);
+    std::vector<int> hf(nr);
+    auto pull = [&]() -> akra_status {
+        AK_HIP(hipMemcpyAsync(hs.data(), scb, sizeof(double) * 8 * nr, hipMemcpyDeviceToHost, P.stream), "copy");
+        AK_HIP(hipMemcpyAsync(hf.data(), P.d_flag, sizeof(int) * nr, hipMemcpyDeviceToHost, P.stream), "copy");
+        AK_HIP(hipStreamSynchronize(P.stream), "sync");
+        return AKRA_OK;
+    };
+    akra_status st = pull();
+    if (st) return st;
+    for (int r = 0; r < nr; ++r) {
+        if (!std::isfinite(hs[8 * r + 5])) {
+            set_error("right-hand side is not finite");
+            return AKRA_ERR_NUMERIC;
+        }
+        bn[r] = std::sqrt(hs[8 * r + 5]);
+        rr[r] = hs[8 * r + 3];
+        rel[r] = bn[r] > 0 ? std::sqrt(rr[r]) / bn[r] : 0.0;
+        rmax[r] = std::sqrt(rr[r]);
+        if (bn[r] == 0.0) {
+            active[r] = 0;
+            status[r] = AKRA_OK;
+        }
+    }
+    auto refresh = [&](int r) -> akra_status {
+        akra_status s2 = true_res(r, V(P.d_r, r));
+        if (s2) return s2;
+        launch_dot(P, V(P.d_r, r), V(P.d_r, r), S(r) + 3, nc);
+        rr[r] = read_scalar(P, S(r) + 3, &he);
+        if (he != hipSuccess) return hip_fail(he, "cg");
+        rel[r] = std::sqrt(rr[r]) / bn[r];
+        rmax[r] = std::sqrt(rr[r]);
+        fresh[r] = 1;
+        return AKRA_OK;
+    };
+    int iters = 0;
+    while (true) {
+        // convergence (accepted on a true residual)
+        for (int r = 0; r < nr; ++r) {
+            if (!active[r] || rel[r] >= o.tol) continue;
+            if (!fresh[r]) {
+                st = refresh(r);
+                if (st) return st;
+                if (rel[r] >= o.tol) {
+                    k_cg_rz<<<1, 1, 0, P.stream>>>(S(r), pc[r]);
+                    continue;
+                }
+            }
+            active[r] = 0;
+            status[r] = AKRA_OK;
+        }
+        bool any = false;
+        for (int r = 0; r < nr; ++r) any |= active[r] != 0;
+        if (!any || iters >= o.maxiter) break;
+        st = apply_H_batched(P, kd, le.data(), 0.0, P.d_p, P.d_p + 2 * na, P.d_w, P.d_w + 2 * na, 2 * na);
+        if (st) return st;
+        for (int r = 0; r < nr; ++r) {
+            if (!active[r]) continue;
+            stage_mark(P, 5, true);
+            launch_dot(P, V(P.d_p, r), V(P.d_w, r), S(r) + 1, nc);
+            k_cg_alpha<<<1, 1, 0, P.stream>>>(S(r), P.d_flag + r);
+            launch_cg_xr(P, V(P.d_x, r), V(P.d_r, r), V(P.d_p, r), V(P.d_w, r), S(r) + 2, nc);
+            launch_dot(P, V(P.d_r, r), V(P.d_r, r), S(r) + 3, nc);
+            k_cg_beta<<<1, 1, 0, P.stream>>>(S(r), pc[r]);
+            launch_cg_p(P, V(P.d_p, r), V(P.d_r, r), S(r) + 4, pc[r], nc);
+            stage_mark(P, 5, false);
+        }
+        ++iters;
+        st = check_launch("cg_batched");
+        if (st) return st;
+        st = pull();
+        if (st) return st;
+        for (int r = 0; r < nr; ++r) {
+            if (!active[r]) continue;
+            fresh[r] = 0;
+            rr[r] = hs[8 * r + 3];
+            if (hf[r] || !std::isfinite(rr[r])) {
+                // p^T H p <= 0 with the FP32 operator: restart once from the true residual,
+                // a second breakdown stops this right-hand side at its last iterate
+                AK_HIP(hipMemsetAsync(P.d_flag + r, 0, sizeof(int), P.stream), "memset");
+                if (restarted[r]) {
+                    active[r] = 0;
+                    continue;
+                }
+                restarted[r] = 1;
+                st = refresh(r);
+                if (st) return st;
+                k_set<<<1, 1, 0, P.stream>>>(S(r) + 4, 0.0);
+                launch_cg_p(P, V(P.d_p, r), V(P.d_r, r), S(r) + 4, pc[r], nc);
+                k_cg_rz<<<1, 1, 0, P.stream>>>(S(r), pc[r]);
+                continue;
+            }
+            rel[r] = std::sqrt(rr[r]) / bn[r];
+            if (std::sqrt(rr[r]) < o.reliable_delta * rmax[r] && rel[r] >= o.tol) {
+                st = refresh(r);
+                if (st) return st;
+                k_cg_rz<<<1, 1, 0, P.stream>>>(S(r), pc[r]);
+            }
+        }
+    }
+    // results and the true residual of every right-hand side
+    double worst_true = 0.0, worst_rel = 0.0;
+    int result = AKRA_OK;
+    for (int r = 0; r < nr; ++r) {
+        const int64_t off = (int64_t)r * 2 * na;
+        double tr = 0.0;
+        if (bn[r] > 0) {
+            st = true_res(r, P.d_xs);
+            if (st) return st;
+            launch_dot(P, P.d_xs, P.d_xs, S(r) + 6, nc);
+            tr = std::sqrt(read_scalar(P, S(r) + 6, &he)) / bn[r];
+            if (he != hipSuccess) return hip_fail(he, "cg");
+        }
+        worst_true = std::max(worst_true, tr);
+        worst_rel = std::max(worst_rel, bn[r] > 0 ? rel[r] : 0.0);
+        if (status[r] != AKRA_OK) result = AKRA_NOT_CONVERGED;
+        AK_HIP(hipMemcpyAsync(xE + off, V(P.d_x, r), sizeof(double2) * na, hipMemcpyDeviceToDevice, P.stream), "copy");
+        AK_HIP(hipMemcpyAsync(xB + off, V(P.d_x, r) + 2 * na, sizeof(double2) * na, hipMemcpyDeviceToDevice,
+                              P.stream),
+               "copy");
+    }
+    AK_HIP(hipStreamSynchronize(P.stream), "sync");
+    info.iters = iters;
+    info.fp64_applies = P.cg_fp64_applies;
+    info.rel_resid = worst_rel;
+    info.rel_resid_true = worst_true;
+    info.lambda_eff = le[0];
+    info.precond = pc[0];
+    if (result != AKRA_OK) set_error("maxiter reached or stalled for some right-hand side");
+    return (akra_status)result;
+}
+
 static akra_status solve_common(Plan &P, const double *g1, const double *g2, const double *ninv, const uint8_t *mask,
                                 const double *bE, const double *bB, const akra_cg_opts *opts, double *xE, double *xB,
                                 akra_cg_info *info_out)
@@ -952,6 +1181,14 @@ static akra_status solve_common(Plan &P, const double *g1, const double *g2, con
     st = kernel_to_device(P, o.kernel_l, &kd);
     if (st) return st;
     akra_status worst = AKRA_OK;
+    if (P.prec == AKRA_FP32 && P.nrhs > 1) {
+        worst = solve_batched(P, g1, g2, bE, bB, o, kd, le, pc, xE, xB, info);
+        if (worst != AKRA_OK && worst != AKRA_NOT_CONVERGED) return worst;
+        info.status = worst;
+        info.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        if (info_out) *info_out = info;
+        return worst;
+    }
     for (int r = 0; r < P.nrhs; ++r) {
         const int64_t off = (int64_t)r * 2 * P.nalm;
         st = cg_prepare(P, g1, g2, bE, bB, xE, xB, o, kd, le, pc, r);

@@ -183,3 +183,30 @@ def test_mixed_solve_with_polar_blocks(shape):
     print("shape", shape, "iters", info["iters"], "true residual", rt, info["rel_resid_true"], flush=True)
     assert rt <= 1.05e-8
     assert abs(rt - info["rel_resid_true"]) <= 1e-11
+
+
+@pytest.mark.parametrize("nr", [3, 10])
+def test_batched_fp32_solve(c1, nr):
+    # lockstep PCG of several right-hand sides (own weights each) on the matrix-core synthesis; every
+    # right-hand side meets the tolerance in the oracle's FP64 residual
+    torch, dev = c1["torch"], c1["dev"]
+    o = c1["o"]
+    mask = c1["cfg"]["mask"]
+    ninvs = np.stack([c1["cfg"]["ninv"][0] * (1.0 + 0.07 * k) for k in range(nr)])
+    g1s = np.stack([c1["g1"] * (1.0 + 0.1 * k) for k in range(nr)])
+    g2s = np.stack([c1["g2"] * (1.0 - 0.05 * k) for k in range(nr)])
+    p = _plan(c1["cfg"]["nside"], c1["cfg"]["lmax"], "fp32", nrhs=nr)
+    xE, xB, info = p.cg_solve(torch.from_numpy(g1s).to(dev), torch.from_numpy(g2s).to(dev),
+                              torch.from_numpy(ninvs).to(dev), c1["t"]["mask"], tol=1e-8, maxiter=3000)
+    assert info["status"] == 0
+    worst = 0.0
+    for k in range(nr):
+        W = o.weights(ninvs[k], mask)
+        lam = o.lambda_eff(ninvs[k], mask)
+        b = o.rhs(g1s[k], g2s[k], W)
+        x = np.stack([xE[k].cpu().numpy(), xB[k].cpu().numpy()])
+        r = b - o.apply_H(x, W, lam)
+        rt = float(np.sqrt(o.dot(r, r) / o.dot(b, b)))
+        worst = max(worst, rt)
+        assert rt <= 1.05e-8, (k, rt)
+    assert abs(worst - info["rel_resid_true"]) <= 1e-11
