@@ -122,6 +122,74 @@ def cpu_baseline(cfg, nside, lmax, nsample):
             "seconds_per_apply": full}
 
 
+def batched_leg(name, tol, maxiter):
+    """Batched form on the tomographic workload: all right-hand sides in one FP32 plan (matrix-core
+    synthesis, lockstep PCG with FP64 reliable updates) against the FP64 solve of one right-hand side."""
+    import numpy as np
+    import torch
+
+    import akra_workloads as wl
+    from paper_2606_06175_amd import Plan
+
+    dev = torch.device("cuda", 0)
+    t = time.time()
+    cfg = wl.make_config(name)
+    nside, lmax, nr = cfg["nside"], cfg["lmax"], cfg["nrhs"]
+    log("batched inputs %s (nside %d lmax %d, %d rhs) generated in %.1f s" % (name, nside, lmax, nr, time.time() - t))
+    K = np.zeros(lmax + 1)
+    ll = np.arange(2, lmax + 1, dtype=np.float64)
+    K[2:] = np.sqrt((ll - 1) * (ll + 2) / (ll * (ll + 1)))
+    kap = torch.from_numpy(cfg["kappa"] * K[l_of(lmax)][None, :]).to(dev)
+    mask = torch.from_numpy(cfg["mask"]).to(dev)
+    m = mask.to(torch.float64)
+    p = Plan(nside, lmax, precision="fp64", device=dev)
+    g1 = torch.empty((nr, 12 * nside * nside), dtype=torch.float64, device=dev)
+    g2 = torch.empty_like(g1)
+    for k in range(nr):
+        a, b = p.synth2(kap[k].contiguous(), torch.zeros_like(kap[k]))
+        g1[k] = m * (a + torch.from_numpy(cfg["eps1"][k]).to(dev))
+        g2[k] = m * (b + torch.from_numpy(cfg["eps2"][k]).to(dev))
+    ninv = torch.from_numpy(cfg["ninv"][cfg["bin"]]).to(dev)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    xE, xB, info64 = p.cg_solve(g1[0].contiguous(), g2[0].contiguous(), ninv[0].contiguous(), mask, tol=tol,
+                                maxiter=maxiter, raise_not_converged=False)
+    torch.cuda.synchronize()
+    t64 = time.perf_counter() - t
+    p.close()
+    pb = Plan(nside, lmax, nrhs=nr, precision="fp32", device=dev)
+    # one batched operator apply (all right-hand sides), timed with HIP events on the plan stream
+    pb.set_timing(True)
+    pb.stage_times()
+    xs = [torch.from_numpy(np.stack([wl.random_alm(lmax, 70 + k) for k in range(nr)])).to(dev) for _ in (0, 1)]
+    pb.apply_H(ninv, mask, xs[0], xs[1], 1e-3)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    pb.apply_H(ninv, mask, xs[0], xs[1], 1e-3)
+    torch.cuda.synchronize()
+    t_apply = time.perf_counter() - t
+    st = pb.stage_times()
+    pb.set_timing(False)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    yE, yB, infob = pb.cg_solve(g1, g2, ninv, mask, tol=tol, maxiter=maxiter, raise_not_converged=False)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t
+    err = full_norm(yE[0] - xE, yB[0] - xB, lmax) / full_norm(xE, xB, lmax)
+    pb.close()
+    out = {"workload": "%s: HEALPix Nside %d, lmax %d, %d right-hand sides (4 bins, own N^-1 each)" % (name, nside, lmax, nr),
+           "fp64_single_rhs": {"seconds": t64, "iters": info64["iters"], "rel_resid_true": info64["rel_resid_true"]},
+           "batched_fp32": {"seconds": tb, "iters": infob["iters"], "fp64_applies": infob["fp64_applies"],
+                            "worst_rel_resid_true": infob["rel_resid_true"], "status": infob["status"],
+                            "rel_err_rhs0_vs_fp64": err},
+           "seconds_per_rhs_fp64": t64, "seconds_per_rhs_batched": tb / nr,
+           "speedup_per_rhs_vs_fp64": t64 / (tb / nr),
+           "batched_apply_ms": t_apply * 1e3, "rhs_applies_per_s": nr / t_apply,
+           "batched_apply_stages_ms": {k: round(v[0], 3) for k, v in st.items() if v[1]}}
+    log("batched: %s" % out)
+    return out
+
+
 def full_norm(a, b, lmax):
     """Full-m norm of stacked (E, B) complex alm on the device."""
     import torch
@@ -140,6 +208,8 @@ def main():
     ap.add_argument("--lmax", type=int, default=None)
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-workload", default="C4")
     ap.add_argument("--cpu-sample-rings", type=int, default=192)
     ap.add_argument("--solve-tol", type=float, default=1e-8)
     ap.add_argument("--maxiter", type=int, default=3000)
@@ -264,6 +334,9 @@ def main():
         out["mixed_speedup_vs_fp64"] = solves["fp64"]["seconds"] / solves["mixed_fp32_fp64"]["seconds"]
     else:
         plan.close()
+
+    if not args.no_solve and not args.no_batched:
+        out["batched"] = batched_leg(args.batched_workload, args.solve_tol, args.maxiter)
 
     if not args.no_cpu_baseline:
         t = time.time()
