@@ -664,7 +664,11 @@ __global__ __launch_bounds__(64 * W) void k_leg_adj(const cplx<T> *__restrict__ 
                                                     int *__restrict__ wgstart, int64_t nalm, int lmax, int npairs,
                                                     int nrings, int g0, int gend, int rb0, int nrbl, int nrb)
 {
-    __shared__ T red[W * L * 4 * 64];
+    // LDS columns (wave, l, c) of 64 lanes, padded to CS entries: the G threads that sum one column
+    // read entries gi + G t of it, and with CS = 64 + G (mod 32 double-banks) the 64 threads of a
+    // wave spread over the banks twice each, as do the lane-contiguous writes
+    constexpr int GR = 16 * W / L, CS = 64 + GR;
+    __shared__ T red[W * L * 4 * CS];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     int m, rbl;
@@ -735,10 +739,10 @@ __global__ __launch_bounds__(64 * W) void k_leg_adj(const cplx<T> *__restrict__ 
     bool ramp = wave_any(neg);
     bool pend = (R > 1 || W > 1) && pending<R>(ls, lmax, e);
     constexpr int NT = 64 * W, NO = 4 * L, G = NT / NO;
-    static_assert(G >= 1 && 64 % G == 0 && NT % (4 * G) == 0, "reduction layout");
+    static_assert(G == GR && G >= 1 && 64 % G == 0 && NT % (4 * G) == 0, "reduction layout");
     const int t = threadIdx.x, o = t / G, gi = t - o * G;
     const int oli = o >> 2, oc = o & 3;
-    const T *col = red + o * 64 + gi;                                   // column o, entry gi
+    const T *col = red + o * CS + gi;                                   // column o, entry gi
     T *pout = part + ((int64_t)rb * nalm + base + ls + oli) * 4 + oc;  // output of the first chunk
 
     using C = typename CoefT<T, F>::type;
@@ -767,10 +771,10 @@ __global__ __launch_bounds__(64 * W) void k_leg_adj(const cplx<T> *__restrict__ 
             T out[4];
             adj_step<T, R, false, false>(cc[li], x, c2, p2, cm, pm, k, GN, GS, HN, HS, out);
 #pragma unroll
-            for (int c = 0; c < 4; ++c) red[((wave * L + li) * 4 + c) * 64 + lane] = out[c];
+            for (int c = 0; c < 4; ++c) red[((wave * L + li) * 4 + c) * CS + lane] = out[c];
             adj_step<T, R, false, true>(cc[li + 1], x, c2, p2, cm, pm, k, GN, GS, HN, HS, out);
 #pragma unroll
-            for (int c = 0; c < 4; ++c) red[((wave * L + li + 1) * 4 + c) * 64 + lane] = out[c];
+            for (int c = 0; c < 4; ++c) red[((wave * L + li + 1) * 4 + c) * CS + lane] = out[c];
         }
         // the next chunk's coefficients load while the chunk is reduced
         C nc[L];
@@ -782,7 +786,7 @@ __global__ __launch_bounds__(64 * W) void k_leg_adj(const cplx<T> *__restrict__ 
         // independent partial sums, then a butterfly over the G threads sharing the output
         T ps[4] = {0, 0, 0, 0};
 #pragma unroll
-        for (int u = 0; u < NT / G; ++u) ps[u & 3] += col[(G * u / 64) * (L * 4 * 64) + (G * u) % 64];
+        for (int u = 0; u < NT / G; ++u) ps[u & 3] += col[(G * u / 64) * (L * 4 * CS) + (G * u) % 64];
         T s = (ps[0] + ps[1]) + (ps[2] + ps[3]);
 #pragma unroll
         for (int off = G >> 1; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
