@@ -64,6 +64,7 @@ struct RingInfo {
     int sub;       // N / 4: length of the four interleaved sub-transforms
     int shift;     // phi0 = pi * shift / N
     int M;         // Bluestein FFT length for the sub-transform (0: sub is a power of two)
+    int64_t bofs;  // Bluestein rings: offset of the chirp spectrum of this sub length
 };
 
 struct Plan {
@@ -90,6 +91,7 @@ struct Plan {
     int *d_wgstart = nullptr;   // [m][adjoint ring block] first degree the block wrote
     int64_t work[3] = {0, 0, 0};  // (l, m, pair) triples: all, evaluated by synthesis, by adjoint
     void *d_tw64 = nullptr, *d_tw32 = nullptr;  // e^{-2 pi i k / twn}, k < twn/2
+    void *d_bhat64 = nullptr, *d_bhat32 = nullptr;  // Bluestein chirp spectra per distinct sub length
     int twn = 1;
     int *d_lof = nullptr;  // l of every alm index
     int *d_order_p2 = nullptr, *d_order_bl = nullptr;
@@ -163,6 +165,8 @@ void launch_scale_scalar(Plan &P, double *out, const double *in, double f);
 // epilogue: sum partials, E/B combination, out = K_l * c + lam * x
 void launch_epilogue(Plan &P, bool fp32, const double *kern, double lam, const double *xE, const double *xB,
                      double *outE, double *outB);
+// chirp spectra of the Bluestein sub lengths Ls (FFT lengths Ms, table offsets ofs; device arrays)
+void launch_bhat(Plan &P, const int *Ls, const int *Ms, const int64_t *ofs, int n, int maxM);
 // weights W = mask * ninv, plus the sums needed for lambda_eff / P and input validation
 void launch_weights(Plan &P, const double *ninv, const uint8_t *mask, int nrhs);
 

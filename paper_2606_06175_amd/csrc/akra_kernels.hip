@@ -946,6 +946,10 @@ constexpr int RU = 8;    // sub-transform elements per thread: L <= RT * RU
 
 __device__ __forceinline__ unsigned brev(unsigned n, int logM) { return logM ? (__builtin_bitreverse32(n) >> (32 - logM)) : 0u; }
 
+// LDS slot of FFT element i: one pad slot per 32 elements, so that the bit-reversed and strided
+// accesses of the radix-2 passes do not all fall into one bank
+__device__ __forceinline__ int pd(int i) { return i + (i >> 5); }
+
 // e^{-i pi n^2 / L}
 template <typename T> __device__ __forceinline__ cplx<T> chirp(int n, int L)
 {
@@ -960,7 +964,7 @@ __device__ void fft_dit(cplx<T> *buf, int M, const cplx<T> *__restrict__ tw, int
         const int stride = twn / (2 * h);
         for (int bI = threadIdx.x; bI < M / 2; bI += RT) {
             const int pos = bI & (h - 1);
-            const int i0 = ((bI - pos) << 1) + pos, i1 = i0 + h;
+            const int i0 = pd(((bI - pos) << 1) + pos), i1 = pd(((bI - pos) << 1) + pos + h);
             cplx<T> w = tw[pos * stride];
             if (sign > 0) w.y = -w.y;
             const cplx<T> t = cmul<T>(w, buf[i1]);
@@ -980,7 +984,7 @@ __device__ void fft_dif(cplx<T> *buf, int M, const cplx<T> *__restrict__ tw, int
         const int stride = twn / (2 * h);
         for (int bI = threadIdx.x; bI < M / 2; bI += RT) {
             const int pos = bI & (h - 1);
-            const int i0 = ((bI - pos) << 1) + pos, i1 = i0 + h;
+            const int i0 = pd(((bI - pos) << 1) + pos), i1 = pd(((bI - pos) << 1) + pos + h);
             cplx<T> w = tw[pos * stride];
             if (sign > 0) w.y = -w.y;
             const cplx<T> a = buf[i0], c = buf[i1];
@@ -1004,26 +1008,26 @@ __device__ __forceinline__ void dft_forward(cplx<T> *buf, const cplx<T> *bhat, i
         if (n < L) {
             cplx<T> v = get(u);
             if (blu) v = cmul<T>(v, chirp<T>(n, L));
-            buf[brev(n, logM)] = v;
+            buf[pd(brev(n, logM))] = v;
         }
     }
-    for (int n = L + tid; n < M; n += RT) buf[brev(n, logM)] = mk<T>(0, 0);
+    for (int n = L + tid; n < M; n += RT) buf[pd(brev(n, logM))] = mk<T>(0, 0);
     __syncthreads();
     fft_dit<T>(buf, M, tw, twn, -1);
     if (blu) {
-        for (int n = tid; n < M; n += RT) buf[n] = cmul<T>(buf[n], bhat[n]);
+        for (int n = tid; n < M; n += RT) buf[pd(n)] = cmul<T>(buf[pd(n)], bhat[n]);
         __syncthreads();
         fft_dif<T>(buf, M, tw, twn, +1);
 #pragma unroll
         for (int u = 0; u < RU; ++u) {
             const int kk = tid + RT * u;
-            if (kk < L) put(u, cmul<T>(buf[brev(kk, logM)], chirp<T>(kk, L)));
+            if (kk < L) put(u, cmul<T>(buf[pd(brev(kk, logM))], chirp<T>(kk, L)));
         }
     } else {
 #pragma unroll
         for (int u = 0; u < RU; ++u) {
             const int kk = tid + RT * u;
-            if (kk < L) put(u, buf[kk]);
+            if (kk < L) put(u, buf[pd(kk)]);
         }
     }
     __syncthreads();
@@ -1077,7 +1081,7 @@ __global__ __launch_bounds__(RT) void k_ring(cplx<T> *__restrict__ FG, int64_t f
                                              const RingInfo *__restrict__ rings, const int *__restrict__ order,
                                              const cplx<T> *__restrict__ tw, int twn, int lmax, double omega,
                                              double *__restrict__ o3, const uint8_t *__restrict__ mask,
-                                             const double *__restrict__ cdev)
+                                             const double *__restrict__ cdev, const cplx<T> *__restrict__ bhat_all)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cplx<T> *buf = reinterpret_cast<cplx<T> *>(smem_raw);
@@ -1088,24 +1092,11 @@ __global__ __launch_bounds__(RT) void k_ring(cplx<T> *__restrict__ FG, int64_t f
     const bool blu = ri.M > 0;
     const int M = blu ? ri.M : L;
     const int logM = 31 - __builtin_clz(M);
-    cplx<T> *bhat = buf + M;
+    // Bluestein rings: spectrum of the chirp for this L, computed at plan creation
+    const cplx<T> *bhat = bhat_all + (blu ? ri.bofs : 0);
     cplx<T> *F = FG + rhs * fg_stride + (int64_t)r * (lmax + 1) * 2;
     const int tid = threadIdx.x;
     const int64_t pofs = rhs * map_stride + ri.ofs;
-
-    if (blu) {  // FFT of the chirp b_n = e^{+i pi n^2/L} (n in (-L, L), wrapped), scaled by 1/M
-        for (int n = tid; n < M; n += RT) {
-            cplx<T> v = mk<T>(0, 0);
-            if (n < L) v = cconj<T>(chirp<T>(n, L));
-            else if (n > M - L) v = cconj<T>(chirp<T>(M - n, L));
-            bhat[brev(n, logM)] = v;
-        }
-        __syncthreads();
-        fft_dit<T>(bhat, M, tw, twn, -1);
-        const T inv = (T)1 / (T)M;
-        for (int n = tid; n < M; n += RT) bhat[n] = cscale<T>(bhat[n], inv);
-        __syncthreads();
-    }
 
     cplx<T> v[RU][4];
     if (MODE != 1) {
@@ -1566,18 +1557,53 @@ static void ring_launch_t(Plan &P, const double *g1, const double *g2, double *o
 {
     const int64_t fg_stride = (int64_t)P.nrings * (P.lmax + 1) * 2;
     const void *tw = std::is_same<T, double>::value ? P.d_tw64 : P.d_tw32;
+    const cplx<T> *bh = (const cplx<T> *)(std::is_same<T, double>::value ? P.d_bhat64 : P.d_bhat32);
     if (P.n_p2) {
-        size_t sm = sizeof(cplx<T>) * (size_t)P.maxM_p2;
+        size_t sm = sizeof(cplx<T>) * (size_t)(P.maxM_p2 + P.maxM_p2 / 32);
         k_ring<T, MODE><<<dim3(P.n_p2, nrhs), RT, sm, P.stream>>>((cplx<T> *)P.d_FG, fg_stride, g1, g2, o1, o2, P.npix,
                                                                   W, P.d_rings, P.d_order_p2, (const cplx<T> *)tw,
-                                                                  P.twn, P.lmax, P.omega, o3, mask, cdev);
+                                                                  P.twn, P.lmax, P.omega, o3, mask, cdev, bh);
     }
     if (P.n_bl) {
-        size_t sm = sizeof(cplx<T>) * (size_t)P.maxM_bl * 2;
+        size_t sm = sizeof(cplx<T>) * (size_t)(P.maxM_bl + P.maxM_bl / 32);
         k_ring<T, MODE><<<dim3(P.n_bl, nrhs), RT, sm, P.stream>>>((cplx<T> *)P.d_FG, fg_stride, g1, g2, o1, o2, P.npix,
                                                                   W, P.d_rings, P.d_order_bl, (const cplx<T> *)tw,
-                                                                  P.twn, P.lmax, P.omega, o3, mask, cdev);
+                                                                  P.twn, P.lmax, P.omega, o3, mask, cdev, bh);
     }
+}
+
+// Spectra of the Bluestein chirps, one per distinct sub-transform length L (plan creation):
+//   bhat = FFT_M(b) / M,  b_n = e^{+i pi n^2 / L} for n in (-L, L) (wrapped mod M), in FP64 and FP32.
+__global__ __launch_bounds__(RT) void k_bhat(const int *__restrict__ Ls, const int *__restrict__ Ms,
+                                             const int64_t *__restrict__ ofs, const double2 *__restrict__ tw,
+                                             int twn, double2 *__restrict__ b64, float2 *__restrict__ b32)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    double2 *buf = reinterpret_cast<double2 *>(smem_raw);
+    const int L = Ls[blockIdx.x], M = Ms[blockIdx.x];
+    const int64_t o = ofs[blockIdx.x];
+    const int logM = 31 - __builtin_clz(M);
+    for (int n = threadIdx.x; n < M; n += RT) {
+        double2 v = make_double2(0.0, 0.0);
+        if (n < L) v = cconj<double>(chirp<double>(n, L));
+        else if (n > M - L) v = cconj<double>(chirp<double>(M - n, L));
+        buf[pd(brev(n, logM))] = v;
+    }
+    __syncthreads();
+    fft_dit<double>(buf, M, tw, twn, -1);
+    const double inv = 1.0 / (double)M;
+    for (int n = threadIdx.x; n < M; n += RT) {
+        const double2 v = cscale<double>(buf[pd(n)], inv);
+        b64[o + n] = v;
+        b32[o + n] = make_float2((float)v.x, (float)v.y);
+    }
+}
+
+void launch_bhat(Plan &P, const int *Ls, const int *Ms, const int64_t *ofs, int n, int maxM)
+{
+    k_bhat<<<n, RT, sizeof(double2) * (size_t)(maxM + maxM / 32), P.stream>>>(Ls, Ms, ofs, (const double2 *)P.d_tw64,
+                                                                              P.twn, (double2 *)P.d_bhat64,
+                                                                              (float2 *)P.d_bhat32);
 }
 
 void launch_ring(Plan &P, bool fp32, int mode, const double *g1, const double *g2, double *o1, double *o2,

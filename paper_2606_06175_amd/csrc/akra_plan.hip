@@ -231,7 +231,7 @@ static void free_plan(Plan *P)
 {
     void *ptrs[] = {P->d_rings, P->d_pair_z, P->d_coef64, P->d_coef32, P->d_seed2, P->d_seedm2, P->d_seedk,
                     P->d_ent, P->d_entk, P->d_entl, P->d_wgstart, P->d_coef32d, P->d_brec,
-                    P->d_tw64, P->d_tw32, P->d_lof, P->d_order_p2, P->d_order_bl, P->d_FG, P->d_part, P->d_rec, P->d_W, P->d_kern, P->d_kuser, P->d_red, P->d_scal, P->d_flag, P->d_x, P->d_r,
+                    P->d_tw64, P->d_tw32, P->d_bhat64, P->d_bhat32, P->d_lof, P->d_order_p2, P->d_order_bl, P->d_FG, P->d_part, P->d_rec, P->d_W, P->d_kern, P->d_kuser, P->d_red, P->d_scal, P->d_flag, P->d_x, P->d_r,
                     P->d_p, P->d_w, P->d_b, P->d_xs};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
@@ -291,6 +291,24 @@ static akra_status create(int nside, int lmax, int nrhs, int prec, void *stream,
     P->maxM_p2 = maxp2;
     P->maxM_bl = maxbl;
     P->twn = std::max(2, std::max(maxp2, maxbl));
+    // one chirp spectrum per distinct Bluestein sub length (the two caps share them)
+    std::vector<int> bL, bM;
+    std::vector<int64_t> bO;
+    int64_t btot = 0;
+    {
+        std::vector<int64_t> at(P->nside + 1, -1);
+        for (int r : bl) {
+            RingInfo &ri = P->h_rings[r];
+            if (at[ri.sub] < 0) {
+                at[ri.sub] = btot;
+                bL.push_back(ri.sub);
+                bM.push_back(ri.M);
+                bO.push_back(btot);
+                btot += ri.M;
+            }
+            ri.bofs = at[ri.sub];
+        }
+    }
 
     // near-polar groups of FP32 plans: first pair of the group within theta_c of a pole
     P->ng64 = (P->npairs + 63) / 64;
@@ -383,6 +401,30 @@ static akra_status create(int nside, int lmax, int nrhs, int prec, void *stream,
         }
         AK_TRY(upload(&P->d_tw64, t64.data(), n * sizeof(double2), *P));
         AK_TRY(upload(&P->d_tw32, t32.data(), n * sizeof(float2), *P));
+    }
+    if (!bL.empty()) {
+        int *dL = nullptr, *dM = nullptr;
+        int64_t *dO = nullptr;
+        AK_TRY(alloc(&P->d_bhat64, (size_t)btot * sizeof(double2), *P));
+        AK_TRY(alloc(&P->d_bhat32, (size_t)btot * sizeof(float2), *P));
+        const size_t nb = bL.size();
+        bool ok = hipMalloc((void **)&dL, nb * sizeof(int)) == hipSuccess &&
+                  hipMalloc((void **)&dM, nb * sizeof(int)) == hipSuccess &&
+                  hipMalloc((void **)&dO, nb * sizeof(int64_t)) == hipSuccess &&
+                  hipMemcpy(dL, bL.data(), nb * sizeof(int), hipMemcpyHostToDevice) == hipSuccess &&
+                  hipMemcpy(dM, bM.data(), nb * sizeof(int), hipMemcpyHostToDevice) == hipSuccess &&
+                  hipMemcpy(dO, bO.data(), nb * sizeof(int64_t), hipMemcpyHostToDevice) == hipSuccess;
+        if (ok) {
+            launch_bhat(*P, dL, dM, dO, (int)nb, P->maxM_bl);
+            ok = hipGetLastError() == hipSuccess && hipStreamSynchronize(P->stream) == hipSuccess;
+        }
+        for (void *q : {(void *)dL, (void *)dM, (void *)dO})
+            if (q) (void)hipFree(q);
+        if (!ok) {
+            free_plan(P);
+            set_error("chirp-spectrum kernel failed");
+            return AKRA_ERR_HIP;
+        }
     }
     {
         std::vector<int> lof(P->nalm);
