@@ -63,6 +63,19 @@ typedef enum {
                              /* solves refine in FP64 to the requested tolerance                  */
 } akra_precision;
 
+/*
+ * Unknowns of a solve (App. A, eq. normal_block).  JOINT_EB solves the full 2x2 block system for
+ * x = (kappa_E, kappa_B).  E_ONLY solves the E block (H_EE + lambda_eff) kappa_E = b_E of the E-mode
+ * reconstruction of the main text: kappa_B is held at zero and returned as zero.  B_ONLY solves
+ * (H_BB + lambda_eff) kappa_B = b_B with kappa_E held at zero (the reduced system of eq.
+ * Bmode_reduced when the right-hand side is given, see akra_cg_solve_cond_b).
+ */
+typedef enum {
+    AKRA_JOINT_EB = 0,
+    AKRA_E_ONLY = 1,
+    AKRA_B_ONLY = 2
+} akra_mode;
+
 typedef struct {
     double lambda;           /* regulariser lambda (default 1e-3, Sec. II.B)                      */
     double tol;              /* ||r|| / ||b|| target (default 1e-3, Sec. III.C)                  */
@@ -74,6 +87,7 @@ typedef struct {
                              /* ||r|| drops by this factor (default 0.1)                         */
     double *resid_hist;      /* HOST, optional: relative residual after each iteration           */
     int resid_hist_len;
+    int mode;                /* akra_mode of the unknowns (default AKRA_JOINT_EB)                 */
 } akra_cg_opts;
 
 typedef struct {
@@ -87,7 +101,7 @@ typedef struct {
     int status;              /* akra_status of the solve                                          */
 } akra_cg_info;
 
-/* Default options (lambda 1e-3, tol 1e-3, maxiter 1000, x0 = 0, kernel sigma_D D_l). */
+/* Default options (lambda 1e-3, tol 1e-3, maxiter 1000, x0 = 0, kernel sigma_D D_l, joint E/B). */
 void akra_cg_opts_default(akra_cg_opts *opts);
 
 /*
@@ -147,6 +161,19 @@ akra_status akra_rhs(akra_plan plan, const double *g1, const double *g2, const d
  */
 akra_status akra_cg_solve(akra_plan plan, const double *g1, const double *g2, const double *ninv,
                           const uint8_t *mask, const akra_cg_opts *opts, double *xE, double *xB, akra_cg_info *info);
+
+/*
+ * Conditional B-mode solve (App. A, eq. lower_block and eq. Bmode_reduced).  Given a converged
+ * E-mode solution kE (device, alm layout, [nrhs] leading), forms the effective right-hand side
+ * b~_B = b_B - H_BE kE, with b_B the B block of b = K Y^H (W gamma_obs) and H_BE kE the B block of
+ * H (kE, 0), both in FP64, then solves (H_BB + lambda_eff) kB = b~_B by PCG as akra_cg_solve does
+ * (opts->mode is ignored; opts->use_x0 must be 0).  The stopping rule is relative to ||b~_B||.
+ * In: g1, g2, ninv, mask, kE.  Out: kB (device, alm layout; must not alias kE), info (HOST, may be
+ * NULL).  Errors and statuses as akra_cg_solve; AKRA_ERR_ARG for use_x0.
+ */
+akra_status akra_cg_solve_cond_b(akra_plan plan, const double *g1, const double *g2, const double *ninv,
+                                 const uint8_t *mask, const akra_cg_opts *opts, const double *kE, double *kB,
+                                 akra_cg_info *info);
 
 /* As akra_cg_solve for a given right-hand side (bE, bB) in alm layout (used by the adjoint solve of the
  * differentiable form). */

@@ -16,6 +16,9 @@ Definitions (paper Sec. II and App. A; where the paper is ambiguous the reading 
   * lambda_eff = lambda <N^-1>_M (mean over unmasked pixels), lambda = 1e-3.
   * P = (<M^2 N^-1> + lambda_eff)^-1 I, <.> the full-sphere pixel mean (eq. precond).
   * PCG (Sec. II.B inversion problem), x0 = 0, stop when ||r_k|| / ||b|| < tol.
+  * block systems (App. A, eq. normal_block): H_kj is block (k, j) of H, k, j in {0: E, 1: B};
+    the E-mode solve of the main text is (H_EE + lambda_eff) kappa_E = b_E, and the conditional
+    B-mode solve is (H_BB + lambda_eff) kappa_B = b_B - H_BE kappa_E (eq. Bmode_reduced).
 """
 import ctypes
 import os
@@ -211,24 +214,32 @@ class Oracle:
         cE, cB = self.adjoint(W * np.asarray(g1), W * np.asarray(g2), ring_idx=act)
         return self._project(np.stack([Kl * cE, Kl * cB]))
 
-    def cg(self, b, W, lam_eff, P=1.0, tol=1e-3, maxiter=1000, x0=None, kern=None, callback=None):
+    def cg(self, b, W, lam_eff, P=1.0, tol=1e-3, maxiter=1000, x0=None, kern=None, callback=None, block=None):
         """Preconditioned CG with the scalar preconditioner P (eq. precond).
 
+        block None: the joint system, b and x stacked (2, nalm).  block 0 or 1: the E or B block
+        system (H_kk + lambda_eff) x = b of App. A, b and x single-block (nalm,) vectors.
         Returns x and a dict with iterations, the recursive residual history and the
         true relative residual ||b - H x|| / ||b||."""
+        if block is None:
+            def op(v):
+                return self.apply_H(v, W, lam_eff, kern)
+        else:
+            def op(v):
+                return self.apply_block(v, W, lam_eff, block, block, kern)
         b = self._project(b)
         bn = np.sqrt(self.dot(b, b))
         if bn == 0.0:
             return np.zeros_like(b), {"iters": 0, "hist": [0.0], "rel_resid_true": 0.0}
         x = np.zeros_like(b) if x0 is None else self._project(x0)
-        r = b - self.apply_H(x, W, lam_eff, kern) if x0 is not None else b.copy()
+        r = b - op(x) if x0 is not None else b.copy()
         z = P * r
         p = z.copy()
         rz = self.dot(r, z)
         hist = [np.sqrt(self.dot(r, r)) / bn]
         it = 0
         while hist[-1] >= tol and it < maxiter:
-            w = self.apply_H(p, W, lam_eff, kern)
+            w = op(p)
             alpha = rz / self.dot(p, w)
             x = x + alpha * p
             r = r - alpha * w
@@ -240,5 +251,19 @@ class Oracle:
             hist.append(np.sqrt(self.dot(r, r)) / bn)
             if callback:
                 callback(it, x, hist[-1])
-        rt = b - self.apply_H(x, W, lam_eff, kern)
+        rt = b - op(x)
         return x, {"iters": it, "hist": hist, "rel_resid_true": float(np.sqrt(self.dot(rt, rt)) / bn)}
+
+    # -- block systems (App. A) -----------------------------------------------------------------
+    def apply_block(self, v, W, lam_eff, out, inp, kern=None):
+        """Block (out, inp) of H applied to the single-block vector v, blocks 0 = E and 1 = B
+        (eq. normal_block): H applied to v placed in block inp, block out of the result.  The
+        regulariser lambda_eff enters the diagonal blocks only."""
+        x = np.zeros((2, self.nalm), np.complex128)
+        x[inp] = v
+        return self.apply_H(x, W, lam_eff, kern)[out]
+
+    def cond_b_rhs(self, g1, g2, W, lam_eff, kE, kern=None):
+        """Effective right-hand side of the reduced B-mode system, b_B - H_BE kE (eq. lower_block,
+        eq. Bmode_reduced)."""
+        return self._project(self.rhs(g1, g2, W, kern)[1] - self.apply_block(kE, W, lam_eff, 1, 0, kern))

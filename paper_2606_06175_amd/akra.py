@@ -34,7 +34,11 @@ class CgOpts(ctypes.Structure):
     _fields_ = [("lambda_", ctypes.c_double), ("tol", ctypes.c_double), ("maxiter", ctypes.c_int),
                 ("use_x0", ctypes.c_int), ("kernel_l", ctypes.POINTER(ctypes.c_double)),
                 ("reliable_delta", ctypes.c_double), ("resid_hist", ctypes.POINTER(ctypes.c_double)),
-                ("resid_hist_len", ctypes.c_int)]
+                ("resid_hist_len", ctypes.c_int), ("mode", ctypes.c_int)]
+
+
+# unknowns of a solve (akra_mode): joint (kappa_E, kappa_B), the E block only, the B block only
+MODES = {"joint": 0, "E": 1, "B": 2}
 
 
 class CgInfo(ctypes.Structure):
@@ -75,11 +79,12 @@ def lib():
     L.akra_plan_work.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
     L.akra_cg_solve_vjp.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(CgOpts), vp, vp, vp, vp, vp, vp, vp,
                                     ctypes.POINTER(CgInfo)]
+    L.akra_cg_solve_cond_b.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(CgOpts), vp, vp, ctypes.POINTER(CgInfo)]
     L.akra_plan_stage_times.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int)]
     for f in ("akra_plan_create", "akra_synth2", "akra_adjoint2", "akra_apply_H", "akra_rhs", "akra_cg_solve",
               "akra_cg_solve_b", "akra_cg_start", "akra_cg_step", "akra_cg_state", "akra_plan_set_timing",
               "akra_plan_stage_times", "akra_plan_set_tuning", "akra_plan_get_tuning", "akra_plan_work",
-              "akra_cg_solve_vjp"):
+              "akra_cg_solve_vjp", "akra_cg_solve_cond_b"):
         getattr(L, f).restype = ctypes.c_int
     _lib = L
     return L
@@ -205,10 +210,13 @@ class Plan:
                                   bE.data_ptr(), bB.data_ptr()))
         return bE, bB
 
-    def _opts(self, tol, maxiter, lam, x0, kernel, reliable_delta, hist_len):
+    def _opts(self, tol, maxiter, lam, x0, kernel, reliable_delta, hist_len, mode="joint"):
         o = CgOpts()
         lib().akra_cg_opts_default(ctypes.byref(o))
         o.lambda_, o.tol, o.maxiter = float(lam), float(tol), int(maxiter)
+        if mode not in MODES:
+            raise ValueError("mode must be one of %s" % sorted(MODES))
+        o.mode = MODES[mode]
         o.use_x0 = 1 if x0 is not None else 0
         o.reliable_delta = float(reliable_delta)
         keep = []
@@ -232,7 +240,9 @@ class Plan:
         return d
 
     def cg_solve(self, g1, g2, ninv, mask, tol=1e-3, maxiter=1000, lam=1e-3, x0=None, kernel=None,
-                 reliable_delta=0.1, hist_len=0, raise_not_converged=True):
+                 reliable_delta=0.1, hist_len=0, raise_not_converged=True, mode="joint"):
+        """Regularised ML estimate (kappa_E, kappa_B).  mode "joint" solves the full E/B system, "E"
+        the E block alone (kappa_B returned as zero), "B" the B block alone."""
         g1, g2 = self._map(g1, "g1"), self._map(g2, "g2")
         ninv = self._map(ninv, "ninv")
         mask = self._map(mask, "mask", torch.uint8, per_rhs=False)
@@ -240,7 +250,7 @@ class Plan:
         if x0 is not None:
             xE.copy_(x0[0].reshape(xE.shape))
             xB.copy_(x0[1].reshape(xB.shape))
-        o, keep = self._opts(tol, maxiter, lam, x0, kernel, reliable_delta, hist_len)
+        o, keep = self._opts(tol, maxiter, lam, x0, kernel, reliable_delta, hist_len, mode)
         inf = CgInfo()
         with torch.cuda.device(self.device):
             st = lib().akra_cg_solve(self._h, g1.data_ptr(), g2.data_ptr(), ninv.data_ptr(), mask.data_ptr(),
@@ -250,7 +260,7 @@ class Plan:
         return xE, xB, self._info(inf, keep, hist_len)
 
     def cg_solve_vjp(self, g1, g2, ninv, mask, xE, xB, vE, vB, tol=1e-3, maxiter=1000, lam=1e-3, kernel=None,
-                     reliable_delta=0.1, raise_not_converged=True):
+                     reliable_delta=0.1, raise_not_converged=True, mode="joint"):
         """dL/dg1, dL/dg2, dL/dninv for x = cg_solve(g1, g2, ninv, mask, ...) and the upstream
         gradient (vE, vB) on the stored (Re, Im) of x (one more CG solve, see akra_cg_solve_vjp)."""
         g1, g2 = self._map(g1, "g1"), self._map(g2, "g2")
@@ -259,7 +269,7 @@ class Plan:
         xE, xB = self._alm(xE, "xE"), self._alm(xB, "xB")
         vE, vB = self._alm(vE, "vE"), self._alm(vB, "vB")
         dg1, dg2, dn = self._map_out(), self._map_out(), self._map_out()
-        o, keep = self._opts(tol, maxiter, lam, None, kernel, reliable_delta, 0)
+        o, keep = self._opts(tol, maxiter, lam, None, kernel, reliable_delta, 0, mode)
         inf = CgInfo()
         with torch.cuda.device(self.device):
             st = lib().akra_cg_solve_vjp(self._h, g1.data_ptr(), g2.data_ptr(), ninv.data_ptr(), mask.data_ptr(),
@@ -270,7 +280,7 @@ class Plan:
         return dg1, dg2, dn, self._info(inf, keep, 0)
 
     def cg_solve_b(self, bE, bB, ninv, mask, tol=1e-3, maxiter=1000, lam=1e-3, x0=None, kernel=None,
-                   reliable_delta=0.1, hist_len=0, raise_not_converged=True):
+                   reliable_delta=0.1, hist_len=0, raise_not_converged=True, mode="joint"):
         bE, bB = self._alm(bE, "bE"), self._alm(bB, "bB")
         ninv = self._map(ninv, "ninv")
         mask = self._map(mask, "mask", torch.uint8, per_rhs=False)
@@ -278,7 +288,7 @@ class Plan:
         if x0 is not None:
             xE.copy_(x0[0].reshape(xE.shape))
             xB.copy_(x0[1].reshape(xB.shape))
-        o, keep = self._opts(tol, maxiter, lam, x0, kernel, reliable_delta, hist_len)
+        o, keep = self._opts(tol, maxiter, lam, x0, kernel, reliable_delta, hist_len, mode)
         inf = CgInfo()
         with torch.cuda.device(self.device):
             st = lib().akra_cg_solve_b(self._h, ninv.data_ptr(), mask.data_ptr(), bE.data_ptr(), bB.data_ptr(),
@@ -287,13 +297,31 @@ class Plan:
             _check(st)
         return xE, xB, self._info(inf, keep, hist_len)
 
+    def cg_solve_cond_b(self, g1, g2, ninv, mask, kE, tol=1e-3, maxiter=1000, lam=1e-3, kernel=None,
+                        reliable_delta=0.1, hist_len=0, raise_not_converged=True):
+        """Conditional B-mode solve: kappa_B of (H_BB + lambda_eff) kappa_B = b_B - H_BE kE for a given
+        E-mode solution kE (see akra_cg_solve_cond_b)."""
+        g1, g2 = self._map(g1, "g1"), self._map(g2, "g2")
+        ninv = self._map(ninv, "ninv")
+        mask = self._map(mask, "mask", torch.uint8, per_rhs=False)
+        kE = self._alm(kE, "kE")
+        kB = self._alm_out()
+        o, keep = self._opts(tol, maxiter, lam, None, kernel, reliable_delta, hist_len)
+        inf = CgInfo()
+        with torch.cuda.device(self.device):
+            st = lib().akra_cg_solve_cond_b(self._h, g1.data_ptr(), g2.data_ptr(), ninv.data_ptr(), mask.data_ptr(),
+                                            ctypes.byref(o), kE.data_ptr(), kB.data_ptr(), ctypes.byref(inf))
+        if st != AKRA_OK and (st != AKRA_NOT_CONVERGED or raise_not_converged):
+            _check(st)
+        return kB, self._info(inf, keep, hist_len)
+
     # -- step-wise PCG ------------------------------------------------------------------------
-    def cg_start(self, g1, g2, ninv, mask, lam=1e-3, kernel=None):
+    def cg_start(self, g1, g2, ninv, mask, lam=1e-3, kernel=None, mode="joint"):
         """Form b, lambda_eff and P and set x0 = 0 (first right-hand side of the plan)."""
         g1, g2 = self._map(g1, "g1"), self._map(g2, "g2")
         ninv = self._map(ninv, "ninv")
         mask = self._map(mask, "mask", torch.uint8, per_rhs=False)
-        o, keep = self._opts(1e-3, 0, lam, None, kernel, 0.1, 0)
+        o, keep = self._opts(1e-3, 0, lam, None, kernel, 0.1, 0, mode)
         with torch.cuda.device(self.device):
             _check(lib().akra_cg_start(self._h, g1.data_ptr(), g2.data_ptr(), ninv.data_ptr(), mask.data_ptr(),
                                        ctypes.byref(o)))
@@ -349,7 +377,8 @@ class AkraSolve(torch.autograd.Function):
         xE, xB = AkraSolve.apply(g1, g2, ninv, mask, plan, dict(tol=1e-8))
 
     Gradients flow to g1, g2 and ninv (not to the mask).  The backward pass is one more CG solve
-    with the same operator, run by akra_cg_solve_vjp; solver options apply to both solves."""
+    with the same operator, run by akra_cg_solve_vjp; solver options (the mode of the unknowns
+    included) apply to both solves."""
 
     @staticmethod
     def forward(ctx, g1, g2, ninv, mask, plan, opts=None):

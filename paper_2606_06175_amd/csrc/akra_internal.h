@@ -126,6 +126,9 @@ struct Plan {
     // solver state of the right-hand side in progress
     bool cg_ready = false;
     int cg_rhs = 0, cg_iters = 0, cg_fp64_applies = 0;
+    // unknowns of the running solve (App. A block systems): 0 joint E/B, 1 E only (the epilogue
+    // zeroes the B block of every output), 2 B only (E block zeroed); cg_proj is kept for akra_cg_step
+    int proj = 0, cg_proj = 0;
     double cg_bn = 0, cg_rr = 0, cg_lam = 0, cg_pc = 1;
     const double *cg_kern = nullptr;
 

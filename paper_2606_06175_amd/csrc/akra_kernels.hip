@@ -863,7 +863,7 @@ template <typename T>
 __global__ void k_epilogue(const T *__restrict__ part, const int *__restrict__ wgstart, int nrb, int64_t nalm,
                            const int *__restrict__ lof, int lmax, const double *__restrict__ kern, double lam,
                            const double *__restrict__ xE, const double *__restrict__ xB, double *__restrict__ outE,
-                           double *__restrict__ outB)
+                           double *__restrict__ outB, int proj)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nalm) return;
@@ -896,6 +896,9 @@ __global__ void k_epilogue(const T *__restrict__ part, const int *__restrict__ w
             bI += lam * xB[2 * i + 1];
         }
     }
+    // block systems: the output block of the unknowns held at zero is zero
+    if (proj == 1) bR = bI = 0.0;
+    if (proj == 2) eR = eI = 0.0;
     outE[2 * i] = eR;
     outE[2 * i + 1] = eI;
     outB[2 * i] = bR;
@@ -1544,10 +1547,10 @@ void launch_epilogue(Plan &P, bool fp32, const double *kern, double lam, const d
     dim3 g((unsigned)cdiv(P.nalm, 256));
     if (fp32)
         k_epilogue<float><<<g, 256, 0, P.stream>>>((const float *)P.d_part, P.d_wgstart, P.adj_nrb, P.nalm, P.d_lof,
-                                                   P.lmax, kern, lam, xE, xB, outE, outB);
+                                                   P.lmax, kern, lam, xE, xB, outE, outB, P.proj);
     else
         k_epilogue<double><<<g, 256, 0, P.stream>>>((const double *)P.d_part, P.d_wgstart, P.adj_nrb, P.nalm,
-                                                    P.d_lof, P.lmax, kern, lam, xE, xB, outE, outB);
+                                                    P.d_lof, P.lmax, kern, lam, xE, xB, outE, outB, P.proj);
 }
 
 template <typename T, int MODE>

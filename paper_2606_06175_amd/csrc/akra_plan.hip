@@ -564,6 +564,23 @@ __global__ void k_set(double *p, double v) { *p = v; }
 // after a residual replacement: rz = P <r, r> for the next alpha; the search direction is kept
 __global__ void k_cg_rz(double *scal, double pc) { scal[0] = pc * scal[3]; }
 
+// ---- block systems (App. A) ---------------------------------------------------------------------
+// Sets the unknowns of a solve for its duration; every apply, right-hand side and gradient formed
+// meanwhile has the block of the held unknowns zeroed by the epilogue.
+struct ProjScope {
+    Plan &P;
+    ProjScope(Plan &p, int mode) : P(p) { P.proj = mode; }
+    ~ProjScope() { P.proj = 0; }
+};
+
+// zero the held block of an (E, B) pair of alm vectors (v: E at v, B at v + 2 nalm)
+static akra_status zero_held(Plan &P, double *v)
+{
+    if (P.proj == 1) AK_HIP(hipMemsetAsync(v + 2 * P.nalm, 0, sizeof(double2) * P.nalm, P.stream), "memset");
+    if (P.proj == 2) AK_HIP(hipMemsetAsync(v, 0, sizeof(double2) * P.nalm, P.stream), "memset");
+    return AKRA_OK;
+}
+
 // ---- stage timing (HIP events on the plan stream) -------------------------------------------
 static void stage_mark(Plan &P, int stage, bool begin)
 {
@@ -988,11 +1005,15 @@ static akra_status cg_prepare(Plan &P, const double *g1, const double *g2, const
                               P.stream),
                "copy");
     }
+    akra_status st = zero_held(P, P.d_b);
+    if (st) return st;
     if (o.use_x0) {
         AK_HIP(hipMemcpyAsync(P.d_x, xE + off, sizeof(double2) * P.nalm, hipMemcpyDeviceToDevice, P.stream), "copy");
         AK_HIP(hipMemcpyAsync(P.d_x + 2 * P.nalm, xB + off, sizeof(double2) * P.nalm, hipMemcpyDeviceToDevice,
                               P.stream),
                "copy");
+        st = zero_held(P, P.d_x);
+        if (st) return st;
     }
     return cg_begin(P, o.use_x0 != 0);
 }
@@ -1001,7 +1022,8 @@ static akra_status read_opts(const akra_cg_opts *opts, akra_cg_opts &o)
 {
     akra_cg_opts_default(&o);
     if (opts) o = *opts;
-    if (!(o.tol > 0) || o.maxiter < 0 || !(o.lambda >= 0) || !(o.reliable_delta > 0 && o.reliable_delta < 1)) {
+    if (!(o.tol > 0) || o.maxiter < 0 || !(o.lambda >= 0) || !(o.reliable_delta > 0 && o.reliable_delta < 1) ||
+        o.mode < AKRA_JOINT_EB || o.mode > AKRA_B_ONLY) {
         set_error("invalid solver options");
         return AKRA_ERR_ARG;
     }
@@ -1035,11 +1057,15 @@ static akra_status solve_batched(Plan &P, const double *g1, const double *g2, co
                                   P.stream),
                    "copy");
         }
+        akra_status s0 = zero_held(P, V(P.d_b, r));
+        if (s0) return s0;
         if (o.use_x0) {
             AK_HIP(hipMemcpyAsync(V(P.d_x, r), xE + off, sizeof(double2) * na, hipMemcpyDeviceToDevice, P.stream), "copy");
             AK_HIP(hipMemcpyAsync(V(P.d_x, r) + 2 * na, xB + off, sizeof(double2) * na, hipMemcpyDeviceToDevice,
                                   P.stream),
                    "copy");
+            s0 = zero_held(P, V(P.d_x, r));
+            if (s0) return s0;
         } else {
             AK_HIP(hipMemsetAsync(V(P.d_x, r), 0, sizeof(double2) * nc, P.stream), "memset");
         }
@@ -1191,7 +1217,9 @@ static akra_status solve_batched(Plan &P, const double *g1, const double *g2, co
         worst_true = std::max(worst_true, tr);
         worst_rel = std::max(worst_rel, bn[r] > 0 ? rel[r] : 0.0);
         if (status[r] != AKRA_OK) result = AKRA_NOT_CONVERGED;
-        AK_HIP(hipMemcpyAsync(xE + off, V(P.d_x, r), sizeof(double2) * na, hipMemcpyDeviceToDevice, P.stream), "copy");
+        if (xE)
+            AK_HIP(hipMemcpyAsync(xE + off, V(P.d_x, r), sizeof(double2) * na, hipMemcpyDeviceToDevice, P.stream),
+                   "copy");
         AK_HIP(hipMemcpyAsync(xB + off, V(P.d_x, r) + 2 * na, sizeof(double2) * na, hipMemcpyDeviceToDevice,
                               P.stream),
                "copy");
@@ -1222,6 +1250,7 @@ static akra_status solve_common(Plan &P, const double *g1, const double *g2, con
     const double *kd;
     st = kernel_to_device(P, o.kernel_l, &kd);
     if (st) return st;
+    ProjScope scope(P, o.mode);
     akra_status worst = AKRA_OK;
     if (P.prec == AKRA_FP32 && P.nrhs > 1) {
         worst = solve_batched(P, g1, g2, bE, bB, o, kd, le, pc, xE, xB, info);
@@ -1237,7 +1266,9 @@ static akra_status solve_common(Plan &P, const double *g1, const double *g2, con
         if (st) return st;
         st = cg_run(P, o, &info);
         if (st == AKRA_OK || st == AKRA_NOT_CONVERGED) {
-            AK_HIP(hipMemcpyAsync(xE + off, P.d_x, sizeof(double2) * P.nalm, hipMemcpyDeviceToDevice, P.stream), "copy");
+            if (xE)
+                AK_HIP(hipMemcpyAsync(xE + off, P.d_x, sizeof(double2) * P.nalm, hipMemcpyDeviceToDevice, P.stream),
+                       "copy");
             AK_HIP(hipMemcpyAsync(xB + off, P.d_x + 2 * P.nalm, sizeof(double2) * P.nalm, hipMemcpyDeviceToDevice,
                                   P.stream),
                    "copy");
@@ -1272,6 +1303,61 @@ akra_status akra_cg_solve_b(akra_plan plan, const double *ninv, const uint8_t *m
         return AKRA_ERR_ARG;
     }
     return solve_common(P, nullptr, nullptr, ninv, mask, bE, bB, opts, xE, xB, info);
+}
+
+// Conditional B-mode solve (App. A): b~_B = b_B - H_BE kE, then (H_BB + lambda_eff) kB = b~_B.
+// b~_B of every right-hand side is formed in FP64 into kB, which then serves as the given
+// right-hand side of a B-only solve (the E block of a given b is zeroed by the B-only scope).
+akra_status akra_cg_solve_cond_b(akra_plan plan, const double *g1, const double *g2, const double *ninv,
+                                 const uint8_t *mask, const akra_cg_opts *opts, const double *kE, double *kB,
+                                 akra_cg_info *info)
+{
+    AK_PLAN();
+    if (!g1 || !g2 || !kE || !kB) {
+        set_error("null pointer argument");
+        return AKRA_ERR_ARG;
+    }
+    akra_cg_opts o;
+    akra_status st = read_opts(opts, o);
+    if (st) return st;
+    if (o.use_x0) {
+        set_error("use_x0 is not supported by the conditional B-mode solve");
+        return AKRA_ERR_ARG;
+    }
+    if (kE == kB) {
+        set_error("kB must not alias kE");
+        return AKRA_ERR_ARG;
+    }
+    std::vector<double> le, pc;
+    st = setup_weights(P, ninv, mask, o.lambda, le, pc);
+    if (st) return st;
+    const double *kd;
+    st = kernel_to_device(P, o.kernel_l, &kd);
+    if (st) return st;
+    const int64_t na = P.nalm, nc = 2 * na;
+    {
+        ProjScope scope(P, AKRA_JOINT_EB);
+        for (int r = 0; r < P.nrhs; ++r) {
+            const int64_t off = (int64_t)r * 2 * na;
+            // b of this right-hand side (both blocks) into d_b
+            launch_ring(P, false, 1, g1 + r * P.npix, g2 + r * P.npix, nullptr, nullptr, P.d_W + r * P.npix, 1);
+            launch_leg_adj(P, false, 0);
+            launch_epilogue(P, false, kd, 0.0, nullptr, nullptr, P.d_b, P.d_b + nc);
+            // H (kE, 0) into d_w; the B block is H_BE kE (the regulariser term of a zero B is zero)
+            AK_HIP(hipMemsetAsync(P.d_xs + nc, 0, sizeof(double2) * na, P.stream), "memset");
+            st = apply_H_timed(P, false, kd, le[r], kE + off, P.d_xs + nc, P.d_w, P.d_w + nc, r);
+            if (st) return st;
+            launch_axpby(P, P.d_b + nc, -1.0, P.d_w + nc, 1.0, na);
+            AK_HIP(hipMemcpyAsync(kB + off, P.d_b + nc, sizeof(double2) * na, hipMemcpyDeviceToDevice, P.stream),
+                   "copy");
+        }
+        st = check_launch("cond_b rhs");
+        if (st) return st;
+    }
+    akra_cg_opts ob = o;
+    ob.mode = AKRA_B_ONLY;
+    // the given right-hand side: B block in kB, its E block is zeroed by the B-only scope
+    return solve_common(P, nullptr, nullptr, ninv, mask, kB, kB, &ob, nullptr, kB, info);
 }
 
 __global__ void k_sum2_scaled(double *out, const double *a, const double *b, double f) { *out = f * (*a + *b); }
@@ -1310,9 +1396,12 @@ akra_status akra_cg_solve_vjp(akra_plan plan, const double *g1, const double *g2
     if (st) return st;
     akra_status worst = AKRA_OK;
     const int64_t na = P.nalm;
+    ProjScope scope(P, o.mode);
     for (int r = 0; r < P.nrhs; ++r) {
         const int64_t off = (int64_t)r * 2 * na, mo = (int64_t)r * P.npix;
         launch_vjp_rhs(P, vE + off, vB + off, P.d_b, P.d_b + 2 * na);
+        st = zero_held(P, P.d_b);
+        if (st) return st;
         P.cg_kern = kd;
         P.cg_lam = le[r];
         P.cg_pc = pc[r];
@@ -1366,6 +1455,8 @@ akra_status akra_cg_start(akra_plan plan, const double *g1, const double *g2, co
     const double *kd;
     st = kernel_to_device(P, o.kernel_l, &kd);
     if (st) return st;
+    P.cg_proj = o.mode;
+    ProjScope scope(P, o.mode);
     return cg_prepare(P, g1, g2, nullptr, nullptr, nullptr, nullptr, o, kd, le, pc, 0);
 }
 
@@ -1376,6 +1467,7 @@ akra_status akra_cg_step(akra_plan plan, int nsteps)
         set_error("akra_cg_step before akra_cg_start");
         return AKRA_ERR_ARG;
     }
+    ProjScope scope(P, P.cg_proj);
     for (int i = 0; i < nsteps; ++i) {
         akra_status st = cg_iterate(P, P.prec == AKRA_FP32);
         if (st) return st;

@@ -34,8 +34,9 @@ def _loss(torch, xE, xB, cE, cB):
         + 0.25 * (cB.real * xB.real).sum()
 
 
-def _dense_grads(nside, lmax, mask, ninv, g1, g2, cE, cB, lam=1e-3):
-    """Gradient of the same loss with the dense H and b, differentiated by torch on the CPU."""
+def _dense_grads(nside, lmax, mask, ninv, g1, g2, cE, cB, lam=1e-3, mode="joint"):
+    """Gradient of the same loss with the dense H and b, differentiated by torch on the CPU.
+    mode "E": the E block system of App. A (kappa_B = 0)."""
     import torch
     rings = healpix_rings(nside)
     o = Oracle(lmax, rings)
@@ -57,7 +58,12 @@ def _dense_grads(nside, lmax, mask, ninv, g1, g2, cE, cB, lam=1e-3):
     lam_eff = lam * W.sum() / M.sum()
     H = Ar.T @ (wt[:, None] * Ar) + lam_eff * torch.eye(nd, dtype=torch.float64)
     b = Ar.T @ (wt * torch.cat([t_1, t_2]))
-    u = torch.linalg.solve(H, b)
+    if mode == "E":
+        e = torch.tensor([f == 0 for (f, _, _, _) in lay])
+        u = torch.zeros(nd, dtype=torch.float64)
+        u = u.masked_scatter(e, torch.linalg.solve(H[e][:, e], b[e]))
+    else:
+        u = torch.linalg.solve(H, b)
     x = torch.complex(Pr @ u, Pi @ u)
     na = alm_size(lmax)
     L = _loss(torch, x[:na], x[na:], torch.from_numpy(cE), torch.from_numpy(cB))
@@ -65,7 +71,7 @@ def _dense_grads(nside, lmax, mask, ninv, g1, g2, cE, cB, lam=1e-3):
     return t_1.grad.numpy(), t_2.grad.numpy(), t_n.grad.numpy(), float(L.detach()), x.detach().numpy()
 
 
-def _gpu(nside, lmax, prec, mask, ninv, g1, g2, cE, cB, tol, nrhs=1):
+def _gpu(nside, lmax, prec, mask, ninv, g1, g2, cE, cB, tol, nrhs=1, mode="joint"):
     import torch
     from paper_2606_06175_amd import AkraSolve, Plan
     print("plan nside=%d lmax=%d %s nrhs=%d" % (nside, lmax, prec, nrhs), flush=True)
@@ -73,7 +79,7 @@ def _gpu(nside, lmax, prec, mask, ninv, g1, g2, cE, cB, tol, nrhs=1):
     p = Plan(nside, lmax, nrhs=nrhs, precision=prec, device=dev)
     t = [torch.tensor(a, dtype=torch.float64, device=dev, requires_grad=True) for a in (g1, g2, ninv)]
     m = torch.from_numpy(mask).to(dev)
-    xE, xB = AkraSolve.apply(t[0], t[1], t[2], m, p, dict(tol=tol, maxiter=5000))
+    xE, xB = AkraSolve.apply(t[0], t[1], t[2], m, p, dict(tol=tol, maxiter=5000, mode=mode))
     L = _loss(torch, xE, xB, torch.from_numpy(cE).to(dev), torch.from_numpy(cB).to(dev))
     L.backward()
     return [a.grad.cpu().numpy() for a in t], float(L.detach()), p
@@ -155,3 +161,18 @@ def test_batched_gradient_matches_single():
     for k in range(2):
         for j in range(3):
             assert rel(t[j].grad[k].cpu().numpy(), single[k][j]) < 1e-9
+
+
+def test_e_only_gradient_matches_dense_reference():
+    # the differentiable E-mode solve (App. A E block): both solves of AkraSolve run on the block
+    nside, lmax = 4, 8
+    mask, ninv, g1, g2 = _problem(nside, 41)
+    cE = wl.random_alm(lmax, 42)
+    cB = wl.random_alm(lmax, 43)
+    d1, d2, dn, Lref, xref = _dense_grads(nside, lmax, mask, ninv, g1, g2, cE, cB, mode="E")
+    (a1, a2, an), L, _ = _gpu(nside, lmax, "fp64", mask, ninv, g1, g2, cE, cB, tol=1e-13, mode="E")
+    print("L %.15e ref %.15e" % (L, Lref), flush=True)
+    assert abs(L - Lref) < 1e-9 * abs(Lref)
+    e = [rel(np.r_[a1, a2], np.r_[d1, d2]), rel(an, dn)]
+    print("rel err d/dgamma %.3e d/dninv %.3e" % tuple(e), flush=True)
+    assert e[0] < 1e-9 and e[1] < 1e-9
