@@ -37,6 +37,19 @@ struct alignas(32) Coef64 {
 struct alignas(16) Coef32 {
     float a, b, g, pad;
 };
+// Scaled form of the same recurrence, run by the Legendre kernels away from the poles.  With
+// lambda_l = c_l mu_l, where c_{l0} = c_{l0+1} = 1 and c_{l+1} = g_l c_{l-1},
+//   mu_{l+1} = (a' x +- b') mu_l - mu_{l-1},   a' = a c_l / c_{l+1},  b' = b c_l / c_{l+1},
+// two FMAs per spin and step instead of three operations and a shared product.  Every g_l < 1 and
+// their products stay of order one (c_l > 2^-3.1 at lmax 16384 over a dense sample of m), so mu
+// has lambda's range.
+// Synthesis records carry the alm multiplied by c_l; the adjoint multiplies its sums by c_l.
+struct alignas(32) Coef64S {
+    double a, b, c, ic;  // a', b', c_l, 1 / c_l
+};
+struct alignas(16) Coef32S {
+    float a, b, c, ic;
+};
 // Near the poles FP32 kernels run the recurrence in difference form, with d_l = lambda_l - lambda_{l-1}
 // and y = 1 - x:
 //   d_{l+1} = (e - a y) lambda_l + g d_l,   lambda_{l+1} = lambda_l + d_{l+1},   e = a +- b - g - 1.
@@ -78,8 +91,10 @@ struct Plan {
     // tables
     RingInfo *d_rings = nullptr;
     double *d_pair_z = nullptr;
-    Coef64 *d_coef64 = nullptr;
-    Coef32 *d_coef32 = nullptr;
+    Coef64 *d_coef64 = nullptr;  // plain form: entry states (plan build)
+    Coef32 *d_coef32 = nullptr;  // plain form: batched matrix-core synthesis
+    Coef64S *d_coef64s = nullptr;  // scaled form (Legendre kernels, FP64), and c_l for every form
+    Coef32S *d_coef32s = nullptr;  // scaled form (Legendre kernels, FP32)
     Coef32D *d_coef32d = nullptr;
     double *d_seed2 = nullptr, *d_seedm2 = nullptr;  // [m][pair] seeds at l = max(m,2) (plan build only)
     int *d_seedk = nullptr;
@@ -109,7 +124,9 @@ struct Plan {
     // workspaces (sized for FP64; FP32 views reuse them)
     void *d_FG = nullptr;       // [nrhs][nrings][lmax+1][2] complex
     void *d_part = nullptr;     // [nrb][nalm][4] adjoint partial sums
-    void *d_rec = nullptr;      // [nrhs][nalm + ALM_PAD] synthesis records (64 B in FP64)
+    void *d_rec = nullptr;      // [nrhs][nalm + ALM_PAD] synthesis records (64 B in FP64), scaled form
+    float4 *d_recu = nullptr;   // FP32 plans with polar groups: [nrhs][nalm + ALM_PAD] unscaled alm for
+                                // the difference form
     float *d_brec = nullptr;    // FP32 plans with nrhs > 1: [nalm + ALM_PAD][8 rhs][4] batched records
     int64_t rec_stride = 0;     // records per right-hand side
     double *d_W = nullptr;      // [nrhs][npix] weights

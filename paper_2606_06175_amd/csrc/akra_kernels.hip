@@ -16,12 +16,16 @@ template <typename T> struct V2;
 template <> struct V2<double> { using type = double2; };
 template <> struct V2<float> { using type = float2; };
 template <typename T> using cplx = typename V2<T>::type;
-// Recurrence forms: 0 the plain three-term form (FP64, and FP32 away from the poles), 1 the
-// difference form of FP32 near the poles (see Coef32D).
+// Recurrence forms of the Legendre kernels: 0 the plain three-term form in its scaled variant (FP64,
+// and FP32 away from the poles; see Coef64S), 1 the difference form of FP32 near the poles (see
+// Coef32D).  The batched matrix-core synthesis runs the unscaled plain form (CoefB).
 template <typename T, int F> struct CoefT;
-template <> struct CoefT<double, 0> { using type = Coef64; };
-template <> struct CoefT<float, 0> { using type = Coef32; };
+template <> struct CoefT<double, 0> { using type = Coef64S; };
+template <> struct CoefT<float, 0> { using type = Coef32S; };
 template <> struct CoefT<float, 1> { using type = Coef32D; };
+template <int F> struct CoefB;
+template <> struct CoefB<0> { using type = Coef32; };
+template <> struct CoefB<1> { using type = Coef32D; };
 
 template <typename T> __device__ __forceinline__ cplx<T> mk(T a, T b) { cplx<T> r; r.x = a; r.y = b; return r; }
 template <typename T> __device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> b)
@@ -48,12 +52,20 @@ template <typename T> __device__ __forceinline__ cplx<T> cis_pi(int64_t k, int64
 // ------------------------------------------------------------------------------------------------
 // Entry states: stored in FP64 as mant * 2^(512 k).  FP32 kernels re-express them in their own unit.
 // ------------------------------------------------------------------------------------------------
+// i0, i1: 1 / c_l and 1 / c_{l-1} at the entry degree l for the scaled plain form (mu = lambda / c);
+// the difference form and the unscaled plain form pass 1.
 template <typename T, int F>
 __device__ __forceinline__ void load_entry(const Ent64 *__restrict__ ent, const int *__restrict__ entk, int64_t idx,
-                                           T &c2, T &p2, T &cm, T &pm, int &k)
+                                           T &c2, T &p2, T &cm, T &pm, int &k, double i0 = 1.0, double i1 = 1.0)
 {
-    const Ent64 e = ent[idx];
+    Ent64 e = ent[idx];
     const int k64 = entk[idx];
+    if constexpr (F == 0) {
+        e.c2 *= i0;
+        e.cm *= i0;
+        e.p2 *= i1;
+        e.pm *= i1;
+    }
     if constexpr (std::is_same<T, double>::value) {
         c2 = e.c2;
         p2 = e.p2;
@@ -115,6 +127,24 @@ __device__ __forceinline__ Coef32 ld_coef(const_as<Coef32> *p)
     c.b = p->b;
     c.g = p->g;
     c.pad = 0;
+    return c;
+}
+__device__ __forceinline__ Coef64S ld_coef(const_as<Coef64S> *p)
+{
+    Coef64S c;
+    c.a = p->a;
+    c.b = p->b;
+    c.c = p->c;
+    c.ic = 1.0;
+    return c;
+}
+__device__ __forceinline__ Coef32S ld_coef(const_as<Coef32S> *p)
+{
+    Coef32S c;
+    c.a = p->a;
+    c.b = p->b;
+    c.c = p->c;
+    c.ic = 1.0f;
     return c;
 }
 __device__ __forceinline__ Coef32D ld_coef(const_as<Coef32D> *p)
@@ -189,6 +219,35 @@ __device__ __forceinline__ void rstep(const C &c, YF y, float &c2, float &p2, fl
     cm += pm;
 }
 
+// Scaled plain form (Coef64S): mu_{l+1} = (a' x +- b') mu_l - mu_{l-1}, two FMAs per spin.
+__device__ __forceinline__ void rstep_s(double a, double b, double x, double &c2, double &p2, double &cm, double &pm)
+{
+    const double n2 = fma(fma(a, x, b), c2, -p2);
+    const double nm = fma(fma(a, x, -b), cm, -pm);
+    p2 = c2;
+    c2 = n2;
+    pm = cm;
+    cm = nm;
+}
+__device__ __forceinline__ void rstep_s(float a, float b, XF x, float &c2, float &p2, float &cm, float &pm)
+{
+    const float up = fmaf(a, x.hi, fmaf(a, x.lo, b)), um = fmaf(a, x.hi, fmaf(a, x.lo, -b));
+    const float n2 = fmaf(up, c2, -p2);
+    const float nm = fmaf(um, cm, -pm);
+    p2 = c2;
+    c2 = n2;
+    pm = cm;
+    cm = nm;
+}
+__device__ __forceinline__ void rstep(const Coef64S &c, double x, double &c2, double &p2, double &cm, double &pm)
+{
+    rstep_s(c.a, c.b, x, c2, p2, cm, pm);
+}
+__device__ __forceinline__ void rstep(const Coef32S &c, XF x, float &c2, float &p2, float &cm, float &pm)
+{
+    rstep_s(c.a, c.b, x, c2, p2, cm, pm);
+}
+
 // wave-uniform "any lane"
 __device__ __forceinline__ bool wave_any(bool p) { return __ballot(p) != 0ull; }
 
@@ -200,8 +259,8 @@ __device__ __forceinline__ bool wave_any(bool p) { return __ballot(p) != 0ull; }
 //   F(m) = -(sum 2lambda (aE + i aB)),  F(-m) = -(sum -2lambda (conj aE + i conj aB)).
 // One wave handles 64*R ring pairs of one m; per-l data (alm, coefficients) are wave-uniform.
 // ================================================================================================
-// Per-(l, m) wave-uniform input of the synthesis, written by the prologue: the recurrence
-// coefficients next to the kernel-scaled alm (Im(a_l0) zeroed), one record of 8 values so that a
+// Per-(l, m) wave-uniform input of the synthesis, written by the prologue: the coefficients a', b'
+// of the scaled plain form next to c_l K_l alm (Im(a_l0) zeroed), one record of 8 values so that a
 // step is a single scalar load.  The record buffer is padded so look-ahead loads stay in bounds.
 template <typename T> struct SynRec;
 template <> struct alignas(64) SynRec<double> {
@@ -215,6 +274,14 @@ struct SynRecD {
     float a, ep, em, g, er, ei, br, bi;
 };
 template <typename T> using SynIn = SynRec<T>;
+__device__ __forceinline__ void rstep(const SynRec<double> &c, double x, double &c2, double &p2, double &cm, double &pm)
+{
+    rstep_s(c.a, c.b, x, c2, p2, cm, pm);
+}
+__device__ __forceinline__ void rstep(const SynRec<float> &c, XF x, float &c2, float &p2, float &cm, float &pm)
+{
+    rstep_s(c.a, c.b, x, c2, p2, cm, pm);
+}
 
 __device__ __forceinline__ SynRec<double> ld_rec(const_as<SynRec<double>> *p)
 {
@@ -251,20 +318,20 @@ __device__ __forceinline__ SynIn<T> syn_load(const SynRec<T> *__restrict__ rec, 
 }
 
 // Wave-uniform source of the synthesis records of form F: the prologue's records for the plain form;
-// for the FP32 difference form the coefficients come from their own table and the alm values from
-// the records.
+// for the FP32 difference form the coefficients come from their own table and the unscaled alm
+// values from the prologue's second record buffer.
 template <typename T, int F> struct SynSrc;
 template <typename T> struct SynSrc<T, 0> {
     const_as<SynRec<T>> *r;
-    __device__ __forceinline__ SynSrc(const SynRec<T> *rec, const Coef32D *) : r(uniform_ptr(rec)) {}
+    __device__ __forceinline__ SynSrc(const SynRec<T> *rec, const float4 *, const Coef32D *) : r(uniform_ptr(rec)) {}
     __device__ __forceinline__ SynRec<T> at(int i) const { return ld_rec(r + i); }
     __device__ __forceinline__ void adv(int n) { r += n; }
 };
 template <> struct SynSrc<float, 1> {
-    const_as<SynRec<float>> *r;
+    const_as<float4> *r;
     const_as<Coef32D> *c;
-    __device__ __forceinline__ SynSrc(const SynRec<float> *rec, const Coef32D *cf)
-        : r(uniform_ptr(rec)), c(uniform_ptr(cf))
+    __device__ __forceinline__ SynSrc(const SynRec<float> *, const float4 *recu, const Coef32D *cf)
+        : r(uniform_ptr(recu)), c(uniform_ptr(cf))
     {
     }
     __device__ __forceinline__ SynRecD at(int i) const
@@ -274,10 +341,10 @@ template <> struct SynSrc<float, 1> {
         o.ep = c[i].ep;
         o.em = c[i].em;
         o.g = c[i].g;
-        o.er = r[i].er;
-        o.ei = r[i].ei;
-        o.br = r[i].br;
-        o.bi = r[i].bi;
+        o.er = r[i].x;
+        o.ei = r[i].y;
+        o.br = r[i].z;
+        o.bi = r[i].w;
         return o;
     }
     __device__ __forceinline__ void adv(int n)
@@ -455,14 +522,16 @@ __global__ __launch_bounds__(256) void k_entry(const double *__restrict__ seed2,
 }
 
 // Start of a slot j whose group enters later than the wave (its values are zero until then).
+// ct: the m's row of the scaled table (1 / c_l for the entry of the scaled plain form)
 template <typename T, int R, int F>
 __device__ __forceinline__ void inject(int l, const int (&e)[R], const int (&pr)[R], const Ent64 *__restrict__ ent,
                                        const int *__restrict__ entk, int64_t row, int npairs, T (&c2)[R], T (&p2)[R],
-                                       T (&cm)[R], T (&pm)[R], int (&k)[R])
+                                       T (&cm)[R], T (&pm)[R], int (&k)[R], const_as<Coef64S> *ct)
 {
 #pragma unroll
     for (int j = 0; j < R; ++j)
-        if (e[j] == l && pr[j] < npairs) load_entry<T, F>(ent, entk, row + pr[j], c2[j], p2[j], cm[j], pm[j], k[j]);
+        if (e[j] == l && pr[j] < npairs)
+            load_entry<T, F>(ent, entk, row + pr[j], c2[j], p2[j], cm[j], pm[j], k[j], ct[l].ic, ct[l - 1].ic);
 }
 
 template <int R> __device__ __forceinline__ bool pending(int l, int lmax, const int (&e)[R])
@@ -476,6 +545,7 @@ template <int R> __device__ __forceinline__ bool pending(int l, int lmax, const 
 // Waves gbeg .. gend-1 (wave w holds the 64-pair groups w R .. w R + R - 1) of every m.
 template <typename T, int R, int V, int F>
 __global__ __launch_bounds__(256) void k_leg_synth(const SynRec<T> *__restrict__ recs, int64_t rec_stride,
+                                                   const float4 *__restrict__ recus, const Coef64S *__restrict__ cs64,
                                                    const Coef32D *__restrict__ coefd, cplx<T> *__restrict__ FG,
                                                    int64_t fg_stride, const Ent64 *__restrict__ ent,
                                                    const int *__restrict__ entk, const int *__restrict__ entl,
@@ -492,8 +562,10 @@ __global__ __launch_bounds__(256) void k_leg_synth(const SynRec<T> *__restrict__
     const int l0 = m > 2 ? m : 2;
     const int64_t base = (int64_t)m * (2 * lmax + 1 - m) / 2;
     const SynRec<T> *rec = recs + rhs * rec_stride + base;
+    const float4 *recu = F ? recus + rhs * rec_stride + base : nullptr;
     const Coef32D *cfd = coefd + base;
-    const SynSrc<T, F> src(rec, cfd);
+    const_as<Coef64S> *ct = uniform_ptr(cs64 + base);
+    const SynSrc<T, F> src(rec, recu, cfd);
     auto rload = [&](int i) {
         if constexpr (F == 0) return rec[i];
         else return src.at(i);
@@ -523,7 +595,8 @@ __global__ __launch_bounds__(256) void k_leg_synth(const SynRec<T> *__restrict__
         k[j] = 0;
         if (p < npairs) {
             setpos(x[j], pair_z[p]);
-            if (e[j] == ls && ls <= lmax) load_entry<T, F>(ent, entk, row + p, c2[j], p2[j], cm[j], pm[j], k[j]);
+            if (e[j] == ls && ls <= lmax)
+                load_entry<T, F>(ent, entk, row + p, c2[j], p2[j], cm[j], pm[j], k[j], ct[ls].ic, ct[ls - 1].ic);
         }
         neg |= (k[j] < 0);
 #pragma unroll
@@ -537,12 +610,12 @@ __global__ __launch_bounds__(256) void k_leg_synth(const SynRec<T> *__restrict__
     bool ramp = wave_any(neg);
     constexpr int S = V == 0 ? 2 : 4;
     int l = __builtin_amdgcn_readfirstlane(ls <= lmax ? ls : lmax + 1);
-    SynSrc<T, F> rp(rec + l, cfd + l);
+    SynSrc<T, F> rp(rec + l, F ? recu + l : nullptr, cfd + l);
     auto a0 = rp.at(0), a1 = rp.at(1), b0 = a0, b1 = a1;
     for (; l + S - 1 <= lmax; l += S, rp.adv(S)) {
         if (pend) {
             // a slot enters at its group's entry degree (entries are l0 + 8q, trips start at ls + S q)
-            inject<T, R, F>(l, e, pr, ent, entk, row, npairs, c2, p2, cm, pm, k);
+            inject<T, R, F>(l, e, pr, ent, entk, row, npairs, c2, p2, cm, pm, k, ct);
             pend = pending<R>(l, lmax, e);
             bool ng = false;
 #pragma unroll
@@ -568,7 +641,7 @@ __global__ __launch_bounds__(256) void k_leg_synth(const SynRec<T> *__restrict__
     }
     // tail (fewer than S steps)
     for (int t = 0; l <= lmax; ++l, ++t) {
-        if (pend) inject<T, R, F>(l, e, pr, ent, entk, row, npairs, c2, p2, cm, pm, k);
+        if (pend) inject<T, R, F>(l, e, pr, ent, entk, row, npairs, c2, p2, cm, pm, k, ct);
         if (t & 1) syn_step<T, R, false>(rload(l), x, c2, p2, cm, pm, k, acc1);
         else syn_step<T, R, false>(rload(l), x, c2, p2, cm, pm, k, acc0);
     }
@@ -653,11 +726,49 @@ __device__ __forceinline__ void adj_step(const C &c, const X (&x)[R], T (&c2)[R]
     out[3] = a3;
 }
 
+// LDS hand-over between the lanes of a workgroup.  A single-wave workgroup needs no s_barrier: the
+// LDS unit executes one wave's instructions in order, so a fence that keeps the compiler from moving
+// LDS accesses across it suffices, and no full wait for outstanding LDS operations is forced.
+// value of lane l ^ 1, l ^ 2 (DPP quad permutations) and of the mirrored lane in the half-row of
+// 8 or the row of 16 lanes (row_half_mirror, row_mirror)
+template <int CTRL> __device__ __forceinline__ float dpp_mov(float v)
+{
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+template <int CTRL> __device__ __forceinline__ double dpp_mov(double v)
+{
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+// sum over the aligned group of G lanes (G = 1, 2, 4, 8, 16), in every lane of the group
+template <int G, typename T> __device__ __forceinline__ T group_sum(T s)
+{
+    static_assert(G == 1 || G == 2 || G == 4 || G == 8 || G == 16, "group size");
+    if constexpr (G >= 2) s += dpp_mov<0xB1>(s);   // quad_perm [1, 0, 3, 2]
+    if constexpr (G >= 4) s += dpp_mov<0x4E>(s);   // quad_perm [2, 3, 0, 1]
+    if constexpr (G >= 8) s += dpp_mov<0x141>(s);  // row_half_mirror: lane 7 - i of the half-row
+    if constexpr (G >= 16) s += dpp_mov<0x140>(s); // row_mirror: lane 15 - i of the row
+    return s;
+}
+
+template <int W> __device__ __forceinline__ void wg_lds_sync()
+{
+    if constexpr (W == 1) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
 // Workgroups rb0 .. rb0 + nrbl - 1 of the nrb ring blocks of every m; this launch's workgroup rbl
 // holds the 64-pair groups g0 + rbl W R .. g0 + (rbl + 1) W R - 1, bounded by gend.
 template <typename T, int R, int W, int L, int F>
 __global__ __launch_bounds__(64 * W) void k_leg_adj(const cplx<T> *__restrict__ FG,
                                                     const typename CoefT<T, F>::type *__restrict__ coef,
+                                                    const Coef64S *__restrict__ cs64,
                                                     const Ent64 *__restrict__ ent, const int *__restrict__ entk,
                                                     const int *__restrict__ entl, int ng64,
                                                     const double *__restrict__ pair_z, T *__restrict__ part,
@@ -680,6 +791,7 @@ __global__ __launch_bounds__(64 * W) void k_leg_adj(const cplx<T> *__restrict__ 
     const int l0 = m > 2 ? m : 2;
     const int64_t base = (int64_t)m * (2 * lmax + 1 - m) / 2;
     const auto *cf = coef + base;
+    const_as<Coef64S> *ct = uniform_ptr(cs64 + base);
     const T sgn0 = ((l0 + m) & 1) ? (T)-1 : (T)1;
 
     // entry degrees of the workgroup's 64-pair groups: the workgroup starts at the earliest, a slot
@@ -714,7 +826,8 @@ __global__ __launch_bounds__(64 * W) void k_leg_adj(const cplx<T> *__restrict__ 
         k[j] = 0;
         if (p < pb) {
             setpos(x[j], pair_z[p]);
-            if (e[j] == ls) load_entry<T, F>(ent, entk, row + p, c2[j], p2[j], cm[j], pm[j], k[j]);
+            if (e[j] == ls)
+                load_entry<T, F>(ent, entk, row + p, c2[j], p2[j], cm[j], pm[j], k[j], ct[ls].ic, ct[ls - 1].ic);
         }
         neg |= (k[j] < 0);
     }
@@ -754,7 +867,7 @@ __global__ __launch_bounds__(64 * W) void k_leg_adj(const cplx<T> *__restrict__ 
     for (int li = 0; li < L; ++li) cc[li] = ld_coef(cp + li);
     for (int lc = ls; lc <= lmax; lc += L, cp += L) {
         if (pend) {
-            inject<T, R, F>(lc, e, pr, ent, entk, row, pb, c2, p2, cm, pm, k);
+            inject<T, R, F>(lc, e, pr, ent, entk, row, pb, c2, p2, cm, pm, k, ct);
             bool ng = false;
 #pragma unroll
             for (int j = 0; j < R; ++j) {
@@ -764,6 +877,11 @@ __global__ __launch_bounds__(64 * W) void k_leg_adj(const cplx<T> *__restrict__ 
             ramp = ramp || wave_any(ng);
             pend = pending<R>(lc, lmax, e);
         }
+        // the next chunk's coefficients (scalar loads) are issued before this chunk's steps: they
+        // share the LDS wait counter, and must have arrived by the time the reduction waits on LDS
+        C nc[L];
+#pragma unroll
+        for (int li = 0; li < L; ++li) nc[li] = ld_coef(cp + L + li);
         // all L steps unmasked: rows past lmax (last chunk) are reduced but not stored, and the
         // coefficient table is padded past its last column
 #pragma unroll
@@ -776,21 +894,27 @@ __global__ __launch_bounds__(64 * W) void k_leg_adj(const cplx<T> *__restrict__ 
 #pragma unroll
             for (int c = 0; c < 4; ++c) red[((wave * L + li + 1) * 4 + c) * CS + lane] = out[c];
         }
-        // the next chunk's coefficients load while the chunk is reduced
-        C nc[L];
+        wg_lds_sync<W>();
+        // column sums over the workgroup's lanes: thread (o, gi) reads the entries q = gi + G t of
+        // column o (wave q / 64, lane q % 64) at compile-time offsets from its column base, all
+        // reads first, adds them in four independent partial sums, then sums over the G adjacent
+        // threads sharing the output with DPP lane moves
+        T rv[NT / G];
 #pragma unroll
-        for (int li = 0; li < L; ++li) nc[li] = ld_coef(cp + L + li);
-        __syncthreads();
-        // column sums over the workgroup's lanes: thread (o, gi) adds the entries q = gi + G t of
-        // column o (wave q / 64, lane q % 64) at compile-time offsets from its column base, in four
-        // independent partial sums, then a butterfly over the G threads sharing the output
-        T ps[4] = {0, 0, 0, 0};
+        for (int u = 0; u < NT / G; ++u) rv[u] = col[(G * u / 64) * (L * 4 * CS) + (G * u) % 64];
+        static_assert(NT / G >= 4, "four partial sums");
+        T ps[4] = {rv[0], rv[1], rv[2], rv[3]};
 #pragma unroll
-        for (int u = 0; u < NT / G; ++u) ps[u & 3] += col[(G * u / 64) * (L * 4 * CS) + (G * u) % 64];
-        T s = (ps[0] + ps[1]) + (ps[2] + ps[3]);
+        for (int u = 4; u < NT / G; ++u) ps[u & 3] += rv[u];
+        const T s = group_sum<G>((ps[0] + ps[1]) + (ps[2] + ps[3]));
+        // the scaled plain form sums mu: the output of degree lc + oli is c_l times the sum
+        T sc = (T)1;
+        if constexpr (F == 0) {
 #pragma unroll
-        for (int off = G >> 1; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-        if (gi == 0 && lc + oli <= lmax) pout[(int64_t)(lc - ls) * 4] = s;
+            for (int li = 0; li < L; ++li)
+                if (oli == li) sc = cc[li].c;
+        }
+        if (gi == 0 && lc + oli <= lmax) pout[(int64_t)(lc - ls) * 4] = s * sc;
 #pragma unroll
         for (int li = 0; li < L; ++li) cc[li] = nc[li];
         if (ramp) {
@@ -815,17 +939,20 @@ __global__ __launch_bounds__(64 * W) void k_leg_adj(const cplx<T> *__restrict__ 
             }
             ramp = wave_any(any_neg);
         }
-        __syncthreads();
+        wg_lds_sync<W>();
     }
 }
 
 // ================================================================================================
 // prologue / epilogue / weights
 // ================================================================================================
+// records of the scaled plain form (c_l K_l alm, FP64 products) and, when recu is given, the
+// unscaled K_l alm for the difference form
 template <typename T>
 __global__ void k_prologue(const double *__restrict__ xE, const double *__restrict__ xB, const double *__restrict__ kern,
-                           const int *__restrict__ lof, const typename CoefT<T, 0>::type *__restrict__ coef, int lmax,
-                           int64_t nalm, int64_t rec_stride, SynRec<T> *__restrict__ rec)
+                           const int *__restrict__ lof, const typename CoefT<T, 0>::type *__restrict__ coef,
+                           const Coef64S *__restrict__ cs64, int lmax, int64_t nalm, int64_t rec_stride,
+                           SynRec<T> *__restrict__ rec, float4 *__restrict__ recu)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int rhs = blockIdx.y;
@@ -834,16 +961,20 @@ __global__ void k_prologue(const double *__restrict__ xE, const double *__restri
     const double K = kern ? kern[lof[i]] : 1.0;
     const bool m0 = i <= lmax;
     const auto c = coef[i];
+    const double er = K * xE[2 * o], ei = m0 ? 0.0 : K * xE[2 * o + 1];
+    const double br = K * xB[2 * o], bi = m0 ? 0.0 : K * xB[2 * o + 1];
+    const double s = cs64[i].c;
     SynRec<T> r;
     r.a = c.a;
     r.b = c.b;
-    r.g = c.g;
+    r.g = (T)0;
     r.pad = (T)0;
-    r.er = (T)(K * xE[2 * o]);
-    r.ei = m0 ? (T)0 : (T)(K * xE[2 * o + 1]);
-    r.br = (T)(K * xB[2 * o]);
-    r.bi = m0 ? (T)0 : (T)(K * xB[2 * o + 1]);
+    r.er = (T)(s * er);
+    r.ei = (T)(s * ei);
+    r.br = (T)(s * br);
+    r.bi = (T)(s * bi);
     rec[rhs * rec_stride + i] = r;
+    if (recu) recu[rhs * rec_stride + i] = make_float4((float)er, (float)ei, (float)br, (float)bi);
 }
 
 // m of the alm index i = m (2 lmax + 1 - m)/2 + l
@@ -959,40 +1090,84 @@ template <typename T> __device__ __forceinline__ cplx<T> chirp(int n, int L)
     return cconj<T>(cis_pi<T>(((int64_t)n * n) % (2 * (int64_t)L), L));
 }
 
-// in-place radix-2 FFT, bit-reversed input -> natural output; sign -1: e^{-2 pi i/M}
+// (-+ i) z for sign -1 / +1: the twiddle W_4^{+-1} of a radix-4 step
+template <typename T> __device__ __forceinline__ cplx<T> rot4(cplx<T> z, int sign)
+{
+    return sign < 0 ? mk<T>(z.y, -z.x) : mk<T>(-z.y, z.x);
+}
+
+// In-place FFT of length M (a power of two) in LDS, bit-reversed input -> natural output, sign -1:
+// e^{-2 pi i/M}.  Two radix-2 stages h, 2h are done as one radix-4 step on the elements i0 + {0, h,
+// 2h, 3h} (twiddles u = W_{4h}^pos and u^2 = W_{2h}^pos from the table), so a length-M transform
+// takes ceil(log2 M / 2) passes through LDS; an odd log2 M starts with one radix-2 stage.
 template <typename T>
 __device__ void fft_dit(cplx<T> *buf, int M, const cplx<T> *__restrict__ tw, int twn, int sign)
 {
-    for (int h = 1; h < M; h <<= 1) {
-        const int stride = twn / (2 * h);
-        for (int bI = threadIdx.x; bI < M / 2; bI += RT) {
-            const int pos = bI & (h - 1);
-            const int i0 = pd(((bI - pos) << 1) + pos), i1 = pd(((bI - pos) << 1) + pos + h);
-            cplx<T> w = tw[pos * stride];
-            if (sign > 0) w.y = -w.y;
-            const cplx<T> t = cmul<T>(w, buf[i1]);
-            const cplx<T> a = buf[i0];
-            buf[i0] = cadd<T>(a, t);
-            buf[i1] = csub<T>(a, t);
+    const int logM = 31 - __builtin_clz(M);
+    int h = 1;
+    if (logM & 1) {
+        for (int b = threadIdx.x; b < M / 2; b += RT) {
+            const cplx<T> a = buf[pd(2 * b)], c = buf[pd(2 * b + 1)];
+            buf[pd(2 * b)] = cadd<T>(a, c);
+            buf[pd(2 * b + 1)] = csub<T>(a, c);
+        }
+        __syncthreads();
+        h = 2;
+    }
+    for (; h < M; h <<= 2) {
+        const int s4 = twn / (4 * h);
+        for (int b = threadIdx.x; b < M / 4; b += RT) {
+            const int pos = b & (h - 1);
+            const int i0 = ((b - pos) << 2) + pos;
+            cplx<T> u = tw[pos * s4], w = tw[2 * pos * s4];
+            if (sign > 0) {
+                u.y = -u.y;
+                w.y = -w.y;
+            }
+            const cplx<T> a0 = buf[pd(i0)], a1 = buf[pd(i0 + h)], a2 = buf[pd(i0 + 2 * h)], a3 = buf[pd(i0 + 3 * h)];
+            const cplx<T> t1 = cmul<T>(w, a1), t3 = cmul<T>(w, a3);
+            const cplx<T> b0 = cadd<T>(a0, t1), b1 = csub<T>(a0, t1), b2 = cadd<T>(a2, t3), b3 = csub<T>(a2, t3);
+            const cplx<T> x2 = cmul<T>(u, b2), y3 = rot4<T>(cmul<T>(u, b3), sign);
+            buf[pd(i0)] = cadd<T>(b0, x2);
+            buf[pd(i0 + 2 * h)] = csub<T>(b0, x2);
+            buf[pd(i0 + h)] = cadd<T>(b1, y3);
+            buf[pd(i0 + 3 * h)] = csub<T>(b1, y3);
         }
         __syncthreads();
     }
 }
 
-// in-place radix-2 FFT, natural input -> bit-reversed output
+// In-place FFT, natural input -> bit-reversed output: the radix-2 stages h = M/2 .. 1 in pairs
+// (2h, h) as radix-4 steps; an odd log2 M ends with the radix-2 stage h = 1.
 template <typename T>
 __device__ void fft_dif(cplx<T> *buf, int M, const cplx<T> *__restrict__ tw, int twn, int sign)
 {
-    for (int h = M >> 1; h >= 1; h >>= 1) {
-        const int stride = twn / (2 * h);
-        for (int bI = threadIdx.x; bI < M / 2; bI += RT) {
-            const int pos = bI & (h - 1);
-            const int i0 = pd(((bI - pos) << 1) + pos), i1 = pd(((bI - pos) << 1) + pos + h);
-            cplx<T> w = tw[pos * stride];
-            if (sign > 0) w.y = -w.y;
-            const cplx<T> a = buf[i0], c = buf[i1];
-            buf[i0] = cadd<T>(a, c);
-            buf[i1] = cmul<T>(csub<T>(a, c), w);
+    int h = M >> 2;
+    for (; h >= 1; h >>= 2) {
+        const int s4 = twn / (4 * h);
+        for (int b = threadIdx.x; b < M / 4; b += RT) {
+            const int pos = b & (h - 1);
+            const int i0 = ((b - pos) << 2) + pos;
+            cplx<T> u = tw[pos * s4], w = tw[2 * pos * s4];
+            if (sign > 0) {
+                u.y = -u.y;
+                w.y = -w.y;
+            }
+            const cplx<T> a0 = buf[pd(i0)], a1 = buf[pd(i0 + h)], a2 = buf[pd(i0 + 2 * h)], a3 = buf[pd(i0 + 3 * h)];
+            const cplx<T> b0 = cadd<T>(a0, a2), b2 = cmul<T>(csub<T>(a0, a2), u);
+            const cplx<T> b1 = cadd<T>(a1, a3), b3 = rot4<T>(cmul<T>(csub<T>(a1, a3), u), sign);
+            buf[pd(i0)] = cadd<T>(b0, b1);
+            buf[pd(i0 + h)] = cmul<T>(csub<T>(b0, b1), w);
+            buf[pd(i0 + 2 * h)] = cadd<T>(b2, b3);
+            buf[pd(i0 + 3 * h)] = cmul<T>(csub<T>(b2, b3), w);
+        }
+        __syncthreads();
+    }
+    if ((31 - __builtin_clz(M)) & 1) {
+        for (int b = threadIdx.x; b < M / 2; b += RT) {
+            const cplx<T> a = buf[pd(2 * b)], c = buf[pd(2 * b + 1)];
+            buf[pd(2 * b)] = cadd<T>(a, c);
+            buf[pd(2 * b + 1)] = csub<T>(a, c);
         }
         __syncthreads();
     }
@@ -1301,7 +1476,7 @@ __device__ __forceinline__ float quad_sum(float v)
 
 template <int F>
 __global__ __launch_bounds__(256) void k_leg_synth_b(const float *__restrict__ brec,
-                                                     const typename CoefT<float, F>::type *__restrict__ coef,
+                                                     const typename CoefB<F>::type *__restrict__ coef,
                                                      float2 *__restrict__ FG, int64_t fg_stride,
                                                      const Ent64 *__restrict__ ent, const int *__restrict__ entk,
                                                      const int *__restrict__ entl, int ng64,
@@ -1331,7 +1506,7 @@ __global__ __launch_bounds__(256) void k_leg_synth_b(const float *__restrict__ b
 #pragma unroll
     for (int r = 0; r < 16; ++r) D2e[r] = D2o[r] = Dme[r] = Dmo[r] = 0.f;
     bool ramp = wave_any(k < 0);
-    using C = typename CoefT<float, F>::type;
+    using C = typename CoefB<F>::type;
     const_as<C> *cp = uniform_ptr(coef + base);
     const float *bl = brec + base * (NBR * 4) + i;  // column i of the group's records
     for (int l = ls; l <= lmax; l += 4) {
@@ -1404,11 +1579,11 @@ void launch_prologue(Plan &P, bool fp32, const double *xE, const double *xB, con
 {
     dim3 g((unsigned)cdiv(P.nalm, 256), nrhs);
     if (fp32)
-        k_prologue<float><<<g, 256, 0, P.stream>>>(xE, xB, kern, P.d_lof, P.d_coef32, P.lmax, P.nalm, P.rec_stride,
-                                                   (SynRec<float> *)P.d_rec);
+        k_prologue<float><<<g, 256, 0, P.stream>>>(xE, xB, kern, P.d_lof, P.d_coef32s, P.d_coef64s, P.lmax, P.nalm,
+                                                   P.rec_stride, (SynRec<float> *)P.d_rec, P.d_recu);
     else
-        k_prologue<double><<<g, 256, 0, P.stream>>>(xE, xB, kern, P.d_lof, P.d_coef64, P.lmax, P.nalm, P.rec_stride,
-                                                    (SynRec<double> *)P.d_rec);
+        k_prologue<double><<<g, 256, 0, P.stream>>>(xE, xB, kern, P.d_lof, P.d_coef64s, P.d_coef64s, P.lmax, P.nalm,
+                                                    P.rec_stride, (SynRec<double> *)P.d_rec, nullptr);
 }
 
 // synthesis waves over the 64-pair groups [g0, g1) (g0 a multiple of R)
@@ -1420,7 +1595,8 @@ static void syn_launch(Plan &P, int nrhs, int64_t fg_stride, int g0, int g1)
     const int nbm = (int)cdiv(gend - gbeg, 4);  // blocks of four waves per m
     const int64_t blocks = 8 * nbm * cdiv(P.lmax + 1, 8);
     dim3 g((unsigned)blocks, nrhs);
-    k_leg_synth<T, R, V, F><<<g, 256, 0, P.stream>>>((const SynRec<T> *)P.d_rec, P.rec_stride, P.d_coef32d,
+    k_leg_synth<T, R, V, F><<<g, 256, 0, P.stream>>>((const SynRec<T> *)P.d_rec, P.rec_stride, P.d_recu,
+                                                     P.d_coef64s, P.d_coef32d,
                                                      (cplx<T> *)P.d_FG, fg_stride, P.d_ent, P.d_entk, P.d_entl,
                                                       P.ng64, P.d_pair_z, P.lmax, P.npairs, P.nrings, gbeg, gend,
                                                       nbm);
@@ -1492,12 +1668,13 @@ static void adj_launch(Plan &P, int rhs, int g0, int g1, int rb0)
     const int nrbl = (int)cdiv(g1 - g0, W * R);
     if (nrbl <= 0) return;
     const int64_t fg_stride = (int64_t)P.nrings * (P.lmax + 1) * 2;
-    const void *coef = std::is_same<T, double>::value ? (const void *)P.d_coef64
+    const void *coef = std::is_same<T, double>::value ? (const void *)P.d_coef64s
                        : F                              ? (const void *)P.d_coef32d
-                                                        : (const void *)P.d_coef32;
+                                                        : (const void *)P.d_coef32s;
     dim3 g((unsigned)(8 * nrbl * cdiv(P.lmax + 1, 8)));
     k_leg_adj<T, R, W, L, F><<<g, 64 * W, 0, P.stream>>>(
-        (const cplx<T> *)P.d_FG + rhs * fg_stride, (const typename CoefT<T, F>::type *)coef, P.d_ent, P.d_entk,
+        (const cplx<T> *)P.d_FG + rhs * fg_stride, (const typename CoefT<T, F>::type *)coef, P.d_coef64s, P.d_ent,
+        P.d_entk,
         P.d_entl, P.ng64, P.d_pair_z, (T *)P.d_part, P.d_wgstart, P.nalm, P.lmax, P.npairs, P.nrings, g0, g1, rb0,
         nrbl, P.adj_nrb);
 }

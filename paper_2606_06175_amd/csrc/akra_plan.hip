@@ -95,17 +95,23 @@ static void build_rings(Plan &P)
 //   g_l = (l+1) R_l sqrt((2l+3)/(2l-1)) / (l R_{l+1}),   R_l = sqrt((l^2 - m^2)(l^2 - 4)).
 // ---------------------------------------------------------------------------------------------
 // Entries past the last column (ALM_PAD) keep the kernels' look-ahead loads in bounds.
-static void build_coef(int lmax, std::vector<Coef64> &c64, std::vector<Coef32> &c32, std::vector<Coef32D> &c32d)
+// The scaled form (Coef64S) divides out c_l with c_{l0} = c_{l0+1} = 1, c_{l+1} = g_l c_{l-1}: entries
+// below l0 and the padding carry c = 1, the entry at lmax its c with a' = b' = 0.
+static void build_coef(int lmax, std::vector<Coef64> &c64, std::vector<Coef32> &c32, std::vector<Coef32D> &c32d,
+                       std::vector<Coef64S> &c64s, std::vector<Coef32S> &c32s)
 {
     const int64_t nalm = (int64_t)(lmax + 1) * (lmax + 2) / 2;
     c64.assign(nalm + ALM_PAD, Coef64{0, 0, 0, 0});
     c32.assign(nalm + ALM_PAD, Coef32{0, 0, 0, 0});
     c32d.assign(nalm + ALM_PAD, Coef32D{0, 0, 0, 0});
+    c64s.assign(nalm + ALM_PAD, Coef64S{0, 0, 1, 1});
+    c32s.assign(nalm + ALM_PAD, Coef32S{0, 0, 1, 1});
     parallel_for(lmax + 1, [&](int m) {
         const int64_t base = (int64_t)m * (2 * lmax + 1 - m) / 2;
         const int l0 = std::max(m, 2);
         typedef long double ld;
         auto R = [&](int l) { return sqrtl(((ld)l * l - (ld)m * m) * ((ld)l * l - 4.0L)); };
+        std::vector<ld> cs(lmax + 2, 1.0L);  // c_l, l0 <= l <= lmax
         for (int l = l0; l < lmax; ++l) {
             const ld L = l;
             const ld r1 = R(l + 1), r0 = R(l);
@@ -116,7 +122,13 @@ static void build_coef(int lmax, std::vector<Coef64> &c64, std::vector<Coef32> &
             c64[base + l] = Coef64{(double)a, (double)b, (double)g, 0.0};
             c32[base + l] = Coef32{(float)a, (float)b, (float)g, 0.0f};
             c32d[base + l] = Coef32D{(float)a, (float)(a + b - g - 1), (float)(a - b - g - 1), (float)g};
+            if (l > l0) cs[l + 1] = g * cs[l - 1];
+            const ld f = cs[l] / cs[l + 1];
+            c64s[base + l] = Coef64S{(double)(a * f), (double)(b * f), (double)cs[l], (double)(1.0L / cs[l])};
+            c32s[base + l] = Coef32S{(float)(a * f), (float)(b * f), (float)cs[l], (float)(1.0L / cs[l])};
         }
+        c64s[base + lmax] = Coef64S{0.0, 0.0, (double)cs[lmax], (double)(1.0L / cs[lmax])};
+        c32s[base + lmax] = Coef32S{0.0f, 0.0f, (float)cs[lmax], (float)(1.0L / cs[lmax])};
     });
 }
 
@@ -229,7 +241,8 @@ static void default_kernel(int lmax, std::vector<double> &k)
 
 static void free_plan(Plan *P)
 {
-    void *ptrs[] = {P->d_rings, P->d_pair_z, P->d_coef64, P->d_coef32, P->d_seed2, P->d_seedm2, P->d_seedk,
+    void *ptrs[] = {P->d_rings, P->d_pair_z, P->d_coef64, P->d_coef32, P->d_coef64s, P->d_coef32s, P->d_recu,
+                    P->d_seed2, P->d_seedm2, P->d_seedk,
                     P->d_ent, P->d_entk, P->d_entl, P->d_wgstart, P->d_coef32d, P->d_brec,
                     P->d_tw64, P->d_tw32, P->d_bhat64, P->d_bhat32, P->d_lof, P->d_order_p2, P->d_order_bl, P->d_FG, P->d_part, P->d_rec, P->d_W, P->d_kern, P->d_kuser, P->d_red, P->d_scal, P->d_flag, P->d_x, P->d_r,
                     P->d_p, P->d_w, P->d_b, P->d_xs};
@@ -349,9 +362,13 @@ static akra_status create(int nside, int lmax, int nrhs, int prec, void *stream,
         std::vector<Coef64> c64;
         std::vector<Coef32> c32;
         std::vector<Coef32D> c32d;
-        build_coef(lmax, c64, c32, c32d);
+        std::vector<Coef64S> c64s;
+        std::vector<Coef32S> c32s;
+        build_coef(lmax, c64, c32, c32d, c64s, c32s);
         AK_TRY(upload((void **)&P->d_coef64, c64.data(), c64.size() * sizeof(Coef64), *P));
         AK_TRY(upload((void **)&P->d_coef32, c32.data(), c32.size() * sizeof(Coef32), *P));
+        AK_TRY(upload((void **)&P->d_coef64s, c64s.data(), c64s.size() * sizeof(Coef64S), *P));
+        AK_TRY(upload((void **)&P->d_coef32s, c32s.data(), c32s.size() * sizeof(Coef32S), *P));
         AK_TRY(upload((void **)&P->d_coef32d, c32d.data(), c32d.size() * sizeof(Coef32D), *P));
     }
     {
@@ -445,6 +462,14 @@ static akra_status create(int nside, int lmax, int nrhs, int prec, void *stream,
     compute_work(*P);
     P->rec_stride = P->nalm + ALM_PAD;
     AK_TRY(alloc(&P->d_rec, (size_t)nrhs * P->rec_stride * 64, *P));
+    if (prec == AKRA_FP32 && P->polar_groups > 0) {
+        AK_TRY(alloc((void **)&P->d_recu, (size_t)nrhs * P->rec_stride * sizeof(float4), *P));
+        if (hipMemset(P->d_recu, 0, (size_t)nrhs * P->rec_stride * sizeof(float4)) != hipSuccess) {
+            free_plan(P);
+            set_error("hipMemset failed");
+            return AKRA_ERR_HIP;
+        }
+    }
     if (prec == AKRA_FP32 && nrhs > 1) AK_TRY(alloc((void **)&P->d_brec, (size_t)P->rec_stride * 8 * 4 * sizeof(float), *P));
     if (hipMemset(P->d_rec, 0, (size_t)nrhs * P->rec_stride * 64) != hipSuccess) {
         free_plan(P);
