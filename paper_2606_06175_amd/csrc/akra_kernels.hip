@@ -129,13 +129,13 @@ __device__ __forceinline__ Coef32 ld_coef(const_as<Coef32> *p)
     c.pad = 0;
     return c;
 }
+// the recurrence reads a' and b' only (scalar registers are scarce in the adjoint's look-ahead)
 __device__ __forceinline__ Coef64S ld_coef(const_as<Coef64S> *p)
 {
     Coef64S c;
     c.a = p->a;
     c.b = p->b;
-    c.c = p->c;
-    c.ic = 1.0;
+    c.c = c.ic = 0.0;
     return c;
 }
 __device__ __forceinline__ Coef32S ld_coef(const_as<Coef32S> *p)
@@ -143,8 +143,7 @@ __device__ __forceinline__ Coef32S ld_coef(const_as<Coef32S> *p)
     Coef32S c;
     c.a = p->a;
     c.b = p->b;
-    c.c = p->c;
-    c.ic = 1.0f;
+    c.c = c.ic = 0.0f;
     return c;
 }
 __device__ __forceinline__ Coef32D ld_coef(const_as<Coef32D> *p)
@@ -726,6 +725,13 @@ __device__ __forceinline__ void adj_step(const C &c, const X (&x)[R], T (&c2)[R]
     out[3] = a3;
 }
 
+// Occupancy the adjoint is compiled for (waves per SIMD): the FP64 form with four ring pairs per
+// lane would otherwise use about 175 registers and run two waves per SIMD, too few to hide its LDS
+// round trips; at three the compiler spills only registers of the rarely taken group-entry path.
+// Eight pairs per lane cannot fit three waves without spilling in the inner loop: no target there.
+template <typename T, int R> struct AdjWaves {
+    static constexpr int value = R > 4 ? 1 : std::is_same<T, double>::value ? 3 : 4;
+};
 // LDS hand-over between the lanes of a workgroup.  A single-wave workgroup needs no s_barrier: the
 // LDS unit executes one wave's instructions in order, so a fence that keeps the compiler from moving
 // LDS accesses across it suffices, and no full wait for outstanding LDS operations is forced.
@@ -766,7 +772,7 @@ template <int W> __device__ __forceinline__ void wg_lds_sync()
 // Workgroups rb0 .. rb0 + nrbl - 1 of the nrb ring blocks of every m; this launch's workgroup rbl
 // holds the 64-pair groups g0 + rbl W R .. g0 + (rbl + 1) W R - 1, bounded by gend.
 template <typename T, int R, int W, int L, int F>
-__global__ __launch_bounds__(64 * W) void k_leg_adj(const cplx<T> *__restrict__ FG,
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(AdjWaves<T, R>::value))) void k_leg_adj(const cplx<T> *__restrict__ FG,
                                                     const typename CoefT<T, F>::type *__restrict__ coef,
                                                     const Coef64S *__restrict__ cs64,
                                                     const Ent64 *__restrict__ ent, const int *__restrict__ entk,
@@ -882,6 +888,9 @@ __global__ __launch_bounds__(64 * W) void k_leg_adj(const cplx<T> *__restrict__ 
         C nc[L];
 #pragma unroll
         for (int li = 0; li < L; ++li) nc[li] = ld_coef(cp + L + li);
+        // c_l of this thread's output row for the scaled plain form (a vector load, used at the store)
+        T sc = (T)1;
+        if constexpr (F == 0) sc = cf[lc + oli < lmax ? lc + oli : lmax].c;
         // all L steps unmasked: rows past lmax (last chunk) are reduced but not stored, and the
         // coefficient table is padded past its last column
 #pragma unroll
@@ -899,21 +908,23 @@ __global__ __launch_bounds__(64 * W) void k_leg_adj(const cplx<T> *__restrict__ 
         // column o (wave q / 64, lane q % 64) at compile-time offsets from its column base, all
         // reads first, adds them in four independent partial sums, then sums over the G adjacent
         // threads sharing the output with DPP lane moves
-        T rv[NT / G];
+        // (in batches of 8 reads, which bounds the registers they hold)
+        constexpr int NR = NT / G, BR = NR < 8 ? NR : 8;
+        static_assert(NR >= 4 && NR % BR == 0, "four partial sums");
+        T ps[4];
 #pragma unroll
-        for (int u = 0; u < NT / G; ++u) rv[u] = col[(G * u / 64) * (L * 4 * CS) + (G * u) % 64];
-        static_assert(NT / G >= 4, "four partial sums");
-        T ps[4] = {rv[0], rv[1], rv[2], rv[3]};
+        for (int b0 = 0; b0 < NR; b0 += BR) {
+            T rv[BR];
 #pragma unroll
-        for (int u = 4; u < NT / G; ++u) ps[u & 3] += rv[u];
+            for (int u = 0; u < BR; ++u) rv[u] = col[(G * (b0 + u) / 64) * (L * 4 * CS) + (G * (b0 + u)) % 64];
+#pragma unroll
+            for (int u = 0; u < BR; ++u) {
+                if (b0 + u < 4) ps[u] = rv[u];
+                else ps[(b0 + u) & 3] += rv[u];
+            }
+        }
         const T s = group_sum<G>((ps[0] + ps[1]) + (ps[2] + ps[3]));
         // the scaled plain form sums mu: the output of degree lc + oli is c_l times the sum
-        T sc = (T)1;
-        if constexpr (F == 0) {
-#pragma unroll
-            for (int li = 0; li < L; ++li)
-                if (oli == li) sc = cc[li].c;
-        }
         if (gi == 0 && lc + oli <= lmax) pout[(int64_t)(lc - ls) * 4] = s * sc;
 #pragma unroll
         for (int li = 0; li < L; ++li) cc[li] = nc[li];
