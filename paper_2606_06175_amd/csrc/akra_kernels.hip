@@ -1111,13 +1111,13 @@ template <typename T> __device__ __forceinline__ cplx<T> rot4(cplx<T> z, int sig
 // e^{-2 pi i/M}.  Two radix-2 stages h, 2h are done as one radix-4 step on the elements i0 + {0, h,
 // 2h, 3h} (twiddles u = W_{4h}^pos and u^2 = W_{2h}^pos from the table), so a length-M transform
 // takes ceil(log2 M / 2) passes through LDS; an odd log2 M starts with one radix-2 stage.
-template <typename T>
+template <typename T, int NT = RT>
 __device__ void fft_dit(cplx<T> *buf, int M, const cplx<T> *__restrict__ tw, int twn, int sign)
 {
     const int logM = 31 - __builtin_clz(M);
     int h = 1;
     if (logM & 1) {
-        for (int b = threadIdx.x; b < M / 2; b += RT) {
+        for (int b = threadIdx.x; b < M / 2; b += NT) {
             const cplx<T> a = buf[pd(2 * b)], c = buf[pd(2 * b + 1)];
             buf[pd(2 * b)] = cadd<T>(a, c);
             buf[pd(2 * b + 1)] = csub<T>(a, c);
@@ -1127,7 +1127,7 @@ __device__ void fft_dit(cplx<T> *buf, int M, const cplx<T> *__restrict__ tw, int
     }
     for (; h < M; h <<= 2) {
         const int s4 = twn / (4 * h);
-        for (int b = threadIdx.x; b < M / 4; b += RT) {
+        for (int b = threadIdx.x; b < M / 4; b += NT) {
             const int pos = b & (h - 1);
             const int i0 = ((b - pos) << 2) + pos;
             cplx<T> u = tw[pos * s4], w = tw[2 * pos * s4];
@@ -1150,13 +1150,13 @@ __device__ void fft_dit(cplx<T> *buf, int M, const cplx<T> *__restrict__ tw, int
 
 // In-place FFT, natural input -> bit-reversed output: the radix-2 stages h = M/2 .. 1 in pairs
 // (2h, h) as radix-4 steps; an odd log2 M ends with the radix-2 stage h = 1.
-template <typename T>
+template <typename T, int NT = RT>
 __device__ void fft_dif(cplx<T> *buf, int M, const cplx<T> *__restrict__ tw, int twn, int sign)
 {
     int h = M >> 2;
     for (; h >= 1; h >>= 2) {
         const int s4 = twn / (4 * h);
-        for (int b = threadIdx.x; b < M / 4; b += RT) {
+        for (int b = threadIdx.x; b < M / 4; b += NT) {
             const int pos = b & (h - 1);
             const int i0 = ((b - pos) << 2) + pos;
             cplx<T> u = tw[pos * s4], w = tw[2 * pos * s4];
@@ -1175,7 +1175,7 @@ __device__ void fft_dif(cplx<T> *buf, int M, const cplx<T> *__restrict__ tw, int
         __syncthreads();
     }
     if ((31 - __builtin_clz(M)) & 1) {
-        for (int b = threadIdx.x; b < M / 2; b += RT) {
+        for (int b = threadIdx.x; b < M / 2; b += NT) {
             const cplx<T> a = buf[pd(2 * b)], c = buf[pd(2 * b + 1)];
             buf[pd(2 * b)] = cadd<T>(a, c);
             buf[pd(2 * b + 1)] = csub<T>(a, c);
@@ -1374,6 +1374,172 @@ __global__ __launch_bounds__(RT) void k_ring(cplx<T> *__restrict__ FG, int64_t f
         dft_forward<T>(
             buf, bhat, L, M, logM, blu, tw, twn, [&](int u) { return v[u][q]; },
             [&](int u, cplx<T> y) { unfold_bin<T>(F, 4 * (tid + RT * u) + q, N, shift, lmax, cscale<T>(y, om)); });
+    }
+}
+
+// ================================================================================================
+// Ring stage for rings whose length N is a power of two (the equatorial belt when Nside is one):
+// the length-N transforms run directly in LDS, one workgroup of RF threads per ring.  F is folded
+// and G unfolded in m order, so neighbouring threads read and write neighbouring entries of the
+// ring's row; each direction is one radix-4 FFT (ceil(log2 N / 2) passes) with the inverse
+// transform taking natural input to bit-reversed output and the forward one back.
+// MODE as for k_ring.
+// ================================================================================================
+constexpr int RF = 1024;  // threads per ring workgroup
+constexpr int RFU = 8;    // elements per thread: N <= RF * RFU
+
+// e^{i pi (k0 + k1 u) / den} for u = 0, 1, ... as a running FP64 product (one rounding per step)
+struct PhaseSeq {
+    double2 cur, step;
+    __device__ __forceinline__ PhaseSeq(int64_t k0, int64_t k1, int64_t den)
+        : cur(cis_pi<double>(k0, den)), step(cis_pi<double>(k1, den))
+    {
+    }
+    __device__ __forceinline__ double2 next()
+    {
+        const double2 r = cur;
+        cur = cmul<double>(cur, step);
+        return r;
+    }
+};
+
+// a / N for 0 <= a < 2^24 from a float reciprocal rN = 1 / N and one correction
+__device__ __forceinline__ int udiv(int a, int N, float rN)
+{
+    int q = (int)((float)a * rN);
+    const int r = a - q * N;
+    if (r < 0) --q;
+    else if (r >= N) ++q;
+    return q;
+}
+
+// fold_bin / unfold_bin with the phase ph = e^{i pi bin / N} supplied (used when shift)
+template <typename T>
+__device__ __forceinline__ cplx<T> fold_bin_ph(const cplx<T> *__restrict__ F, int bin, int N, float rN, int shift,
+                                               int lmax, const double2 &ph)
+{
+    const int tlo = -udiv(lmax + bin, N, rN);
+    const int thi = (lmax >= bin) ? udiv(lmax - bin, N, rN) : -1;
+    T sr = 0, si = 0;
+    for (int t = tlo; t <= thi; ++t) {
+        const int m = bin + N * t;
+        cplx<T> f = (m >= 0) ? F[2 * m] : F[2 * (-m) + 1];
+        if (shift && (t & 1)) f = mk<T>(-f.x, -f.y);
+        sr += f.x;
+        si += f.y;
+    }
+    cplx<T> s = mk<T>(sr, si);
+    if (shift) s = cmul<T>(s, mk<T>((T)ph.x, (T)ph.y));
+    return s;
+}
+template <typename T>
+__device__ __forceinline__ void unfold_bin_ph(cplx<T> *__restrict__ G, int bin, int N, float rN, int shift, int lmax,
+                                              cplx<T> y, const double2 &ph)
+{
+    if (shift) y = cmul<T>(y, mk<T>((T)ph.x, (T)-ph.y));
+    const int tlo = -udiv(lmax + bin, N, rN);
+    const int thi = (lmax >= bin) ? udiv(lmax - bin, N, rN) : -1;
+    for (int t = tlo; t <= thi; ++t) {
+        const int m = bin + N * t;
+        const cplx<T> g = (shift && (t & 1)) ? mk<T>(-y.x, -y.y) : y;
+        if (m > 0) G[2 * m] = g;
+        else if (m < 0) G[2 * (-m) + 1] = g;
+        else {
+            G[0] = g;
+            G[1] = g;
+        }
+    }
+}
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(RF) void k_ring_full(cplx<T> *__restrict__ FG, int64_t fg_stride,
+                                                  const double *__restrict__ g1, const double *__restrict__ g2,
+                                                  double *__restrict__ o1, double *__restrict__ o2, int64_t map_stride,
+                                                  const double *__restrict__ Wt, const RingInfo *__restrict__ rings,
+                                                  const int *__restrict__ order, const cplx<T> *__restrict__ tw,
+                                                  int twn, int lmax, double omega, double *__restrict__ o3,
+                                                  const uint8_t *__restrict__ mask, const double *__restrict__ cdev)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cplx<T> *buf = reinterpret_cast<cplx<T> *>(smem_raw);
+    const int r = order[blockIdx.x];
+    const int rhs = blockIdx.y;
+    const RingInfo ri = rings[r];
+    const int N = ri.nphi, shift = ri.shift;
+    const int logN = 31 - __builtin_clz(N);
+    cplx<T> *F = FG + rhs * fg_stride + (int64_t)r * (lmax + 1) * 2;
+    const int tid = threadIdx.x;
+    const int64_t pofs = rhs * map_stride + ri.ofs;
+    const float rN = 1.0f / (float)N;
+    cplx<T> v[RFU];
+
+    if (MODE != 1) {
+        // bin b collects F(m) e^{i m phi0} over m = b + N t, |m| <= lmax (phi0 = pi shift / N)
+        PhaseSeq ph(tid, RF, N);  // e^{i pi b / N}
+#pragma unroll
+        for (int u = 0; u < RFU; ++u) {
+            const int b = tid + RF * u;
+            const double2 e = ph.next();
+            if (b < N) buf[pd(b)] = fold_bin_ph<T>(F, b, N, rN, shift, lmax, e);
+        }
+        __syncthreads();
+        fft_dif<T, RF>(buf, N, tw, twn, +1);  // gamma_j = sum_b X_b e^{+2 pi i b j / N}, at brev(j)
+#pragma unroll
+        for (int u = 0; u < RFU; ++u) {
+            const int j = tid + RF * u;
+            if (j < N) v[u] = buf[pd(brev(j, logN))];
+        }
+        __syncthreads();
+    }
+    if (MODE == 0) {
+#pragma unroll
+        for (int u = 0; u < RFU; ++u) {
+            const int j = tid + RF * u;
+            if (j >= N) continue;
+            o1[pofs + j] = (double)v[u].x;
+            o2[pofs + j] = (double)v[u].y;
+        }
+        return;
+    }
+    if (MODE == 3) {
+        const double c = *cdev;
+#pragma unroll
+        for (int u = 0; u < RFU; ++u) {
+            const int j = tid + RF * u;
+            if (j >= N) continue;
+            const int64_t pix = pofs + j;
+            const int64_t pm = ri.ofs + j;  // the mask is shared by all right-hand sides
+            const double q1 = o1[pix], q2 = o2[pix];
+            const double r1 = g1[pix] - (double)v[u].x, r2 = g2[pix] - (double)v[u].y;
+            o3[pix] = mask[pm] ? omega * (q1 * r1 + q2 * r2) - c : 0.0;
+            const double w = omega * Wt[pix];
+            o1[pix] = w * q1;
+            o2[pix] = w * q2;
+        }
+        return;
+    }
+    // h_j = W_j gamma_j (MODE 2) or W_j (g1 + i g2)_j (MODE 1), in natural order
+#pragma unroll
+    for (int u = 0; u < RFU; ++u) {
+        const int j = tid + RF * u;
+        if (j >= N) continue;
+        const int64_t pix = pofs + j;
+        if (MODE == 1) {
+            const T w = Wt ? (T)Wt[pix] : (T)1;
+            buf[pd(j)] = mk<T>((T)g1[pix] * w, (T)g2[pix] * w);
+        } else {
+            buf[pd(j)] = cscale<T>(v[u], (T)Wt[pix]);
+        }
+    }
+    __syncthreads();
+    fft_dif<T, RF>(buf, N, tw, twn, -1);  // Y_b = sum_j h_j e^{-2 pi i b j / N}, at brev(b)
+    const T om = (T)omega;
+    PhaseSeq ph(tid, RF, N);
+#pragma unroll
+    for (int u = 0; u < RFU; ++u) {
+        const int b = tid + RF * u;
+        const double2 e = ph.next();
+        if (b < N) unfold_bin_ph<T>(F, b, N, rN, shift, lmax, cscale<T>(buf[pd(brev(b, logN))], om), e);
     }
 }
 
@@ -1750,10 +1916,12 @@ static void ring_launch_t(Plan &P, const double *g1, const double *g2, double *o
     const void *tw = std::is_same<T, double>::value ? P.d_tw64 : P.d_tw32;
     const cplx<T> *bh = (const cplx<T> *)(std::is_same<T, double>::value ? P.d_bhat64 : P.d_bhat32);
     if (P.n_p2) {
-        size_t sm = sizeof(cplx<T>) * (size_t)(P.maxM_p2 + P.maxM_p2 / 32);
-        k_ring<T, MODE><<<dim3(P.n_p2, nrhs), RT, sm, P.stream>>>((cplx<T> *)P.d_FG, fg_stride, g1, g2, o1, o2, P.npix,
-                                                                  W, P.d_rings, P.d_order_p2, (const cplx<T> *)tw,
-                                                                  P.twn, P.lmax, P.omega, o3, mask, cdev, bh);
+        // whole rings: N = 4 sub <= 4 nside <= 8192 = RF RFU (nside <= 2048 is enforced at plan creation)
+        const size_t nmax = 4 * (size_t)P.maxM_p2;
+        size_t sm = sizeof(cplx<T>) * (nmax + nmax / 32);
+        k_ring_full<T, MODE><<<dim3(P.n_p2, nrhs), RF, sm, P.stream>>>(
+            (cplx<T> *)P.d_FG, fg_stride, g1, g2, o1, o2, P.npix, W, P.d_rings, P.d_order_p2, (const cplx<T> *)tw,
+            P.twn, P.lmax, P.omega, o3, mask, cdev);
     }
     if (P.n_bl) {
         size_t sm = sizeof(cplx<T>) * (size_t)(P.maxM_bl + P.maxM_bl / 32);

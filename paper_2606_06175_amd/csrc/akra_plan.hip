@@ -303,7 +303,8 @@ static akra_status create(int nside, int lmax, int nrhs, int prec, void *stream,
     P->n_bl = (int)bl.size();
     P->maxM_p2 = maxp2;
     P->maxM_bl = maxbl;
-    P->twn = std::max(2, std::max(maxp2, maxbl));
+    // twiddles for the Bluestein convolutions and for whole power-of-two rings (N = 4 sub)
+    P->twn = std::max(2, std::max(4 * maxp2, maxbl));
     // one chirp spectrum per distinct Bluestein sub length (the two caps share them)
     std::vector<int> bL, bM;
     std::vector<int64_t> bO;
