@@ -76,8 +76,9 @@ struct RingInfo {
     int nphi;      // pixels on the ring, N = 4 * sub
     int sub;       // N / 4: length of the four interleaved sub-transforms
     int shift;     // phi0 = pi * shift / N
-    int M;         // Bluestein FFT length for the sub-transform (0: sub is a power of two)
-    int64_t bofs;  // Bluestein rings: offset of the chirp spectrum of this sub length
+    int M;         // Bluestein FFT length (0: sub is a power of two): of the whole ring when the
+                   // ring is transformed whole, else of the sub-transform
+    int64_t bofs;  // Bluestein rings: offset of the chirp spectrum of the transformed length
 };
 
 struct Plan {
@@ -109,8 +110,8 @@ struct Plan {
     void *d_bhat64 = nullptr, *d_bhat32 = nullptr;  // Bluestein chirp spectra per distinct sub length
     int twn = 1;
     int *d_lof = nullptr;  // l of every alm index
-    int *d_order_p2 = nullptr, *d_order_bl = nullptr;
-    int n_p2 = 0, n_bl = 0, maxM_p2 = 1, maxM_bl = 1;
+    int *d_order_p2 = nullptr, *d_order_bl = nullptr, *d_order_bf = nullptr;
+    int n_p2 = 0, n_bl = 0, n_bf = 0, maxM_p2 = 1, maxM_bl = 1, maxM_bf = 1;
     std::vector<RingInfo> h_rings;
 
     // Legendre launch shapes

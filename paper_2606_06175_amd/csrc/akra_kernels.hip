@@ -1184,38 +1184,38 @@ __device__ void fft_dif(cplx<T> *buf, int M, const cplx<T> *__restrict__ tw, int
     }
 }
 
-// Forward DFT of length L: y_k = sum_n x_n e^{-2 pi i n k / L}; x_n = get(u) for n = tid + RT u,
-// y_k delivered as put(u, y) for k = tid + RT u.
-template <typename T, class Get, class Put>
+// Forward DFT of length L: y_k = sum_n x_n e^{-2 pi i n k / L}; x_n = get(u) for n = tid + NT u,
+// y_k delivered as put(u, y) for k = tid + NT u (NT threads, L <= NT NU).
+template <typename T, int NT = RT, int NU = RU, class Get, class Put>
 __device__ __forceinline__ void dft_forward(cplx<T> *buf, const cplx<T> *bhat, int L, int M, int logM, bool blu,
                                             const cplx<T> *__restrict__ tw, int twn, Get &&get, Put &&put)
 {
     const int tid = threadIdx.x;
 #pragma unroll
-    for (int u = 0; u < RU; ++u) {
-        const int n = tid + RT * u;
+    for (int u = 0; u < NU; ++u) {
+        const int n = tid + NT * u;
         if (n < L) {
             cplx<T> v = get(u);
             if (blu) v = cmul<T>(v, chirp<T>(n, L));
             buf[pd(brev(n, logM))] = v;
         }
     }
-    for (int n = L + tid; n < M; n += RT) buf[pd(brev(n, logM))] = mk<T>(0, 0);
+    for (int n = L + tid; n < M; n += NT) buf[pd(brev(n, logM))] = mk<T>(0, 0);
     __syncthreads();
-    fft_dit<T>(buf, M, tw, twn, -1);
+    fft_dit<T, NT>(buf, M, tw, twn, -1);
     if (blu) {
-        for (int n = tid; n < M; n += RT) buf[pd(n)] = cmul<T>(buf[pd(n)], bhat[n]);
+        for (int n = tid; n < M; n += NT) buf[pd(n)] = cmul<T>(buf[pd(n)], bhat[n]);
         __syncthreads();
-        fft_dif<T>(buf, M, tw, twn, +1);
+        fft_dif<T, NT>(buf, M, tw, twn, +1);
 #pragma unroll
-        for (int u = 0; u < RU; ++u) {
-            const int kk = tid + RT * u;
+        for (int u = 0; u < NU; ++u) {
+            const int kk = tid + NT * u;
             if (kk < L) put(u, cmul<T>(buf[pd(brev(kk, logM))], chirp<T>(kk, L)));
         }
     } else {
 #pragma unroll
-        for (int u = 0; u < RU; ++u) {
-            const int kk = tid + RT * u;
+        for (int u = 0; u < NU; ++u) {
+            const int kk = tid + NT * u;
             if (kk < L) put(u, buf[pd(kk)]);
         }
     }
@@ -1541,6 +1541,98 @@ __global__ __launch_bounds__(RF) void k_ring_full(cplx<T> *__restrict__ FG, int6
         const double2 e = ph.next();
         if (b < N) unfold_bin_ph<T>(F, b, N, rN, shift, lmax, cscale<T>(buf[pd(brev(b, logN))], om), e);
     }
+}
+
+// ================================================================================================
+// Ring stage for rings of any length N whose Bluestein convolution (length M >= 2N - 1, a power of
+// two) fits in LDS: one DFT of the whole ring per direction by Bluestein's chirp-z, with the chirp
+// spectrum of length N from the plan's table; fold and unfold in m order as in k_ring_full.
+// MODE as for k_ring.
+// ================================================================================================
+constexpr int RBU = 4;  // elements per thread: N <= RF * RBU
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(RF) void k_ring_bfull(cplx<T> *__restrict__ FG, int64_t fg_stride,
+                                                   const double *__restrict__ g1, const double *__restrict__ g2,
+                                                   double *__restrict__ o1, double *__restrict__ o2, int64_t map_stride,
+                                                   const double *__restrict__ Wt, const RingInfo *__restrict__ rings,
+                                                   const int *__restrict__ order, const cplx<T> *__restrict__ tw,
+                                                   int twn, int lmax, double omega, double *__restrict__ o3,
+                                                   const uint8_t *__restrict__ mask, const double *__restrict__ cdev,
+                                                   const cplx<T> *__restrict__ bhat_all)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cplx<T> *buf = reinterpret_cast<cplx<T> *>(smem_raw);
+    const int r = order[blockIdx.x];
+    const int rhs = blockIdx.y;
+    const RingInfo ri = rings[r];
+    const int N = ri.nphi, shift = ri.shift, M = ri.M;
+    const int logM = 31 - __builtin_clz(M);
+    const cplx<T> *bhat = bhat_all + ri.bofs;
+    cplx<T> *F = FG + rhs * fg_stride + (int64_t)r * (lmax + 1) * 2;
+    const int tid = threadIdx.x;
+    const int64_t pofs = rhs * map_stride + ri.ofs;
+    const float rN = 1.0f / (float)N;
+    cplx<T> v[RBU];
+
+    if (MODE != 1) {
+        // gamma_j = sum_b X_b e^{+2 pi i b j / N} = conj(DFT(conj X))_j; get and put run in u order
+        PhaseSeq ph(tid, RF, N);  // e^{i pi b / N} along b = tid + RF u
+        dft_forward<T, RF, RBU>(
+            buf, bhat, N, M, logM, true, tw, twn,
+            [&](int u) {
+                const double2 e = ph.next();
+                return cconj<T>(fold_bin_ph<T>(F, tid + RF * u, N, rN, shift, lmax, e));
+            },
+            [&](int u, cplx<T> y) { v[u] = cconj<T>(y); });
+    }
+    if (MODE == 0) {
+#pragma unroll
+        for (int u = 0; u < RBU; ++u) {
+            const int j = tid + RF * u;
+            if (j >= N) continue;
+            o1[pofs + j] = (double)v[u].x;
+            o2[pofs + j] = (double)v[u].y;
+        }
+        return;
+    }
+    if (MODE == 3) {
+        const double c = *cdev;
+#pragma unroll
+        for (int u = 0; u < RBU; ++u) {
+            const int j = tid + RF * u;
+            if (j >= N) continue;
+            const int64_t pix = pofs + j;
+            const int64_t pm = ri.ofs + j;  // the mask is shared by all right-hand sides
+            const double q1 = o1[pix], q2 = o2[pix];
+            const double r1 = g1[pix] - (double)v[u].x, r2 = g2[pix] - (double)v[u].y;
+            o3[pix] = mask[pm] ? omega * (q1 * r1 + q2 * r2) - c : 0.0;
+            const double w = omega * Wt[pix];
+            o1[pix] = w * q1;
+            o2[pix] = w * q2;
+        }
+        return;
+    }
+#pragma unroll
+    for (int u = 0; u < RBU; ++u) {
+        const int j = tid + RF * u;
+        if (j >= N) continue;
+        const int64_t pix = pofs + j;
+        if (MODE == 1) {
+            const T w = Wt ? (T)Wt[pix] : (T)1;
+            v[u] = mk<T>((T)g1[pix] * w, (T)g2[pix] * w);
+        } else {
+            v[u] = cscale<T>(v[u], (T)Wt[pix]);
+        }
+    }
+    const T om = (T)omega;
+    PhaseSeq ph(tid, RF, N);
+    dft_forward<T, RF, RBU>(
+        buf, bhat, N, M, logM, true, tw, twn, [&](int u) { return v[u]; },
+        [&](int u, cplx<T> y) {
+            const double2 e = ph.next();
+            unfold_bin_ph<T>(F, tid + RF * u, N, rN, shift, lmax, cscale<T>(y, om), e);
+        });
 }
 
 // ================================================================================================
@@ -1922,6 +2014,12 @@ static void ring_launch_t(Plan &P, const double *g1, const double *g2, double *o
         k_ring_full<T, MODE><<<dim3(P.n_p2, nrhs), RF, sm, P.stream>>>(
             (cplx<T> *)P.d_FG, fg_stride, g1, g2, o1, o2, P.npix, W, P.d_rings, P.d_order_p2, (const cplx<T> *)tw,
             P.twn, P.lmax, P.omega, o3, mask, cdev);
+    }
+    if (P.n_bf) {
+        size_t sm = sizeof(cplx<T>) * (size_t)(P.maxM_bf + P.maxM_bf / 32);
+        k_ring_bfull<T, MODE><<<dim3(P.n_bf, nrhs), RF, sm, P.stream>>>(
+            (cplx<T> *)P.d_FG, fg_stride, g1, g2, o1, o2, P.npix, W, P.d_rings, P.d_order_bf, (const cplx<T> *)tw,
+            P.twn, P.lmax, P.omega, o3, mask, cdev, bh);
     }
     if (P.n_bl) {
         size_t sm = sizeof(cplx<T>) * (size_t)(P.maxM_bl + P.maxM_bl / 32);

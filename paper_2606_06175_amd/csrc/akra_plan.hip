@@ -244,7 +244,7 @@ static void free_plan(Plan *P)
     void *ptrs[] = {P->d_rings, P->d_pair_z, P->d_coef64, P->d_coef32, P->d_coef64s, P->d_coef32s, P->d_recu,
                     P->d_seed2, P->d_seedm2, P->d_seedk,
                     P->d_ent, P->d_entk, P->d_entl, P->d_wgstart, P->d_coef32d, P->d_brec,
-                    P->d_tw64, P->d_tw32, P->d_bhat64, P->d_bhat32, P->d_lof, P->d_order_p2, P->d_order_bl, P->d_FG, P->d_part, P->d_rec, P->d_W, P->d_kern, P->d_kuser, P->d_red, P->d_scal, P->d_flag, P->d_x, P->d_r,
+                    P->d_tw64, P->d_tw32, P->d_bhat64, P->d_bhat32, P->d_lof, P->d_order_p2, P->d_order_bl, P->d_order_bf, P->d_FG, P->d_part, P->d_rec, P->d_W, P->d_kern, P->d_kuser, P->d_red, P->d_scal, P->d_flag, P->d_x, P->d_r,
                     P->d_p, P->d_w, P->d_b, P->d_xs};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
@@ -284,44 +284,62 @@ static akra_status create(int nside, int lmax, int nrhs, int prec, void *stream,
     P->nalm = (int64_t)(lmax + 1) * (lmax + 2) / 2;
     build_rings(*P);
 
-    // ring launch lists (power-of-two sub-transforms / Bluestein), largest first
-    std::vector<int> p2, bl;
-    int maxp2 = 1, maxbl = 1;
+    // ring launch lists, largest first: power-of-two rings (whole-ring FFT), rings whose whole-ring
+    // Bluestein convolution fits in LDS (M <= BF_MAXM), and the rest (four sub-transforms, each
+    // by Bluestein)
+    constexpr int BF_MAXM = 8192;
+    std::vector<int> p2, bl, bf;
+    int maxp2 = 1, maxbl = 1, maxbf = 1;
     for (int r = 0; r < P->nrings; ++r) {
-        if (P->h_rings[r].M) {
-            bl.push_back(r);
-            maxbl = std::max(maxbl, P->h_rings[r].M);
-        } else {
+        RingInfo &ri = P->h_rings[r];
+        if (!ri.M) {
             p2.push_back(r);
-            maxp2 = std::max(maxp2, P->h_rings[r].sub);
+            maxp2 = std::max(maxp2, ri.sub);
+            continue;
+        }
+        int MF = 1;
+        while (MF < 2 * ri.nphi - 1) MF <<= 1;
+        if (MF <= BF_MAXM) {
+            ri.M = MF;  // the whole ring's convolution length
+            bf.push_back(r);
+            maxbf = std::max(maxbf, MF);
+        } else {
+            bl.push_back(r);
+            maxbl = std::max(maxbl, ri.M);
         }
     }
     auto bysize = [&](int a, int b) { return P->h_rings[a].nphi > P->h_rings[b].nphi; };
     std::stable_sort(p2.begin(), p2.end(), bysize);
     std::stable_sort(bl.begin(), bl.end(), bysize);
+    std::stable_sort(bf.begin(), bf.end(), bysize);
     P->n_p2 = (int)p2.size();
     P->n_bl = (int)bl.size();
+    P->n_bf = (int)bf.size();
     P->maxM_p2 = maxp2;
     P->maxM_bl = maxbl;
+    P->maxM_bf = maxbf;
     // twiddles for the Bluestein convolutions and for whole power-of-two rings (N = 4 sub)
-    P->twn = std::max(2, std::max(4 * maxp2, maxbl));
-    // one chirp spectrum per distinct Bluestein sub length (the two caps share them)
+    P->twn = std::max(2, std::max(4 * maxp2, std::max(maxbl, maxbf)));
+    // one chirp spectrum per distinct chirp length: the sub length of the split rings, the ring
+    // length of the whole-ring ones (the two caps share them)
     std::vector<int> bL, bM;
     std::vector<int64_t> bO;
     int64_t btot = 0;
     {
-        std::vector<int64_t> at(P->nside + 1, -1);
-        for (int r : bl) {
+        std::vector<int64_t> at(4 * (size_t)P->nside + 1, -1);
+        auto key = [&](int r, int len) {
             RingInfo &ri = P->h_rings[r];
-            if (at[ri.sub] < 0) {
-                at[ri.sub] = btot;
-                bL.push_back(ri.sub);
+            if (at[len] < 0) {
+                at[len] = btot;
+                bL.push_back(len);
                 bM.push_back(ri.M);
                 bO.push_back(btot);
                 btot += ri.M;
             }
-            ri.bofs = at[ri.sub];
-        }
+            ri.bofs = at[len];
+        };
+        for (int r : bl) key(r, P->h_rings[r].sub);
+        for (int r : bf) key(r, P->h_rings[r].nphi);
     }
 
     // near-polar groups of FP32 plans: first pair of the group within theta_c of a pole
@@ -387,6 +405,7 @@ static akra_status create(int nside, int lmax, int nrhs, int prec, void *stream,
         AK_TRY(upload((void **)&P->d_rings, P->h_rings.data(), P->h_rings.size() * sizeof(RingInfo), *P));
         AK_TRY(upload((void **)&P->d_order_p2, p2.data(), p2.size() * sizeof(int), *P));
         AK_TRY(upload((void **)&P->d_order_bl, bl.data(), bl.size() * sizeof(int), *P));
+        AK_TRY(upload((void **)&P->d_order_bf, bf.data(), bf.size() * sizeof(int), *P));
     }
     // entry states of the recurrence (the seeds are only needed to build them)
     {
@@ -433,7 +452,7 @@ static akra_status create(int nside, int lmax, int nrhs, int prec, void *stream,
                   hipMemcpy(dM, bM.data(), nb * sizeof(int), hipMemcpyHostToDevice) == hipSuccess &&
                   hipMemcpy(dO, bO.data(), nb * sizeof(int64_t), hipMemcpyHostToDevice) == hipSuccess;
         if (ok) {
-            launch_bhat(*P, dL, dM, dO, (int)nb, P->maxM_bl);
+            launch_bhat(*P, dL, dM, dO, (int)nb, std::max(P->maxM_bl, P->maxM_bf));
             ok = hipGetLastError() == hipSuccess && hipStreamSynchronize(P->stream) == hipSuccess;
         }
         for (void *q : {(void *)dL, (void *)dM, (void *)dO})
