@@ -32,9 +32,9 @@ FLOP_PER_TRIPLE = 26     # per (l, m, ring pair) and direction: 2 recurrences (1
 # workload, each scaled by the same counter's reading for a device copy of known size; valid only for
 # the kernel source they were taken from (its SHA-256 is checked at run time).
 TRAFFIC = {
-    # profiles/k_leg_adj_nside2048_lmax4096_fp64.md: FETCH 2.350e6 KiB x 1.9999 + WRITE 3.242e6 KiB x 1.0000
-    "leg_adj": {"bytes": 8.1334e9, "workload": (2048, 4096),
-                "kernels_sha256": "abe87c6da6d23eb6135fb81bca2492357454b563e45c10a0df799ab45cc96278"},
+    # profiles/k_leg_adj_nside2048_lmax4096_fp64.md: FETCH 2.3555e6 KiB x 1.99994 + WRITE 3.3155e6 KiB x 1.0000
+    "leg_adj": {"bytes": 8.2189e9, "workload": (2048, 4096),
+                "kernels_sha256": "2024379d37f4c8f9b7a3fee0f5c2058a6081d63dae1f7481c0c343fdf775229a"},
 }
 
 
