@@ -288,6 +288,11 @@ def main():
                 "algorithmic": "26 flop x %d evaluated (l, m, ring-pair) triples = %.4g flop per launch "
                                "(all triples T = %d; below each ring group's entry degree the terms are zero "
                                "and are skipped)" % (evaluated[dom], flops, T)}
+    # ring stage against HBM: F read and G written (32 B per (ring, m) each) and W read (8 B per pixel)
+    ring_bytes = 2 * 32 * (4 * nside - 1) * (lmax + 1) + 8 * 12 * nside * nside
+    roofline["ring_algorithmic_bytes"] = ring_bytes
+    roofline["ring_hbm_GBs"] = ring_bytes / (stages["ring"]["ms_avg"] * 1e-3) / 1e9
+    roofline["ring_hbm_frac"] = roofline["ring_hbm_GBs"] / 8000.0
     for k in ("leg_synth", "leg_adj"):
         t = stages[k]["ms_avg"] * 1e-3
         roofline["frac_" + k] = FLOP_PER_TRIPLE * evaluated[k] / t / PEAK_FP64
