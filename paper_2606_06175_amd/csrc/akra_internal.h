@@ -129,6 +129,8 @@ struct Plan {
     float4 *d_recu = nullptr;   // FP32 plans with polar groups: [nrhs][nalm + ALM_PAD] unscaled alm for
                                 // the difference form
     float *d_brec = nullptr;    // FP32 plans with nrhs > 1: [nalm + ALM_PAD][8 rhs][4] batched records
+    int nrb_b = 0;              // FP32 plans with nrhs > 1: ring blocks of the batched adjoint
+    int *d_wgstart_b = nullptr; // [m][nrb_b] first degree each batched adjoint block wrote
     int64_t rec_stride = 0;     // records per right-hand side
     double *d_W = nullptr;      // [nrhs][npix] weights
     double *d_kern = nullptr;   // [lmax+1]
@@ -186,6 +188,11 @@ void launch_scale_scalar(Plan &P, double *out, const double *in, double f);
 // epilogue: sum partials, E/B combination, out = K_l * c + lam * x
 void launch_epilogue(Plan &P, bool fp32, const double *kern, double lam, const double *xE, const double *xB,
                      double *outE, double *outB);
+// batched FP32 adjoint (matrix cores) of right-hand-side group q, and the epilogue of one right-hand
+// side from its slabs
+void launch_adj_batched(Plan &P, int q);
+void launch_epilogue_batched(Plan &P, int rhs, const double *kern, double lam, const double *xE, const double *xB,
+                             double *outE, double *outB);
 // chirp spectra of the Bluestein sub lengths Ls (FFT lengths Ms, table offsets ofs; device arrays)
 void launch_bhat(Plan &P, const int *Ls, const int *Ms, const int64_t *ofs, int n, int maxM);
 // weights W = mask * ninv, plus the sums needed for lambda_eff / P and input validation

@@ -1842,6 +1842,157 @@ __global__ __launch_bounds__(256) void k_leg_synth_b(const float *__restrict__ b
     }
 }
 
+// ================================================================================================
+// Batched FP32 Legendre adjoint on the matrix cores.  For one m, a block of ABW 64-pair groups (one per
+// wave) and the NBR right-hand sides of group q, the partial sums over the block's ring pairs
+//   out_rhs[l][c],  c = 0..3 as in k_leg_adj (2h_lm and -2h_lm, Re and Im).
+// Per chunk of ABL = 32 degrees each wave writes the recurrence values of its pairs to LDS (one row
+// per degree), then v_mfma_f32_32x32x2_f32 contracts over the pairs, two per instruction:
+//   D+ = Lambda+ [GN.x, GN.y, HS.x, HS.y],   D- = Lambda- [HN.x, HN.y, GS.x, GS.y]
+// (columns 4 rhs + c, G of the north ring GN, HN = conj of its second component, S the south ring),
+// and the south terms take the sign s = (-1)^(l+m) of their row:
+//   out_0,1 = D+[c] + s D-[c+2],   out_2,3 = D-[c-2] + s D+[c].
+// G is loaded once per wave into registers (it does not depend on l).  The waves of the block are
+// summed in LDS and one slab per (right-hand side of the group, block) is written,
+// [rhs - NBR q][nrb][nalm][4], rows from the chunk holding the block's first entry degree (recorded in
+// wgstart) to lmax.
+// ================================================================================================
+constexpr int ABW = 4;   // waves (64-pair groups) per workgroup
+constexpr int ABL = 32;  // degrees per chunk: the rows of the MFMA
+constexpr int ABS = 33;  // LDS stride of one pair's 32 rows (bank-conflict-free writes)
+
+template <int F>
+__global__ __launch_bounds__(64 * ABW) void k_leg_adj_b(const float2 *__restrict__ FG, int64_t fg_stride,
+                                                        const typename CoefB<F>::type *__restrict__ coef,
+                                                        const Ent64 *__restrict__ ent, const int *__restrict__ entk,
+                                                        const int *__restrict__ entl, int ng64,
+                                                        const double *__restrict__ pair_z, float *__restrict__ part,
+                                                        int *__restrict__ wgstart, int64_t nalm, int lmax, int npairs,
+                                                        int nrings, int nrhs, int q, int g0, int gend, int rb0,
+                                                        int nrbl, int nrb)
+{
+    __shared__ float lam[ABW][2][64 * ABS];  // per wave: lambda+ and lambda- of its 64 pairs x 32 rows
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    int m, rbl;
+    xcd_map((int)blockIdx.x, nrbl, m, rbl);
+    if (m > lmax) return;
+    const int rb = rb0 + rbl;
+    const int gb = g0 + rbl * ABW;  // first group of the block
+    const int l0 = m > 2 ? m : 2;
+    const int64_t base = (int64_t)m * (2 * lmax + 1 - m) / 2;
+    const_as<int> *el = uniform_ptr(entl + (int64_t)m * ng64);
+    int ls = ENT_SKIP;
+    for (int g = gb; g < gb + ABW && g < gend; ++g) ls = el[g] < ls ? el[g] : ls;
+    if (threadIdx.x == 0) wgstart[(int64_t)m * nrb + rb] = ls;
+    if (ls > lmax) return;
+    const int g = gb + wave;
+    const int e = (g < gend) ? el[g] : ENT_SKIP;  // this wave's entry degree
+    const int p = g * 64 + lane;
+    const bool valid = g < gend && p < npairs;
+
+    // B operands: lane l holds, for pair-pair kk, pair 64 g + 2 kk + l / 32 and column j = l % 32
+    const int j = lane & 31, c = j & 3, rhs = q * NBR + (j >> 2);
+    float Bp[32], Bm[32];
+#pragma unroll
+    for (int kk = 0; kk < 32; ++kk) {
+        Bp[kk] = Bm[kk] = 0.f;
+        const int pk = g * 64 + 2 * kk + (lane >> 5);
+        if (e > lmax || g >= gend || pk >= npairs || rhs >= nrhs) continue;
+        const float2 *Fb = FG + rhs * fg_stride;
+        if (c < 2) {
+            const float2 *fn = Fb + ((int64_t)pk * (lmax + 1) + m) * 2;
+            const float2 gn = fn[0], hn = fn[1];  // HN = conj(hn)
+            Bp[kk] = c ? gn.y : gn.x;
+            Bm[kk] = c ? -hn.y : hn.x;
+        } else {
+            const int rs = nrings - 1 - pk;
+            if (rs != pk) {
+                const float2 *fs = Fb + ((int64_t)rs * (lmax + 1) + m) * 2;
+                const float2 gs = fs[0], hs = fs[1];  // HS = conj(hs)
+                Bp[kk] = (c & 1) ? -hs.y : hs.x;
+                Bm[kk] = (c & 1) ? gs.y : gs.x;
+            }
+        }
+    }
+
+    typename PosT<float, F>::type x;
+    setpos(x, valid ? pair_z[p] : 0.0);
+    float c2 = 0.f, p2 = 0.f, cm = 0.f, pm = 0.f;
+    int k = 0;
+    bool ramp = false;
+    using C = typename CoefB<F>::type;
+    const_as<C> *cp = uniform_ptr(coef + base);
+    float *lp = &lam[wave][0][lane * ABS], *lmn = &lam[wave][1][lane * ABS];
+    const float *ap = &lam[wave][0][(lane >> 5) * ABS + (lane & 31)], *am = &lam[wave][1][(lane >> 5) * ABS + (lane & 31)];
+    const int lstart = l0 + ((ls - l0) / ABL) * ABL;
+    for (int lc = lstart; lc <= lmax; lc += ABL) {
+        // recurrence values of the chunk's rows (zero before the wave's entry, for lanes still in the
+        // scaled range and past lmax)
+        const bool active = e <= lc + ABL - 1 && e <= lmax;
+        v16f Dp, Dm;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) Dp[r] = Dm[r] = 0.f;
+        if (active) {
+            for (int t = 0; t < ABL; ++t) {
+                const int l = lc + t;
+                if (l == e) {
+                    if (valid) load_entry<float, F>(ent, entk, (int64_t)m * npairs + p, c2, p2, cm, pm, k);
+                    ramp = wave_any(k < 0);
+                }
+                const bool live = l >= e && l <= lmax && k == 0;
+                lp[t] = live ? c2 : 0.f;
+                lmn[t] = live ? cm : 0.f;
+                if (l >= e && l <= lmax) rstep(ld_coef(cp + l), x, c2, p2, cm, pm);
+                if (ramp && (t & 3) == 3) {
+                    // every four steps (the growth over four steps stays far from overflow)
+                    if (k < 0 && fmaxf(fabsf(c2), fabsf(cm)) > scale_hi<float>()) {
+                        const float d = scale_down<float>();
+                        c2 *= d;
+                        p2 *= d;
+                        cm *= d;
+                        pm *= d;
+                        k += 1;
+                    }
+                    ramp = wave_any(k < 0);
+                }
+            }
+            wg_lds_sync<1>();  // the wave reads only its own rows
+#pragma unroll
+            for (int kk = 0; kk < 32; ++kk) {
+                Dp = __builtin_amdgcn_mfma_f32_32x32x2f32(ap[2 * kk * ABS], Bp[kk], Dp, 0, 0, 0);
+                Dm = __builtin_amdgcn_mfma_f32_32x32x2f32(am[2 * kk * ABS], Bm[kk], Dm, 0, 0, 0);
+            }
+        }
+        // D row of register r in lane l: 8 (r / 4) + 4 (l / 32) + r % 4, column l % 32
+        float o[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int i = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+            const float s = ((lc + i + m) & 1) ? -1.f : 1.f;
+            const float t2 = dpp_mov<0x4E>(Dm[r]);  // D- of column j ^ 2
+            o[r] = c < 2 ? fmaf(s, t2, Dp[r]) : fmaf(s, Dp[r], t2);
+        }
+        // sum over the block's waves in LDS (the rows of lam are free once every wave has multiplied)
+        __syncthreads();
+        float *red = &lam[0][0][0];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) red[(wave * 16 + r) * 64 + lane] = o[r];
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < 16 / ABW; ++u) {
+            const int r = wave * (16 / ABW) + u;  // this thread's register index, lane as it was
+            float sum = 0.f;
+#pragma unroll
+            for (int w = 0; w < ABW; ++w) sum += red[(w * 16 + r) * 64 + lane];
+            const int i = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3), l = lc + i;
+            if (l <= lmax && rhs < nrhs)
+                part[(((int64_t)(j >> 2) * nrb + rb) * nalm + base + l) * 4 + c] = sum;
+        }
+        __syncthreads();
+    }
+}
+
 static int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 void launch_prologue(Plan &P, bool fp32, const double *xE, const double *xB, const double *kern, int nrhs)
@@ -1908,6 +2059,34 @@ void launch_synth_batched(Plan &P, const double *xE, const double *xB, int64_t r
                 P.lmax, P.npairs, P.nrings, P.nrhs, q, wpol, nw, nbm);
         }
     }
+}
+
+// batched adjoint of the right-hand-side group q into the [rhs - NBR q][nrb_b][nalm][4] slabs of d_part
+void launch_adj_batched(Plan &P, int q)
+{
+    const int64_t fg_stride = (int64_t)P.nrings * (P.lmax + 1) * 2;
+    const int64_t lblocks = cdiv(P.lmax + 1, 8);
+    // polar groups: a multiple of four, or all groups of a small plan
+    const int npol = (int)cdiv(P.polar_groups, ABW);
+    if (P.polar_groups > 0)
+        k_leg_adj_b<1><<<(unsigned)(8 * npol * lblocks), 64 * ABW, 0, P.stream>>>(
+            (const float2 *)P.d_FG, fg_stride, P.d_coef32d, P.d_ent, P.d_entk, P.d_entl, P.ng64, P.d_pair_z,
+            (float *)P.d_part, P.d_wgstart_b, P.nalm, P.lmax, P.npairs, P.nrings, P.nrhs, q, 0, P.polar_groups, 0,
+            npol, P.nrb_b);
+    const int nmain = (int)cdiv(P.ng64 - P.polar_groups, ABW);
+    if (nmain > 0)
+        k_leg_adj_b<0><<<(unsigned)(8 * nmain * lblocks), 64 * ABW, 0, P.stream>>>(
+            (const float2 *)P.d_FG, fg_stride, P.d_coef32, P.d_ent, P.d_entk, P.d_entl, P.ng64, P.d_pair_z,
+            (float *)P.d_part, P.d_wgstart_b, P.nalm, P.lmax, P.npairs, P.nrings, P.nrhs, q, P.polar_groups, P.ng64,
+            npol, nmain, P.nrb_b);
+}
+
+void launch_epilogue_batched(Plan &P, int rhs, const double *kern, double lam, const double *xE, const double *xB,
+                             double *outE, double *outB)
+{
+    const float *part = (const float *)P.d_part + (int64_t)(rhs % NBR) * P.nrb_b * P.nalm * 4;
+    k_epilogue<float><<<(unsigned)cdiv(P.nalm, 256), 256, 0, P.stream>>>(part, P.d_wgstart_b, P.nrb_b, P.nalm, P.d_lof,
+                                                                        P.lmax, kern, lam, xE, xB, outE, outB, P.proj);
 }
 
 void launch_entry(Plan &P)

@@ -243,7 +243,7 @@ static void free_plan(Plan *P)
 {
     void *ptrs[] = {P->d_rings, P->d_pair_z, P->d_coef64, P->d_coef32, P->d_coef64s, P->d_coef32s, P->d_recu,
                     P->d_seed2, P->d_seedm2, P->d_seedk,
-                    P->d_ent, P->d_entk, P->d_entl, P->d_wgstart, P->d_coef32d, P->d_brec,
+                    P->d_ent, P->d_entk, P->d_entl, P->d_wgstart, P->d_wgstart_b, P->d_coef32d, P->d_brec,
                     P->d_tw64, P->d_tw32, P->d_bhat64, P->d_bhat32, P->d_lof, P->d_order_p2, P->d_order_bl, P->d_order_bf, P->d_FG, P->d_part, P->d_rec, P->d_W, P->d_kern, P->d_kuser, P->d_red, P->d_scal, P->d_flag, P->d_x, P->d_r,
                     P->d_p, P->d_w, P->d_b, P->d_xs};
     for (void *q : ptrs)
@@ -477,6 +477,12 @@ static akra_status create(int nside, int lmax, int nrhs, int prec, void *stream,
     const size_t fg = (size_t)nrhs * P->nrings * (lmax + 1) * 2 * sizeof(double2);
     AK_TRY(alloc(&P->d_FG, fg, *P));
     P->part_rb_cap = (size_t)std::max(P->adj_nrb, P->adj_nrb_polar + (P->npairs <= 1024 ? P->ng64 : (P->ng64 + 3) / 4));
+    if (prec == AKRA_FP32 && nrhs > 1) {
+        // batched adjoint: blocks of four groups (polar blocks apart), 8 right-hand sides of FP32 slabs
+        P->nrb_b = (P->polar_groups + 3) / 4 + (P->ng64 - P->polar_groups + 3) / 4;
+        P->part_rb_cap = std::max(P->part_rb_cap, (size_t)4 * P->nrb_b);
+        AK_TRY(alloc((void **)&P->d_wgstart_b, (size_t)P->nrb_b * (lmax + 1) * sizeof(int), *P));
+    }
     AK_TRY(alloc(&P->d_part, P->part_rb_cap * P->nalm * 4 * sizeof(double), *P));
     AK_TRY(alloc((void **)&P->d_wgstart, P->part_rb_cap * (lmax + 1) * sizeof(int), *P));
     compute_work(*P);
@@ -667,10 +673,9 @@ static akra_status apply_H_timed(Plan &P, bool fp32, const double *kern_dev, dou
     return check_launch("apply_H");
 }
 
-// r = b - H64 x (true residual) and rr = <r, r> on the device
 // H applied to all right-hand sides of an FP32 plan at once: batched matrix-core synthesis, ring
-// stage of every right-hand side with its own W, then the adjoint and epilogue of each.  lam_dev
-// (device, per rhs) overrides lam when given.
+// stage of every right-hand side with its own W, then per group of 8 right-hand sides the batched
+// matrix-core adjoint and the epilogue of each.  lam_host (per rhs) overrides lam when given.
 static akra_status apply_H_batched(Plan &P, const double *kern_dev, const double *lam_host, double lam,
                                    const double *xE, const double *xB, double *yE, double *yB, int64_t rstride)
 {
@@ -680,14 +685,16 @@ static akra_status apply_H_batched(Plan &P, const double *kern_dev, const double
     stage_mark(P, 2, true);
     launch_ring(P, true, 2, nullptr, nullptr, nullptr, nullptr, P.d_W, P.nrhs);
     stage_mark(P, 2, false);
-    for (int r = 0; r < P.nrhs; ++r) {
-        const int64_t o = (int64_t)r * 2 * rstride;
+    for (int q = 0; q * 8 < P.nrhs; ++q) {
         stage_mark(P, 3, true);
-        launch_leg_adj(P, true, r);
+        launch_adj_batched(P, q);
         stage_mark(P, 3, false);
-        stage_mark(P, 4, true);
-        launch_epilogue(P, true, kern_dev, lam_host ? lam_host[r] : lam, xE + o, xB + o, yE + o, yB + o);
-        stage_mark(P, 4, false);
+        for (int r = 8 * q; r < P.nrhs && r < 8 * q + 8; ++r) {
+            const int64_t o = (int64_t)r * 2 * rstride;
+            stage_mark(P, 4, true);
+            launch_epilogue_batched(P, r, kern_dev, lam_host ? lam_host[r] : lam, xE + o, xB + o, yE + o, yB + o);
+            stage_mark(P, 4, false);
+        }
     }
     return check_launch("apply_H_batched");
 }

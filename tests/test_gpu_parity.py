@@ -149,10 +149,11 @@ def test_zero_input_gives_zero(torch_dev):
     assert float(g1.abs().max()) == 0 and float(g2.abs().max()) == 0
 
 
-@pytest.mark.parametrize("nside,lmax,nrhs", [(8, 16, 3), (13, 40, 10), (32, 64, 9)])
+@pytest.mark.parametrize("nside,lmax,nrhs", [(8, 16, 3), (13, 40, 10), (32, 64, 9), (256, 512, 3)])
 def test_batched_fp32_matrix_core_path(torch_dev, nside, lmax, nrhs):
-    # FP32 plans with several right-hand sides synthesise all of them on the matrix cores (groups of
-    # eight); synthesis and H of every right-hand side against the oracle
+    # FP32 plans with several right-hand sides synthesise all of them on the matrix cores and run the
+    # adjoint on them in groups of eight; synthesis and H of every right-hand side against the oracle
+    # (Nside 256: adjoint blocks of near-polar groups in the difference form and of plain groups)
     torch, dev = torch_dev
     o = Oracle(lmax, healpix_rings(nside))
     A = np.stack([wl.random_alm(lmax, 60 + k) for k in range(nrhs)])
