@@ -1934,27 +1934,39 @@ __global__ __launch_bounds__(64 * ABW) void k_leg_adj_b(const float2 *__restrict
 #pragma unroll
         for (int r = 0; r < 16; ++r) Dp[r] = Dm[r] = 0.f;
         if (active) {
-            for (int t = 0; t < ABL; ++t) {
-                const int l = lc + t;
-                if (l == e) {
+            // rows in blocks of 8: entry degrees are l0 + 8 q and chunks start at l0 + 32 j
+            for (int t8 = 0; t8 < ABL; t8 += 8) {
+                const int lb = lc + t8;
+                if (lb == e) {
                     if (valid) load_entry<float, F>(ent, entk, (int64_t)m * npairs + p, c2, p2, cm, pm, k);
                     ramp = wave_any(k < 0);
                 }
-                const bool live = l >= e && l <= lmax && k == 0;
-                lp[t] = live ? c2 : 0.f;
-                lmn[t] = live ? cm : 0.f;
-                if (l >= e && l <= lmax) rstep(ld_coef(cp + l), x, c2, p2, cm, pm);
-                if (ramp && (t & 3) == 3) {
-                    // every four steps (the growth over four steps stays far from overflow)
-                    if (k < 0 && fmaxf(fabsf(c2), fabsf(cm)) > scale_hi<float>()) {
-                        const float d = scale_down<float>();
-                        c2 *= d;
-                        p2 *= d;
-                        cm *= d;
-                        pm *= d;
-                        k += 1;
+                if (lb < e || lb > lmax) {
+#pragma unroll
+                    for (int t = 0; t < 8; ++t) lp[t8 + t] = lmn[t8 + t] = 0.f;
+                    continue;
+                }
+                C cc[8];
+#pragma unroll
+                for (int t = 0; t < 8; ++t) cc[t] = ld_coef(cp + lb + t);  // padded past lmax
+#pragma unroll
+                for (int t = 0; t < 8; ++t) {
+                    const bool live = k == 0 && lb + t <= lmax;
+                    lp[t8 + t] = live ? c2 : 0.f;
+                    lmn[t8 + t] = live ? cm : 0.f;
+                    rstep(cc[t], x, c2, p2, cm, pm);
+                    if (ramp && (t & 3) == 3) {
+                        // every four steps (the growth over four steps stays far from overflow)
+                        if (k < 0 && fmaxf(fabsf(c2), fabsf(cm)) > scale_hi<float>()) {
+                            const float d = scale_down<float>();
+                            c2 *= d;
+                            p2 *= d;
+                            cm *= d;
+                            pm *= d;
+                            k += 1;
+                        }
+                        ramp = wave_any(k < 0);
                     }
-                    ramp = wave_any(k < 0);
                 }
             }
             wg_lds_sync<1>();  // the wave reads only its own rows
