@@ -440,8 +440,11 @@ __device__ __forceinline__ bool rescale_restart(T (&c2)[R], T (&p2)[R], T (&cm)[
 // Entry states (plan build).  One wave per (m, 64-pair group) runs the FP64 recurrence from the
 // seeds at l0 = max(m, 2) with the same steps and rescaling as the Legendre kernels' ramp (two
 // steps, then a rescale), and stops at the first degree where some pair of the group contributes:
-// it has left the scaled range and reaches `live` (0 for FP64 plans; for FP32 plans a bound below
-// which the FP32 kernels' scaled values are still masked).  The state at the last degree l0 + 8q
+// it has left the scaled range and reaches `live`.  FP64 plans take live = 2^-100: the values are
+// of order one where they oscillate, so the terms of a group that is still below 2^-100 everywhere
+// change a sum by less than 2^-100 of its scale, far under FP64 rounding (2^-53), and skipping them
+// saves about 5% of the triples at lmax 4096.  FP32 plans take 2^-44, the bound below which the
+// FP32 kernels' scaled values are still masked.  The state at the last degree l0 + 8q
 // before it is stored with that degree; a group that never contributes up to lmax is marked
 // ENT_SKIP.
 // ------------------------------------------------------------------------------------------------
@@ -1700,15 +1703,18 @@ __global__ void k_scalar_div(double *out, const double *num, const double *den) 
 bool pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
 
 // ================================================================================================
-// Batched synthesis (FP32 plans with several right-hand sides): for one m, 32 ring pairs and a group
-// of NB = 8 right-hand sides, the sums over l of lambda(l, pair) a(l, rhs, c) are a matrix product
-// [pairs x l] x [l x (rhs, c)] with the lambda generated on the fly, accumulated on the matrix cores
-// (v_mfma_f32_32x32x2_f32: D[32 x 32] += A[32 x 2] B[2 x 32]).
-//   A[i][k]  lambda of pair i at degree l0 + 2k (even-offset product) or l0 + 1 + 2k (odd), held by
-//            lane i + 32k: both halves of the wave run the recurrence of pair i
+// Batched synthesis (FP32 plans with several right-hand sides): for one m, a group of 64 ring pairs
+// (one per lane) and NBR = 8 right-hand sides, the sums over l of lambda(l, pair) a(l, rhs, c) are a
+// matrix product [pairs x l] x [l x (rhs, c)] with the lambda generated on the fly, accumulated on
+// the matrix cores (v_mfma_f32_32x32x2_f32: D[32 x 32] += A[32 x 2] B[2 x 32]), per half of the pairs.
+//   A[i][k]  lambda of pair i (of the half) at degree l + 2k (even offsets from the step l of four) or
+//            l + 1 + 2k (odd), held by lane i + 32k.  Every lane runs the recurrence of its own pair;
+//            one v_permlane32_swap per pair of degrees (l, l+2) moves the values into that layout:
+//            [low lanes at l | low lanes at l+2] for the first half, [high at l | high at l+2] for
+//            the second.
 //   B[k][j]  record value j = 4 rhs + c (c = Re/Im of aE, Re/Im of aB) at the same degree
-//   D        four accumulators: spin +2 / -2 times even / odd offsets from the start degree
-// Lane l, register r of D holds pair i = 8 (r/4) + 4 (l/32) + r%4 and column j = l%32.
+//   D        per half four accumulators: spin +2 / -2 times even / odd offsets from the start degree
+// Lane l, register r of D holds pair i = 8 (r/4) + 4 (l/32) + r%4 of the half and column j = l%32.
 // ================================================================================================
 typedef float v16f __attribute__((ext_vector_type(16)));
 constexpr int NBR = 8;  // right-hand sides per batched group
@@ -1743,8 +1749,16 @@ __device__ __forceinline__ float quad_sum(float v)
     return v;
 }
 
+// exchange the upper half of a's lanes with the lower half of b's: a = [a_lo | b_lo], b = [a_hi | b_hi]
+__device__ __forceinline__ void swap_halves(float &a, float &b)
+{
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_int(a), __float_as_int(b), false, false);
+    a = __int_as_float(r[0]);
+    b = __int_as_float(r[1]);
+}
+
 template <int F>
-__global__ __launch_bounds__(256) void k_leg_synth_b(const float *__restrict__ brec,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_leg_synth_b(const float *__restrict__ brec,
                                                      const typename CoefB<F>::type *__restrict__ coef,
                                                      float2 *__restrict__ FG, int64_t fg_stride,
                                                      const Ent64 *__restrict__ ent, const int *__restrict__ entk,
@@ -1756,12 +1770,13 @@ __global__ __launch_bounds__(256) void k_leg_synth_b(const float *__restrict__ b
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     int m, blk;
     xcd_map((int)blockIdx.x, nbm, m, blk);
-    const int w = wbeg + blk * 4 + wave;  // 32 ring pairs 32 w .. 32 w + 31
+    const int w = wbeg + blk * 4 + wave;  // 64-pair group: pairs 64 w .. 64 w + 63
     if (m > lmax || w >= wend) return;
     const int l0 = m > 2 ? m : 2;
     const int64_t base = (int64_t)m * (2 * lmax + 1 - m) / 2;
-    const int p = 32 * w + i;
-    const int ls = __builtin_amdgcn_readfirstlane(uniform_ptr(entl + (int64_t)m * ng64)[w >> 1]);
+    const int p = 64 * w + lane;
+    // a group that never enters still writes its (zero) F
+    const int ls = __builtin_amdgcn_readfirstlane(uniform_ptr(entl + (int64_t)m * ng64)[w]);
 
     typename PosT<float, F>::type x;
     float c2 = 0.f, p2 = 0.f, cm = 0.f, pm = 0.f;
@@ -1771,9 +1786,11 @@ __global__ __launch_bounds__(256) void k_leg_synth_b(const float *__restrict__ b
         setpos(x, pair_z[p]);
         load_entry<float, F>(ent, entk, (int64_t)m * npairs + p, c2, p2, cm, pm, k);
     }
-    v16f D2e, D2o, Dme, Dmo;
+    v16f D2e[2], D2o[2], Dme[2], Dmo[2];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) D2e[r] = D2o[r] = Dme[r] = Dmo[r] = 0.f;
+    for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) D2e[s2][r] = D2o[s2][r] = Dme[s2][r] = Dmo[s2][r] = 0.f;
     bool ramp = wave_any(k < 0);
     using C = typename CoefB<F>::type;
     const_as<C> *cp = uniform_ptr(coef + base);
@@ -1791,12 +1808,18 @@ __global__ __launch_bounds__(256) void k_leg_synth_b(const float *__restrict__ b
             vm[t] = live ? cm : 0.f;
             rstep(ld_coef(cp + l + t), x, c2, p2, cm, pm);
         }
-        const float a2e = h ? v2[2] : v2[0], a2o = h ? v2[3] : v2[1];
-        const float ame = h ? vm[2] : vm[0], amo = h ? vm[3] : vm[1];
-        D2e = __builtin_amdgcn_mfma_f32_32x32x2f32(a2e, be, D2e, 0, 0, 0);
-        D2o = __builtin_amdgcn_mfma_f32_32x32x2f32(a2o, bo, D2o, 0, 0, 0);
-        Dme = __builtin_amdgcn_mfma_f32_32x32x2f32(ame, be, Dme, 0, 0, 0);
-        Dmo = __builtin_amdgcn_mfma_f32_32x32x2f32(amo, bo, Dmo, 0, 0, 0);
+        // degrees (l, l+2) and (l+1, l+3) of both halves of the pairs
+        swap_halves(v2[0], v2[2]);
+        swap_halves(v2[1], v2[3]);
+        swap_halves(vm[0], vm[2]);
+        swap_halves(vm[1], vm[3]);
+#pragma unroll
+        for (int s2 = 0; s2 < 2; ++s2) {
+            D2e[s2] = __builtin_amdgcn_mfma_f32_32x32x2f32(v2[2 * s2], be, D2e[s2], 0, 0, 0);
+            D2o[s2] = __builtin_amdgcn_mfma_f32_32x32x2f32(v2[2 * s2 + 1], bo, D2o[s2], 0, 0, 0);
+            Dme[s2] = __builtin_amdgcn_mfma_f32_32x32x2f32(vm[2 * s2], be, Dme[s2], 0, 0, 0);
+            Dmo[s2] = __builtin_amdgcn_mfma_f32_32x32x2f32(vm[2 * s2 + 1], bo, Dmo[s2], 0, 0, 0);
+        }
         if (ramp) {
             // once per four steps (the growth over four steps stays far from overflow)
             if (k < 0 && fmaxf(fabsf(c2), fabsf(cm)) > scale_hi<float>()) {
@@ -1811,32 +1834,35 @@ __global__ __launch_bounds__(256) void k_leg_synth_b(const float *__restrict__ b
         }
     }
     // F of the north and south ring of every (pair, rhs): quad sums over c, written by lane c = 0
-    const bool odd0 = ((l0 + m) & 1) != 0;
+    const bool odd0 = ((l0 + m) & 1) != 0;  // entries are l0 + 8 q: D2e holds degrees of parity l0 + m
     const int c = i & 3, rl = i >> 2, rhs = q * NBR + rl;
+    const float s0r = c == 0 ? -1.f : (c == 3 ? 1.f : 0.f), s0i = (c == 1 || c == 2) ? -1.f : 0.f;
+    const float s1r = (c == 0 || c == 3) ? -1.f : 0.f, s1i = c == 2 ? -1.f : (c == 1 ? 1.f : 0.f);
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        const int pi = 32 * w + 8 * (r >> 2) + 4 * h + (r & 3);
-        const float E2 = odd0 ? D2o[r] : D2e[r], O2 = odd0 ? D2e[r] : D2o[r];
-        const float Em = odd0 ? Dmo[r] : Dme[r], Om = odd0 ? Dme[r] : Dmo[r];
-        // north: S2 = E2 + O2, Sm = Em + Om;  south: S2 = Em - Om, Sm = E2 - O2
-        const float S2n = E2 + O2, Smn = Em + Om, S2s = Em - Om, Sms = E2 - O2;
-        // f0 = -(S2[0] - S2[3], S2[1] + S2[2]),  f1 = -(Sm[0] + Sm[3], Sm[2] - Sm[1])
-        const float s0r = c == 0 ? -1.f : (c == 3 ? 1.f : 0.f), s0i = (c == 1 || c == 2) ? -1.f : 0.f;
-        const float s1r = (c == 0 || c == 3) ? -1.f : 0.f, s1i = c == 2 ? -1.f : (c == 1 ? 1.f : 0.f);
-        const float fn0r = quad_sum(s0r * S2n), fn0i = quad_sum(s0i * S2n);
-        const float fn1r = quad_sum(s1r * Smn), fn1i = quad_sum(s1i * Smn);
-        const float fs0r = quad_sum(s0r * S2s), fs0i = quad_sum(s0i * S2s);
-        const float fs1r = quad_sum(s1r * Sms), fs1i = quad_sum(s1i * Sms);
-        if (c == 0 && rhs < nrhs && pi < npairs) {
-            float2 *Fb = FG + (int64_t)rhs * fg_stride;
-            const int rn = pi, rs = nrings - 1 - pi;
-            float2 *f = Fb + ((int64_t)rn * (lmax + 1) + m) * 2;
-            f[0] = make_float2(fn0r, fn0i);
-            f[1] = make_float2(fn1r, fn1i);
-            if (rs != rn) {
-                float2 *g = Fb + ((int64_t)rs * (lmax + 1) + m) * 2;
-                g[0] = make_float2(fs0r, fs0i);
-                g[1] = make_float2(fs1r, fs1i);
+    for (int s2 = 0; s2 < 2; ++s2) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int pi = 64 * w + 32 * s2 + 8 * (r >> 2) + 4 * h + (r & 3);
+            const float E2 = odd0 ? D2o[s2][r] : D2e[s2][r], O2 = odd0 ? D2e[s2][r] : D2o[s2][r];
+            const float Em = odd0 ? Dmo[s2][r] : Dme[s2][r], Om = odd0 ? Dme[s2][r] : Dmo[s2][r];
+            // north: S2 = E2 + O2, Sm = Em + Om;  south: S2 = Em - Om, Sm = E2 - O2
+            const float S2n = E2 + O2, Smn = Em + Om, S2s = Em - Om, Sms = E2 - O2;
+            // f0 = -(S2[0] - S2[3], S2[1] + S2[2]),  f1 = -(Sm[0] + Sm[3], Sm[2] - Sm[1])
+            const float fn0r = quad_sum(s0r * S2n), fn0i = quad_sum(s0i * S2n);
+            const float fn1r = quad_sum(s1r * Smn), fn1i = quad_sum(s1i * Smn);
+            const float fs0r = quad_sum(s0r * S2s), fs0i = quad_sum(s0i * S2s);
+            const float fs1r = quad_sum(s1r * Sms), fs1i = quad_sum(s1i * Sms);
+            if (c == 0 && rhs < nrhs && pi < npairs) {
+                float2 *Fb = FG + (int64_t)rhs * fg_stride;
+                const int rn = pi, rs = nrings - 1 - pi;
+                float2 *f = Fb + ((int64_t)rn * (lmax + 1) + m) * 2;
+                f[0] = make_float2(fn0r, fn0i);
+                f[1] = make_float2(fn1r, fn1i);
+                if (rs != rn) {
+                    float2 *g = Fb + ((int64_t)rs * (lmax + 1) + m) * 2;
+                    g[0] = make_float2(fs0r, fs0i);
+                    g[1] = make_float2(fs1r, fs1i);
+                }
             }
         }
     }
@@ -2053,7 +2079,7 @@ static void syn_dispatch(Plan &P, int nrhs, int64_t fg_stride, int g0)
 void launch_synth_batched(Plan &P, const double *xE, const double *xB, int64_t rstride, const double *kern)
 {
     const int64_t fg_stride = (int64_t)P.nrings * (P.lmax + 1) * 2;
-    const int nw = (int)cdiv(P.npairs, 32), wpol = 2 * P.polar_groups < nw ? 2 * P.polar_groups : nw;
+    const int nw = P.ng64, wpol = P.polar_groups;  // 64-pair groups
     const int64_t lblocks = cdiv(P.lmax + 1, 8);
     for (int q = 0; q * NBR < P.nrhs; ++q) {
         k_prologue_b<<<(unsigned)cdiv(P.nalm * NBR, 256), 256, 0, P.stream>>>(xE, xB, rstride, kern, P.d_lof, P.lmax,
@@ -2106,7 +2132,7 @@ void launch_entry(Plan &P)
     const int gpb = (int)cdiv(P.ng64, 4);
     k_entry<<<(unsigned)((int64_t)gpb * (P.lmax + 1)), 256, 0, P.stream>>>(
         P.d_seed2, P.d_seedm2, P.d_seedk, P.d_pair_z, P.d_coef64, P.d_ent, P.d_entk, P.d_entl, P.lmax, P.npairs, P.ng64,
-        gpb, P.prec == AKRA_FP32 ? 0x1p-44 : 0.0);
+        gpb, P.prec == AKRA_FP32 ? 0x1p-44 : 0x1p-100);
 }
 
 void launch_leg_synth(Plan &P, bool fp32, int nrhs)
