@@ -240,12 +240,21 @@ akra_status akra_plan_get_tuning(akra_plan plan, int *out5);
  * Work of one Legendre launch, in (l, m, ring pair) triples, written to out3 (HOST): [0] all triples
  * with max(2, m) <= l <= lmax; [1] those the synthesis evaluates and [2] those the adjoint evaluates
  * with the current launch shapes.  Below the degree where the recurrence values of a whole 64-pair
- * ring group first exceed the transform precision's underflow bound (2^-256 in FP64, 2^-44 in FP32
- * plans) their terms are masked to zero by the kernels anyway; they are skipped, and the kernels
- * start from recurrence states stored at plan creation.
+ * ring group first reach 2^-100 (FP64 plans; their sum is far under FP64 rounding) or 2^-44 (FP32
+ * plans; the FP32 kernels mask them) the terms are skipped, and the kernels start from recurrence
+ * states stored at plan creation.
  */
 akra_status akra_plan_work(akra_plan plan, int64_t *out3);
 akra_status akra_plan_set_timing(akra_plan plan, int on);
+/*
+ * Ring-stage kernel choice of plans created afterwards (process-wide, not thread-safe against
+ * concurrent akra_plan_create).  A ring whose length N is not a power of two is transformed whole by
+ * Bluestein when its convolution length (the power of two M >= 2N - 1) is at most maxm, else as two
+ * sub-transforms of length N / 2.  maxm: a power of two in [2, 8192]; default 8192, the largest
+ * convolution LDS holds in FP64.  Results do not depend on the choice beyond rounding; smaller values
+ * exist to exercise the split kernel at small sizes.  Errors: AKRA_ERR_ARG.
+ */
+akra_status akra_set_ring_whole_maxm(int maxm);
 akra_status akra_plan_stage_times(akra_plan plan, double *ms, int *calls);
 
 #ifdef __cplusplus

@@ -80,11 +80,12 @@ def lib():
     L.akra_cg_solve_vjp.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(CgOpts), vp, vp, vp, vp, vp, vp, vp,
                                     ctypes.POINTER(CgInfo)]
     L.akra_cg_solve_cond_b.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(CgOpts), vp, vp, ctypes.POINTER(CgInfo)]
+    L.akra_set_ring_whole_maxm.argtypes = [ctypes.c_int]
     L.akra_plan_stage_times.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int)]
     for f in ("akra_plan_create", "akra_synth2", "akra_adjoint2", "akra_apply_H", "akra_rhs", "akra_cg_solve",
               "akra_cg_solve_b", "akra_cg_start", "akra_cg_step", "akra_cg_state", "akra_plan_set_timing",
               "akra_plan_stage_times", "akra_plan_set_tuning", "akra_plan_get_tuning", "akra_plan_work",
-              "akra_cg_solve_vjp", "akra_cg_solve_cond_b"):
+              "akra_cg_solve_vjp", "akra_cg_solve_cond_b", "akra_set_ring_whole_maxm"):
         getattr(L, f).restype = ctypes.c_int
     _lib = L
     return L
@@ -93,6 +94,11 @@ def lib():
 def _check(st):
     if st != AKRA_OK:
         raise AkraError(st, lib().akra_last_error().decode())
+
+
+def set_ring_whole_maxm(maxm):
+    """Ring-stage kernel choice of plans created afterwards (see akra_set_ring_whole_maxm)."""
+    _check(lib().akra_set_ring_whole_maxm(int(maxm)))
 
 
 def alm_size(lmax):

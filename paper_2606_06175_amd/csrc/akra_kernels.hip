@@ -1082,15 +1082,15 @@ __global__ void k_weights(const double *__restrict__ ninv, const uint8_t *__rest
 }
 
 // ================================================================================================
-// Ring stage.  One workgroup per ring of N = 4L pixels.  The length-N DFTs are split into four
-// interleaved length-L sub-transforms (radix-4 step in registers); a sub-transform is a radix-2
-// FFT in LDS when L is a power of two, else Bluestein's chirp-z with a power-of-two FFT of length
-// M >= 2L - 1.  Synthesis direction: fold F(m), |m| <= lmax, into the N bins (phase e^{i m phi0}),
-// inverse DFT -> gamma at the pixels.  Adjoint direction: weight, forward DFT, unfold into every
-// |m| <= lmax (phase e^{-i m phi0}) and multiply by the pixel area.
+// Ring stage.  One workgroup per ring of N pixels.  Synthesis direction: fold F(m), |m| <= lmax,
+// into the N bins (phase e^{i m phi0}), inverse DFT -> gamma at the pixels.  Adjoint direction:
+// weight, forward DFT, unfold into every |m| <= lmax (phase e^{-i m phi0}) and multiply by the pixel
+// area.  Three kernels cover the rings: a radix-4 FFT of the whole ring in LDS when N is a power of
+// two, Bluestein's chirp-z over the whole ring when its convolution (a power-of-two length
+// M >= 2N - 1) fits in LDS, else two interleaved sub-transforms of length N / 2, each by Bluestein.
 // ================================================================================================
-constexpr int RT = 256;  // threads per ring workgroup
-constexpr int RU = 8;    // sub-transform elements per thread: L <= RT * RU
+constexpr int RT = 256;  // default thread count of the FFT helpers (and the chirp-spectrum kernel)
+constexpr int RU = 8;    // default elements per thread of dft_forward
 
 __device__ __forceinline__ unsigned brev(unsigned n, int logM) { return logM ? (__builtin_bitreverse32(n) >> (32 - logM)) : 0u; }
 
@@ -1225,171 +1225,21 @@ __device__ __forceinline__ void dft_forward(cplx<T> *buf, const cplx<T> *bhat, i
     __syncthreads();
 }
 
-// sum over m = bin (mod N), |m| <= lmax, of F(m) e^{i m phi0}, phi0 = pi shift / N
-template <typename T>
-__device__ __forceinline__ cplx<T> fold_bin(const cplx<T> *__restrict__ F, int bin, int N, int shift, int lmax)
-{
-    // m = bin + N t,  t in [tlo, thi]
-    const int tlo = -((lmax + bin) / N);
-    const int thi = (lmax >= bin) ? (lmax - bin) / N : -1;
-    T sr = 0, si = 0;
-    for (int t = tlo; t <= thi; ++t) {
-        const int m = bin + N * t;
-        cplx<T> f = (m >= 0) ? F[2 * m] : F[2 * (-m) + 1];
-        if (shift && (t & 1)) f = mk<T>(-f.x, -f.y);  // e^{i pi (N t) shift / N} = (-1)^(t shift)
-        sr += f.x;
-        si += f.y;
-    }
-    cplx<T> s = mk<T>(sr, si);
-    if (shift) s = cmul<T>(s, cis_pi<T>(bin, N));
-    return s;
-}
-
-template <typename T>
-__device__ __forceinline__ void unfold_bin(cplx<T> *__restrict__ G, int bin, int N, int shift, int lmax, cplx<T> y)
-{
-    if (shift) y = cmul<T>(y, cconj<T>(cis_pi<T>(bin, N)));
-    const int tlo = -((lmax + bin) / N);
-    const int thi = (lmax >= bin) ? (lmax - bin) / N : -1;
-    for (int t = tlo; t <= thi; ++t) {
-        const int m = bin + N * t;
-        const cplx<T> g = (shift && (t & 1)) ? mk<T>(-y.x, -y.y) : y;
-        if (m > 0) G[2 * m] = g;
-        else if (m < 0) G[2 * (-m) + 1] = g;
-        else {
-            G[0] = g;
-            G[1] = g;
-        }
-    }
-}
-
-// MODE 0: F -> maps (o1, o2).  MODE 1: maps (g1, g2) x W -> G.  MODE 2: F -> maps x W -> G in place.
-// MODE 3 (gradient of the solve): F = Y K x as maps px; with o1, o2 holding q = Y K u, per pixel
-//   o3 = M (omega q . (g - px) - c),   (o1, o2) = omega W q.
-template <typename T, int MODE>
-__global__ __launch_bounds__(RT) void k_ring(cplx<T> *__restrict__ FG, int64_t fg_stride, const double *__restrict__ g1,
-                                             const double *__restrict__ g2, double *__restrict__ o1,
-                                             double *__restrict__ o2, int64_t map_stride, const double *__restrict__ Wt,
-                                             const RingInfo *__restrict__ rings, const int *__restrict__ order,
-                                             const cplx<T> *__restrict__ tw, int twn, int lmax, double omega,
-                                             double *__restrict__ o3, const uint8_t *__restrict__ mask,
-                                             const double *__restrict__ cdev, const cplx<T> *__restrict__ bhat_all)
-{
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    cplx<T> *buf = reinterpret_cast<cplx<T> *>(smem_raw);
-    const int r = order[blockIdx.x];
-    const int rhs = blockIdx.y;
-    const RingInfo ri = rings[r];
-    const int N = ri.nphi, L = ri.sub, shift = ri.shift;
-    const bool blu = ri.M > 0;
-    const int M = blu ? ri.M : L;
-    const int logM = 31 - __builtin_clz(M);
-    // Bluestein rings: spectrum of the chirp for this L, computed at plan creation
-    const cplx<T> *bhat = bhat_all + (blu ? ri.bofs : 0);
-    cplx<T> *F = FG + rhs * fg_stride + (int64_t)r * (lmax + 1) * 2;
-    const int tid = threadIdx.x;
-    const int64_t pofs = rhs * map_stride + ri.ofs;
-
-    cplx<T> v[RU][4];
-    if (MODE != 1) {
-        // gamma[j1 + L j2] = sum_q i^(q j2) e^{2 pi i q j1/N} X_q[j1],  X_q = inverse DFT_L of bins 4k'+q
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            dft_forward<T>(
-                buf, bhat, L, M, logM, blu, tw, twn,
-                [&](int u) { return cconj<T>(fold_bin<T>(F, 4 * (tid + RT * u) + q, N, shift, lmax)); },
-                [&](int u, cplx<T> y) { v[u][q] = cconj<T>(y); });
-        }
-#pragma unroll
-        for (int u = 0; u < RU; ++u) {
-            const int j1 = tid + RT * u;
-            if (j1 >= L) continue;
-            const cplx<T> t0 = v[u][0];
-            const cplx<T> t1 = cmul<T>(cis_pi<T>(2 * (int64_t)j1, N), v[u][1]);
-            const cplx<T> t2 = cmul<T>(cis_pi<T>(4 * (int64_t)j1, N), v[u][2]);
-            const cplx<T> t3 = cmul<T>(cis_pi<T>(6 * (int64_t)j1, N), v[u][3]);
-            const cplx<T> a = cadd<T>(t0, t2), b = csub<T>(t0, t2), c = cadd<T>(t1, t3), d = cmuli<T>(csub<T>(t1, t3));
-            v[u][0] = cadd<T>(a, c);
-            v[u][1] = cadd<T>(b, d);
-            v[u][2] = csub<T>(a, c);
-            v[u][3] = csub<T>(b, d);
-        }
-    }
-    if (MODE == 0) {
-#pragma unroll
-        for (int u = 0; u < RU; ++u) {
-            const int j1 = tid + RT * u;
-            if (j1 >= L) continue;
-#pragma unroll
-            for (int j2 = 0; j2 < 4; ++j2) {
-                o1[pofs + j1 + L * j2] = (double)v[u][j2].x;
-                o2[pofs + j1 + L * j2] = (double)v[u][j2].y;
-            }
-        }
-        return;
-    }
-    if (MODE == 3) {
-        const double c = *cdev;
-#pragma unroll
-        for (int u = 0; u < RU; ++u) {
-            const int j1 = tid + RT * u;
-            if (j1 >= L) continue;
-#pragma unroll
-            for (int j2 = 0; j2 < 4; ++j2) {
-                const int64_t pix = pofs + j1 + L * j2;
-                const int64_t pm = ri.ofs + j1 + L * j2;  // the mask is shared by all right-hand sides
-                const double q1 = o1[pix], q2 = o2[pix];
-                const double r1 = g1[pix] - (double)v[u][j2].x, r2 = g2[pix] - (double)v[u][j2].y;
-                o3[pix] = mask[pm] ? omega * (q1 * r1 + q2 * r2) - c : 0.0;
-                const double w = omega * Wt[pix];
-                o1[pix] = w * q1;
-                o2[pix] = w * q2;
-            }
-        }
-        return;
-    }
-#pragma unroll
-    for (int u = 0; u < RU; ++u) {
-        const int j1 = tid + RT * u;
-        if (j1 >= L) continue;
-#pragma unroll
-        for (int j2 = 0; j2 < 4; ++j2) {
-            const int64_t pix = pofs + j1 + L * j2;
-            if (MODE == 1) {
-                const T w = Wt ? (T)Wt[pix] : (T)1;
-                v[u][j2] = mk<T>((T)g1[pix] * w, (T)g2[pix] * w);
-            } else {
-                const T w = (T)Wt[pix];
-                v[u][j2] = cscale<T>(v[u][j2], w);
-            }
-        }
-        // u_q = e^{-2 pi i q j1/N} sum_j2 (-i)^(j2 q) h[j1 + L j2]
-        const cplx<T> h0 = v[u][0], h1 = v[u][1], h2 = v[u][2], h3 = v[u][3];
-        const cplx<T> a = cadd<T>(h0, h2), b = csub<T>(h0, h2), c = cadd<T>(h1, h3), d = cmuli<T>(csub<T>(h1, h3));
-        v[u][0] = cadd<T>(a, c);
-        v[u][1] = cmul<T>(cconj<T>(cis_pi<T>(2 * (int64_t)j1, N)), csub<T>(b, d));
-        v[u][2] = cmul<T>(cconj<T>(cis_pi<T>(4 * (int64_t)j1, N)), csub<T>(a, c));
-        v[u][3] = cmul<T>(cconj<T>(cis_pi<T>(6 * (int64_t)j1, N)), cadd<T>(b, d));
-    }
-    const T om = (T)omega;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        dft_forward<T>(
-            buf, bhat, L, M, logM, blu, tw, twn, [&](int u) { return v[u][q]; },
-            [&](int u, cplx<T> y) { unfold_bin<T>(F, 4 * (tid + RT * u) + q, N, shift, lmax, cscale<T>(y, om)); });
-    }
-}
-
+// Ring kernels.  MODE 0: F -> maps (o1, o2).  MODE 1: maps (g1, g2) x W -> G.  MODE 2: F -> maps x W -> G
+// in place.  MODE 3 (gradient of the solve): F = Y K x as maps px; with o1, o2 holding q = Y K u, per
+// pixel  o3 = M (omega q . (g - px) - c),   (o1, o2) = omega W q.
 // ================================================================================================
 // Ring stage for rings whose length N is a power of two (the equatorial belt when Nside is one):
 // the length-N transforms run directly in LDS, one workgroup of RF threads per ring.  F is folded
 // and G unfolded in m order, so neighbouring threads read and write neighbouring entries of the
 // ring's row; each direction is one radix-4 FFT (ceil(log2 N / 2) passes) with the inverse
 // transform taking natural input to bit-reversed output and the forward one back.
-// MODE as for k_ring.
+// MODE as above.
 // ================================================================================================
 constexpr int RF = 1024;  // threads per ring workgroup
 constexpr int RFU = 8;    // elements per thread: N <= RF * RFU
+
+template <typename T> __device__ __forceinline__ cplx<T> to_t(double2 z) { return mk<T>((T)z.x, (T)z.y); }
 
 // e^{i pi (k0 + k1 u) / den} for u = 0, 1, ... as a running FP64 product (one rounding per step)
 struct PhaseSeq {
@@ -1550,7 +1400,7 @@ __global__ __launch_bounds__(RF) void k_ring_full(cplx<T> *__restrict__ FG, int6
 // Ring stage for rings of any length N whose Bluestein convolution (length M >= 2N - 1, a power of
 // two) fits in LDS: one DFT of the whole ring per direction by Bluestein's chirp-z, with the chirp
 // spectrum of length N from the plan's table; fold and unfold in m order as in k_ring_full.
-// MODE as for k_ring.
+// MODE as above.
 // ================================================================================================
 constexpr int RBU = 4;  // elements per thread: N <= RF * RBU
 
@@ -1636,6 +1486,128 @@ __global__ __launch_bounds__(RF) void k_ring_bfull(cplx<T> *__restrict__ FG, int
             const double2 e = ph.next();
             unfold_bin_ph<T>(F, tid + RF * u, N, rN, shift, lmax, cscale<T>(y, om), e);
         });
+}
+
+// ================================================================================================
+// Ring stage for the remaining rings (whole-ring convolution too long for LDS): the length-N DFT
+// (N even) splits into two interleaved sub-DFTs of length L = N / 2 over the even and odd bins, each
+// by Bluestein with the chirp spectrum of length L; the radix-2 step in registers combines them:
+//   synthesis  gamma[j1] = Y0[j1] + w^j1 Y1[j1],  gamma[j1 + L] = Y0[j1] - w^j1 Y1[j1],  w = e^{2 pi i/N}
+//   adjoint    u_q[j1] = w^{-q j1} (h[j1] + (-1)^q h[j1 + L]),  bins 2 k + q = DFT_L(u_q)[k].
+// MODE as above.
+// ================================================================================================
+template <typename T, int MODE>
+__global__ __launch_bounds__(RF) void k_ring_b2(cplx<T> *__restrict__ FG, int64_t fg_stride,
+                                                const double *__restrict__ g1, const double *__restrict__ g2,
+                                                double *__restrict__ o1, double *__restrict__ o2, int64_t map_stride,
+                                                const double *__restrict__ Wt, const RingInfo *__restrict__ rings,
+                                                const int *__restrict__ order, const cplx<T> *__restrict__ tw,
+                                                int twn, int lmax, double omega, double *__restrict__ o3,
+                                                const uint8_t *__restrict__ mask, const double *__restrict__ cdev,
+                                                const cplx<T> *__restrict__ bhat_all)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cplx<T> *buf = reinterpret_cast<cplx<T> *>(smem_raw);
+    const int r = order[blockIdx.x];
+    const int rhs = blockIdx.y;
+    const RingInfo ri = rings[r];
+    const int N = ri.nphi, L = N / 2, shift = ri.shift, M = ri.M;
+    const int logM = 31 - __builtin_clz(M);
+    const cplx<T> *bhat = bhat_all + ri.bofs;
+    cplx<T> *F = FG + rhs * fg_stride + (int64_t)r * (lmax + 1) * 2;
+    const int tid = threadIdx.x;
+    const int64_t pofs = rhs * map_stride + ri.ofs;
+    const float rN = 1.0f / (float)N;
+    cplx<T> v[RBU][2];
+
+    if (MODE != 1) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            // Y_q = inverse DFT_L of the bins 2 k + q; get and put run in u order
+            PhaseSeq ph(2 * tid + q, 2 * RF, N);  // e^{i pi b / N} along b = 2 (tid + RF u) + q
+            dft_forward<T, RF, RBU>(
+                buf, bhat, L, M, logM, true, tw, twn,
+                [&](int u) {
+                    const double2 e = ph.next();
+                    return cconj<T>(fold_bin_ph<T>(F, 2 * (tid + RF * u) + q, N, rN, shift, lmax, e));
+                },
+                [&](int u, cplx<T> y) { v[u][q] = cconj<T>(y); });
+        }
+        PhaseSeq pw(2 * tid, 2 * RF, N);  // e^{2 pi i j1 / N}
+#pragma unroll
+        for (int u = 0; u < RBU; ++u) {
+            const int j1 = tid + RF * u;
+            const double2 w = pw.next();
+            if (j1 >= L) continue;
+            const cplx<T> t = cmul<T>(to_t<T>(w), v[u][1]), a = v[u][0];
+            v[u][0] = cadd<T>(a, t);
+            v[u][1] = csub<T>(a, t);
+        }
+    }
+    if (MODE == 0) {
+#pragma unroll
+        for (int u = 0; u < RBU; ++u) {
+            const int j1 = tid + RF * u;
+            if (j1 >= L) continue;
+#pragma unroll
+            for (int j2 = 0; j2 < 2; ++j2) {
+                o1[pofs + j1 + L * j2] = (double)v[u][j2].x;
+                o2[pofs + j1 + L * j2] = (double)v[u][j2].y;
+            }
+        }
+        return;
+    }
+    if (MODE == 3) {
+        const double c = *cdev;
+#pragma unroll
+        for (int u = 0; u < RBU; ++u) {
+            const int j1 = tid + RF * u;
+            if (j1 >= L) continue;
+#pragma unroll
+            for (int j2 = 0; j2 < 2; ++j2) {
+                const int64_t pix = pofs + j1 + L * j2;
+                const int64_t pm = ri.ofs + j1 + L * j2;  // the mask is shared by all right-hand sides
+                const double q1 = o1[pix], q2 = o2[pix];
+                const double r1 = g1[pix] - (double)v[u][j2].x, r2 = g2[pix] - (double)v[u][j2].y;
+                o3[pix] = mask[pm] ? omega * (q1 * r1 + q2 * r2) - c : 0.0;
+                const double w = omega * Wt[pix];
+                o1[pix] = w * q1;
+                o2[pix] = w * q2;
+            }
+        }
+        return;
+    }
+    PhaseSeq pw(2 * tid, 2 * RF, N);
+#pragma unroll
+    for (int u = 0; u < RBU; ++u) {
+        const int j1 = tid + RF * u;
+        const double2 w = pw.next();
+        if (j1 >= L) continue;
+#pragma unroll
+        for (int j2 = 0; j2 < 2; ++j2) {
+            const int64_t pix = pofs + j1 + L * j2;
+            if (MODE == 1) {
+                const T wt = Wt ? (T)Wt[pix] : (T)1;
+                v[u][j2] = mk<T>((T)g1[pix] * wt, (T)g2[pix] * wt);
+            } else {
+                v[u][j2] = cscale<T>(v[u][j2], (T)Wt[pix]);
+            }
+        }
+        const cplx<T> h0 = v[u][0], h1 = v[u][1];
+        v[u][0] = cadd<T>(h0, h1);
+        v[u][1] = cmul<T>(cconj<T>(to_t<T>(w)), csub<T>(h0, h1));
+    }
+    const T om = (T)omega;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        PhaseSeq pf(2 * tid + q, 2 * RF, N);  // put runs in u order
+        dft_forward<T, RF, RBU>(
+            buf, bhat, L, M, logM, true, tw, twn, [&](int u) { return v[u][q]; },
+            [&](int u, cplx<T> y) {
+                const double2 e = pf.next();
+                unfold_bin_ph<T>(F, 2 * (tid + RF * u) + q, N, rN, shift, lmax, cscale<T>(y, om), e);
+            });
+    }
 }
 
 // ================================================================================================
@@ -2240,9 +2212,9 @@ static void ring_launch_t(Plan &P, const double *g1, const double *g2, double *o
     }
     if (P.n_bl) {
         size_t sm = sizeof(cplx<T>) * (size_t)(P.maxM_bl + P.maxM_bl / 32);
-        k_ring<T, MODE><<<dim3(P.n_bl, nrhs), RT, sm, P.stream>>>((cplx<T> *)P.d_FG, fg_stride, g1, g2, o1, o2, P.npix,
-                                                                  W, P.d_rings, P.d_order_bl, (const cplx<T> *)tw,
-                                                                  P.twn, P.lmax, P.omega, o3, mask, cdev, bh);
+        k_ring_b2<T, MODE><<<dim3(P.n_bl, nrhs), RF, sm, P.stream>>>(
+            (cplx<T> *)P.d_FG, fg_stride, g1, g2, o1, o2, P.npix, W, P.d_rings, P.d_order_bl, (const cplx<T> *)tw,
+            P.twn, P.lmax, P.omega, o3, mask, cdev, bh);
     }
 }
 

@@ -23,6 +23,8 @@
 namespace akra {
 
 static thread_local std::string g_err;
+// largest whole-ring Bluestein convolution of plans created afterwards (akra_set_ring_whole_maxm)
+static int g_ring_whole_maxm = 8192;
 void set_error(const std::string &msg) { g_err = msg; }
 akra_status hip_fail(hipError_t e, const char *what)
 {
@@ -285,9 +287,9 @@ static akra_status create(int nside, int lmax, int nrhs, int prec, void *stream,
     build_rings(*P);
 
     // ring launch lists, largest first: power-of-two rings (whole-ring FFT), rings whose whole-ring
-    // Bluestein convolution fits in LDS (M <= BF_MAXM), and the rest (four sub-transforms, each
-    // by Bluestein)
-    constexpr int BF_MAXM = 8192;
+    // Bluestein convolution fits in LDS (M <= BF_MAXM), and the rest as two sub-transforms of length
+    // N / 2, each by Bluestein (M <= 8192 since N <= 4 nside <= 8192)
+    const int BF_MAXM = g_ring_whole_maxm;
     std::vector<int> p2, bl, bf;
     int maxp2 = 1, maxbl = 1, maxbf = 1;
     for (int r = 0; r < P->nrings; ++r) {
@@ -304,8 +306,11 @@ static akra_status create(int nside, int lmax, int nrhs, int prec, void *stream,
             bf.push_back(r);
             maxbf = std::max(maxbf, MF);
         } else {
+            int M2 = 1;
+            while (M2 < ri.nphi - 1) M2 <<= 1;  // 2 (N / 2) - 1
+            ri.M = M2;
             bl.push_back(r);
-            maxbl = std::max(maxbl, ri.M);
+            maxbl = std::max(maxbl, M2);
         }
     }
     auto bysize = [&](int a, int b) { return P->h_rings[a].nphi > P->h_rings[b].nphi; };
@@ -320,8 +325,8 @@ static akra_status create(int nside, int lmax, int nrhs, int prec, void *stream,
     P->maxM_bf = maxbf;
     // twiddles for the Bluestein convolutions and for whole power-of-two rings (N = 4 sub)
     P->twn = std::max(2, std::max(4 * maxp2, std::max(maxbl, maxbf)));
-    // one chirp spectrum per distinct chirp length: the sub length of the split rings, the ring
-    // length of the whole-ring ones (the two caps share them)
+    // one chirp spectrum per distinct chirp length: N / 2 for the split rings, N for the whole-ring
+    // ones (the two caps share them)
     std::vector<int> bL, bM;
     std::vector<int64_t> bO;
     int64_t btot = 0;
@@ -338,7 +343,7 @@ static akra_status create(int nside, int lmax, int nrhs, int prec, void *stream,
             }
             ri.bofs = at[len];
         };
-        for (int r : bl) key(r, P->h_rings[r].sub);
+        for (int r : bl) key(r, P->h_rings[r].nphi / 2);
         for (int r : bf) key(r, P->h_rings[r].nphi);
     }
 
@@ -1576,6 +1581,16 @@ akra_status akra_plan_set_tuning(akra_plan plan, int syn_variant, int syn_rings,
     P.adj_L = adj_chunk;
     P.adj_nrb = nrb;
     compute_work(P);
+    return AKRA_OK;
+}
+
+akra_status akra_set_ring_whole_maxm(int maxm)
+{
+    if (maxm < 2 || maxm > 8192 || (maxm & (maxm - 1))) {
+        set_error("ring whole-transform bound must be a power of two in [2, 8192]");
+        return AKRA_ERR_ARG;
+    }
+    g_ring_whole_maxm = maxm;
     return AKRA_OK;
 }
 

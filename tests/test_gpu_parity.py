@@ -170,3 +170,58 @@ def test_batched_fp32_matrix_core_path(torch_dev, nside, lmax, nrhs):
     for k in range(nrhs):
         ref = o.apply_H(np.stack([A[k], B[k]]), o.weights(ninvs[k], mask), 0.02)
         assert rel(np.stack([yE[k].cpu().numpy(), yB[k].cpu().numpy()]), ref) < TOL["fp32"], k
+
+
+@pytest.fixture
+def split_rings():
+    # plans created meanwhile transform every ring whose length is not a power of two as two
+    # sub-transforms of length N / 2 (the kernel the largest cap rings use at Nside above 1024)
+    from paper_2606_06175_amd import akra
+    akra.set_ring_whole_maxm(2)
+    yield
+    akra.set_ring_whole_maxm(8192)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("nside,lmax", [(3, 12), (13, 40), (100, 200)])
+def test_split_ring_kernel(torch_dev, split_rings, nside, lmax, prec):
+    torch, dev = torch_dev
+    o = Oracle(lmax, healpix_rings(nside))
+    aE, aB = wl.random_alm(lmax, 400 + nside), wl.random_alm(lmax, 500 + nside)
+    p = _plan(nside, lmax, prec)
+    g1, g2 = p.synth2(torch.from_numpy(aE).to(dev), torch.from_numpy(aB).to(dev))
+    r1, r2 = o.synth(aE, aB)
+    assert rel(np.r_[g1.cpu().numpy(), g2.cpu().numpy()], np.r_[r1, r2]) < TOL[prec]
+    h1, h2 = wl.random_maps(o.rings.npix, 600 + nside)
+    cE, cB = p.adjoint2(torch.from_numpy(h1).to(dev), torch.from_numpy(h2).to(dev))
+    rE, rB = o.adjoint(h1, h2)
+    assert rel(np.r_[cE.cpu().numpy(), cB.cpu().numpy()], np.r_[rE, rB]) < TOL[prec]
+    mask, ninv = _mask_ninv(nside, 7)
+    yE, yB = p.apply_H(torch.from_numpy(ninv).to(dev), torch.from_numpy(mask).to(dev),
+                       torch.from_numpy(aE).to(dev), torch.from_numpy(aB).to(dev), 0.02)
+    ref = o.apply_H(np.stack([aE, aB]), o.weights(ninv, mask), 0.02)
+    assert rel(np.stack([yE.cpu().numpy(), yB.cpu().numpy()]), ref) < TOL[prec]
+
+
+def test_split_ring_kernel_gradient(torch_dev, split_rings):
+    # the gradient epilogue of the split kernel against the same gradient with whole-ring kernels
+    torch, dev = torch_dev
+    from paper_2606_06175_amd import AkraSolve, Plan, akra
+    nside, lmax = 13, 26
+    mask, ninv = _mask_ninv(nside, 9)
+    g1, g2 = (m * mask for m in wl.random_maps(12 * nside * nside, 10))
+    cE = torch.from_numpy(wl.random_alm(lmax, 11)).to(dev)
+
+    def grads():
+        p = Plan(nside, lmax, precision="fp64", device=dev)
+        t = [torch.tensor(a, dtype=torch.float64, device=dev, requires_grad=True) for a in (g1, g2, ninv)]
+        xE, xB = AkraSolve.apply(t[0], t[1], t[2], torch.from_numpy(mask).to(dev), p, dict(tol=1e-13, maxiter=5000))
+        L = (cE.real * xE.real + cE.imag * xE.imag).sum() + 0.5 * (xB.real ** 2 + xB.imag ** 2).sum()
+        L.backward()
+        return [a.grad.cpu().numpy() for a in t]
+
+    split = grads()
+    akra.set_ring_whole_maxm(8192)
+    whole = grads()
+    for a, b in zip(split, whole):
+        assert rel(a, b) < 1e-9
