@@ -32,9 +32,9 @@ FLOP_PER_TRIPLE = 26     # per (l, m, ring pair) and direction: 2 recurrences (1
 # workload, each scaled by the same counter's reading for a device copy of known size; valid only for
 # the kernel source they were taken from (its SHA-256 is checked at run time).
 TRAFFIC = {
-    # profiles/k_leg_adj_nside2048_lmax4096_fp64.md: FETCH 2.3555e6 KiB x 1.99994 + WRITE 3.3155e6 KiB x 1.0000
-    "leg_adj": {"bytes": 8.2189e9, "workload": (2048, 4096),
-                "kernels_sha256": "2024379d37f4c8f9b7a3fee0f5c2058a6081d63dae1f7481c0c343fdf775229a"},
+    # profiles/k_leg_adj_nside2048_lmax4096_fp64.md: FETCH 2.4884e6 KiB x 1.99994 + WRITE 3.1589e6 KiB x 1.0000
+    "leg_adj": {"bytes": 8.3309e9, "workload": (2048, 4096),
+                "kernels_sha256": "128d810e83c49b02a0081d2d01ca5a18c1189084a0d8e4fd45826b891591448c"},
 }
 
 
@@ -287,8 +287,8 @@ def main():
                 "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_FP64, "traffic": traffic(dom, nside, lmax),
                 "algorithmic": "26 flop x %d evaluated (l, m, ring-pair) triples = %.4g flop per launch "
-                               "(all triples T = %d; below each ring group's entry degree the terms are zero "
-                               "and are skipped)" % (evaluated[dom], flops, T)}
+                               "(all triples T = %d; the terms below each ring group's entry degree, where its "
+                               "recurrence values first reach 2^-100, are skipped)" % (evaluated[dom], flops, T)}
     # ring stage against HBM: F read and G written (32 B per (ring, m) each) and W read (8 B per pixel)
     ring_bytes = 2 * 32 * (4 * nside - 1) * (lmax + 1) + 8 * 12 * nside * nside
     roofline["ring_algorithmic_bytes"] = ring_bytes
