@@ -39,7 +39,7 @@ CONFIGS = {
 _CFG_NUM = {"C1": 1, "C2": 2, "C3": 3, "C4": 4, "C5": 5}
 
 # random-stream ids inside one configuration
-S_KAPPA, S_FOOT, S_COUNTS, S_NOISE, S_DEPTH, S_ROT = 1, 2, 3, 4, 5, 6
+S_KAPPA, S_FOOT, S_COUNTS, S_NOISE, S_DEPTH, S_ROT, S_SHUFFLE, S_SPLIT = 1, 2, 3, 4, 5, 6, 7, 8
 
 
 def rng(seed_base, stream):
@@ -238,3 +238,36 @@ def make_config(name, nside=None, lmax=None):
         bins.append(b)
     return dict(name=name, nside=nside, lmax=lmax, nrhs=nrhs, mask=mask.astype(np.uint8), ninv=ninv,
                 kappa=np.stack(kappa), eps1=np.stack(e1), eps2=np.stack(e2), bin=np.array(bins))
+
+
+# ---------------------------------------------------------------------------------------------
+# shape-noise realisations and split halves (Sec. IV power spectra)
+# ---------------------------------------------------------------------------------------------
+def shuffle_perms(n_obs, n_real, seed_base, half=0):
+    """n_real independent uniform permutations of 0 .. n_obs-1 (int32, shape (n_real, n_obs)).
+
+    The random draw of the pixel-shuffling procedure; `half` selects an independent stream for
+    the second half of a split sample."""
+    g = rng(seed_base, S_SHUFFLE + 100 * int(half))
+    out = np.empty((int(n_real), int(n_obs)), np.int32)
+    for k in range(int(n_real)):
+        out[k] = g.permutation(int(n_obs))
+    return out
+
+
+def split_halves(cfg, seed_base):
+    """Two disjoint random halves of the per-pixel galaxies of configuration `cfg` (first bin).
+
+    Each galaxy goes to half A or B with probability 1/2: n_A ~ Binomial(n, 1/2), n_B = n - n_A.
+    Returns ninv (2, Npix) = n_half / sigma_e^2 and independent shape noise eps1, eps2 (2, Npix)
+    with per-component standard deviation sigma_e / sqrt(n_half), zero where n_half = 0 or the
+    shared mask is 0."""
+    counts = np.rint(cfg["ninv"][0] * SIGMA_E ** 2).astype(np.int64)
+    g = rng(seed_base, S_SPLIT)
+    na = g.binomial(counts, 0.5)
+    halves = np.stack([na, counts - na])
+    mask = cfg["mask"].astype(bool)
+    sd = np.where(halves > 0, SIGMA_E / np.sqrt(np.maximum(halves, 1)), 0.0)
+    e1 = sd * g.normal(size=halves.shape) * mask
+    e2 = sd * g.normal(size=halves.shape) * mask
+    return dict(ninv=halves / SIGMA_E ** 2, eps1=e1, eps2=e2)
