@@ -257,6 +257,96 @@ akra_status akra_plan_set_timing(akra_plan plan, int on);
 akra_status akra_set_ring_whole_maxm(int maxm);
 akra_status akra_plan_stage_times(akra_plan plan, double *ms, int *calls);
 
+/*
+ * Shape-noise realisations and power spectra (Sec. IV, power spectrum results).  The paper estimates
+ * the shape-noise bias N_l of an auto spectrum, and the error bars of auto and cross spectra, from
+ * realisations made by permuting the observed shear at random among the unmasked pixels and passing
+ * each permuted map through the full reconstruction; the cross spectrum correlates the
+ * reconstructions of two disjoint random halves of the sample.  The random permutations are
+ * inputs.  The paper gives no formula for the spectrum; these calls take, for coefficient sets X, Y
+ * of real fields (m >= 0 storage),
+ *   C_l^{XY} = (2l+1)^-1 [ Re(X_l0 conj Y_l0) + 2 sum_{m>0} Re(X_lm conj Y_lm) ]   (l >= 2),
+ *   C_0 = C_1 = 0,
+ * with no mask, f_sky or shear-calibration correction.  The shuffle moves the shear only: the
+ * weights W = M N^-1 stay with their pixels.
+ */
+
+/*
+ * Ascending RING indices of the unmasked pixels (mask != 0).
+ *   mask   device uint8 [Npix];
+ *   idx    device int32 [Npix] capacity; the first n_obs entries are written;
+ *   n_obs  HOST int64, out.
+ * Synchronises the plan stream.  Errors: AKRA_ERR_ARG (null pointers), AKRA_ERR_HIP.
+ */
+akra_status akra_unmasked_index(akra_plan plan, const uint8_t *mask, int32_t *idx, int64_t *n_obs);
+
+/*
+ * Shear permuted among the unmasked pixels, for realisations k < n_real and j < n_obs:
+ *   g1_out[k][idx[j]] = g1[idx[perm[k][j]]],  g2_out[k][idx[j]] = g2[idx[perm[k][j]]],
+ * and 0 at every other pixel of g1_out[k], g2_out[k].
+ *   g1, g2          device float64 [Npix];
+ *   idx             device int32 [n_obs], the list akra_unmasked_index returns (0 <= n_obs <= Npix);
+ *   perm            device int32 [n_real][n_obs]; each row should be a permutation of 0 .. n_obs-1
+ *                   (not checked), every entry must lie in [0, n_obs) (checked);
+ *   g1_out, g2_out  device float64 [n_real][Npix]; must not overlap the inputs or each other.
+ * Synchronises the plan stream.  Errors: AKRA_ERR_ARG for null pointers, counts out of range,
+ * overlapping outputs, or an entry of perm or idx out of range (entries out of range are skipped and
+ * the outputs are then incomplete), AKRA_ERR_HIP.
+ */
+akra_status akra_shuffle_shear(akra_plan plan, const double *g1, const double *g2, const int32_t *idx, int64_t n_obs,
+                               const int32_t *perm, int n_real, double *g1_out, double *g2_out);
+
+/*
+ * Spectra C_l^{XY} of coefficient pairs: for q < npairs, cl[q] = C^{x[i] y[j]} with
+ * (i, j) = (pairs[2q], pairs[2q+1]).
+ *   x      device complex128 [nx][n_alm];  y  device complex128 [ny][n_alm] (y == x allowed);
+ *   pairs  HOST int32 [npairs][2], 0 <= i < nx, 0 <= j < ny;
+ *   cl     device float64 [npairs][lmax+1].
+ * Stream-ordered, no host synchronisation; the sum over m has a fixed order, so results repeat
+ * bit for bit.  Errors: AKRA_ERR_ARG (null pointers, negative counts, a pair out of range),
+ * AKRA_ERR_HIP.
+ */
+akra_status akra_alm_spectra(akra_plan plan, const double *x, int nx, const double *y, int ny, const int32_t *pairs,
+                             int npairs, double *cl);
+
+/*
+ * Device bytes of the workspace akra_noise_spectra needs for nset (1 or 2) shear sets, written to
+ * *bytes (HOST): the unmasked list, the shuffled maps and the solutions of max(nrhs, nset) right-hand
+ * sides.  Errors: AKRA_ERR_ARG.
+ */
+akra_status akra_noise_work_size(akra_plan plan, int nset, int64_t *bytes);
+
+/*
+ * Shape-noise realisations through the full solve, and their spectra.
+ *   nset = 1  g1, g2, ninv: device float64 [Npix].  Realisation k solves the shear shuffled by
+ *             perm[k] (the akra_shuffle_shear rule) with the unshuffled ninv and mask, and keeps the
+ *             auto spectra of its solution x = (E, B).
+ *   nset = 2  split halves A, B: g1, g2, ninv are [2][Npix].  Realisation k shuffles half q with
+ *             perm[q][k], solves both halves and keeps the cross spectra of the two solutions.
+ *   mask      device uint8 [Npix], shared by every solve;
+ *   perm      device int32 [nset][n_real][n_obs], n_obs = the number of unmasked pixels (checked);
+ *   opts      as for akra_cg_solve.  opts->mode picks the unknowns and the spectra kept:
+ *             AKRA_JOINT_EB  nspec = 3: (EE, BB, EB); for nset = 2 (A_E B_E, A_B B_B, A_E B_B),
+ *             AKRA_E_ONLY    nspec = 1: EE,   AKRA_B_ONLY  nspec = 1: BB;
+ *   work      device workspace of work_bytes >= akra_noise_work_size(plan, nset) bytes;
+ *   cl        device float64 [n_real][nspec][lmax+1];
+ *   cl_mean, cl_std  device float64 [nspec][lmax+1] or NULL: the mean over the realisations (for
+ *             nset = 1 the noise-bias estimate N_l) and the sample standard deviation (n_real - 1 in
+ *             the denominator; 0 when n_real < 2);
+ *   info      HOST, nullable: iters and fp64_applies summed over the solves, the worst rel_resid and
+ *             rel_resid_true, lambda_eff and precond of the first solve, the worst status.
+ * The right-hand sides are solved in groups of the plan's nrhs (the batched solver on FP32 plans
+ * with nrhs > 1); with nset = 2 and nrhs > 1, nrhs must be even.  A last, partial group is filled
+ * with zero shear, which the solver finishes without iterating.  Synchronises the plan stream.
+ * Errors: AKRA_ERR_ARG (null pointers, sizes, n_obs differing from the mask, a perm entry out of
+ * range, a small workspace), the errors of akra_cg_solve, AKRA_NOT_CONVERGED when some solve stopped
+ * at maxiter (its spectra are those of the last iterate).
+ */
+akra_status akra_noise_spectra(akra_plan plan, int nset, const double *g1, const double *g2, const double *ninv,
+                               const uint8_t *mask, const int32_t *perm, int64_t n_obs, int n_real,
+                               const akra_cg_opts *opts, void *work, int64_t work_bytes, double *cl,
+                               double *cl_mean, double *cl_std, akra_cg_info *info);
+
 #ifdef __cplusplus
 }
 #endif

@@ -82,10 +82,17 @@ def lib():
     L.akra_cg_solve_cond_b.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(CgOpts), vp, vp, ctypes.POINTER(CgInfo)]
     L.akra_set_ring_whole_maxm.argtypes = [ctypes.c_int]
     L.akra_plan_stage_times.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int)]
+    L.akra_unmasked_index.argtypes = [vp, vp, vp, ctypes.POINTER(i64)]
+    L.akra_shuffle_shear.argtypes = [vp, vp, vp, vp, i64, vp, ctypes.c_int, vp, vp]
+    L.akra_alm_spectra.argtypes = [vp, vp, ctypes.c_int, vp, ctypes.c_int, vp, ctypes.c_int, vp]
+    L.akra_noise_work_size.argtypes = [vp, ctypes.c_int, ctypes.POINTER(i64)]
+    L.akra_noise_spectra.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp, vp, i64, ctypes.c_int,
+                                     ctypes.POINTER(CgOpts), vp, i64, vp, vp, vp, ctypes.POINTER(CgInfo)]
     for f in ("akra_plan_create", "akra_synth2", "akra_adjoint2", "akra_apply_H", "akra_rhs", "akra_cg_solve",
               "akra_cg_solve_b", "akra_cg_start", "akra_cg_step", "akra_cg_state", "akra_plan_set_timing",
               "akra_plan_stage_times", "akra_plan_set_tuning", "akra_plan_get_tuning", "akra_plan_work",
-              "akra_cg_solve_vjp", "akra_cg_solve_cond_b", "akra_set_ring_whole_maxm"):
+              "akra_cg_solve_vjp", "akra_cg_solve_cond_b", "akra_set_ring_whole_maxm", "akra_unmasked_index",
+              "akra_shuffle_shear", "akra_alm_spectra", "akra_noise_work_size", "akra_noise_spectra"):
         getattr(L, f).restype = ctypes.c_int
     _lib = L
     return L
@@ -320,6 +327,94 @@ class Plan:
         if st != AKRA_OK and (st != AKRA_NOT_CONVERGED or raise_not_converged):
             _check(st)
         return kB, self._info(inf, keep, hist_len)
+
+    # -- shape-noise realisations and spectra (Sec. IV power spectra) --------------------------
+    def _dev(self, t, name, dtype, numel=None):
+        if t.dtype != dtype or t.device != self.device:
+            raise TypeError("%s must be %s on %s" % (name, dtype, self.device))
+        if numel is not None and t.numel() != numel:
+            raise ValueError("%s must hold %d entries" % (name, numel))
+        return t.contiguous()
+
+    def unmasked_index(self, mask):
+        """Ascending RING indices of the unmasked pixels (int32, length n_obs)."""
+        mask = self._dev(mask, "mask", torch.uint8, self.npix)
+        idx = torch.empty(self.npix, dtype=torch.int32, device=self.device)
+        n = ctypes.c_int64()
+        with torch.cuda.device(self.device):
+            _check(lib().akra_unmasked_index(self._h, mask.data_ptr(), idx.data_ptr(), ctypes.byref(n)))
+        return idx[: n.value]
+
+    def shuffle_shear(self, g1, g2, idx, perm):
+        """Shear permuted among the unmasked pixels `idx` by each row of `perm` (int32 [n_real, n_obs]):
+        out[k][idx[j]] = g[idx[perm[k][j]]], zero elsewhere; returns g1_out, g2_out [n_real, Npix]."""
+        g1 = self._dev(g1, "g1", torch.float64, self.npix)
+        g2 = self._dev(g2, "g2", torch.float64, self.npix)
+        idx = self._dev(idx, "idx", torch.int32)
+        perm = self._dev(perm, "perm", torch.int32)
+        n_obs = idx.numel()
+        if perm.dim() != 2 or perm.shape[1] != n_obs:
+            raise ValueError("perm must have shape [n_real, %d]" % n_obs)
+        n_real = perm.shape[0]
+        o1 = torch.empty((n_real, self.npix), dtype=torch.float64, device=self.device)
+        o2 = torch.empty_like(o1)
+        with torch.cuda.device(self.device):
+            _check(lib().akra_shuffle_shear(self._h, g1.data_ptr(), g2.data_ptr(), idx.data_ptr(), n_obs,
+                                            perm.data_ptr(), n_real, o1.data_ptr(), o2.data_ptr()))
+        return o1, o2
+
+    def alm_spectra(self, x, y, pairs):
+        """C_l^{x[i] y[j]} for every (i, j) in `pairs`; x, y complex128 [n, n_alm] (or [n_alm]).
+        Returns float64 [npairs, lmax+1]."""
+        import numpy as np
+        x = self._dev(x, "x", torch.complex128).reshape(-1, self.nalm)
+        y = self._dev(y, "y", torch.complex128).reshape(-1, self.nalm)
+        pr = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1, 2))
+        cl = torch.empty((pr.shape[0], self.lmax + 1), dtype=torch.float64, device=self.device)
+        with torch.cuda.device(self.device):
+            _check(lib().akra_alm_spectra(self._h, x.data_ptr(), x.shape[0], y.data_ptr(), y.shape[0],
+                                          pr.ctypes.data, pr.shape[0], cl.data_ptr()))
+        return cl
+
+    def noise_work_bytes(self, nset=1):
+        n = ctypes.c_int64()
+        _check(lib().akra_noise_work_size(self._h, int(nset), ctypes.byref(n)))
+        return n.value
+
+    def noise_spectra(self, g1, g2, ninv, mask, perm, tol=1e-3, maxiter=1000, lam=1e-3, kernel=None,
+                      reliable_delta=0.1, mode="E", raise_not_converged=True, work=None):
+        """Shape-noise realisations through the full solve and their spectra (akra_noise_spectra).
+
+        One shear set: g1, g2, ninv [Npix], perm int32 [n_real, n_obs] -> auto spectra.  Split halves:
+        g1, g2, ninv [2, Npix], perm [2, n_real, n_obs] -> cross spectra of the halves.  mode "E"
+        (default, the E-mode reconstruction) keeps EE, "B" keeps BB, "joint" keeps (EE, BB, EB).
+        Returns cl [n_real, nspec, lmax+1], its mean and sample standard deviation [nspec, lmax+1],
+        and the solve info."""
+        nset = 1 if g1.dim() == 1 else g1.shape[0]
+        g1 = self._dev(g1, "g1", torch.float64, nset * self.npix)
+        g2 = self._dev(g2, "g2", torch.float64, nset * self.npix)
+        ninv = self._dev(ninv, "ninv", torch.float64, nset * self.npix)
+        mask = self._dev(mask, "mask", torch.uint8, self.npix)
+        perm = self._dev(perm, "perm", torch.int32)
+        if perm.dim() != (2 if nset == 1 else 3) or (nset == 2 and perm.shape[0] != 2):
+            raise ValueError("perm must have shape [n_real, n_obs] (one set) or [2, n_real, n_obs] (halves)")
+        n_real, n_obs = perm.shape[-2], perm.shape[-1]
+        nspec = 3 if mode == "joint" else 1
+        if work is None:
+            work = torch.empty(self.noise_work_bytes(nset), dtype=torch.uint8, device=self.device)
+        cl = torch.empty((n_real, nspec, self.lmax + 1), dtype=torch.float64, device=self.device)
+        mean = torch.empty((nspec, self.lmax + 1), dtype=torch.float64, device=self.device)
+        std = torch.empty_like(mean)
+        o, keep = self._opts(tol, maxiter, lam, None, kernel, reliable_delta, 0, mode)
+        inf = CgInfo()
+        with torch.cuda.device(self.device):
+            st = lib().akra_noise_spectra(self._h, nset, g1.data_ptr(), g2.data_ptr(), ninv.data_ptr(),
+                                          mask.data_ptr(), perm.data_ptr(), n_obs, n_real, ctypes.byref(o),
+                                          work.data_ptr(), work.numel(), cl.data_ptr(), mean.data_ptr(),
+                                          std.data_ptr(), ctypes.byref(inf))
+        if st != AKRA_OK and (st != AKRA_NOT_CONVERGED or raise_not_converged):
+            _check(st)
+        return cl, mean, std, self._info(inf, keep, 0)
 
     # -- step-wise PCG ------------------------------------------------------------------------
     def cg_start(self, g1, g2, ninv, mask, lam=1e-3, kernel=None, mode="joint"):

@@ -19,6 +19,15 @@ namespace akra {
 // ------------------------------------------------------------------------------------------------
 // padding (in entries) after the coefficient table and the kernel-scaled alm buffers
 constexpr int ALM_PAD = 64;
+// unmasked-pixel compaction: threads per block, contiguous pixels per thread, pixels per tile
+constexpr int CMP_T = 256, CMP_PER = 16, CMP_TILE = CMP_T * CMP_PER;
+// spectra: degrees per block, orders per partial sum, pairs per launch
+constexpr int SPEC_LT = 256, SPEC_MC = 64, SPEC_NP = 8;
+struct SpecArgs {
+    const double2 *x[SPEC_NP];  // coefficient sets X of the pairs (m >= 0 storage)
+    const double2 *y[SPEC_NP];  // coefficient sets Y
+    double *cl[SPEC_NP];        // [lmax+1] outputs
+};
 
 template <typename T> struct Scale;
 template <> struct Scale<double> {
@@ -141,6 +150,15 @@ struct Plan {
     // solver vectors [nrhs][2][nalm] complex FP64
     double *d_x = nullptr, *d_r = nullptr, *d_p = nullptr, *d_w = nullptr, *d_b = nullptr, *d_xs = nullptr;
     double *h_pin = nullptr;    // pinned host scalars
+    // unmasked-pixel list (compaction scratch) and spectrum partial sums
+    int64_t cmp_ntile = 0;        // tiles of CMP_TILE pixels
+    void *d_cmp = nullptr;        // one allocation holding the four members below
+    int *d_cmp_cnt = nullptr;     // [cmp_ntile] unmasked pixels per tile
+    int64_t *d_cmp_offs = nullptr;  // [cmp_ntile] first list position of each tile
+    int64_t *d_cmp_nobs = nullptr;  // number of unmasked pixels
+    int *d_cmp_flag = nullptr;    // nonzero: a shuffle met an index out of range
+    int spec_nmc = 0;             // m-chunks of the spectrum partial sums
+    double *d_spec = nullptr;     // [SPEC_NP][spec_nmc][lmax+1]
     int64_t device_bytes = 0;
 
     // solver state of the right-hand side in progress
@@ -195,8 +213,9 @@ void launch_epilogue_batched(Plan &P, int rhs, const double *kern, double lam, c
                              double *outE, double *outB);
 // chirp spectra of the Bluestein sub lengths Ls (FFT lengths Ms, table offsets ofs; device arrays)
 void launch_bhat(Plan &P, const int *Ls, const int *Ms, const int64_t *ofs, int n, int maxM);
-// weights W = mask * ninv, plus the sums needed for lambda_eff / P and input validation
-void launch_weights(Plan &P, const double *ninv, const uint8_t *mask, int nrhs);
+// weights W = mask * ninv, plus the sums needed for lambda_eff / P and input validation; right-hand
+// side r reads the N^-1 map r mod ncount of ninv ([ncount][npix])
+void launch_weights(Plan &P, const double *ninv, const uint8_t *mask, int nrhs, int ncount);
 
 // full-m dot products and CG vector updates on [2][nalm] complex FP64 vectors
 void launch_dot(Plan &P, const double *a, const double *b, double *out_dev, int64_t n_complex);
@@ -205,6 +224,17 @@ void launch_cg_xr(Plan &P, double *x, double *r, const double *p, const double *
 void launch_cg_p(Plan &P, double *p, const double *r, const double *beta_dev, double precond, int64_t n_complex);
 void launch_axpby(Plan &P, double *y, double a, const double *x, double b, int64_t n_complex);
 void launch_scalar_div(Plan &P, double *out, const double *num, const double *den);
+// shape-noise realisations and spectra (akra_spectra.hip)
+// ascending indices of the unmasked pixels into idx (capacity npix), their count into d_cmp_nobs
+void launch_unmasked_index(Plan &P, const uint8_t *mask, int32_t *idx);
+// o = shear permuted by perm among the n_obs unmasked pixels idx, zero elsewhere (o all zero when
+// perm is null); indices out of range set d_cmp_flag and are skipped
+void launch_shuffle(Plan &P, const double *g1, const double *g2, const int32_t *idx, int64_t n_obs,
+                    const int32_t *perm, double *o1, double *o2);
+// C_l of the first n (<= SPEC_NP) pairs of a
+void launch_spectra(Plan &P, const SpecArgs &a, int n);
+// mean and sample standard deviation over n realisations of len values (either output nullable)
+void launch_cl_moments(Plan &P, const double *cl, int n, int64_t len, double *mean, double *sd);
 bool pow2(int n);
 bool adj_shape_supported(int r, int w, int l);
 

@@ -1052,13 +1052,15 @@ __global__ void k_epilogue(const T *__restrict__ part, const int *__restrict__ w
 
 // W = mask * ninv; block partials of sum(M N^-1), sum(M), #non-finite, #negative, sum over all pixels
 __global__ void k_weights(const double *__restrict__ ninv, const uint8_t *__restrict__ mask, double *__restrict__ W,
-                          int64_t npix, double *__restrict__ red)
+                          int64_t npix, int ncount, double *__restrict__ red)
 {
+    // right-hand side rhs takes the N^-1 map rhs mod ncount
     const int rhs = blockIdx.y;
+    const int64_t nofs = (int64_t)(rhs % ncount) * npix;
     __shared__ double sh[5][256];
     double a = 0, b = 0, c = 0, d = 0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < npix; i += (int64_t)gridDim.x * blockDim.x) {
-        const double v = ninv[rhs * npix + i];
+        const double v = ninv[nofs + i];
         const bool obs = mask[i] != 0;
         if (!isfinite(v)) c += 1;
         if (v < 0) d += 1;
@@ -2299,9 +2301,9 @@ void launch_scale_scalar(Plan &P, double *out, const double *in, double f)
     k_scale_scalar<<<1, 1, 0, P.stream>>>(out, in, f);
 }
 
-void launch_weights(Plan &P, const double *ninv, const uint8_t *mask, int nrhs)
+void launch_weights(Plan &P, const double *ninv, const uint8_t *mask, int nrhs, int ncount)
 {
-    k_weights<<<dim3(RED_BLOCKS, nrhs), 256, 0, P.stream>>>(ninv, mask, P.d_W, P.npix, P.d_red);
+    k_weights<<<dim3(RED_BLOCKS, nrhs), 256, 0, P.stream>>>(ninv, mask, P.d_W, P.npix, ncount, P.d_red);
     for (int r = 0; r < nrhs; ++r)
         k_sum_part<<<1, 64, 0, P.stream>>>(P.d_red + (int64_t)r * RED_BLOCKS * 4, RED_BLOCKS, 4, 4, P.d_scal + 8 + 4 * r);
 }

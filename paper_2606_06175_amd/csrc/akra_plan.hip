@@ -247,7 +247,7 @@ static void free_plan(Plan *P)
                     P->d_seed2, P->d_seedm2, P->d_seedk,
                     P->d_ent, P->d_entk, P->d_entl, P->d_wgstart, P->d_wgstart_b, P->d_coef32d, P->d_brec,
                     P->d_tw64, P->d_tw32, P->d_bhat64, P->d_bhat32, P->d_lof, P->d_order_p2, P->d_order_bl, P->d_order_bf, P->d_FG, P->d_part, P->d_rec, P->d_W, P->d_kern, P->d_kuser, P->d_red, P->d_scal, P->d_flag, P->d_x, P->d_r,
-                    P->d_p, P->d_w, P->d_b, P->d_xs};
+                    P->d_p, P->d_w, P->d_b, P->d_xs, P->d_cmp, P->d_spec};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     if (P->h_pin) (void)hipHostFree(P->h_pin);
@@ -511,6 +511,24 @@ static akra_status create(int nside, int lmax, int nrhs, int prec, void *stream,
     AK_TRY(alloc((void **)&P->d_red, (size_t)512 * 4 * nrhs * sizeof(double), *P));
     AK_TRY(alloc((void **)&P->d_scal, (size_t)(64 + 16 * nrhs) * sizeof(double), *P));
     AK_TRY(alloc((void **)&P->d_flag, 64 * sizeof(int), *P));
+    // unmasked-pixel list scratch: count and flag, then per-tile counts and offsets
+    P->cmp_ntile = (P->npix + CMP_TILE - 1) / CMP_TILE;
+    {
+        const size_t nt = (size_t)P->cmp_ntile, cnt_b = (nt * sizeof(int) + 255) / 256 * 256;
+        AK_TRY(alloc(&P->d_cmp, 256 + cnt_b + nt * sizeof(int64_t), *P));
+        char *b = (char *)P->d_cmp;
+        P->d_cmp_nobs = (int64_t *)b;
+        P->d_cmp_flag = (int *)(b + 64);
+        P->d_cmp_cnt = (int *)(b + 256);
+        P->d_cmp_offs = (int64_t *)(b + 256 + cnt_b);
+        if (hipMemset(P->d_cmp, 0, 256) != hipSuccess) {
+            free_plan(P);
+            set_error("hipMemset failed");
+            return AKRA_ERR_HIP;
+        }
+    }
+    P->spec_nmc = (lmax + SPEC_MC) / SPEC_MC;
+    AK_TRY(alloc((void **)&P->d_spec, (size_t)SPEC_NP * P->spec_nmc * (lmax + 1) * sizeof(double), *P));
     const size_t vb = (size_t)nrhs * 2 * P->nalm * sizeof(double2);
     AK_TRY(alloc((void **)&P->d_x, vb, *P));
     AK_TRY(alloc((void **)&P->d_r, vb, *P));
@@ -541,15 +559,16 @@ static akra_status check_launch(const char *what)
     return AKRA_OK;
 }
 
-// W from ninv/mask, validated; returns lambda_eff and P for every rhs (host)
+// W from ninv/mask, validated; returns lambda_eff and P for every rhs (host).  ninv holds ncount
+// maps (0: one per right-hand side); right-hand side r takes map r mod ncount.
 static akra_status setup_weights(Plan &P, const double *ninv, const uint8_t *mask, double lam, std::vector<double> &lam_eff,
-                                 std::vector<double> &pc, std::vector<double> *msum = nullptr)
+                                 std::vector<double> &pc, std::vector<double> *msum = nullptr, int ncount = 0)
 {
     if (!ninv || !mask) {
         set_error("ninv and mask must be device pointers");
         return AKRA_ERR_ARG;
     }
-    launch_weights(P, ninv, mask, P.nrhs);
+    launch_weights(P, ninv, mask, P.nrhs, ncount > 0 ? ncount : P.nrhs);
     akra_status st = check_launch("weights");
     if (st) return st;
     AK_HIP(hipMemcpyAsync(P.h_pin, P.d_scal + 8, sizeof(double) * 4 * P.nrhs, hipMemcpyDeviceToHost, P.stream),
@@ -1294,7 +1313,7 @@ static akra_status solve_batched(Plan &P, const double *g1, const double *g2, co
 
 static akra_status solve_common(Plan &P, const double *g1, const double *g2, const double *ninv, const uint8_t *mask,
                                 const double *bE, const double *bB, const akra_cg_opts *opts, double *xE, double *xB,
-                                akra_cg_info *info_out)
+                                akra_cg_info *info_out, int ninv_count = 0)
 {
     auto t0 = std::chrono::steady_clock::now();
     akra_cg_opts o;
@@ -1302,7 +1321,7 @@ static akra_status solve_common(Plan &P, const double *g1, const double *g2, con
     if (st) return st;
     akra_cg_info info{};
     std::vector<double> le, pc;
-    st = setup_weights(P, ninv, mask, o.lambda, le, pc);
+    st = setup_weights(P, ninv, mask, o.lambda, le, pc, nullptr, ninv_count);
     if (st) return st;
     const double *kd;
     st = kernel_to_device(P, o.kernel_l, &kd);
@@ -1645,6 +1664,257 @@ akra_status akra_plan_stage_times(akra_plan plan, double *ms, int *calls)
     }
     P.ev_used = 0;
     return AKRA_OK;
+}
+
+
+// ---- shape-noise realisations and power spectra (Sec. IV, power spectrum results) ---------------
+static bool overlaps(const void *a, int64_t na, const void *b, int64_t nb)
+{
+    const char *pa = (const char *)a, *pb = (const char *)b;
+    return pa < pb + nb && pb < pa + na;
+}
+
+static akra_status read_nobs(Plan &P, int64_t *n)
+{
+    AK_HIP(hipMemcpyAsync(P.h_pin, P.d_cmp_nobs, sizeof(int64_t), hipMemcpyDeviceToHost, P.stream), "copy");
+    AK_HIP(hipStreamSynchronize(P.stream), "sync");
+    std::memcpy(n, P.h_pin, sizeof(int64_t));
+    return AKRA_OK;
+}
+
+// range check of the shuffles since the flag was last cleared
+static akra_status shuffle_flag(Plan &P)
+{
+    akra_status st = check_launch("shuffle");
+    if (st) return st;
+    int f = 0;
+    AK_HIP(hipMemcpyAsync(P.h_pin, P.d_cmp_flag, sizeof(int), hipMemcpyDeviceToHost, P.stream), "copy");
+    AK_HIP(hipStreamSynchronize(P.stream), "sync");
+    std::memcpy(&f, P.h_pin, sizeof(int));
+    if (f) {
+        AK_HIP(hipMemsetAsync(P.d_cmp_flag, 0, sizeof(int), P.stream), "memset");
+        set_error(f == 1 ? "perm holds an entry outside [0, n_obs)" : "idx holds a pixel index outside [0, Npix)");
+        return AKRA_ERR_ARG;
+    }
+    return AKRA_OK;
+}
+
+akra_status akra_unmasked_index(akra_plan plan, const uint8_t *mask, int32_t *idx, int64_t *n_obs)
+{
+    AK_PLAN();
+    if (!mask || !idx || !n_obs) {
+        set_error("null pointer argument");
+        return AKRA_ERR_ARG;
+    }
+    launch_unmasked_index(P, mask, idx);
+    akra_status st = check_launch("unmasked_index");
+    if (st) return st;
+    return read_nobs(P, n_obs);
+}
+
+akra_status akra_shuffle_shear(akra_plan plan, const double *g1, const double *g2, const int32_t *idx, int64_t n_obs,
+                               const int32_t *perm, int n_real, double *g1_out, double *g2_out)
+{
+    AK_PLAN();
+    if (n_real < 0 || n_obs < 0 || n_obs > P.npix) {
+        set_error("n_real must be >= 0 and n_obs in [0, Npix]");
+        return AKRA_ERR_ARG;
+    }
+    if (n_real == 0) return AKRA_OK;
+    if (!g1 || !g2 || !g1_out || !g2_out || (n_obs > 0 && (!idx || !perm))) {
+        set_error("null pointer argument");
+        return AKRA_ERR_ARG;
+    }
+    const int64_t mb = P.npix * (int64_t)sizeof(double), ob = mb * n_real;
+    if (overlaps(g1_out, ob, g1, mb) || overlaps(g1_out, ob, g2, mb) || overlaps(g2_out, ob, g1, mb) ||
+        overlaps(g2_out, ob, g2, mb) || overlaps(g1_out, ob, g2_out, ob)) {
+        set_error("outputs alias inputs or each other");
+        return AKRA_ERR_ARG;
+    }
+    AK_HIP(hipMemsetAsync(P.d_cmp_flag, 0, sizeof(int), P.stream), "memset");
+    for (int k = 0; k < n_real; ++k)
+        launch_shuffle(P, g1, g2, idx, n_obs, perm ? perm + (int64_t)k * n_obs : nullptr, g1_out + (int64_t)k * P.npix,
+                       g2_out + (int64_t)k * P.npix);
+    return shuffle_flag(P);
+}
+
+akra_status akra_alm_spectra(akra_plan plan, const double *x, int nx, const double *y, int ny, const int32_t *pairs,
+                             int npairs, double *cl)
+{
+    AK_PLAN();
+    if (npairs < 0 || nx < 0 || ny < 0) {
+        set_error("counts must be >= 0");
+        return AKRA_ERR_ARG;
+    }
+    if (npairs == 0) return AKRA_OK;
+    if (!x || !y || !pairs || !cl) {
+        set_error("null pointer argument");
+        return AKRA_ERR_ARG;
+    }
+    for (int q = 0; q < npairs; ++q)
+        if (pairs[2 * q] < 0 || pairs[2 * q] >= nx || pairs[2 * q + 1] < 0 || pairs[2 * q + 1] >= ny) {
+            set_error("pair " + std::to_string(q) + " is out of range");
+            return AKRA_ERR_ARG;
+        }
+    const double2 *X = (const double2 *)x, *Y = (const double2 *)y;
+    for (int q0 = 0; q0 < npairs; q0 += SPEC_NP) {
+        SpecArgs a{};
+        const int n = std::min(SPEC_NP, npairs - q0);
+        for (int i = 0; i < n; ++i) {
+            a.x[i] = X + (int64_t)pairs[2 * (q0 + i)] * P.nalm;
+            a.y[i] = Y + (int64_t)pairs[2 * (q0 + i) + 1] * P.nalm;
+            a.cl[i] = cl + (int64_t)(q0 + i) * (P.lmax + 1);
+        }
+        launch_spectra(P, a, n);
+    }
+    return check_launch("spectra");
+}
+
+static int64_t align256(int64_t b) { return (b + 255) / 256 * 256; }
+
+akra_status akra_noise_work_size(akra_plan plan, int nset, int64_t *bytes)
+{
+    AK_PLAN();
+    if ((nset != 1 && nset != 2) || !bytes) {
+        set_error("nset must be 1 or 2 and bytes non-NULL");
+        return AKRA_ERR_ARG;
+    }
+    const int64_t gx = std::max(P.nrhs, nset);
+    *bytes = align256(P.npix * 4) + 2 * align256(gx * P.npix * 8) + 2 * align256(gx * P.nalm * 16);
+    return AKRA_OK;
+}
+
+akra_status akra_noise_spectra(akra_plan plan, int nset, const double *g1, const double *g2, const double *ninv,
+                               const uint8_t *mask, const int32_t *perm, int64_t n_obs, int n_real,
+                               const akra_cg_opts *opts, void *work, int64_t work_bytes, double *cl, double *cl_mean,
+                               double *cl_std, akra_cg_info *info_out)
+{
+    AK_PLAN();
+    auto t0 = std::chrono::steady_clock::now();
+    if (nset != 1 && nset != 2) {
+        set_error("nset must be 1 or 2");
+        return AKRA_ERR_ARG;
+    }
+    if (n_real < 0 || n_obs < 0 || n_obs > P.npix) {
+        set_error("n_real must be >= 0 and n_obs in [0, Npix]");
+        return AKRA_ERR_ARG;
+    }
+    const int G = P.nrhs, gx = std::max(G, nset);
+    if (nset == 2 && G > 1 && G % 2) {
+        set_error("split halves need an even nrhs (or nrhs = 1)");
+        return AKRA_ERR_ARG;
+    }
+    akra_cg_opts o;
+    akra_status st = read_opts(opts, o);
+    if (st) return st;
+    const int nspec = o.mode == AKRA_JOINT_EB ? 3 : 1;
+    int64_t need = 0;
+    st = akra_noise_work_size(plan, nset, &need);
+    if (st) return st;
+    if (!g1 || !g2 || !ninv || !mask || !work || (n_real > 0 && !cl) || (n_obs > 0 && n_real > 0 && !perm)) {
+        set_error("null pointer argument");
+        return AKRA_ERR_ARG;
+    }
+    if (work_bytes < need) {
+        set_error("workspace too small: " + std::to_string(need) + " bytes needed");
+        return AKRA_ERR_ARG;
+    }
+    const int64_t npix = P.npix, na = P.nalm, L1 = P.lmax + 1;
+    char *w = (char *)work;
+    int32_t *idx = (int32_t *)w;
+    w += align256(npix * 4);
+    double *m1 = (double *)w;
+    w += align256(gx * npix * 8);
+    double *m2 = (double *)w;
+    w += align256(gx * npix * 8);
+    double *xE = (double *)w;
+    w += align256(gx * na * 16);
+    double *xB = (double *)w;
+
+    launch_unmasked_index(P, mask, idx);
+    st = check_launch("unmasked_index");
+    if (st) return st;
+    int64_t nob = 0;
+    st = read_nobs(P, &nob);
+    if (st) return st;
+    if (nob != n_obs) {
+        set_error("n_obs (" + std::to_string(n_obs) + ") differs from the unmasked pixels of the mask (" +
+                  std::to_string(nob) + ")");
+        return AKRA_ERR_ARG;
+    }
+    AK_HIP(hipMemsetAsync(P.d_cmp_flag, 0, sizeof(int), P.stream), "memset");
+    akra_cg_info agg{};
+    int worst = AKRA_OK;
+    bool first = true;
+    const int R = gx / nset;  // realisations per pass
+    for (int k0 = 0; k0 < n_real; k0 += R) {
+        // shuffled maps of the pass: slot s = realisation k0 + s / nset, set s % nset (zero past n_real)
+        for (int s = 0; s < gx; ++s) {
+            const int k = k0 + s / nset, q = s % nset;
+            const int32_t *pr = (k < n_real && n_obs > 0) ? perm + ((int64_t)q * n_real + k) * n_obs : nullptr;
+            launch_shuffle(P, g1 + (int64_t)q * npix, g2 + (int64_t)q * npix, idx, n_obs, pr, m1 + (int64_t)s * npix,
+                           m2 + (int64_t)s * npix);
+        }
+        st = shuffle_flag(P);
+        if (st) return st;
+        // solves in groups of nrhs slots; slot s takes N^-1 map s mod nset
+        for (int g0 = 0; g0 < gx; g0 += G) {
+            akra_cg_info gi{};
+            st = solve_common(P, m1 + (int64_t)g0 * npix, m2 + (int64_t)g0 * npix, ninv + (int64_t)(g0 % nset) * npix,
+                              mask, nullptr, nullptr, &o, xE + (int64_t)g0 * 2 * na, xB + (int64_t)g0 * 2 * na, &gi,
+                              G == 1 ? 1 : nset);
+            if (st != AKRA_OK && st != AKRA_NOT_CONVERGED) return st;
+            if (st == AKRA_NOT_CONVERGED) worst = AKRA_NOT_CONVERGED;
+            agg.iters += gi.iters;
+            agg.fp64_applies += gi.fp64_applies;
+            agg.rel_resid = std::max(agg.rel_resid, gi.rel_resid);
+            agg.rel_resid_true = std::max(agg.rel_resid_true, gi.rel_resid_true);
+            if (first) {
+                agg.lambda_eff = gi.lambda_eff;
+                agg.precond = gi.precond;
+                first = false;
+            }
+        }
+        // spectra of the pass's realisations: sets A (slot r nset) and B (slot r nset + nset - 1)
+        SpecArgs a{};
+        int n = 0;
+        auto add = [&](const double2 *u, const double2 *v, double *c) {
+            a.x[n] = u;
+            a.y[n] = v;
+            a.cl[n] = c;
+            if (++n == SPEC_NP) {
+                launch_spectra(P, a, n);
+                n = 0;
+            }
+        };
+        for (int r = 0; r < R && k0 + r < n_real; ++r) {
+            const int64_t sa = (int64_t)r * nset, sb = sa + nset - 1;
+            const double2 *EA = (const double2 *)xE + sa * na, *EB = (const double2 *)xE + sb * na;
+            const double2 *BA = (const double2 *)xB + sa * na, *BB = (const double2 *)xB + sb * na;
+            double *c = cl + (int64_t)(k0 + r) * nspec * L1;
+            if (o.mode == AKRA_E_ONLY) {
+                add(EA, EB, c);
+            } else if (o.mode == AKRA_B_ONLY) {
+                add(BA, BB, c);
+            } else {
+                add(EA, EB, c);
+                add(BA, BB, c + L1);
+                add(EA, BB, c + 2 * L1);
+            }
+        }
+        if (n) launch_spectra(P, a, n);
+        st = check_launch("spectra");
+        if (st) return st;
+    }
+    if (cl_mean || cl_std) launch_cl_moments(P, cl, n_real, (int64_t)nspec * L1, cl_mean, cl_std);
+    st = check_launch("cl_moments");
+    if (st) return st;
+    AK_HIP(hipStreamSynchronize(P.stream), "sync");
+    agg.status = worst;
+    agg.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (info_out) *info_out = agg;
+    if (worst != AKRA_OK) set_error("maxiter reached or stalled for some realisation");
+    return (akra_status)worst;
 }
 
 }  // extern "C"

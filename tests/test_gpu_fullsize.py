@@ -115,3 +115,33 @@ def test_apply_H_symmetric_and_fp32_agrees(big):
         a = torch.stack([out["fp32"][i][0], out["fp32"][i][1]]).cpu().numpy()
         b = torch.stack([out["fp64"][i][0], out["fp64"][i][1]]).cpu().numpy()
         assert rel(a, b) < 1e-5
+
+
+def test_spectra_and_shuffle_full_size(big):
+    # spectra of two coefficient sets at sampled degrees (tile edges, lmax) and the unmasked list and
+    # one shuffle of a seeded f_sky = 0.1 mask, bit for bit, at the benchmark size
+    from oracle import spectra as sp
+    torch, dev = big["torch"], big["dev"]
+    aE, aB = big["aE"], big["aB"]
+    p = _plan("fp64")
+    x = torch.stack([torch.from_numpy(aE), torch.from_numpy(aB)]).to(dev)
+    cl = p.alm_spectra(x, x, [(0, 0), (0, 1), (1, 1)]).cpu().numpy()
+    ells = [2, 3, 255, 256, 257, 1000, 4095, 4096]
+    auto = {0: sp.spectrum(aE, aE, LMAX, ells), 1: sp.spectrum(aB, aB, LMAX, ells)}
+    for q, (i, j) in enumerate([(0, 0), (0, 1), (1, 1)]):
+        ref = sp.spectrum((aE, aB)[i], (aE, aB)[j], LMAX, ells)
+        scale = np.sqrt(auto[i] * auto[j])
+        for l in ells:
+            assert abs(cl[q, l] - ref[l]) <= 1e-13 * scale[l], (q, l)
+    npix = 12 * NSIDE * NSIDE
+    g = np.random.default_rng(21)
+    mask = (g.random(npix) < 0.1).astype(np.uint8)
+    idx = p.unmasked_index(torch.from_numpy(mask).to(dev))
+    u = sp.unmasked_index(mask)
+    assert np.array_equal(idx.cpu().numpy(), u)
+    perm = wl.shuffle_perms(u.size, 1, 22)
+    h1, h2 = big["h1"], big["h2"]
+    o1, o2 = p.shuffle_shear(torch.from_numpy(h1).to(dev), torch.from_numpy(h2).to(dev), idx,
+                             torch.from_numpy(perm).to(dev))
+    r1, r2 = sp.shuffle_shear(h1, h2, mask, perm[0])
+    assert np.array_equal(o1[0].cpu().numpy(), r1) and np.array_equal(o2[0].cpu().numpy(), r2)
