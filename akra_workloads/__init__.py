@@ -39,7 +39,7 @@ CONFIGS = {
 _CFG_NUM = {"C1": 1, "C2": 2, "C3": 3, "C4": 4, "C5": 5}
 
 # random-stream ids inside one configuration
-S_KAPPA, S_FOOT, S_COUNTS, S_NOISE, S_DEPTH, S_ROT, S_SHUFFLE, S_SPLIT = 1, 2, 3, 4, 5, 6, 7, 8
+S_KAPPA, S_FOOT, S_COUNTS, S_NOISE, S_DEPTH, S_ROT, S_SHUFFLE, S_SPLIT, S_CAT = 1, 2, 3, 4, 5, 6, 7, 8, 9
 
 
 def rng(seed_base, stream):
@@ -271,3 +271,37 @@ def split_halves(cfg, seed_base):
     e1 = sd * g.normal(size=halves.shape) * mask
     e2 = sd * g.normal(size=halves.shape) * mask
     return dict(ninv=halves / SIGMA_E ** 2, eps1=e1, eps2=e2)
+
+
+# ---------------------------------------------------------------------------------------------
+# shear catalogue (Sec. III.B pixelisation)
+# ---------------------------------------------------------------------------------------------
+CAT_R = 0.7      # mean shear response standing in for the sample's <R>
+CAT_NTH = 5.0    # N_eff threshold of the mask
+
+
+def make_catalog(n_gal, seed_base, fsky=0.1, amp=0.02):
+    """Synthetic galaxy catalogue shaped like the DES Y3 sample (about 1e8 galaxies over f_sky ~ 0.1).
+
+    Positions are uniform in area inside a southern box z in [-0.95, -0.35], phi in [0, dphi) with
+    dphi set by f_sky.  Weights w ~ U[0.2, 1.2].  Ellipticities are eps = R g + n per component,
+    g a smooth shear pattern of amplitude `amp` and n ~ N(0, sigma_e^2).  Returns float64 arrays z
+    (= cos theta), phi, e1, e2, w and the scalars R, sigma_e, n_th."""
+    g = rng(seed_base, S_CAT)
+    n = int(n_gal)
+    z0, z1 = -0.95, -0.35
+    dphi = 4.0 * math.pi * fsky / (z1 - z0)
+    z = g.uniform(z0, z1, n)
+    phi = g.uniform(0.0, dphi, n)
+    w = g.uniform(0.2, 1.2, n)
+    s1 = amp * np.sin(3.0 * phi) * np.cos(7.0 * z)
+    s2 = amp * np.cos(2.0 * phi) * np.sin(5.0 * z)
+    e1 = CAT_R * s1 + SIGMA_E * g.normal(size=n)
+    e2 = CAT_R * s2 + SIGMA_E * g.normal(size=n)
+    return dict(z=z, phi=phi, e1=e1, e2=e2, w=w, R=CAT_R, sigma_e=SIGMA_E, n_th=CAT_NTH)
+
+
+def sphere_points(n, seed_base):
+    """Directions uniform on the sphere: z ~ U[-1, 1], phi ~ U[0, 2 pi)."""
+    g = rng(seed_base, S_CAT + 100)
+    return g.uniform(-1.0, 1.0, int(n)), g.uniform(0.0, 2.0 * math.pi, int(n))
