@@ -347,6 +347,48 @@ akra_status akra_noise_spectra(akra_plan plan, int nset, const double *g1, const
                                const akra_cg_opts *opts, void *work, int64_t work_bytes, double *cl,
                                double *cl_mean, double *cl_std, akra_cg_info *info);
 
+/*
+ * Catalogue pixelisation (Sec. III.B pixelization).  Galaxies j with direction (z_j = cos theta_j,
+ * phi_j), ellipticities (e1_j, e2_j) and weights w_j >= 0 are binned onto the plan's HEALPix RING
+ * grid, and per pixel i:
+ *   g_i^nu  = sum_j w_j e^nu_j / (R sum_j w_j)      (eq. gamma_obs; 0 where sum_j w_j = 0)
+ *   N_eff,i = (sum_j w_j)^2 / sum_j w_j^2           (eq. Neff_pixel; 0 where sum_j w_j^2 = 0)
+ *   N^-1_i  = N_eff,i / sigma_e^2                   (eq. noise_var)
+ *   M_i     = N_eff,i >= n_th                       (eq. mask)
+ * The sums of a pixel run over its galaxies in catalogue order, each product rounded before it is
+ * added, and R sum_j w_j is formed before the division: the results are a fixed function of the
+ * catalogue (no atomics), reproducible bit for bit.  The outputs feed akra_cg_solve directly
+ * (g1, g2, ninv, mask).
+ */
+
+/*
+ * RING pixel of each direction: z = cos theta in [-1, 1], phi in [0, 2 pi) (the inverse of the
+ * pixel boundaries of Gorski et al. 2005, computed in FP64 with every operation rounded on its own).
+ *   z, phi  device float64 [n];  pix  device int32 [n].
+ * Synchronises the plan stream.  Errors: AKRA_ERR_ARG (null pointers, n < 0, a direction out of
+ * range), AKRA_ERR_HIP.
+ */
+akra_status akra_ang2pix(akra_plan plan, const double *z, const double *phi, int64_t n, int32_t *pix);
+
+/* Device bytes of the workspace akra_pixelize needs for n_gal galaxies (0 <= n_gal < 2^31), written
+ * to *bytes (HOST): pixel keys, their sorted copy and galaxy order, per-pixel runs and the radix-sort
+ * storage.  Errors: AKRA_ERR_ARG. */
+akra_status akra_pixelize_work_size(akra_plan plan, int64_t n_gal, int64_t *bytes);
+
+/*
+ * Pixelise a catalogue of n_gal galaxies (definitions above).
+ *   z, phi, e1, e2, w   device float64 [n_gal] (may be NULL when n_gal = 0);
+ *   R                   mean shear response (finite, nonzero); sigma_e > 0; n_th finite;
+ *   work                device workspace of work_bytes >= akra_pixelize_work_size(plan, n_gal);
+ *   g1, g2, ninv, neff  device float64 [Npix];  mask  device uint8 [Npix].
+ * Synchronises the plan stream.  Errors: AKRA_ERR_ARG (null pointers, sizes, a direction out of
+ * range, a negative or non-finite weight, a non-finite ellipticity, a small workspace; the outputs
+ * are then not written), AKRA_ERR_HIP.
+ */
+akra_status akra_pixelize(akra_plan plan, const double *z, const double *phi, const double *e1, const double *e2,
+                          const double *w, int64_t n_gal, double R, double sigma_e, double n_th, void *work,
+                          int64_t work_bytes, double *g1, double *g2, double *ninv, double *neff, uint8_t *mask);
+
 #ifdef __cplusplus
 }
 #endif

@@ -86,13 +86,18 @@ def lib():
     L.akra_shuffle_shear.argtypes = [vp, vp, vp, vp, i64, vp, ctypes.c_int, vp, vp]
     L.akra_alm_spectra.argtypes = [vp, vp, ctypes.c_int, vp, ctypes.c_int, vp, ctypes.c_int, vp]
     L.akra_noise_work_size.argtypes = [vp, ctypes.c_int, ctypes.POINTER(i64)]
+    L.akra_ang2pix.argtypes = [vp, vp, vp, i64, vp]
+    L.akra_pixelize_work_size.argtypes = [vp, i64, ctypes.POINTER(i64)]
+    L.akra_pixelize.argtypes = [vp, vp, vp, vp, vp, vp, i64, ctypes.c_double, ctypes.c_double, ctypes.c_double, vp,
+                                i64, vp, vp, vp, vp, vp]
     L.akra_noise_spectra.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp, vp, i64, ctypes.c_int,
                                      ctypes.POINTER(CgOpts), vp, i64, vp, vp, vp, ctypes.POINTER(CgInfo)]
     for f in ("akra_plan_create", "akra_synth2", "akra_adjoint2", "akra_apply_H", "akra_rhs", "akra_cg_solve",
               "akra_cg_solve_b", "akra_cg_start", "akra_cg_step", "akra_cg_state", "akra_plan_set_timing",
               "akra_plan_stage_times", "akra_plan_set_tuning", "akra_plan_get_tuning", "akra_plan_work",
               "akra_cg_solve_vjp", "akra_cg_solve_cond_b", "akra_set_ring_whole_maxm", "akra_unmasked_index",
-              "akra_shuffle_shear", "akra_alm_spectra", "akra_noise_work_size", "akra_noise_spectra"):
+              "akra_shuffle_shear", "akra_alm_spectra", "akra_noise_work_size", "akra_noise_spectra", "akra_ang2pix",
+              "akra_pixelize_work_size", "akra_pixelize"):
         getattr(L, f).restype = ctypes.c_int
     _lib = L
     return L
@@ -415,6 +420,38 @@ class Plan:
         if st != AKRA_OK and (st != AKRA_NOT_CONVERGED or raise_not_converged):
             _check(st)
         return cl, mean, std, self._info(inf, keep, 0)
+
+    # -- catalogue pixelisation (Sec. III.B) -----------------------------------------------------
+    def ang2pix(self, z, phi):
+        """RING pixel (int32) of the directions z = cos(theta), phi in [0, 2 pi) (float64 tensors)."""
+        z = self._dev(z, "z", torch.float64)
+        phi = self._dev(phi, "phi", torch.float64, z.numel())
+        pix = torch.empty(z.numel(), dtype=torch.int32, device=self.device)
+        with torch.cuda.device(self.device):
+            _check(lib().akra_ang2pix(self._h, z.data_ptr(), phi.data_ptr(), z.numel(), pix.data_ptr()))
+        return pix
+
+    def pixelize_work_bytes(self, n_gal):
+        n = ctypes.c_int64()
+        _check(lib().akra_pixelize_work_size(self._h, int(n_gal), ctypes.byref(n)))
+        return n.value
+
+    def pixelize(self, z, phi, e1, e2, w, R, sigma_e, n_th, work=None):
+        """Per-pixel gamma_obs (g1, g2), N^-1, N_eff and mask of a galaxy catalogue (akra_pixelize);
+        all inputs float64 tensors of one length on the plan's device."""
+        n = z.numel()
+        z = self._dev(z, "z", torch.float64)
+        phi, e1, e2, w = (self._dev(t, k, torch.float64, n) for t, k in ((phi, "phi"), (e1, "e1"), (e2, "e2"), (w, "w")))
+        if work is None:
+            work = torch.empty(self.pixelize_work_bytes(n), dtype=torch.uint8, device=self.device)
+        out = {k: torch.empty(self.npix, dtype=torch.float64, device=self.device) for k in ("g1", "g2", "ninv", "neff")}
+        out["mask"] = torch.empty(self.npix, dtype=torch.uint8, device=self.device)
+        with torch.cuda.device(self.device):
+            _check(lib().akra_pixelize(self._h, z.data_ptr(), phi.data_ptr(), e1.data_ptr(), e2.data_ptr(), w.data_ptr(),
+                                       n, float(R), float(sigma_e), float(n_th), work.data_ptr(), work.numel(),
+                                       out["g1"].data_ptr(), out["g2"].data_ptr(), out["ninv"].data_ptr(),
+                                       out["neff"].data_ptr(), out["mask"].data_ptr()))
+        return out
 
     # -- step-wise PCG ------------------------------------------------------------------------
     def cg_start(self, g1, g2, ninv, mask, lam=1e-3, kernel=None, mode="joint"):

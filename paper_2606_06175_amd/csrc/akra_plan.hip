@@ -1917,4 +1917,93 @@ akra_status akra_noise_spectra(akra_plan plan, int nset, const double *g1, const
     return (akra_status)worst;
 }
 
+// ---- catalogue pixelisation (Sec. III.B) -----------------------------------------------------------
+static akra_status read_flags2(Plan &P, int *f)
+{
+    AK_HIP(hipMemcpyAsync(P.h_pin, P.d_cmp_flag, 2 * sizeof(int), hipMemcpyDeviceToHost, P.stream), "copy");
+    AK_HIP(hipStreamSynchronize(P.stream), "sync");
+    std::memcpy(f, P.h_pin, 2 * sizeof(int));
+    if (f[0] || f[1]) AK_HIP(hipMemsetAsync(P.d_cmp_flag, 0, 2 * sizeof(int), P.stream), "memset");
+    return AKRA_OK;
+}
+
+akra_status akra_ang2pix(akra_plan plan, const double *z, const double *phi, int64_t n, int32_t *pix)
+{
+    AK_PLAN();
+    if (n < 0) {
+        set_error("n must be >= 0");
+        return AKRA_ERR_ARG;
+    }
+    if (n == 0) return AKRA_OK;
+    if (!z || !phi || !pix) {
+        set_error("null pointer argument");
+        return AKRA_ERR_ARG;
+    }
+    AK_HIP(hipMemsetAsync(P.d_cmp_flag, 0, 2 * sizeof(int), P.stream), "memset");
+    launch_ang2pix(P, z, phi, nullptr, nullptr, nullptr, n, (uint32_t *)pix);
+    akra_status st = check_launch("ang2pix");
+    if (st) return st;
+    int f[2];
+    st = read_flags2(P, f);
+    if (st) return st;
+    if (f[0]) {
+        set_error("a direction lies outside z in [-1, 1], phi in [0, 2 pi)");
+        return AKRA_ERR_ARG;
+    }
+    return AKRA_OK;
+}
+
+akra_status akra_pixelize_work_size(akra_plan plan, int64_t n_gal, int64_t *bytes)
+{
+    AK_PLAN();
+    if (n_gal < 0 || n_gal > INT32_MAX || !bytes) {
+        set_error("n_gal must be in [0, 2^31 - 1] and bytes non-NULL");
+        return AKRA_ERR_ARG;
+    }
+    AK_HIP(pixelize_work_bytes(P, n_gal, bytes), "radix sort storage query");
+    return AKRA_OK;
+}
+
+akra_status akra_pixelize(akra_plan plan, const double *z, const double *phi, const double *e1, const double *e2,
+                          const double *w, int64_t n_gal, double R, double sigma_e, double n_th, void *work,
+                          int64_t work_bytes, double *g1, double *g2, double *ninv, double *neff, uint8_t *mask)
+{
+    AK_PLAN();
+    if (n_gal < 0 || n_gal > INT32_MAX) {
+        set_error("n_gal must be in [0, 2^31 - 1]");
+        return AKRA_ERR_ARG;
+    }
+    if (!(std::isfinite(R) && R != 0.0) || !(std::isfinite(sigma_e) && sigma_e > 0.0) || !std::isfinite(n_th)) {
+        set_error("R must be finite and nonzero, sigma_e finite and > 0, n_th finite");
+        return AKRA_ERR_ARG;
+    }
+    if (!work || !g1 || !g2 || !ninv || !neff || !mask || (n_gal > 0 && (!z || !phi || !e1 || !e2 || !w))) {
+        set_error("null pointer argument");
+        return AKRA_ERR_ARG;
+    }
+    int64_t need = 0;
+    akra_status st = akra_pixelize_work_size(plan, n_gal, &need);
+    if (st) return st;
+    if (work_bytes < need) {
+        set_error("workspace too small: " + std::to_string(need) + " bytes needed");
+        return AKRA_ERR_ARG;
+    }
+    AK_HIP(hipMemsetAsync(P.d_cmp_flag, 0, 2 * sizeof(int), P.stream), "memset");
+    launch_ang2pix(P, z, phi, e1, e2, w, n_gal, pixelize_keys(P, n_gal, work));
+    st = check_launch("ang2pix");
+    if (st) return st;
+    int f[2];
+    st = read_flags2(P, f);
+    if (st) return st;
+    if (f[0] || f[1]) {
+        set_error(f[0] ? "a direction lies outside z in [-1, 1], phi in [0, 2 pi)"
+                       : "a weight is negative or not finite, or an ellipticity is not finite");
+        return AKRA_ERR_ARG;
+    }
+    AK_HIP(launch_pixelize(P, e1, e2, w, n_gal, R, sigma_e * sigma_e, n_th, work, g1, g2, ninv, neff, mask),
+           "pixelize");
+    AK_HIP(hipStreamSynchronize(P.stream), "sync");
+    return AKRA_OK;
+}
+
 }  // extern "C"
