@@ -39,7 +39,7 @@ CONFIGS = {
 _CFG_NUM = {"C1": 1, "C2": 2, "C3": 3, "C4": 4, "C5": 5}
 
 # random-stream ids inside one configuration
-S_KAPPA, S_FOOT, S_COUNTS, S_NOISE, S_DEPTH, S_ROT, S_SHUFFLE, S_SPLIT, S_CAT = 1, 2, 3, 4, 5, 6, 7, 8, 9
+S_KAPPA, S_FOOT, S_COUNTS, S_NOISE, S_DEPTH, S_ROT, S_SHUFFLE, S_SPLIT, S_CAT, S_FLAT = 1, 2, 3, 4, 5, 6, 7, 8, 9, 10
 
 
 def rng(seed_base, stream):
@@ -305,3 +305,43 @@ def sphere_points(n, seed_base):
     """Directions uniform on the sphere: z ~ U[-1, 1], phi ~ U[0, 2 pi)."""
     g = rng(seed_base, S_CAT + 100)
     return g.uniform(-1.0, 1.0, int(n)), g.uniform(0.0, 2.0 * math.pi, int(n))
+
+
+# ---------------------------------------------------------------------------------------------
+# flat-sky field (the four-step operator with a 2-D FFT)
+# ---------------------------------------------------------------------------------------------
+def make_flat(nx, ny, seed_base, mu=2.0, border=0.05, holes=2000, amp=1e-2):
+    """A flat field of nx x ny square pixels (maps indexed [i2][i1]).
+
+    Mask: the grid minus a border of `border` of each side (zero padding against the periodic
+    boundary), minus `holes` circular holes of radius U[2, 10] pixels (scaled down on small grids),
+    and pixels with no galaxy.  Counts n ~ Poisson(mu), N^-1 = n / sigma_e^2, shape noise
+    eps ~ N(0, sigma_e^2 / n) per component.  kappa_E: a Gaussian random field of power
+    amp (|k| + 0.01)^-1.2 in units of the grid frequency (B = 0).  Returns mask (uint8), ninv,
+    kappa (complex, kappa_E + i 0), eps1, eps2."""
+    g = rng(seed_base, S_FLAT)
+    nx, ny = int(nx), int(ny)
+    i1 = np.arange(nx)[None, :]
+    i2 = np.arange(ny)[:, None]
+    bx, by = int(border * nx), int(border * ny)
+    foot = (i1 >= bx) & (i1 < nx - bx) & (i2 >= by) & (i2 < ny - by)
+    scale = min(nx, ny) / 4096.0
+    for _ in range(int(holes * min(1.0, scale * scale * 4))):
+        cx, cy = g.uniform(0, nx), g.uniform(0, ny)
+        r = max(1.0, g.uniform(2, 10) * max(scale, 0.25))
+        x0, x1 = int(max(cx - r, 0)), int(min(cx + r + 1, nx))
+        y0, y1 = int(max(cy - r, 0)), int(min(cy + r + 1, ny))
+        yy, xx = np.mgrid[y0:y1, x0:x1]
+        foot[y0:y1, x0:x1] &= (xx - cx) ** 2 + (yy - cy) ** 2 > r * r
+    n = g.poisson(mu, (ny, nx))
+    mask = foot & (n >= 1)
+    ninv = n / SIGMA_E ** 2
+    sd = np.where(n > 0, SIGMA_E / np.sqrt(np.maximum(n, 1)), 0.0)
+    e1 = sd * g.normal(size=(ny, nx)) * mask
+    e2 = sd * g.normal(size=(ny, nx)) * mask
+    kx = np.fft.fftfreq(nx)[None, :]
+    ky = np.fft.fftfreq(ny)[:, None]
+    pk = amp * (np.sqrt(kx * kx + ky * ky) + 0.01) ** -1.2
+    white = np.fft.fft2(g.normal(size=(ny, nx)), norm="ortho")
+    kap = np.fft.ifft2(np.sqrt(pk) * white, norm="ortho").real
+    return dict(nx=nx, ny=ny, mask=mask.astype(np.uint8), ninv=ninv, kappa=kap.astype(np.complex128), eps1=e1, eps2=e2)
