@@ -389,6 +389,55 @@ akra_status akra_pixelize(akra_plan plan, const double *z, const double *phi, co
                           const double *w, int64_t n_gal, double R, double sigma_e, double n_th, void *work,
                           int64_t work_bytes, double *g1, double *g2, double *ninv, double *neff, uint8_t *mask);
 
+/*
+ * Flat-sky variant (Sec. II.B, storage problem: on a flat field each spherical harmonic transform
+ * becomes a 2-D FFT, the four-step operator and the CG solver otherwise unchanged).
+ *   field    nx x ny square pixels, periodic; maps float64 [ny][nx] (x index fastest);
+ *   unknown  z = kappa_E + i kappa_B on the grid (joint E/B);
+ *   A z      = F^-1 (D . F z), F the unitary 2-D DFT, D(k) = (k1 + i k2)^2 / |k|^2 the flat-sky
+ *            Kaiser-Squires kernel with D(0) = 0 (it depends only on the direction of k, so the
+ *            pixel size does not enter); gamma = gamma_1 + i gamma_2 = A z;
+ *   H z      = A^H (W . A z) + lambda_eff z,  b = A^H (W . gamma_obs), W = M N^-1,
+ *            lambda_eff = lambda <N^-1>_M, P = (<W> + lambda_eff)^-1 (as on the sphere);
+ * with A^H z = F^-1 (conj(D) . F z), the adjoint for <u, v> = sum_p Re(conj(u_p) v_p).  FP64.
+ * The solver holds x = F z, so one H apply costs two 2-D FFTs.
+ */
+typedef struct akra_flat_plan_s *akra_flat_plan;
+
+/* Plan for an nx x ny field (powers of two in [4, 8192]) on HIP stream hip_stream (NULL = default
+ * stream).  Allocates all device memory of the flat calls.  Errors: AKRA_ERR_ARG, AKRA_ERR_ALLOC,
+ * AKRA_ERR_HIP. */
+akra_status akra_flat_plan_create(int nx, int ny, void *hip_stream, akra_flat_plan *out);
+void akra_flat_plan_destroy(akra_flat_plan plan);
+int64_t akra_flat_plan_device_bytes(akra_flat_plan plan);
+
+/* gamma = A z: kE, kB, g1, g2 device float64 [ny][nx].  Stream-ordered.  Errors: AKRA_ERR_ARG. */
+akra_status akra_flat_synth(akra_flat_plan plan, const double *kE, const double *kB, double *g1, double *g2);
+/* (yE + i yB) = A^H (g1 + i g2).  Stream-ordered.  Errors: AKRA_ERR_ARG. */
+akra_status akra_flat_adjoint(akra_flat_plan plan, const double *g1, const double *g2, double *yE, double *yB);
+/* (yE + i yB) = H (kE + i kB) for W from ninv (device float64 [ny][nx], finite, >= 0) and mask (device
+ * uint8 [ny][nx]) and the given lambda_eff.  Synchronises once (weight validation).  Errors:
+ * AKRA_ERR_ARG (null pointers, negative weights), AKRA_ERR_NUMERIC (non-finite weights). */
+akra_status akra_flat_apply_H(akra_flat_plan plan, const double *ninv, const uint8_t *mask, double lambda_eff,
+                              const double *kE, const double *kB, double *yE, double *yB);
+/* (bE + i bB) = A^H (W (g1 + i g2)).  Errors as akra_flat_apply_H. */
+akra_status akra_flat_rhs(akra_flat_plan plan, const double *g1, const double *g2, const double *ninv,
+                          const uint8_t *mask, double *bE, double *bB);
+/* Regularised estimate (kappa_E, kappa_B) of the flat field by PCG (opts as for akra_cg_solve:
+ * lambda, tol, maxiter, use_x0 with kE/kB as the start maps, resid_hist; mode must be AKRA_JOINT_EB,
+ * kernel_l NULL, reliable_delta unused).  Outputs kE, kB device float64 [ny][nx]; info as for
+ * akra_cg_solve (fp64_applies 0).  ||b|| = 0 gives zero maps.  Errors: AKRA_ERR_ARG, AKRA_ERR_NUMERIC
+ * (non-finite data, CG breakdown), AKRA_NOT_CONVERGED (maxiter; kE, kB hold the last iterate). */
+akra_status akra_flat_cg_solve(akra_flat_plan plan, const double *g1, const double *g2, const double *ninv,
+                               const uint8_t *mask, const akra_cg_opts *opts, double *kE, double *kB,
+                               akra_cg_info *info);
+/* Step-wise PCG on the plan's state: akra_flat_cg_start forms W, lambda_eff = lambda <N^-1>_M, P and b,
+ * and sets x0 = 0 (one synchronisation); akra_flat_cg_step runs nsteps iterations stream-ordered with no
+ * host synchronisation and no convergence test (for timing).  Errors: AKRA_ERR_ARG. */
+akra_status akra_flat_cg_start(akra_flat_plan plan, const double *g1, const double *g2, const double *ninv,
+                               const uint8_t *mask, double lambda);
+akra_status akra_flat_cg_step(akra_flat_plan plan, int nsteps);
+
 #ifdef __cplusplus
 }
 #endif

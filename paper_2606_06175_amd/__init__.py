@@ -5,4 +5,4 @@
     xE, xB, info = plan.cg_solve(g1, g2, ninv, mask, tol=1e-8)
     xE, xB = AkraSolve.apply(g1, g2, ninv, mask, plan, dict(tol=1e-8))   # differentiable
 """
-from .akra import AkraError, AkraSolve, Plan, alm_size, lib  # noqa: F401
+from .akra import AkraError, AkraSolve, FlatPlan, Plan, alm_size, lib  # noqa: F401

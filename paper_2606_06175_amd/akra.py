@@ -87,6 +87,18 @@ def lib():
     L.akra_alm_spectra.argtypes = [vp, vp, ctypes.c_int, vp, ctypes.c_int, vp, ctypes.c_int, vp]
     L.akra_noise_work_size.argtypes = [vp, ctypes.c_int, ctypes.POINTER(i64)]
     L.akra_ang2pix.argtypes = [vp, vp, vp, i64, vp]
+    L.akra_flat_plan_create.argtypes = [ctypes.c_int, ctypes.c_int, vp, ctypes.POINTER(vp)]
+    L.akra_flat_plan_destroy.argtypes = [vp]
+    L.akra_flat_plan_destroy.restype = None
+    L.akra_flat_plan_device_bytes.argtypes = [vp]
+    L.akra_flat_plan_device_bytes.restype = i64
+    L.akra_flat_synth.argtypes = [vp, vp, vp, vp, vp]
+    L.akra_flat_adjoint.argtypes = [vp, vp, vp, vp, vp]
+    L.akra_flat_apply_H.argtypes = [vp, vp, vp, ctypes.c_double, vp, vp, vp, vp]
+    L.akra_flat_rhs.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    L.akra_flat_cg_solve.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(CgOpts), vp, vp, ctypes.POINTER(CgInfo)]
+    L.akra_flat_cg_start.argtypes = [vp, vp, vp, vp, vp, ctypes.c_double]
+    L.akra_flat_cg_step.argtypes = [vp, ctypes.c_int]
     L.akra_pixelize_work_size.argtypes = [vp, i64, ctypes.POINTER(i64)]
     L.akra_pixelize.argtypes = [vp, vp, vp, vp, vp, vp, i64, ctypes.c_double, ctypes.c_double, ctypes.c_double, vp,
                                 i64, vp, vp, vp, vp, vp]
@@ -97,7 +109,9 @@ def lib():
               "akra_plan_stage_times", "akra_plan_set_tuning", "akra_plan_get_tuning", "akra_plan_work",
               "akra_cg_solve_vjp", "akra_cg_solve_cond_b", "akra_set_ring_whole_maxm", "akra_unmasked_index",
               "akra_shuffle_shear", "akra_alm_spectra", "akra_noise_work_size", "akra_noise_spectra", "akra_ang2pix",
-              "akra_pixelize_work_size", "akra_pixelize"):
+              "akra_pixelize_work_size", "akra_pixelize", "akra_flat_plan_create", "akra_flat_synth",
+              "akra_flat_adjoint", "akra_flat_apply_H", "akra_flat_rhs", "akra_flat_cg_solve", "akra_flat_cg_start",
+              "akra_flat_cg_step"):
         getattr(L, f).restype = ctypes.c_int
     _lib = L
     return L
@@ -507,6 +521,122 @@ class Plan:
         v = (ctypes.c_int64 * 3)()
         _check(lib().akra_plan_work(self._h, v))
         return {"all": v[0], "synth": v[1], "adjoint": v[2]}
+
+
+class FlatPlan:
+    """A flat-sky plan (akra_flat_*): an nx x ny periodic field, maps float64 [ny, nx] on the device."""
+
+    def __init__(self, nx, ny, device=None, stream=None):
+        L = lib()
+        self.nx, self.ny = int(nx), int(ny)
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        if self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        with torch.cuda.device(self.device):
+            s = stream if stream is not None else torch.cuda.current_stream(self.device)
+            self.stream = s
+            h = ctypes.c_void_p()
+            _check(L.akra_flat_plan_create(self.nx, self.ny, ctypes.c_void_p(s.cuda_stream), ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().akra_flat_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def device_bytes(self):
+        return lib().akra_flat_plan_device_bytes(self._h)
+
+    def _m(self, t, name, dtype=torch.float64):
+        if t.dtype != dtype or t.device != self.device:
+            raise TypeError("%s must be %s on %s" % (name, dtype, self.device))
+        if t.numel() != self.nx * self.ny:
+            raise ValueError("%s must hold ny x nx = %d x %d entries" % (name, self.ny, self.nx))
+        return t.contiguous()
+
+    def _out(self):
+        return torch.empty((self.ny, self.nx), dtype=torch.float64, device=self.device)
+
+    def synth(self, kE, kB):
+        kE, kB = self._m(kE, "kE"), self._m(kB, "kB")
+        g1, g2 = self._out(), self._out()
+        with torch.cuda.device(self.device):
+            _check(lib().akra_flat_synth(self._h, kE.data_ptr(), kB.data_ptr(), g1.data_ptr(), g2.data_ptr()))
+        return g1, g2
+
+    def adjoint(self, g1, g2):
+        g1, g2 = self._m(g1, "g1"), self._m(g2, "g2")
+        yE, yB = self._out(), self._out()
+        with torch.cuda.device(self.device):
+            _check(lib().akra_flat_adjoint(self._h, g1.data_ptr(), g2.data_ptr(), yE.data_ptr(), yB.data_ptr()))
+        return yE, yB
+
+    def apply_H(self, ninv, mask, kE, kB, lambda_eff):
+        ninv, mask = self._m(ninv, "ninv"), self._m(mask, "mask", torch.uint8)
+        kE, kB = self._m(kE, "kE"), self._m(kB, "kB")
+        yE, yB = self._out(), self._out()
+        with torch.cuda.device(self.device):
+            _check(lib().akra_flat_apply_H(self._h, ninv.data_ptr(), mask.data_ptr(), float(lambda_eff), kE.data_ptr(),
+                                           kB.data_ptr(), yE.data_ptr(), yB.data_ptr()))
+        return yE, yB
+
+    def rhs(self, g1, g2, ninv, mask):
+        g1, g2 = self._m(g1, "g1"), self._m(g2, "g2")
+        ninv, mask = self._m(ninv, "ninv"), self._m(mask, "mask", torch.uint8)
+        bE, bB = self._out(), self._out()
+        with torch.cuda.device(self.device):
+            _check(lib().akra_flat_rhs(self._h, g1.data_ptr(), g2.data_ptr(), ninv.data_ptr(), mask.data_ptr(),
+                                       bE.data_ptr(), bB.data_ptr()))
+        return bE, bB
+
+    def cg_solve(self, g1, g2, ninv, mask, tol=1e-3, maxiter=1000, lam=1e-3, x0=None, hist_len=0,
+                 raise_not_converged=True):
+        """Regularised flat-sky estimate (kappa_E, kappa_B) by PCG (see akra_flat_cg_solve)."""
+        g1, g2 = self._m(g1, "g1"), self._m(g2, "g2")
+        ninv, mask = self._m(ninv, "ninv"), self._m(mask, "mask", torch.uint8)
+        kE, kB = self._out(), self._out()
+        if x0 is not None:
+            kE.copy_(x0[0].reshape(kE.shape))
+            kB.copy_(x0[1].reshape(kB.shape))
+        o = CgOpts()
+        lib().akra_cg_opts_default(ctypes.byref(o))
+        o.lambda_, o.tol, o.maxiter = float(lam), float(tol), int(maxiter)
+        o.use_x0 = 1 if x0 is not None else 0
+        keep = []
+        if hist_len:
+            import numpy as np
+            h = np.zeros(hist_len)
+            keep.append(h)
+            o.resid_hist = h.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            o.resid_hist_len = hist_len
+        inf = CgInfo()
+        with torch.cuda.device(self.device):
+            st = lib().akra_flat_cg_solve(self._h, g1.data_ptr(), g2.data_ptr(), ninv.data_ptr(), mask.data_ptr(),
+                                          ctypes.byref(o), kE.data_ptr(), kB.data_ptr(), ctypes.byref(inf))
+        if st != AKRA_OK and (st != AKRA_NOT_CONVERGED or raise_not_converged):
+            _check(st)
+        d = {k: getattr(inf, k) for k, _ in CgInfo._fields_}
+        if hist_len:
+            d["hist"] = keep[0][: inf.iters].copy()
+        return kE, kB, d
+
+    def cg_start(self, g1, g2, ninv, mask, lam=1e-3):
+        g1, g2 = self._m(g1, "g1"), self._m(g2, "g2")
+        ninv, mask = self._m(ninv, "ninv"), self._m(mask, "mask", torch.uint8)
+        with torch.cuda.device(self.device):
+            _check(lib().akra_flat_cg_start(self._h, g1.data_ptr(), g2.data_ptr(), ninv.data_ptr(), mask.data_ptr(),
+                                            float(lam)))
+
+    def cg_step(self, nsteps=1):
+        with torch.cuda.device(self.device):
+            _check(lib().akra_flat_cg_step(self._h, int(nsteps)))
 
 
 class AkraSolve(torch.autograd.Function):

@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libakra.so")
-SOURCES = ["akra_plan.hip", "akra_kernels.hip", "akra_spectra.hip", "akra_pixel.hip"]
+SOURCES = ["akra_plan.hip", "akra_kernels.hip", "akra_spectra.hip", "akra_pixel.hip", "akra_flat.hip"]
 # Packed FP32 VALU forms are disabled for every HIP translation unit.
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
