@@ -244,6 +244,57 @@ def pixelize_leg(n_gal, nside, reps=3):
     return out
 
 
+# HBM bytes one flat-sky H apply must move per grid point: three row-transform passes that read and
+# write the complex field (3 x 32 B), two transposes (2 x 32 B), the weight (8 B) and the + lambda x
+# read of the last pass (16 B)
+FLAT_BYTES_PER_POINT = 3 * 32 + 2 * 32 + 8 + 16
+
+
+def flat_leg(n, steps, tol, maxiter):
+    """Flat-sky variant: an n x n field (border and holes, Poisson mean 2), FP64 operator; applies/s
+    from the step-wise PCG on device-resident data, the HBM roofline of one apply, and a solve."""
+    import torch
+
+    import akra_workloads as wl
+    from paper_2606_06175_amd import FlatPlan
+
+    dev = torch.device("cuda", 0)
+    t = time.time()
+    f = wl.make_flat(n, n, 3)
+    log("flat field %d x %d generated in %.1f s (unmasked %.3f)" % (n, n, time.time() - t, f["mask"].mean()))
+    p = FlatPlan(n, n, device=dev)
+    kE = torch.from_numpy(f["kappa"].real.copy()).to(dev)
+    g1, g2 = p.synth(kE, torch.zeros_like(kE))
+    m = torch.from_numpy(f["mask"]).to(dev)
+    mf = m.to(torch.float64)
+    g1 = mf * (g1 + torch.from_numpy(f["eps1"]).to(dev))
+    g2 = mf * (g2 + torch.from_numpy(f["eps2"]).to(dev))
+    ninv = torch.from_numpy(f["ninv"]).to(dev)
+    p.cg_start(g1, g2, ninv, m)
+    p.cg_step(2)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    p.cg_step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    _, _, info = p.cg_solve(g1, g2, ninv, m, tol=tol, maxiter=maxiter, raise_not_converged=False)
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t
+    gbs = FLAT_BYTES_PER_POINT * n * n / (ms * 1e-3) / 1e9
+    out = {"workload": "flat field %d x %d, FP64, joint E/B" % (n, n), "applies_per_s": 1e3 / ms,
+           "ms_per_step": ms, "algorithmic_bytes_per_apply": FLAT_BYTES_PER_POINT * n * n,
+           "hbm_GBs": gbs, "hbm_frac": gbs / 8000.0,
+           "solve_to_%g" % tol: {"seconds": ts, "iters": info["iters"], "rel_resid_true": info["rel_resid_true"],
+                                 "status": info["status"]}}
+    log("flat: %s" % out)
+    p.close()
+    return out
+
+
 def full_norm(a, b, lmax):
     """Full-m norm of stacked (E, B) complex alm on the device."""
     import torch
@@ -265,6 +316,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-workload", default="C4")
     ap.add_argument("--no-pixelize", action="store_true")
+    ap.add_argument("--no-flat", action="store_true")
+    ap.add_argument("--flat-n", type=int, default=4096)
     ap.add_argument("--pixelize-galaxies", type=int, default=100_000_000)
     ap.add_argument("--cpu-sample-rings", type=int, default=192)
     ap.add_argument("--solve-tol", type=float, default=1e-8)
@@ -400,6 +453,8 @@ def main():
         out["batched"] = batched_leg(args.batched_workload, args.solve_tol, args.maxiter)
     if not args.no_pixelize:
         out["pixelize"] = pixelize_leg(args.pixelize_galaxies, nside)
+    if not args.no_flat:
+        out["flat"] = flat_leg(args.flat_n, max(args.steps, 10), args.solve_tol, args.maxiter)
 
     if not args.no_cpu_baseline:
         t = time.time()
