@@ -30,11 +30,12 @@ FLOP_PER_TRIPLE = 26     # per (l, m, ring pair) and direction: 2 recurrences (1
 
 # HBM bytes per launch of the dominant kernel from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE at this
 # workload, each scaled by the same counter's reading for a device copy of known size; valid only for
-# the kernel source they were taken from (its SHA-256 is checked at run time).
+# the kernel sources they were taken from (the SHA-256 of akra_kernels.hip followed by akra_fft.h is
+# checked at run time).
 TRAFFIC = {
-    # profiles/k_leg_adj_nside2048_lmax4096_fp64.md: FETCH 2.4884e6 KiB x 1.99994 + WRITE 3.1589e6 KiB x 1.0000
-    "leg_adj": {"bytes": 8.3309e9, "workload": (2048, 4096),
-                "kernels_sha256": "128d810e83c49b02a0081d2d01ca5a18c1189084a0d8e4fd45826b891591448c"},
+    # profiles/k_leg_adj_nside2048_lmax4096_fp64.md: FETCH 2.4826e6 KiB x 2.0 + WRITE 3.1590e6 KiB x 1.0
+    "leg_adj": {"bytes": 8.319e9, "workload": (2048, 4096),
+                "kernels_sha256": "9875e55018237c8f8b166b4df8d6150855e9e3622ea2644ac7e01920c380a790"},
 }
 
 
@@ -43,10 +44,12 @@ def traffic(stage, nside, lmax):
     rec = TRAFFIC.get(stage)
     if not rec or rec["workload"] != (nside, lmax):
         return None
-    src = os.path.join(ROOT, "paper_2606_06175_amd", "csrc", "akra_kernels.hip")
-    with open(src, "rb") as f:
-        if hashlib.sha256(f.read()).hexdigest() != rec["kernels_sha256"]:
-            return None
+    h = hashlib.sha256()
+    for name in ("akra_kernels.hip", "akra_fft.h"):
+        with open(os.path.join(ROOT, "paper_2606_06175_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest() != rec["kernels_sha256"]:
+        return None
     return rec["bytes"]
 
 

@@ -73,6 +73,7 @@ struct FRowArgs {
     double *out1, *out2;        // real maps (FR_INV_MAPS)
     const double *W;            // weights [rows][L] (FR_PIX_W; FR_FWD_MAPS when non-null)
     const double2 *xadd;        // FR_FWD_OUT: + lam * xadd when non-null
+    double *dot_part;           // FR_FWD_OUT: per-row Re sum conj(xadd) out when non-null
     double lam, scale;
     int L;                      // row length (power of two)
     int dmode;                  // FR_INV_D / FR_FWD_OUT: 0 times D, 1 times conj(D), -1 none
@@ -147,6 +148,7 @@ __global__ __launch_bounds__(NT) void k_frow(FRowArgs a)
         }
         __syncthreads();
         fft_dit<double, NT>(buf, L, a.tw, a.twn, -1);
+        double dot = 0.0;
         for (int k = tid; k < L; k += NT) {
             double2 v = buf[pd(k)];
             v = make_double2(v.x * a.scale, v.y * a.scale);
@@ -155,9 +157,25 @@ __global__ __launch_bounds__(NT) void k_frow(FRowArgs a)
                 if (a.xadd) {
                     const double2 x = a.xadd[base + k];
                     v = make_double2(v.x + a.lam * x.x, v.y + a.lam * x.y);
+                    dot += x.x * v.x + x.y * v.y;
                 }
             }
             a.out[base + k] = v;
+        }
+        if constexpr (MODE == FR_FWD_OUT) {
+            if (a.dot_part) {
+                // row sum in a fixed order: within waves by butterfly, then the waves in order
+                __shared__ double wsum[NT / 64];
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) dot += __shfl_xor(dot, o, 64);
+                if ((tid & 63) == 0) wsum[tid >> 6] = dot;
+                __syncthreads();
+                if (tid == 0) {
+                    double t = 0.0;
+                    for (int w = 0; w < NT / 64; ++w) t += wsum[w];
+                    a.dot_part[r] = t;
+                }
+            }
         }
     }
 }
@@ -267,28 +285,36 @@ __global__ void k_fcg_beta(double *s, double pc)
     s[0] = rz;
 }
 
-__global__ void k_fcg_xr(double2 *__restrict__ x, double2 *__restrict__ r, const double2 *__restrict__ p,
-                         const double2 *__restrict__ w, const double *__restrict__ s, int64_t n)
+// r -= alpha w, with per-block partials of <r, r>
+__global__ __launch_bounds__(256) void k_fcg_r(double2 *__restrict__ r, const double2 *__restrict__ w,
+                                               const double *__restrict__ s, int64_t n, double *__restrict__ part)
 {
+    __shared__ double sh[256];
     const double al = s[2];
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const double2 pv = p[i], wv = w[i];
-        double2 xv = x[i], rv = r[i];
-        xv.x += al * pv.x;
-        xv.y += al * pv.y;
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const double2 wv = w[i];
+        double2 rv = r[i];
         rv.x -= al * wv.x;
         rv.y -= al * wv.y;
-        x[i] = xv;
         r[i] = rv;
+        acc += rv.x * rv.x + rv.y * rv.y;
     }
+    acc = block_sum256(acc, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = acc;
 }
 
-__global__ void k_fcg_p(double2 *__restrict__ p, const double2 *__restrict__ r, const double *__restrict__ s, double pc,
-                        int64_t n)
+// x += alpha p, then p = P r + beta p, in one pass
+__global__ void k_fcg_px(double2 *__restrict__ x, double2 *__restrict__ p, const double2 *__restrict__ r,
+                         const double *__restrict__ s, double pc, int64_t n)
 {
-    const double be = s[4];
+    const double al = s[2], be = s[4];
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const double2 rv = r[i], pv = p[i];
+        const double2 pv = p[i], rv = r[i];
+        double2 xv = x[i];
+        xv.x += al * pv.x;
+        xv.y += al * pv.y;
+        x[i] = xv;
         p[i] = make_double2(pc * rv.x + be * pv.x, pc * rv.y + be * pv.y);
     }
 }
@@ -303,6 +329,8 @@ __global__ void k_faxpby(double2 *__restrict__ y, double a, const double2 *__res
 }
 
 // ---- launch helpers ---------------------------------------------------------------------------------
+static int vgrid(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096)); }
+
 // LDS bytes of a row of length L with the pad slot of pd() every 32 elements
 static size_t row_lds(int L) { return (size_t)(L + (L - 1) / 32) * sizeof(double2); }
 
@@ -380,8 +408,8 @@ static void to_maps(FlatPlan &F, const double2 *x, int dmode, double *o1, double
     row_pass_nt<FR_INV_MAPS>(F, b, F.ny);
 }
 
-// y = conj(D) F (W F^-1 (D x)) + lam x, with the weights in d_W
-static void apply_H(FlatPlan &F, const double2 *x, double2 *y, double lam)
+// y = conj(D) F (W F^-1 (D x)) + lam x, with the weights in d_W; with dot_out, also <x, y> there
+static void apply_H(FlatPlan &F, const double2 *x, double2 *y, double lam, double *dot_out = nullptr)
 {
     FRowArgs a = row_args(F, F.ny);
     a.in = x;
@@ -400,9 +428,26 @@ static void apply_H(FlatPlan &F, const double2 *x, double2 *y, double lam)
     c.out = y;
     c.dmode = 1;
     c.scale = 1.0 / (double)F.n;
-    c.xadd = lam != 0.0 ? x : nullptr;
+    c.xadd = (lam != 0.0 || dot_out) ? x : nullptr;
     c.lam = lam;
+    c.dot_part = dot_out ? F.d_red : nullptr;
     row_pass_nt<FR_FWD_OUT>(F, c, F.nx);
+    if (dot_out) k_fsum<<<1, 256, 0, F.stream>>>(F.d_red, F.nx, 1, dot_out);
+}
+
+// one PCG iteration on device-resident state (scalars in d_scal):
+//   w = H p and <p, w> in one pass, alpha, r -= alpha w and <r, r>, beta, x += alpha p and
+//   p = P r + beta p in one pass
+static void cg_iteration(FlatPlan &F, double lam, double pc)
+{
+    double *s = F.d_scal;
+    const int vg = vgrid(F.n);
+    apply_H(F, F.d_p, F.d_w, lam, s + 1);
+    k_fcg_alpha<<<1, 1, 0, F.stream>>>(s, F.d_flag);
+    k_fcg_r<<<FL_RED, 256, 0, F.stream>>>(F.d_r, F.d_w, s, F.n, F.d_red);
+    k_fsum<<<1, 256, 0, F.stream>>>(F.d_red, FL_RED, 1, s + 3);
+    k_fcg_beta<<<1, 1, 0, F.stream>>>(s, pc);
+    k_fcg_px<<<vg, 256, 0, F.stream>>>(F.d_x, F.d_p, F.d_r, s, pc, F.n);
 }
 
 static void fdot(FlatPlan &F, const double2 *a, const double2 *b, double *out)
@@ -442,8 +487,6 @@ static akra_status weights(FlatPlan &F, const double *ninv, const uint8_t *mask,
     *pc = 1.0 / (s[0] / (double)F.n + *lam_eff);
     return AKRA_OK;
 }
-
-static int vgrid(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096)); }
 
 static void free_flat(FlatPlan *F)
 {
@@ -496,7 +539,7 @@ akra_status akra_flat_plan_create(int nx, int ny, void *hip_stream, akra_flat_pl
     bool ok = al((void **)&F->d_tw, sizeof(double2) * (F->twn / 2)) && al((void **)&F->d_W, sizeof(double) * F->n) &&
               al((void **)&F->d_x, cb) && al((void **)&F->d_r, cb) && al((void **)&F->d_p, cb) &&
               al((void **)&F->d_w, cb) && al((void **)&F->d_b, cb) && al((void **)&F->d_t1, cb) &&
-              al((void **)&F->d_t2, cb) && al((void **)&F->d_red, sizeof(double) * FL_RED * 4) &&
+              al((void **)&F->d_t2, cb) && al((void **)&F->d_red, sizeof(double) * std::max(FL_RED * 4, nx)) &&
               al((void **)&F->d_scal, sizeof(double) * 64) && al((void **)&F->d_flag, sizeof(int) * 4);
     if (ok && hipHostMalloc((void **)&F->h_pin, 64 * sizeof(double)) != hipSuccess) {
         F->h_pin = nullptr;
@@ -667,13 +710,7 @@ akra_status akra_flat_cg_solve(akra_flat_plan plan, const double *g1, const doub
                 break;
             }
             if (it >= o.maxiter) break;
-            apply_H(F, F.d_p, F.d_w, le);
-            fdot(F, F.d_p, F.d_w, s + 1);
-            k_fcg_alpha<<<1, 1, 0, F.stream>>>(s, F.d_flag);
-            k_fcg_xr<<<vg, 256, 0, F.stream>>>(F.d_x, F.d_r, F.d_p, F.d_w, s, n);
-            fdot(F, F.d_r, F.d_r, s + 3);
-            k_fcg_beta<<<1, 1, 0, F.stream>>>(s, pc);
-            k_fcg_p<<<vg, 256, 0, F.stream>>>(F.d_p, F.d_r, s, pc, n);
+            cg_iteration(F, le, pc);
             ++it;
             st = fl_check("flat_cg");
             if (st) return st;
@@ -749,17 +786,7 @@ akra_status akra_flat_cg_step(akra_flat_plan plan, int nsteps)
         return AKRA_ERR_ARG;
     }
     const double le = F.step_lam, pc = F.step_pc;
-    const int vg = vgrid(F.n);
-    double *s = F.d_scal;
-    for (int k = 0; k < nsteps; ++k) {
-        apply_H(F, F.d_p, F.d_w, le);
-        fdot(F, F.d_p, F.d_w, s + 1);
-        k_fcg_alpha<<<1, 1, 0, F.stream>>>(s, F.d_flag);
-        k_fcg_xr<<<vg, 256, 0, F.stream>>>(F.d_x, F.d_r, F.d_p, F.d_w, s, F.n);
-        fdot(F, F.d_r, F.d_r, s + 3);
-        k_fcg_beta<<<1, 1, 0, F.stream>>>(s, pc);
-        k_fcg_p<<<vg, 256, 0, F.stream>>>(F.d_p, F.d_r, s, pc, F.n);
-    }
+    for (int k = 0; k < nsteps; ++k) cg_iteration(F, le, pc);
     return fl_check("flat_cg_step");
 }
 
