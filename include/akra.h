@@ -371,8 +371,8 @@ akra_status akra_noise_spectra(akra_plan plan, int nset, const double *g1, const
 akra_status akra_ang2pix(akra_plan plan, const double *z, const double *phi, int64_t n, int32_t *pix);
 
 /* Device bytes of the workspace akra_pixelize needs for n_gal galaxies (0 <= n_gal < 2^31), written
- * to *bytes (HOST): pixel keys, their sorted copy and galaxy order, per-pixel runs and the radix-sort
- * storage.  Errors: AKRA_ERR_ARG. */
+ * to *bytes (HOST): a 32-byte record {w, w e1, w e2, w^2} per galaxy, pixel keys, their sorted copy
+ * and galaxy order, per-pixel runs and the radix-sort storage.  Errors: AKRA_ERR_ARG. */
 akra_status akra_pixelize_work_size(akra_plan plan, int64_t n_gal, int64_t *bytes);
 
 /*

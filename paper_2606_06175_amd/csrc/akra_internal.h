@@ -238,16 +238,16 @@ void launch_cl_moments(Plan &P, const double *cl, int n, int64_t len, double *me
 // catalogue pixelisation (akra_pixel.hip)
 // device bytes of the pixelisation workspace for n_gal galaxies (sort keys, runs, sort storage)
 hipError_t pixelize_work_bytes(Plan &P, int64_t n_gal, int64_t *bytes);
-// where the pixel keys of the galaxies live inside that workspace
-uint32_t *pixelize_keys(Plan &P, int64_t n, void *work);
+// where the pixel keys and the galaxy records live inside that workspace
+uint32_t *pixelize_keys(Plan &P, int64_t n, void *work, double4 **rec);
 // RING pixel of every galaxy into pix; out-of-range inputs set d_cmp_flag[0] (position) or
-// d_cmp_flag[1] (weight / ellipticity, checked when e1 is non-null)
+// d_cmp_flag[1] (weight / ellipticity, checked when e1 is non-null, which also writes the galaxy
+// records {w, w e1, w e2, w^2} into rec)
 void launch_ang2pix(Plan &P, const double *z, const double *phi, const double *e1, const double *e2, const double *w,
-                    int64_t n, uint32_t *pix);
-// sort by pixel, per-pixel sums in catalogue order and the pixel products (keys already written)
-hipError_t launch_pixelize(Plan &P, const double *e1, const double *e2, const double *w, int64_t n, double R,
-                           double se2, double n_th, void *work, double *g1, double *g2, double *ninv, double *neff,
-                           uint8_t *mask);
+                    int64_t n, uint32_t *pix, double4 *rec);
+// sort by pixel, per-pixel sums in catalogue order and the pixel products (keys and records written)
+hipError_t launch_pixelize(Plan &P, int64_t n, double R, double se2, double n_th, void *work, double *g1, double *g2,
+                           double *ninv, double *neff, uint8_t *mask);
 bool pow2(int n);
 bool adj_shape_supported(int r, int w, int l);
 

@@ -44,12 +44,15 @@ __device__ int64_t ang2pix_ring(int nside, double z, double phi)
 }
 
 // pixel of every galaxy; inputs out of range set flag (1: position, 2: weight or ellipticity) and
-// give pixel 0, so later stages stay in bounds
+// give pixel 0, so later stages stay in bounds.  With ellipticities, also the galaxy's record
+// {w, w e1, w e2, w^2} (each product rounded once), so that the per-pixel pass gathers one 32-byte
+// record per galaxy instead of three scattered values.
 __global__ void k_ang2pix(const double *__restrict__ z, const double *__restrict__ phi,
                           const double *__restrict__ e1, const double *__restrict__ e2,
                           const double *__restrict__ w, int64_t n, int nside, uint32_t *__restrict__ pix,
-                          int *__restrict__ flag)
+                          double4 *__restrict__ rec, int *__restrict__ flag)
 {
+#pragma clang fp contract(off)
     for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
         const double zz = z[j], pp = phi[j];
         int64_t p = 0;
@@ -59,8 +62,9 @@ __global__ void k_ang2pix(const double *__restrict__ z, const double *__restrict
             p = ang2pix_ring(nside, zz, pp);
         }
         if (e1) {
-            const double ww = w[j];
-            if (!(ww >= 0.0) || !isfinite(ww) || !isfinite(e1[j]) || !isfinite(e2[j])) flag[1] = 2;
+            const double ww = w[j], a = e1[j], b = e2[j];
+            if (!(ww >= 0.0) || !isfinite(ww) || !isfinite(a) || !isfinite(b)) flag[1] = 2;
+            rec[j] = make_double4(ww, ww * a, ww * b, ww * ww);
         }
         pix[j] = (uint32_t)p;
     }
@@ -88,8 +92,7 @@ __global__ void k_seg_bounds(const uint32_t *__restrict__ keys, int64_t n, int32
 // per pixel: sums over its galaxies in catalogue order, then eq. gamma_obs, Neff_pixel, noise_var,
 // mask (sum w = 0: no shear; sum w^2 = 0: N_eff = 0)
 __global__ void k_pix_accum(const int32_t *__restrict__ start, const int32_t *__restrict__ end,
-                            const uint32_t *__restrict__ gal, const double *__restrict__ e1,
-                            const double *__restrict__ e2, const double *__restrict__ w, int64_t npix, double R,
+                            const uint32_t *__restrict__ gal, const double4 *__restrict__ rec, int64_t npix, double R,
                             double se2, double n_th, double *__restrict__ g1, double *__restrict__ g2,
                             double *__restrict__ ninv, double *__restrict__ neff, uint8_t *__restrict__ mask)
 {
@@ -98,12 +101,11 @@ __global__ void k_pix_accum(const int32_t *__restrict__ start, const int32_t *__
         double sw = 0.0, s1 = 0.0, s2 = 0.0, sww = 0.0;
         const int32_t b = start[p], e = end[p];
         for (int32_t i = b; i < e; ++i) {
-            const uint32_t j = gal[i];
-            const double wj = w[j];
-            sw = sw + wj;
-            s1 = s1 + wj * e1[j];
-            s2 = s2 + wj * e2[j];
-            sww = sww + wj * wj;
+            const double4 g = rec[gal[i]];
+            sw = sw + g.x;
+            s1 = s1 + g.y;
+            s2 = s2 + g.z;
+            sww = sww + g.w;
         }
         const double den = R * sw;
         const double ne = (sww != 0.0) ? (sw * sw) / sww : 0.0;
@@ -127,8 +129,10 @@ static int grid_for(int64_t n)
     return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 16384));
 }
 
-// workspace: unsorted keys, sorted keys, sorted galaxy indices, pixel runs, radix-sort storage
+// workspace: galaxy records, unsorted keys, sorted keys, sorted galaxy indices, pixel runs,
+// radix-sort storage
 struct PixWork {
+    double4 *rec;
     uint32_t *keys, *keys_s, *gal_s;
     int32_t *seg_a, *seg_b;
     void *tmp;
@@ -147,10 +151,12 @@ static hipError_t pixelize_work(Plan &P, int64_t n_gal, void *base, int64_t *byt
                                              P.stream);
     if (e != hipSuccess) return e;
     const int64_t ng = std::max<int64_t>(n_gal, 1);
-    const int64_t total = 3 * a256(4 * ng) + 2 * a256(4 * P.npix) + a256((int64_t)tb);
+    const int64_t total = a256(32 * ng) + 3 * a256(4 * ng) + 2 * a256(4 * P.npix) + a256((int64_t)tb);
     if (bytes) *bytes = total;
     if (pw && base) {
         char *c = (char *)base;
+        pw->rec = (double4 *)c;
+        c += a256(32 * ng);
         pw->keys = (uint32_t *)c;
         c += a256(4 * ng);
         pw->keys_s = (uint32_t *)c;
@@ -168,14 +174,13 @@ static hipError_t pixelize_work(Plan &P, int64_t n_gal, void *base, int64_t *byt
 }
 
 void launch_ang2pix(Plan &P, const double *z, const double *phi, const double *e1, const double *e2, const double *w,
-                    int64_t n, uint32_t *pix)
+                    int64_t n, uint32_t *pix, double4 *rec)
 {
-    if (n > 0) k_ang2pix<<<grid_for(n), 256, 0, P.stream>>>(z, phi, e1, e2, w, n, P.nside, pix, P.d_cmp_flag);
+    if (n > 0) k_ang2pix<<<grid_for(n), 256, 0, P.stream>>>(z, phi, e1, e2, w, n, P.nside, pix, rec, P.d_cmp_flag);
 }
 
-hipError_t launch_pixelize(Plan &P, const double *e1, const double *e2, const double *w, int64_t n, double R,
-                           double se2, double n_th, void *work, double *g1, double *g2, double *ninv, double *neff,
-                           uint8_t *mask)
+hipError_t launch_pixelize(Plan &P, int64_t n, double R, double se2, double n_th, void *work, double *g1, double *g2,
+                           double *ninv, double *neff, uint8_t *mask)
 {
     PixWork pw;
     int64_t total = 0;
@@ -189,8 +194,8 @@ hipError_t launch_pixelize(Plan &P, const double *e1, const double *e2, const do
         if (e != hipSuccess) return e;
         k_seg_bounds<<<grid_for(n), 256, 0, P.stream>>>(pw.keys_s, n, pw.seg_a, pw.seg_b);
     }
-    k_pix_accum<<<grid_for(P.npix), 256, 0, P.stream>>>(pw.seg_a, pw.seg_b, pw.gal_s, e1, e2, w, P.npix, R, se2, n_th,
-                                                        g1, g2, ninv, neff, mask);
+    k_pix_accum<<<grid_for(P.npix), 256, 0, P.stream>>>(pw.seg_a, pw.seg_b, pw.gal_s, pw.rec, P.npix, R, se2, n_th, g1,
+                                                        g2, ninv, neff, mask);
     return hipGetLastError();
 }
 
@@ -199,10 +204,11 @@ hipError_t pixelize_work_bytes(Plan &P, int64_t n_gal, int64_t *bytes)
     return pixelize_work(P, n_gal, nullptr, bytes, nullptr);
 }
 
-uint32_t *pixelize_keys(Plan &P, int64_t n, void *work)
+uint32_t *pixelize_keys(Plan &P, int64_t n, void *work, double4 **rec)
 {
     PixWork pw;
     if (pixelize_work(P, n, work, nullptr, &pw) != hipSuccess) return nullptr;
+    *rec = pw.rec;
     return pw.keys;
 }
 

@@ -1940,7 +1940,7 @@ akra_status akra_ang2pix(akra_plan plan, const double *z, const double *phi, int
         return AKRA_ERR_ARG;
     }
     AK_HIP(hipMemsetAsync(P.d_cmp_flag, 0, 2 * sizeof(int), P.stream), "memset");
-    launch_ang2pix(P, z, phi, nullptr, nullptr, nullptr, n, (uint32_t *)pix);
+    launch_ang2pix(P, z, phi, nullptr, nullptr, nullptr, n, (uint32_t *)pix, nullptr);
     akra_status st = check_launch("ang2pix");
     if (st) return st;
     int f[2];
@@ -1989,7 +1989,13 @@ akra_status akra_pixelize(akra_plan plan, const double *z, const double *phi, co
         return AKRA_ERR_ARG;
     }
     AK_HIP(hipMemsetAsync(P.d_cmp_flag, 0, 2 * sizeof(int), P.stream), "memset");
-    launch_ang2pix(P, z, phi, e1, e2, w, n_gal, pixelize_keys(P, n_gal, work));
+    double4 *rec = nullptr;
+    uint32_t *keys = pixelize_keys(P, n_gal, work, &rec);
+    if (!keys) {
+        set_error("radix sort storage query failed");
+        return AKRA_ERR_HIP;
+    }
+    launch_ang2pix(P, z, phi, e1, e2, w, n_gal, keys, rec);
     st = check_launch("ang2pix");
     if (st) return st;
     int f[2];
@@ -2000,8 +2006,7 @@ akra_status akra_pixelize(akra_plan plan, const double *z, const double *phi, co
                        : "a weight is negative or not finite, or an ellipticity is not finite");
         return AKRA_ERR_ARG;
     }
-    AK_HIP(launch_pixelize(P, e1, e2, w, n_gal, R, sigma_e * sigma_e, n_th, work, g1, g2, ninv, neff, mask),
-           "pixelize");
+    AK_HIP(launch_pixelize(P, n_gal, R, sigma_e * sigma_e, n_th, work, g1, g2, ninv, neff, mask), "pixelize");
     AK_HIP(hipStreamSynchronize(P.stream), "sync");
     return AKRA_OK;
 }
