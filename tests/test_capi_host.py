@@ -1,6 +1,6 @@
-"""Host-side logic of the C ABI that runs without a GPU: argument validation of akra_plan_create
-(rejected before any HIP call), the error message channel, NULL-plan handling and the default
-solver options."""
+"""Host-side logic of the C ABI that runs without a GPU: argument validation of akra_plan_create and
+akra_flat_plan_create (rejected before any HIP call), the error message channel, NULL-plan handling
+of every entry point that takes a plan, and the default solver options."""
 import ctypes
 import os
 
@@ -48,3 +48,40 @@ def test_default_options(L):
     assert o.lambda_ == 1e-3 and o.tol == 1e-3 and o.maxiter == 1000
     assert o.use_x0 == 0 and not o.kernel_l and o.reliable_delta == 0.1
     assert not o.resid_hist and o.resid_hist_len == 0
+
+
+def test_null_plan_of_the_stage_calls(L):
+    # every entry point that takes a plan rejects NULL before touching the device
+    n = ctypes.c_int64()
+    assert L.akra_unmasked_index(None, None, None, ctypes.byref(n)) == akra.AKRA_ERR_ARG
+    assert L.akra_shuffle_shear(None, None, None, None, 0, None, 1, None, None) == akra.AKRA_ERR_ARG
+    assert L.akra_alm_spectra(None, None, 1, None, 1, None, 1, None) == akra.AKRA_ERR_ARG
+    assert L.akra_noise_work_size(None, 1, ctypes.byref(n)) == akra.AKRA_ERR_ARG
+    assert L.akra_noise_spectra(None, 1, None, None, None, None, None, 0, 0, None, None, 0, None, None, None,
+                                None) == akra.AKRA_ERR_ARG
+    assert L.akra_ang2pix(None, None, None, 1, None) == akra.AKRA_ERR_ARG
+    assert L.akra_pixelize_work_size(None, 1, ctypes.byref(n)) == akra.AKRA_ERR_ARG
+    assert L.akra_pixelize(None, None, None, None, None, None, 0, 0.7, 0.26, 1.0, None, 0, None, None, None, None,
+                           None) == akra.AKRA_ERR_ARG
+    assert "plan is NULL" in L.akra_last_error().decode()
+
+
+@pytest.mark.parametrize("nx,ny", [(3, 8), (8, 3), (2, 8), (16384, 8), (8, 16384), (12, 16), (0, 4)])
+def test_flat_plan_rejects_bad_sizes(L, nx, ny):
+    h = ctypes.c_void_p()
+    assert L.akra_flat_plan_create(nx, ny, None, ctypes.byref(h)) == akra.AKRA_ERR_ARG
+    assert not h.value
+    assert "powers of two" in L.akra_last_error().decode()
+
+
+def test_null_flat_plan(L):
+    assert L.akra_flat_synth(None, None, None, None, None) == akra.AKRA_ERR_ARG
+    assert L.akra_flat_adjoint(None, None, None, None, None) == akra.AKRA_ERR_ARG
+    assert L.akra_flat_apply_H(None, None, None, 0.0, None, None, None, None) == akra.AKRA_ERR_ARG
+    assert L.akra_flat_rhs(None, None, None, None, None, None, None) == akra.AKRA_ERR_ARG
+    assert L.akra_flat_cg_solve(None, None, None, None, None, None, None, None, None) == akra.AKRA_ERR_ARG
+    assert L.akra_flat_cg_start(None, None, None, None, None, 1e-3) == akra.AKRA_ERR_ARG
+    assert L.akra_flat_cg_step(None, 1) == akra.AKRA_ERR_ARG
+    assert L.akra_flat_plan_device_bytes(None) == 0
+    L.akra_flat_plan_destroy(None)  # a no-op
+    assert L.akra_flat_plan_create(8, 8, None, None) == akra.AKRA_ERR_ARG
