@@ -298,6 +298,101 @@ def flat_leg(n, steps, tol, maxiter):
     return out
 
 
+def rates_leg(c3cfg, tol, maxiter):
+    """Apply rates of akra_apply_H (FP64 and FP32, single right-hand side) at every configuration and
+    time-to-tol below the headline size (the oracle beside them is part of cpu_baseline).  Each rate is the median
+    of 20 applies after 3 warm-ups, HIP events on the plan stream; an apply includes its weight
+    set-up (one reduction and one host synchronisation)."""
+    import numpy as np
+    import torch
+
+    import akra_workloads as wl
+    from paper_2606_06175_amd import Plan
+
+    dev = torch.device("cuda", 0)
+    out = {}
+    for name in ("C1", "C5", "C2", "C3"):
+        cfg = c3cfg if name == "C3" else wl.make_config(name)
+        nside, lmax = cfg["nside"], cfg["lmax"]
+        ninv = torch.from_numpy(cfg["ninv"][0]).to(dev)
+        mask = torch.from_numpy(cfg["mask"]).to(dev)
+        xa = [torch.from_numpy(wl.random_alm(lmax, 1 + k)).to(dev) for k in (0, 1)]
+        row = {"workload": "%s: HEALPix Nside %d, lmax %d" % (name, nside, lmax)}
+        if name != "C3":
+            l = l_of(lmax)
+            K = np.zeros(lmax + 1)
+            ll = np.arange(2, lmax + 1, dtype=np.float64)
+            K[2:] = np.sqrt((ll - 1) * (ll + 2) / (ll * (ll + 1)))
+            kap = torch.from_numpy(cfg["kappa"][0] * K[l]).to(dev)
+        for prec in ("fp64", "fp32"):
+            p = Plan(nside, lmax, precision=prec, device=dev)
+            for _ in range(3):
+                p.apply_H(ninv, mask, xa[0], xa[1], 1e-3)
+            ts = []
+            for _ in range(20):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                p.apply_H(ninv, mask, xa[0], xa[1], 1e-3)
+                e1.record()
+                torch.cuda.synchronize()
+                ts.append(e0.elapsed_time(e1))
+            row[prec + "_applies_per_s"] = 1e3 / float(np.median(ts))
+            if name != "C3":
+                g1, g2 = p.synth2(kap, torch.zeros_like(kap))
+                m = mask.to(torch.float64)
+                g1 = m * (g1 + torch.from_numpy(cfg["eps1"][0]).to(dev))
+                g2 = m * (g2 + torch.from_numpy(cfg["eps2"][0]).to(dev))
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                _, _, info = p.cg_solve(g1, g2, ninv, mask, tol=tol, maxiter=maxiter, raise_not_converged=False)
+                torch.cuda.synchronize()
+                row[prec + "_solve"] = {"seconds": time.perf_counter() - t, "iters": info["iters"],
+                                        "fp64_applies": info["fp64_applies"],
+                                        "rel_resid_true": info["rel_resid_true"], "status": info["status"]}
+            p.close()
+        log("rates %s: %s" % (name, row))
+        out[name] = row
+    return out
+
+
+def cpu_baseline_configs(rates, tol, maxiter):
+    """The oracle beside the GPU rates of rates_leg: applies/s at C1, C5 and C2, its time-to-tol at C1
+    (measured) and at C5 and C2 (extrapolated from the GPU FP64 iteration count)."""
+    import numpy as np
+
+    import akra_workloads as wl
+    from oracle.core import Oracle
+    from oracle.geometry import healpix_rings
+
+    out = {}
+    for name in ("C1", "C5", "C2"):
+        cfg = wl.make_config(name)
+        nside, lmax = cfg["nside"], cfg["lmax"]
+        o = Oracle(lmax, healpix_rings(nside))
+        W = o.weights(cfg["ninv"][0], cfg["mask"])
+        x = np.stack([wl.random_alm(lmax, 1), wl.random_alm(lmax, 2)])
+        t = time.time()
+        o.apply_H(x, W, 1e-3)
+        dt = time.time() - t
+        orc = {"workload": "%s: HEALPix Nside %d, lmax %d" % (name, nside, lmax), "applies_per_s": 1.0 / dt,
+               "seconds_per_apply": dt}
+        iters = rates[name]["fp64_solve"]["iters"]
+        if name == "C1":
+            lam = o.lambda_eff(cfg["ninv"][0], cfg["mask"])
+            g1, g2 = o.synth(o.kernel()[o.l_of] * cfg["kappa"][0], np.zeros(o.nalm, np.complex128))
+            m = cfg["mask"].astype(np.float64)
+            b = o.rhs(m * (g1 + cfg["eps1"][0]), m * (g2 + cfg["eps2"][0]), W)
+            t = time.time()
+            _, oi = o.cg(b, W, lam, o.precond(cfg["ninv"][0], cfg["mask"], lam), tol=tol, maxiter=maxiter)
+            orc["time_to_tol"] = {"seconds": time.time() - t, "iters": oi["iters"], "measured": True}
+        else:
+            orc["time_to_tol"] = {"seconds": iters * dt, "iters": iters, "measured": False,
+                                  "note": "extrapolated: GPU FP64 iteration count x oracle seconds per apply"}
+        log("oracle %s: %s" % (name, orc))
+        out[name] = orc
+    return out
+
+
 def full_norm(a, b, lmax):
     """Full-m norm of stacked (E, B) complex alm on the device."""
     import torch
@@ -320,6 +415,7 @@ def main():
     ap.add_argument("--batched-workload", default="C4")
     ap.add_argument("--no-pixelize", action="store_true")
     ap.add_argument("--no-flat", action="store_true")
+    ap.add_argument("--no-rates", action="store_true")
     ap.add_argument("--flat-n", type=int, default=4096)
     ap.add_argument("--pixelize-galaxies", type=int, default=100_000_000)
     ap.add_argument("--cpu-sample-rings", type=int, default=192)
@@ -458,11 +554,17 @@ def main():
         out["pixelize"] = pixelize_leg(args.pixelize_galaxies, nside)
     if not args.no_flat:
         out["flat"] = flat_leg(args.flat_n, max(args.steps, 10), args.solve_tol, args.maxiter)
+    rates = None
+    if not args.no_solve and not args.no_rates and args.workload == "C3" and args.nside is None and args.lmax is None:
+        rates = rates_leg(cfg, args.solve_tol, args.maxiter)
+        out["apply_rates"] = rates
 
     if not args.no_cpu_baseline:
         t = time.time()
         out["cpu_baseline"] = cpu_baseline(cfg, nside, lmax, args.cpu_sample_rings)
         log("cpu baseline in %.1f s: %s" % (time.time() - t, out["cpu_baseline"]["sample"]))
+        if rates is not None:
+            out["cpu_baseline"]["per_config"] = cpu_baseline_configs(rates, args.solve_tol, args.maxiter)
     print(json.dumps(out), flush=True)
 
 
