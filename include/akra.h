@@ -299,7 +299,8 @@ akra_status akra_shuffle_shear(akra_plan plan, const double *g1, const double *g
 /*
  * Spectra C_l^{XY} of coefficient pairs: for q < npairs, cl[q] = C^{x[i] y[j]} with
  * (i, j) = (pairs[2q], pairs[2q+1]).
- *   x      device complex128 [nx][n_alm];  y  device complex128 [ny][n_alm] (y == x allowed);
+ *   x      device complex128 [nx][n_alm];  y  device complex128 [ny][n_alm] (y == x allowed), both
+ *          16-byte aligned;
  *   pairs  HOST int32 [npairs][2], 0 <= i < nx, 0 <= j < ny;
  *   cl     device float64 [npairs][lmax+1].
  * Stream-ordered, no host synchronisation; the sum over m has a fixed order, so results repeat
@@ -328,7 +329,8 @@ akra_status akra_noise_work_size(akra_plan plan, int nset, int64_t *bytes);
  *   opts      as for akra_cg_solve.  opts->mode picks the unknowns and the spectra kept:
  *             AKRA_JOINT_EB  nspec = 3: (EE, BB, EB); for nset = 2 (A_E B_E, A_B B_B, A_E B_B),
  *             AKRA_E_ONLY    nspec = 1: EE,   AKRA_B_ONLY  nspec = 1: BB;
- *   work      device workspace of work_bytes >= akra_noise_work_size(plan, nset) bytes;
+ *   work      device workspace of work_bytes >= akra_noise_work_size(plan, nset) bytes, 256-byte
+ *             aligned;
  *   cl        device float64 [n_real][nspec][lmax+1];
  *   cl_mean, cl_std  device float64 [nspec][lmax+1] or NULL: the mean over the realisations (for
  *             nset = 1 the noise-bias estimate N_l) and the sample standard deviation (n_real - 1 in
@@ -379,7 +381,8 @@ akra_status akra_pixelize_work_size(akra_plan plan, int64_t n_gal, int64_t *byte
  * Pixelise a catalogue of n_gal galaxies (definitions above).
  *   z, phi, e1, e2, w   device float64 [n_gal] (may be NULL when n_gal = 0);
  *   R                   mean shear response (finite, nonzero); sigma_e > 0; n_th finite;
- *   work                device workspace of work_bytes >= akra_pixelize_work_size(plan, n_gal);
+ *   work                device workspace of work_bytes >= akra_pixelize_work_size(plan, n_gal), 256-byte
+ *                       aligned;
  *   g1, g2, ninv, neff  device float64 [Npix];  mask  device uint8 [Npix].
  * Synchronises the plan stream.  Errors: AKRA_ERR_ARG (null pointers, sizes, a direction out of
  * range, a negative or non-finite weight, a non-finite ellipticity, a small workspace; the outputs

@@ -1751,6 +1751,10 @@ akra_status akra_alm_spectra(akra_plan plan, const double *x, int nx, const doub
         set_error("null pointer argument");
         return AKRA_ERR_ARG;
     }
+    if (((uintptr_t)x | (uintptr_t)y) % 16) {
+        set_error("coefficient arrays must be 16-byte aligned (complex128)");
+        return AKRA_ERR_ARG;
+    }
     for (int q = 0; q < npairs; ++q)
         if (pairs[2 * q] < 0 || pairs[2 * q] >= nx || pairs[2 * q + 1] < 0 || pairs[2 * q + 1] >= ny) {
             set_error("pair " + std::to_string(q) + " is out of range");
@@ -1817,6 +1821,10 @@ akra_status akra_noise_spectra(akra_plan plan, int nset, const double *g1, const
     }
     if (work_bytes < need) {
         set_error("workspace too small: " + std::to_string(need) + " bytes needed");
+        return AKRA_ERR_ARG;
+    }
+    if ((uintptr_t)work % 256) {
+        set_error("workspace must be 256-byte aligned");
         return AKRA_ERR_ARG;
     }
     const int64_t npix = P.npix, na = P.nalm, L1 = P.lmax + 1;
@@ -1986,6 +1994,10 @@ akra_status akra_pixelize(akra_plan plan, const double *z, const double *phi, co
     if (st) return st;
     if (work_bytes < need) {
         set_error("workspace too small: " + std::to_string(need) + " bytes needed");
+        return AKRA_ERR_ARG;
+    }
+    if ((uintptr_t)work % 256) {
+        set_error("workspace must be 256-byte aligned");
         return AKRA_ERR_ARG;
     }
     AK_HIP(hipMemsetAsync(P.d_cmp_flag, 0, 2 * sizeof(int), P.stream), "memset");

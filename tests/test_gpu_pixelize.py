@@ -101,6 +101,9 @@ def test_pixelize_no_galaxies_and_errors():
     w = torch.empty(p.pixelize_work_bytes(1000) - 1, dtype=torch.uint8, device="cuda:0")
     with pytest.raises(akra.AkraError, match="workspace too small"):
         p.pixelize(*(_t(args[k]) for k in ("z", "phi", "e1", "e2", "w")), 0.7, 0.26, 1.0, work=w)
+    w = torch.empty(p.pixelize_work_bytes(1000) + 256, dtype=torch.uint8, device="cuda:0")
+    with pytest.raises(akra.AkraError, match="aligned"):
+        p.pixelize(*(_t(args[k]) for k in ("z", "phi", "e1", "e2", "w")), 0.7, 0.26, 1.0, work=w[16:])
     o = p.pixelize(*(_t(args[k]) for k in ("z", "phi", "e1", "e2", "w")), 0.7, 0.26, 1.0)
     _compare(o, pixelize(4, *(args[k] for k in ("z", "phi", "e1", "e2", "w")), 0.7, 0.26, 1.0))
 

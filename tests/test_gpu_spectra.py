@@ -111,6 +111,11 @@ def test_alm_spectra_argument_errors():
     with pytest.raises(akra.AkraError, match="out of range"):
         p.alm_spectra(x, x, [(0, 2)])
     assert p.alm_spectra(x, x, np.zeros((0, 2), np.int32)).shape == (0, 17)
+    # misaligned coefficients through the C ABI
+    cl = torch.empty((1, 17), dtype=torch.float64, device=dev)
+    pr = np.zeros(2, np.int32)
+    st = akra.lib().akra_alm_spectra(p._h, x.data_ptr() + 8, 1, x.data_ptr(), 1, pr.ctypes.data, 1, cl.data_ptr())
+    assert st == akra.AKRA_ERR_ARG and "aligned" in akra.lib().akra_last_error().decode()
 
 
 @pytest.fixture(scope="module")
@@ -224,6 +229,11 @@ def test_noise_spectra_argument_errors(c1):
     w = torch.empty(p.noise_work_bytes(1) - 1, dtype=torch.uint8, device=t["g1"].device)
     with pytest.raises(akra.AkraError, match="workspace too small"):
         p.noise_spectra(t["g1"], t["g2"], t["ninv"], t["mask"], _t(bad), work=w)
+    # a workspace that is not 256-byte aligned
+    w = torch.empty(p.noise_work_bytes(1) + 256, dtype=torch.uint8, device=t["g1"].device)
+    with pytest.raises(akra.AkraError, match="aligned"):
+        p.noise_spectra(t["g1"], t["g2"], t["ninv"], t["mask"], _t(np.stack([np.arange(n_obs, dtype=np.int32)])),
+                        work=w[8:])
     # no realisations: nothing solved, zero moments
     cl, mean, std, info = p.noise_spectra(t["g1"], t["g2"], t["ninv"], t["mask"], _t(np.zeros((0, n_obs), np.int32)))
     assert cl.shape[0] == 0 and info["iters"] == 0
