@@ -213,6 +213,17 @@ akra_status akra_cg_step(akra_plan plan, int nsteps);
 akra_status akra_cg_state(akra_plan plan, double *rel_resid, int *iters, double *xE, double *xB);
 
 /*
+ * Graph replay of the PCG iteration (Sec. II.B inversion problem; the loop of akra_cg_step and of the
+ * single-right-hand-side solves of akra_cg_solve): when on (the default), the plan records the kernel
+ * launches of one iteration once as a HIP graph, on a private capture stream of default priority, and
+ * replays it on the plan stream; it records again when lambda_eff, the preconditioner, the K_l table,
+ * the precision, the right-hand side, the E/B unknowns or the Legendre launch shapes change.  Results
+ * are bit-identical to direct launches.  Stage timing (akra_plan_set_timing) always launches directly.
+ * akra_plan_set_graph synchronises the plan stream; off releases the recorded graph.
+ */
+akra_status akra_plan_set_graph(akra_plan plan, int on);
+
+/*
  * Stage timing: when on, every operator apply records HIP events on the plan stream around its
  * stages; akra_plan_stage_times synchronises, returns the summed milliseconds and launch counts per
  * stage in HOST arrays of AKRA_NSTAGES entries, and resets the counters.

@@ -74,6 +74,7 @@ def lib():
     L.akra_cg_step.argtypes = [vp, ctypes.c_int]
     L.akra_cg_state.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int), vp, vp]
     L.akra_plan_set_timing.argtypes = [vp, ctypes.c_int]
+    L.akra_plan_set_graph.argtypes = [vp, ctypes.c_int]
     L.akra_plan_set_tuning.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     L.akra_plan_get_tuning.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
     L.akra_plan_work.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
@@ -111,7 +112,7 @@ def lib():
               "akra_shuffle_shear", "akra_alm_spectra", "akra_noise_work_size", "akra_noise_spectra", "akra_ang2pix",
               "akra_pixelize_work_size", "akra_pixelize", "akra_flat_plan_create", "akra_flat_synth",
               "akra_flat_adjoint", "akra_flat_apply_H", "akra_flat_rhs", "akra_flat_cg_solve", "akra_flat_cg_start",
-              "akra_flat_cg_step"):
+              "akra_flat_cg_step", "akra_plan_set_graph"):
         getattr(L, f).restype = ctypes.c_int
     _lib = L
     return L
@@ -498,6 +499,10 @@ class Plan:
     # -- stage timing -------------------------------------------------------------------------
     def set_timing(self, on=True):
         _check(lib().akra_plan_set_timing(self._h, 1 if on else 0))
+
+    def set_graph(self, on=True):
+        """Replay the PCG iteration as a recorded HIP graph (default) or launch its kernels directly."""
+        _check(lib().akra_plan_set_graph(self._h, 1 if on else 0))
 
     def stage_times(self):
         """{stage: (total_ms, launches)} since the last call; synchronises the plan stream."""

@@ -170,6 +170,13 @@ struct Plan {
     double cg_bn = 0, cg_rr = 0, cg_lam = 0, cg_pc = 1;
     const double *cg_kern = nullptr;
 
+    // one single-right-hand-side PCG iteration recorded as a HIP graph (on a private capture stream)
+    // and replayed on the plan stream; cg_graph_key holds every by-value kernel argument it baked in
+    bool use_graph = true;
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t cg_graph = nullptr;
+    double cg_graph_key[12] = {};
+
     // stage timing with HIP events on the plan stream
     bool timing = false;
     std::vector<std::array<hipEvent_t, 2>> ev_pool;

@@ -255,6 +255,8 @@ static void free_plan(Plan *P)
         (void)hipEventDestroy(e[0]);
         (void)hipEventDestroy(e[1]);
     }
+    if (P->cg_graph) (void)hipGraphExecDestroy(P->cg_graph);
+    if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
     delete P;
 }
 
@@ -794,6 +796,68 @@ static akra_status cg_iterate(Plan &P, bool fp32)
     return check_launch("cg_step");
 }
 
+// Every value the launches of one iteration take by value, besides plan-constant pointers and
+// sizes: precision, right-hand side, projection, lambda_eff, P, the K_l table and the Legendre
+// launch shapes.  A recorded iteration is valid while these are unchanged.
+static void iter_key(const Plan &P, bool fp32, double *k)
+{
+    const double v[12] = {(double)fp32, (double)P.cg_rhs, (double)P.proj, P.cg_lam, P.cg_pc,
+                          (double)(uintptr_t)P.cg_kern, (double)P.syn_V, (double)P.syn_R, (double)P.adj_R,
+                          (double)P.adj_W, (double)P.adj_L, (double)P.adj_nrb};
+    std::memcpy(k, v, sizeof v);
+}
+
+static void drop_graph(Plan &P)
+{
+    if (P.cg_graph) (void)hipGraphExecDestroy(P.cg_graph);
+    P.cg_graph = nullptr;
+}
+
+// Records one cg_iterate into a graph: the launches go to the private capture stream (the plan
+// stream may be the legacy default stream, which cannot be captured).  Nothing executes here.
+static akra_status record_iteration(Plan &P, bool fp32)
+{
+    drop_graph(P);
+    if (!P.cap_stream) AK_HIP(hipStreamCreateWithFlags(&P.cap_stream, hipStreamNonBlocking), "hipStreamCreate");
+    AK_HIP(hipGetLastError(), "launch");
+    const hipStream_t s = P.stream;
+    const int iters = P.cg_iters;
+    AK_HIP(hipStreamBeginCapture(P.cap_stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    P.stream = P.cap_stream;
+    akra_status st = cg_iterate(P, fp32);
+    P.stream = s;
+    P.cg_iters = iters;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(P.cap_stream, &g);
+    if (st == AKRA_OK && e != hipSuccess) st = hip_fail(e, "hipStreamEndCapture");
+    if (st == AKRA_OK) {
+        e = hipGraphInstantiate(&P.cg_graph, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            P.cg_graph = nullptr;
+            st = hip_fail(e, "hipGraphInstantiate");
+        }
+    }
+    if (g) (void)hipGraphDestroy(g);
+    if (st == AKRA_OK) iter_key(P, fp32, P.cg_graph_key);
+    return st;
+}
+
+// One PCG iteration: a replay of the recorded graph (recorded again when a by-value argument has
+// changed), or direct launches when stage timing is on or graphs are switched off.
+static akra_status cg_step1(Plan &P, bool fp32)
+{
+    if (P.timing || !P.use_graph) return cg_iterate(P, fp32);
+    double k[12];
+    iter_key(P, fp32, k);
+    if (!P.cg_graph || std::memcmp(k, P.cg_graph_key, sizeof k) != 0) {
+        akra_status st = record_iteration(P, fp32);
+        if (st) return st;
+    }
+    AK_HIP(hipGraphLaunch(P.cg_graph, P.stream), "hipGraphLaunch");
+    P.cg_iters++;
+    return AKRA_OK;
+}
+
 // host view of <r, r> and the breakdown flag (one synchronisation)
 static akra_status cg_poll(Plan &P, double *rr, int *flag)
 {
@@ -854,7 +918,7 @@ static akra_status cg_run(Plan &P, const akra_cg_opts &o, akra_cg_info *info)
             k_cg_rz<<<1, 1, 0, P.stream>>>(P.d_scal, P.cg_pc);
         }
         if (P.cg_iters >= o.maxiter) break;
-        akra_status st = cg_iterate(P, fp32);
+        akra_status st = cg_step1(P, fp32);
         if (st) return st;
         if (!fp32 && P.prec == AKRA_FP32) P.cg_fp64_applies++;
         int flag = 0;
@@ -1545,7 +1609,7 @@ akra_status akra_cg_step(akra_plan plan, int nsteps)
     }
     ProjScope scope(P, P.cg_proj);
     for (int i = 0; i < nsteps; ++i) {
-        akra_status st = cg_iterate(P, P.prec == AKRA_FP32);
+        akra_status st = cg_step1(P, P.prec == AKRA_FP32);
         if (st) return st;
     }
     return AKRA_OK;
@@ -1644,6 +1708,15 @@ akra_status akra_plan_set_timing(akra_plan plan, int on)
     AK_PLAN();
     P.timing = on != 0;
     P.ev_used = 0;
+    return AKRA_OK;
+}
+
+akra_status akra_plan_set_graph(akra_plan plan, int on)
+{
+    AK_PLAN();
+    AK_HIP(hipStreamSynchronize(P.stream), "sync");
+    P.use_graph = on != 0;
+    if (!P.use_graph) drop_graph(P);
     return AKRA_OK;
 }
 
