@@ -96,6 +96,18 @@ def make_inputs(name, nside, lmax, dev):
     return cfg, g1, g2, ninv, mask
 
 
+def cpu_model():
+    """Model name of the host CPU (from /proc/cpuinfo), or None."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(cfg, nside, lmax, nsample):
     """The oracle (plain C, long double, direct ring sums) applying H on a stratified sample of rings;
     one full apply is extrapolated as sample time x nrings / nsample."""
@@ -120,6 +132,7 @@ def cpu_baseline(cfg, nside, lmax, nsample):
     full = dt * rings.nrings / nsample
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count()))
     return {"value": 1.0 / full, "unit": "H·v applies/s", "cores": cores, "kind": "oracle",
+            "cpu_model": cpu_model(), "nproc": os.cpu_count(),
             "sample": "oracle H v with the weight on %d of %d rings (stratified in z): %.1f s; one full apply "
                       "extrapolated as x%d = %.0f s" % (nsample, rings.nrings, dt, rings.nrings // nsample, full),
             "seconds_per_apply": full}

@@ -54,7 +54,9 @@ typedef enum {
     AKRA_ERR_ALLOC = 2,      /* device or host allocation failed                                 */
     AKRA_ERR_HIP = 3,        /* a HIP runtime call or kernel launch failed                        */
     AKRA_ERR_NUMERIC = 4,    /* NaN/Inf in the inputs, or CG breakdown (p^T H p <= 0)             */
-    AKRA_NOT_CONVERGED = 5   /* maxiter reached; x holds the last iterate                         */
+    AKRA_NOT_CONVERGED = 5,  /* maxiter reached; x holds the last iterate                         */
+    AKRA_STAGNATED = 6       /* ||r|| reached no new minimum in opts->stall_iters iterations;     */
+                             /* x holds the last iterate                                          */
 } akra_status;
 
 typedef enum {
@@ -88,6 +90,9 @@ typedef struct {
     double *resid_hist;      /* HOST, optional: relative residual after each iteration           */
     int resid_hist_len;
     int mode;                /* akra_mode of the unknowns (default AKRA_JOINT_EB)                 */
+    int stall_iters;         /* > 0: stop with AKRA_STAGNATED once the relative residual has not  */
+                             /* fallen below its smallest earlier value for this many iterations  */
+                             /* (the residual the convergence test sees); 0 (default): off        */
 } akra_cg_opts;
 
 typedef struct {
@@ -101,7 +106,8 @@ typedef struct {
     int status;              /* akra_status of the solve                                          */
 } akra_cg_info;
 
-/* Default options (lambda 1e-3, tol 1e-3, maxiter 1000, x0 = 0, kernel sigma_D D_l, joint E/B). */
+/* Default options (lambda 1e-3, tol 1e-3, maxiter 1000, x0 = 0, kernel sigma_D D_l, joint E/B,
+ * no stagnation test). */
 void akra_cg_opts_default(akra_cg_opts *opts);
 
 /*
@@ -157,7 +163,10 @@ akra_status akra_rhs(akra_plan plan, const double *g1, const double *g2, const d
  * (tol below the attainable accuracy of the system), the call returns AKRA_NOT_CONVERGED with the
  * last iterate and its true residual in info.
  * Out: xE, xB (alm layout), info (HOST, may be NULL).  Returns AKRA_NOT_CONVERGED (x valid) at maxiter,
- * AKRA_ERR_NUMERIC on breakdown.  ||b|| = 0 gives x = 0 after 0 iterations.
+ * AKRA_STAGNATED (x valid) when opts->stall_iters is set and the residual stops falling,
+ * AKRA_ERR_NUMERIC on breakdown.  ||b|| = 0 gives x = 0 after 0 iterations.  With several right-hand
+ * sides the status is the most severe of theirs (NOT_CONVERGED over STAGNATED over OK); a batched
+ * FP32 plan stops each right-hand side on its own.
  */
 akra_status akra_cg_solve(akra_plan plan, const double *g1, const double *g2, const double *ninv,
                           const uint8_t *mask, const akra_cg_opts *opts, double *xE, double *xB, akra_cg_info *info);
@@ -441,7 +450,8 @@ akra_status akra_flat_rhs(akra_flat_plan plan, const double *g1, const double *g
  * lambda, tol, maxiter, use_x0 with kE/kB as the start maps, resid_hist; mode must be AKRA_JOINT_EB,
  * kernel_l NULL, reliable_delta unused).  Outputs kE, kB device float64 [ny][nx]; info as for
  * akra_cg_solve (fp64_applies 0).  ||b|| = 0 gives zero maps.  Errors: AKRA_ERR_ARG, AKRA_ERR_NUMERIC
- * (non-finite data, CG breakdown), AKRA_NOT_CONVERGED (maxiter; kE, kB hold the last iterate). */
+ * (non-finite data, CG breakdown), AKRA_NOT_CONVERGED (maxiter; kE, kB hold the last iterate),
+ * AKRA_STAGNATED (opts->stall_iters; kE, kB hold the last iterate). */
 akra_status akra_flat_cg_solve(akra_flat_plan plan, const double *g1, const double *g2, const double *ninv,
                                const uint8_t *mask, const akra_cg_opts *opts, double *kE, double *kB,
                                akra_cg_info *info);

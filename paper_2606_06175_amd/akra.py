@@ -14,13 +14,14 @@ import os
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libakra.so")
+# AKRA_LIBRARY names another build of the same library (the sanitizer-instrumented one in tests)
+LIB_PATH = os.environ.get("AKRA_LIBRARY") or os.path.join(_HERE, "libakra.so")
 _lib = None
 
-AKRA_OK, AKRA_ERR_ARG, AKRA_ERR_ALLOC, AKRA_ERR_HIP, AKRA_ERR_NUMERIC, AKRA_NOT_CONVERGED = range(6)
+AKRA_OK, AKRA_ERR_ARG, AKRA_ERR_ALLOC, AKRA_ERR_HIP, AKRA_ERR_NUMERIC, AKRA_NOT_CONVERGED, AKRA_STAGNATED = range(7)
 STAGES = ("prologue", "leg_synth", "ring", "leg_adj", "epilogue", "cg_vec")
 STATUS_NAMES = {0: "AKRA_OK", 1: "AKRA_ERR_ARG", 2: "AKRA_ERR_ALLOC", 3: "AKRA_ERR_HIP", 4: "AKRA_ERR_NUMERIC",
-                5: "AKRA_NOT_CONVERGED"}
+                5: "AKRA_NOT_CONVERGED", 6: "AKRA_STAGNATED"}
 PRECISIONS = {"fp64": 0, "fp32": 1}
 
 
@@ -34,7 +35,7 @@ class CgOpts(ctypes.Structure):
     _fields_ = [("lambda_", ctypes.c_double), ("tol", ctypes.c_double), ("maxiter", ctypes.c_int),
                 ("use_x0", ctypes.c_int), ("kernel_l", ctypes.POINTER(ctypes.c_double)),
                 ("reliable_delta", ctypes.c_double), ("resid_hist", ctypes.POINTER(ctypes.c_double)),
-                ("resid_hist_len", ctypes.c_int), ("mode", ctypes.c_int)]
+                ("resid_hist_len", ctypes.c_int), ("mode", ctypes.c_int), ("stall_iters", ctypes.c_int)]
 
 
 # unknowns of a solve (akra_mode): joint (kappa_E, kappa_B), the E block only, the B block only
@@ -243,10 +244,11 @@ class Plan:
                                   bE.data_ptr(), bB.data_ptr()))
         return bE, bB
 
-    def _opts(self, tol, maxiter, lam, x0, kernel, reliable_delta, hist_len, mode="joint"):
+    def _opts(self, tol, maxiter, lam, x0, kernel, reliable_delta, hist_len, mode="joint", stall_iters=0):
         o = CgOpts()
         lib().akra_cg_opts_default(ctypes.byref(o))
         o.lambda_, o.tol, o.maxiter = float(lam), float(tol), int(maxiter)
+        o.stall_iters = int(stall_iters)
         if mode not in MODES:
             raise ValueError("mode must be one of %s" % sorted(MODES))
         o.mode = MODES[mode]
@@ -273,7 +275,7 @@ class Plan:
         return d
 
     def cg_solve(self, g1, g2, ninv, mask, tol=1e-3, maxiter=1000, lam=1e-3, x0=None, kernel=None,
-                 reliable_delta=0.1, hist_len=0, raise_not_converged=True, mode="joint"):
+                 reliable_delta=0.1, hist_len=0, raise_not_converged=True, mode="joint", stall_iters=0):
         """Regularised ML estimate (kappa_E, kappa_B).  mode "joint" solves the full E/B system, "E"
         the E block alone (kappa_B returned as zero), "B" the B block alone."""
         g1, g2 = self._map(g1, "g1"), self._map(g2, "g2")
@@ -283,17 +285,17 @@ class Plan:
         if x0 is not None:
             xE.copy_(x0[0].reshape(xE.shape))
             xB.copy_(x0[1].reshape(xB.shape))
-        o, keep = self._opts(tol, maxiter, lam, x0, kernel, reliable_delta, hist_len, mode)
+        o, keep = self._opts(tol, maxiter, lam, x0, kernel, reliable_delta, hist_len, mode, stall_iters)
         inf = CgInfo()
         with torch.cuda.device(self.device):
             st = lib().akra_cg_solve(self._h, g1.data_ptr(), g2.data_ptr(), ninv.data_ptr(), mask.data_ptr(),
                                      ctypes.byref(o), xE.data_ptr(), xB.data_ptr(), ctypes.byref(inf))
-        if st != AKRA_OK and (st != AKRA_NOT_CONVERGED or raise_not_converged):
+        if st != AKRA_OK and (st not in (AKRA_NOT_CONVERGED, AKRA_STAGNATED) or raise_not_converged):
             _check(st)
         return xE, xB, self._info(inf, keep, hist_len)
 
     def cg_solve_vjp(self, g1, g2, ninv, mask, xE, xB, vE, vB, tol=1e-3, maxiter=1000, lam=1e-3, kernel=None,
-                     reliable_delta=0.1, raise_not_converged=True, mode="joint"):
+                     reliable_delta=0.1, raise_not_converged=True, mode="joint", stall_iters=0):
         """dL/dg1, dL/dg2, dL/dninv for x = cg_solve(g1, g2, ninv, mask, ...) and the upstream
         gradient (vE, vB) on the stored (Re, Im) of x (one more CG solve, see akra_cg_solve_vjp)."""
         g1, g2 = self._map(g1, "g1"), self._map(g2, "g2")
@@ -302,18 +304,18 @@ class Plan:
         xE, xB = self._alm(xE, "xE"), self._alm(xB, "xB")
         vE, vB = self._alm(vE, "vE"), self._alm(vB, "vB")
         dg1, dg2, dn = self._map_out(), self._map_out(), self._map_out()
-        o, keep = self._opts(tol, maxiter, lam, None, kernel, reliable_delta, 0, mode)
+        o, keep = self._opts(tol, maxiter, lam, None, kernel, reliable_delta, 0, mode, stall_iters)
         inf = CgInfo()
         with torch.cuda.device(self.device):
             st = lib().akra_cg_solve_vjp(self._h, g1.data_ptr(), g2.data_ptr(), ninv.data_ptr(), mask.data_ptr(),
                                          ctypes.byref(o), xE.data_ptr(), xB.data_ptr(), vE.data_ptr(), vB.data_ptr(),
                                          dg1.data_ptr(), dg2.data_ptr(), dn.data_ptr(), ctypes.byref(inf))
-        if st != AKRA_OK and (st != AKRA_NOT_CONVERGED or raise_not_converged):
+        if st != AKRA_OK and (st not in (AKRA_NOT_CONVERGED, AKRA_STAGNATED) or raise_not_converged):
             _check(st)
         return dg1, dg2, dn, self._info(inf, keep, 0)
 
     def cg_solve_b(self, bE, bB, ninv, mask, tol=1e-3, maxiter=1000, lam=1e-3, x0=None, kernel=None,
-                   reliable_delta=0.1, hist_len=0, raise_not_converged=True, mode="joint"):
+                   reliable_delta=0.1, hist_len=0, raise_not_converged=True, mode="joint", stall_iters=0):
         bE, bB = self._alm(bE, "bE"), self._alm(bB, "bB")
         ninv = self._map(ninv, "ninv")
         mask = self._map(mask, "mask", torch.uint8, per_rhs=False)
@@ -321,17 +323,17 @@ class Plan:
         if x0 is not None:
             xE.copy_(x0[0].reshape(xE.shape))
             xB.copy_(x0[1].reshape(xB.shape))
-        o, keep = self._opts(tol, maxiter, lam, x0, kernel, reliable_delta, hist_len, mode)
+        o, keep = self._opts(tol, maxiter, lam, x0, kernel, reliable_delta, hist_len, mode, stall_iters)
         inf = CgInfo()
         with torch.cuda.device(self.device):
             st = lib().akra_cg_solve_b(self._h, ninv.data_ptr(), mask.data_ptr(), bE.data_ptr(), bB.data_ptr(),
                                        ctypes.byref(o), xE.data_ptr(), xB.data_ptr(), ctypes.byref(inf))
-        if st != AKRA_OK and (st != AKRA_NOT_CONVERGED or raise_not_converged):
+        if st != AKRA_OK and (st not in (AKRA_NOT_CONVERGED, AKRA_STAGNATED) or raise_not_converged):
             _check(st)
         return xE, xB, self._info(inf, keep, hist_len)
 
     def cg_solve_cond_b(self, g1, g2, ninv, mask, kE, tol=1e-3, maxiter=1000, lam=1e-3, kernel=None,
-                        reliable_delta=0.1, hist_len=0, raise_not_converged=True):
+                        reliable_delta=0.1, hist_len=0, raise_not_converged=True, stall_iters=0):
         """Conditional B-mode solve: kappa_B of (H_BB + lambda_eff) kappa_B = b_B - H_BE kE for a given
         E-mode solution kE (see akra_cg_solve_cond_b)."""
         g1, g2 = self._map(g1, "g1"), self._map(g2, "g2")
@@ -339,12 +341,12 @@ class Plan:
         mask = self._map(mask, "mask", torch.uint8, per_rhs=False)
         kE = self._alm(kE, "kE")
         kB = self._alm_out()
-        o, keep = self._opts(tol, maxiter, lam, None, kernel, reliable_delta, hist_len)
+        o, keep = self._opts(tol, maxiter, lam, None, kernel, reliable_delta, hist_len, "joint", stall_iters)
         inf = CgInfo()
         with torch.cuda.device(self.device):
             st = lib().akra_cg_solve_cond_b(self._h, g1.data_ptr(), g2.data_ptr(), ninv.data_ptr(), mask.data_ptr(),
                                             ctypes.byref(o), kE.data_ptr(), kB.data_ptr(), ctypes.byref(inf))
-        if st != AKRA_OK and (st != AKRA_NOT_CONVERGED or raise_not_converged):
+        if st != AKRA_OK and (st not in (AKRA_NOT_CONVERGED, AKRA_STAGNATED) or raise_not_converged):
             _check(st)
         return kB, self._info(inf, keep, hist_len)
 
@@ -402,7 +404,7 @@ class Plan:
         return n.value
 
     def noise_spectra(self, g1, g2, ninv, mask, perm, tol=1e-3, maxiter=1000, lam=1e-3, kernel=None,
-                      reliable_delta=0.1, mode="E", raise_not_converged=True, work=None):
+                      reliable_delta=0.1, mode="E", raise_not_converged=True, work=None, stall_iters=0):
         """Shape-noise realisations through the full solve and their spectra (akra_noise_spectra).
 
         One shear set: g1, g2, ninv [Npix], perm int32 [n_real, n_obs] -> auto spectra.  Split halves:
@@ -425,14 +427,14 @@ class Plan:
         cl = torch.empty((n_real, nspec, self.lmax + 1), dtype=torch.float64, device=self.device)
         mean = torch.empty((nspec, self.lmax + 1), dtype=torch.float64, device=self.device)
         std = torch.empty_like(mean)
-        o, keep = self._opts(tol, maxiter, lam, None, kernel, reliable_delta, 0, mode)
+        o, keep = self._opts(tol, maxiter, lam, None, kernel, reliable_delta, 0, mode, stall_iters)
         inf = CgInfo()
         with torch.cuda.device(self.device):
             st = lib().akra_noise_spectra(self._h, nset, g1.data_ptr(), g2.data_ptr(), ninv.data_ptr(),
                                           mask.data_ptr(), perm.data_ptr(), n_obs, n_real, ctypes.byref(o),
                                           work.data_ptr(), work.numel(), cl.data_ptr(), mean.data_ptr(),
                                           std.data_ptr(), ctypes.byref(inf))
-        if st != AKRA_OK and (st != AKRA_NOT_CONVERGED or raise_not_converged):
+        if st != AKRA_OK and (st not in (AKRA_NOT_CONVERGED, AKRA_STAGNATED) or raise_not_converged):
             _check(st)
         return cl, mean, std, self._info(inf, keep, 0)
 
@@ -602,7 +604,7 @@ class FlatPlan:
         return bE, bB
 
     def cg_solve(self, g1, g2, ninv, mask, tol=1e-3, maxiter=1000, lam=1e-3, x0=None, hist_len=0,
-                 raise_not_converged=True):
+                 raise_not_converged=True, stall_iters=0):
         """Regularised flat-sky estimate (kappa_E, kappa_B) by PCG (see akra_flat_cg_solve)."""
         g1, g2 = self._m(g1, "g1"), self._m(g2, "g2")
         ninv, mask = self._m(ninv, "ninv"), self._m(mask, "mask", torch.uint8)
@@ -614,6 +616,7 @@ class FlatPlan:
         lib().akra_cg_opts_default(ctypes.byref(o))
         o.lambda_, o.tol, o.maxiter = float(lam), float(tol), int(maxiter)
         o.use_x0 = 1 if x0 is not None else 0
+        o.stall_iters = int(stall_iters)
         keep = []
         if hist_len:
             import numpy as np
@@ -625,7 +628,7 @@ class FlatPlan:
         with torch.cuda.device(self.device):
             st = lib().akra_flat_cg_solve(self._h, g1.data_ptr(), g2.data_ptr(), ninv.data_ptr(), mask.data_ptr(),
                                           ctypes.byref(o), kE.data_ptr(), kB.data_ptr(), ctypes.byref(inf))
-        if st != AKRA_OK and (st != AKRA_NOT_CONVERGED or raise_not_converged):
+        if st != AKRA_OK and (st not in (AKRA_NOT_CONVERGED, AKRA_STAGNATED) or raise_not_converged):
             _check(st)
         d = {k: getattr(inf, k) for k, _ in CgInfo._fields_}
         if hist_len:

@@ -657,8 +657,10 @@ akra_status akra_flat_cg_solve(akra_flat_plan plan, const double *g1, const doub
     akra_cg_opts o;
     akra_cg_opts_default(&o);
     if (opts) o = *opts;
-    if (!(o.tol > 0) || o.maxiter < 0 || !(o.lambda >= 0) || o.mode != AKRA_JOINT_EB || o.kernel_l) {
-        set_error("flat solve: tol > 0, maxiter >= 0, lambda >= 0, joint mode and no kernel_l are required");
+    if (!(o.tol > 0) || o.maxiter < 0 || !(o.lambda >= 0) || o.mode != AKRA_JOINT_EB || o.kernel_l ||
+        o.stall_iters < 0) {
+        set_error("flat solve: tol > 0, maxiter >= 0, lambda >= 0, stall_iters >= 0, joint mode and no kernel_l "
+                  "are required");
         return AKRA_ERR_ARG;
     }
     if (!g1 || !g2 || !kE || !kB) {
@@ -704,6 +706,7 @@ akra_status akra_flat_cg_solve(akra_flat_plan plan, const double *g1, const doub
         const double rz0 = pc * rr;
         FK_HIP(hipMemcpyAsync(s, &rz0, sizeof(double), hipMemcpyHostToDevice, F.stream), "copy");
         result = AKRA_NOT_CONVERGED;
+        StallWatch stall(o.stall_iters, rel);
         while (true) {
             if (rel < o.tol) {
                 result = AKRA_OK;
@@ -726,6 +729,11 @@ akra_status akra_flat_cg_solve(akra_flat_plan plan, const double *g1, const doub
             }
             rel = std::sqrt(rr) / bn;
             if (o.resid_hist && it <= o.resid_hist_len) o.resid_hist[it - 1] = rel;
+            if (rel >= o.tol && stall.step(rel)) {
+                result = AKRA_STAGNATED;
+                set_error("CG stagnated: no new smallest residual in stall_iters iterations");
+                break;
+            }
         }
         info.rel_resid = rel;
         // true residual
@@ -747,7 +755,7 @@ akra_status akra_flat_cg_solve(akra_flat_plan plan, const double *g1, const doub
     info.status = result;
     info.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     if (info_out) *info_out = info;
-    if (result != AKRA_OK) set_error("maxiter reached");
+    if (result == AKRA_NOT_CONVERGED) set_error("maxiter reached");
     return (akra_status)result;
 }
 

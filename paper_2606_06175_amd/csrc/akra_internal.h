@@ -184,6 +184,34 @@ struct Plan {
     int ev_used = 0;
 };
 
+// Solves that stopped with a valid iterate (maxiter or stagnation), and the status of several such
+// solves together: NOT_CONVERGED over STAGNATED over OK.
+inline bool stopped_early(akra_status s) { return s == AKRA_NOT_CONVERGED || s == AKRA_STAGNATED; }
+inline akra_status merge_stops(akra_status a, akra_status b)
+{
+    if (a == AKRA_NOT_CONVERGED || b == AKRA_NOT_CONVERGED) return AKRA_NOT_CONVERGED;
+    if (a == AKRA_STAGNATED || b == AKRA_STAGNATED) return AKRA_STAGNATED;
+    return AKRA_OK;
+}
+// Stagnation test: true once `window` consecutive observed residuals have failed to go below the
+// smallest one seen before them (window <= 0: never).
+struct StallWatch {
+    int window = 0;
+    double best = 0.0;
+    int since = 0;
+    StallWatch(int w = 0, double start = 0.0) : window(w), best(start) {}
+    bool step(double rel)
+    {
+        if (window <= 0) return false;
+        if (rel < best) {
+            best = rel;
+            since = 0;
+            return false;
+        }
+        return ++since >= window;
+    }
+};
+
 // error handling
 void set_error(const std::string &msg);
 akra_status hip_fail(hipError_t e, const char *what);

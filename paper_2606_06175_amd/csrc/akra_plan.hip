@@ -891,6 +891,7 @@ static akra_status cg_run(Plan &P, const akra_cg_opts &o, akra_cg_info *info)
     double rr = P.cg_rr, rel = std::sqrt(rr) / bn, rmax = std::sqrt(rr);
     bool fresh = true;
     akra_status result = AKRA_NOT_CONVERGED;
+    StallWatch stall(o.stall_iters, rel);
     auto refresh = [&]() -> akra_status {
         akra_status s2 = true_residual(P, P.d_r);
         if (s2) return s2;
@@ -950,6 +951,11 @@ static akra_status cg_run(Plan &P, const akra_cg_opts &o, akra_cg_info *info)
         }
         rel = std::sqrt(rr) / bn;
         if (o.resid_hist && P.cg_iters - 1 < o.resid_hist_len) o.resid_hist[P.cg_iters - 1] = rel;
+        if (rel >= o.tol && stall.step(rel)) {
+            result = AKRA_STAGNATED;
+            set_error("CG stagnated: no new smallest residual in stall_iters iterations");
+            break;
+        }
         if (fp32 && std::sqrt(rr) < o.reliable_delta * rmax && rel >= o.tol) {
             st = refresh();
             if (st) return st;
@@ -1163,7 +1169,7 @@ static akra_status read_opts(const akra_cg_opts *opts, akra_cg_opts &o)
     akra_cg_opts_default(&o);
     if (opts) o = *opts;
     if (!(o.tol > 0) || o.maxiter < 0 || !(o.lambda >= 0) || !(o.reliable_delta > 0 && o.reliable_delta < 1) ||
-        o.mode < AKRA_JOINT_EB || o.mode > AKRA_B_ONLY) {
+        o.mode < AKRA_JOINT_EB || o.mode > AKRA_B_ONLY || o.stall_iters < 0) {
         set_error("invalid solver options");
         return AKRA_ERR_ARG;
     }
@@ -1223,6 +1229,7 @@ static akra_status solve_batched(Plan &P, const double *g1, const double *g2, co
     std::vector<double> bn(nr), rel(nr), rmax(nr), rr(nr);
     std::vector<char> active(nr, 1), fresh(nr, 1), restarted(nr, 0);
     std::vector<int> status(nr, AKRA_NOT_CONVERGED);
+    std::vector<StallWatch> stall(nr);
     P.cg_fp64_applies = 0;
     AK_HIP(hipMemsetAsync(P.d_flag, 0, sizeof(int) * nr, P.stream), "memset");
     for (int r = 0; r < nr; ++r) {
@@ -1260,6 +1267,7 @@ static akra_status solve_batched(Plan &P, const double *g1, const double *g2, co
         rr[r] = hs[8 * r + 3];
         rel[r] = bn[r] > 0 ? std::sqrt(rr[r]) / bn[r] : 0.0;
         rmax[r] = std::sqrt(rr[r]);
+        stall[r] = StallWatch(o.stall_iters, rel[r]);
         if (bn[r] == 0.0) {
             active[r] = 0;
             status[r] = AKRA_OK;
@@ -1334,6 +1342,11 @@ static akra_status solve_batched(Plan &P, const double *g1, const double *g2, co
                 continue;
             }
             rel[r] = std::sqrt(rr[r]) / bn[r];
+            if (rel[r] >= o.tol && stall[r].step(rel[r])) {
+                active[r] = 0;
+                status[r] = AKRA_STAGNATED;
+                continue;
+            }
             if (std::sqrt(rr[r]) < o.reliable_delta * rmax[r] && rel[r] >= o.tol) {
                 st = refresh(r);
                 if (st) return st;
@@ -1356,7 +1369,7 @@ static akra_status solve_batched(Plan &P, const double *g1, const double *g2, co
         }
         worst_true = std::max(worst_true, tr);
         worst_rel = std::max(worst_rel, bn[r] > 0 ? rel[r] : 0.0);
-        if (status[r] != AKRA_OK) result = AKRA_NOT_CONVERGED;
+        result = merge_stops((akra_status)result, (akra_status)status[r]);
         if (xE)
             AK_HIP(hipMemcpyAsync(xE + off, V(P.d_x, r), sizeof(double2) * na, hipMemcpyDeviceToDevice, P.stream),
                    "copy");
@@ -1371,7 +1384,8 @@ static akra_status solve_batched(Plan &P, const double *g1, const double *g2, co
     info.rel_resid_true = worst_true;
     info.lambda_eff = le[0];
     info.precond = pc[0];
-    if (result != AKRA_OK) set_error("maxiter reached or stalled for some right-hand side");
+    if (result == AKRA_NOT_CONVERGED) set_error("maxiter reached or stalled for some right-hand side");
+    if (result == AKRA_STAGNATED) set_error("CG stagnated for some right-hand side");
     return (akra_status)result;
 }
 
@@ -1394,7 +1408,7 @@ static akra_status solve_common(Plan &P, const double *g1, const double *g2, con
     akra_status worst = AKRA_OK;
     if (P.prec == AKRA_FP32 && P.nrhs > 1) {
         worst = solve_batched(P, g1, g2, bE, bB, o, kd, le, pc, xE, xB, info);
-        if (worst != AKRA_OK && worst != AKRA_NOT_CONVERGED) return worst;
+        if (worst != AKRA_OK && !stopped_early(worst)) return worst;
         info.status = worst;
         info.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
         if (info_out) *info_out = info;
@@ -1405,7 +1419,7 @@ static akra_status solve_common(Plan &P, const double *g1, const double *g2, con
         st = cg_prepare(P, g1, g2, bE, bB, xE, xB, o, kd, le, pc, r);
         if (st) return st;
         st = cg_run(P, o, &info);
-        if (st == AKRA_OK || st == AKRA_NOT_CONVERGED) {
+        if (st == AKRA_OK || stopped_early(st)) {
             if (xE)
                 AK_HIP(hipMemcpyAsync(xE + off, P.d_x, sizeof(double2) * P.nalm, hipMemcpyDeviceToDevice, P.stream),
                        "copy");
@@ -1414,8 +1428,8 @@ static akra_status solve_common(Plan &P, const double *g1, const double *g2, con
                    "copy");
             AK_HIP(hipStreamSynchronize(P.stream), "sync");
         }
-        if (st != AKRA_OK && st != AKRA_NOT_CONVERGED) return st;
-        if (st == AKRA_NOT_CONVERGED) worst = st;
+        if (st != AKRA_OK && !stopped_early(st)) return st;
+        worst = merge_stops(worst, st);
     }
     info.status = worst;
     info.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -1549,8 +1563,8 @@ akra_status akra_cg_solve_vjp(akra_plan plan, const double *g1, const double *g2
         st = cg_begin(P, false);
         if (st) return st;
         st = cg_run(P, o, &info);
-        if (st != AKRA_OK && st != AKRA_NOT_CONVERGED) return st;
-        if (st == AKRA_NOT_CONVERGED) worst = st;
+        if (st != AKRA_OK && !stopped_early(st)) return st;
+        worst = merge_stops(worst, st);
         // c = lambda / sum M * <u, x>_w, in scalar slots past the per-rhs weight sums
         double *sc = P.d_scal + 8 + 4 * P.nrhs;
         launch_dot(P, P.d_x, xE + off, sc, na);
@@ -1925,7 +1939,7 @@ akra_status akra_noise_spectra(akra_plan plan, int nset, const double *g1, const
     }
     AK_HIP(hipMemsetAsync(P.d_cmp_flag, 0, sizeof(int), P.stream), "memset");
     akra_cg_info agg{};
-    int worst = AKRA_OK;
+    akra_status worst = AKRA_OK;
     bool first = true;
     const int R = gx / nset;  // realisations per pass
     for (int k0 = 0; k0 < n_real; k0 += R) {
@@ -1944,8 +1958,8 @@ akra_status akra_noise_spectra(akra_plan plan, int nset, const double *g1, const
             st = solve_common(P, m1 + (int64_t)g0 * npix, m2 + (int64_t)g0 * npix, ninv + (int64_t)(g0 % nset) * npix,
                               mask, nullptr, nullptr, &o, xE + (int64_t)g0 * 2 * na, xB + (int64_t)g0 * 2 * na, &gi,
                               G == 1 ? 1 : nset);
-            if (st != AKRA_OK && st != AKRA_NOT_CONVERGED) return st;
-            if (st == AKRA_NOT_CONVERGED) worst = AKRA_NOT_CONVERGED;
+            if (st != AKRA_OK && !stopped_early(st)) return st;
+            worst = merge_stops(worst, st);
             agg.iters += gi.iters;
             agg.fp64_applies += gi.fp64_applies;
             agg.rel_resid = std::max(agg.rel_resid, gi.rel_resid);
@@ -1994,8 +2008,9 @@ akra_status akra_noise_spectra(akra_plan plan, int nset, const double *g1, const
     agg.status = worst;
     agg.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     if (info_out) *info_out = agg;
-    if (worst != AKRA_OK) set_error("maxiter reached or stalled for some realisation");
-    return (akra_status)worst;
+    if (worst == AKRA_NOT_CONVERGED) set_error("maxiter reached or stalled for some realisation");
+    if (worst == AKRA_STAGNATED) set_error("CG stagnated for some realisation");
+    return worst;
 }
 
 // ---- catalogue pixelisation (Sec. III.B) -----------------------------------------------------------

@@ -48,6 +48,13 @@ def test_default_options(L):
     assert o.lambda_ == 1e-3 and o.tol == 1e-3 and o.maxiter == 1000
     assert o.use_x0 == 0 and not o.kernel_l and o.reliable_delta == 0.1
     assert not o.resid_hist and o.resid_hist_len == 0
+    assert o.mode == 0 and o.stall_iters == 0
+    # the C struct is no larger than the binding's: the defaults leave the bytes past it alone
+    n = ctypes.sizeof(akra.CgOpts)
+    buf = (ctypes.c_ubyte * (n + 32))(*([0xAB] * (n + 32)))
+    L.akra_cg_opts_default(ctypes.cast(buf, ctypes.POINTER(akra.CgOpts)))
+    assert list(buf[n:]) == [0xAB] * 32
+    assert akra.CgOpts.from_buffer(buf).stall_iters == 0
 
 
 def test_null_plan_of_the_stage_calls(L):
