@@ -16,6 +16,8 @@ SOURCES = ["akra_plan.hip", "akra_kernels.hip", "akra_spectra.hip", "akra_pixel.
 # Packed FP32 VALU forms are disabled for every HIP translation unit.
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# roctx: host-side trace ranges around entry calls and operator stages
+LINK = ["-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx"]
 # host-side sanitizers only: each -fsanitize= applies to the host compilation
 SAN_FLAGS = ["-g", "-fno-omit-frame-pointer", "-Xarch_host", "-fsanitize=address",
              "-Xarch_host", "-fsanitize=undefined"]
@@ -43,7 +45,7 @@ def _build(out, extra, verbose, jobs):
         with ThreadPoolExecutor(max_workers=jobs) as ex:
             list(ex.map(lambda c: _run(c, verbose), cmds))
         tmp = out + ".tmp%d" % os.getpid()
-        _run([_hipcc()] + FLAGS + list(extra) + ["-shared"] + objs + ["-o", tmp], verbose)
+        _run([_hipcc()] + FLAGS + list(extra) + ["-shared"] + objs + LINK + ["-o", tmp], verbose)
         os.replace(tmp, out)
     finally:
         shutil.rmtree(tmpdir, ignore_errors=True)

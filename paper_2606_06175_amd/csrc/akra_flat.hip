@@ -512,6 +512,7 @@ static bool pow2_in(int n) { return n >= 4 && n <= FL_MAXN && (n & (n - 1)) == 0
 
 akra_status akra_flat_plan_create(int nx, int ny, void *hip_stream, akra_flat_plan *out)
 {
+    TraceRange trace_range("akra_flat_plan_create");
     if (!out) {
         set_error("out is NULL");
         return AKRA_ERR_ARG;
@@ -593,6 +594,7 @@ static akra_status fl_check(const char *what)
 
 akra_status akra_flat_synth(akra_flat_plan plan, const double *kE, const double *kB, double *g1, double *g2)
 {
+    TraceRange trace_range("akra_flat_synth");
     FL_PLAN();
     if (!kE || !kB || !g1 || !g2) {
         set_error("null pointer argument");
@@ -605,6 +607,7 @@ akra_status akra_flat_synth(akra_flat_plan plan, const double *kE, const double 
 
 akra_status akra_flat_adjoint(akra_flat_plan plan, const double *g1, const double *g2, double *yE, double *yB)
 {
+    TraceRange trace_range("akra_flat_adjoint");
     FL_PLAN();
     if (!g1 || !g2 || !yE || !yB) {
         set_error("null pointer argument");
@@ -618,6 +621,7 @@ akra_status akra_flat_adjoint(akra_flat_plan plan, const double *g1, const doubl
 akra_status akra_flat_apply_H(akra_flat_plan plan, const double *ninv, const uint8_t *mask, double lambda_eff,
                               const double *kE, const double *kB, double *yE, double *yB)
 {
+    TraceRange trace_range("akra_flat_apply_H");
     FL_PLAN();
     if (!kE || !kB || !yE || !yB) {
         set_error("null pointer argument");
@@ -635,6 +639,7 @@ akra_status akra_flat_apply_H(akra_flat_plan plan, const double *ninv, const uin
 akra_status akra_flat_rhs(akra_flat_plan plan, const double *g1, const double *g2, const double *ninv,
                           const uint8_t *mask, double *bE, double *bB)
 {
+    TraceRange trace_range("akra_flat_rhs");
     FL_PLAN();
     if (!g1 || !g2 || !bE || !bB) {
         set_error("null pointer argument");
@@ -652,6 +657,7 @@ akra_status akra_flat_cg_solve(akra_flat_plan plan, const double *g1, const doub
                                const uint8_t *mask, const akra_cg_opts *opts, double *kE, double *kB,
                                akra_cg_info *info_out)
 {
+    TraceRange trace_range("akra_flat_cg_solve");
     FL_PLAN();
     auto t0 = std::chrono::steady_clock::now();
     akra_cg_opts o;
@@ -763,6 +769,7 @@ akra_status akra_flat_cg_solve(akra_flat_plan plan, const double *g1, const doub
 akra_status akra_flat_cg_start(akra_flat_plan plan, const double *g1, const double *g2, const double *ninv,
                                const uint8_t *mask, double lambda)
 {
+    TraceRange trace_range("akra_flat_cg_start");
     FL_PLAN();
     if (!g1 || !g2) {
         set_error("null pointer argument");
@@ -788,6 +795,7 @@ akra_status akra_flat_cg_start(akra_flat_plan plan, const double *g1, const doub
 
 akra_status akra_flat_cg_step(akra_flat_plan plan, int nsteps)
 {
+    TraceRange trace_range("akra_flat_cg_step");
     FL_PLAN();
     if (nsteps < 0 || !F.step_ready) {
         set_error("nsteps must be >= 0, after akra_flat_cg_start");

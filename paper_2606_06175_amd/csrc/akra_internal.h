@@ -7,6 +7,8 @@
 #include <string>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "../../include/akra.h"
 
 namespace akra {
@@ -173,6 +175,7 @@ struct Plan {
     // one single-right-hand-side PCG iteration recorded as a HIP graph (on a private capture stream)
     // and replayed on the plan stream; cg_graph_key holds every by-value kernel argument it baked in
     bool use_graph = true;
+    bool capturing = false;  // recording the graph: host-side trace ranges are not emitted
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t cg_graph = nullptr;
     double cg_graph_key[12] = {};
@@ -182,6 +185,15 @@ struct Plan {
     std::vector<std::array<hipEvent_t, 2>> ev_pool;
     std::vector<int> ev_stage;
     int ev_used = 0;
+};
+
+// Host-side trace range for the duration of a scope (shown by rocprofv3 --marker-trace, which
+// attributes the kernels dispatched inside it; without a tracer the calls return at once).
+struct TraceRange {
+    explicit TraceRange(const char *name) { roctxRangePushA(name); }
+    ~TraceRange() { roctxRangePop(); }
+    TraceRange(const TraceRange &) = delete;
+    TraceRange &operator=(const TraceRange &) = delete;
 };
 
 // Solves that stopped with a valid iterate (maxiter or stagnation), and the status of several such

@@ -658,9 +658,15 @@ static akra_status zero_held(Plan &P, double *v)
     return AKRA_OK;
 }
 
-// ---- stage timing (HIP events on the plan stream) -------------------------------------------
+// ---- stage marks: trace ranges, and timing with HIP events on the plan stream ------------------
+static const char *const k_stage_names[AKRA_NSTAGES] = {"akra.prologue", "akra.leg_synth", "akra.ring",
+                                                         "akra.leg_adj", "akra.epilogue", "akra.cg_vec"};
 static void stage_mark(Plan &P, int stage, bool begin)
 {
+    if (!P.capturing) {
+        if (begin) roctxRangePushA(k_stage_names[stage]);
+        else roctxRangePop();
+    }
     if (!P.timing) return;
     if (begin) {
         if (P.ev_used == (int)P.ev_pool.size()) {
@@ -824,7 +830,9 @@ static akra_status record_iteration(Plan &P, bool fp32)
     const int iters = P.cg_iters;
     AK_HIP(hipStreamBeginCapture(P.cap_stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
     P.stream = P.cap_stream;
+    P.capturing = true;
     akra_status st = cg_iterate(P, fp32);
+    P.capturing = false;
     P.stream = s;
     P.cg_iters = iters;
     hipGraph_t g = nullptr;
@@ -853,6 +861,7 @@ static akra_status cg_step1(Plan &P, bool fp32)
         akra_status st = record_iteration(P, fp32);
         if (st) return st;
     }
+    TraceRange tr("akra.cg_iteration_graph");
     AK_HIP(hipGraphLaunch(P.cg_graph, P.stream), "hipGraphLaunch");
     P.cg_iters++;
     return AKRA_OK;
@@ -1006,6 +1015,7 @@ void akra_cg_opts_default(akra_cg_opts *o)
 
 akra_status akra_plan_create(int nside, int lmax, int nrhs, int precision, void *hip_stream, akra_plan *out)
 {
+    TraceRange trace_range("akra_plan_create");
     if (!out) {
         set_error("out is NULL");
         return AKRA_ERR_ARG;
@@ -1043,6 +1053,7 @@ int64_t akra_plan_device_bytes(akra_plan plan) { return plan ? plan->P->device_b
 
 akra_status akra_synth2(akra_plan plan, const double *almE, const double *almB, double *g1, double *g2)
 {
+    TraceRange trace_range("akra_synth2");
     AK_PLAN();
     if (!almE || !almB || !g1 || !g2) {
         set_error("null pointer argument");
@@ -1061,6 +1072,7 @@ akra_status akra_synth2(akra_plan plan, const double *almE, const double *almB, 
 
 akra_status akra_adjoint2(akra_plan plan, const double *g1, const double *g2, double *almE, double *almB)
 {
+    TraceRange trace_range("akra_adjoint2");
     AK_PLAN();
     if (!almE || !almB || !g1 || !g2) {
         set_error("null pointer argument");
@@ -1079,6 +1091,7 @@ akra_status akra_adjoint2(akra_plan plan, const double *g1, const double *g2, do
 akra_status akra_apply_H(akra_plan plan, const double *ninv, const uint8_t *mask, const double *kernel_l,
                          double lambda_eff, const double *xE, const double *xB, double *yE, double *yB)
 {
+    TraceRange trace_range("akra_apply_H");
     AK_PLAN();
     if (!xE || !xB || !yE || !yB) {
         set_error("null pointer argument");
@@ -1117,6 +1130,7 @@ static akra_status rhs_core(Plan &P, const double *g1, const double *g2, const d
 akra_status akra_rhs(akra_plan plan, const double *g1, const double *g2, const double *ninv, const uint8_t *mask,
                      const double *kernel_l, double *bE, double *bB)
 {
+    TraceRange trace_range("akra_rhs");
     AK_PLAN();
     if (!g1 || !g2 || !bE || !bB) {
         set_error("null pointer argument");
@@ -1440,6 +1454,7 @@ static akra_status solve_common(Plan &P, const double *g1, const double *g2, con
 akra_status akra_cg_solve(akra_plan plan, const double *g1, const double *g2, const double *ninv, const uint8_t *mask,
                           const akra_cg_opts *opts, double *xE, double *xB, akra_cg_info *info)
 {
+    TraceRange trace_range("akra_cg_solve");
     AK_PLAN();
     if (!g1 || !g2 || !xE || !xB) {
         set_error("null pointer argument");
@@ -1451,6 +1466,7 @@ akra_status akra_cg_solve(akra_plan plan, const double *g1, const double *g2, co
 akra_status akra_cg_solve_b(akra_plan plan, const double *ninv, const uint8_t *mask, const double *bE, const double *bB,
                             const akra_cg_opts *opts, double *xE, double *xB, akra_cg_info *info)
 {
+    TraceRange trace_range("akra_cg_solve_b");
     AK_PLAN();
     if (!bE || !bB || !xE || !xB) {
         set_error("null pointer argument");
@@ -1466,6 +1482,7 @@ akra_status akra_cg_solve_cond_b(akra_plan plan, const double *g1, const double 
                                  const uint8_t *mask, const akra_cg_opts *opts, const double *kE, double *kB,
                                  akra_cg_info *info)
 {
+    TraceRange trace_range("akra_cg_solve_cond_b");
     AK_PLAN();
     if (!g1 || !g2 || !kE || !kB) {
         set_error("null pointer argument");
@@ -1528,6 +1545,7 @@ akra_status akra_cg_solve_vjp(akra_plan plan, const double *g1, const double *g2
                               const double *vE, const double *vB, double *dg1, double *dg2, double *dninv,
                               akra_cg_info *info_out)
 {
+    TraceRange trace_range("akra_cg_solve_vjp");
     AK_PLAN();
     if (!g1 || !g2 || !xE || !xB || !vE || !vB || !dg1 || !dg2 || !dninv) {
         set_error("null pointer argument");
@@ -1591,6 +1609,7 @@ akra_status akra_cg_solve_vjp(akra_plan plan, const double *g1, const double *g2
 akra_status akra_cg_start(akra_plan plan, const double *g1, const double *g2, const double *ninv, const uint8_t *mask,
                           const akra_cg_opts *opts)
 {
+    TraceRange trace_range("akra_cg_start");
     AK_PLAN();
     if (!g1 || !g2) {
         set_error("null pointer argument");
@@ -1616,6 +1635,7 @@ akra_status akra_cg_start(akra_plan plan, const double *g1, const double *g2, co
 
 akra_status akra_cg_step(akra_plan plan, int nsteps)
 {
+    TraceRange trace_range("akra_cg_step");
     AK_PLAN();
     if (!P.cg_ready) {
         set_error("akra_cg_step before akra_cg_start");
@@ -1631,6 +1651,7 @@ akra_status akra_cg_step(akra_plan plan, int nsteps)
 
 akra_status akra_cg_state(akra_plan plan, double *rel_resid, int *iters, double *xE, double *xB)
 {
+    TraceRange trace_range("akra_cg_state");
     AK_PLAN();
     if (!P.cg_ready) {
         set_error("akra_cg_state before akra_cg_start");
@@ -1788,6 +1809,7 @@ static akra_status shuffle_flag(Plan &P)
 
 akra_status akra_unmasked_index(akra_plan plan, const uint8_t *mask, int32_t *idx, int64_t *n_obs)
 {
+    TraceRange trace_range("akra_unmasked_index");
     AK_PLAN();
     if (!mask || !idx || !n_obs) {
         set_error("null pointer argument");
@@ -1802,6 +1824,7 @@ akra_status akra_unmasked_index(akra_plan plan, const uint8_t *mask, int32_t *id
 akra_status akra_shuffle_shear(akra_plan plan, const double *g1, const double *g2, const int32_t *idx, int64_t n_obs,
                                const int32_t *perm, int n_real, double *g1_out, double *g2_out)
 {
+    TraceRange trace_range("akra_shuffle_shear");
     AK_PLAN();
     if (n_real < 0 || n_obs < 0 || n_obs > P.npix) {
         set_error("n_real must be >= 0 and n_obs in [0, Npix]");
@@ -1828,6 +1851,7 @@ akra_status akra_shuffle_shear(akra_plan plan, const double *g1, const double *g
 akra_status akra_alm_spectra(akra_plan plan, const double *x, int nx, const double *y, int ny, const int32_t *pairs,
                              int npairs, double *cl)
 {
+    TraceRange trace_range("akra_alm_spectra");
     AK_PLAN();
     if (npairs < 0 || nx < 0 || ny < 0) {
         set_error("counts must be >= 0");
@@ -1880,6 +1904,7 @@ akra_status akra_noise_spectra(akra_plan plan, int nset, const double *g1, const
                                const akra_cg_opts *opts, void *work, int64_t work_bytes, double *cl, double *cl_mean,
                                double *cl_std, akra_cg_info *info_out)
 {
+    TraceRange trace_range("akra_noise_spectra");
     AK_PLAN();
     auto t0 = std::chrono::steady_clock::now();
     if (nset != 1 && nset != 2) {
@@ -2025,6 +2050,7 @@ static akra_status read_flags2(Plan &P, int *f)
 
 akra_status akra_ang2pix(akra_plan plan, const double *z, const double *phi, int64_t n, int32_t *pix)
 {
+    TraceRange trace_range("akra_ang2pix");
     AK_PLAN();
     if (n < 0) {
         set_error("n must be >= 0");
@@ -2064,6 +2090,7 @@ akra_status akra_pixelize(akra_plan plan, const double *z, const double *phi, co
                           const double *w, int64_t n_gal, double R, double sigma_e, double n_th, void *work,
                           int64_t work_bytes, double *g1, double *g2, double *ninv, double *neff, uint8_t *mask)
 {
+    TraceRange trace_range("akra_pixelize");
     AK_PLAN();
     if (n_gal < 0 || n_gal > INT32_MAX) {
         set_error("n_gal must be in [0, 2^31 - 1]");
