@@ -362,6 +362,16 @@ def rates_leg(c3cfg, tol, maxiter):
                 row[prec + "_solve"] = {"seconds": time.perf_counter() - t, "iters": info["iters"],
                                         "fp64_applies": info["fp64_applies"],
                                         "rel_resid_true": info["rel_resid_true"], "status": info["status"]}
+                if prec == "fp64":
+                    # the same solve testing convergence every 8 iterations (one synchronisation per test)
+                    torch.cuda.synchronize()
+                    t = time.perf_counter()
+                    _, _, info = p.cg_solve(g1, g2, ninv, mask, tol=tol, maxiter=maxiter, raise_not_converged=False,
+                                            check_every=8)
+                    torch.cuda.synchronize()
+                    row["fp64_solve_check_every_8"] = {"seconds": time.perf_counter() - t, "iters": info["iters"],
+                                                       "rel_resid_true": info["rel_resid_true"],
+                                                       "status": info["status"]}
             p.close()
         log("rates %s: %s" % (name, row))
         out[name] = row

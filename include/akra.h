@@ -93,6 +93,12 @@ typedef struct {
     int stall_iters;         /* > 0: stop with AKRA_STAGNATED once the relative residual has not  */
                              /* fallen below its smallest earlier value for this many iterations  */
                              /* (the residual the convergence test sees); 0 (default): off        */
+    int check_every;         /* > 1: iterations between convergence tests, run back to back with */
+                             /* one host synchronisation per test (single-RHS and flat solves);   */
+                             /* the history is written at tested iterations only, stall_iters    */
+                             /* counts tests, and a solve may run up to check_every - 1           */
+                             /* iterations past the one that met tol; 0 or 1 (default): every     */
+                             /* iteration                                                        */
 } akra_cg_opts;
 
 typedef struct {

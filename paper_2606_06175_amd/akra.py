@@ -35,7 +35,8 @@ class CgOpts(ctypes.Structure):
     _fields_ = [("lambda_", ctypes.c_double), ("tol", ctypes.c_double), ("maxiter", ctypes.c_int),
                 ("use_x0", ctypes.c_int), ("kernel_l", ctypes.POINTER(ctypes.c_double)),
                 ("reliable_delta", ctypes.c_double), ("resid_hist", ctypes.POINTER(ctypes.c_double)),
-                ("resid_hist_len", ctypes.c_int), ("mode", ctypes.c_int), ("stall_iters", ctypes.c_int)]
+                ("resid_hist_len", ctypes.c_int), ("mode", ctypes.c_int), ("stall_iters", ctypes.c_int),
+                ("check_every", ctypes.c_int)]
 
 
 # unknowns of a solve (akra_mode): joint (kappa_E, kappa_B), the E block only, the B block only
@@ -244,11 +245,13 @@ class Plan:
                                   bE.data_ptr(), bB.data_ptr()))
         return bE, bB
 
-    def _opts(self, tol, maxiter, lam, x0, kernel, reliable_delta, hist_len, mode="joint", stall_iters=0):
+    def _opts(self, tol, maxiter, lam, x0, kernel, reliable_delta, hist_len, mode="joint", stall_iters=0,
+              check_every=1):
         o = CgOpts()
         lib().akra_cg_opts_default(ctypes.byref(o))
         o.lambda_, o.tol, o.maxiter = float(lam), float(tol), int(maxiter)
         o.stall_iters = int(stall_iters)
+        o.check_every = int(check_every)
         if mode not in MODES:
             raise ValueError("mode must be one of %s" % sorted(MODES))
         o.mode = MODES[mode]
@@ -275,7 +278,7 @@ class Plan:
         return d
 
     def cg_solve(self, g1, g2, ninv, mask, tol=1e-3, maxiter=1000, lam=1e-3, x0=None, kernel=None,
-                 reliable_delta=0.1, hist_len=0, raise_not_converged=True, mode="joint", stall_iters=0):
+                 reliable_delta=0.1, hist_len=0, raise_not_converged=True, mode="joint", stall_iters=0, check_every=1):
         """Regularised ML estimate (kappa_E, kappa_B).  mode "joint" solves the full E/B system, "E"
         the E block alone (kappa_B returned as zero), "B" the B block alone."""
         g1, g2 = self._map(g1, "g1"), self._map(g2, "g2")
@@ -285,7 +288,7 @@ class Plan:
         if x0 is not None:
             xE.copy_(x0[0].reshape(xE.shape))
             xB.copy_(x0[1].reshape(xB.shape))
-        o, keep = self._opts(tol, maxiter, lam, x0, kernel, reliable_delta, hist_len, mode, stall_iters)
+        o, keep = self._opts(tol, maxiter, lam, x0, kernel, reliable_delta, hist_len, mode, stall_iters, check_every)
         inf = CgInfo()
         with torch.cuda.device(self.device):
             st = lib().akra_cg_solve(self._h, g1.data_ptr(), g2.data_ptr(), ninv.data_ptr(), mask.data_ptr(),
@@ -295,7 +298,7 @@ class Plan:
         return xE, xB, self._info(inf, keep, hist_len)
 
     def cg_solve_vjp(self, g1, g2, ninv, mask, xE, xB, vE, vB, tol=1e-3, maxiter=1000, lam=1e-3, kernel=None,
-                     reliable_delta=0.1, raise_not_converged=True, mode="joint", stall_iters=0):
+                     reliable_delta=0.1, raise_not_converged=True, mode="joint", stall_iters=0, check_every=1):
         """dL/dg1, dL/dg2, dL/dninv for x = cg_solve(g1, g2, ninv, mask, ...) and the upstream
         gradient (vE, vB) on the stored (Re, Im) of x (one more CG solve, see akra_cg_solve_vjp)."""
         g1, g2 = self._map(g1, "g1"), self._map(g2, "g2")
@@ -304,7 +307,7 @@ class Plan:
         xE, xB = self._alm(xE, "xE"), self._alm(xB, "xB")
         vE, vB = self._alm(vE, "vE"), self._alm(vB, "vB")
         dg1, dg2, dn = self._map_out(), self._map_out(), self._map_out()
-        o, keep = self._opts(tol, maxiter, lam, None, kernel, reliable_delta, 0, mode, stall_iters)
+        o, keep = self._opts(tol, maxiter, lam, None, kernel, reliable_delta, 0, mode, stall_iters, check_every)
         inf = CgInfo()
         with torch.cuda.device(self.device):
             st = lib().akra_cg_solve_vjp(self._h, g1.data_ptr(), g2.data_ptr(), ninv.data_ptr(), mask.data_ptr(),
@@ -315,7 +318,7 @@ class Plan:
         return dg1, dg2, dn, self._info(inf, keep, 0)
 
     def cg_solve_b(self, bE, bB, ninv, mask, tol=1e-3, maxiter=1000, lam=1e-3, x0=None, kernel=None,
-                   reliable_delta=0.1, hist_len=0, raise_not_converged=True, mode="joint", stall_iters=0):
+                   reliable_delta=0.1, hist_len=0, raise_not_converged=True, mode="joint", stall_iters=0, check_every=1):
         bE, bB = self._alm(bE, "bE"), self._alm(bB, "bB")
         ninv = self._map(ninv, "ninv")
         mask = self._map(mask, "mask", torch.uint8, per_rhs=False)
@@ -323,7 +326,7 @@ class Plan:
         if x0 is not None:
             xE.copy_(x0[0].reshape(xE.shape))
             xB.copy_(x0[1].reshape(xB.shape))
-        o, keep = self._opts(tol, maxiter, lam, x0, kernel, reliable_delta, hist_len, mode, stall_iters)
+        o, keep = self._opts(tol, maxiter, lam, x0, kernel, reliable_delta, hist_len, mode, stall_iters, check_every)
         inf = CgInfo()
         with torch.cuda.device(self.device):
             st = lib().akra_cg_solve_b(self._h, ninv.data_ptr(), mask.data_ptr(), bE.data_ptr(), bB.data_ptr(),
@@ -333,7 +336,7 @@ class Plan:
         return xE, xB, self._info(inf, keep, hist_len)
 
     def cg_solve_cond_b(self, g1, g2, ninv, mask, kE, tol=1e-3, maxiter=1000, lam=1e-3, kernel=None,
-                        reliable_delta=0.1, hist_len=0, raise_not_converged=True, stall_iters=0):
+                        reliable_delta=0.1, hist_len=0, raise_not_converged=True, stall_iters=0, check_every=1):
         """Conditional B-mode solve: kappa_B of (H_BB + lambda_eff) kappa_B = b_B - H_BE kE for a given
         E-mode solution kE (see akra_cg_solve_cond_b)."""
         g1, g2 = self._map(g1, "g1"), self._map(g2, "g2")
@@ -341,7 +344,7 @@ class Plan:
         mask = self._map(mask, "mask", torch.uint8, per_rhs=False)
         kE = self._alm(kE, "kE")
         kB = self._alm_out()
-        o, keep = self._opts(tol, maxiter, lam, None, kernel, reliable_delta, hist_len, "joint", stall_iters)
+        o, keep = self._opts(tol, maxiter, lam, None, kernel, reliable_delta, hist_len, "joint", stall_iters, check_every)
         inf = CgInfo()
         with torch.cuda.device(self.device):
             st = lib().akra_cg_solve_cond_b(self._h, g1.data_ptr(), g2.data_ptr(), ninv.data_ptr(), mask.data_ptr(),
@@ -404,7 +407,7 @@ class Plan:
         return n.value
 
     def noise_spectra(self, g1, g2, ninv, mask, perm, tol=1e-3, maxiter=1000, lam=1e-3, kernel=None,
-                      reliable_delta=0.1, mode="E", raise_not_converged=True, work=None, stall_iters=0):
+                      reliable_delta=0.1, mode="E", raise_not_converged=True, work=None, stall_iters=0, check_every=1):
         """Shape-noise realisations through the full solve and their spectra (akra_noise_spectra).
 
         One shear set: g1, g2, ninv [Npix], perm int32 [n_real, n_obs] -> auto spectra.  Split halves:
@@ -427,7 +430,7 @@ class Plan:
         cl = torch.empty((n_real, nspec, self.lmax + 1), dtype=torch.float64, device=self.device)
         mean = torch.empty((nspec, self.lmax + 1), dtype=torch.float64, device=self.device)
         std = torch.empty_like(mean)
-        o, keep = self._opts(tol, maxiter, lam, None, kernel, reliable_delta, 0, mode, stall_iters)
+        o, keep = self._opts(tol, maxiter, lam, None, kernel, reliable_delta, 0, mode, stall_iters, check_every)
         inf = CgInfo()
         with torch.cuda.device(self.device):
             st = lib().akra_noise_spectra(self._h, nset, g1.data_ptr(), g2.data_ptr(), ninv.data_ptr(),
@@ -604,7 +607,7 @@ class FlatPlan:
         return bE, bB
 
     def cg_solve(self, g1, g2, ninv, mask, tol=1e-3, maxiter=1000, lam=1e-3, x0=None, hist_len=0,
-                 raise_not_converged=True, stall_iters=0):
+                 raise_not_converged=True, stall_iters=0, check_every=1):
         """Regularised flat-sky estimate (kappa_E, kappa_B) by PCG (see akra_flat_cg_solve)."""
         g1, g2 = self._m(g1, "g1"), self._m(g2, "g2")
         ninv, mask = self._m(ninv, "ninv"), self._m(mask, "mask", torch.uint8)
@@ -617,6 +620,7 @@ class FlatPlan:
         o.lambda_, o.tol, o.maxiter = float(lam), float(tol), int(maxiter)
         o.use_x0 = 1 if x0 is not None else 0
         o.stall_iters = int(stall_iters)
+        o.check_every = int(check_every)
         keep = []
         if hist_len:
             import numpy as np

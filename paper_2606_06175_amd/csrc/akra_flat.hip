@@ -269,8 +269,9 @@ __global__ __launch_bounds__(256) void k_fweights(const double *__restrict__ nin
 // scalars s: [0] rz, [1] <p, w>, [2] alpha, [3] <r, r>, [4] beta
 __global__ void k_fcg_alpha(double *s, int *flag)
 {
+    // breakdown when p^T H p <= 0; the flag is sticky (alpha = 0 until the host reads it)
     const double pw = s[1];
-    if (!(pw > 0.0) || !isfinite(pw)) {
+    if (flag[0] || !(pw > 0.0) || !isfinite(pw)) {
         flag[0] = 1;
         s[2] = 0.0;
     } else {
@@ -664,9 +665,9 @@ akra_status akra_flat_cg_solve(akra_flat_plan plan, const double *g1, const doub
     akra_cg_opts_default(&o);
     if (opts) o = *opts;
     if (!(o.tol > 0) || o.maxiter < 0 || !(o.lambda >= 0) || o.mode != AKRA_JOINT_EB || o.kernel_l ||
-        o.stall_iters < 0) {
-        set_error("flat solve: tol > 0, maxiter >= 0, lambda >= 0, stall_iters >= 0, joint mode and no kernel_l "
-                  "are required");
+        o.stall_iters < 0 || o.check_every < 0) {
+        set_error("flat solve: tol > 0, maxiter >= 0, lambda >= 0, stall_iters >= 0, check_every >= 0, joint mode "
+                  "and no kernel_l are required");
         return AKRA_ERR_ARG;
     }
     if (!g1 || !g2 || !kE || !kB) {
@@ -719,8 +720,9 @@ akra_status akra_flat_cg_solve(akra_flat_plan plan, const double *g1, const doub
                 break;
             }
             if (it >= o.maxiter) break;
-            cg_iteration(F, le, pc);
-            ++it;
+            const int nb = std::min(o.check_every > 1 ? o.check_every : 1, o.maxiter - it);
+            for (int b = 0; b < nb; ++b) cg_iteration(F, le, pc);
+            it += nb;
             st = fl_check("flat_cg");
             if (st) return st;
             FK_HIP(hipMemcpyAsync(F.h_pin, s + 3, sizeof(double), hipMemcpyDeviceToHost, F.stream), "copy");

@@ -618,9 +618,11 @@ static double read_scalar(Plan &P, const double *dev, hipError_t *err)
 
 __global__ void k_cg_alpha(double *scal, int *flag)
 {
-    // scal[0] = rz, scal[1] = pw -> scal[2] = alpha; breakdown when p^T H p <= 0
+    // scal[0] = rz, scal[1] = pw -> scal[2] = alpha; breakdown when p^T H p <= 0.  The flag is
+    // sticky: once set, later iterations take alpha = 0 and x stays the last good iterate until the
+    // host reads the flag
     const double pw = scal[1];
-    if (!(pw > 0.0) || !isfinite(pw)) {
+    if (flag[0] || !(pw > 0.0) || !isfinite(pw)) {
         flag[0] = 1;
         scal[2] = 0.0;
     } else {
@@ -928,9 +930,13 @@ static akra_status cg_run(Plan &P, const akra_cg_opts &o, akra_cg_info *info)
             k_cg_rz<<<1, 1, 0, P.stream>>>(P.d_scal, P.cg_pc);
         }
         if (P.cg_iters >= o.maxiter) break;
-        akra_status st = cg_step1(P, fp32);
-        if (st) return st;
-        if (!fp32 && P.prec == AKRA_FP32) P.cg_fp64_applies++;
+        const int nb = std::min(o.check_every > 1 ? o.check_every : 1, o.maxiter - P.cg_iters);
+        akra_status st = AKRA_OK;
+        for (int b = 0; b < nb; ++b) {
+            st = cg_step1(P, fp32);
+            if (st) return st;
+            if (!fp32 && P.prec == AKRA_FP32) P.cg_fp64_applies++;
+        }
         int flag = 0;
         st = cg_poll(P, &rr, &flag);
         if (st) return st;
@@ -1183,7 +1189,7 @@ static akra_status read_opts(const akra_cg_opts *opts, akra_cg_opts &o)
     akra_cg_opts_default(&o);
     if (opts) o = *opts;
     if (!(o.tol > 0) || o.maxiter < 0 || !(o.lambda >= 0) || !(o.reliable_delta > 0 && o.reliable_delta < 1) ||
-        o.mode < AKRA_JOINT_EB || o.mode > AKRA_B_ONLY || o.stall_iters < 0) {
+        o.mode < AKRA_JOINT_EB || o.mode > AKRA_B_ONLY || o.stall_iters < 0 || o.check_every < 0) {
         set_error("invalid solver options");
         return AKRA_ERR_ARG;
     }

@@ -48,7 +48,7 @@ def test_default_options(L):
     assert o.lambda_ == 1e-3 and o.tol == 1e-3 and o.maxiter == 1000
     assert o.use_x0 == 0 and not o.kernel_l and o.reliable_delta == 0.1
     assert not o.resid_hist and o.resid_hist_len == 0
-    assert o.mode == 0 and o.stall_iters == 0
+    assert o.mode == 0 and o.stall_iters == 0 and o.check_every == 0
     # the C struct is no larger than the binding's: the defaults leave the bytes past it alone
     n = ctypes.sizeof(akra.CgOpts)
     buf = (ctypes.c_ubyte * (n + 32))(*([0xAB] * (n + 32)))

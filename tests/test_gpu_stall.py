@@ -3,6 +3,9 @@ iteration after which its relative residual has failed, stall_iters times in a r
 smallest earlier value (the start counts as the first value).  The stop is checked against that rule
 applied to the residual history the solve itself returns, on FP64 and mixed plans, the flat-sky
 solver and a batched FP32 plan; with the test off (the default) the same solves converge as before.
+Also the convergence test every k iterations (opts.check_every): the tested residuals equal those of
+the solve testing every iteration, and the stop is the first tested iteration whose residual is
+below the tolerance.
 
 Inputs: the C1 workload (HEALPix Nside 32, lmax 64) with seeded random maps, and a 64 x 32 flat field
 from the flat-field recipe."""
@@ -110,3 +113,55 @@ def test_batched_plan_stops_each_rhs():
     print("batched stagnation after %d lockstep iterations" % info["iters"], flush=True)
     assert info["status"] == akra.AKRA_STAGNATED and info["iters"] < 2000
     assert bool(xE.isfinite().all()) and bool(xB.isfinite().all())
+
+
+def first_tested_below(hist, k, tol):
+    """1-based first multiple of k whose residual in the history is below tol, or None."""
+    for j in range(k, len(hist) + 1, k):
+        if hist[j - 1] < tol:
+            return j
+    return None
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_check_every_runs_the_same_iterations(prec):
+    # iterations between tests are the same kernels in the same order: the tested residuals equal
+    # those of a run testing every iteration, bit for bit, and the stop is the first tested
+    # iteration whose residual is below tol (the residual of CG is not monotone, so that can be
+    # later than the first multiple of k after the first iteration below tol)
+    from paper_2606_06175_amd import Plan
+    cfg, t = _c1()
+    print("plan C1 %s, check_every" % prec, flush=True)
+    p = Plan(cfg["nside"], cfg["lmax"], precision=prec, device="cuda:0")
+    # reference history, run past the tolerance used below
+    x1, y1, ref = p.cg_solve(*t, tol=1e-10, maxiter=3000, hist_len=3000)
+    hist = ref["hist"]
+    for k in (2, 5, 8):
+        xk, yk, ik = p.cg_solve(*t, tol=1e-8, maxiter=3000, hist_len=3000, check_every=k)
+        print("check_every %d: %d iterations" % (k, ik["iters"]), flush=True)
+        assert ik["status"] == 0 and ik["rel_resid_true"] <= 1e-8
+        if prec == "fp64":
+            assert ik["iters"] == first_tested_below(hist, k, 1e-8)
+            tested = np.arange(k, ik["iters"] + 1, k) - 1
+            assert np.array_equal(ik["hist"][tested], hist[tested])
+
+
+def test_flat_check_every():
+    import torch
+    from paper_2606_06175_amd import FlatPlan
+    nx, ny = 64, 32
+    f = wl.make_flat(nx, ny, 7)
+    g = np.random.default_rng(3)
+    m = f["mask"].astype(np.float64)
+    dev = torch.device("cuda", 0)
+    t = [torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+         for a in (m * g.normal(size=(ny, nx)), m * g.normal(size=(ny, nx)), f["ninv"], f["mask"])]
+    p = FlatPlan(nx, ny, device="cuda:0")
+    # reference: a fixed 24 iterations (the residual settles at the rounding floor, far above 1e-300)
+    _, _, ref = p.cg_solve(*t, tol=1e-300, maxiter=24, hist_len=24, raise_not_converged=False)
+    _, _, i3 = p.cg_solve(*t, tol=1e-6, maxiter=500, hist_len=500, check_every=3)
+    print("flat: reference %d iterations, check_every 3 stops after %d" % (ref["iters"], i3["iters"]), flush=True)
+    assert i3["status"] == 0 and i3["iters"] == first_tested_below(ref["hist"], 3, 1e-6)
+    tested = np.arange(3, i3["iters"] + 1, 3) - 1
+    assert np.array_equal(i3["hist"][tested], ref["hist"][tested])
+    assert i3["rel_resid_true"] <= 1e-6
