@@ -147,6 +147,7 @@ struct Plan {
     double *d_kern = nullptr;   // [lmax+1]
     double *d_kuser = nullptr;  // [lmax+1] caller-supplied kernel
     double *d_red = nullptr;    // reduction partials
+    double *d_red_cg = nullptr; // [2][CG_RED_BLOCKS] partials of the PCG iteration's inner products
     double *d_scal = nullptr;   // device scalars
     int *d_flag = nullptr;
     // solver vectors [nrhs][2][nalm] complex FP64
@@ -250,9 +251,10 @@ void launch_ring_grad(Plan &P, const double *g1, const double *g2, double *q1, d
 // b = upstream alm gradient / full-m weight (Im(a_l0) dropped), for the backward solve
 void launch_vjp_rhs(Plan &P, const double *vE, const double *vB, double *bE, double *bB);
 void launch_scale_scalar(Plan &P, double *out, const double *in, double f);
-// epilogue: sum partials, E/B combination, out = K_l * c + lam * x
+// epilogue: sum partials, E/B combination, out = K_l * c + lam * x; with dot_red (and x), also the
+// workgroup partials of the full-m <x, out> (cg_red_blocks(P) of them)
 void launch_epilogue(Plan &P, bool fp32, const double *kern, double lam, const double *xE, const double *xB,
-                     double *outE, double *outB);
+                     double *outE, double *outB, double *dot_red = nullptr);
 // batched FP32 adjoint (matrix cores) of right-hand-side group q, and the epilogue of one right-hand
 // side from its slabs
 void launch_adj_batched(Plan &P, int q);
@@ -269,6 +271,15 @@ void launch_dot(Plan &P, const double *a, const double *b, double *out_dev, int6
 void launch_cg_xr(Plan &P, double *x, double *r, const double *p, const double *w, const double *alpha_dev,
                   int64_t n_complex);
 void launch_cg_p(Plan &P, double *p, const double *r, const double *beta_dev, double precond, int64_t n_complex);
+// The PCG iteration's fused scalar path: at most CG_RED_BLOCKS workgroup partials per inner
+// product (the epilogue's <p, w>, the update's <r, r>), summed in a fixed order by the kernels that
+// form alpha and beta (scalars at scal[0..4] as in k_cg_alpha / k_cg_beta)
+constexpr int CG_RED_BLOCKS = 1024;
+int cg_red_blocks(const Plan &P);
+void launch_cg_alpha_sum(Plan &P, const double *red, double *scal, int *flag);
+void launch_cg_xr_rr(Plan &P, double *x, double *r, const double *p, const double *w, const double *alpha_dev,
+                     int64_t n_complex, double *rr_red);
+void launch_cg_beta_sum(Plan &P, const double *red, double *scal, double precond);
 void launch_axpby(Plan &P, double *y, double a, const double *x, double b, int64_t n_complex);
 void launch_scalar_div(Plan &P, double *out, const double *num, const double *den);
 // shape-noise realisations and spectra (akra_spectra.hip)

@@ -979,14 +979,27 @@ __device__ __forceinline__ int m_of(int64_t i, int l, int lmax)
     return m;
 }
 
-template <typename T>
-__global__ void k_epilogue(const T *__restrict__ part, const int *__restrict__ wgstart, int nrb, int64_t nalm,
-                           const int *__restrict__ lof, int lmax, const double *__restrict__ kern, double lam,
-                           const double *__restrict__ xE, const double *__restrict__ xB, double *__restrict__ outE,
-                           double *__restrict__ outB, int proj)
+// Workgroup sum of 256 threads' values in a fixed order (deterministic); the result in thread 0.
+__device__ __forceinline__ double block_sum256(double s, double *sh)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nalm) return;
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int q = 128; q > 0; q >>= 1) {
+        if ((int)threadIdx.x < q) sh[threadIdx.x] += sh[threadIdx.x + q];
+        __syncthreads();
+    }
+    return sh[0];
+}
+
+// One alm index of the epilogue; returns the full-m weighted Re<x, out> of the index (for the
+// fused inner product of a CG iteration).
+template <typename T>
+__device__ __forceinline__ double epilogue_one(int64_t i, const T *__restrict__ part, const int *__restrict__ wgstart,
+                                               int nrb, int64_t nalm, const int *__restrict__ lof, int lmax,
+                                               const double *__restrict__ kern, double lam,
+                                               const double *__restrict__ xE, const double *__restrict__ xB,
+                                               double *__restrict__ outE, double *__restrict__ outB, int proj)
+{
     const int l = lof[i];
     const bool m0 = i <= lmax;
     double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
@@ -1023,6 +1036,30 @@ __global__ void k_epilogue(const T *__restrict__ part, const int *__restrict__ w
     outE[2 * i + 1] = eI;
     outB[2 * i] = bR;
     outB[2 * i + 1] = bI;
+    if (!xE) return 0.0;
+    const double wgt = m0 ? 1.0 : 2.0;
+    return wgt * ((eR * xE[2 * i] + eI * xE[2 * i + 1]) + (bR * xB[2 * i] + bI * xB[2 * i + 1]));
+}
+
+// E/B combination of the adjoint's partial sums, harmonic diagonal and + lambda x (grid-stride over
+// the alm indices).  With dot_red, also the workgroup partials of the full-m inner product <x, out>
+// (one per workgroup, summed in a fixed order by the CG scalar kernel).
+template <typename T>
+__global__ __launch_bounds__(256) void k_epilogue(const T *__restrict__ part, const int *__restrict__ wgstart, int nrb,
+                                                  int64_t nalm, const int *__restrict__ lof, int lmax,
+                                                  const double *__restrict__ kern, double lam,
+                                                  const double *__restrict__ xE, const double *__restrict__ xB,
+                                                  double *__restrict__ outE, double *__restrict__ outB, int proj,
+                                                  double *__restrict__ dot_red)
+{
+    __shared__ double sh[256];
+    double s = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nalm; i += (int64_t)gridDim.x * blockDim.x)
+        s += epilogue_one<T>(i, part, wgstart, nrb, nalm, lof, lmax, kern, lam, xE, xB, outE, outB, proj);
+    if (dot_red) {
+        const double t = block_sum256(s, sh);
+        if (threadIdx.x == 0) dot_red[blockIdx.x] = t;
+    }
 }
 
 // W = mask * ninv; block partials of sum(M N^-1), sum(M), #non-finite, #negative, sum over all pixels
@@ -1538,6 +1575,71 @@ __global__ void k_cg_xr(double *__restrict__ x, double *__restrict__ r, const do
     }
 }
 
+// x += alpha p, r -= alpha w on complex elements (re, im pairs), with the workgroup partials of the
+// full-m <r, r> of the updated r
+__global__ __launch_bounds__(256) void k_cg_xr_rr(double2 *__restrict__ x, double2 *__restrict__ r,
+                                                  const double2 *__restrict__ p, const double2 *__restrict__ w,
+                                                  const double *__restrict__ alpha, int64_t nc, int64_t nalm, int lmax,
+                                                  double *__restrict__ rr_red)
+{
+    __shared__ double sh[256];
+    const double a = *alpha;
+    double s = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nc; i += (int64_t)gridDim.x * blockDim.x) {
+        const double2 pi = p[i], wi = w[i];
+        double2 xi = x[i], ri = r[i];
+        xi.x = fma(a, pi.x, xi.x);
+        xi.y = fma(a, pi.y, xi.y);
+        ri.x = fma(-a, wi.x, ri.x);
+        ri.y = fma(-a, wi.y, ri.y);
+        x[i] = xi;
+        r[i] = ri;
+        const double wgt = ((i % nalm) <= lmax) ? 1.0 : 2.0;
+        s += wgt * (ri.x * ri.x + ri.y * ri.y);
+    }
+    const double t = block_sum256(s, sh);
+    if (threadIdx.x == 0) rr_red[blockIdx.x] = t;
+}
+
+// Fixed-order sum of n workgroup partials by one workgroup of 256 threads (thread t sums partials
+// t, t + 256, ... in order, then a tree), the total in thread 0
+__device__ __forceinline__ double sum_partials256(const double *__restrict__ red, int n, double *sh)
+{
+    double s = 0.0;
+    for (int j = threadIdx.x; j < n; j += 256) s += red[j];
+    return block_sum256(s, sh);
+}
+
+// scal[1] = <p, w> from the epilogue's partials, then alpha = rz / <p, w> into scal[2]; breakdown
+// (p^T H p <= 0 or non-finite) sets the flag, which is sticky: alpha = 0 until the host reads it
+__global__ __launch_bounds__(256) void k_cg_alpha_sum(const double *__restrict__ red, int n, double *__restrict__ scal,
+                                                      int *__restrict__ flag)
+{
+    __shared__ double sh[256];
+    const double pw = sum_partials256(red, n, sh);
+    if (threadIdx.x != 0) return;
+    scal[1] = pw;
+    if (flag[0] || !(pw > 0.0) || !isfinite(pw)) {
+        flag[0] = 1;
+        scal[2] = 0.0;
+    } else {
+        scal[2] = scal[0] / pw;
+    }
+}
+
+// scal[3] = <r, r> from the update's partials, then beta = P <r, r> / rz into scal[4], rz <- P <r, r>
+__global__ __launch_bounds__(256) void k_cg_beta_sum(const double *__restrict__ red, int n, double *__restrict__ scal,
+                                                     double pc)
+{
+    __shared__ double sh[256];
+    const double rr = sum_partials256(red, n, sh);
+    if (threadIdx.x != 0) return;
+    scal[3] = rr;
+    const double rz = pc * rr;
+    scal[4] = (scal[0] > 0.0) ? rz / scal[0] : 0.0;
+    scal[0] = rz;
+}
+
 __global__ void k_cg_p(double *__restrict__ p, const double *__restrict__ r, const double *__restrict__ beta,
                        double precond, int64_t n2)
 {
@@ -1981,7 +2083,8 @@ void launch_epilogue_batched(Plan &P, int rhs, const double *kern, double lam, c
 {
     const float *part = (const float *)P.d_part + (int64_t)(rhs % NBR) * P.nrb_b * P.nalm * 4;
     k_epilogue<float><<<(unsigned)cdiv(P.nalm, 256), 256, 0, P.stream>>>(part, P.d_wgstart_b, P.nrb_b, P.nalm, P.d_lof,
-                                                                        P.lmax, kern, lam, xE, xB, outE, outB, P.proj);
+                                                                        P.lmax, kern, lam, xE, xB, outE, outB, P.proj,
+                                                                        nullptr);
 }
 
 void launch_entry(Plan &P)
@@ -2061,16 +2164,36 @@ void launch_leg_adj(Plan &P, bool fp32, int rhs)
     }
 }
 
+int cg_red_blocks(const Plan &P) { return (int)std::min<int64_t>(CG_RED_BLOCKS, cdiv(P.nalm, 256)); }
+
 void launch_epilogue(Plan &P, bool fp32, const double *kern, double lam, const double *xE, const double *xB,
-                     double *outE, double *outB)
+                     double *outE, double *outB, double *dot_red)
 {
-    dim3 g((unsigned)cdiv(P.nalm, 256));
+    const dim3 g(dot_red ? (unsigned)cg_red_blocks(P) : (unsigned)cdiv(P.nalm, 256));
     if (fp32)
         k_epilogue<float><<<g, 256, 0, P.stream>>>((const float *)P.d_part, P.d_wgstart, P.adj_nrb, P.nalm, P.d_lof,
-                                                   P.lmax, kern, lam, xE, xB, outE, outB, P.proj);
+                                                   P.lmax, kern, lam, xE, xB, outE, outB, P.proj, dot_red);
     else
         k_epilogue<double><<<g, 256, 0, P.stream>>>((const double *)P.d_part, P.d_wgstart, P.adj_nrb, P.nalm,
-                                                    P.d_lof, P.lmax, kern, lam, xE, xB, outE, outB, P.proj);
+                                                    P.d_lof, P.lmax, kern, lam, xE, xB, outE, outB, P.proj, dot_red);
+}
+
+void launch_cg_alpha_sum(Plan &P, const double *red, double *scal, int *flag)
+{
+    k_cg_alpha_sum<<<1, 256, 0, P.stream>>>(red, cg_red_blocks(P), scal, flag);
+}
+
+void launch_cg_xr_rr(Plan &P, double *x, double *r, const double *p, const double *w, const double *alpha_dev,
+                     int64_t n_complex, double *rr_red)
+{
+    k_cg_xr_rr<<<cg_red_blocks(P), 256, 0, P.stream>>>((double2 *)x, (double2 *)r, (const double2 *)p,
+                                                       (const double2 *)w, alpha_dev, n_complex, P.nalm, P.lmax,
+                                                       rr_red);
+}
+
+void launch_cg_beta_sum(Plan &P, const double *red, double *scal, double precond)
+{
+    k_cg_beta_sum<<<1, 256, 0, P.stream>>>(red, cg_red_blocks(P), scal, precond);
 }
 
 template <typename T, int MODE>

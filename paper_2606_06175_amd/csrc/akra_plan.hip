@@ -246,7 +246,7 @@ static void free_plan(Plan *P)
     void *ptrs[] = {P->d_rings, P->d_pair_z, P->d_coef64, P->d_coef32, P->d_coef64s, P->d_coef32s, P->d_recu,
                     P->d_seed2, P->d_seedm2, P->d_seedk,
                     P->d_ent, P->d_entk, P->d_entl, P->d_wgstart, P->d_wgstart_b, P->d_coef32d, P->d_brec,
-                    P->d_tw64, P->d_tw32, P->d_bhat64, P->d_bhat32, P->d_lof, P->d_order_p2, P->d_order_bl, P->d_order_bf, P->d_FG, P->d_part, P->d_rec, P->d_W, P->d_kern, P->d_kuser, P->d_red, P->d_scal, P->d_flag, P->d_x, P->d_r,
+                    P->d_tw64, P->d_tw32, P->d_bhat64, P->d_bhat32, P->d_lof, P->d_order_p2, P->d_order_bl, P->d_order_bf, P->d_FG, P->d_part, P->d_rec, P->d_W, P->d_kern, P->d_kuser, P->d_red, P->d_red_cg, P->d_scal, P->d_flag, P->d_x, P->d_r,
                     P->d_p, P->d_w, P->d_b, P->d_xs, P->d_cmp, P->d_spec};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
@@ -511,6 +511,7 @@ static akra_status create(int nside, int lmax, int nrhs, int prec, void *stream,
     }
     AK_TRY(alloc((void **)&P->d_W, (size_t)nrhs * P->npix * sizeof(double), *P));
     AK_TRY(alloc((void **)&P->d_red, (size_t)512 * 4 * nrhs * sizeof(double), *P));
+    AK_TRY(alloc((void **)&P->d_red_cg, (size_t)2 * CG_RED_BLOCKS * sizeof(double), *P));
     AK_TRY(alloc((void **)&P->d_scal, (size_t)(64 + 16 * nrhs) * sizeof(double), *P));
     AK_TRY(alloc((void **)&P->d_flag, 64 * sizeof(int), *P));
     // unmasked-pixel list scratch: count and flag, then per-tile counts and offsets
@@ -685,9 +686,10 @@ static void stage_mark(Plan &P, int stage, bool begin)
     }
 }
 
-// w = H p style apply with timing marks; W of right-hand side `rhs` must be in P.d_W
+// w = H p style apply with timing marks; W of right-hand side `rhs` must be in P.d_W.  With dot_red,
+// the epilogue also leaves the partials of <x, y>.
 static akra_status apply_H_timed(Plan &P, bool fp32, const double *kern_dev, double lam, const double *xE,
-                                 const double *xB, double *yE, double *yB, int rhs)
+                                 const double *xB, double *yE, double *yB, int rhs, double *dot_red = nullptr)
 {
     stage_mark(P, 0, true);
     launch_prologue(P, fp32, xE, xB, kern_dev, 1);
@@ -702,7 +704,7 @@ static akra_status apply_H_timed(Plan &P, bool fp32, const double *kern_dev, dou
     launch_leg_adj(P, fp32, 0);
     stage_mark(P, 3, false);
     stage_mark(P, 4, true);
-    launch_epilogue(P, fp32, kern_dev, lam, xE, xB, yE, yB);
+    launch_epilogue(P, fp32, kern_dev, lam, xE, xB, yE, yB, dot_red);
     stage_mark(P, 4, false);
     return check_launch("apply_H");
 }
@@ -786,18 +788,21 @@ static akra_status cg_begin(Plan &P, bool use_x0)
 // One PCG iteration on device-resident state, no host synchronisation:
 //   w = H p, alpha = rz / <p, w>, x += alpha p, r -= alpha w, rr = <r, r>,
 //   beta = P rr / rz, p = P r + beta p.
+// The inner products ride on the kernels that already stream the vectors: the epilogue forms the
+// partials of <p, w> as it writes w, the x/r update those of <r, r> as it writes r; the alpha and
+// beta kernels sum them in a fixed order.
 static akra_status cg_iterate(Plan &P, bool fp32)
 {
     const int64_t nc = 2 * P.nalm;
     double *x = P.d_x, *r = P.d_r, *p = P.d_p, *w = P.d_w;
-    akra_status st = apply_H_timed(P, fp32, P.cg_kern, P.cg_lam, p, p + 2 * P.nalm, w, w + 2 * P.nalm, P.cg_rhs);
+    double *red_pw = P.d_red_cg, *red_rr = P.d_red_cg + CG_RED_BLOCKS;
+    akra_status st =
+        apply_H_timed(P, fp32, P.cg_kern, P.cg_lam, p, p + 2 * P.nalm, w, w + 2 * P.nalm, P.cg_rhs, red_pw);
     if (st) return st;
     stage_mark(P, 5, true);
-    launch_dot(P, p, w, P.d_scal + 1, nc);
-    k_cg_alpha<<<1, 1, 0, P.stream>>>(P.d_scal, P.d_flag);
-    launch_cg_xr(P, x, r, p, w, P.d_scal + 2, nc);
-    launch_dot(P, r, r, P.d_scal + 3, nc);
-    k_cg_beta<<<1, 1, 0, P.stream>>>(P.d_scal, P.cg_pc);
+    launch_cg_alpha_sum(P, red_pw, P.d_scal, P.d_flag);
+    launch_cg_xr_rr(P, x, r, p, w, P.d_scal + 2, nc, red_rr);
+    launch_cg_beta_sum(P, red_rr, P.d_scal, P.cg_pc);
     launch_cg_p(P, p, r, P.d_scal + 4, P.cg_pc, nc);
     stage_mark(P, 5, false);
     P.cg_iters++;
