@@ -147,7 +147,7 @@ struct Plan {
     double *d_kern = nullptr;   // [lmax+1]
     double *d_kuser = nullptr;  // [lmax+1] caller-supplied kernel
     double *d_red = nullptr;    // reduction partials
-    double *d_red_cg = nullptr; // [2][CG_RED_BLOCKS] partials of the PCG iteration's inner products
+    double *d_red_cg = nullptr; // [nrhs][2][CG_RED_BLOCKS] partials of the PCG iteration's inner products
     double *d_scal = nullptr;   // device scalars
     int *d_flag = nullptr;
     // solver vectors [nrhs][2][nalm] complex FP64
@@ -259,7 +259,7 @@ void launch_epilogue(Plan &P, bool fp32, const double *kern, double lam, const d
 // side from its slabs
 void launch_adj_batched(Plan &P, int q);
 void launch_epilogue_batched(Plan &P, int rhs, const double *kern, double lam, const double *xE, const double *xB,
-                             double *outE, double *outB);
+                             double *outE, double *outB, double *dot_red = nullptr);
 // chirp spectra of the Bluestein sub lengths Ls (FFT lengths Ms, table offsets ofs; device arrays)
 void launch_bhat(Plan &P, const int *Ls, const int *Ms, const int64_t *ofs, int n, int maxM);
 // weights W = mask * ninv, plus the sums needed for lambda_eff / P and input validation; right-hand

@@ -1555,14 +1555,19 @@ __global__ void k_dot_part(const double *__restrict__ a, const double *__restric
     if (threadIdx.x == 0) red[blockIdx.x] = sh[0];
 }
 
-__global__ void k_sum_part(const double *__restrict__ red, int n, int stride, int ncomp, double *__restrict__ out)
+__global__ __launch_bounds__(256) void k_sum_part(const double *__restrict__ red, int n, int stride, int ncomp,
+                                                  double *__restrict__ out)
 {
-    // deterministic: one thread per component sums the block partials in order
-    const int c = threadIdx.x;
-    if (c >= ncomp) return;
-    double s = 0;
-    for (int i = 0; i < n; ++i) s += red[(int64_t)i * stride + c];
-    out[c] = s;
+    // deterministic: per component, thread t sums the block partials t, t + 256, ... in order, then
+    // a fixed tree over the threads
+    __shared__ double sh[256];
+    for (int c = 0; c < ncomp; ++c) {
+        double s = 0;
+        for (int i = threadIdx.x; i < n; i += 256) s += red[(int64_t)i * stride + c];
+        const double t = block_sum256(s, sh);
+        if (threadIdx.x == 0) out[c] = t;
+        __syncthreads();
+    }
 }
 
 __global__ void k_cg_xr(double *__restrict__ x, double *__restrict__ r, const double *__restrict__ p,
@@ -2079,12 +2084,12 @@ void launch_adj_batched(Plan &P, int q)
 }
 
 void launch_epilogue_batched(Plan &P, int rhs, const double *kern, double lam, const double *xE, const double *xB,
-                             double *outE, double *outB)
+                             double *outE, double *outB, double *dot_red)
 {
     const float *part = (const float *)P.d_part + (int64_t)(rhs % NBR) * P.nrb_b * P.nalm * 4;
-    k_epilogue<float><<<(unsigned)cdiv(P.nalm, 256), 256, 0, P.stream>>>(part, P.d_wgstart_b, P.nrb_b, P.nalm, P.d_lof,
-                                                                        P.lmax, kern, lam, xE, xB, outE, outB, P.proj,
-                                                                        nullptr);
+    const unsigned g = dot_red ? (unsigned)cg_red_blocks(P) : (unsigned)cdiv(P.nalm, 256);
+    k_epilogue<float><<<g, 256, 0, P.stream>>>(part, P.d_wgstart_b, P.nrb_b, P.nalm, P.d_lof, P.lmax, kern, lam, xE,
+                                              xB, outE, outB, P.proj, dot_red);
 }
 
 void launch_entry(Plan &P)
@@ -2311,13 +2316,13 @@ void launch_weights(Plan &P, const double *ninv, const uint8_t *mask, int nrhs, 
 {
     k_weights<<<dim3(RED_BLOCKS, nrhs), 256, 0, P.stream>>>(ninv, mask, P.d_W, P.npix, ncount, P.d_red);
     for (int r = 0; r < nrhs; ++r)
-        k_sum_part<<<1, 64, 0, P.stream>>>(P.d_red + (int64_t)r * RED_BLOCKS * 4, RED_BLOCKS, 4, 4, P.d_scal + 8 + 4 * r);
+        k_sum_part<<<1, 256, 0, P.stream>>>(P.d_red + (int64_t)r * RED_BLOCKS * 4, RED_BLOCKS, 4, 4, P.d_scal + 8 + 4 * r);
 }
 
 void launch_dot(Plan &P, const double *a, const double *b, double *out_dev, int64_t n_complex)
 {
     k_dot_part<<<RED_BLOCKS, 256, 0, P.stream>>>(a, b, n_complex, P.nalm, P.lmax, P.d_red);
-    k_sum_part<<<1, 64, 0, P.stream>>>(P.d_red, RED_BLOCKS, 1, 1, out_dev);
+    k_sum_part<<<1, 256, 0, P.stream>>>(P.d_red, RED_BLOCKS, 1, 1, out_dev);
 }
 
 void launch_cg_xr(Plan &P, double *x, double *r, const double *p, const double *w, const double *alpha_dev,

@@ -511,7 +511,7 @@ static akra_status create(int nside, int lmax, int nrhs, int prec, void *stream,
     }
     AK_TRY(alloc((void **)&P->d_W, (size_t)nrhs * P->npix * sizeof(double), *P));
     AK_TRY(alloc((void **)&P->d_red, (size_t)512 * 4 * nrhs * sizeof(double), *P));
-    AK_TRY(alloc((void **)&P->d_red_cg, (size_t)2 * CG_RED_BLOCKS * sizeof(double), *P));
+    AK_TRY(alloc((void **)&P->d_red_cg, (size_t)2 * CG_RED_BLOCKS * nrhs * sizeof(double), *P));
     AK_TRY(alloc((void **)&P->d_scal, (size_t)(64 + 16 * nrhs) * sizeof(double), *P));
     AK_TRY(alloc((void **)&P->d_flag, 64 * sizeof(int), *P));
     // unmasked-pixel list scratch: count and flag, then per-tile counts and offsets
@@ -712,8 +712,11 @@ static akra_status apply_H_timed(Plan &P, bool fp32, const double *kern_dev, dou
 // H applied to all right-hand sides of an FP32 plan at once: batched matrix-core synthesis, ring
 // stage of every right-hand side with its own W, then per group of 8 right-hand sides the batched
 // matrix-core adjoint and the epilogue of each.  lam_host (per rhs) overrides lam when given.
+// With dot_red, right-hand side r's epilogue also leaves the partials of <x_r, y_r> at
+// dot_red + r 2 CG_RED_BLOCKS.
 static akra_status apply_H_batched(Plan &P, const double *kern_dev, const double *lam_host, double lam,
-                                   const double *xE, const double *xB, double *yE, double *yB, int64_t rstride)
+                                   const double *xE, const double *xB, double *yE, double *yB, int64_t rstride,
+                                   double *dot_red = nullptr)
 {
     stage_mark(P, 1, true);
     launch_synth_batched(P, xE, xB, rstride, kern_dev);
@@ -728,7 +731,8 @@ static akra_status apply_H_batched(Plan &P, const double *kern_dev, const double
         for (int r = 8 * q; r < P.nrhs && r < 8 * q + 8; ++r) {
             const int64_t o = (int64_t)r * 2 * rstride;
             stage_mark(P, 4, true);
-            launch_epilogue_batched(P, r, kern_dev, lam_host ? lam_host[r] : lam, xE + o, xB + o, yE + o, yB + o);
+            launch_epilogue_batched(P, r, kern_dev, lam_host ? lam_host[r] : lam, xE + o, xB + o, yE + o, yB + o,
+                                    dot_red ? dot_red + (int64_t)r * 2 * CG_RED_BLOCKS : nullptr);
             stage_mark(P, 4, false);
         }
     }
@@ -1328,16 +1332,17 @@ static akra_status solve_batched(Plan &P, const double *g1, const double *g2, co
         bool any = false;
         for (int r = 0; r < nr; ++r) any |= active[r] != 0;
         if (!any || iters >= o.maxiter) break;
-        st = apply_H_batched(P, kd, le.data(), 0.0, P.d_p, P.d_p + 2 * na, P.d_w, P.d_w + 2 * na, 2 * na);
+        st = apply_H_batched(P, kd, le.data(), 0.0, P.d_p, P.d_p + 2 * na, P.d_w, P.d_w + 2 * na, 2 * na,
+                             P.d_red_cg);
         if (st) return st;
         for (int r = 0; r < nr; ++r) {
             if (!active[r]) continue;
+            // the epilogue left the partials of <p, w>; the update leaves those of <r, r>
+            double *red_pw = P.d_red_cg + (int64_t)r * 2 * CG_RED_BLOCKS, *red_rr = red_pw + CG_RED_BLOCKS;
             stage_mark(P, 5, true);
-            launch_dot(P, V(P.d_p, r), V(P.d_w, r), S(r) + 1, nc);
-            k_cg_alpha<<<1, 1, 0, P.stream>>>(S(r), P.d_flag + r);
-            launch_cg_xr(P, V(P.d_x, r), V(P.d_r, r), V(P.d_p, r), V(P.d_w, r), S(r) + 2, nc);
-            launch_dot(P, V(P.d_r, r), V(P.d_r, r), S(r) + 3, nc);
-            k_cg_beta<<<1, 1, 0, P.stream>>>(S(r), pc[r]);
+            launch_cg_alpha_sum(P, red_pw, S(r), P.d_flag + r);
+            launch_cg_xr_rr(P, V(P.d_x, r), V(P.d_r, r), V(P.d_p, r), V(P.d_w, r), S(r) + 2, nc, red_rr);
+            launch_cg_beta_sum(P, red_rr, S(r), pc[r]);
             launch_cg_p(P, V(P.d_p, r), V(P.d_r, r), S(r) + 4, pc[r], nc);
             stage_mark(P, 5, false);
         }
