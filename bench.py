@@ -33,9 +33,9 @@ FLOP_PER_TRIPLE = 26     # per (l, m, ring pair) and direction: 2 recurrences (1
 # the kernel sources they were taken from (the SHA-256 of akra_kernels.hip followed by akra_fft.h is
 # checked at run time).
 TRAFFIC = {
-    # profiles/k_leg_adj_nside2048_lmax4096_fp64.md: FETCH 2.4826e6 KiB x 2.0 + WRITE 3.1590e6 KiB x 1.0
-    "leg_adj": {"bytes": 8.319e9, "workload": (2048, 4096),
-                "kernels_sha256": "bbcf67f3d7e98be0d9c1e97979fdaa8d5a648b346be901ce6d5f94a0667f681a"},
+    # profiles/k_leg_adj_nside2048_lmax4096_fp64.md: FETCH 2.4792e6 KiB x 2.0 + WRITE 3.1590e6 KiB x 1.0
+    "leg_adj": {"bytes": 8.312e9, "workload": (2048, 4096),
+                "kernels_sha256": "3e39f41e4baf0d4cb4f076633c23fd7b37590e0ed13fe87e552451f22797c0d3"},
 }
 
 

@@ -280,6 +280,11 @@ void launch_cg_alpha_sum(Plan &P, const double *red, double *scal, int *flag);
 void launch_cg_xr_rr(Plan &P, double *x, double *r, const double *p, const double *w, const double *alpha_dev,
                      int64_t n_complex, double *rr_red);
 void launch_cg_beta_sum(Plan &P, const double *red, double *scal, double precond);
+// the same iteration in two vector kernels for one right-hand side (scal[7] holds rz between them)
+void launch_cg_xr_alpha(Plan &P, double *x, double *r, const double *p, const double *w, const double *red_pw,
+                        double *scal, int *flag, int64_t n_complex, double *rr_red);
+void launch_cg_p_beta(Plan &P, double *p, const double *r, const double *red_rr, double *scal, double precond,
+                      int64_t n_complex);
 void launch_axpby(Plan &P, double *y, double a, const double *x, double b, int64_t n_complex);
 void launch_scalar_div(Plan &P, double *out, const double *num, const double *den);
 // shape-noise realisations and spectra (akra_spectra.hip)

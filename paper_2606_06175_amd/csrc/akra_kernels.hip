@@ -1632,6 +1632,72 @@ __global__ __launch_bounds__(256) void k_cg_alpha_sum(const double *__restrict__
     }
 }
 
+// Single-right-hand-side iteration with the scalar steps inside the vector kernels: every
+// workgroup sums the same partials in the same fixed order, so all hold the same alpha (beta), and
+// workgroup 0 records the scalars.  The x/r update reads rz at scal[0] and keeps it at scal[7] for
+// the p update, which then owns scal[0].
+__global__ __launch_bounds__(256) void k_cg_xr_alpha(double2 *__restrict__ x, double2 *__restrict__ r,
+                                                     const double2 *__restrict__ p, const double2 *__restrict__ w,
+                                                     const double *__restrict__ red_pw, int n_pw,
+                                                     double *__restrict__ scal, int *__restrict__ flag, int64_t nc,
+                                                     int64_t nalm, int lmax, double *__restrict__ rr_red)
+{
+    __shared__ double sh[256];
+    const double pw = sum_partials256(red_pw, n_pw, sh);
+    __syncthreads();
+    const double rz = scal[0];
+    const bool bad = flag[0] != 0 || !(pw > 0.0) || !isfinite(pw);
+    const double a = bad ? 0.0 : rz / pw;
+    double s = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nc; i += (int64_t)gridDim.x * blockDim.x) {
+        const double2 pi = p[i], wi = w[i];
+        double2 xi = x[i], ri = r[i];
+        xi.x = fma(a, pi.x, xi.x);
+        xi.y = fma(a, pi.y, xi.y);
+        ri.x = fma(-a, wi.x, ri.x);
+        ri.y = fma(-a, wi.y, ri.y);
+        x[i] = xi;
+        r[i] = ri;
+        const double wgt = ((i % nalm) <= lmax) ? 1.0 : 2.0;
+        s += wgt * (ri.x * ri.x + ri.y * ri.y);
+    }
+    const double t = block_sum256(s, sh);
+    if (threadIdx.x == 0) {
+        rr_red[blockIdx.x] = t;
+        if (blockIdx.x == 0) {
+            scal[1] = pw;
+            scal[2] = a;
+            scal[7] = rz;
+            if (bad) flag[0] = 1;
+        }
+    }
+}
+
+// p = P r + beta p with beta = P <r, r> / rz (rz from scal[7]); workgroup 0 records <r, r> at scal[3],
+// beta at scal[4] and the new rz = P <r, r> at scal[0]
+__global__ __launch_bounds__(256) void k_cg_p_beta(double2 *__restrict__ p, const double2 *__restrict__ r,
+                                                   const double *__restrict__ red_rr, int n_rr,
+                                                   double *__restrict__ scal, double pc, int64_t nc)
+{
+    __shared__ double sh[256];
+    const double rr = sum_partials256(red_rr, n_rr, sh);
+    const double rz_old = scal[7];
+    const double rz = pc * rr;
+    const double bt = (rz_old > 0.0) ? rz / rz_old : 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nc; i += (int64_t)gridDim.x * blockDim.x) {
+        const double2 ri = r[i];
+        double2 pi = p[i];
+        pi.x = fma(bt, pi.x, pc * ri.x);
+        pi.y = fma(bt, pi.y, pc * ri.y);
+        p[i] = pi;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        scal[3] = rr;
+        scal[4] = bt;
+        scal[0] = rz;
+    }
+}
+
 // scal[3] = <r, r> from the update's partials, then beta = P <r, r> / rz into scal[4], rz <- P <r, r>
 __global__ __launch_bounds__(256) void k_cg_beta_sum(const double *__restrict__ red, int n, double *__restrict__ scal,
                                                      double pc)
@@ -2194,6 +2260,21 @@ void launch_cg_xr_rr(Plan &P, double *x, double *r, const double *p, const doubl
     k_cg_xr_rr<<<cg_red_blocks(P), 256, 0, P.stream>>>((double2 *)x, (double2 *)r, (const double2 *)p,
                                                        (const double2 *)w, alpha_dev, n_complex, P.nalm, P.lmax,
                                                        rr_red);
+}
+
+void launch_cg_xr_alpha(Plan &P, double *x, double *r, const double *p, const double *w, const double *red_pw,
+                        double *scal, int *flag, int64_t n_complex, double *rr_red)
+{
+    const int nb = cg_red_blocks(P);
+    k_cg_xr_alpha<<<nb, 256, 0, P.stream>>>((double2 *)x, (double2 *)r, (const double2 *)p, (const double2 *)w, red_pw,
+                                            nb, scal, flag, n_complex, P.nalm, P.lmax, rr_red);
+}
+
+void launch_cg_p_beta(Plan &P, double *p, const double *r, const double *red_rr, double *scal, double precond,
+                      int64_t n_complex)
+{
+    const int nb = cg_red_blocks(P);
+    k_cg_p_beta<<<nb, 256, 0, P.stream>>>((double2 *)p, (const double2 *)r, red_rr, nb, scal, precond, n_complex);
 }
 
 void launch_cg_beta_sum(Plan &P, const double *red, double *scal, double precond)

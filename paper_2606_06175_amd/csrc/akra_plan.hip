@@ -793,8 +793,9 @@ static akra_status cg_begin(Plan &P, bool use_x0)
 //   w = H p, alpha = rz / <p, w>, x += alpha p, r -= alpha w, rr = <r, r>,
 //   beta = P rr / rz, p = P r + beta p.
 // The inner products ride on the kernels that already stream the vectors: the epilogue forms the
-// partials of <p, w> as it writes w, the x/r update those of <r, r> as it writes r; the alpha and
-// beta kernels sum them in a fixed order.
+// partials of <p, w> as it writes w, the x/r update those of <r, r> as it writes r; each workgroup
+// of the x/r update (of the p update) sums the <p, w> (<r, r>) partials in the same fixed order and
+// forms alpha (beta) itself.
 static akra_status cg_iterate(Plan &P, bool fp32)
 {
     const int64_t nc = 2 * P.nalm;
@@ -804,10 +805,8 @@ static akra_status cg_iterate(Plan &P, bool fp32)
         apply_H_timed(P, fp32, P.cg_kern, P.cg_lam, p, p + 2 * P.nalm, w, w + 2 * P.nalm, P.cg_rhs, red_pw);
     if (st) return st;
     stage_mark(P, 5, true);
-    launch_cg_alpha_sum(P, red_pw, P.d_scal, P.d_flag);
-    launch_cg_xr_rr(P, x, r, p, w, P.d_scal + 2, nc, red_rr);
-    launch_cg_beta_sum(P, red_rr, P.d_scal, P.cg_pc);
-    launch_cg_p(P, p, r, P.d_scal + 4, P.cg_pc, nc);
+    launch_cg_xr_alpha(P, x, r, p, w, red_pw, P.d_scal, P.d_flag, nc, red_rr);
+    launch_cg_p_beta(P, p, r, red_rr, P.d_scal, P.cg_pc, nc);
     stage_mark(P, 5, false);
     P.cg_iters++;
     return check_launch("cg_step");
