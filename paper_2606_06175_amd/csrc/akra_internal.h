@@ -268,12 +268,10 @@ void launch_weights(Plan &P, const double *ninv, const uint8_t *mask, int nrhs, 
 
 // full-m dot products and CG vector updates on [2][nalm] complex FP64 vectors
 void launch_dot(Plan &P, const double *a, const double *b, double *out_dev, int64_t n_complex);
-void launch_cg_xr(Plan &P, double *x, double *r, const double *p, const double *w, const double *alpha_dev,
-                  int64_t n_complex);
 void launch_cg_p(Plan &P, double *p, const double *r, const double *beta_dev, double precond, int64_t n_complex);
 // The PCG iteration's fused scalar path: at most CG_RED_BLOCKS workgroup partials per inner
 // product (the epilogue's <p, w>, the update's <r, r>), summed in a fixed order by the kernels that
-// form alpha and beta (scalars at scal[0..4] as in k_cg_alpha / k_cg_beta)
+// form alpha and beta (scal[0] rz, [1] <p, w>, [2] alpha, [3] <r, r>, [4] beta)
 constexpr int CG_RED_BLOCKS = 1024;
 int cg_red_blocks(const Plan &P);
 void launch_cg_alpha_sum(Plan &P, const double *red, double *scal, int *flag);

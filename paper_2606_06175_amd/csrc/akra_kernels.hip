@@ -1570,16 +1570,6 @@ __global__ __launch_bounds__(256) void k_sum_part(const double *__restrict__ red
     }
 }
 
-__global__ void k_cg_xr(double *__restrict__ x, double *__restrict__ r, const double *__restrict__ p,
-                        const double *__restrict__ w, const double *__restrict__ alpha, int64_t n2)
-{
-    const double a = *alpha;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += (int64_t)gridDim.x * blockDim.x) {
-        x[i] = fma(a, p[i], x[i]);
-        r[i] = fma(-a, w[i], r[i]);
-    }
-}
-
 // x += alpha p, r -= alpha w on complex elements (re, im pairs), with the workgroup partials of the
 // full-m <r, r> of the updated r
 __global__ __launch_bounds__(256) void k_cg_xr_rr(double2 *__restrict__ x, double2 *__restrict__ r,
@@ -2404,12 +2394,6 @@ void launch_dot(Plan &P, const double *a, const double *b, double *out_dev, int6
 {
     k_dot_part<<<RED_BLOCKS, 256, 0, P.stream>>>(a, b, n_complex, P.nalm, P.lmax, P.d_red);
     k_sum_part<<<1, 256, 0, P.stream>>>(P.d_red, RED_BLOCKS, 1, 1, out_dev);
-}
-
-void launch_cg_xr(Plan &P, double *x, double *r, const double *p, const double *w, const double *alpha_dev,
-                  int64_t n_complex)
-{
-    k_cg_xr<<<1024, 256, 0, P.stream>>>(x, r, p, w, alpha_dev, 2 * n_complex);
 }
 
 void launch_cg_p(Plan &P, double *p, const double *r, const double *beta_dev, double precond, int64_t n_complex)

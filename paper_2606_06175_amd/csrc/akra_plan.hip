@@ -617,20 +617,6 @@ static double read_scalar(Plan &P, const double *dev, hipError_t *err)
     return P.h_pin[0];
 }
 
-__global__ void k_cg_alpha(double *scal, int *flag)
-{
-    // scal[0] = rz, scal[1] = pw -> scal[2] = alpha; breakdown when p^T H p <= 0.  The flag is
-    // sticky: once set, later iterations take alpha = 0 and x stays the last good iterate until the
-    // host reads the flag
-    const double pw = scal[1];
-    if (flag[0] || !(pw > 0.0) || !isfinite(pw)) {
-        flag[0] = 1;
-        scal[2] = 0.0;
-    } else {
-        scal[2] = scal[0] / pw;
-    }
-}
-
 __global__ void k_cg_beta(double *scal, double pc)
 {
     // scal[3] = <r, r> (new), scal[0] = rz (old) -> scal[4] = beta, scal[0] = P <r, r>
