@@ -451,7 +451,7 @@ def main():
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         if int(os.environ.get("RANK", "0")) == 0:
-            print("bench.py: this build runs on exactly one GPU (the operator shards by m and by ring "
+            print("bench.py: the benchmark runs on exactly one GPU (the operator shards by m and by ring "
                   "across GPUs only in design); run with --gpus 1", flush=True)
         sys.exit(2)
 
