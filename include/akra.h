@@ -229,10 +229,11 @@ akra_status akra_cg_state(akra_plan plan, double *rel_resid, int *iters, double 
 
 /*
  * Graph replay of the PCG iteration (Sec. II.B inversion problem; the loop of akra_cg_step and of the
- * single-right-hand-side solves of akra_cg_solve): when on (the default), the plan records the kernel
- * launches of one iteration once as a HIP graph, on a private capture stream of default priority, and
- * replays it on the plan stream; it records again when lambda_eff, the preconditioner, the K_l table,
- * the precision, the right-hand side, the E/B unknowns or the Legendre launch shapes change.  Results
+ * solves of akra_cg_solve, single-right-hand-side and batched lockstep): when on (the default), the
+ * plan records the kernel launches of one iteration once as a HIP graph, on a private capture stream
+ * of default priority, and replays it on the plan stream; it records again when lambda_eff, the
+ * preconditioner, the K_l table, the precision, the right-hand side, the E/B unknowns, the Legendre
+ * launch shapes or (batched) the set of right-hand sides still iterating change.  Results
  * are bit-identical to direct launches.  Stage timing (akra_plan_set_timing) always launches directly.
  * akra_plan_set_graph synchronises the plan stream; off releases the recorded graph.
  */

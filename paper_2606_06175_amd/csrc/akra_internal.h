@@ -180,6 +180,9 @@ struct Plan {
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t cg_graph = nullptr;
     double cg_graph_key[12] = {};
+    // the lockstep iteration of the batched solve, keyed by its by-value arguments and active set
+    hipGraphExec_t cg_graph_b = nullptr;
+    std::vector<double> cg_graph_b_key;
 
     // stage timing with HIP events on the plan stream
     bool timing = false;

@@ -256,6 +256,7 @@ static void free_plan(Plan *P)
         (void)hipEventDestroy(e[1]);
     }
     if (P->cg_graph) (void)hipGraphExecDestroy(P->cg_graph);
+    if (P->cg_graph_b) (void)hipGraphExecDestroy(P->cg_graph_b);
     if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
     delete P;
 }
@@ -813,35 +814,46 @@ static void drop_graph(Plan &P)
 {
     if (P.cg_graph) (void)hipGraphExecDestroy(P.cg_graph);
     P.cg_graph = nullptr;
+    if (P.cg_graph_b) (void)hipGraphExecDestroy(P.cg_graph_b);
+    P.cg_graph_b = nullptr;
+    P.cg_graph_b_key.clear();
 }
 
-// Records one cg_iterate into a graph: the launches go to the private capture stream (the plan
-// stream may be the legacy default stream, which cannot be captured).  Nothing executes here.
-static akra_status record_iteration(Plan &P, bool fp32)
+// Records the launches of fn() into exec: they go to the private capture stream (the plan stream
+// may be the legacy default stream, which cannot be captured).  Nothing executes here.
+template <class Fn> static akra_status record_graph(Plan &P, hipGraphExec_t &exec, Fn &&fn)
 {
-    drop_graph(P);
+    if (exec) (void)hipGraphExecDestroy(exec);
+    exec = nullptr;
     if (!P.cap_stream) AK_HIP(hipStreamCreateWithFlags(&P.cap_stream, hipStreamNonBlocking), "hipStreamCreate");
     AK_HIP(hipGetLastError(), "launch");
     const hipStream_t s = P.stream;
-    const int iters = P.cg_iters;
     AK_HIP(hipStreamBeginCapture(P.cap_stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
     P.stream = P.cap_stream;
     P.capturing = true;
-    akra_status st = cg_iterate(P, fp32);
+    akra_status st = fn();
     P.capturing = false;
     P.stream = s;
-    P.cg_iters = iters;
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(P.cap_stream, &g);
     if (st == AKRA_OK && e != hipSuccess) st = hip_fail(e, "hipStreamEndCapture");
     if (st == AKRA_OK) {
-        e = hipGraphInstantiate(&P.cg_graph, g, nullptr, nullptr, 0);
+        e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
         if (e != hipSuccess) {
-            P.cg_graph = nullptr;
+            exec = nullptr;
             st = hip_fail(e, "hipGraphInstantiate");
         }
     }
     if (g) (void)hipGraphDestroy(g);
+    return st;
+}
+
+// Records one cg_iterate (the iteration count is not advanced by the recording)
+static akra_status record_iteration(Plan &P, bool fp32)
+{
+    const int iters = P.cg_iters;
+    akra_status st = record_graph(P, P.cg_graph, [&]() { return cg_iterate(P, fp32); });
+    P.cg_iters = iters;
     if (st == AKRA_OK) iter_key(P, fp32, P.cg_graph_key);
     return st;
 }
@@ -1317,23 +1329,52 @@ static akra_status solve_batched(Plan &P, const double *g1, const double *g2, co
         bool any = false;
         for (int r = 0; r < nr; ++r) any |= active[r] != 0;
         if (!any || iters >= o.maxiter) break;
-        st = apply_H_batched(P, kd, le.data(), 0.0, P.d_p, P.d_p + 2 * na, P.d_w, P.d_w + 2 * na, 2 * na,
-                             P.d_red_cg);
-        if (st) return st;
-        for (int r = 0; r < nr; ++r) {
-            if (!active[r]) continue;
-            // the epilogue left the partials of <p, w>; the update leaves those of <r, r>
-            double *red_pw = P.d_red_cg + (int64_t)r * 2 * CG_RED_BLOCKS, *red_rr = red_pw + CG_RED_BLOCKS;
-            stage_mark(P, 5, true);
-            launch_cg_alpha_sum(P, red_pw, S(r), P.d_flag + r);
-            launch_cg_xr_rr(P, V(P.d_x, r), V(P.d_r, r), V(P.d_p, r), V(P.d_w, r), S(r) + 2, nc, red_rr);
-            launch_cg_beta_sum(P, red_rr, S(r), pc[r]);
-            launch_cg_p(P, V(P.d_p, r), V(P.d_r, r), S(r) + 4, pc[r], nc);
-            stage_mark(P, 5, false);
+        // one lockstep iteration: the batched apply, then the updates of the active right-hand sides
+        auto iterate = [&]() -> akra_status {
+            akra_status s2 = apply_H_batched(P, kd, le.data(), 0.0, P.d_p, P.d_p + 2 * na, P.d_w, P.d_w + 2 * na,
+                                             2 * na, P.d_red_cg);
+            if (s2) return s2;
+            for (int r = 0; r < nr; ++r) {
+                if (!active[r]) continue;
+                // the epilogue left the partials of <p, w>; the update leaves those of <r, r>
+                double *red_pw = P.d_red_cg + (int64_t)r * 2 * CG_RED_BLOCKS, *red_rr = red_pw + CG_RED_BLOCKS;
+                stage_mark(P, 5, true);
+                launch_cg_alpha_sum(P, red_pw, S(r), P.d_flag + r);
+                launch_cg_xr_rr(P, V(P.d_x, r), V(P.d_r, r), V(P.d_p, r), V(P.d_w, r), S(r) + 2, nc, red_rr);
+                launch_cg_beta_sum(P, red_rr, S(r), pc[r]);
+                launch_cg_p(P, V(P.d_p, r), V(P.d_r, r), S(r) + 4, pc[r], nc);
+                stage_mark(P, 5, false);
+            }
+            return check_launch("cg_batched");
+        };
+        if (P.timing || !P.use_graph) {
+            st = iterate();
+        } else {
+            // replay of the recorded iteration; recorded again when a by-value argument or the active
+            // set has changed
+            std::vector<double> key;
+            key.reserve(9 + 3 * (size_t)nr);
+            key.push_back((double)(uintptr_t)kd);
+            key.push_back((double)P.proj);
+            key.push_back((double)nr);
+            for (int v : {P.syn_V, P.syn_R, P.adj_R, P.adj_W, P.adj_L, P.adj_nrb}) key.push_back((double)v);
+            for (int r = 0; r < nr; ++r) {
+                key.push_back(le[r]);
+                key.push_back(pc[r]);
+                key.push_back((double)active[r]);
+            }
+            st = AKRA_OK;
+            if (!P.cg_graph_b || key != P.cg_graph_b_key) {
+                st = record_graph(P, P.cg_graph_b, iterate);
+                if (st == AKRA_OK) P.cg_graph_b_key = key;
+            }
+            if (st == AKRA_OK) {
+                TraceRange tr("akra.cg_batched_iteration_graph");
+                AK_HIP(hipGraphLaunch(P.cg_graph_b, P.stream), "hipGraphLaunch");
+            }
         }
-        ++iters;
-        st = check_launch("cg_batched");
         if (st) return st;
+        ++iters;
         st = pull();
         if (st) return st;
         for (int r = 0; r < nr; ++r) {

@@ -2,7 +2,8 @@
 through the C ABI: the iterates, residuals and iteration counts of a plan that replays its recorded
 iteration equal, bit for bit, those of a plan that launches the same kernels directly.  Every replay
 is checked on its own, with unrelated torch work and host synchronisations between replays; the
-recording is renewed when the launch shapes, lambda_eff or the unknowns change.
+recording is renewed when the launch shapes, lambda_eff or the unknowns change; the lockstep iteration
+of a batched FP32 plan likewise, renewed whenever its set of active right-hand sides changes.
 
 Inputs: the C1 workload (HEALPix Nside 32, lmax 64, one cap with f_sky 0.1, Poisson mean 5) and its
 seeded random maps; the C5 workload (Nside 256, lmax 512) for one FP32 check."""
@@ -152,3 +153,40 @@ def test_fp32_replays_at_nside_256():
         b.cg_step(2)
         _other_work()
         _same_state(a, b)
+
+
+@pytest.mark.parametrize("nrhs", [4, 9, 16])
+def test_batched_solve_replays_equal_direct_launches(nrhs):
+    # the lockstep iteration of an FP32 batch replayed from its recording; the right-hand sides have
+    # their own noise patterns (a uniform rescaling of N^-1 would leave the relative system
+    # unchanged), converge at different iterations, and every change of the active set renews the
+    # recording
+    import torch
+    from paper_2606_06175_amd import Plan
+    cfg, t = _inputs("C1")
+    print("batched plans C1 nrhs=%d" % nrhs, flush=True)
+    a = Plan(cfg["nside"], cfg["lmax"], nrhs=nrhs, precision="fp32", device="cuda:0")
+    b = Plan(cfg["nside"], cfg["lmax"], nrhs=nrhs, precision="fp32", device="cuda:0")
+    b.set_graph(False)
+    gen = np.random.default_rng(5)
+    npix = t[0].numel()
+    mod = [torch.from_numpy(gen.uniform(0.05, 1.0, npix) ** (2 * k)).to(t[2].device) for k in range(nrhs)]
+    g1 = torch.stack([t[0] * (1 + 0.3 * k) for k in range(nrhs)])
+    g2 = torch.stack([t[1] * (1 - 0.02 * k) for k in range(nrhs)])
+    ninv = torch.stack([t[2] * mod[k] for k in range(nrhs)])
+    for rep in range(2):
+        xa, ya, ia = a.cg_solve(g1, g2, ninv, t[3], tol=1e-8, maxiter=3000)
+        xb, yb, ib = b.cg_solve(g1, g2, ninv, t[3], tol=1e-8, maxiter=3000)
+        _other_work()
+        print("batched nrhs=%d: %d lockstep iterations" % (nrhs, ia["iters"]), flush=True)
+        assert ia["status"] == ib["status"] == 0 and ia["iters"] == ib["iters"]
+        assert ia["rel_resid_true"] == ib["rel_resid_true"]
+        assert bool((xa == xb).all()) and bool((ya == yb).all())
+    # the right-hand sides converge at different iterations (the active set changes mid-solve)
+    its = []
+    for k in (0, nrhs - 1):
+        s1 = Plan(cfg["nside"], cfg["lmax"], precision="fp64", device="cuda:0")
+        _, _, inf = s1.cg_solve(g1[k], g2[k], ninv[k], t[3], tol=1e-8, maxiter=3000)
+        its.append(inf["iters"])
+    print("single-RHS iterations of the first and last right-hand side: %s" % its, flush=True)
+    assert its[0] != its[1]
