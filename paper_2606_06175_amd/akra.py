@@ -280,7 +280,10 @@ class Plan:
     def cg_solve(self, g1, g2, ninv, mask, tol=1e-3, maxiter=1000, lam=1e-3, x0=None, kernel=None,
                  reliable_delta=0.1, hist_len=0, raise_not_converged=True, mode="joint", stall_iters=0, check_every=1):
         """Regularised ML estimate (kappa_E, kappa_B).  mode "joint" solves the full E/B system, "E"
-        the E block alone (kappa_B returned as zero), "B" the B block alone."""
+        the E block alone (kappa_B returned as zero), "B" the B block alone.  stall_iters > 0 stops
+        with AKRA_STAGNATED once the residual has reached no new minimum for that many tests;
+        check_every > 1 tests convergence every that many iterations (akra_cg_opts).  A solve
+        stopped by maxiter or stagnation raises unless raise_not_converged is False."""
         g1, g2 = self._map(g1, "g1"), self._map(g2, "g2")
         ninv = self._map(ninv, "ninv")
         mask = self._map(mask, "mask", torch.uint8, per_rhs=False)
@@ -608,7 +611,8 @@ class FlatPlan:
 
     def cg_solve(self, g1, g2, ninv, mask, tol=1e-3, maxiter=1000, lam=1e-3, x0=None, hist_len=0,
                  raise_not_converged=True, stall_iters=0, check_every=1):
-        """Regularised flat-sky estimate (kappa_E, kappa_B) by PCG (see akra_flat_cg_solve)."""
+        """Regularised flat-sky estimate (kappa_E, kappa_B) by PCG (see akra_flat_cg_solve);
+        stall_iters and check_every as for Plan.cg_solve."""
         g1, g2 = self._m(g1, "g1"), self._m(g2, "g2")
         ninv, mask = self._m(ninv, "ninv"), self._m(mask, "mask", torch.uint8)
         kE, kB = self._out(), self._out()
