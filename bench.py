@@ -25,6 +25,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "H·v applies/s + CG time-to-1e-8 at Nside 2048 ℓmax 4096, mixed/batched vs FP64"
 PEAK_FP64 = 78.6e12      # MI355X FP64 vector FMA, FLOP/s
+PEAK_FP32 = 157.3e12     # MI355X FP32 vector (packed) FMA, FLOP/s
 FLOP_PER_TRIPLE = 26     # per (l, m, ring pair) and direction: 2 recurrences (10) + 8 contraction FMAs (16)
 
 
@@ -94,6 +95,31 @@ def make_inputs(name, nside, lmax, dev):
     g2 = m * (g2 + torch.from_numpy(cfg["eps2"][0]).to(dev))
     torch.cuda.synchronize()
     return cfg, g1, g2, ninv, mask
+
+
+def fp32_roofline(plan32, g1, g2, ninv, mask, nside, lmax, steps=3):
+    """The FP32 operator's Legendre kernels (the mixed solve's iterations) against the FP32 peaks:
+    157.3 TFLOP/s is the packed-FP32 figure; the kernels issue plain FP32 VALU instructions, whose
+    rate is that of FP64 (78.6 TFLOP/s).  Stage times are HIP events over `steps` PCG steps; the
+    flop count is 26 per (l, m, ring-pair) triple the FP32 plan evaluates."""
+    import torch
+    plan32.cg_start(g1, g2, ninv, mask)
+    plan32.cg_step(1)
+    torch.cuda.synchronize()
+    plan32.set_timing(True)
+    plan32.stage_times()
+    plan32.cg_step(steps)
+    st = plan32.stage_times()
+    plan32.set_timing(False)
+    work = plan32.work()
+    out = {"unit": "TFLOP/s", "peak_packed_fp32": PEAK_FP32 / 1e12, "peak_plain_fp32_issue": PEAK_FP64 / 1e12,
+           "steps": steps}
+    for stage, key in (("leg_synth", "synth"), ("leg_adj", "adjoint")):
+        ms = st[stage][0] / max(st[stage][1], 1)
+        achieved = FLOP_PER_TRIPLE * work[key] / (ms * 1e-3)
+        out[stage] = {"ms": ms, "evaluated_triples": work[key], "achieved": achieved / 1e12,
+                      "frac_of_packed_peak": achieved / PEAK_FP32, "frac_of_plain_issue": achieved / PEAK_FP64}
+    return out
 
 
 def cpu_model():
@@ -565,6 +591,8 @@ def main():
                                      "rel_resid_true": info32["rel_resid_true"], "status": info32["status"],
                                      "rel_err_vs_fp64_solution": err}
         log("mixed solve: %s" % solves["mixed_fp32_fp64"])
+        out["roofline_fp32"] = fp32_roofline(plan32, g1, g2, ninv, mask, nside, lmax)
+        log("fp32 Legendre roofline: %s" % out["roofline_fp32"])
         plan32.close()
         out["time_to_1e-8"] = solves
         out["mixed_speedup_vs_fp64"] = solves["fp64"]["seconds"] / solves["mixed_fp32_fp64"]["seconds"]
