@@ -1,7 +1,7 @@
 """GPU parity at the benchmark size (HEALPix Nside 2048, lmax 4096), in the launch configuration the
 benchmark times (autotuned shapes): outputs the oracle can compute one by one (the synthesis on
 sampled rings, the adjoint for sampled m) and properties that hold at any size (symmetry of H,
-FP32 against FP64)."""
+FP32 against FP64, the recursive residual of the step-wise PCG against its true residual)."""
 import numpy as np
 import pytest
 
@@ -191,3 +191,40 @@ def test_noise_spectra_at_batched_workload_size():
     # both solutions meet the 1e-8 residual; their spectra agree far inside the realisation scatter
     assert np.sqrt(np.sum(w * (clb[0, 0] - direct) ** 2) / np.sum(w * direct ** 2)) < 1e-4
     pb.close()
+
+
+def test_stepwise_pcg_full_size(big):
+    # the step-wise PCG the benchmark times (recorded iteration replayed, fused inner products):
+    # after k steps the recursive residual equals the FP64 true residual ||b - H x_k|| / ||b||, and
+    # the replayed iterations equal direct launches bit for bit
+    torch, dev = big["torch"], big["dev"]
+    npix = 12 * NSIDE * NSIDE
+    mask = torch.from_numpy(wl.cap_mask(NSIDE, 2.0, 0.5, 0.1).astype(np.uint8)).to(dev)
+    ninv = torch.from_numpy(np.random.default_rng(4).uniform(5.0, 60.0, npix)).to(dev)
+    m = mask.to(torch.float64)
+    g1, g2 = (torch.from_numpy(a).to(dev) * m for a in wl.random_maps(npix, 14))
+    a, b = _plan("fp64"), _plan("fp64")
+    b.set_graph(False)
+    lam_eff = a.cg_solve(g1, g2, ninv, mask, maxiter=0, raise_not_converged=False)[2]["lambda_eff"]
+    for p in (a, b):
+        p.cg_start(g1, g2, ninv, mask)
+    k = 6
+    a.cg_step(k)
+    b.cg_step(k)
+    ra, ia, xa, ya = a.cg_state(copy_x=True)
+    rb, ib, xb, yb = b.cg_state(copy_x=True)
+    assert ia == ib == k and ra == rb
+    assert bool((xa == xb).all()) and bool((ya == yb).all())
+    bE, bB = a.rhs(g1, g2, ninv, mask)
+    hE, hB = a.apply_H(ninv, mask, xa, ya, lam_eff)
+    w = torch.full((bE.numel(),), 2.0, dtype=torch.float64, device=dev)
+    w[: LMAX + 1] = 1.0
+
+    def nrm(e, f):
+        return float(((w * (e.conj() * e).real).sum() + (w * (f.conj() * f).real).sum()).sqrt())
+
+    true_rel = nrm(bE - hE, bB - hB) / nrm(bE, bB)
+    print("after %d steps: recursive %.6e, true %.6e" % (k, ra, true_rel), flush=True)
+    assert ra < 0.5 and abs(ra - true_rel) < 1e-8 * max(true_rel, 1e-300) + 1e-12
+    a.close()
+    b.close()
