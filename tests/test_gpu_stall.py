@@ -3,6 +3,7 @@ iteration after which its relative residual has failed, stall_iters times in a r
 smallest earlier value (the start counts as the first value).  The stop is checked against that rule
 applied to the residual history the solve itself returns, on FP64 and mixed plans, the flat-sky
 solver and a batched FP32 plan; with the test off (the default) the same solves converge as before.
+Breakdown forced from the host (K_l = 0 and lambda = 0 make H = 0) in FP64, FP32 and batched plans.
 Also the convergence test every k iterations (opts.check_every): the tested residuals equal those of
 the solve testing every iteration, and the stop is the first tested iteration whose residual is
 below the tolerance.
@@ -165,3 +166,37 @@ def test_flat_check_every():
     tested = np.arange(3, i3["iters"] + 1, 3) - 1
     assert np.array_equal(i3["hist"][tested], ref["hist"][tested])
     assert i3["rel_resid_true"] <= 1e-6
+
+
+@pytest.mark.parametrize("prec,nrhs", [("fp64", 1), ("fp32", 1), ("fp32", 2)])
+def test_forced_breakdown(prec, nrhs):
+    # p^T H p = 0 forced from the host: a given right-hand side b != 0 with the harmonic kernel K_l = 0
+    # and lambda = 0 makes H = 0.  FP64 plans report AKRA_ERR_NUMERIC; FP32 plans restart with the
+    # FP64 operator, break down again and stop with AKRA_NOT_CONVERGED and a finite last iterate
+    # (x = 0: alpha is held at zero once the flag is up).  The same with convergence tested every 4
+    # iterations, where the sticky flag keeps x from moving between tests.
+    import torch
+    from paper_2606_06175_amd import Plan, akra
+    cfg, t = _c1()
+    lmax = cfg["lmax"]
+    print("plan C1 %s nrhs=%d, zero kernel" % (prec, nrhs), flush=True)
+    p = Plan(cfg["nside"], lmax, nrhs=nrhs, precision=prec, device="cuda:0")
+    bE = torch.stack([torch.from_numpy(wl.random_alm(lmax, 31 + k)).to(t[0].device) for k in range(nrhs)])
+    bB = torch.stack([torch.from_numpy(wl.random_alm(lmax, 41 + k)).to(t[0].device) for k in range(nrhs)])
+    ninv = torch.stack([t[2]] * nrhs) if nrhs > 1 else t[2]
+    if nrhs == 1:
+        bE, bB = bE[0], bB[0]
+    zero = np.zeros(lmax + 1)
+    for every in (1, 4):
+        if prec == "fp64":
+            with pytest.raises(akra.AkraError, match="NUMERIC"):
+                p.cg_solve_b(bE, bB, ninv, t[3], tol=1e-8, maxiter=50, lam=0.0, kernel=zero, check_every=every)
+            continue
+        xE, xB, info = p.cg_solve_b(bE, bB, ninv, t[3], tol=1e-8, maxiter=50, lam=0.0, kernel=zero,
+                                    raise_not_converged=False, check_every=every)
+        assert info["status"] == akra.AKRA_NOT_CONVERGED
+        assert float(xE.abs().max()) == 0.0 and float(xB.abs().max()) == 0.0
+    # the plan is usable afterwards: a regular solve converges
+    if nrhs == 1:
+        _, _, info = p.cg_solve(*t, tol=1e-8, maxiter=3000)
+        assert info["status"] == 0
