@@ -1,4 +1,4 @@
-// Complex arithmetic and in-place radix-4 FFTs in LDS for the ring stage and the flat-sky
+// Complex arithmetic and in-place radix-8 FFTs in LDS for the ring stage and the flat-sky
 // transforms (device code, gfx950).  Not part of the public ABI.
 #pragma once
 #include <hip/hip_runtime.h>

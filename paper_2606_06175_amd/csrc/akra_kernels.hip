@@ -1099,7 +1099,7 @@ __global__ void k_weights(const double *__restrict__ ninv, const uint8_t *__rest
 // Ring stage.  One workgroup per ring of N pixels.  Synthesis direction: fold F(m), |m| <= lmax,
 // into the N bins (phase e^{i m phi0}), inverse DFT -> gamma at the pixels.  Adjoint direction:
 // weight, forward DFT, unfold into every |m| <= lmax (phase e^{-i m phi0}) and multiply by the pixel
-// area.  Three kernels cover the rings: a radix-4 FFT of the whole ring in LDS when N is a power of
+// area.  Three kernels cover the rings: a radix-8 FFT of the whole ring in LDS when N is a power of
 // two, Bluestein's chirp-z over the whole ring when its convolution (a power-of-two length
 // M >= 2N - 1) fits in LDS, else two interleaved sub-transforms of length N / 2, each by Bluestein.
 // ================================================================================================
@@ -1154,8 +1154,9 @@ __device__ __forceinline__ void dft_forward(cplx<T> *buf, const cplx<T> *bhat, i
 // Ring stage for rings whose length N is a power of two (the equatorial belt when Nside is one):
 // the length-N transforms run directly in LDS, one workgroup of RF threads per ring.  F is folded
 // and G unfolded in m order, so neighbouring threads read and write neighbouring entries of the
-// ring's row; each direction is one radix-4 FFT (ceil(log2 N / 2) passes) with the inverse
-// transform taking natural input to bit-reversed output and the forward one back.
+// ring's row; each direction is one FFT of radix-8 passes (floor(log2 N / 3) of them, plus one
+// radix-2 or radix-4 step for the remainder), both directions taking natural input to bit-reversed
+// output.
 // MODE as above.
 // ================================================================================================
 constexpr int RF = 1024;  // threads per ring workgroup
