@@ -266,18 +266,7 @@ __global__ __launch_bounds__(256) void k_fweights(const double *__restrict__ nin
     }
 }
 
-// scalars s: [0] rz, [1] <p, w>, [2] alpha, [3] <r, r>, [4] beta
-__global__ void k_fcg_alpha(double *s, int *flag)
-{
-    // breakdown when p^T H p <= 0; the flag is sticky (alpha = 0 until the host reads it)
-    const double pw = s[1];
-    if (flag[0] || !(pw > 0.0) || !isfinite(pw)) {
-        flag[0] = 1;
-        s[2] = 0.0;
-    } else {
-        s[2] = s[0] / pw;
-    }
-}
+// scalars s: [0] rz, [1] <p, w>, [2] alpha, [3] <r, r>, [4] beta, [7] rz of the iteration in progress
 
 __global__ void k_fcg_beta(double *s, double pc)
 {
@@ -286,12 +275,18 @@ __global__ void k_fcg_beta(double *s, double pc)
     s[0] = rz;
 }
 
-// r -= alpha w, with per-block partials of <r, r>
-__global__ __launch_bounds__(256) void k_fcg_r(double2 *__restrict__ r, const double2 *__restrict__ w,
-                                               const double *__restrict__ s, int64_t n, double *__restrict__ part)
+// r -= alpha w, with per-block partials of <r, r>.  Every workgroup forms alpha = rz / <p, w> itself;
+// breakdown (p^T H p <= 0 or non-finite) gives alpha = 0 and raises the flag, which is sticky (alpha
+// stays 0 until the host reads it).  Workgroup 0 records alpha, keeps rz at s[7] for the p update
+// and raises the flag.
+__global__ __launch_bounds__(256) void k_fcg_r_alpha(double2 *__restrict__ r, const double2 *__restrict__ w,
+                                                     double *__restrict__ s, int *__restrict__ flag, int64_t n,
+                                                     double *__restrict__ part)
 {
     __shared__ double sh[256];
-    const double al = s[2];
+    const double pw = s[1], rz = s[0];
+    const bool bad = flag[0] != 0 || !(pw > 0.0) || !isfinite(pw);
+    const double al = bad ? 0.0 : rz / pw;
     double acc = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
         const double2 wv = w[i];
@@ -302,14 +297,36 @@ __global__ __launch_bounds__(256) void k_fcg_r(double2 *__restrict__ r, const do
         acc += rv.x * rv.x + rv.y * rv.y;
     }
     acc = block_sum256(acc, sh);
-    if (threadIdx.x == 0) part[blockIdx.x] = acc;
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = acc;
+        if (blockIdx.x == 0) {
+            s[2] = al;
+            s[7] = rz;
+            if (bad) flag[0] = 1;
+        }
+    }
 }
 
-// x += alpha p, then p = P r + beta p, in one pass
-__global__ void k_fcg_px(double2 *__restrict__ x, double2 *__restrict__ p, const double2 *__restrict__ r,
-                         const double *__restrict__ s, double pc, int64_t n)
+// <r, r> from the np partials (every workgroup, in the order of k_fsum), beta = P <r, r> / rz with rz
+// from s[7], then x += alpha p and p = P r + beta p in one pass; workgroup 0 records <r, r>, beta and
+// the new rz = P <r, r>
+__global__ __launch_bounds__(256) void k_fcg_px_beta(double2 *__restrict__ x, double2 *__restrict__ p,
+                                                     const double2 *__restrict__ r, const double *__restrict__ part,
+                                                     int np, double *__restrict__ s, double pc, int64_t n)
 {
-    const double al = s[2], be = s[4];
+    __shared__ double sh[256];
+    double t = 0.0;
+    for (int b = threadIdx.x; b < np; b += 256) t += part[b];
+    const double rr = block_sum256(t, sh);
+    const double rzn = pc * rr;
+    const double rz_old = s[7];
+    const double be = rz_old > 0.0 ? rzn / rz_old : 0.0;
+    const double al = s[2];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        s[3] = rr;
+        s[4] = be;
+        s[0] = rzn;
+    }
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const double2 pv = p[i], rv = r[i];
         double2 xv = x[i];
@@ -444,11 +461,8 @@ static void cg_iteration(FlatPlan &F, double lam, double pc)
     double *s = F.d_scal;
     const int vg = vgrid(F.n);
     apply_H(F, F.d_p, F.d_w, lam, s + 1);
-    k_fcg_alpha<<<1, 1, 0, F.stream>>>(s, F.d_flag);
-    k_fcg_r<<<FL_RED, 256, 0, F.stream>>>(F.d_r, F.d_w, s, F.n, F.d_red);
-    k_fsum<<<1, 256, 0, F.stream>>>(F.d_red, FL_RED, 1, s + 3);
-    k_fcg_beta<<<1, 1, 0, F.stream>>>(s, pc);
-    k_fcg_px<<<vg, 256, 0, F.stream>>>(F.d_x, F.d_p, F.d_r, s, pc, F.n);
+    k_fcg_r_alpha<<<FL_RED, 256, 0, F.stream>>>(F.d_r, F.d_w, s, F.d_flag, F.n, F.d_red);
+    k_fcg_px_beta<<<vg, 256, 0, F.stream>>>(F.d_x, F.d_p, F.d_r, F.d_red, FL_RED, s, pc, F.n);
 }
 
 static void fdot(FlatPlan &F, const double2 *a, const double2 *b, double *out)
