@@ -210,3 +210,43 @@ def test_batched_fp32_solve(c1, nr):
         worst = max(worst, rt)
         assert rt <= 1.05e-8, (k, rt)
     assert abs(worst - info["rel_resid_true"]) <= 1e-11
+
+
+def test_lambda_eff_and_precond_hand_worked():
+    # the solver's lambda_eff and P against the hand-worked values of tests/golden/regulariser.json
+    # (Sec. II.B, eq. ML_estimator_reg and eq. precond): HEALPix Nside 1 and a 4 x 4 flat field
+    import json
+    import os
+    import torch
+    from paper_2606_06175_amd import FlatPlan
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "regulariser.json")))
+    dev = torch.device("cuda", 0)
+    g = gold["sphere_nside1"]
+    ninv = torch.tensor(g["ninv"], dtype=torch.float64, device=dev)
+    mask = torch.tensor(g["mask"], dtype=torch.uint8, device=dev)
+    g1, g2 = (torch.from_numpy(a).to(dev) for a in wl.random_maps(12, 5))
+    p = _plan(1, 2, "fp64")
+    for c in g["cases"]:
+        _, _, info = p.cg_solve(g1, g2, ninv, mask, tol=1e-12, maxiter=200, lam=c["lambda"],
+                                raise_not_converged=False)
+        lam, P = c["lambda_eff"][0] / c["lambda_eff"][1], c["P"][0] / c["P"][1]
+        print("sphere lambda %g: lambda_eff %.17g (%.17g) P %.17g (%.17g)"
+              % (c["lambda"], info["lambda_eff"], lam, info["precond"], P), flush=True)
+        assert abs(info["lambda_eff"] - lam) <= 1e-15 * lam
+        assert abs(info["precond"] - P) <= 1e-15 * P
+    p.close()
+    g = gold["flat_4x4"]
+    ninv = torch.tensor(g["ninv"], dtype=torch.float64, device=dev)
+    mask = torch.tensor(g["mask"], dtype=torch.uint8, device=dev)
+    rng = np.random.default_rng(6)
+    g1, g2 = (torch.from_numpy(rng.normal(size=(4, 4))).to(dev) for _ in range(2))
+    fp = FlatPlan(4, 4, device=dev)
+    for c in g["cases"]:
+        _, _, info = fp.cg_solve(g1, g2, ninv, mask, tol=1e-12, maxiter=200, lam=c["lambda"],
+                                 raise_not_converged=False)
+        lam, P = c["lambda_eff"][0] / c["lambda_eff"][1], c["P"][0] / c["P"][1]
+        print("flat lambda %g: lambda_eff %.17g (%.17g) P %.17g (%.17g)"
+              % (c["lambda"], info["lambda_eff"], lam, info["precond"], P), flush=True)
+        assert abs(info["lambda_eff"] - lam) <= 1e-15 * lam
+        assert abs(info["precond"] - P) <= 1e-15 * P
+    fp.close()
