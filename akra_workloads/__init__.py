@@ -31,8 +31,9 @@ CONFIGS = {
     "C3": dict(nside=2048, lmax=4096, mask="footprint", fsky=0.1, mu=2.0, amp=[1e-7], nrhs=1, holes=2000,
                depth=True),
     # batched: 4 tomographic bins x (1 signal + 3 noise realisations) = 16 RHS, shared footprint
+    # (the noise right-hand sides rotate the galaxy ellipticities, see make_config)
     "C4": dict(nside=1024, lmax=2048, mask="footprint", fsky=0.1, mu=15.34, amp=[0.5e-7, 1e-7, 1.5e-7, 2e-7],
-               nrhs=16, holes=2000),
+               nrhs=16, holes=2000, rotate=True),
     # differentiable solve
     "C5": dict(nside=256, lmax=512, mask="footprint", fsky=0.1, mu=5.0, amp=[1e-7], nrhs=1, holes=200),
 }
@@ -203,8 +204,18 @@ def make_config(name, nside=None, lmax=None):
 
     Returns dict with: nside, lmax, nrhs, mask (uint8, Npix), ninv (float64, (nrhs_bins, Npix)),
     kappa (complex128, (nrhs, nalm)) -- E-mode convergence coefficients, B = 0 --,
-    eps1/eps2 (float64, (nrhs, Npix)) -- shape noise, zero outside the mask --, and bin (int per RHS).
-    The observed shear is gamma_obs = M (Y(K kappa) + eps); callers apply Y and K themselves."""
+    eps1/eps2 (float64, (nrhs, Npix)) -- shape noise, zero outside the mask --, bin (int per RHS),
+    and rot1/rot2 (float64, (nrhs, Npix), or None when no right-hand side is rotated).
+    The observed shear is gamma_obs = M (eps + R Y(K kappa)) with the complex per-pixel factor
+    R = rot1 + i rot2 multiplying gamma = gamma_1 + i gamma_2 (R = 1 without rotation); callers
+    apply Y and K themselves.
+
+    Configurations with rotate=True (the batched workload) simulate galaxies: pixel p of bin b holds
+    n_p galaxies with ellipticity e_j = e_int,j + gamma(p), e_int ~ N(0, sigma_e^2) per component.
+    The first right-hand side of a bin is the per-pixel mean of e_j as observed; each further one is
+    a shape-noise realisation, the mean of e_j exp(2 i psi_j) with psi_j ~ U[0, pi) drawn afresh, so
+    that eps is the mean of the rotated e_int and R the mean of exp(2 i psi_j) (Sec. III.B
+    pixelisation; Sec. IV noise realisations)."""
     p = dict(CONFIGS[name])
     c = _CFG_NUM[name]
     nside = int(nside or p["nside"])
@@ -226,18 +237,59 @@ def make_config(name, nside=None, lmax=None):
     ninv = counts / SIGMA_E ** 2
     gk = rng(c, S_KAPPA)
     kap = [gaussian_alm(lmax, cl_kappa(lmax, a), gk) for a in p["amp"]]
-    gn = rng(c, S_NOISE)
     per_bin = nrhs // nb
-    kappa, e1, e2, bins = [], [], [], []
-    for k in range(nrhs):
-        b = k // per_bin
-        sd = np.where(counts[b] > 0, SIGMA_E / np.sqrt(np.maximum(counts[b], 1)), 0.0)
-        kappa.append(kap[b])
-        e1.append(sd * gn.normal(size=npix) * mask)
-        e2.append(sd * gn.normal(size=npix) * mask)
-        bins.append(b)
+    kappa = np.stack([kap[k // per_bin] for k in range(nrhs)])
+    bins = np.array([k // per_bin for k in range(nrhs)])
+    if p.get("rotate"):
+        e1, e2, r1, r2 = rotated_noise(counts, mask, per_bin, rng(c, S_ROT))
+    else:
+        gn = rng(c, S_NOISE)
+        e1, e2 = [], []
+        for k in range(nrhs):
+            b = k // per_bin
+            sd = np.where(counts[b] > 0, SIGMA_E / np.sqrt(np.maximum(counts[b], 1)), 0.0)
+            e1.append(sd * gn.normal(size=npix) * mask)
+            e2.append(sd * gn.normal(size=npix) * mask)
+        e1, e2, r1, r2 = np.stack(e1), np.stack(e2), None, None
     return dict(name=name, nside=nside, lmax=lmax, nrhs=nrhs, mask=mask.astype(np.uint8), ninv=ninv,
-                kappa=np.stack(kappa), eps1=np.stack(e1), eps2=np.stack(e2), bin=np.array(bins))
+                kappa=kappa, eps1=e1, eps2=e2, rot1=r1, rot2=r2, bin=bins)
+
+
+def rotated_noise(counts, mask, per_bin, g):
+    """Galaxy-level shape noise with random rotations (see make_config).
+
+    counts (nbins, Npix): galaxies per pixel of each bin; only unmasked pixels are populated.  For
+    each bin, right-hand side 0 is the per-pixel mean of e_int (the galaxies as observed) with
+    R = 1; right-hand sides 1 .. per_bin-1 are the means of e_int exp(2 i psi) and R = the mean of
+    exp(2 i psi), psi ~ U[0, pi) per galaxy and realisation.  Returns eps1, eps2, rot1, rot2, each
+    (nbins * per_bin, Npix), zero outside the mask."""
+    nb, npix = counts.shape
+    idx = np.flatnonzero(mask)
+    shape = (nb * per_bin, npix)
+    e1, e2 = np.zeros(shape), np.zeros(shape)
+    r1, r2 = np.zeros(shape), np.zeros(shape)
+    for b in range(nb):
+        n = counts[b][idx]
+        gal = np.repeat(np.arange(len(idx)), n)
+        inv_n = 1.0 / n
+
+        def mean(v):
+            return np.bincount(gal, weights=v, minlength=len(idx)) * inv_n
+
+        i1 = g.normal(0.0, SIGMA_E, gal.size)
+        i2 = g.normal(0.0, SIGMA_E, gal.size)
+        k = b * per_bin
+        e1[k, idx], e2[k, idx] = mean(i1), mean(i2)
+        r1[k, idx] = 1.0
+        for j in range(1, per_bin):
+            psi = g.uniform(0.0, math.pi, gal.size)
+            c2, s2 = np.cos(2.0 * psi), np.sin(2.0 * psi)
+            del psi
+            k = b * per_bin + j
+            e1[k, idx] = mean(i1 * c2 - i2 * s2)
+            e2[k, idx] = mean(i1 * s2 + i2 * c2)
+            r1[k, idx], r2[k, idx] = mean(c2), mean(s2)
+    return e1, e2, r1, r2
 
 
 # ---------------------------------------------------------------------------------------------

@@ -164,9 +164,10 @@ def cpu_baseline(cfg, nside, lmax, nsample):
             "seconds_per_apply": full}
 
 
-def batched_leg(name, tol, maxiter):
+def batched_leg(name, tol, maxiter, solves=True, napply=20):
     """Batched form on the tomographic workload: all right-hand sides in one FP32 plan (matrix-core
-    synthesis, lockstep PCG with FP64 reliable updates) against the FP64 solve of one right-hand side."""
+    synthesis, lockstep PCG with FP64 reliable updates) against the FP64 solve of one right-hand side.
+    solves=False times the batched applies only."""
     import numpy as np
     import torch
 
@@ -189,30 +190,63 @@ def batched_leg(name, tol, maxiter):
     g2 = torch.empty_like(g1)
     for k in range(nr):
         a, b = p.synth2(kap[k].contiguous(), torch.zeros_like(kap[k]))
+        if cfg["rot1"] is not None:
+            # shape-noise realisations: the signal enters rotated, R gamma with R = rot1 + i rot2
+            r1, r2 = (torch.from_numpy(cfg[n][k]).to(dev) for n in ("rot1", "rot2"))
+            a, b = r1 * a - r2 * b, r1 * b + r2 * a
         g1[k] = m * (a + torch.from_numpy(cfg["eps1"][k]).to(dev))
         g2[k] = m * (b + torch.from_numpy(cfg["eps2"][k]).to(dev))
     ninv = torch.from_numpy(cfg["ninv"][cfg["bin"]]).to(dev)
     torch.cuda.synchronize()
-    t = time.perf_counter()
-    xE, xB, info64 = p.cg_solve(g1[0].contiguous(), g2[0].contiguous(), ninv[0].contiguous(), mask, tol=tol,
-                                maxiter=maxiter, raise_not_converged=False)
-    torch.cuda.synchronize()
-    t64 = time.perf_counter() - t
+    if solves:
+        t = time.perf_counter()
+        xE, xB, info64 = p.cg_solve(g1[0].contiguous(), g2[0].contiguous(), ninv[0].contiguous(), mask, tol=tol,
+                                    maxiter=maxiter, raise_not_converged=False)
+        torch.cuda.synchronize()
+        t64 = time.perf_counter() - t
     p.close()
     pb = Plan(nside, lmax, nrhs=nr, precision="fp32", device=dev)
-    # one batched operator apply (all right-hand sides), timed with HIP events on the plan stream
+    # batched operator applies (all right-hand sides): 3 warm-ups, then the median of 20, each timed with
+    # HIP events on the plan stream (torch's current stream); stage times averaged over the 20
+    xs = [torch.from_numpy(np.stack([wl.random_alm(lmax, 70 + k) for k in range(nr)])).to(dev) for _ in (0, 1)]
+    for _ in range(3):
+        pb.apply_H(ninv, mask, xs[0], xs[1], 1e-3)
+    torch.cuda.synchronize()
     pb.set_timing(True)
     pb.stage_times()
-    xs = [torch.from_numpy(np.stack([wl.random_alm(lmax, 70 + k) for k in range(nr)])).to(dev) for _ in (0, 1)]
-    pb.apply_H(ninv, mask, xs[0], xs[1], 1e-3)
-    torch.cuda.synchronize()
-    pb.stage_times()  # stage times of the timed apply only
-    t = time.perf_counter()
-    pb.apply_H(ninv, mask, xs[0], xs[1], 1e-3)
-    torch.cuda.synchronize()
-    t_apply = time.perf_counter() - t
+    ts = []
+    for _ in range(napply):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        pb.apply_H(ninv, mask, xs[0], xs[1], 1e-3)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
     st = pb.stage_times()
     pb.set_timing(False)
+    t_apply = float(np.median(ts)) * 1e-3
+    per_apply = {k: v[0] / napply for k, v in st.items() if v[1]}
+    # matrix-core Legendre stages against the FP32 MFMA peak: (10 + 16 K) flop per evaluated
+    # (l, m, ring-pair) triple and direction for K right-hand sides (two recurrence steps shared by the
+    # right-hand sides, eight multiply-adds per right-hand side)
+    tb_eval = pb.work()["batched"]
+    flop = (10 + 16 * nr) * tb_eval
+    mfma = {"unit": "TFLOP/s", "peak": PEAK_FP32 / 1e12, "evaluated_triples": tb_eval,
+            "flop_per_launch_set": flop, "note": "per batched apply; the right-hand sides run in groups of 8"}
+    for stage in ("leg_synth", "leg_adj"):
+        if stage in per_apply:
+            a = flop / (per_apply[stage] * 1e-3)
+            mfma[stage] = {"ms": per_apply[stage], "achieved": a / 1e12, "frac": a / PEAK_FP32}
+    apply_out = {"batched_apply_ms": t_apply * 1e3, "rhs_applies_per_s": nr / t_apply,
+                 "batched_apply_timing": "median of %d applies after 3 warm-ups, HIP events" % napply,
+                 "batched_apply_stages_ms": {k: round(v, 3) for k, v in per_apply.items()},
+                 "mfma_roofline": mfma}
+    if not solves:
+        pb.close()
+        out = {"workload": "%s: HEALPix Nside %d, lmax %d, %d right-hand sides (applies only)" % (name, nside, lmax, nr)}
+        out.update(apply_out)
+        log("batched: %s" % out)
+        return out
     torch.cuda.synchronize()
     t = time.perf_counter()
     yE, yB, infob = pb.cg_solve(g1, g2, ninv, mask, tol=tol, maxiter=maxiter, raise_not_converged=False)
@@ -237,17 +271,66 @@ def batched_leg(name, tol, maxiter):
              "status": infon["status"], "finite": bool(torch.isfinite(cl).all())}
     del work, perm, cl
     pb.close()
-    out = {"workload": "%s: HEALPix Nside %d, lmax %d, %d right-hand sides (4 bins, own N^-1 each)" % (name, nside, lmax, nr),
+    out = {"workload": "%s: HEALPix Nside %d, lmax %d, %d right-hand sides (4 bins with own N^-1, each a signal and "
+                       "3 shape-noise realisations of randomly rotated galaxy ellipticities)" % (name, nside, lmax, nr),
            "fp64_single_rhs": {"seconds": t64, "iters": info64["iters"], "rel_resid_true": info64["rel_resid_true"]},
            "batched_fp32": {"seconds": tb, "iters": infob["iters"], "fp64_applies": infob["fp64_applies"],
                             "worst_rel_resid_true": infob["rel_resid_true"], "status": infob["status"],
                             "rel_err_rhs0_vs_fp64": err},
            "seconds_per_rhs_fp64": t64, "seconds_per_rhs_batched": tb / nr,
            "speedup_per_rhs_vs_fp64": t64 / (tb / nr),
-           "batched_apply_ms": t_apply * 1e3, "rhs_applies_per_s": nr / t_apply,
-           "batched_apply_stages_ms": {k: round(v[0], 3) for k, v in st.items() if v[1]},
            "noise_realisations": noise}
+    out.update(apply_out)
     log("batched: %s" % out)
+    return out
+
+
+def grad_leg(name, tol, maxiter, reps=3):
+    """Differentiable solve on the C5 workload (HEALPix Nside 256, lmax 512, FP64): forward solve
+    through AkraSolve, loss = sum of the E-mode band powers of kappa_E over 8 log bins, backward
+    (the adjoint CG solve and the pullback to gamma_1, gamma_2, N^-1).  Seconds are the median of
+    `reps` runs after one warm-up, each phase between two device synchronisations."""
+    import numpy as np
+    import torch
+
+    import akra_workloads as wl
+    from paper_2606_06175_amd import AkraSolve, Plan
+    from paper_2606_06175_amd.bandpower import BandPower
+
+    dev = torch.device("cuda", 0)
+    t = time.time()
+    nside, lmax = wl.CONFIGS[name]["nside"], wl.CONFIGS[name]["lmax"]
+    cfg, g1, g2, ninv, mask = make_inputs(name, nside, lmax, dev)
+    log("grad inputs %s generated in %.1f s" % (name, time.time() - t))
+    p = Plan(nside, lmax, precision="fp64", device=dev)
+    bp = BandPower(lmax, device=dev)
+    opts = dict(tol=tol, maxiter=maxiter)
+    fw, bw = [], []
+    for it in range(reps + 1):
+        ts = [a.detach().clone().requires_grad_(True) for a in (g1, g2, ninv)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        xE, xB = AkraSolve.apply(ts[0], ts[1], ts[2], mask, p, opts)
+        L = bp.loss(xE)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        L.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        if it:
+            fw.append(t1 - t0)
+            bw.append(t2 - t1)
+    fi, bi = p.last_solve_info, p.last_vjp_info
+    finite = all(bool(torch.isfinite(a.grad).all()) for a in ts)
+    out = {"workload": "%s: HEALPix Nside %d, lmax %d, FP64, loss = sum of 8 log-bin E-mode band powers of kappa_E"
+                       % (name, nside, lmax),
+           "forward_s": float(np.median(fw)), "backward_s": float(np.median(bw)),
+           "forward_backward_s": float(np.median(fw)) + float(np.median(bw)),
+           "forward_iters": fi["iters"], "backward_iters": bi["iters"], "tol": tol,
+           "forward_rel_resid_true": fi["rel_resid_true"], "backward_rel_resid_true": bi["rel_resid_true"],
+           "loss": float(L.detach()), "gradients_finite": finite, "reps": reps}
+    log("grad: %s" % out)
+    p.close()
     return out
 
 
@@ -463,6 +546,12 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-workload", default="C4")
     ap.add_argument("--no-pixelize", action="store_true")
+    ap.add_argument("--no-grad", action="store_true")
+    ap.add_argument("--only", choices=("batched", "grad", "pixelize", "flat"), default=None,
+                    help="run one leg alone and print its JSON (with --no-solve the batched leg times its applies "
+                         "only); for profiling one group of kernels")
+    ap.add_argument("--precision", choices=("fp64", "fp32"), default="fp64",
+                    help="precision of the plan the timed PCG steps run on")
     ap.add_argument("--no-flat", action="store_true")
     ap.add_argument("--no-rates", action="store_true")
     ap.add_argument("--flat-n", type=int, default=4096)
@@ -502,6 +591,18 @@ def main():
         print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "ms_per_copy": dt * 1e3,
                           "GB_per_s": 2 * n / dt / 1e9}), flush=True)
         return
+    if args.only:
+        if args.only == "batched":
+            res = batched_leg(args.batched_workload, args.solve_tol, args.maxiter, solves=not args.no_solve,
+                              napply=max(args.steps, 1))
+        elif args.only == "grad":
+            res = grad_leg("C5", args.solve_tol, args.maxiter)
+        elif args.only == "pixelize":
+            res = pixelize_leg(args.pixelize_galaxies, args.nside or 2048)
+        else:
+            res = flat_leg(args.flat_n, max(args.steps, 10), args.solve_tol, args.maxiter)
+        print(json.dumps({"leg": args.only, **res}), flush=True)
+        return
     p = wl.CONFIGS[args.workload]
     nside = args.nside or p["nside"]
     lmax = args.lmax or p["lmax"]
@@ -509,10 +610,10 @@ def main():
     cfg, g1, g2, ninv, mask = make_inputs(args.workload, nside, lmax, dev)
 
     t = time.time()
-    plan = Plan(nside, lmax, precision="fp64", device=dev)
+    plan = Plan(nside, lmax, precision=args.precision, device=dev)
     torch.cuda.synchronize()
     plan_s = time.time() - t
-    log("fp64 plan built in %.1f s, %.2f GB on device" % (plan_s, plan.device_bytes / 1e9))
+    log("%s plan built in %.1f s, %.2f GB on device" % (args.precision, plan_s, plan.device_bytes / 1e9))
     plan.cg_start(g1, g2, ninv, mask)
     plan.cg_step(args.warmup)
     torch.cuda.synchronize()
@@ -539,35 +640,41 @@ def main():
     dom = max(("leg_synth", "leg_adj"), key=lambda k: stages[k]["ms_avg"])
     flops = FLOP_PER_TRIPLE * evaluated[dom]
     achieved = flops / (stages[dom]["ms_avg"] * 1e-3)
+    peak = PEAK_FP64 if args.precision == "fp64" else PEAK_FP32
     roofline = {"bound": "alu", "kernel": "k_leg_adj" if dom == "leg_adj" else "k_leg_synth",
-                "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP64, "traffic": traffic(dom, nside, lmax),
+                "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+                "frac": achieved / peak,
+                "traffic": traffic(dom, nside, lmax) if args.precision == "fp64" else None,
                 "algorithmic": "26 flop x %d evaluated (l, m, ring-pair) triples = %.4g flop per launch "
                                "(all triples T = %d; the terms below each ring group's entry degree, where its "
                                "recurrence values first reach 2^-100, are skipped)" % (evaluated[dom], flops, T)}
     # ring stage against HBM: F read and G written (32 B per (ring, m) each) and W read (8 B per pixel)
-    ring_bytes = 2 * 32 * (4 * nside - 1) * (lmax + 1) + 8 * 12 * nside * nside
+    fg_bytes = 32 if args.precision == "fp64" else 16  # (Q, U) complex entry of F or G per (ring, m)
+    ring_bytes = 2 * fg_bytes * (4 * nside - 1) * (lmax + 1) + 8 * 12 * nside * nside
     roofline["ring_algorithmic_bytes"] = ring_bytes
     roofline["ring_hbm_GBs"] = ring_bytes / (stages["ring"]["ms_avg"] * 1e-3) / 1e9
     roofline["ring_hbm_frac"] = roofline["ring_hbm_GBs"] / 8000.0
     for k in ("leg_synth", "leg_adj"):
         t = stages[k]["ms_avg"] * 1e-3
-        roofline["frac_" + k] = FLOP_PER_TRIPLE * evaluated[k] / t / PEAK_FP64
+        roofline["frac_" + k] = FLOP_PER_TRIPLE * evaluated[k] / t / peak
         roofline["evaluated_fraction_" + k] = evaluated[k] / T
         roofline["full_T_rate_TFLOPs_" + k] = FLOP_PER_TRIPLE * T / t / 1e12
 
     out = {"metric": METRIC, "value": 1e3 / ms_step, "unit": "H·v applies/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f32",
+           "data": "synthetic",
            "config": {"workload": "%s: HEALPix Nside %d, lmax %d, single RHS, joint E/B, f_sky %.3f"
                                   % (args.workload, nside, lmax, float(cfg["mask"].mean())),
-                      "nside": nside, "lmax": lmax, "nrhs": 1, "precision": "fp64"},
+                      "nside": nside, "lmax": lmax, "nrhs": 1, "precision": args.precision},
            "roofline": roofline,
            "stages_ms": {k: round(v["ms_avg"], 4) for k, v in stages.items()},
            "plan_build_s": plan_s,
            "paper_context": {"applies_per_s": 0.044, "hardware": "one 72-CPU node",
                              "note": "derived from ~80 CG iterations in ~0.5 h at Nside 2048, lmax 4096 (DES Y3)"}}
 
+    if args.precision != "fp64":
+        args.no_solve = True  # the solve comparison runs its own FP64 and FP32 plans
     if not args.no_solve:
         solves = {}
         torch.cuda.synchronize()
@@ -601,6 +708,8 @@ def main():
 
     if not args.no_solve and not args.no_batched:
         out["batched"] = batched_leg(args.batched_workload, args.solve_tol, args.maxiter)
+    if not args.no_solve and not args.no_grad:
+        out["differentiable"] = grad_leg("C5", args.solve_tol, args.maxiter)
     if not args.no_pixelize:
         out["pixelize"] = pixelize_leg(args.pixelize_galaxies, nside)
     if not args.no_flat:

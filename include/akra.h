@@ -272,6 +272,14 @@ akra_status akra_plan_get_tuning(akra_plan plan, int *out5);
  * states stored at plan creation.
  */
 akra_status akra_plan_work(akra_plan plan, int64_t *out3);
+/*
+ * Work of the batched matrix-core Legendre kernels (FP32 plans with nrhs > 1), written to out1 (HOST):
+ * the (l, m, ring pair) triples evaluated per right-hand side when every 64-pair ring group starts
+ * at its own entry degree, as those kernels do.  One batched synthesis or adjoint of K right-hand
+ * sides performs (10 + 16 K) flop per such triple: two recurrence steps shared by the right-hand
+ * sides and eight multiply-adds per right-hand side (the transform of eq. shear_SH and its adjoint).
+ */
+akra_status akra_plan_work_batched(akra_plan plan, int64_t *out1);
 akra_status akra_plan_set_timing(akra_plan plan, int on);
 /*
  * Ring-stage kernel choice of plans created afterwards (process-wide, not thread-safe against

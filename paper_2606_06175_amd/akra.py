@@ -80,6 +80,7 @@ def lib():
     L.akra_plan_set_tuning.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     L.akra_plan_get_tuning.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
     L.akra_plan_work.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
+    L.akra_plan_work_batched.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
     L.akra_cg_solve_vjp.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(CgOpts), vp, vp, vp, vp, vp, vp, vp,
                                     ctypes.POINTER(CgInfo)]
     L.akra_cg_solve_cond_b.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(CgOpts), vp, vp, ctypes.POINTER(CgInfo)]
@@ -110,6 +111,7 @@ def lib():
     for f in ("akra_plan_create", "akra_synth2", "akra_adjoint2", "akra_apply_H", "akra_rhs", "akra_cg_solve",
               "akra_cg_solve_b", "akra_cg_start", "akra_cg_step", "akra_cg_state", "akra_plan_set_timing",
               "akra_plan_stage_times", "akra_plan_set_tuning", "akra_plan_get_tuning", "akra_plan_work",
+              "akra_plan_work_batched",
               "akra_cg_solve_vjp", "akra_cg_solve_cond_b", "akra_set_ring_whole_maxm", "akra_unmasked_index",
               "akra_shuffle_shear", "akra_alm_spectra", "akra_noise_work_size", "akra_noise_spectra", "akra_ang2pix",
               "akra_pixelize_work_size", "akra_pixelize", "akra_flat_plan_create", "akra_flat_synth",
@@ -533,7 +535,9 @@ class Plan:
         """(l, m, ring-pair) triples per Legendre launch: all, evaluated by the synthesis, by the adjoint."""
         v = (ctypes.c_int64 * 3)()
         _check(lib().akra_plan_work(self._h, v))
-        return {"all": v[0], "synth": v[1], "adjoint": v[2]}
+        b = ctypes.c_int64()
+        _check(lib().akra_plan_work_batched(self._h, ctypes.byref(b)))
+        return {"all": v[0], "synth": v[1], "adjoint": v[2], "batched": b.value}
 
 
 class FlatPlan:
@@ -662,12 +666,14 @@ class AkraSolve(torch.autograd.Function):
 
     Gradients flow to g1, g2 and ninv (not to the mask).  The backward pass is one more CG solve
     with the same operator, run by akra_cg_solve_vjp; solver options (the mode of the unknowns
-    included) apply to both solves."""
+    included) apply to both solves.  The solve information of the last forward and backward solve
+    is left in plan.last_solve_info and plan.last_vjp_info."""
 
     @staticmethod
     def forward(ctx, g1, g2, ninv, mask, plan, opts=None):
         opts = dict(opts or {})
         xE, xB, info = plan.cg_solve(g1, g2, ninv, mask, **opts)
+        plan.last_solve_info = info
         ctx.plan, ctx.opts = plan, opts
         ctx.save_for_backward(g1, g2, ninv, mask, xE, xB)
         ctx.mark_non_differentiable(mask)
@@ -681,5 +687,7 @@ class AkraSolve(torch.autograd.Function):
         if vB is None:
             vB = torch.zeros_like(xB)
         opts = {k: v for k, v in ctx.opts.items() if k not in ("x0", "hist_len")}
-        dg1, dg2, dn, _ = ctx.plan.cg_solve_vjp(g1, g2, ninv, mask, xE, xB, vE.contiguous(), vB.contiguous(), **opts)
+        dg1, dg2, dn, info = ctx.plan.cg_solve_vjp(g1, g2, ninv, mask, xE, xB, vE.contiguous(), vB.contiguous(),
+                                                   **opts)
+        ctx.plan.last_vjp_info = info
         return dg1, dg2, dn, None, None, None

@@ -117,6 +117,7 @@ struct Plan {
     std::vector<int> h_entl;
     int *d_wgstart = nullptr;   // [m][adjoint ring block] first degree the block wrote
     int64_t work[3] = {0, 0, 0};  // (l, m, pair) triples: all, evaluated by synthesis, by adjoint
+    int64_t work_b = 0;           // triples per right-hand side of the batched kernels (each group from its entry)
     void *d_tw64 = nullptr, *d_tw32 = nullptr;  // e^{-2 pi i k / twn}, k < twn/2
     void *d_bhat64 = nullptr, *d_bhat32 = nullptr;  // Bluestein chirp spectra per distinct sub length
     int twn = 1;

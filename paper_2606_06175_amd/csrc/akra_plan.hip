@@ -197,7 +197,7 @@ static void compute_work(Plan &P)
 {
     const int lmax = P.lmax, np = P.npairs, ng = P.ng64, gp = P.polar_groups;
     auto pairs_in = [&](int g0, int g1) { return (int64_t)std::max(0, std::min(np, 64 * g1) - 64 * g0); };
-    int64_t all = 0, syn = 0, adj = 0;
+    int64_t all = 0, syn = 0, adj = 0, bat = 0;
     // blocks of gs groups over [g0, g1): each starts at the earliest entry degree of its groups
     auto seg = [&](const int *e, int g0, int g1, int gs) {
         int64_t w = 0;
@@ -213,10 +213,12 @@ static void compute_work(Plan &P)
         const int *e = P.h_entl.data() + (size_t)m * ng;
         syn += seg(e, 0, gp, 1) + seg(e, gp, ng, P.syn_R);
         adj += seg(e, 0, gp, 4) + seg(e, gp, ng, P.adj_R * P.adj_W);
+        bat += seg(e, 0, ng, 1);
     }
     P.work[0] = all;
     P.work[1] = syn;
     P.work[2] = adj;
+    P.work_b = bat;
 }
 
 static akra_status upload(void **dst, const void *src, size_t bytes, Plan &P)
@@ -1762,6 +1764,17 @@ akra_status akra_plan_work(akra_plan plan, int64_t *out3)
         return AKRA_ERR_ARG;
     }
     for (int i = 0; i < 3; ++i) out3[i] = P.work[i];
+    return AKRA_OK;
+}
+
+akra_status akra_plan_work_batched(akra_plan plan, int64_t *out1)
+{
+    AK_PLAN();
+    if (!out1) {
+        set_error("out1 is NULL");
+        return AKRA_ERR_ARG;
+    }
+    *out1 = P.work_b;
     return AKRA_OK;
 }
 
