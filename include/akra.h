@@ -346,6 +346,25 @@ akra_status akra_alm_spectra(akra_plan plan, const double *x, int nx, const doub
                              int npairs, double *cl);
 
 /*
+ * Allocation-free form of akra_alm_spectra, for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).  It needs no
+ * plan: the band limit is an argument, and the partial sums live in a static device array of the
+ * library (SPEC pairs x chunks x degrees of float64, 16.3 MiB at AKRA_NOALLOC_LMAX_MAX), one copy
+ * per GPU held until the process ends.  The call allocates nothing; its device address is looked
+ * up once per device, at the first call with that device current.
+ *   lmax      0 <= lmax <= AKRA_NOALLOC_LMAX_MAX (AKRA_ERR_ARG beyond it, before any HIP call);
+ *   x, y, nx, ny, pairs, npairs, cl   as for akra_alm_spectra, with n_alm = (lmax+1)(lmax+2)/2;
+ *   hip_stream  a stream of the current device (NULL: the null stream).
+ * Stream-ordered, no host synchronisation; results equal akra_alm_spectra's bit for bit.  Calls that
+ * overlap on one GPU (other threads or other streams) share the scratch array and race: serialise
+ * them.  Errors: AKRA_ERR_ARG as for akra_alm_spectra, lmax out of range, or a stream of another
+ * device; AKRA_ERR_HIP.
+ */
+#define AKRA_NOALLOC_LMAX_MAX 4096
+akra_status akra_alm_spectra_noalloc(int lmax, const double *x, int nx, const double *y, int ny,
+                                     const int32_t *pairs, int npairs, double *cl, void *hip_stream);
+
+/*
  * Device bytes of the workspace akra_noise_spectra needs for nset (1 or 2) shear sets, written to
  * *bytes (HOST): the unmasked list, the shuffled maps and the solutions of max(nrhs, nset) right-hand
  * sides.  Errors: AKRA_ERR_ARG.

@@ -90,6 +90,8 @@ def lib():
     L.akra_shuffle_shear.argtypes = [vp, vp, vp, vp, i64, vp, ctypes.c_int, vp, vp]
     L.akra_alm_spectra.argtypes = [vp, vp, ctypes.c_int, vp, ctypes.c_int, vp, ctypes.c_int, vp]
     L.akra_noise_work_size.argtypes = [vp, ctypes.c_int, ctypes.POINTER(i64)]
+    L.akra_alm_spectra_noalloc.argtypes = [ctypes.c_int, vp, ctypes.c_int, vp, ctypes.c_int, vp, ctypes.c_int, vp,
+                                           vp]
     L.akra_ang2pix.argtypes = [vp, vp, vp, i64, vp]
     L.akra_flat_plan_create.argtypes = [ctypes.c_int, ctypes.c_int, vp, ctypes.POINTER(vp)]
     L.akra_flat_plan_destroy.argtypes = [vp]
@@ -113,7 +115,7 @@ def lib():
               "akra_plan_stage_times", "akra_plan_set_tuning", "akra_plan_get_tuning", "akra_plan_work",
               "akra_plan_work_batched",
               "akra_cg_solve_vjp", "akra_cg_solve_cond_b", "akra_set_ring_whole_maxm", "akra_unmasked_index",
-              "akra_shuffle_shear", "akra_alm_spectra", "akra_noise_work_size", "akra_noise_spectra", "akra_ang2pix",
+              "akra_shuffle_shear", "akra_alm_spectra", "akra_alm_spectra_noalloc", "akra_noise_work_size", "akra_noise_spectra", "akra_ang2pix",
               "akra_pixelize_work_size", "akra_pixelize", "akra_flat_plan_create", "akra_flat_synth",
               "akra_flat_adjoint", "akra_flat_apply_H", "akra_flat_rhs", "akra_flat_cg_solve", "akra_flat_cg_start",
               "akra_flat_cg_step", "akra_plan_set_graph"):
@@ -142,6 +144,36 @@ def _kernel_arg(kernel):
     import numpy as np
     k = np.ascontiguousarray(kernel, dtype=np.float64)
     return k, k.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+NOALLOC_LMAX_MAX = 4096  # AKRA_NOALLOC_LMAX_MAX
+
+
+def alm_spectra_noalloc(x, y, pairs, lmax, out=None, stream=None):
+    """C_l of coefficient pairs without a plan and without device allocation by the library
+    (akra_alm_spectra_noalloc): x [nx, n_alm], y [ny, n_alm] complex128 on one device, pairs a list of
+    (i, j); returns (or fills) float64 [npairs, lmax + 1].  Calls overlapping on one GPU race (they
+    share the library's static scratch)."""
+    import numpy as np
+    lmax = int(lmax)
+    nalm = alm_size(lmax)
+    if x.dtype != torch.complex128 or y.dtype != torch.complex128 or x.device != y.device:
+        raise TypeError("x and y must be complex128 on one device")
+    if x.shape[-1] != nalm or y.shape[-1] != nalm:
+        raise ValueError("coefficient arrays must have n_alm = %d entries per row" % nalm)
+    x, y = x.contiguous(), y.contiguous()
+    pr = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1, 2))
+    if out is None:
+        out = torch.empty((len(pr), lmax + 1), dtype=torch.float64, device=x.device)
+    elif out.dtype != torch.float64 or out.device != x.device or out.numel() != len(pr) * (lmax + 1) \
+            or not out.is_contiguous():
+        raise ValueError("out must be contiguous float64 [npairs, lmax + 1] on the coefficients' device")
+    with torch.cuda.device(x.device):
+        s = stream if stream is not None else torch.cuda.current_stream(x.device)
+        _check(lib().akra_alm_spectra_noalloc(lmax, x.data_ptr(), x.numel() // nalm, y.data_ptr(),
+                                               y.numel() // nalm, pr.ctypes.data, len(pr), out.data_ptr(),
+                                               ctypes.c_void_p(s.cuda_stream)))
+    return out
 
 
 class Plan:

@@ -8,6 +8,8 @@
 // summation order).
 #include "akra_internal.h"
 
+#include <mutex>
+
 namespace akra {
 
 // ---- unmasked pixel list --------------------------------------------------------------------
@@ -196,11 +198,18 @@ void launch_shuffle(Plan &P, const double *g1, const double *g2, const int32_t *
     }
 }
 
+// partial sums in part[n][nmc][lmax + 1]; every entry the sum kernel reads is written first by the
+// part kernel of the same launch pair, so part needs no clearing
+static void spectra_on(const SpecArgs &a, int n, int lmax, int nmc, double *part, hipStream_t stream)
+{
+    const int nlt = (lmax + SPEC_LT) / SPEC_LT;
+    k_spec_part<<<dim3(nlt, nmc, n), SPEC_LT, 0, stream>>>(a, lmax, nmc, part);
+    k_spec_sum<<<dim3(nlt, n), SPEC_LT, 0, stream>>>(a, lmax, nmc, part);
+}
+
 void launch_spectra(Plan &P, const SpecArgs &a, int n)
 {
-    const int nlt = (P.lmax + SPEC_LT) / SPEC_LT;
-    k_spec_part<<<dim3(nlt, P.spec_nmc, n), SPEC_LT, 0, P.stream>>>(a, P.lmax, P.spec_nmc, P.d_spec);
-    k_spec_sum<<<dim3(nlt, n), SPEC_LT, 0, P.stream>>>(a, P.lmax, P.spec_nmc, P.d_spec);
+    spectra_on(a, n, P.lmax, P.spec_nmc, P.d_spec, P.stream);
 }
 
 void launch_cl_moments(Plan &P, const double *cl, int n, int64_t len, double *mean, double *sd)
@@ -208,4 +217,104 @@ void launch_cl_moments(Plan &P, const double *cl, int n, int64_t len, double *me
     k_cl_moments<<<(int)((len + 255) / 256), 256, 0, P.stream>>>(cl, n, len, mean, sd);
 }
 
+// ---- spectra without allocation --------------------------------------------------------------
+// The partial sums of akra_alm_spectra_noalloc live in this file-scope device array, one copy per
+// GPU for the life of the process, sized for SPEC_NP pairs at lmax = AKRA_NOALLOC_LMAX_MAX.  Host code
+// never uses the array's name as an address: the device address of each GPU's copy comes from
+// hipGetSymbolAddress, taken once per device with that device current, and only that address is
+// passed to the kernels.
+constexpr int64_t NOALLOC_NMC = (AKRA_NOALLOC_LMAX_MAX + SPEC_MC) / SPEC_MC;
+constexpr int64_t NOALLOC_DOUBLES = (int64_t)SPEC_NP * NOALLOC_NMC * (AKRA_NOALLOC_LMAX_MAX + 1);
+static __device__ __align__(256) double scratch[NOALLOC_DOUBLES];
+
+constexpr int NOALLOC_MAX_DEV = 64;
+static std::mutex g_scratch_mu;
+static double *g_scratch_ptr[NOALLOC_MAX_DEV] = {};
+
+// device address of the current device's scratch array (set up on the first call on that device)
+static akra_status scratch_address(int dev, double **out)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            set_error(std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+            return AKRA_ERR_HIP;
+        }
+        g_scratch_ptr[dev] = (double *)ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return AKRA_OK;
+}
+
 }  // namespace akra
+
+using namespace akra;
+
+extern "C" akra_status akra_alm_spectra_noalloc(int lmax, const double *x, int nx, const double *y, int ny,
+                                                const int32_t *pairs, int npairs, double *cl, void *hip_stream)
+{
+    TraceRange trace_range("akra_alm_spectra_noalloc");
+    // every argument is checked before the first HIP call
+    if (lmax < 0 || lmax > AKRA_NOALLOC_LMAX_MAX) {
+        set_error("lmax " + std::to_string(lmax) + " is outside [0, " + std::to_string(AKRA_NOALLOC_LMAX_MAX) +
+                  "], the largest band limit the static scratch of akra_alm_spectra_noalloc holds");
+        return AKRA_ERR_ARG;
+    }
+    if (npairs < 0 || nx < 0 || ny < 0) {
+        set_error("counts must be >= 0");
+        return AKRA_ERR_ARG;
+    }
+    if (npairs == 0) return AKRA_OK;
+    if (!x || !y || !pairs || !cl) {
+        set_error("null pointer argument");
+        return AKRA_ERR_ARG;
+    }
+    if (((uintptr_t)x | (uintptr_t)y) % 16) {
+        set_error("coefficient arrays must be 16-byte aligned (complex128)");
+        return AKRA_ERR_ARG;
+    }
+    for (int q = 0; q < npairs; ++q)
+        if (pairs[2 * q] < 0 || pairs[2 * q] >= nx || pairs[2 * q + 1] < 0 || pairs[2 * q + 1] >= ny) {
+            set_error("pair " + std::to_string(q) + " is out of range");
+            return AKRA_ERR_ARG;
+        }
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess || dev < 0 || dev >= NOALLOC_MAX_DEV) {
+        set_error(std::string("hipGetDevice: ") + hipGetErrorString(e));
+        return AKRA_ERR_HIP;
+    }
+    hipStream_t stream = (hipStream_t)hip_stream;
+    if (stream) {
+        int sdev = -1;
+        e = hipStreamGetDevice(stream, &sdev);
+        if (e != hipSuccess || sdev != dev) {
+            set_error("the stream does not belong to the current device");
+            return AKRA_ERR_ARG;
+        }
+    }
+    double *part = nullptr;
+    const akra_status st = scratch_address(dev, &part);
+    if (st != AKRA_OK) return st;
+    const int64_t nalm = (int64_t)(lmax + 1) * (lmax + 2) / 2;
+    const int nmc = (lmax + SPEC_MC) / SPEC_MC;
+    const double2 *X = (const double2 *)x, *Y = (const double2 *)y;
+    for (int q0 = 0; q0 < npairs; q0 += SPEC_NP) {
+        SpecArgs a{};
+        const int n = std::min(SPEC_NP, npairs - q0);
+        for (int i = 0; i < n; ++i) {
+            a.x[i] = X + (int64_t)pairs[2 * (q0 + i)] * nalm;
+            a.y[i] = Y + (int64_t)pairs[2 * (q0 + i) + 1] * nalm;
+            a.cl[i] = cl + (int64_t)(q0 + i) * (lmax + 1);
+        }
+        spectra_on(a, n, lmax, nmc, part, stream);
+    }
+    e = hipGetLastError();
+    if (e != hipSuccess) {
+        set_error(std::string("spectra launch: ") + hipGetErrorString(e));
+        return AKRA_ERR_HIP;
+    }
+    return AKRA_OK;
+}

@@ -92,3 +92,18 @@ def test_null_flat_plan(L):
     assert L.akra_flat_plan_device_bytes(None) == 0
     L.akra_flat_plan_destroy(None)  # a no-op
     assert L.akra_flat_plan_create(8, 8, None, None) == akra.AKRA_ERR_ARG
+
+
+def test_noalloc_spectra_rejects_bad_arguments_before_any_hip_call(L):
+    # the allocation-free spectrum call checks its arguments on the host first
+    assert L.akra_alm_spectra_noalloc(4097, None, 0, None, 0, None, 1, None, None) == akra.AKRA_ERR_ARG
+    assert "4096" in L.akra_last_error().decode()
+    assert L.akra_alm_spectra_noalloc(-1, None, 0, None, 0, None, 1, None, None) == akra.AKRA_ERR_ARG
+    assert L.akra_alm_spectra_noalloc(8, None, 0, None, 0, None, -1, None, None) == akra.AKRA_ERR_ARG
+    assert L.akra_alm_spectra_noalloc(8, None, 0, None, 0, None, 0, None, None) == akra.AKRA_OK
+    assert L.akra_alm_spectra_noalloc(8, None, 1, None, 1, None, 1, None, None) == akra.AKRA_ERR_ARG
+    assert "null" in L.akra_last_error().decode()
+    x = ctypes.c_void_p(16)
+    pairs = (ctypes.c_int32 * 2)(0, 1)
+    assert L.akra_alm_spectra_noalloc(8, x, 1, x, 1, pairs, 1, x, None) == akra.AKRA_ERR_ARG
+    assert "out of range" in L.akra_last_error().decode()
