@@ -550,6 +550,8 @@ def main():
     ap.add_argument("--only", choices=("batched", "grad", "pixelize", "flat"), default=None,
                     help="run one leg alone and print its JSON (with --no-solve the batched leg times its applies "
                          "only); for profiling one group of kernels")
+    ap.add_argument("--lds-rings", action="store_true",
+                    help="run every ring on the LDS kernels (no register engine), for timing comparisons")
     ap.add_argument("--precision", choices=("fp64", "fp32"), default="fp64",
                     help="precision of the plan the timed PCG steps run on")
     ap.add_argument("--no-flat", action="store_true")
@@ -578,6 +580,9 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.lds_rings:
+        from paper_2606_06175_amd import akra
+        akra.set_ring_register_engine(False)
     if args.copy_calibration:
         n = args.copy_calibration << 20
         src = torch.ones(n // 8, dtype=torch.float64, device=dev)

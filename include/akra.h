@@ -290,6 +290,14 @@ akra_status akra_plan_set_timing(akra_plan plan, int on);
  * exist to exercise the split kernel at small sizes.  Errors: AKRA_ERR_ARG.
  */
 akra_status akra_set_ring_whole_maxm(int maxm);
+/*
+ * Register engine of the ring stage for plans created afterwards (process-wide, not thread-safe
+ * against concurrent akra_plan_create).  on != 0 (the default): rings whose transform length is 4096
+ * or 8192 (whole power-of-two rings and whole-ring Bluestein convolutions) run the kernels that hold
+ * a transform in registers and exchange through LDS; on = 0: every ring runs the LDS kernels.  The
+ * results agree to rounding; the switch exists for tests and timing comparisons.  Returns AKRA_OK.
+ */
+akra_status akra_set_ring_register_engine(int on);
 akra_status akra_plan_stage_times(akra_plan plan, double *ms, int *calls);
 
 /*

@@ -85,6 +85,7 @@ def lib():
                                     ctypes.POINTER(CgInfo)]
     L.akra_cg_solve_cond_b.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(CgOpts), vp, vp, ctypes.POINTER(CgInfo)]
     L.akra_set_ring_whole_maxm.argtypes = [ctypes.c_int]
+    L.akra_set_ring_register_engine.argtypes = [ctypes.c_int]
     L.akra_plan_stage_times.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int)]
     L.akra_unmasked_index.argtypes = [vp, vp, vp, ctypes.POINTER(i64)]
     L.akra_shuffle_shear.argtypes = [vp, vp, vp, vp, i64, vp, ctypes.c_int, vp, vp]
@@ -114,7 +115,7 @@ def lib():
               "akra_cg_solve_b", "akra_cg_start", "akra_cg_step", "akra_cg_state", "akra_plan_set_timing",
               "akra_plan_stage_times", "akra_plan_set_tuning", "akra_plan_get_tuning", "akra_plan_work",
               "akra_plan_work_batched",
-              "akra_cg_solve_vjp", "akra_cg_solve_cond_b", "akra_set_ring_whole_maxm", "akra_unmasked_index",
+              "akra_cg_solve_vjp", "akra_cg_solve_cond_b", "akra_set_ring_whole_maxm", "akra_set_ring_register_engine", "akra_unmasked_index",
               "akra_shuffle_shear", "akra_alm_spectra", "akra_alm_spectra_noalloc", "akra_noise_work_size", "akra_noise_spectra", "akra_ang2pix",
               "akra_pixelize_work_size", "akra_pixelize", "akra_flat_plan_create", "akra_flat_synth",
               "akra_flat_adjoint", "akra_flat_apply_H", "akra_flat_rhs", "akra_flat_cg_solve", "akra_flat_cg_start",
@@ -132,6 +133,11 @@ def _check(st):
 def set_ring_whole_maxm(maxm):
     """Ring-stage kernel choice of plans created afterwards (see akra_set_ring_whole_maxm)."""
     _check(lib().akra_set_ring_whole_maxm(int(maxm)))
+
+
+def set_ring_register_engine(on):
+    """Register engine of the ring stage for plans created afterwards (see akra_set_ring_register_engine)."""
+    _check(lib().akra_set_ring_register_engine(1 if on else 0))
 
 
 def alm_size(lmax):

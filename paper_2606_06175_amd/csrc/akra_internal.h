@@ -90,6 +90,7 @@ struct RingInfo {
     int M;         // Bluestein FFT length (0: sub is a power of two): of the whole ring when the
                    // ring is transformed whole, else of the sub-transform
     int64_t bofs;  // Bluestein rings: offset of the chirp spectrum of the transformed length
+    int64_t rofs;  // Bluestein rings of the register engine: offset of that spectrum in register order
 };
 
 struct Plan {
@@ -124,6 +125,11 @@ struct Plan {
     int *d_lof = nullptr;  // l of every alm index
     int *d_order_p2 = nullptr, *d_order_bl = nullptr, *d_order_bf = nullptr;
     int n_p2 = 0, n_bl = 0, n_bf = 0, maxM_p2 = 1, maxM_bl = 1, maxM_bf = 1;
+    // rings of the register engine (transform length 4096 or 8192): [0] direct M = 4096, [1] direct
+    // 8192, [2] whole-ring Bluestein M = 4096, [3] 8192, [4] two-half Bluestein M = 4096, [5] 8192
+    int *d_order_r[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    int n_r[6] = {0, 0, 0, 0, 0, 0};
+    void *d_bhatr64 = nullptr, *d_bhatr32 = nullptr;  // their chirp spectra in register order
     std::vector<RingInfo> h_rings;
 
     // Legendre launch shapes
@@ -266,6 +272,7 @@ void launch_epilogue_batched(Plan &P, int rhs, const double *kern, double lam, c
                              double *outE, double *outB, double *dot_red = nullptr);
 // chirp spectra of the Bluestein sub lengths Ls (FFT lengths Ms, table offsets ofs; device arrays)
 void launch_bhat(Plan &P, const int *Ls, const int *Ms, const int64_t *ofs, int n, int maxM);
+void launch_bhat_reorder(Plan &P, int logm, const int64_t *src_ofs, const int64_t *dst_ofs, int n);
 // weights W = mask * ninv, plus the sums needed for lambda_eff / P and input validation; right-hand
 // side r reads the N^-1 map r mod ncount of ninv ([ncount][npix])
 void launch_weights(Plan &P, const double *ninv, const uint8_t *mask, int nrhs, int ncount);

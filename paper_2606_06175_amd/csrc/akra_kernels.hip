@@ -1227,6 +1227,79 @@ __device__ __forceinline__ void unfold_bin_ph(cplx<T> *__restrict__ G, int bin, 
     }
 }
 
+// Short rings (many orders per bin: 2 lmax + 1 > 8 N): the fold and the unfold run over the orders
+// with the whole workgroup instead of one thread per bin.  Thread tau < Q N (Q = floor(RF / N)) takes
+// the orders m = tau - lmax + Q N u, which all fall into one bin, sums them in order, and the Q
+// partial sums of a bin are added in a fixed tree in LDS.  The unfold gives every order its own
+// thread.  Both read and write F / G in m order, neighbouring threads on neighbouring entries.
+__device__ __forceinline__ bool short_ring(int N, int lmax) { return 2 * lmax + 1 > 8 * N; }
+
+// X_b = e^{i pi b shift / N} sum_{m = b + N t, |m| <= lmax} (-1)^{t shift} F(m) into buf[pd(b)], b < N;
+// buf must hold RF complex entries; ends with a barrier
+template <typename T>
+__device__ void fold_short(const cplx<T> *__restrict__ F, cplx<T> *buf, int N, int shift, int lmax)
+{
+    const int tid = threadIdx.x, Q = RF / N, RFp = Q * N;
+    if (tid < RFp) {
+        const int r = tid - (tid / N) * N;
+        const int b = ((r - lmax) % N + N) % N;             // bin of every order of this thread
+        int t = (tid - lmax - b) / N;                         // m = b + N t for m = tid - lmax
+        const bool flip = shift && (Q & 1);                   // t advances by Q per step
+        bool neg = shift && (t & 1);
+        T sr = 0, si = 0;
+        for (int mm = tid; mm <= 2 * lmax; mm += RFp) {
+            const int m = mm - lmax;
+            const cplx<T> f = (m >= 0) ? F[2 * m] : F[2 * (-m) + 1];
+            sr += neg ? -f.x : f.x;
+            si += neg ? -f.y : f.y;
+            neg ^= flip;
+        }
+        buf[tid] = mk<T>(sr, si);
+    }
+    for (int st = 1; st < Q; st <<= 1) {
+        __syncthreads();
+        if (tid < RFp) {
+            const int q = tid / N;
+            if ((q % (2 * st)) == 0 && q + st < Q) buf[tid] = cadd<T>(buf[tid], buf[tid + st * N]);
+        }
+    }
+    __syncthreads();
+    cplx<T> x = mk<T>(0, 0);
+    int b = 0;
+    if (tid < N) {
+        b = ((tid - lmax) % N + N) % N;
+        x = buf[tid];
+        if (shift) x = cmul<T>(x, to_t<T>(cis_pi<double>(b, N)));
+    }
+    __syncthreads();
+    if (tid < N) buf[pd(b)] = x;
+    __syncthreads();
+}
+
+// G(m) = (-1)^{t shift} e^{-i pi b shift / N} Y_b for every |m| <= lmax, m = b + N t, from Y_b in
+// buf[pd(b)] (already scaled); G(0) goes to both components
+template <typename T>
+__device__ void unfold_short(cplx<T> *__restrict__ G, cplx<T> *buf, int N, int shift, int lmax)
+{
+    const int tid = threadIdx.x;
+    if (shift) {
+        for (int b = tid; b < N; b += RF) buf[pd(b)] = cmul<T>(buf[pd(b)], to_t<T>(cis_pi<double>(-b, N)));
+        __syncthreads();
+    }
+    for (int mm = tid; mm <= 2 * lmax; mm += RF) {
+        const int m = mm - lmax;
+        const int b = ((m % N) + N) % N, t = (m - b) / N;
+        cplx<T> g = buf[pd(b)];
+        if (shift && (t & 1)) g = mk<T>(-g.x, -g.y);
+        if (m > 0) G[2 * m] = g;
+        else if (m < 0) G[2 * (-m) + 1] = g;
+        else {
+            G[0] = g;
+            G[1] = g;
+        }
+    }
+}
+
 template <typename T, int MODE>
 __global__ __launch_bounds__(RF) void k_ring_full(cplx<T> *__restrict__ FG, int64_t fg_stride,
                                                   const double *__restrict__ g1, const double *__restrict__ g2,
@@ -1249,16 +1322,21 @@ __global__ __launch_bounds__(RF) void k_ring_full(cplx<T> *__restrict__ FG, int6
     const float rN = 1.0f / (float)N;
     cplx<T> v[RFU];
 
+    const bool shortr = short_ring(N, lmax);
     if (MODE != 1) {
         // bin b collects F(m) e^{i m phi0} over m = b + N t, |m| <= lmax (phi0 = pi shift / N)
-        PhaseSeq ph(tid, RF, N);  // e^{i pi b / N}
+        if (shortr) {
+            fold_short<T>(F, buf, N, shift, lmax);
+        } else {
+            PhaseSeq ph(tid, RF, N);  // e^{i pi b / N}
 #pragma unroll
-        for (int u = 0; u < RFU; ++u) {
-            const int b = tid + RF * u;
-            const double2 e = ph.next();
-            if (b < N) buf[pd(b)] = fold_bin_ph<T>(F, b, N, rN, shift, lmax, e);
+            for (int u = 0; u < RFU; ++u) {
+                const int b = tid + RF * u;
+                const double2 e = ph.next();
+                if (b < N) buf[pd(b)] = fold_bin_ph<T>(F, b, N, rN, shift, lmax, e);
+            }
+            __syncthreads();
         }
-        __syncthreads();
         fft_dif<T, RF>(buf, N, tw, twn, +1);  // gamma_j = sum_b X_b e^{+2 pi i b j / N}, at brev(j)
 #pragma unroll
         for (int u = 0; u < RFU; ++u) {
@@ -1310,6 +1388,23 @@ __global__ __launch_bounds__(RF) void k_ring_full(cplx<T> *__restrict__ FG, int6
     __syncthreads();
     fft_dif<T, RF>(buf, N, tw, twn, -1);  // Y_b = sum_j h_j e^{-2 pi i b j / N}, at brev(b)
     const T om = (T)omega;
+    if (shortr) {
+        // bins to natural order, scaled (read all, then write: the two orders overlap)
+#pragma unroll
+        for (int u = 0; u < RFU; ++u) {
+            const int b = tid + RF * u;
+            if (b < N) v[u] = cscale<T>(buf[pd(brev(b, logN))], om);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < RFU; ++u) {
+            const int b = tid + RF * u;
+            if (b < N) buf[pd(b)] = v[u];
+        }
+        __syncthreads();
+        unfold_short<T>(F, buf, N, shift, lmax);
+        return;
+    }
     PhaseSeq ph(tid, RF, N);
 #pragma unroll
     for (int u = 0; u < RFU; ++u) {
@@ -1351,16 +1446,30 @@ __global__ __launch_bounds__(RF) void k_ring_bfull(cplx<T> *__restrict__ FG, int
     const float rN = 1.0f / (float)N;
     cplx<T> v[RBU];
 
+    const bool shortr = short_ring(N, lmax);
     if (MODE != 1) {
         // gamma_j = sum_b X_b e^{+2 pi i b j / N} = conj(DFT(conj X))_j; get and put run in u order
-        PhaseSeq ph(tid, RF, N);  // e^{i pi b / N} along b = tid + RF u
-        dft_forward<T, RF, RBU>(
-            buf, bhat, N, M, logM, true, tw, twn,
-            [&](int u) {
-                const double2 e = ph.next();
-                return cconj<T>(fold_bin_ph<T>(F, tid + RF * u, N, rN, shift, lmax, e));
-            },
-            [&](int u, cplx<T> y) { v[u] = cconj<T>(y); });
+        if (shortr) {
+            fold_short<T>(F, buf, N, shift, lmax);
+#pragma unroll
+            for (int u = 0; u < RBU; ++u) {
+                const int b = tid + RF * u;
+                v[u] = b < N ? buf[pd(b)] : mk<T>(0, 0);
+            }
+            __syncthreads();
+            dft_forward<T, RF, RBU>(
+                buf, bhat, N, M, logM, true, tw, twn, [&](int u) { return cconj<T>(v[u]); },
+                [&](int u, cplx<T> y) { v[u] = cconj<T>(y); });
+        } else {
+            PhaseSeq ph(tid, RF, N);  // e^{i pi b / N} along b = tid + RF u
+            dft_forward<T, RF, RBU>(
+                buf, bhat, N, M, logM, true, tw, twn,
+                [&](int u) {
+                    const double2 e = ph.next();
+                    return cconj<T>(fold_bin_ph<T>(F, tid + RF * u, N, rN, shift, lmax, e));
+                },
+                [&](int u, cplx<T> y) { v[u] = cconj<T>(y); });
+        }
     }
     if (MODE == 0) {
 #pragma unroll
@@ -1402,6 +1511,19 @@ __global__ __launch_bounds__(RF) void k_ring_bfull(cplx<T> *__restrict__ FG, int
         }
     }
     const T om = (T)omega;
+    if (shortr) {
+        dft_forward<T, RF, RBU>(
+            buf, bhat, N, M, logM, true, tw, twn, [&](int u) { return v[u]; },
+            [&](int u, cplx<T> y) { v[u] = cscale<T>(y, om); });
+#pragma unroll
+        for (int u = 0; u < RBU; ++u) {
+            const int b = tid + RF * u;
+            if (b < N) buf[pd(b)] = v[u];
+        }
+        __syncthreads();
+        unfold_short<T>(F, buf, N, shift, lmax);
+        return;
+    }
     PhaseSeq ph(tid, RF, N);
     dft_forward<T, RF, RBU>(
         buf, bhat, N, M, logM, true, tw, twn, [&](int u) { return v[u]; },
@@ -1531,6 +1653,457 @@ __global__ __launch_bounds__(RF) void k_ring_b2(cplx<T> *__restrict__ FG, int64_
                 unfold_bin_ph<T>(F, 2 * (tid + RF * u) + q, N, rN, shift, lmax, cscale<T>(y, om), e);
             });
     }
+}
+
+// ================================================================================================
+// Register-resident ring transforms for transform lengths M = 2^LOGM, LOGM = 12 or 13 (the equatorial
+// belt and the long cap rings of Nside 1024 and 2048).  A workgroup of NT = M / 16 threads holds the
+// M points of a transform in registers, 16 per thread, and runs the radix-2 stages four at a time
+// in registers.  Between the three register passes the points move through LDS in two exchanges;
+// every access pattern is contiguous across lanes (or has stride 2 with one pad slot per 32), so the
+// exchanges are free of bank conflicts.  With the LDS holding one component at a time in FP64, two
+// rings share a compute unit.
+//
+// Layouts: in the layout of stride S, register k of thread t holds position
+//   pos = (t mod S) + S k + 16 S (t div S),
+// so the register index runs over the four position bits log2 S .. log2 S + 3.  The three layouts
+// have S0 = M / 16 (bits LOGM-1 .. LOGM-4: thread t holds t + NT k, the natural order of the fold
+// and the unfold), S1 = M / 256 and S2 = M / 4096 (bits 3..0 for LOGM = 12; bits 4..1 for
+// LOGM = 13, whose bit 0 is the lane's bit 0 and is crossed with a DPP swap of neighbouring lanes).
+//
+// A decimation-in-frequency transform (natural input, bit-reversed output) runs the passes S0, S1,
+// S2; a decimation-in-time transform (bit-reversed input, natural output) runs them back.  Between
+// the two the values sit at bit-reversed positions, where the pointwise step of each use happens:
+// the pixel weights W (belt rings: inverse DFT, x W, forward DFT) or the chirp spectrum of a
+// Bluestein convolution (forward FFT, x bhat, inverse FFT).
+// ================================================================================================
+template <int LOGM> struct R16 {
+    static constexpr int M = 1 << LOGM, NT = M / 16;
+    static constexpr int S0 = NT, S1 = 1 << (LOGM - 8), S2 = 1 << (LOGM - 12);
+};
+
+template <int S> __device__ __forceinline__ int lpos(int t, int k) { return (t & (S - 1)) + S * k + 16 * S * (t / S); }
+
+template <int LOGM> __device__ __forceinline__ int brevm(int p) { return (int)(__builtin_bitreverse32((unsigned)p) >> (32 - LOGM)); }
+
+// x, made opaque to the compiler at this point: loads indexed by it are not hoisted above it (keeps
+// the twiddle, weight and chirp-spectrum loads of a later phase from holding registers early)
+__device__ __forceinline__ int opaque(int x)
+{
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
+// z W_16^q, W_16 = e^{-2 pi i / 16} for sign -1 (its conjugate for +1), q in [0, 8) a constant after
+// unrolling
+template <typename T> __device__ __forceinline__ cplx<T> mul_w16(cplx<T> z, int q, int sign)
+{
+    switch (q) {
+    case 0: return z;
+    case 2: return rot8<T>(z, sign);
+    case 4: return rot4<T>(z, sign);
+    case 6: return rot8_3<T>(z, sign);
+    default: {
+        const T c1 = (T)0.92387953251128675613, s1 = (T)0.38268343236508977173;
+        const T c = q == 1 ? c1 : q == 3 ? s1 : q == 5 ? -s1 : -c1;
+        const T s = q == 1 ? s1 : q == 3 ? c1 : q == 5 ? c1 : s1;
+        return cmul<T>(z, mk<T>(c, sign < 0 ? -s : s));
+    }
+    }
+}
+
+// base twiddles of a pass at stride S: B[j] = W_{2 S 2^j}^u, u = t mod S (table e^{-2 pi i k / twn})
+template <typename T, int S>
+__device__ __forceinline__ void pass_tw(cplx<T> (&B)[4], const cplx<T> *__restrict__ tw, int twn, int t, int sign)
+{
+    const int u = opaque(t) & (S - 1);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) B[j] = twid<T>(tw, u * (twn / (S << (j + 1))), sign);
+}
+
+// four DIF stages of spans 8S, 4S, 2S, S: (a, b) -> (a + b, (a - b) W_{2h}^pos), pos = u + S (k mod 2^j)
+template <typename T, int S>
+__device__ __forceinline__ void dif_pass(cplx<T> (&v)[16], const cplx<T> *__restrict__ tw, int twn, int t, int sign)
+{
+    cplx<T> B[4];
+    if (S > 1) pass_tw<T, S>(B, tw, twn, t, sign);
+#pragma unroll
+    for (int j = 3; j >= 0; --j) {
+        const int s = 1 << j;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            if (k & s) continue;
+            const cplx<T> a = v[k], b = v[k + s];
+            v[k] = cadd<T>(a, b);
+            cplx<T> d = csub<T>(a, b);
+            if (S > 1) d = cmul<T>(d, B[j]);
+            v[k + s] = mul_w16<T>(d, (k & (s - 1)) << (3 - j), sign);
+        }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+// four DIT stages of spans S, 2S, 4S, 8S: (a, b) -> (a + w b, a - w b), w = W_{2h}^pos
+template <typename T, int S>
+__device__ __forceinline__ void dit_pass(cplx<T> (&v)[16], const cplx<T> *__restrict__ tw, int twn, int t, int sign)
+{
+    cplx<T> B[4];
+    if (S > 1) pass_tw<T, S>(B, tw, twn, t, sign);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int s = 1 << j;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            if (k & s) continue;
+            cplx<T> b = v[k + s];
+            if (S > 1) b = cmul<T>(b, B[j]);
+            b = mul_w16<T>(b, (k & (s - 1)) << (3 - j), sign);
+            const cplx<T> a = v[k];
+            v[k] = cadd<T>(a, b);
+            v[k + s] = csub<T>(a, b);
+        }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+// move the 16 registers of every thread from layout SA to layout SB through LDS (lds: M + M / 32
+// scalars of T when SPLIT, else as many complex values); the leading barrier retires the reads of
+// the previous exchange.  In every layout the padded slot of register k is the padded slot of
+// register 0 plus pd(S k), so each access is a base register plus a constant offset.
+template <typename T, bool SPLIT, int SA, int SB>
+__device__ __forceinline__ void exchange16(cplx<T> (&v)[16], T *lds, int t)
+{
+    const int tt = opaque(t);
+    const int ba = pd(lpos<SA>(tt, 0)), bb = pd(lpos<SB>(tt, 0));
+    if constexpr (SPLIT) {
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 16; ++k) lds[ba + pd(SA * k)] = v[k].x;
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 16; ++k) v[k].x = lds[bb + pd(SB * k)];
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 16; ++k) lds[ba + pd(SA * k)] = v[k].y;
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 16; ++k) v[k].y = lds[bb + pd(SB * k)];
+    } else {
+        cplx<T> *b = reinterpret_cast<cplx<T> *>(lds);
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 16; ++k) b[ba + pd(SA * k)] = v[k];
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 16; ++k) v[k] = b[bb + pd(SB * k)];
+    }
+}
+
+// the value of the neighbouring lane (lane ^ 1)
+template <typename T> __device__ __forceinline__ cplx<T> lane_swap1(cplx<T> z)
+{
+    return mk<T>(dpp_mov<0xB1>(z.x), dpp_mov<0xB1>(z.y));
+}
+
+// radix-2 stage on position bit 0 held across neighbouring lanes (LOGM = 13): (a, b) -> (a + b, a - b)
+// with a in the even lane; its twiddle is 1 in both directions
+template <typename T> __device__ __forceinline__ void lane_stage(cplx<T> (&v)[16], int c)
+{
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const cplx<T> p = lane_swap1<T>(v[k]);
+        v[k] = c ? csub<T>(p, v[k]) : cadd<T>(v[k], p);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+// full DIF from layout S0 (natural) to the bit-reversed positions of layout S2, all stages done
+template <typename T, int LOGM, bool SPLIT>
+__device__ __forceinline__ void fft16_dif(cplx<T> (&v)[16], T *lds, const cplx<T> *__restrict__ tw, int twn, int t,
+                                          int sign)
+{
+    using G = R16<LOGM>;
+    dif_pass<T, G::S0>(v, tw, twn, t, sign);
+    exchange16<T, SPLIT, G::S0, G::S1>(v, lds, t);
+    dif_pass<T, G::S1>(v, tw, twn, t, sign);
+    exchange16<T, SPLIT, G::S1, G::S2>(v, lds, t);
+    dif_pass<T, G::S2>(v, tw, twn, t, sign);
+    if constexpr (LOGM == 13) lane_stage<T>(v, t & 1);
+}
+
+// full DIT from the bit-reversed positions of layout S2 to the natural layout S0
+template <typename T, int LOGM, bool SPLIT>
+__device__ __forceinline__ void fft16_dit(cplx<T> (&v)[16], T *lds, const cplx<T> *__restrict__ tw, int twn, int t,
+                                          int sign)
+{
+    using G = R16<LOGM>;
+    if constexpr (LOGM == 13) lane_stage<T>(v, t & 1);
+    dit_pass<T, G::S2>(v, tw, twn, t, sign);
+    exchange16<T, SPLIT, G::S2, G::S1>(v, lds, t);
+    dit_pass<T, G::S1>(v, tw, twn, t, sign);
+    exchange16<T, SPLIT, G::S1, G::S0>(v, lds, t);
+    dit_pass<T, G::S0>(v, tw, twn, t, sign);
+}
+
+// e^{-i pi n^2 / N} along n = t + NT k, k = 0, 1, ... as running FP64 products (exact start values):
+// c_{k+1} = c_k r_k, r_{k+1} = r_k q
+struct ChirpSeq {
+    double2 c, r, q;
+    __device__ __forceinline__ ChirpSeq(int t, int NT, int N)
+    {
+        const int64_t twoN = 2 * (int64_t)N, tt = t, nt = NT;
+        c = cis_pi<double>(-((tt * tt) % twoN), N);
+        r = cis_pi<double>(-((2 * nt * tt + nt * nt) % twoN), N);
+        q = cis_pi<double>(-((2 * nt * nt) % twoN), N);
+    }
+    __device__ __forceinline__ double2 next()
+    {
+        const double2 o = c;
+        c = cmul<double>(c, r);
+        r = cmul<double>(r, q);
+        return o;
+    }
+};
+
+// keeps the compiler from moving memory accesses across this point: the per-register loops over
+// global memory run in groups of four, which bounds the registers that loads in flight hold
+__device__ __forceinline__ void mem_fence_compiler()
+{
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+// One Bluestein DFT of length L on v (natural order n = t + NT k, zero from n = L): chirp, forward
+// FFT, x bhat (the chirp spectrum in register order), inverse FFT, chirp
+template <typename T, int LOGM, bool SPLIT>
+__device__ __forceinline__ void bluestein16(cplx<T> (&v)[16], T *lds, const cplx<T> *__restrict__ tw, int twn, int t,
+                                            int L, const cplx<T> *__restrict__ bh)
+{
+    // the input is zero from n = L and L <= M / 2: registers 8 .. 15 start at zero, and their outputs
+    // (n >= M / 2) are not used
+    constexpr int NT = R16<LOGM>::NT;
+    {
+        ChirpSeq ch(opaque(t), NT, L);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = cmul<T>(v[k], to_t<T>(ch.next()));
+    }
+#pragma unroll
+    for (int k = 8; k < 16; ++k) v[k] = mk<T>(0, 0);
+    fft16_dif<T, LOGM, SPLIT>(v, lds, tw, twn, t, -1);
+    const int tt = opaque(t);
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        v[k] = cmul<T>(v[k], bh[k * NT + tt]);
+        if ((k & 3) == 3) mem_fence_compiler();
+    }
+    fft16_dit<T, LOGM, SPLIT>(v, lds, tw, twn, t, +1);
+    ChirpSeq ch(opaque(t), NT, L);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = cmul<T>(v[k], to_t<T>(ch.next()));
+}
+
+// fold of the bins b = NH n + q, n = t + NT k < L, into v (conjugated: the synthesis transform is
+// conj(DFT(conj X)))
+template <typename T, int NT, int NH>
+__device__ __forceinline__ void fold16_conj(cplx<T> (&v)[16], const cplx<T> *__restrict__ F, int t, int q, int L,
+                                            int N, float rN, int shift, int lmax)
+{
+    PhaseSeq ph(NH * t + q, NH * NT, N);  // e^{i pi b / N} along b = NH (t + NT k) + q
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {  // n < L <= 8 NT
+        const int n = t + NT * k, b = NH * n + q;
+        const double2 e = ph.next();
+        v[k] = n < L ? cconj<T>(fold_bin_ph<T>(F, b, N, rN, shift, lmax, e)) : mk<T>(0, 0);
+        if ((k & 3) == 3) mem_fence_compiler();
+    }
+}
+
+// unfold of the bins b = NH n + q, n = t + NT k < L, from v with the pixel area
+template <typename T, int NT, int NH, int K>
+__device__ __forceinline__ void unfold16(const cplx<T> (&v)[16], cplx<T> *__restrict__ G, int t, int q, int L, int N,
+                                         float rN, int shift, int lmax, T om)
+{
+    PhaseSeq ph(NH * t + q, NH * NT, N);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int n = t + NT * k;
+        const double2 e = ph.next();
+        if (n < L) unfold_bin_ph<T>(G, NH * n + q, N, rN, shift, lmax, cscale<T>(v[k], om), e);
+        if ((k & 3) == 3) mem_fence_compiler();
+    }
+}
+
+// The per-pixel step of one half of the registers: MODE 0 stores gamma, MODE 3 the gradient
+// epilogue, MODE 1 loads W (g1 + i g2), MODE 2 multiplies by W.  Pixel of register k: brev(pos) of
+// layout S2 (BREV), else p0 + NT k (below lim).
+template <typename T, int MODE, int LOGM, bool BREV, int K, int KA>
+__device__ __forceinline__ void pixels16(cplx<T> (&v)[KA], int tp, int p0, int lim, int64_t pofs, int64_t mofs,
+                                         const double *__restrict__ g1, const double *__restrict__ g2,
+                                         double *__restrict__ o1, double *__restrict__ o2, const double *__restrict__ Wt,
+                                         double omega, double *__restrict__ o3, const uint8_t *__restrict__ mask,
+                                         double cc)
+{
+    constexpr int NT = R16<LOGM>::NT;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int j = BREV ? brevm<LOGM>(lpos<R16<LOGM>::S2>(tp, k)) : p0 + NT * k;
+        const bool live = BREV || tp + NT * k < lim;
+        if (MODE == 0) {
+            if (live) {
+                o1[pofs + j] = (double)v[k].x;
+                o2[pofs + j] = (double)v[k].y;
+            }
+        } else if (MODE == 3) {
+            if (live) {
+                const int64_t pix = pofs + j;
+                const double q1 = o1[pix], q2 = o2[pix];
+                const double r1 = g1[pix] - (double)v[k].x, r2 = g2[pix] - (double)v[k].y;
+                o3[pix] = mask[mofs + j] ? omega * (q1 * r1 + q2 * r2) - cc : 0.0;
+                const double w = omega * Wt[pix];
+                o1[pix] = w * q1;
+                o2[pix] = w * q2;
+            }
+        } else if (!live) {
+            v[k] = mk<T>(0, 0);
+        } else if (MODE == 1) {
+            const int64_t pix = pofs + j;
+            const T w = Wt ? (T)Wt[pix] : (T)1;
+            v[k] = mk<T>((T)g1[pix] * w, (T)g2[pix] * w);
+        } else {
+            v[k] = cscale<T>(v[k], (T)Wt[pofs + j]);
+        }
+        if ((k & 3) == 3) mem_fence_compiler();
+    }
+}
+
+// Ring kernel of the register engine.  KIND 0: rings whose length N is the transform length M (an
+// inverse DIF FFT to the pixels, a forward DIT FFT back).  KIND 1: rings transformed whole by
+// Bluestein's chirp-z with a convolution of length M >= 2N - 1.  KIND 2: rings of even length N = 2L
+// split into two interleaved sub-transforms of length L over the even and odd bins, each by Bluestein
+// with M >= 2L - 1, combined by a radix-2 step in registers:
+//   synthesis  gamma[j] = Y0[j] + w^j Y1[j],  gamma[j + L] = Y0[j] - w^j Y1[j],  w = e^{2 pi i / N}
+//   adjoint    u_q[j] = w^{-q j} (h[j] + (-1)^q h[j + L]),  bins 2 k + q = DFT_L(u_q)[k].
+// bhat_r holds the chirp spectrum of the transformed length in register order (thread t, register k
+// of layout S2 at index k NT + t).  MODE as for the other ring kernels.
+template <typename T> struct Ring16Waves {
+    // FP64 holds 16 complex values and, in the split form, a second set of 16 per thread
+    static constexpr int value = std::is_same<T, double>::value ? 2 : 4;
+};
+
+template <typename T, int MODE, int LOGM, int KIND>
+__global__ __launch_bounds__(R16<LOGM>::NT) __attribute__((amdgpu_waves_per_eu(Ring16Waves<T>::value))) void k_ring16(
+    cplx<T> *__restrict__ FG, int64_t fg_stride, const double *__restrict__ g1, const double *__restrict__ g2,
+    double *__restrict__ o1, double *__restrict__ o2, int64_t map_stride, const double *__restrict__ Wt,
+    const RingInfo *__restrict__ rings, const int *__restrict__ order, const cplx<T> *__restrict__ tw, int twn,
+    int lmax, double omega, double *__restrict__ o3, const uint8_t *__restrict__ mask, const double *__restrict__ cdev,
+    const cplx<T> *__restrict__ bhat_r)
+{
+    using G = R16<LOGM>;
+    constexpr int NT = G::NT;
+    constexpr int NH = KIND == 2 ? 2 : 1;  // sub-transforms per ring
+    // exchanges one component at a time in FP64, and in FP32 for the split rings, which also keep
+    // one half-ring in LDS (two workgroups per compute unit either way)
+    constexpr bool SPLIT = std::is_same<T, double>::value || KIND == 2;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *lds = reinterpret_cast<T *>(smem_raw);
+    // KIND 2: the half-ring waiting while the other is transformed, thread t's register k at k NT + t
+    cplx<T> *stash = reinterpret_cast<cplx<T> *>(lds + (G::M + G::M / 32));
+    const int r = order[blockIdx.x];
+    const int rhs = blockIdx.y;
+    const RingInfo ri = rings[r];
+    const int N = ri.nphi, shift = ri.shift;
+    const int L = KIND == 2 ? N / 2 : N;  // transformed length
+    cplx<T> *F = FG + rhs * fg_stride + (int64_t)r * (lmax + 1) * 2;
+    const int t = threadIdx.x;
+    const int64_t pofs = rhs * map_stride + ri.ofs;
+    const float rN = 1.0f / (float)N;
+    const cplx<T> *bh = KIND ? bhat_r + ri.rofs : nullptr;
+    cplx<T> v[16];
+    cplx<T> u[KIND == 2 ? 8 : 1];  // KIND 2: the values at pixels n + L (n = t + NT k < L <= 8 NT)
+    auto stash_put = [&](const cplx<T> *a) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) stash[k * NT + t] = a[k];
+    };
+    auto stash_get = [&](cplx<T> *a) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) a[k] = stash[k * NT + t];
+    };
+
+    if (MODE != 1) {
+        // gamma_j = sum_b X_b e^{+2 pi i b j / N}
+        if constexpr (KIND == 0) {
+            PhaseSeq ph(t, NT, N);  // e^{i pi b / N} along b = t + NT k
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                v[k] = fold_bin_ph<T>(F, t + NT * k, N, rN, shift, lmax, ph.next());
+                if ((k & 3) == 3) mem_fence_compiler();
+            }
+            fft16_dif<T, LOGM, SPLIT>(v, lds, tw, twn, t, +1);  // gamma at pixel brev(pos)
+        } else {
+            fold16_conj<T, NT, NH>(v, F, t, 0, L, N, rN, shift, lmax);
+            bluestein16<T, LOGM, SPLIT>(v, lds, tw, twn, t, L, bh);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) v[k] = cconj<T>(v[k]);
+            if constexpr (KIND == 2) {
+                // Y0 waits in LDS while Y1 is transformed in v (each thread reads back its own slots)
+                stash_put(v);
+                fold16_conj<T, NT, NH>(v, F, t, 1, L, N, rN, shift, lmax);
+                bluestein16<T, LOGM, SPLIT>(v, lds, tw, twn, t, L, bh);
+                stash_get(u);
+                PhaseSeq pw(2 * t, 2 * NT, N);  // e^{2 pi i n / N}
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const cplx<T> a = u[k], b = cmul<T>(to_t<T>(pw.next()), cconj<T>(v[k]));
+                    v[k] = cadd<T>(a, b);
+                    u[k] = csub<T>(a, b);
+                }
+            }
+        }
+    }
+    const int tp = opaque(t);
+    const double cc = MODE == 3 ? *cdev : 0.0;
+    pixels16<T, MODE, LOGM, KIND == 0, KIND == 0 ? 16 : 8, 16>(v, tp, tp, L, pofs, ri.ofs, g1, g2, o1, o2, Wt, omega,
+                                                               o3, mask, cc);
+    if constexpr (KIND == 2)
+        pixels16<T, MODE, LOGM, false, 8, 8>(u, tp, tp + L, L, pofs, ri.ofs, g1, g2, o1, o2, Wt, omega, o3, mask, cc);
+    if (MODE == 0 || MODE == 3) return;
+    // Y_b = sum_j h_j e^{-2 pi i b j / N}, then unfold with the pixel area
+    const T om = (T)omega;
+    if constexpr (KIND == 0) {
+        fft16_dit<T, LOGM, SPLIT>(v, lds, tw, twn, t, -1);  // natural bins b = t + NT k
+        unfold16<T, NT, 1, 16>(v, F, t, 0, N, N, rN, shift, lmax, om);
+    } else {
+        if constexpr (KIND == 2) {
+            PhaseSeq pw(2 * t, 2 * NT, N);  // e^{2 pi i n / N}
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const cplx<T> a = v[k], b = u[k];
+                v[k] = cadd<T>(a, b);
+                u[k] = cmul<T>(cconj<T>(to_t<T>(pw.next())), csub<T>(a, b));
+            }
+        }
+        if constexpr (KIND == 2) stash_put(u);
+        bluestein16<T, LOGM, SPLIT>(v, lds, tw, twn, t, L, bh);
+        unfold16<T, NT, NH, 8>(v, F, t, 0, L, N, rN, shift, lmax, om);
+        if constexpr (KIND == 2) {
+            stash_get(v);
+            bluestein16<T, LOGM, SPLIT>(v, lds, tw, twn, t, L, bh);
+            unfold16<T, NT, NH, 8>(v, F, t, 1, L, N, rN, shift, lmax, om);
+        }
+    }
+}
+
+// Chirp spectra of the register-engine Bluestein rings in register order: out[o + k NT + t] =
+// bhat[brev(pos)] with pos the layout-S2 position of register k of thread t (one block per length).
+template <typename T, int LOGM>
+__global__ void k_bhat_reorder(const cplx<T> *__restrict__ bhat, const int64_t *__restrict__ src_ofs,
+                               const int64_t *__restrict__ dst_ofs, cplx<T> *__restrict__ out)
+{
+    using G = R16<LOGM>;
+    const int64_t so = src_ofs[blockIdx.x], d = dst_ofs[blockIdx.x];
+    for (int t = threadIdx.x; t < G::NT; t += blockDim.x)
+#pragma unroll
+        for (int k = 0; k < 16; ++k) out[d + k * G::NT + t] = bhat[so + brevm<LOGM>(lpos<G::S2>(t, k))];
 }
 
 // ================================================================================================
@@ -2283,14 +2856,15 @@ static void ring_launch_t(Plan &P, const double *g1, const double *g2, double *o
     const cplx<T> *bh = (const cplx<T> *)(std::is_same<T, double>::value ? P.d_bhat64 : P.d_bhat32);
     if (P.n_p2) {
         // whole rings: N = 4 sub <= 4 nside <= 8192 = RF RFU (nside <= 2048 is enforced at plan creation)
-        const size_t nmax = 4 * (size_t)P.maxM_p2;
+        const size_t nmax = std::max((size_t)RF, 4 * (size_t)P.maxM_p2);  // RF: the short-ring fold
         size_t sm = sizeof(cplx<T>) * (nmax + nmax / 32);
         k_ring_full<T, MODE><<<dim3(P.n_p2, nrhs), RF, sm, P.stream>>>(
             (cplx<T> *)P.d_FG, fg_stride, g1, g2, o1, o2, P.npix, W, P.d_rings, P.d_order_p2, (const cplx<T> *)tw,
             P.twn, P.lmax, P.omega, o3, mask, cdev);
     }
     if (P.n_bf) {
-        size_t sm = sizeof(cplx<T>) * (size_t)(P.maxM_bf + P.maxM_bf / 32);
+        const size_t nmax = std::max((size_t)RF, (size_t)P.maxM_bf);  // RF: the short-ring fold
+        size_t sm = sizeof(cplx<T>) * (nmax + nmax / 32);
         k_ring_bfull<T, MODE><<<dim3(P.n_bf, nrhs), RF, sm, P.stream>>>(
             (cplx<T> *)P.d_FG, fg_stride, g1, g2, o1, o2, P.npix, W, P.d_rings, P.d_order_bf, (const cplx<T> *)tw,
             P.twn, P.lmax, P.omega, o3, mask, cdev, bh);
@@ -2301,6 +2875,24 @@ static void ring_launch_t(Plan &P, const double *g1, const double *g2, double *o
             (cplx<T> *)P.d_FG, fg_stride, g1, g2, o1, o2, P.npix, W, P.d_rings, P.d_order_bl, (const cplx<T> *)tw,
             P.twn, P.lmax, P.omega, o3, mask, cdev, bh);
     }
+    // register engine: LDS of M + M / 32 components (FP64, one component at a time) or complex values (FP32)
+    const cplx<T> *bhr = (const cplx<T> *)(std::is_same<T, double>::value ? P.d_bhatr64 : P.d_bhatr32);
+    auto reg = [&](auto kern, int q, int M) {
+        if (!P.n_r[q]) return;
+        const bool split_ring = q >= 4;  // KIND 2: one-component exchanges and a half-ring stash
+        const size_t sm = ((std::is_same<T, double>::value || split_ring) ? sizeof(T) : sizeof(cplx<T>)) *
+                              (size_t)(M + M / 32) +
+                          (split_ring ? sizeof(cplx<T>) * (size_t)(M / 2) : 0);
+        kern<<<dim3(P.n_r[q], nrhs), M / 16, sm, P.stream>>>(
+            (cplx<T> *)P.d_FG, fg_stride, g1, g2, o1, o2, P.npix, W, P.d_rings, P.d_order_r[q], (const cplx<T> *)tw,
+            P.twn, P.lmax, P.omega, o3, mask, cdev, bhr);
+    };
+    reg(k_ring16<T, MODE, 13, 2>, 5, 8192);
+    reg(k_ring16<T, MODE, 13, 0>, 1, 8192);
+    reg(k_ring16<T, MODE, 13, 1>, 3, 8192);
+    reg(k_ring16<T, MODE, 12, 2>, 4, 4096);
+    reg(k_ring16<T, MODE, 12, 0>, 0, 4096);
+    reg(k_ring16<T, MODE, 12, 1>, 2, 4096);
 }
 
 // Spectra of the Bluestein chirps, one per distinct sub-transform length L (plan creation):
@@ -2327,6 +2919,21 @@ __global__ __launch_bounds__(RT) void k_bhat(const int *__restrict__ Ls, const i
         const double2 v = cscale<double>(buf[pd(n)], inv);
         b64[o + n] = v;
         b32[o + n] = make_float2((float)v.x, (float)v.y);
+    }
+}
+
+void launch_bhat_reorder(Plan &P, int logm, const int64_t *src_ofs, const int64_t *dst_ofs, int n)
+{
+    if (logm == 13) {
+        k_bhat_reorder<double, 13><<<n, 256, 0, P.stream>>>((const double2 *)P.d_bhat64, src_ofs, dst_ofs,
+                                                            (double2 *)P.d_bhatr64);
+        k_bhat_reorder<float, 13><<<n, 256, 0, P.stream>>>((const float2 *)P.d_bhat32, src_ofs, dst_ofs,
+                                                           (float2 *)P.d_bhatr32);
+    } else {
+        k_bhat_reorder<double, 12><<<n, 256, 0, P.stream>>>((const double2 *)P.d_bhat64, src_ofs, dst_ofs,
+                                                            (double2 *)P.d_bhatr64);
+        k_bhat_reorder<float, 12><<<n, 256, 0, P.stream>>>((const float2 *)P.d_bhat32, src_ofs, dst_ofs,
+                                                           (float2 *)P.d_bhatr32);
     }
 }
 

@@ -25,6 +25,7 @@ namespace akra {
 static thread_local std::string g_err;
 // largest whole-ring Bluestein convolution of plans created afterwards (akra_set_ring_whole_maxm)
 static int g_ring_whole_maxm = 8192;
+static int g_ring_register = 1;
 void set_error(const std::string &msg) { g_err = msg; }
 akra_status hip_fail(hipError_t e, const char *what)
 {
@@ -248,7 +249,8 @@ static void free_plan(Plan *P)
     void *ptrs[] = {P->d_rings, P->d_pair_z, P->d_coef64, P->d_coef32, P->d_coef64s, P->d_coef32s, P->d_recu,
                     P->d_seed2, P->d_seedm2, P->d_seedk,
                     P->d_ent, P->d_entk, P->d_entl, P->d_wgstart, P->d_wgstart_b, P->d_coef32d, P->d_brec,
-                    P->d_tw64, P->d_tw32, P->d_bhat64, P->d_bhat32, P->d_lof, P->d_order_p2, P->d_order_bl, P->d_order_bf, P->d_FG, P->d_part, P->d_rec, P->d_W, P->d_kern, P->d_kuser, P->d_red, P->d_red_cg, P->d_scal, P->d_flag, P->d_x, P->d_r,
+                    P->d_tw64, P->d_tw32, P->d_bhat64, P->d_bhat32, P->d_bhatr64, P->d_bhatr32, P->d_order_r[0], P->d_order_r[1],
+                    P->d_order_r[2], P->d_order_r[3], P->d_order_r[4], P->d_order_r[5], P->d_lof, P->d_order_p2, P->d_order_bl, P->d_order_bf, P->d_FG, P->d_part, P->d_rec, P->d_W, P->d_kern, P->d_kuser, P->d_red, P->d_red_cg, P->d_scal, P->d_flag, P->d_x, P->d_r,
                     P->d_p, P->d_w, P->d_b, P->d_xs, P->d_cmp, P->d_spec};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
@@ -294,34 +296,53 @@ static akra_status create(int nside, int lmax, int nrhs, int prec, void *stream,
     // ring launch lists, largest first: power-of-two rings (whole-ring FFT), rings whose whole-ring
     // Bluestein convolution fits in LDS (M <= BF_MAXM), and the rest as two sub-transforms of length
     // N / 2, each by Bluestein (M <= 8192 since N <= 4 nside <= 8192)
+    // Rings whose transform length is 4096 or 8192 (a whole power-of-two ring, or a whole-ring
+    // Bluestein convolution) go to the register engine unless it is switched off.
     const int BF_MAXM = g_ring_whole_maxm;
-    std::vector<int> p2, bl, bf;
-    int maxp2 = 1, maxbl = 1, maxbf = 1;
+    std::vector<int> p2, bl, bf, rl[6];
+    int maxp2 = 1, maxbl = 1, maxbf = 1, maxreg = 1;  // the LDS kernels' lists, and the register engine
     for (int r = 0; r < P->nrings; ++r) {
         RingInfo &ri = P->h_rings[r];
         if (!ri.M) {
-            p2.push_back(r);
-            maxp2 = std::max(maxp2, ri.sub);
+            if (g_ring_register && (ri.nphi == 4096 || ri.nphi == 8192)) {
+                rl[ri.nphi == 4096 ? 0 : 1].push_back(r);
+                maxreg = std::max(maxreg, ri.nphi);
+            } else {
+                p2.push_back(r);
+                maxp2 = std::max(maxp2, ri.sub);
+            }
             continue;
         }
         int MF = 1;
         while (MF < 2 * ri.nphi - 1) MF <<= 1;
         if (MF <= BF_MAXM) {
             ri.M = MF;  // the whole ring's convolution length
-            bf.push_back(r);
-            maxbf = std::max(maxbf, MF);
+            if (g_ring_register && (MF == 4096 || MF == 8192)) {
+                rl[MF == 4096 ? 2 : 3].push_back(r);
+                maxreg = std::max(maxreg, MF);
+            } else {
+                bf.push_back(r);
+                maxbf = std::max(maxbf, MF);
+            }
         } else {
             int M2 = 1;
             while (M2 < ri.nphi - 1) M2 <<= 1;  // 2 (N / 2) - 1
             ri.M = M2;
-            bl.push_back(r);
-            maxbl = std::max(maxbl, M2);
+            if (g_ring_register && (M2 == 4096 || M2 == 8192)) {
+                rl[M2 == 4096 ? 4 : 5].push_back(r);
+                maxreg = std::max(maxreg, M2);
+            } else {
+                bl.push_back(r);
+                maxbl = std::max(maxbl, M2);
+            }
         }
     }
     auto bysize = [&](int a, int b) { return P->h_rings[a].nphi > P->h_rings[b].nphi; };
     std::stable_sort(p2.begin(), p2.end(), bysize);
     std::stable_sort(bl.begin(), bl.end(), bysize);
     std::stable_sort(bf.begin(), bf.end(), bysize);
+    for (auto &v : rl) std::stable_sort(v.begin(), v.end(), bysize);
+    for (int q = 0; q < 6; ++q) P->n_r[q] = (int)rl[q].size();
     P->n_p2 = (int)p2.size();
     P->n_bl = (int)bl.size();
     P->n_bf = (int)bf.size();
@@ -329,7 +350,7 @@ static akra_status create(int nside, int lmax, int nrhs, int prec, void *stream,
     P->maxM_bl = maxbl;
     P->maxM_bf = maxbf;
     // twiddles for the Bluestein convolutions and for whole power-of-two rings (N = 4 sub)
-    P->twn = std::max(2, std::max(4 * maxp2, std::max(maxbl, maxbf)));
+    P->twn = std::max(std::max(2, maxreg), std::max(4 * maxp2, std::max(maxbl, maxbf)));
     // one chirp spectrum per distinct chirp length: N / 2 for the split rings, N for the whole-ring
     // ones (the two caps share them)
     std::vector<int> bL, bM;
@@ -350,6 +371,27 @@ static akra_status create(int nside, int lmax, int nrhs, int prec, void *stream,
         };
         for (int r : bl) key(r, P->h_rings[r].nphi / 2);
         for (int r : bf) key(r, P->h_rings[r].nphi);
+        for (int q = 2; q < 6; ++q)
+            for (int r : rl[q]) key(r, q < 4 ? P->h_rings[r].nphi : P->h_rings[r].nphi / 2);
+    }
+    // the register engine's chirp spectra in register order, one per distinct transformed length
+    // (lists 2 and 4 transform in 4096 points, 3 and 5 in 8192)
+    std::vector<int64_t> rsrc[2], rdst[2];
+    int64_t rtot = 0;
+    {
+        std::vector<int64_t> at(4 * (size_t)P->nside + 1, -1);
+        for (int q = 2; q < 6; ++q)
+            for (int r : rl[q]) {
+                RingInfo &ri = P->h_rings[r];
+                const int len = q < 4 ? ri.nphi : ri.nphi / 2;
+                if (at[len] < 0) {
+                    at[len] = rtot;
+                    rsrc[(q & 1) ? 1 : 0].push_back(ri.bofs);
+                    rdst[(q & 1) ? 1 : 0].push_back(rtot);
+                    rtot += ri.M;
+                }
+                ri.rofs = at[len];
+            }
     }
 
     // near-polar groups of FP32 plans: first pair of the group within theta_c of a pole
@@ -416,6 +458,8 @@ static akra_status create(int nside, int lmax, int nrhs, int prec, void *stream,
         AK_TRY(upload((void **)&P->d_order_p2, p2.data(), p2.size() * sizeof(int), *P));
         AK_TRY(upload((void **)&P->d_order_bl, bl.data(), bl.size() * sizeof(int), *P));
         AK_TRY(upload((void **)&P->d_order_bf, bf.data(), bf.size() * sizeof(int), *P));
+        for (int q = 0; q < 6; ++q)
+            if (!rl[q].empty()) AK_TRY(upload((void **)&P->d_order_r[q], rl[q].data(), rl[q].size() * sizeof(int), *P));
     }
     // entry states of the recurrence (the seeds are only needed to build them)
     {
@@ -462,7 +506,7 @@ static akra_status create(int nside, int lmax, int nrhs, int prec, void *stream,
                   hipMemcpy(dM, bM.data(), nb * sizeof(int), hipMemcpyHostToDevice) == hipSuccess &&
                   hipMemcpy(dO, bO.data(), nb * sizeof(int64_t), hipMemcpyHostToDevice) == hipSuccess;
         if (ok) {
-            launch_bhat(*P, dL, dM, dO, (int)nb, std::max(P->maxM_bl, P->maxM_bf));
+            launch_bhat(*P, dL, dM, dO, (int)nb, std::max(std::max(P->maxM_bl, P->maxM_bf), maxreg));
             ok = hipGetLastError() == hipSuccess && hipStreamSynchronize(P->stream) == hipSuccess;
         }
         for (void *q : {(void *)dL, (void *)dM, (void *)dO})
@@ -470,6 +514,31 @@ static akra_status create(int nside, int lmax, int nrhs, int prec, void *stream,
         if (!ok) {
             free_plan(P);
             set_error("chirp-spectrum kernel failed");
+            return AKRA_ERR_HIP;
+        }
+    }
+    if (rtot > 0) {
+        AK_TRY(alloc(&P->d_bhatr64, (size_t)rtot * sizeof(double2), *P));
+        AK_TRY(alloc(&P->d_bhatr32, (size_t)rtot * sizeof(float2), *P));
+        bool ok = true;
+        for (int q = 0; q < 2 && ok; ++q) {
+            const size_t nb = rsrc[q].size();
+            if (!nb) continue;
+            int64_t *dS = nullptr, *dD = nullptr;
+            ok = hipMalloc((void **)&dS, nb * sizeof(int64_t)) == hipSuccess &&
+                 hipMalloc((void **)&dD, nb * sizeof(int64_t)) == hipSuccess &&
+                 hipMemcpy(dS, rsrc[q].data(), nb * sizeof(int64_t), hipMemcpyHostToDevice) == hipSuccess &&
+                 hipMemcpy(dD, rdst[q].data(), nb * sizeof(int64_t), hipMemcpyHostToDevice) == hipSuccess;
+            if (ok) {
+                launch_bhat_reorder(*P, q ? 13 : 12, dS, dD, (int)nb);
+                ok = hipGetLastError() == hipSuccess && hipStreamSynchronize(P->stream) == hipSuccess;
+            }
+            for (void *d : {(void *)dS, (void *)dD})
+                if (d) (void)hipFree(d);
+        }
+        if (!ok) {
+            free_plan(P);
+            set_error("chirp-spectrum reordering kernel failed");
             return AKRA_ERR_HIP;
         }
     }
@@ -1743,6 +1812,12 @@ akra_status akra_plan_set_tuning(akra_plan plan, int syn_variant, int syn_rings,
     P.adj_L = adj_chunk;
     P.adj_nrb = nrb;
     compute_work(P);
+    return AKRA_OK;
+}
+
+akra_status akra_set_ring_register_engine(int on)
+{
+    g_ring_register = on != 0;
     return AKRA_OK;
 }
 

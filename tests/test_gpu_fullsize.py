@@ -13,8 +13,9 @@ pytestmark = pytest.mark.gpu
 
 NSIDE, LMAX = 2048, 4096
 TOL = {"fp64": 1e-10, "fp32": 1e-5}
-# north pole, cap, last cap ring, belt, equator, south belt, south cap, south pole
-RINGS = [0, 5, 1500, 2046, 4095, 7000, 8190]
+# north pole, cap (LDS kernels; register engine: Bluestein of 4096 and 8192 points, the
+# power-of-two cap ring of 4096), last cap ring, belt, equator, south belt, south cap, south pole
+RINGS = [0, 5, 300, 700, 1023, 1500, 2046, 4095, 7000, 7490, 8190]
 MS = [0, 1, 2, 1000, 3333, 4096]
 
 
