@@ -264,6 +264,18 @@ akra_status akra_plan_set_tuning(akra_plan plan, int syn_variant, int syn_rings,
                                  int adj_chunk);
 akra_status akra_plan_get_tuning(akra_plan plan, int *out5);
 /*
+ * Launch shapes of the batched matrix-core Legendre kernels (FP32 plans with nrhs > 1): syn_waves
+ * 64-pair ring groups (one per wave) per workgroup of the batched synthesis, in {1, 2, 4, 8};
+ * adj_waves groups per workgroup of the batched adjoint, in {2, 4, 8}, whose waves are summed in LDS
+ * into one partial-sum slab per workgroup (fewer waves: more slabs for the epilogue to add).  The
+ * default is (4, 4); results do not depend on the shapes beyond the rounding order of the adjoint's
+ * sums.  Synchronises the plan stream and drops a recorded iteration.  akra_plan_get_tuning_batched
+ * writes the two current values to out2 (HOST).  Errors: AKRA_ERR_ARG (other values, or a plan that
+ * is not FP32 with several right-hand sides), AKRA_ERR_HIP.
+ */
+akra_status akra_plan_set_tuning_batched(akra_plan plan, int syn_waves, int adj_waves);
+akra_status akra_plan_get_tuning_batched(akra_plan plan, int *out2);
+/*
  * Work of one Legendre launch, in (l, m, ring pair) triples, written to out3 (HOST): [0] all triples
  * with max(2, m) <= l <= lmax; [1] those the synthesis evaluates and [2] those the adjoint evaluates
  * with the current launch shapes.  Below the degree where the recurrence values of a whole 64-pair

@@ -79,6 +79,8 @@ def lib():
     L.akra_plan_set_graph.argtypes = [vp, ctypes.c_int]
     L.akra_plan_set_tuning.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     L.akra_plan_get_tuning.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
+    L.akra_plan_set_tuning_batched.argtypes = [vp, ctypes.c_int, ctypes.c_int]
+    L.akra_plan_get_tuning_batched.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
     L.akra_plan_work.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
     L.akra_plan_work_batched.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
     L.akra_cg_solve_vjp.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(CgOpts), vp, vp, vp, vp, vp, vp, vp,
@@ -114,6 +116,7 @@ def lib():
     for f in ("akra_plan_create", "akra_synth2", "akra_adjoint2", "akra_apply_H", "akra_rhs", "akra_cg_solve",
               "akra_cg_solve_b", "akra_cg_start", "akra_cg_step", "akra_cg_state", "akra_plan_set_timing",
               "akra_plan_stage_times", "akra_plan_set_tuning", "akra_plan_get_tuning", "akra_plan_work",
+              "akra_plan_set_tuning_batched", "akra_plan_get_tuning_batched",
               "akra_plan_work_batched",
               "akra_cg_solve_vjp", "akra_cg_solve_cond_b", "akra_set_ring_whole_maxm", "akra_set_ring_register_engine", "akra_unmasked_index",
               "akra_shuffle_shear", "akra_alm_spectra", "akra_alm_spectra_noalloc", "akra_noise_work_size", "akra_noise_spectra", "akra_ang2pix",
@@ -203,11 +206,15 @@ class Plan:
                                       ctypes.c_void_p(s.cuda_stream), ctypes.byref(h)))
         self._h = h
         if tuned:
-            from .tune import lookup
+            from .tune import lookup, lookup_batched
             e = lookup(self.nside, self.lmax, precision)
             if e:
                 self.set_tuning(e["syn_variant"], e["syn_rings"], e["adj_rings"], e["adj_waves"],
                                 e.get("adj_chunk", 8))
+            if precision == "fp32" and self.nrhs > 1:
+                b = lookup_batched(self.nside, self.lmax, self.nrhs)
+                if b:
+                    self.set_tuning_batched(b["syn_waves"], b["adj_waves"])
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -567,6 +574,15 @@ class Plan:
     def get_tuning(self):
         v = (ctypes.c_int * 5)()
         _check(lib().akra_plan_get_tuning(self._h, v))
+        return tuple(v)
+
+    def set_tuning_batched(self, syn_waves, adj_waves):
+        """Waves per workgroup of the batched matrix-core synthesis and adjoint (FP32, nrhs > 1)."""
+        _check(lib().akra_plan_set_tuning_batched(self._h, int(syn_waves), int(adj_waves)))
+
+    def get_tuning_batched(self):
+        v = (ctypes.c_int * 2)()
+        _check(lib().akra_plan_get_tuning_batched(self._h, v))
         return tuple(v)
 
     def work(self):

@@ -139,6 +139,9 @@ struct Plan {
     // FP32 plans: the 64-pair groups nearest the poles run the Legendre stages in the difference
     // form; the adjoint covers them with adj_nrb_polar ring blocks of four groups
     int polar_groups = 0, adj_nrb_polar = 0;
+    // batched matrix-core kernels: waves (64-pair groups) per workgroup of the synthesis and the
+    // adjoint; nrb_b adjoint ring blocks of bat_AW groups (the buffers hold those of bat_AW = 2)
+    int bat_SW = 4, bat_AW = 4, nrb_b_cap = 0;
 
     // workspaces (sized for FP64; FP32 views reuse them)
     void *d_FG = nullptr;       // [nrhs][nrings][lmax+1][2] complex

@@ -2351,8 +2351,9 @@ __device__ __forceinline__ void swap_halves(float &a, float &b)
     b = __int_as_float(r[1]);
 }
 
-template <int F>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_leg_synth_b(const float *__restrict__ brec,
+// SW waves (64-pair groups) per workgroup, a launch shape of the autotuner
+template <int F, int SW>
+__global__ __launch_bounds__(64 * SW) __attribute__((amdgpu_waves_per_eu(2))) void k_leg_synth_b(const float *__restrict__ brec,
                                                      const typename CoefB<F>::type *__restrict__ coef,
                                                      float2 *__restrict__ FG, int64_t fg_stride,
                                                      const Ent64 *__restrict__ ent, const int *__restrict__ entk,
@@ -2364,7 +2365,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     int m, blk;
     xcd_map((int)blockIdx.x, nbm, m, blk);
-    const int w = wbeg + blk * 4 + wave;  // 64-pair group: pairs 64 w .. 64 w + 63
+    const int w = wbeg + blk * SW + wave;  // 64-pair group: pairs 64 w .. 64 w + 63
     if (m > lmax || w >= wend) return;
     const int l0 = m > 2 ? m : 2;
     const int64_t base = (int64_t)m * (2 * lmax + 1 - m) / 2;
@@ -2463,7 +2464,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 }
 
 // ================================================================================================
-// Batched FP32 Legendre adjoint on the matrix cores.  For one m, a block of ABW 64-pair groups (one per
+// Batched FP32 Legendre adjoint on the matrix cores.  For one m, a block of AW 64-pair groups (one per
 // wave) and the NBR right-hand sides of group q, the partial sums over the block's ring pairs
 //   out_rhs[l][c],  c = 0..3 as in k_leg_adj (2h_lm and -2h_lm, Re and Im).
 // Per chunk of ABL = 32 degrees each wave writes the recurrence values of its pairs to LDS (one row
@@ -2477,12 +2478,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 // [rhs - NBR q][nrb][nalm][4], rows from the chunk holding the block's first entry degree (recorded in
 // wgstart) to lmax.
 // ================================================================================================
-constexpr int ABW = 4;   // waves (64-pair groups) per workgroup
+// AW waves (64-pair groups) per workgroup is a launch shape of the autotuner (2, 4 or 8)
 constexpr int ABL = 32;  // degrees per chunk: the rows of the MFMA
 constexpr int ABS = 33;  // LDS stride of one pair's 32 rows (bank-conflict-free writes)
 
-template <int F>
-__global__ __launch_bounds__(64 * ABW) void k_leg_adj_b(const float2 *__restrict__ FG, int64_t fg_stride,
+template <int F, int AW>
+__global__ __launch_bounds__(64 * AW) void k_leg_adj_b(const float2 *__restrict__ FG, int64_t fg_stride,
                                                         const typename CoefB<F>::type *__restrict__ coef,
                                                         const Ent64 *__restrict__ ent, const int *__restrict__ entk,
                                                         const int *__restrict__ entl, int ng64,
@@ -2491,19 +2492,19 @@ __global__ __launch_bounds__(64 * ABW) void k_leg_adj_b(const float2 *__restrict
                                                         int nrings, int nrhs, int q, int g0, int gend, int rb0,
                                                         int nrbl, int nrb)
 {
-    __shared__ float lam[ABW][2][64 * ABS];  // per wave: lambda+ and lambda- of its 64 pairs x 32 rows
+    __shared__ float lam[AW][2][64 * ABS];  // per wave: lambda+ and lambda- of its 64 pairs x 32 rows
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     int m, rbl;
     xcd_map((int)blockIdx.x, nrbl, m, rbl);
     if (m > lmax) return;
     const int rb = rb0 + rbl;
-    const int gb = g0 + rbl * ABW;  // first group of the block
+    const int gb = g0 + rbl * AW;  // first group of the block
     const int l0 = m > 2 ? m : 2;
     const int64_t base = (int64_t)m * (2 * lmax + 1 - m) / 2;
     const_as<int> *el = uniform_ptr(entl + (int64_t)m * ng64);
     int ls = ENT_SKIP;
-    for (int g = gb; g < gb + ABW && g < gend; ++g) ls = el[g] < ls ? el[g] : ls;
+    for (int g = gb; g < gb + AW && g < gend; ++g) ls = el[g] < ls ? el[g] : ls;
     if (threadIdx.x == 0) wgstart[(int64_t)m * nrb + rb] = ls;
     if (ls > lmax) return;
     const int g = gb + wave;
@@ -2612,11 +2613,11 @@ __global__ __launch_bounds__(64 * ABW) void k_leg_adj_b(const float2 *__restrict
         for (int r = 0; r < 16; ++r) red[(wave * 16 + r) * 64 + lane] = o[r];
         __syncthreads();
 #pragma unroll
-        for (int u = 0; u < 16 / ABW; ++u) {
-            const int r = wave * (16 / ABW) + u;  // this thread's register index, lane as it was
+        for (int u = 0; u < 16 / AW; ++u) {
+            const int r = wave * (16 / AW) + u;  // this thread's register index, lane as it was
             float sum = 0.f;
 #pragma unroll
-            for (int w = 0; w < ABW; ++w) sum += red[(w * 16 + r) * 64 + lane];
+            for (int w = 0; w < AW; ++w) sum += red[(w * 16 + r) * 64 + lane];
             const int i = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3), l = lc + i;
             if (l <= lmax && rhs < nrhs)
                 part[(((int64_t)(j >> 2) * nrb + rb) * nalm + base + l) * 4 + c] = sum;
@@ -2669,6 +2670,42 @@ static void syn_dispatch(Plan &P, int nrhs, int64_t fg_stride, int g0)
     else syn_dispatch_r<T, 1>(P, nrhs, fg_stride, g0);
 }
 
+// the polar groups [0, wpol) in the difference form and the others [wpol, nw) in the plain form, SW
+// groups per workgroup
+template <int SW>
+static void synth_b_launch(Plan &P, int q, int64_t fg_stride, int64_t lblocks, int wpol, int nw)
+{
+    if (wpol > 0) {
+        const int nbm = (int)cdiv(wpol, SW);
+        k_leg_synth_b<1, SW><<<(unsigned)(8 * nbm * lblocks), 64 * SW, 0, P.stream>>>(
+            P.d_brec, P.d_coef32d, (float2 *)P.d_FG, fg_stride, P.d_ent, P.d_entk, P.d_entl, P.ng64, P.d_pair_z,
+            P.lmax, P.npairs, P.nrings, P.nrhs, q, 0, wpol, nbm);
+    }
+    if (nw > wpol) {
+        const int nbm = (int)cdiv(nw - wpol, SW);
+        k_leg_synth_b<0, SW><<<(unsigned)(8 * nbm * lblocks), 64 * SW, 0, P.stream>>>(
+            P.d_brec, P.d_coef32, (float2 *)P.d_FG, fg_stride, P.d_ent, P.d_entk, P.d_entl, P.ng64, P.d_pair_z,
+            P.lmax, P.npairs, P.nrings, P.nrhs, q, wpol, nw, nbm);
+    }
+}
+
+// ring blocks of AW groups: the polar groups first (difference form), then the others
+template <int AW>
+static void adj_b_launch(Plan &P, int q, int64_t fg_stride, int64_t lblocks)
+{
+    const int npol = (int)cdiv(P.polar_groups, AW), nmain = (int)cdiv(P.ng64 - P.polar_groups, AW);
+    if (npol > 0)
+        k_leg_adj_b<1, AW><<<(unsigned)(8 * npol * lblocks), 64 * AW, 0, P.stream>>>(
+            (const float2 *)P.d_FG, fg_stride, P.d_coef32d, P.d_ent, P.d_entk, P.d_entl, P.ng64, P.d_pair_z,
+            (float *)P.d_part, P.d_wgstart_b, P.nalm, P.lmax, P.npairs, P.nrings, P.nrhs, q, 0, P.polar_groups, 0,
+            npol, P.nrb_b);
+    if (nmain > 0)
+        k_leg_adj_b<0, AW><<<(unsigned)(8 * nmain * lblocks), 64 * AW, 0, P.stream>>>(
+            (const float2 *)P.d_FG, fg_stride, P.d_coef32, P.d_ent, P.d_entk, P.d_entl, P.ng64, P.d_pair_z,
+            (float *)P.d_part, P.d_wgstart_b, P.nalm, P.lmax, P.npairs, P.nrings, P.nrhs, q, P.polar_groups, P.ng64,
+            npol, nmain, P.nrb_b);
+}
+
 // batched synthesis of FP32 plans: records and matrix-core sums per group of NBR right-hand sides
 void launch_synth_batched(Plan &P, const double *xE, const double *xB, int64_t rstride, const double *kern)
 {
@@ -2678,17 +2715,11 @@ void launch_synth_batched(Plan &P, const double *xE, const double *xB, int64_t r
     for (int q = 0; q * NBR < P.nrhs; ++q) {
         k_prologue_b<<<(unsigned)cdiv(P.nalm * NBR, 256), 256, 0, P.stream>>>(xE, xB, rstride, kern, P.d_lof, P.lmax,
                                                                              P.nalm, P.nrhs, q, P.d_brec);
-        if (wpol > 0) {
-            const int nbm = (int)cdiv(wpol, 4);
-            k_leg_synth_b<1><<<(unsigned)(8 * nbm * lblocks), 256, 0, P.stream>>>(
-                P.d_brec, P.d_coef32d, (float2 *)P.d_FG, fg_stride, P.d_ent, P.d_entk, P.d_entl, P.ng64, P.d_pair_z,
-                P.lmax, P.npairs, P.nrings, P.nrhs, q, 0, wpol, nbm);
-        }
-        if (nw > wpol) {
-            const int nbm = (int)cdiv(nw - wpol, 4);
-            k_leg_synth_b<0><<<(unsigned)(8 * nbm * lblocks), 256, 0, P.stream>>>(
-                P.d_brec, P.d_coef32, (float2 *)P.d_FG, fg_stride, P.d_ent, P.d_entk, P.d_entl, P.ng64, P.d_pair_z,
-                P.lmax, P.npairs, P.nrings, P.nrhs, q, wpol, nw, nbm);
+        switch (P.bat_SW) {
+        case 1: synth_b_launch<1>(P, q, fg_stride, lblocks, wpol, nw); break;
+        case 2: synth_b_launch<2>(P, q, fg_stride, lblocks, wpol, nw); break;
+        case 8: synth_b_launch<8>(P, q, fg_stride, lblocks, wpol, nw); break;
+        default: synth_b_launch<4>(P, q, fg_stride, lblocks, wpol, nw);
         }
     }
 }
@@ -2698,19 +2729,11 @@ void launch_adj_batched(Plan &P, int q)
 {
     const int64_t fg_stride = (int64_t)P.nrings * (P.lmax + 1) * 2;
     const int64_t lblocks = cdiv(P.lmax + 1, 8);
-    // polar groups: a multiple of four, or all groups of a small plan
-    const int npol = (int)cdiv(P.polar_groups, ABW);
-    if (P.polar_groups > 0)
-        k_leg_adj_b<1><<<(unsigned)(8 * npol * lblocks), 64 * ABW, 0, P.stream>>>(
-            (const float2 *)P.d_FG, fg_stride, P.d_coef32d, P.d_ent, P.d_entk, P.d_entl, P.ng64, P.d_pair_z,
-            (float *)P.d_part, P.d_wgstart_b, P.nalm, P.lmax, P.npairs, P.nrings, P.nrhs, q, 0, P.polar_groups, 0,
-            npol, P.nrb_b);
-    const int nmain = (int)cdiv(P.ng64 - P.polar_groups, ABW);
-    if (nmain > 0)
-        k_leg_adj_b<0><<<(unsigned)(8 * nmain * lblocks), 64 * ABW, 0, P.stream>>>(
-            (const float2 *)P.d_FG, fg_stride, P.d_coef32, P.d_ent, P.d_entk, P.d_entl, P.ng64, P.d_pair_z,
-            (float *)P.d_part, P.d_wgstart_b, P.nalm, P.lmax, P.npairs, P.nrings, P.nrhs, q, P.polar_groups, P.ng64,
-            npol, nmain, P.nrb_b);
+    switch (P.bat_AW) {
+    case 2: adj_b_launch<2>(P, q, fg_stride, lblocks); break;
+    case 8: adj_b_launch<8>(P, q, fg_stride, lblocks); break;
+    default: adj_b_launch<4>(P, q, fg_stride, lblocks);
+    }
 }
 
 void launch_epilogue_batched(Plan &P, int rhs, const double *kern, double lam, const double *xE, const double *xB,

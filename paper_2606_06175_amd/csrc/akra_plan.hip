@@ -558,9 +558,11 @@ static akra_status create(int nside, int lmax, int nrhs, int prec, void *stream,
     P->part_rb_cap = (size_t)std::max(P->adj_nrb, P->adj_nrb_polar + (P->npairs <= 1024 ? P->ng64 : (P->ng64 + 3) / 4));
     if (prec == AKRA_FP32 && nrhs > 1) {
         // batched adjoint: blocks of four groups (polar blocks apart), 8 right-hand sides of FP32 slabs
-        P->nrb_b = (P->polar_groups + 3) / 4 + (P->ng64 - P->polar_groups + 3) / 4;
-        P->part_rb_cap = std::max(P->part_rb_cap, (size_t)4 * P->nrb_b);
-        AK_TRY(alloc((void **)&P->d_wgstart_b, (size_t)P->nrb_b * (lmax + 1) * sizeof(int), *P));
+        // ring blocks of bat_AW groups (polar blocks apart); room for the smallest supported bat_AW, 2
+        P->nrb_b = (P->polar_groups + P->bat_AW - 1) / P->bat_AW + (P->ng64 - P->polar_groups + P->bat_AW - 1) / P->bat_AW;
+        P->nrb_b_cap = (P->polar_groups + 1) / 2 + (P->ng64 - P->polar_groups + 1) / 2;
+        P->part_rb_cap = std::max(P->part_rb_cap, (size_t)4 * P->nrb_b_cap);
+        AK_TRY(alloc((void **)&P->d_wgstart_b, (size_t)P->nrb_b_cap * (lmax + 1) * sizeof(int), *P));
     }
     AK_TRY(alloc(&P->d_part, P->part_rb_cap * P->nalm * 4 * sizeof(double), *P));
     AK_TRY(alloc((void **)&P->d_wgstart, P->part_rb_cap * (lmax + 1) * sizeof(int), *P));
@@ -1812,6 +1814,39 @@ akra_status akra_plan_set_tuning(akra_plan plan, int syn_variant, int syn_rings,
     P.adj_L = adj_chunk;
     P.adj_nrb = nrb;
     compute_work(P);
+    return AKRA_OK;
+}
+
+akra_status akra_plan_set_tuning_batched(akra_plan plan, int syn_waves, int adj_waves)
+{
+    AK_PLAN();
+    const bool sw = syn_waves == 1 || syn_waves == 2 || syn_waves == 4 || syn_waves == 8;
+    const bool aw = adj_waves == 2 || adj_waves == 4 || adj_waves == 8;
+    if (!sw || !aw) {
+        set_error("unsupported batched tuning: syn_waves in {1, 2, 4, 8}, adj_waves in {2, 4, 8}");
+        return AKRA_ERR_ARG;
+    }
+    if (P.prec != AKRA_FP32 || P.nrhs < 2) {
+        set_error("batched tuning applies to FP32 plans with several right-hand sides");
+        return AKRA_ERR_ARG;
+    }
+    AK_HIP(hipStreamSynchronize(P.stream), "sync");
+    P.bat_SW = syn_waves;
+    P.bat_AW = adj_waves;
+    P.nrb_b = (P.polar_groups + adj_waves - 1) / adj_waves + (P.ng64 - P.polar_groups + adj_waves - 1) / adj_waves;
+    drop_graph(P);  // recorded iterations hold the old launch shapes
+    return AKRA_OK;
+}
+
+akra_status akra_plan_get_tuning_batched(akra_plan plan, int *out2)
+{
+    AK_PLAN();
+    if (!out2) {
+        set_error("out2 is NULL");
+        return AKRA_ERR_ARG;
+    }
+    out2[0] = P.bat_SW;
+    out2[1] = P.bat_AW;
     return AKRA_OK;
 }
 

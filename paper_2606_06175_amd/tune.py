@@ -3,9 +3,13 @@
 For one (Nside, lmax, precision) it times every supported synthesis variant / ring-pairs-per-lane
 choice and every adjoint (ring pairs per lane, waves per workgroup) shape with HIP events on the
 plan stream (stage times of PCG iterations on synthetic data), and stores the fastest in
-tuning.json next to this file.  Plan() applies the cached shapes automatically.
+tuning.json next to this file.  For FP32 plans with several right-hand sides (--nrhs K > 1) it tunes
+the batched matrix-core kernels instead: waves per workgroup of the synthesis and of the adjoint,
+timed over batched operator applies (synthesis, adjoint and the epilogues that add the adjoint's
+slabs), cached per (Nside, lmax, K).  Plan() applies the cached shapes automatically.
 
     python -m paper_2606_06175_amd.tune --nside 2048 --lmax 4096 --precision fp64
+    python -m paper_2606_06175_amd.tune --nside 1024 --lmax 2048 --precision fp32 --nrhs 16
 """
 import argparse
 import json
@@ -18,8 +22,15 @@ ADJ = [(1, 1, 8), (1, 2, 8), (1, 4, 8), (2, 2, 8), (2, 4, 8), (4, 2, 8), (4, 4, 
        (2, 4, 4), (4, 2, 4), (4, 4, 4), (8, 1, 4), (2, 1, 8), (4, 1, 4), (4, 1, 8)]
 
 
+BATCHED = [(sw, aw) for sw in (1, 2, 4, 8) for aw in (2, 4, 8)]
+
+
 def key(nside, lmax, precision):
     return "%d:%d:%s" % (nside, lmax, precision)
+
+
+def key_batched(nside, lmax, nrhs):
+    return "%d:%d:fp32:nrhs%d" % (nside, lmax, nrhs)
 
 
 def load_cache():
@@ -31,6 +42,45 @@ def load_cache():
 
 def lookup(nside, lmax, precision):
     return load_cache().get(key(nside, lmax, precision))
+
+
+def lookup_batched(nside, lmax, nrhs):
+    return load_cache().get(key_batched(nside, lmax, nrhs))
+
+
+def tune_batched(nside, lmax, nrhs, reps=3, log=print):
+    """Time every batched shape over `reps` batched applies (after one warm-up) on random coefficients
+    and weights; the figure of merit is synthesis + adjoint + epilogue time per apply."""
+    import torch
+
+    from .akra import Plan
+    dev = torch.device("cuda", 0)
+    plan = Plan(nside, lmax, nrhs=nrhs, precision="fp32", device=dev, tuned=False)
+    npix = 12 * nside * nside
+    g = torch.Generator(device="cpu").manual_seed(11)
+    ninv = (5.0 + 50.0 * torch.rand(nrhs, npix, generator=g, dtype=torch.float64)).to(dev)
+    mask = torch.ones(npix, dtype=torch.uint8, device=dev)
+    x = [torch.randn(nrhs, plan.nalm, generator=g, dtype=torch.complex128).to(dev) for _ in (0, 1)]
+    res = {}
+    best, best_t = plan.get_tuning_batched(), float("inf")
+    for sw, aw in BATCHED:
+        plan.set_tuning_batched(sw, aw)
+        plan.apply_H(ninv, mask, x[0], x[1], 1e-3)
+        plan.set_timing(True)
+        plan.stage_times()
+        for _ in range(reps):
+            plan.apply_H(ninv, mask, x[0], x[1], 1e-3)
+        st = plan.stage_times()
+        plan.set_timing(False)
+        t = {k: st[k][0] / reps for k in ("leg_synth", "leg_adj", "epilogue")}
+        tot = sum(t.values())
+        res["%d,%d" % (sw, aw)] = t
+        log("  batched synthesis waves %d adjoint waves %d: synth %.3f adj %.3f epi %.3f ms"
+            % (sw, aw, t["leg_synth"], t["leg_adj"], t["epilogue"]))
+        if tot < best_t:
+            best, best_t = (sw, aw), tot
+    plan.close()
+    return {"syn_waves": best[0], "adj_waves": best[1], "ms": best_t, "reps": reps, "sweep": res}
 
 
 def _time_stage(plan, stage, steps):
@@ -90,14 +140,23 @@ def main():
     ap.add_argument("--lmax", type=int, required=True)
     ap.add_argument("--precision", default="fp64")
     ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--nrhs", type=int, default=1)
     ap.add_argument("--out", default=CACHE)
     a = ap.parse_args()
-    e = tune(a.nside, a.lmax, a.precision, a.steps, log=lambda *x: print(*x, flush=True))
+    logf = lambda *x: print(*x, flush=True)  # noqa: E731
+    if a.nrhs > 1:
+        if a.precision != "fp32":
+            raise SystemExit("the batched kernels belong to FP32 plans")
+        e = tune_batched(a.nside, a.lmax, a.nrhs, log=logf)
+        k = key_batched(a.nside, a.lmax, a.nrhs)
+    else:
+        e = tune(a.nside, a.lmax, a.precision, a.steps, log=logf)
+        k = key(a.nside, a.lmax, a.precision)
     cache = {}
     if os.path.exists(a.out):
         with open(a.out) as f:
             cache = json.load(f)
-    cache[key(a.nside, a.lmax, a.precision)] = e
+    cache[k] = e
     with open(a.out, "w") as f:
         json.dump(cache, f, indent=1, sort_keys=True)
     print(json.dumps({k: v for k, v in e.items() if k != "sweep"}), flush=True)

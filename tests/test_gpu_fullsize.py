@@ -229,3 +229,42 @@ def test_stepwise_pcg_full_size(big):
     assert ra < 0.5 and abs(ra - true_rel) < 1e-8 * max(true_rel, 1e-300) + 1e-12
     a.close()
     b.close()
+
+
+def test_batched_sixteen_rhs_sampled_against_oracle():
+    # the batched workload's size (HEALPix Nside 1024, lmax 2048, 16 right-hand sides, FP32 matrix-core
+    # kernels in their tuned shapes): two of the sixteen right-hand sides on sampled rings (synthesis)
+    # and sampled m (adjoint) against the oracle
+    import torch
+    from paper_2606_06175_amd import Plan
+    nside, lmax, nrhs = 1024, 2048, 16
+    dev = torch.device("cuda", 0)
+    o = Oracle(lmax, healpix_rings(nside))
+    rings = [0, 150, 700, 1023, 2047, 3800, 4094]
+    ms = [0, 2, 700, 2048]
+    picks = (3, 14)
+    A = np.stack([wl.random_alm(lmax, 130 + k) for k in range(nrhs)])
+    B = np.stack([wl.random_alm(lmax, 150 + k) for k in range(nrhs)])
+    H = [wl.random_maps(o.rings.npix, 170 + k) for k in range(nrhs)]
+    print("plan nside=%d lmax=%d fp32 nrhs=%d" % (nside, lmax, nrhs), flush=True)
+    p = Plan(nside, lmax, nrhs=nrhs, precision="fp32", device=dev)
+    g1, g2 = p.synth2(torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev))
+    h1 = torch.from_numpy(np.stack([h[0] for h in H])).to(dev)
+    h2 = torch.from_numpy(np.stack([h[1] for h in H])).to(dev)
+    cE, cB = p.adjoint2(h1, h2)
+    p.close()
+    for k in picks:
+        r1, r2 = o.synth(A[k], B[k], ring_idx=rings)
+        a1, a2 = g1[k].cpu().numpy(), g2[k].cpu().numpy()
+        for r in rings:
+            a, n = int(o.rings.ofs[r]), int(o.rings.nphi[r])
+            e = rel(np.r_[a1[a:a + n], a2[a:a + n]], np.r_[r1[a:a + n], r2[a:a + n]])
+            print("rhs %d ring %d rel %.3e" % (k, r, e), flush=True)
+            assert e < 1e-5, (k, r, e)
+        rE, rB = o.adjoint(H[k][0], H[k][1], mlist=ms)
+        eE, eB = cE[k].cpu().numpy(), cB[k].cpu().numpy()
+        for m in ms:
+            sl = slice(m * (2 * lmax + 1 - m) // 2 + m, m * (2 * lmax + 1 - m) // 2 + lmax + 1)
+            e = rel(np.r_[eE[sl], eB[sl]], np.r_[rE[sl], rB[sl]])
+            print("rhs %d m %d rel %.3e" % (k, m, e), flush=True)
+            assert e < 1e-5, (k, m, e)

@@ -42,3 +42,42 @@ def test_all_shapes_match_oracle(prec, tol):
         cE, cB = p.adjoint2(th1, th2)
         assert rel(np.stack([cE.cpu().numpy(), cB.cpu().numpy()]), np.stack([rE, rB])) < tol, (r, w)
     p.close()
+
+
+BATCHED = [(sw, aw) for sw in (1, 2, 4, 8) for aw in (2, 4, 8)]
+
+
+def test_all_batched_shapes_match_oracle():
+    # every (synthesis waves, adjoint waves) shape of the batched matrix-core kernels, on a plan with
+    # polar groups in the difference form and a padded second group of right-hand sides
+    import torch
+    from paper_2606_06175_amd import Plan
+    nside, lmax, nrhs = 300, 600, 9   # 600 ring pairs: ten 64-pair groups, ragged for every shape
+    dev = torch.device("cuda", 0)
+    o = Oracle(lmax, healpix_rings(nside))
+    A = np.stack([wl.random_alm(lmax, 90 + k) for k in range(nrhs)])
+    B = np.stack([wl.random_alm(lmax, 110 + k) for k in range(nrhs)])
+    g = np.random.default_rng(12)
+    mask = (g.uniform(size=o.rings.npix) < 0.8).astype(np.uint8)
+    ninvs = np.stack([g.uniform(5.0, 60.0, o.rings.npix) for _ in range(nrhs)])
+    check = (0, 8)   # first and last right-hand side (the second group is padded)
+    ref_s = {k: o.synth(A[k], B[k]) for k in check}
+    ref_h = {k: o.apply_H(np.stack([A[k], B[k]]), o.weights(ninvs[k], mask), 0.02) for k in check}
+    p = Plan(nside, lmax, nrhs=nrhs, precision="fp32", device=dev, tuned=False)
+    tA, tB = torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev)
+    tn, tm = torch.from_numpy(ninvs).to(dev), torch.from_numpy(mask).to(dev)
+    for sw, aw in BATCHED:
+        print("batched synthesis waves", sw, "adjoint waves", aw, flush=True)
+        p.set_tuning_batched(sw, aw)
+        assert p.get_tuning_batched() == (sw, aw)
+        g1, g2 = p.synth2(tA, tB)
+        yE, yB = p.apply_H(tn, tm, tA, tB, 0.02)
+        for k in check:
+            r1, r2 = ref_s[k]
+            assert rel(np.r_[g1[k].cpu().numpy(), g2[k].cpu().numpy()], np.r_[r1, r2]) < 1e-5, (sw, aw, k)
+            assert rel(np.stack([yE[k].cpu().numpy(), yB[k].cpu().numpy()]), ref_h[k]) < 1e-5, (sw, aw, k)
+    with pytest.raises(Exception):
+        p.set_tuning_batched(3, 4)
+    with pytest.raises(Exception):
+        p.set_tuning_batched(4, 1)
+    p.close()
