@@ -27,6 +27,23 @@ METRIC = "H·v applies/s + CG time-to-1e-8 at Nside 2048 ℓmax 4096, mixed/batc
 PEAK_FP64 = 78.6e12      # MI355X FP64 vector FMA, FLOP/s
 PEAK_FP32 = 157.3e12     # MI355X FP32 vector (packed) FMA, FLOP/s
 FLOP_PER_TRIPLE = 26     # per (l, m, ring pair) and direction: 2 recurrences (10) + 8 contraction FMAs (16)
+FLOP_PER_TRIPLE_ONE = 18  # the same with one ring of the pair weighted: 2 recurrences + 4 contraction FMAs
+
+
+def weighted_flops(ww):
+    """Algorithmic flop of the weighted synthesis and adjoint launches (akra_plan_work_weighted)."""
+    return {"leg_synth": FLOP_PER_TRIPLE * ww["synth_two"] + FLOP_PER_TRIPLE_ONE * ww["synth_one"],
+            "leg_adj": FLOP_PER_TRIPLE * ww["adjoint_two"] + FLOP_PER_TRIPLE_ONE * ww["adjoint_one"]}
+
+
+def live_ring_bytes(nside, lmax, w, fg_bytes):
+    """Algorithmic HBM bytes of the weighted ring stage: F read and G written for every ring that
+    carries weight (fg_bytes per (ring, m) each) and W read on those rings (8 B per pixel)."""
+    import numpy as np
+    import akra_workloads as wl
+    zs, ns, p0, ofs = wl.ring_layout(nside)
+    live = np.array([np.any(w[o:o + n] != 0) for o, n in zip(ofs, ns)])
+    return int(2 * fg_bytes * live.sum() * (lmax + 1) + 8 * ns[live].sum()), int(live.sum())
 
 
 # HBM bytes per launch of the dominant kernel from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE at this
@@ -101,7 +118,8 @@ def fp32_roofline(plan32, g1, g2, ninv, mask, nside, lmax, steps=3):
     """The FP32 operator's Legendre kernels (the mixed solve's iterations) against the FP32 peaks:
     157.3 TFLOP/s is the packed-FP32 figure; the kernels issue plain FP32 VALU instructions, whose
     rate is that of FP64 (78.6 TFLOP/s).  Stage times are HIP events over `steps` PCG steps; the
-    flop count is 26 per (l, m, ring-pair) triple the FP32 plan evaluates."""
+    flop count is 26 per (l, m, ring-pair) triple the FP32 plan evaluates in ring groups weighted on
+    both sides and 18 per triple of groups weighted on one side."""
     import torch
     plan32.cg_start(g1, g2, ninv, mask)
     plan32.cg_step(1)
@@ -111,13 +129,15 @@ def fp32_roofline(plan32, g1, g2, ninv, mask, nside, lmax, steps=3):
     plan32.cg_step(steps)
     st = plan32.stage_times()
     plan32.set_timing(False)
-    work = plan32.work()
+    ww = plan32.work_weighted()
+    fl = weighted_flops(ww)
     out = {"unit": "TFLOP/s", "peak_packed_fp32": PEAK_FP32 / 1e12, "peak_plain_fp32_issue": PEAK_FP64 / 1e12,
            "steps": steps}
     for stage, key in (("leg_synth", "synth"), ("leg_adj", "adjoint")):
         ms = st[stage][0] / max(st[stage][1], 1)
-        achieved = FLOP_PER_TRIPLE * work[key] / (ms * 1e-3)
-        out[stage] = {"ms": ms, "evaluated_triples": work[key], "achieved": achieved / 1e12,
+        achieved = fl[stage] / (ms * 1e-3)
+        out[stage] = {"ms": ms, "evaluated_triples_two_sided": ww[key + "_two"],
+                      "evaluated_triples_one_sided": ww[key + "_one"], "flop": fl[stage], "achieved": achieved / 1e12,
                       "frac_of_packed_peak": achieved / PEAK_FP32, "frac_of_plain_issue": achieved / PEAK_FP64}
     return out
 
@@ -229,7 +249,7 @@ def batched_leg(name, tol, maxiter, solves=True, napply=20):
     # matrix-core Legendre stages against the FP32 MFMA peak: (10 + 16 K) flop per evaluated
     # (l, m, ring-pair) triple and direction for K right-hand sides (two recurrence steps shared by the
     # right-hand sides, eight multiply-adds per right-hand side)
-    tb_eval = pb.work()["batched"]
+    tb_eval = pb.work_weighted()["batched"]  # ring groups with weight in some right-hand side
     flop = (10 + 16 * nr) * tb_eval
     mfma = {"unit": "TFLOP/s", "peak": PEAK_FP32 / 1e12, "evaluated_triples": tb_eval,
             "flop_per_launch_set": flop, "note": "per batched apply; the right-hand sides run in groups of 8"}
@@ -641,30 +661,36 @@ def main():
     T = triples(nside, lmax)
     work = plan.work()
     assert work["all"] == T
-    evaluated = {"leg_synth": work["synth"], "leg_adj": work["adjoint"]}
+    ww = plan.work_weighted()  # the weighted launches of the timed steps
+    fl = weighted_flops(ww)
     dom = max(("leg_synth", "leg_adj"), key=lambda k: stages[k]["ms_avg"])
-    flops = FLOP_PER_TRIPLE * evaluated[dom]
-    achieved = flops / (stages[dom]["ms_avg"] * 1e-3)
+    achieved = fl[dom] / (stages[dom]["ms_avg"] * 1e-3)
     peak = PEAK_FP64 if args.precision == "fp64" else PEAK_FP32
+    key = "synth" if dom == "leg_synth" else "adjoint"
     roofline = {"bound": "alu", "kernel": "k_leg_adj" if dom == "leg_adj" else "k_leg_synth",
                 "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
                 "frac": achieved / peak,
                 "traffic": traffic(dom, nside, lmax) if args.precision == "fp64" else None,
-                "algorithmic": "26 flop x %d evaluated (l, m, ring-pair) triples = %.4g flop per launch "
-                               "(all triples T = %d; the terms below each ring group's entry degree, where its "
-                               "recurrence values first reach 2^-100, are skipped)" % (evaluated[dom], flops, T)}
+                "algorithmic": "26 flop x %d triples of ring groups weighted on both sides + 18 flop x %d of groups "
+                               "weighted on one side = %.4g flop per launch (all (l, m, ring-pair) triples T = %d; "
+                               "groups without a weighted ring and the terms below each group's entry degree, where "
+                               "its recurrence values first reach 2^-100, are skipped)"
+                               % (ww[key + "_two"], ww[key + "_one"], fl[dom], T)}
     # ring stage against HBM: F read and G written (32 B per (ring, m) each) and W read (8 B per pixel)
+    # on the rings that carry weight (the others are skipped)
     fg_bytes = 32 if args.precision == "fp64" else 16  # (Q, U) complex entry of F or G per (ring, m)
-    ring_bytes = 2 * fg_bytes * (4 * nside - 1) * (lmax + 1) + 8 * 12 * nside * nside
+    ring_bytes, n_live = live_ring_bytes(nside, lmax, cfg["mask"] * cfg["ninv"][0], fg_bytes)
+    assert n_live == ww["live_rings"], (n_live, ww["live_rings"])
     roofline["ring_algorithmic_bytes"] = ring_bytes
+    roofline["ring_rings_with_weight"] = n_live
     roofline["ring_hbm_GBs"] = ring_bytes / (stages["ring"]["ms_avg"] * 1e-3) / 1e9
     roofline["ring_hbm_frac"] = roofline["ring_hbm_GBs"] / 8000.0
     for k in ("leg_synth", "leg_adj"):
         t = stages[k]["ms_avg"] * 1e-3
-        roofline["frac_" + k] = FLOP_PER_TRIPLE * evaluated[k] / t / peak
-        roofline["evaluated_fraction_" + k] = evaluated[k] / T
+        kk = "synth" if k == "leg_synth" else "adjoint"
+        roofline["frac_" + k] = fl[k] / t / peak
+        roofline["evaluated_fraction_" + k] = (ww[kk + "_two"] + ww[kk + "_one"]) / T
         roofline["full_T_rate_TFLOPs_" + k] = FLOP_PER_TRIPLE * T / t / 1e12
-
     out = {"metric": METRIC, "value": 1e3 / ms_step, "unit": "H·v applies/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f32",

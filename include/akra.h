@@ -259,10 +259,18 @@ akra_status akra_plan_set_graph(akra_plan plan, int on);
  *                pairs per workgroup than the plan's partial-sum buffer allows (at least 256 pairs
  *                per workgroup when Nside > 512) is rejected with AKRA_ERR_ARG.
  * akra_plan_get_tuning writes the five current values to out5 (HOST).
+ * These shapes apply to every group of an unweighted transform and to the ring groups weighted on
+ * both sides in weighted applies (see akra_plan_set_skip_unweighted); akra_plan_set_tuning_one_sided
+ * sets the same five values for the groups weighted on one side only (their contraction has half
+ * the FMAs per loaded record or adjoint chunk, so another shape can pay), with the same rules, and
+ * akra_plan_get_tuning_one_sided reads them.  A new plan starts with both equal.
  */
 akra_status akra_plan_set_tuning(akra_plan plan, int syn_variant, int syn_rings, int adj_rings, int adj_waves,
                                  int adj_chunk);
 akra_status akra_plan_get_tuning(akra_plan plan, int *out5);
+akra_status akra_plan_set_tuning_one_sided(akra_plan plan, int syn_variant, int syn_rings, int adj_rings,
+                                           int adj_waves, int adj_chunk);
+akra_status akra_plan_get_tuning_one_sided(akra_plan plan, int *out5);
 /*
  * Launch shapes of the batched matrix-core Legendre kernels (FP32 plans with nrhs > 1): syn_waves
  * 64-pair ring groups (one per wave) per workgroup of the batched synthesis, in {1, 2, 4, 8};
@@ -292,6 +300,32 @@ akra_status akra_plan_work(akra_plan plan, int64_t *out3);
  * sides and eight multiply-adds per right-hand side (the transform of eq. shear_SH and its adjoint).
  */
 akra_status akra_plan_work_batched(akra_plan plan, int64_t *out1);
+/*
+ * Rings without weight.  H v and the right-hand side depend on a ring only through its weights
+ * W = M N^-1 (Sec. II.B: the pixel diagonal between the inverse and the forward SHT), so a ring whose
+ * weights are all zero -- outside the survey footprint, eq. mask -- contributes nothing.  Every weight
+ * set-up (akra_apply_H, akra_rhs and the solves) records which rings carry weight; the weighted
+ * operator's ring stage then transforms only those rings, and its Legendre stages skip the 64-pair
+ * ring groups none of whose rings (north ring p or south ring nrings - 1 - p) carries weight and
+ * contract only the weighted side of groups with weight on one side.  The results are those of the
+ * full transforms up to the rounding order of the adjoint's sums.  akra_synth2, akra_adjoint2 and
+ * the gradient's synthesis always transform every ring.
+ *
+ * akra_plan_set_skip_unweighted: on != 0 (the default) as above; on = 0 runs every ring and group in
+ * weighted applies too (for comparisons).  Synchronises the plan stream and drops a recorded
+ * iteration.  Errors: AKRA_ERR_ARG (null plan), AKRA_ERR_HIP.
+ *
+ * akra_plan_work_weighted writes to out6 (HOST): [0] the rings that carry weight in the last weight
+ * set-up (all rings before one), then the (l, m, ring pair) triples the weighted Legendre launches
+ * evaluate with the current shapes: [1] synthesis in groups weighted on both sides, [2] synthesis in
+ * groups weighted on one side, [3] adjoint on both sides, [4] adjoint on one side, [5] the batched
+ * kernels per right-hand side (FP32 plans with nrhs > 1; they contract both sides of every weighted
+ * group).  A two-sided triple costs 26 flop per direction (two recurrence steps and eight
+ * multiply-adds), a one-sided one 18 (the same recurrence and four multiply-adds).  Errors:
+ * AKRA_ERR_ARG.
+ */
+akra_status akra_plan_set_skip_unweighted(akra_plan plan, int on);
+akra_status akra_plan_work_weighted(akra_plan plan, int64_t *out6);
 akra_status akra_plan_set_timing(akra_plan plan, int on);
 /*
  * Ring-stage kernel choice of plans created afterwards (process-wide, not thread-safe against

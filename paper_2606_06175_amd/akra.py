@@ -79,10 +79,15 @@ def lib():
     L.akra_plan_set_graph.argtypes = [vp, ctypes.c_int]
     L.akra_plan_set_tuning.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     L.akra_plan_get_tuning.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
+    L.akra_plan_set_tuning_one_sided.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                                 ctypes.c_int]
+    L.akra_plan_get_tuning_one_sided.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
     L.akra_plan_set_tuning_batched.argtypes = [vp, ctypes.c_int, ctypes.c_int]
     L.akra_plan_get_tuning_batched.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
     L.akra_plan_work.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
     L.akra_plan_work_batched.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
+    L.akra_plan_work_weighted.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
+    L.akra_plan_set_skip_unweighted.argtypes = [vp, ctypes.c_int]
     L.akra_cg_solve_vjp.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(CgOpts), vp, vp, vp, vp, vp, vp, vp,
                                     ctypes.POINTER(CgInfo)]
     L.akra_cg_solve_cond_b.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(CgOpts), vp, vp, ctypes.POINTER(CgInfo)]
@@ -117,7 +122,8 @@ def lib():
               "akra_cg_solve_b", "akra_cg_start", "akra_cg_step", "akra_cg_state", "akra_plan_set_timing",
               "akra_plan_stage_times", "akra_plan_set_tuning", "akra_plan_get_tuning", "akra_plan_work",
               "akra_plan_set_tuning_batched", "akra_plan_get_tuning_batched",
-              "akra_plan_work_batched",
+              "akra_plan_work_batched", "akra_plan_work_weighted", "akra_plan_set_skip_unweighted",
+              "akra_plan_set_tuning_one_sided", "akra_plan_get_tuning_one_sided",
               "akra_cg_solve_vjp", "akra_cg_solve_cond_b", "akra_set_ring_whole_maxm", "akra_set_ring_register_engine", "akra_unmasked_index",
               "akra_shuffle_shear", "akra_alm_spectra", "akra_alm_spectra_noalloc", "akra_noise_work_size", "akra_noise_spectra", "akra_ang2pix",
               "akra_pixelize_work_size", "akra_pixelize", "akra_flat_plan_create", "akra_flat_synth",
@@ -211,6 +217,9 @@ class Plan:
             if e:
                 self.set_tuning(e["syn_variant"], e["syn_rings"], e["adj_rings"], e["adj_waves"],
                                 e.get("adj_chunk", 8))
+                o = e.get("one_sided", e)
+                self.set_tuning_one_sided(o["syn_variant"], o["syn_rings"], o["adj_rings"], o["adj_waves"],
+                                          o.get("adj_chunk", 8))
             if precision == "fp32" and self.nrhs > 1:
                 b = lookup_batched(self.nside, self.lmax, self.nrhs)
                 if b:
@@ -576,6 +585,16 @@ class Plan:
         _check(lib().akra_plan_get_tuning(self._h, v))
         return tuple(v)
 
+    def set_tuning_one_sided(self, syn_variant, syn_rings, adj_rings, adj_waves, adj_chunk=8):
+        """Launch shapes of the ring groups weighted on one side only (akra_plan_set_tuning_one_sided)."""
+        _check(lib().akra_plan_set_tuning_one_sided(self._h, int(syn_variant), int(syn_rings), int(adj_rings),
+                                                    int(adj_waves), int(adj_chunk)))
+
+    def get_tuning_one_sided(self):
+        v = (ctypes.c_int * 5)()
+        _check(lib().akra_plan_get_tuning_one_sided(self._h, v))
+        return tuple(v)
+
     def set_tuning_batched(self, syn_waves, adj_waves):
         """Waves per workgroup of the batched matrix-core synthesis and adjoint (FP32, nrhs > 1)."""
         _check(lib().akra_plan_set_tuning_batched(self._h, int(syn_waves), int(adj_waves)))
@@ -592,6 +611,19 @@ class Plan:
         b = ctypes.c_int64()
         _check(lib().akra_plan_work_batched(self._h, ctypes.byref(b)))
         return {"all": v[0], "synth": v[1], "adjoint": v[2], "batched": b.value}
+
+    def work_weighted(self):
+        """Rings that carry weight in the last weight set-up, and the (l, m, ring-pair) triples the
+        weighted Legendre launches evaluate: synthesis and adjoint, in groups weighted on both sides
+        (26 flop each) and on one side (18 flop each), and per right-hand side of the batched kernels."""
+        v = (ctypes.c_int64 * 6)()
+        _check(lib().akra_plan_work_weighted(self._h, v))
+        return {"live_rings": v[0], "synth_two": v[1], "synth_one": v[2], "adjoint_two": v[3],
+                "adjoint_one": v[4], "batched": v[5]}
+
+    def set_skip_unweighted(self, on):
+        """Skip rings without weight in weighted applies (the default), or run every ring (on False)."""
+        _check(lib().akra_plan_set_skip_unweighted(self._h, 1 if on else 0))
 
 
 class FlatPlan:

@@ -93,6 +93,37 @@ struct RingInfo {
     int64_t rofs;  // Bluestein rings of the register engine: offset of that spectrum in register order
 };
 
+// Rings that carry weight.  A ring whose weights W = M N^-1 are all zero contributes nothing to
+// H v or to the right-hand side (its G is zero), so with a weight set in place the ring stage skips
+// such rings and the Legendre stages skip the 64-pair groups none of whose rings carry weight.  A
+// group of ring pairs (north ring p, south ring nrings - 1 - p) falls in one of three classes:
+// weight on north and south rings (GCLS_BOTH), on north rings only (GCLS_NORTH; the equatorial ring
+// counts as a north ring) or on south rings only (GCLS_SOUTH).  A one-ring class contracts with half
+// of the FMAs of the two-ring class.
+enum { GCLS_BOTH = 0, GCLS_NORTH = 1, GCLS_SOUTH = 2, GCLS_N = 3 };
+// 64-pair groups of one apply: per class an ascending list whose first npol entries are near-polar
+// groups of FP32 plans (difference form), then nmain others; list_any holds every listed group
+// (the union of the classes, for the batched kernels, which have no one-ring form).
+struct GroupSet {
+    const int *list[GCLS_N] = {nullptr, nullptr, nullptr};
+    int npol[GCLS_N] = {0, 0, 0}, nmain[GCLS_N] = {0, 0, 0};
+    const int *list_any = nullptr;
+    int npol_any = 0, nmain_any = 0;
+};
+// rings of one ring-stage launch set, by kernel kind: whole power-of-two rings in LDS (RK_P2), whole-ring
+// Bluestein (RK_BF), two half-length Bluestein transforms (RK_BL), and the register engine's six
+// lists (RK_REG + q, q as in Plan::d_order_r)
+enum { RK_P2 = 0, RK_BF = 1, RK_BL = 2, RK_REG = 3, RING_KINDS = 9 };
+// ring blocks a class-split adjoint may write beyond the unsplit layout (each of up to two polar
+// and two further main parts rounds up by at most one block)
+constexpr int LIVE_NRB_EXTRA = 4;
+// values keying a recorded PCG iteration (see iter_key)
+constexpr int ITER_KEY_N = 18;
+struct RingSet {
+    const int *order[RING_KINDS] = {};
+    int n[RING_KINDS] = {};
+};
+
 struct Plan {
     int nside = 0, lmax = 0, nrhs = 1, prec = AKRA_FP64;
     int dev = 0;
@@ -132,9 +163,30 @@ struct Plan {
     void *d_bhatr64 = nullptr, *d_bhatr32 = nullptr;  // their chirp spectra in register order
     std::vector<RingInfo> h_rings;
 
+    // every ring and group (transforms without weights), and those of the current weights: the
+    // lists of the weighted set are rebuilt at every weight set-up (setup_weights)
+    RingSet rs_all, rs_live;
+    GroupSet gs_all, gs_live;
+    std::vector<int> h_order[RING_KINDS];  // host copies of the rings of every kind
+    int *d_gl_all = nullptr;      // [ng64] 0, 1, .., ng64 - 1
+    int *d_live_lists = nullptr;  // [RING_KINDS][nrings] ring lists, then [GCLS_N + 1][ng64] group lists
+    uint8_t *d_ring_live = nullptr;  // [nrings] 1: the ring carries weight in some right-hand side's W
+    uint8_t *h_live = nullptr;       // pinned: the flags read back, then the lists staged for upload
+    int live_gen = 0;                // counts weight set-ups (recorded graphs hold the lists' sizes)
+    bool skip_rings = true;          // weighted applies use the weighted sets (akra_plan_set_skip_unweighted)
+    int n_live_rings = 0;            // rings that carry weight in the current weights
+    int nrb_cur = 1;                 // ring blocks the last single-right-hand-side adjoint wrote
+    int nrb_b_cur = 1;               // ring blocks the last batched adjoint wrote
+    int64_t work_live[5] = {0, 0, 0, 0, 0};  // evaluated triples with the current weights: synthesis of
+                                             // two-ring, one-ring groups, adjoint of two-ring, one-ring,
+                                             // batched kernels per right-hand side
+
     // Legendre launch shapes
     int syn_R = 1, syn_V = 1, syn_groups = 1;
     int adj_R = 1, adj_W = 1, adj_L = 8, adj_nrb = 1;
+    // the shapes of groups weighted on one side only (GCLS_NORTH, GCLS_SOUTH), tuned apart: they
+    // contract with half the FMAs per loaded record or chunk
+    int syn_R1 = 1, syn_V1 = 1, adj_R1 = 1, adj_W1 = 1, adj_L1 = 8;
     size_t part_rb_cap = 1;  // ring blocks the partial-sum buffer holds
     // FP32 plans: the 64-pair groups nearest the poles run the Legendre stages in the difference
     // form; the adjoint covers them with adj_nrb_polar ring blocks of four groups
@@ -189,7 +241,7 @@ struct Plan {
     bool capturing = false;  // recording the graph: host-side trace ranges are not emitted
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t cg_graph = nullptr;
-    double cg_graph_key[12] = {};
+    double cg_graph_key[ITER_KEY_N] = {};
     // the lockstep iteration of the batched solve, keyed by its by-value arguments and active set
     hipGraphExec_t cg_graph_b = nullptr;
     std::vector<double> cg_graph_b_key;
@@ -249,14 +301,24 @@ void launch_prologue(Plan &P, bool fp32, const double *xE, const double *xB, con
 void launch_entry(Plan &P);
 // FP32 plans with nrhs > 1: kernel-scaled records and matrix-core synthesis of all right-hand sides
 // (alm of right-hand side r at xE/xB + 2 r rstride doubles)
-void launch_synth_batched(Plan &P, const double *xE, const double *xB, int64_t rstride, const double *kern);
-// Legendre synthesis of the prologue's records (d_rec) into d_FG
-void launch_leg_synth(Plan &P, bool fp32, int nrhs);
-// ring stage: mode 0 = F -> maps, 1 = maps -> G, 2 = F -> W -> G (in place)
+// (live: only the 64-pair groups with a ring that carries weight in the current weights)
+void launch_synth_batched(Plan &P, const double *xE, const double *xB, int64_t rstride, const double *kern,
+                          bool live);
+// Legendre synthesis of the prologue's records (d_rec) into d_FG: every group (live false) or the
+// groups of the current weights by class (live true: F only of rings that carry weight)
+void launch_leg_synth(Plan &P, bool fp32, int nrhs, bool live);
+// ring stage: mode 0 = F -> maps, 1 = maps -> G, 2 = F -> W -> G (in place); every ring (live false)
+// or only the rings that carry weight (live true: the others' G is left as it was, and adjoints with
+// live true read it as zero)
 void launch_ring(Plan &P, bool fp32, int mode, const double *g1, const double *g2, double *o1, double *o2,
-                 const double *W, int nrhs);
-// Legendre adjoint of d_FG into the partial sums d_part
-void launch_leg_adj(Plan &P, bool fp32, int rhs);
+                 const double *W, int nrhs, bool live);
+// Legendre adjoint of d_FG into the partial sums d_part (live as for the synthesis; with live true,
+// rings without weight are read as G = 0); sets nrb_cur for the epilogue
+void launch_leg_adj(Plan &P, bool fp32, int rhs, bool live);
+// ring blocks an adjoint launch set writes
+int adj_blocks_total(const Plan &P, bool live);
+// per-ring flags (any weight nonzero on the ring, over the nrhs maps of W) into d_ring_live
+void launch_ring_live(Plan &P, int nrhs);
 // gradient of the solve (ring MODE 3, FP64): F = Y K x in d_FG, q = Y K u in (q1, q2) on entry;
 // dninv = M (Omega q . (g - Y K x) - c), (q1, q2) <- Omega W q
 void launch_ring_grad(Plan &P, const double *g1, const double *g2, double *q1, double *q2, const double *W,
@@ -270,7 +332,7 @@ void launch_epilogue(Plan &P, bool fp32, const double *kern, double lam, const d
                      double *outE, double *outB, double *dot_red = nullptr);
 // batched FP32 adjoint (matrix cores) of right-hand-side group q, and the epilogue of one right-hand
 // side from its slabs
-void launch_adj_batched(Plan &P, int q);
+void launch_adj_batched(Plan &P, int q, bool live);
 void launch_epilogue_batched(Plan &P, int rhs, const double *kern, double lam, const double *xE, const double *xB,
                              double *outE, double *outB, double *dot_red = nullptr);
 // chirp spectra of the Bluestein sub lengths Ls (FFT lengths Ms, table offsets ofs; device arrays)

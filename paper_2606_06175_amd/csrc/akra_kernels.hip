@@ -8,408 +8,9 @@
 //   epilogue      E/B combination (eq. EB_decomp), K_l, + lambda_eff x   (eq. ML_estimator_reg)
 #include <type_traits>
 
-#include "akra_fft.h"
-#include "akra_internal.h"
+#include "akra_leg.h"
 
 namespace akra {
-
-// Recurrence forms of the Legendre kernels: 0 the plain three-term form in its scaled variant (FP64,
-// and FP32 away from the poles; see Coef64S), 1 the difference form of FP32 near the poles (see
-// Coef32D).  The batched matrix-core synthesis runs the unscaled plain form (CoefB).
-template <typename T, int F> struct CoefT;
-template <> struct CoefT<double, 0> { using type = Coef64S; };
-template <> struct CoefT<float, 0> { using type = Coef32S; };
-template <> struct CoefT<float, 1> { using type = Coef32D; };
-template <int F> struct CoefB;
-template <> struct CoefB<0> { using type = Coef32; };
-template <> struct CoefB<1> { using type = Coef32D; };
-
-// ------------------------------------------------------------------------------------------------
-// Entry states: stored in FP64 as mant * 2^(512 k).  FP32 kernels re-express them in their own unit.
-// ------------------------------------------------------------------------------------------------
-// i0, i1: 1 / c_l and 1 / c_{l-1} at the entry degree l for the scaled plain form (mu = lambda / c);
-// the difference form and the unscaled plain form pass 1.
-template <typename T, int F>
-__device__ __forceinline__ void load_entry(const Ent64 *__restrict__ ent, const int *__restrict__ entk, int64_t idx,
-                                           T &c2, T &p2, T &cm, T &pm, int &k, double i0 = 1.0, double i1 = 1.0)
-{
-    Ent64 e = ent[idx];
-    const int k64 = entk[idx];
-    if constexpr (F == 0) {
-        e.c2 *= i0;
-        e.cm *= i0;
-        e.p2 *= i1;
-        e.pm *= i1;
-    }
-    if constexpr (std::is_same<T, double>::value) {
-        c2 = e.c2;
-        p2 = e.p2;
-        cm = e.cm;
-        pm = e.pm;
-        k = k64;
-    } else {
-        // difference form: p2, pm carry lambda_l - lambda_{l-1}
-        const double d2 = F ? e.c2 - e.p2 : e.p2, dm = F ? e.cm - e.pm : e.pm;
-        const double big = fmax(fmax(fabs(e.c2), fabs(e.cm)), fmax(fabs(d2), fabs(dm)));
-        if (big == 0.0) {
-            c2 = p2 = cm = pm = 0.0f;
-            k = 0;
-            return;
-        }
-        const int ex = ilogb(big) + 512 * k64;
-        const int k32 = (ex >= -40) ? 0 : -((20 - ex) / 64);
-        const int sh = 512 * k64 - 64 * k32;
-        c2 = (float)ldexp(e.c2, sh);
-        p2 = (float)ldexp(d2, sh);
-        cm = (float)ldexp(e.cm, sh);
-        pm = (float)ldexp(dm, sh);
-        k = k32;
-    }
-}
-
-template <typename T> __device__ __forceinline__ T scale_hi();
-template <> __device__ __forceinline__ double scale_hi<double>() { return 0x1p256; }
-template <> __device__ __forceinline__ float scale_hi<float>() { return 0x1p32f; }
-template <typename T> __device__ __forceinline__ T scale_down();
-template <> __device__ __forceinline__ double scale_down<double>() { return 0x1p-512; }
-template <> __device__ __forceinline__ float scale_down<float>() { return 0x1p-64f; }
-
-// A read-only pointer that is the same in every lane, made explicit for the compiler: the value is
-// taken from the first lane and the result lives in the constant address space, so uniform loads
-// through it become scalar loads.
-template <typename P> using const_as = const __attribute__((address_space(4))) P;
-template <typename P> __device__ __forceinline__ const_as<P> *uniform_ptr(const P *p)
-{
-    const uint64_t v = (uint64_t)p;
-    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
-    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
-    return (const_as<P> *)(((uint64_t)hi << 32) | lo);
-}
-
-__device__ __forceinline__ Coef64 ld_coef(const_as<Coef64> *p)
-{
-    Coef64 c;
-    c.a = p->a;
-    c.b = p->b;
-    c.g = p->g;
-    c.pad = 0;
-    return c;
-}
-__device__ __forceinline__ Coef32 ld_coef(const_as<Coef32> *p)
-{
-    Coef32 c;
-    c.a = p->a;
-    c.b = p->b;
-    c.g = p->g;
-    c.pad = 0;
-    return c;
-}
-// the recurrence reads a' and b' only (scalar registers are scarce in the adjoint's look-ahead)
-__device__ __forceinline__ Coef64S ld_coef(const_as<Coef64S> *p)
-{
-    Coef64S c;
-    c.a = p->a;
-    c.b = p->b;
-    c.c = c.ic = 0.0;
-    return c;
-}
-__device__ __forceinline__ Coef32S ld_coef(const_as<Coef32S> *p)
-{
-    Coef32S c;
-    c.a = p->a;
-    c.b = p->b;
-    c.c = c.ic = 0.0f;
-    return c;
-}
-__device__ __forceinline__ Coef32D ld_coef(const_as<Coef32D> *p)
-{
-    Coef32D c;
-    c.a = p->a;
-    c.ep = p->ep;
-    c.em = p->em;
-    c.g = p->g;
-    return c;
-}
-
-// The ring pair's position as the recurrences use it.  FP64: x = cos(theta).  FP32 carries its
-// coordinate as an unevaluated sum hi + lo of two floats, x = cos(theta) in the plain form and
-// y = 1 - cos(theta) (exact in double for the ring's defining z) in the difference form: rounding
-// it to one float would move the ring by a fixed angle, an error that grows linearly along l.
-struct XF {
-    float hi, lo;
-};
-struct YF {
-    float hi, lo;
-};
-template <typename T, int F> struct PosT;
-template <> struct PosT<double, 0> { using type = double; };
-template <> struct PosT<float, 0> { using type = XF; };
-template <> struct PosT<float, 1> { using type = YF; };
-__device__ __forceinline__ void setpos(double &x, double z) { x = z; }
-__device__ __forceinline__ void setpos(XF &x, double z)
-{
-    x.hi = (float)z;
-    x.lo = (float)(z - (double)x.hi);
-}
-__device__ __forceinline__ void setpos(YF &y, double z)
-{
-    const double v = 1.0 - z;
-    y.hi = (float)v;
-    y.lo = (float)(v - (double)y.hi);
-}
-
-// One step l -> l+1 of the spin +2 and spin -2 recurrences.  Plain form: (c2, p2) = (lambda_l,
-// lambda_{l-1}).  Difference form: (c2, p2) = (lambda_l, lambda_l - lambda_{l-1}).
-template <class C>
-__device__ __forceinline__ void rstep(const C &c, double x, double &c2, double &p2, double &cm, double &pm)
-{
-    const double u = c.a * x;
-    const double n2 = fma(u + c.b, c2, -(c.g * p2));
-    const double nm = fma(u - c.b, cm, -(c.g * pm));
-    p2 = c2;
-    c2 = n2;
-    pm = cm;
-    cm = nm;
-}
-template <class C>
-__device__ __forceinline__ void rstep(const C &c, XF x, float &c2, float &p2, float &cm, float &pm)
-{
-    const float u = fmaf(c.a, x.hi, c.a * x.lo);
-    const float n2 = fmaf(u + c.b, c2, -(c.g * p2));
-    const float nm = fmaf(u - c.b, cm, -(c.g * pm));
-    p2 = c2;
-    c2 = n2;
-    pm = cm;
-    cm = nm;
-}
-template <class C>
-__device__ __forceinline__ void rstep(const C &c, YF y, float &c2, float &p2, float &cm, float &pm)
-{
-    const float t = c.a * y.lo;
-    const float kp = fmaf(-c.a, y.hi, c.ep - t), km = fmaf(-c.a, y.hi, c.em - t);
-    p2 = fmaf(kp, c2, c.g * p2);
-    pm = fmaf(km, cm, c.g * pm);
-    c2 += p2;
-    cm += pm;
-}
-
-// Scaled plain form (Coef64S): mu_{l+1} = (a' x +- b') mu_l - mu_{l-1}, two FMAs per spin.
-__device__ __forceinline__ void rstep_s(double a, double b, double x, double &c2, double &p2, double &cm, double &pm)
-{
-    const double n2 = fma(fma(a, x, b), c2, -p2);
-    const double nm = fma(fma(a, x, -b), cm, -pm);
-    p2 = c2;
-    c2 = n2;
-    pm = cm;
-    cm = nm;
-}
-__device__ __forceinline__ void rstep_s(float a, float b, XF x, float &c2, float &p2, float &cm, float &pm)
-{
-    const float up = fmaf(a, x.hi, fmaf(a, x.lo, b)), um = fmaf(a, x.hi, fmaf(a, x.lo, -b));
-    const float n2 = fmaf(up, c2, -p2);
-    const float nm = fmaf(um, cm, -pm);
-    p2 = c2;
-    c2 = n2;
-    pm = cm;
-    cm = nm;
-}
-__device__ __forceinline__ void rstep(const Coef64S &c, double x, double &c2, double &p2, double &cm, double &pm)
-{
-    rstep_s(c.a, c.b, x, c2, p2, cm, pm);
-}
-__device__ __forceinline__ void rstep(const Coef32S &c, XF x, float &c2, float &p2, float &cm, float &pm)
-{
-    rstep_s(c.a, c.b, x, c2, p2, cm, pm);
-}
-
-// wave-uniform "any lane"
-__device__ __forceinline__ bool wave_any(bool p) { return __ballot(p) != 0ull; }
-
-// ================================================================================================
-// Legendre synthesis: for every (m, ring pair) accumulate
-//   P2[par] += 2lambda_lm * (aE, aB),  Pm[par] += -2lambda_lm * (aE, aB)       par = (l + m) mod 2
-// over l = max(m,2) .. lmax, with the recurrence values of the north ring in registers.  The south
-// ring follows from 2lambda_lm(pi - theta) = (-1)^(l+m) -2lambda_lm(theta).  Then
-//   F(m) = -(sum 2lambda (aE + i aB)),  F(-m) = -(sum -2lambda (conj aE + i conj aB)).
-// One wave handles 64*R ring pairs of one m; per-l data (alm, coefficients) are wave-uniform.
-// ================================================================================================
-// Per-(l, m) wave-uniform input of the synthesis, written by the prologue: the coefficients a', b'
-// of the scaled plain form next to c_l K_l alm (Im(a_l0) zeroed), one record of 8 values so that a
-// step is a single scalar load.  The record buffer is padded so look-ahead loads stay in bounds.
-template <typename T> struct SynRec;
-template <> struct alignas(64) SynRec<double> {
-    double a, b, g, pad, er, ei, br, bi;
-};
-template <> struct alignas(32) SynRec<float> {
-    float a, b, g, pad, er, ei, br, bi;
-};
-// record of the difference form, assembled from the coefficient table and the alm records
-struct SynRecD {
-    float a, ep, em, g, er, ei, br, bi;
-};
-template <typename T> using SynIn = SynRec<T>;
-__device__ __forceinline__ void rstep(const SynRec<double> &c, double x, double &c2, double &p2, double &cm, double &pm)
-{
-    rstep_s(c.a, c.b, x, c2, p2, cm, pm);
-}
-__device__ __forceinline__ void rstep(const SynRec<float> &c, XF x, float &c2, float &p2, float &cm, float &pm)
-{
-    rstep_s(c.a, c.b, x, c2, p2, cm, pm);
-}
-
-__device__ __forceinline__ SynRec<double> ld_rec(const_as<SynRec<double>> *p)
-{
-    SynRec<double> r;
-    r.a = p->a;
-    r.b = p->b;
-    r.g = p->g;
-    r.pad = 0.0;
-    r.er = p->er;
-    r.ei = p->ei;
-    r.br = p->br;
-    r.bi = p->bi;
-    return r;
-}
-__device__ __forceinline__ SynRec<float> ld_rec(const_as<SynRec<float>> *p)
-{
-    SynRec<float> r;
-    r.a = p->a;
-    r.b = p->b;
-    r.g = p->g;
-    r.pad = 0.0f;
-    r.er = p->er;
-    r.ei = p->ei;
-    r.br = p->br;
-    r.bi = p->bi;
-    return r;
-}
-
-
-template <typename T>
-__device__ __forceinline__ SynIn<T> syn_load(const SynRec<T> *__restrict__ rec, int l)
-{
-    return rec[l];
-}
-
-// Wave-uniform source of the synthesis records of form F: the prologue's records for the plain form;
-// for the FP32 difference form the coefficients come from their own table and the unscaled alm
-// values from the prologue's second record buffer.
-template <typename T, int F> struct SynSrc;
-template <typename T> struct SynSrc<T, 0> {
-    const_as<SynRec<T>> *r;
-    __device__ __forceinline__ SynSrc(const SynRec<T> *rec, const float4 *, const Coef32D *) : r(uniform_ptr(rec)) {}
-    __device__ __forceinline__ SynRec<T> at(int i) const { return ld_rec(r + i); }
-    __device__ __forceinline__ void adv(int n) { r += n; }
-};
-template <> struct SynSrc<float, 1> {
-    const_as<float4> *r;
-    const_as<Coef32D> *c;
-    __device__ __forceinline__ SynSrc(const SynRec<float> *, const float4 *recu, const Coef32D *cf)
-        : r(uniform_ptr(recu)), c(uniform_ptr(cf))
-    {
-    }
-    __device__ __forceinline__ SynRecD at(int i) const
-    {
-        SynRecD o;
-        o.a = c[i].a;
-        o.ep = c[i].ep;
-        o.em = c[i].em;
-        o.g = c[i].g;
-        o.er = r[i].x;
-        o.ei = r[i].y;
-        o.br = r[i].z;
-        o.bi = r[i].w;
-        return o;
-    }
-    __device__ __forceinline__ void adv(int n)
-    {
-        r += n;
-        c += n;
-    }
-};
-
-// XCD-aware placement: workgroups are dealt to the 8 XCDs round-robin, so all blocks of one m
-// are mapped to blocks with the same index mod 8 (they share that XCD's L2 for the per-m data),
-// and each XCD walks its m values in increasing order (decreasing work).
-__device__ __forceinline__ void xcd_map(int b, int nbm, int &m, int &blk)
-{
-    const int xcd = b & 7, local = b >> 3;
-    m = xcd + 8 * (local / nbm);
-    blk = local - (local / nbm) * nbm;
-}
-
-template <typename T, int R, bool MASK, typename In, typename X>
-__device__ __forceinline__ void syn_step(const In &in, const X (&x)[R], T (&c2)[R], T (&p2)[R], T (&cm)[R],
-                                         T (&pm)[R], const int (&k)[R], T (&acc)[8][R])
-{
-#pragma unroll
-    for (int j = 0; j < R; ++j) {
-        T v2 = c2[j], vm = cm[j];
-        if (MASK) {
-            if (k[j] != 0) v2 = vm = (T)0;
-        }
-        acc[0][j] = fma(v2, in.er, acc[0][j]);
-        acc[1][j] = fma(v2, in.ei, acc[1][j]);
-        acc[2][j] = fma(v2, in.br, acc[2][j]);
-        acc[3][j] = fma(v2, in.bi, acc[3][j]);
-        acc[4][j] = fma(vm, in.er, acc[4][j]);
-        acc[5][j] = fma(vm, in.ei, acc[5][j]);
-        acc[6][j] = fma(vm, in.br, acc[6][j]);
-        acc[7][j] = fma(vm, in.bi, acc[7][j]);
-        rstep(in, x[j], c2[j], p2[j], cm[j], pm[j]);
-    }
-}
-
-template <typename T, int R>
-__device__ __forceinline__ bool rescale(T (&c2)[R], T (&p2)[R], T (&cm)[R], T (&pm)[R], int (&k)[R])
-{
-    bool any_neg = false;
-#pragma unroll
-    for (int j = 0; j < R; ++j) {
-        if (k[j] < 0) {
-            T big = fmax(fabs(c2[j]), fabs(cm[j]));
-            if (big > scale_hi<T>()) {
-                const T d = scale_down<T>();
-                c2[j] *= d;
-                p2[j] *= d;
-                cm[j] *= d;
-                pm[j] *= d;
-                k[j] += 1;
-            }
-            any_neg |= (k[j] < 0);
-        }
-    }
-    return wave_any(any_neg);
-}
-
-// Rescale check of the synthesis ramp: a lane whose exponent reaches zero restarts its sums (what it
-// accumulated while scaled is discarded).  Returns whether any lane of the wave is still scaled.
-template <typename T, int R>
-__device__ __forceinline__ bool rescale_restart(T (&c2)[R], T (&p2)[R], T (&cm)[R], T (&pm)[R], int (&k)[R],
-                                                T (&acc0)[8][R], T (&acc1)[8][R])
-{
-    bool any_neg = false;
-#pragma unroll
-    for (int j = 0; j < R; ++j) {
-        if (k[j] < 0) {
-            const T big = fmax(fabs(c2[j]), fabs(cm[j]));
-            if (big > scale_hi<T>()) {
-                const T d = scale_down<T>();
-                c2[j] *= d;
-                p2[j] *= d;
-                cm[j] *= d;
-                pm[j] *= d;
-                k[j] += 1;
-                if (k[j] == 0) {
-#pragma unroll
-                    for (int c = 0; c < 8; ++c) acc0[c][j] = acc1[c][j] = (T)0;
-                }
-            }
-            any_neg |= (k[j] < 0);
-        }
-    }
-    return wave_any(any_neg);
-}
 
 // ------------------------------------------------------------------------------------------------
 // Entry states (plan build).  One wave per (m, 64-pair group) runs the FP64 recurrence from the
@@ -498,445 +99,11 @@ __global__ __launch_bounds__(256) void k_entry(const double *__restrict__ seed2,
     if (lane == 0) entl[(int64_t)m * ng + g] = res;
 }
 
-// Start of a slot j whose group enters later than the wave (its values are zero until then).
-// ct: the m's row of the scaled table (1 / c_l for the entry of the scaled plain form)
-template <typename T, int R, int F>
-__device__ __forceinline__ void inject(int l, const int (&e)[R], const int (&pr)[R], const Ent64 *__restrict__ ent,
-                                       const int *__restrict__ entk, int64_t row, int npairs, T (&c2)[R], T (&p2)[R],
-                                       T (&cm)[R], T (&pm)[R], int (&k)[R], const_as<Coef64S> *ct)
-{
-#pragma unroll
-    for (int j = 0; j < R; ++j)
-        if (e[j] == l && pr[j] < npairs)
-            load_entry<T, F>(ent, entk, row + pr[j], c2[j], p2[j], cm[j], pm[j], k[j], ct[l].ic, ct[l - 1].ic);
-}
-
-template <int R> __device__ __forceinline__ bool pending(int l, int lmax, const int (&e)[R])
-{
-    bool q = false;
-#pragma unroll
-    for (int j = 0; j < R; ++j) q |= (e[j] > l && e[j] <= lmax);
-    return q;
-}
-
-// Waves gbeg .. gend-1 (wave w holds the 64-pair groups w R .. w R + R - 1) of every m.
-template <typename T, int R, int V, int F>
-__global__ __launch_bounds__(256) void k_leg_synth(const SynRec<T> *__restrict__ recs, int64_t rec_stride,
-                                                   const float4 *__restrict__ recus, const Coef64S *__restrict__ cs64,
-                                                   const Coef32D *__restrict__ coefd, cplx<T> *__restrict__ FG,
-                                                   int64_t fg_stride, const Ent64 *__restrict__ ent,
-                                                   const int *__restrict__ entk, const int *__restrict__ entl,
-                                                   int ng64, const double *__restrict__ pair_z, int lmax, int npairs,
-                                                   int nrings, int gbeg, int gend, int nbm)
-{
-    const int rhs = blockIdx.y;
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    int m, blk;
-    xcd_map((int)blockIdx.x, nbm, m, blk);
-    const int grp = gbeg + blk * 4 + wave;
-    if (m > lmax || grp >= gend) return;
-    const int l0 = m > 2 ? m : 2;
-    const int64_t base = (int64_t)m * (2 * lmax + 1 - m) / 2;
-    const SynRec<T> *rec = recs + rhs * rec_stride + base;
-    const float4 *recu = F ? recus + rhs * rec_stride + base : nullptr;
-    const Coef32D *cfd = coefd + base;
-    const_as<Coef64S> *ct = uniform_ptr(cs64 + base);
-    const SynSrc<T, F> src(rec, recu, cfd);
-    auto rload = [&](int i) {
-        if constexpr (F == 0) return rec[i];
-        else return src.at(i);
-    };
-
-    typename PosT<T, F>::type x[R];
-    T c2[R], p2[R], cm[R], pm[R];
-    int k[R], pr[R], e[R];
-    T acc0[8][R], acc1[8][R];
-    // entry degree of each slot's 64-pair group; the wave starts at the earliest
-    const_as<int> *el = uniform_ptr(entl + (int64_t)m * ng64);
-    int ls = ENT_SKIP;
-#pragma unroll
-    for (int j = 0; j < R; ++j) {
-        const int g = grp * R + j;
-        e[j] = g < ng64 ? el[g] : ENT_SKIP;
-        ls = e[j] < ls ? e[j] : ls;
-    }
-    const int64_t row = (int64_t)m * npairs;
-    bool neg = false;
-#pragma unroll
-    for (int j = 0; j < R; ++j) {
-        const int p = grp * 64 * R + j * 64 + lane;
-        pr[j] = p;
-        setpos(x[j], 0.0);
-        c2[j] = p2[j] = cm[j] = pm[j] = (T)0;
-        k[j] = 0;
-        if (p < npairs) {
-            setpos(x[j], pair_z[p]);
-            if (e[j] == ls && ls <= lmax)
-                load_entry<T, F>(ent, entk, row + p, c2[j], p2[j], cm[j], pm[j], k[j], ct[ls].ic, ct[ls - 1].ic);
-        }
-        neg |= (k[j] < 0);
-#pragma unroll
-        for (int c = 0; c < 8; ++c) acc0[c][j] = acc1[c][j] = (T)0;
-    }
-    // Lanes whose scale exponent is still negative ("ramp") run the same unmasked steps: their
-    // scaled values accumulate garbage that is discarded when the lane's exponent reaches zero (its
-    // sums restart there) or at the end; the check runs once per trip of S steps, which the growth
-    // of the recurrence over S steps keeps far from overflow.
-    bool pend = R > 1 && pending<R>(ls, lmax, e);
-    bool ramp = wave_any(neg);
-    constexpr int S = V == 0 ? 2 : 4;
-    int l = __builtin_amdgcn_readfirstlane(ls <= lmax ? ls : lmax + 1);
-    SynSrc<T, F> rp(rec + l, F ? recu + l : nullptr, cfd + l);
-    auto a0 = rp.at(0), a1 = rp.at(1), b0 = a0, b1 = a1;
-    for (; l + S - 1 <= lmax; l += S, rp.adv(S)) {
-        if (pend) {
-            // a slot enters at its group's entry degree (entries are l0 + 8q, trips start at ls + S q)
-            inject<T, R, F>(l, e, pr, ent, entk, row, npairs, c2, p2, cm, pm, k, ct);
-            pend = pending<R>(l, lmax, e);
-            bool ng = false;
-#pragma unroll
-            for (int j = 0; j < R; ++j) ng |= (k[j] < 0);
-            ramp = ramp || wave_any(ng);
-        }
-        if constexpr (S == 4) {
-            b0 = rp.at(2);
-            b1 = rp.at(3);
-            syn_step<T, R, false>(a0, x, c2, p2, cm, pm, k, acc0);
-            syn_step<T, R, false>(a1, x, c2, p2, cm, pm, k, acc1);
-            a0 = rp.at(4);
-            a1 = rp.at(5);
-            syn_step<T, R, false>(b0, x, c2, p2, cm, pm, k, acc0);
-            syn_step<T, R, false>(b1, x, c2, p2, cm, pm, k, acc1);
-        } else {
-            syn_step<T, R, false>(a0, x, c2, p2, cm, pm, k, acc0);
-            syn_step<T, R, false>(a1, x, c2, p2, cm, pm, k, acc1);
-            a0 = rp.at(2);
-            a1 = rp.at(3);
-        }
-        if (ramp) ramp = rescale_restart<T, R>(c2, p2, cm, pm, k, acc0, acc1);
-    }
-    // tail (fewer than S steps)
-    for (int t = 0; l <= lmax; ++l, ++t) {
-        if (pend) inject<T, R, F>(l, e, pr, ent, entk, row, npairs, c2, p2, cm, pm, k, ct);
-        if (t & 1) syn_step<T, R, false>(rload(l), x, c2, p2, cm, pm, k, acc1);
-        else syn_step<T, R, false>(rload(l), x, c2, p2, cm, pm, k, acc0);
-    }
-    // lanes that never left the scaled range contribute nothing
-#pragma unroll
-    for (int j = 0; j < R; ++j)
-        if (k[j] < 0) {
-#pragma unroll
-            for (int c = 0; c < 8; ++c) acc0[c][j] = acc1[c][j] = (T)0;
-        }
-
-    const bool odd0 = ((l0 + m) & 1) != 0;  // acc0 holds l + m odd terms when true
-    cplx<T> *Fb = FG + rhs * fg_stride;
-#pragma unroll
-    for (int j = 0; j < R; ++j) {
-        if (pr[j] >= npairs) continue;
-        T E[8], O[8];
-#pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            E[c] = odd0 ? acc1[c][j] : acc0[c][j];
-            O[c] = odd0 ? acc0[c][j] : acc1[c][j];
-        }
-        const int rn = pr[j], rs = nrings - 1 - pr[j];
-        {
-            T S2[4], Sm[4];
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                S2[c] = E[c] + O[c];
-                Sm[c] = E[4 + c] + O[4 + c];
-            }
-            cplx<T> *f = Fb + ((int64_t)rn * (lmax + 1) + m) * 2;
-            f[0] = mk<T>(-(S2[0] - S2[3]), -(S2[1] + S2[2]));
-            f[1] = mk<T>(-(Sm[0] + Sm[3]), -(Sm[2] - Sm[1]));
-        }
-        if (rs != rn) {
-            T S2[4], Sm[4];
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                S2[c] = E[4 + c] - O[4 + c];
-                Sm[c] = E[c] - O[c];
-            }
-            cplx<T> *f = Fb + ((int64_t)rs * (lmax + 1) + m) * 2;
-            f[0] = mk<T>(-(S2[0] - S2[3]), -(S2[1] + S2[2]));
-            f[1] = mk<T>(-(Sm[0] + Sm[3]), -(Sm[2] - Sm[1]));
-        }
-    }
-}
-
-// ================================================================================================
-// Legendre adjoint: for one m and a block of ring pairs, the partial sums
-//   2h_lm  = sum_r 2lambda_lm(theta_r) G_r(m),      -2h_lm = sum_r -2lambda_lm(theta_r) conj(G_r(-m))
-// (south rings through the reflection symmetry).  Each lane sums its R ring pairs in registers;
-// every L steps of l the per-lane partials go through LDS and are reduced over the workgroup.
-// ================================================================================================
-template <typename T, int R, bool MASK, bool ODD, typename C, typename X>
-__device__ __forceinline__ void adj_step(const C &c, const X (&x)[R], T (&c2)[R],
-                                         T (&p2)[R], T (&cm)[R], T (&pm)[R], const int (&k)[R],
-                                         const cplx<T> (&GN)[R], const cplx<T> (&GS)[R], const cplx<T> (&HN)[R],
-                                         const cplx<T> (&HS)[R], T (&out)[4])
-{
-    T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-#pragma unroll
-    for (int j = 0; j < R; ++j) {
-        T v2 = c2[j], vm = cm[j];
-        if (MASK) {
-            if (k[j] != 0) v2 = vm = (T)0;
-        }
-        const T s = ODD ? (T)-1 : (T)1;
-        a0 = fma(v2, GN[j].x, a0);
-        a1 = fma(v2, GN[j].y, a1);
-        a2 = fma(vm, HN[j].x, a2);
-        a3 = fma(vm, HN[j].y, a3);
-        a0 = fma(s * vm, GS[j].x, a0);
-        a1 = fma(s * vm, GS[j].y, a1);
-        a2 = fma(s * v2, HS[j].x, a2);
-        a3 = fma(s * v2, HS[j].y, a3);
-        rstep(c, x[j], c2[j], p2[j], cm[j], pm[j]);
-    }
-    out[0] = a0;
-    out[1] = a1;
-    out[2] = a2;
-    out[3] = a3;
-}
-
-// Occupancy the adjoint is compiled for (waves per SIMD): the FP64 form with four ring pairs per
-// lane would otherwise use about 175 registers and run two waves per SIMD, too few to hide its LDS
-// round trips; at three the compiler spills only registers of the rarely taken group-entry path.
-// Eight pairs per lane cannot fit three waves without spilling in the inner loop: no target there.
-template <typename T, int R> struct AdjWaves {
-    static constexpr int value = R > 4 ? 1 : std::is_same<T, double>::value ? 3 : 4;
-};
-// LDS hand-over between the lanes of a workgroup.  A single-wave workgroup needs no s_barrier: the
-// LDS unit executes one wave's instructions in order, so a fence that keeps the compiler from moving
-// LDS accesses across it suffices, and no full wait for outstanding LDS operations is forced.
-// value of lane l ^ 1, l ^ 2 (DPP quad permutations) and of the mirrored lane in the half-row of
-// 8 or the row of 16 lanes (row_half_mirror, row_mirror)
-template <int CTRL> __device__ __forceinline__ float dpp_mov(float v)
-{
-    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xf, 0xf, false));
-}
-template <int CTRL> __device__ __forceinline__ double dpp_mov(double v)
-{
-    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xf, 0xf, false);
-    return __hiloint2double(hi, lo);
-}
-// sum over the aligned group of G lanes (G = 1, 2, 4, 8, 16), in every lane of the group
-template <int G, typename T> __device__ __forceinline__ T group_sum(T s)
-{
-    static_assert(G == 1 || G == 2 || G == 4 || G == 8 || G == 16, "group size");
-    if constexpr (G >= 2) s += dpp_mov<0xB1>(s);   // quad_perm [1, 0, 3, 2]
-    if constexpr (G >= 4) s += dpp_mov<0x4E>(s);   // quad_perm [2, 3, 0, 1]
-    if constexpr (G >= 8) s += dpp_mov<0x141>(s);  // row_half_mirror: lane 7 - i of the half-row
-    if constexpr (G >= 16) s += dpp_mov<0x140>(s); // row_mirror: lane 15 - i of the row
-    return s;
-}
-
-template <int W> __device__ __forceinline__ void wg_lds_sync()
-{
-    if constexpr (W == 1) {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    } else {
-        __syncthreads();
-    }
-}
-
-// Workgroups rb0 .. rb0 + nrbl - 1 of the nrb ring blocks of every m; this launch's workgroup rbl
-// holds the 64-pair groups g0 + rbl W R .. g0 + (rbl + 1) W R - 1, bounded by gend.
-template <typename T, int R, int W, int L, int F>
-__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(AdjWaves<T, R>::value))) void k_leg_adj(const cplx<T> *__restrict__ FG,
-                                                    const typename CoefT<T, F>::type *__restrict__ coef,
-                                                    const Coef64S *__restrict__ cs64,
-                                                    const Ent64 *__restrict__ ent, const int *__restrict__ entk,
-                                                    const int *__restrict__ entl, int ng64,
-                                                    const double *__restrict__ pair_z, T *__restrict__ part,
-                                                    int *__restrict__ wgstart, int64_t nalm, int lmax, int npairs,
-                                                    int nrings, int g0, int gend, int rb0, int nrbl, int nrb)
-{
-    // LDS columns (wave, l, c) of 64 lanes, padded to CS entries: the G threads that sum one column
-    // read entries gi + G t of it, and with CS = 64 + G (mod 32 double-banks) the 64 threads of a
-    // wave spread over the banks twice each, as do the lane-contiguous writes
-    constexpr int GR = 16 * W / L, CS = 64 + GR;
-    __shared__ T red[W * L * 4 * CS];
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    int m, rbl;
-    xcd_map((int)blockIdx.x, nrbl, m, rbl);
-    if (m > lmax) return;
-    const int rb = rb0 + rbl;
-    const int gw = g0 + rbl * W * R;                            // first group of the workgroup
-    const int pb = npairs < 64 * gend ? npairs : 64 * gend;    // pairs of this launch end here
-    const int l0 = m > 2 ? m : 2;
-    const int64_t base = (int64_t)m * (2 * lmax + 1 - m) / 2;
-    const auto *cf = coef + base;
-    const_as<Coef64S> *ct = uniform_ptr(cs64 + base);
-    const T sgn0 = ((l0 + m) & 1) ? (T)-1 : (T)1;
-
-    // entry degrees of the workgroup's 64-pair groups: the workgroup starts at the earliest, a slot
-    // whose group enters later holds zeros until its entry (always at a chunk start: entries are
-    // l0 + 8q and chunks start at l0 + Lq)
-    const_as<int> *el = uniform_ptr(entl + (int64_t)m * ng64);
-    int ls = ENT_SKIP;
-    for (int g = gw; g < gw + W * R && g < gend; ++g) ls = el[g] < ls ? el[g] : ls;
-    if (threadIdx.x == 0) wgstart[(int64_t)m * nrb + rb] = ls;
-    if (ls > lmax) return;
-    int e[R], pr[R];
-#pragma unroll
-    for (int j = 0; j < R; ++j) {
-        const int g = gw + wave * R + j;
-        e[j] = g < gend ? el[g] : ENT_SKIP;
-    }
-    const int64_t row = (int64_t)m * npairs;
-
-    typename PosT<T, F>::type x[R];
-    T c2[R], p2[R], cm[R], pm[R];
-    int k[R];
-    cplx<T> GN[R], GS[R], HN[R], HS[R];
-    bool neg = false;
-#pragma unroll
-    for (int j = 0; j < R; ++j) {
-        const int p = (gw + wave * R + j) * 64 + lane;
-        pr[j] = p;
-        const cplx<T> z = mk<T>(0, 0);
-        GN[j] = GS[j] = HN[j] = HS[j] = z;
-        setpos(x[j], 0.0);
-        c2[j] = cm[j] = p2[j] = pm[j] = (T)0;
-        k[j] = 0;
-        if (p < pb) {
-            setpos(x[j], pair_z[p]);
-            if (e[j] == ls)
-                load_entry<T, F>(ent, entk, row + p, c2[j], p2[j], cm[j], pm[j], k[j], ct[ls].ic, ct[ls - 1].ic);
-        }
-        neg |= (k[j] < 0);
-    }
-    // G of slot j's ring pair; lanes still in the scaled range (k < 0) hold G = 0, so the unmasked
-    // steps add nothing for them until their exponent reaches zero and G is loaded
-    auto load_g = [&](int j) {
-        const int p = pr[j];
-        if (p >= pb || k[j] < 0) return;
-        const int rn = p, rs = nrings - 1 - p;
-        const cplx<T> *fn = FG + ((int64_t)rn * (lmax + 1) + m) * 2;
-        GN[j] = fn[0];
-        HN[j] = cconj<T>(fn[1]);
-        if (rs != rn) {
-            const cplx<T> *fs = FG + ((int64_t)rs * (lmax + 1) + m) * 2;
-            GS[j] = cscale<T>(fs[0], sgn0);
-            HS[j] = cscale<T>(cconj<T>(fs[1]), sgn0);
-        }
-    };
-#pragma unroll
-    for (int j = 0; j < R; ++j)
-        if (e[j] == ls) load_g(j);
-    bool ramp = wave_any(neg);
-    bool pend = (R > 1 || W > 1) && pending<R>(ls, lmax, e);
-    constexpr int NT = 64 * W, NO = 4 * L, G = NT / NO;
-    static_assert(G == GR && G >= 1 && 64 % G == 0 && NT % (4 * G) == 0, "reduction layout");
-    const int t = threadIdx.x, o = t / G, gi = t - o * G;
-    const int oli = o >> 2, oc = o & 3;
-    const T *col = red + o * CS + gi;                                   // column o, entry gi
-    T *pout = part + ((int64_t)rb * nalm + base + ls + oli) * 4 + oc;  // output of the first chunk
-
-    using C = typename CoefT<T, F>::type;
-    // coefficient records through an explicitly uniform pointer (scalar loads); the table is padded
-    // past its last column, so the look-ahead loads stay in bounds
-    const_as<C> *cp = uniform_ptr(cf + ls);
-    C cc[L];
-#pragma unroll
-    for (int li = 0; li < L; ++li) cc[li] = ld_coef(cp + li);
-    for (int lc = ls; lc <= lmax; lc += L, cp += L) {
-        if (pend) {
-            inject<T, R, F>(lc, e, pr, ent, entk, row, pb, c2, p2, cm, pm, k, ct);
-            bool ng = false;
-#pragma unroll
-            for (int j = 0; j < R; ++j) {
-                if (e[j] == lc) load_g(j);
-                ng |= (k[j] < 0);
-            }
-            ramp = ramp || wave_any(ng);
-            pend = pending<R>(lc, lmax, e);
-        }
-        // the next chunk's coefficients (scalar loads) are issued before this chunk's steps: they
-        // share the LDS wait counter, and must have arrived by the time the reduction waits on LDS
-        C nc[L];
-#pragma unroll
-        for (int li = 0; li < L; ++li) nc[li] = ld_coef(cp + L + li);
-        // c_l of this thread's output row for the scaled plain form (a vector load, used at the store)
-        T sc = (T)1;
-        if constexpr (F == 0) sc = cf[lc + oli < lmax ? lc + oli : lmax].c;
-        // all L steps unmasked: rows past lmax (last chunk) are reduced but not stored, and the
-        // coefficient table is padded past its last column
-#pragma unroll
-        for (int li = 0; li < L; li += 2) {
-            T out[4];
-            adj_step<T, R, false, false>(cc[li], x, c2, p2, cm, pm, k, GN, GS, HN, HS, out);
-#pragma unroll
-            for (int c = 0; c < 4; ++c) red[((wave * L + li) * 4 + c) * CS + lane] = out[c];
-            adj_step<T, R, false, true>(cc[li + 1], x, c2, p2, cm, pm, k, GN, GS, HN, HS, out);
-#pragma unroll
-            for (int c = 0; c < 4; ++c) red[((wave * L + li + 1) * 4 + c) * CS + lane] = out[c];
-        }
-        wg_lds_sync<W>();
-        // column sums over the workgroup's lanes: thread (o, gi) reads the entries q = gi + G t of
-        // column o (wave q / 64, lane q % 64) at compile-time offsets from its column base, all
-        // reads first, adds them in four independent partial sums, then sums over the G adjacent
-        // threads sharing the output with DPP lane moves
-        // (in batches of 8 reads, which bounds the registers they hold)
-        constexpr int NR = NT / G, BR = NR < 8 ? NR : 8;
-        static_assert(NR >= 4 && NR % BR == 0, "four partial sums");
-        T ps[4];
-#pragma unroll
-        for (int b0 = 0; b0 < NR; b0 += BR) {
-            T rv[BR];
-#pragma unroll
-            for (int u = 0; u < BR; ++u) rv[u] = col[(G * (b0 + u) / 64) * (L * 4 * CS) + (G * (b0 + u)) % 64];
-#pragma unroll
-            for (int u = 0; u < BR; ++u) {
-                if (b0 + u < 4) ps[u] = rv[u];
-                else ps[(b0 + u) & 3] += rv[u];
-            }
-        }
-        const T s = group_sum<G>((ps[0] + ps[1]) + (ps[2] + ps[3]));
-        // the scaled plain form sums mu: the output of degree lc + oli is c_l times the sum
-        if (gi == 0 && lc + oli <= lmax) pout[(int64_t)(lc - ls) * 4] = s * sc;
-#pragma unroll
-        for (int li = 0; li < L; ++li) cc[li] = nc[li];
-        if (ramp) {
-            // once per chunk (the growth over L steps stays far from overflow): rescale, and load
-            // G for lanes whose exponent reached zero
-            bool any_neg = false;
-#pragma unroll
-            for (int j = 0; j < R; ++j) {
-                if (k[j] < 0) {
-                    const T big = fmax(fabs(c2[j]), fabs(cm[j]));
-                    if (big > scale_hi<T>()) {
-                        const T d = scale_down<T>();
-                        c2[j] *= d;
-                        p2[j] *= d;
-                        cm[j] *= d;
-                        pm[j] *= d;
-                        k[j] += 1;
-                        if (k[j] == 0) load_g(j);
-                    }
-                    any_neg |= (k[j] < 0);
-                }
-            }
-            ramp = wave_any(any_neg);
-        }
-        wg_lds_sync<W>();
-    }
-}
-
 // ================================================================================================
 // prologue / epilogue / weights
 // ================================================================================================
-// records of the scaled plain form (c_l K_l alm, FP64 products) and, when recu is given, the
-// unscaled K_l alm for the difference form
+// records of the scaled plain form (c_l times the u combinations of K_l alm, FP64 arithmetic; see
+// SynRec) and, when recu is given, the unscaled u combinations for the difference form
 template <typename T>
 __global__ void k_prologue(const double *__restrict__ xE, const double *__restrict__ xB, const double *__restrict__ kern,
                            const int *__restrict__ lof, const typename CoefT<T, 0>::type *__restrict__ coef,
@@ -953,17 +120,18 @@ __global__ void k_prologue(const double *__restrict__ xE, const double *__restri
     const double er = K * xE[2 * o], ei = m0 ? 0.0 : K * xE[2 * o + 1];
     const double br = K * xB[2 * o], bi = m0 ? 0.0 : K * xB[2 * o + 1];
     const double s = cs64[i].c;
+    const double u0 = er - bi, u1 = ei + br, u2 = er + bi, u3 = br - ei;
     SynRec<T> r;
     r.a = c.a;
     r.b = c.b;
     r.g = (T)0;
     r.pad = (T)0;
-    r.er = (T)(s * er);
-    r.ei = (T)(s * ei);
-    r.br = (T)(s * br);
-    r.bi = (T)(s * bi);
+    r.u0 = (T)(s * u0);
+    r.u1 = (T)(s * u1);
+    r.u2 = (T)(s * u2);
+    r.u3 = (T)(s * u3);
     rec[rhs * rec_stride + i] = r;
-    if (recu) recu[rhs * rec_stride + i] = make_float4((float)er, (float)ei, (float)br, (float)bi);
+    if (recu) recu[rhs * rec_stride + i] = make_float4((float)u0, (float)u1, (float)u2, (float)u3);
 }
 
 // m of the alm index i = m (2 lmax + 1 - m)/2 + l
@@ -2359,14 +1527,16 @@ __global__ __launch_bounds__(64 * SW) __attribute__((amdgpu_waves_per_eu(2))) vo
                                                      const Ent64 *__restrict__ ent, const int *__restrict__ entk,
                                                      const int *__restrict__ entl, int ng64,
                                                      const double *__restrict__ pair_z, int lmax, int npairs,
-                                                     int nrings, int nrhs, int q, int wbeg, int wend, int nbm)
+                                                     int nrings, int nrhs, int q, const int *__restrict__ glist,
+                                                     int ngl, int nbm)
 {
     const int lane = threadIdx.x & 63, h = lane >> 5, i = lane & 31;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     int m, blk;
     xcd_map((int)blockIdx.x, nbm, m, blk);
-    const int w = wbeg + blk * SW + wave;  // 64-pair group: pairs 64 w .. 64 w + 63
-    if (m > lmax || w >= wend) return;
+    const int wi = blk * SW + wave;  // list entry of the wave
+    if (m > lmax || wi >= ngl) return;
+    const int w = uniform_ptr(glist)[wi];  // 64-pair group: pairs 64 w .. 64 w + 63
     const int l0 = m > 2 ? m : 2;
     const int64_t base = (int64_t)m * (2 * lmax + 1 - m) / 2;
     const int p = 64 * w + lane;
@@ -2489,7 +1659,8 @@ __global__ __launch_bounds__(64 * AW) void k_leg_adj_b(const float2 *__restrict_
                                                         const int *__restrict__ entl, int ng64,
                                                         const double *__restrict__ pair_z, float *__restrict__ part,
                                                         int *__restrict__ wgstart, int64_t nalm, int lmax, int npairs,
-                                                        int nrings, int nrhs, int q, int g0, int gend, int rb0,
+                                                        int nrings, int nrhs, int q, const int *__restrict__ glist,
+                                                        int ngl, const uint8_t *__restrict__ live, int rb0,
                                                         int nrbl, int nrb)
 {
     __shared__ float lam[AW][2][64 * ABS];  // per wave: lambda+ and lambda- of its 64 pairs x 32 rows
@@ -2499,18 +1670,19 @@ __global__ __launch_bounds__(64 * AW) void k_leg_adj_b(const float2 *__restrict_
     xcd_map((int)blockIdx.x, nrbl, m, rbl);
     if (m > lmax) return;
     const int rb = rb0 + rbl;
-    const int gb = g0 + rbl * AW;  // first group of the block
+    const int lb = rbl * AW;  // first list entry of the block
     const int l0 = m > 2 ? m : 2;
     const int64_t base = (int64_t)m * (2 * lmax + 1 - m) / 2;
     const_as<int> *el = uniform_ptr(entl + (int64_t)m * ng64);
+    const_as<int> *gl = uniform_ptr(glist);
     int ls = ENT_SKIP;
-    for (int g = gb; g < gb + AW && g < gend; ++g) ls = el[g] < ls ? el[g] : ls;
+    for (int li = lb; li < lb + AW && li < ngl; ++li) ls = el[gl[li]] < ls ? el[gl[li]] : ls;
     if (threadIdx.x == 0) wgstart[(int64_t)m * nrb + rb] = ls;
     if (ls > lmax) return;
-    const int g = gb + wave;
-    const int e = (g < gend) ? el[g] : ENT_SKIP;  // this wave's entry degree
+    const int g = lb + wave < ngl ? gl[lb + wave] : -1;  // this wave's group
+    const int e = g >= 0 ? el[g] : ENT_SKIP;             // and its entry degree
     const int p = g * 64 + lane;
-    const bool valid = g < gend && p < npairs;
+    const bool valid = g >= 0 && p < npairs;
 
     // B operands: lane l holds, for pair-pair kk, pair 64 g + 2 kk + l / 32 and column j = l % 32
     const int j = lane & 31, c = j & 3, rhs = q * NBR + (j >> 2);
@@ -2519,16 +1691,17 @@ __global__ __launch_bounds__(64 * AW) void k_leg_adj_b(const float2 *__restrict_
     for (int kk = 0; kk < 32; ++kk) {
         Bp[kk] = Bm[kk] = 0.f;
         const int pk = g * 64 + 2 * kk + (lane >> 5);
-        if (e > lmax || g >= gend || pk >= npairs || rhs >= nrhs) continue;
+        if (e > lmax || g < 0 || pk >= npairs || rhs >= nrhs) continue;
         const float2 *Fb = FG + rhs * fg_stride;
         if (c < 2) {
+            if (live && !live[pk]) continue;  // a ring without weight has G = 0
             const float2 *fn = Fb + ((int64_t)pk * (lmax + 1) + m) * 2;
             const float2 gn = fn[0], hn = fn[1];  // HN = conj(hn)
             Bp[kk] = c ? gn.y : gn.x;
             Bm[kk] = c ? -hn.y : hn.x;
         } else {
             const int rs = nrings - 1 - pk;
-            if (rs != pk) {
+            if (rs != pk && (!live || live[rs])) {
                 const float2 *fs = Fb + ((int64_t)rs * (lmax + 1) + m) * 2;
                 const float2 gs = fs[0], hs = fs[1];  // HS = conj(hs)
                 Bp[kk] = (c & 1) ? -hs.y : hs.x;
@@ -2626,7 +1799,6 @@ __global__ __launch_bounds__(64 * AW) void k_leg_adj_b(const float2 *__restrict_
     }
 }
 
-static int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 void launch_prologue(Plan &P, bool fp32, const double *xE, const double *xB, const double *kern, int nrhs)
 {
@@ -2639,109 +1811,87 @@ void launch_prologue(Plan &P, bool fp32, const double *xE, const double *xB, con
                                                     P.rec_stride, (SynRec<double> *)P.d_rec, nullptr);
 }
 
-// synthesis waves over the 64-pair groups [g0, g1) (g0 a multiple of R)
-template <typename T, int R, int V, int F>
-static void syn_launch(Plan &P, int nrhs, int64_t fg_stride, int g0, int g1)
-{
-    const int gbeg = g0 / R, gend = (int)cdiv(g1, R);
-    if (gend <= gbeg) return;
-    const int nbm = (int)cdiv(gend - gbeg, 4);  // blocks of four waves per m
-    const int64_t blocks = 8 * nbm * cdiv(P.lmax + 1, 8);
-    dim3 g((unsigned)blocks, nrhs);
-    k_leg_synth<T, R, V, F><<<g, 256, 0, P.stream>>>((const SynRec<T> *)P.d_rec, P.rec_stride, P.d_recu,
-                                                     P.d_coef64s, P.d_coef32d,
-                                                     (cplx<T> *)P.d_FG, fg_stride, P.d_ent, P.d_entk, P.d_entl,
-                                                      P.ng64, P.d_pair_z, P.lmax, P.npairs, P.nrings, gbeg, gend,
-                                                      nbm);
-}
-
-template <typename T, int V>
-static void syn_dispatch_r(Plan &P, int nrhs, int64_t fg_stride, int g0)
-{
-    if (P.syn_R == 1) syn_launch<T, 1, V, 0>(P, nrhs, fg_stride, g0, P.ng64);
-    else if (P.syn_R == 2) syn_launch<T, 2, V, 0>(P, nrhs, fg_stride, g0, P.ng64);
-    else syn_launch<T, 4, V, 0>(P, nrhs, fg_stride, g0, P.ng64);
-}
-
-template <typename T>
-static void syn_dispatch(Plan &P, int nrhs, int64_t fg_stride, int g0)
-{
-    if (P.syn_V == 0) syn_dispatch_r<T, 0>(P, nrhs, fg_stride, g0);
-    else syn_dispatch_r<T, 1>(P, nrhs, fg_stride, g0);
-}
-
-// the polar groups [0, wpol) in the difference form and the others [wpol, nw) in the plain form, SW
-// groups per workgroup
+// the near-polar groups list[0 .. npol) in the difference form and list[npol .. npol + nmain) in the
+// plain form, SW groups per workgroup
 template <int SW>
-static void synth_b_launch(Plan &P, int q, int64_t fg_stride, int64_t lblocks, int wpol, int nw)
+static void synth_b_launch(Plan &P, int q, int64_t fg_stride, int64_t lblocks, const int *list, int npol, int nmain)
 {
-    if (wpol > 0) {
-        const int nbm = (int)cdiv(wpol, SW);
+    if (npol > 0) {
+        const int nbm = (int)cdiv(npol, SW);
         k_leg_synth_b<1, SW><<<(unsigned)(8 * nbm * lblocks), 64 * SW, 0, P.stream>>>(
             P.d_brec, P.d_coef32d, (float2 *)P.d_FG, fg_stride, P.d_ent, P.d_entk, P.d_entl, P.ng64, P.d_pair_z,
-            P.lmax, P.npairs, P.nrings, P.nrhs, q, 0, wpol, nbm);
+            P.lmax, P.npairs, P.nrings, P.nrhs, q, list, npol, nbm);
     }
-    if (nw > wpol) {
-        const int nbm = (int)cdiv(nw - wpol, SW);
+    if (nmain > 0) {
+        const int nbm = (int)cdiv(nmain, SW);
         k_leg_synth_b<0, SW><<<(unsigned)(8 * nbm * lblocks), 64 * SW, 0, P.stream>>>(
             P.d_brec, P.d_coef32, (float2 *)P.d_FG, fg_stride, P.d_ent, P.d_entk, P.d_entl, P.ng64, P.d_pair_z,
-            P.lmax, P.npairs, P.nrings, P.nrhs, q, wpol, nw, nbm);
+            P.lmax, P.npairs, P.nrings, P.nrhs, q, list + npol, nmain, nbm);
     }
 }
 
-// ring blocks of AW groups: the polar groups first (difference form), then the others
+// ring blocks of AW groups: the near-polar groups first (difference form), then the others
 template <int AW>
-static void adj_b_launch(Plan &P, int q, int64_t fg_stride, int64_t lblocks)
+static void adj_b_launch(Plan &P, int q, int64_t fg_stride, int64_t lblocks, const int *list, int npol, int nmain,
+                         const uint8_t *live, int nrb)
 {
-    const int npol = (int)cdiv(P.polar_groups, AW), nmain = (int)cdiv(P.ng64 - P.polar_groups, AW);
-    if (npol > 0)
-        k_leg_adj_b<1, AW><<<(unsigned)(8 * npol * lblocks), 64 * AW, 0, P.stream>>>(
+    const int nbp = (int)cdiv(npol, AW), nbn = (int)cdiv(nmain, AW);
+    if (nbp > 0)
+        k_leg_adj_b<1, AW><<<(unsigned)(8 * nbp * lblocks), 64 * AW, 0, P.stream>>>(
             (const float2 *)P.d_FG, fg_stride, P.d_coef32d, P.d_ent, P.d_entk, P.d_entl, P.ng64, P.d_pair_z,
-            (float *)P.d_part, P.d_wgstart_b, P.nalm, P.lmax, P.npairs, P.nrings, P.nrhs, q, 0, P.polar_groups, 0,
-            npol, P.nrb_b);
-    if (nmain > 0)
-        k_leg_adj_b<0, AW><<<(unsigned)(8 * nmain * lblocks), 64 * AW, 0, P.stream>>>(
+            (float *)P.d_part, P.d_wgstart_b, P.nalm, P.lmax, P.npairs, P.nrings, P.nrhs, q, list, npol, live, 0, nbp,
+            nrb);
+    if (nbn > 0)
+        k_leg_adj_b<0, AW><<<(unsigned)(8 * nbn * lblocks), 64 * AW, 0, P.stream>>>(
             (const float2 *)P.d_FG, fg_stride, P.d_coef32, P.d_ent, P.d_entk, P.d_entl, P.ng64, P.d_pair_z,
-            (float *)P.d_part, P.d_wgstart_b, P.nalm, P.lmax, P.npairs, P.nrings, P.nrhs, q, P.polar_groups, P.ng64,
-            npol, nmain, P.nrb_b);
+            (float *)P.d_part, P.d_wgstart_b, P.nalm, P.lmax, P.npairs, P.nrings, P.nrhs, q, list + npol, nmain, live,
+            nbp, nbn, nrb);
 }
 
-// batched synthesis of FP32 plans: records and matrix-core sums per group of NBR right-hand sides
-void launch_synth_batched(Plan &P, const double *xE, const double *xB, int64_t rstride, const double *kern)
+// batched synthesis of FP32 plans: records and matrix-core sums per group of NBR right-hand sides, over
+// every 64-pair group (live false) or those with a ring that carries weight (live true)
+void launch_synth_batched(Plan &P, const double *xE, const double *xB, int64_t rstride, const double *kern, bool live)
 {
     const int64_t fg_stride = (int64_t)P.nrings * (P.lmax + 1) * 2;
-    const int nw = P.ng64, wpol = P.polar_groups;  // 64-pair groups
-    const int64_t lblocks = cdiv(P.lmax + 1, 8);
+    const GroupSet &G = live && P.skip_rings ? P.gs_live : P.gs_all;
+    const int64_t lblocks = xcd_slots(P.lmax);
     for (int q = 0; q * NBR < P.nrhs; ++q) {
         k_prologue_b<<<(unsigned)cdiv(P.nalm * NBR, 256), 256, 0, P.stream>>>(xE, xB, rstride, kern, P.d_lof, P.lmax,
                                                                              P.nalm, P.nrhs, q, P.d_brec);
         switch (P.bat_SW) {
-        case 1: synth_b_launch<1>(P, q, fg_stride, lblocks, wpol, nw); break;
-        case 2: synth_b_launch<2>(P, q, fg_stride, lblocks, wpol, nw); break;
-        case 8: synth_b_launch<8>(P, q, fg_stride, lblocks, wpol, nw); break;
-        default: synth_b_launch<4>(P, q, fg_stride, lblocks, wpol, nw);
+        case 1: synth_b_launch<1>(P, q, fg_stride, lblocks, G.list_any, G.npol_any, G.nmain_any); break;
+        case 2: synth_b_launch<2>(P, q, fg_stride, lblocks, G.list_any, G.npol_any, G.nmain_any); break;
+        case 8: synth_b_launch<8>(P, q, fg_stride, lblocks, G.list_any, G.npol_any, G.nmain_any); break;
+        default: synth_b_launch<4>(P, q, fg_stride, lblocks, G.list_any, G.npol_any, G.nmain_any);
         }
     }
 }
 
-// batched adjoint of the right-hand-side group q into the [rhs - NBR q][nrb_b][nalm][4] slabs of d_part
-void launch_adj_batched(Plan &P, int q)
+// batched adjoint of the right-hand-side group q into the [rhs - NBR q][nrb_cur_b][nalm][4] slabs of
+// d_part, over every 64-pair group (live false) or those with a ring that carries weight, reading
+// only such rings (live true)
+void launch_adj_batched(Plan &P, int q, bool live)
 {
+    live = live && P.skip_rings;
     const int64_t fg_stride = (int64_t)P.nrings * (P.lmax + 1) * 2;
-    const int64_t lblocks = cdiv(P.lmax + 1, 8);
+    const GroupSet &G = live ? P.gs_live : P.gs_all;
+    const uint8_t *lv = live ? P.d_ring_live : nullptr;
+    const int64_t lblocks = xcd_slots(P.lmax);
+    const int nrb = (int)(cdiv(G.npol_any, P.bat_AW) + cdiv(G.nmain_any, P.bat_AW));
     switch (P.bat_AW) {
-    case 2: adj_b_launch<2>(P, q, fg_stride, lblocks); break;
-    case 8: adj_b_launch<8>(P, q, fg_stride, lblocks); break;
-    default: adj_b_launch<4>(P, q, fg_stride, lblocks);
+    case 2: adj_b_launch<2>(P, q, fg_stride, lblocks, G.list_any, G.npol_any, G.nmain_any, lv, nrb); break;
+    case 8: adj_b_launch<8>(P, q, fg_stride, lblocks, G.list_any, G.npol_any, G.nmain_any, lv, nrb); break;
+    default: adj_b_launch<4>(P, q, fg_stride, lblocks, G.list_any, G.npol_any, G.nmain_any, lv, nrb);
     }
+    P.nrb_b_cur = nrb;
 }
 
 void launch_epilogue_batched(Plan &P, int rhs, const double *kern, double lam, const double *xE, const double *xB,
                              double *outE, double *outB, double *dot_red)
 {
-    const float *part = (const float *)P.d_part + (int64_t)(rhs % NBR) * P.nrb_b * P.nalm * 4;
+    const float *part = (const float *)P.d_part + (int64_t)(rhs % NBR) * P.nrb_b_cur * P.nalm * 4;
     const unsigned g = dot_red ? (unsigned)cg_red_blocks(P) : (unsigned)cdiv(P.nalm, 256);
-    k_epilogue<float><<<g, 256, 0, P.stream>>>(part, P.d_wgstart_b, P.nrb_b, P.nalm, P.d_lof, P.lmax, kern, lam, xE,
+    k_epilogue<float><<<g, 256, 0, P.stream>>>(part, P.d_wgstart_b, P.nrb_b_cur, P.nalm, P.d_lof, P.lmax, kern, lam, xE,
                                               xB, outE, outB, P.proj, dot_red);
 }
 
@@ -2753,50 +1903,17 @@ void launch_entry(Plan &P)
         gpb, P.prec == AKRA_FP32 ? 0x1p-44 : 0x1p-100);
 }
 
-void launch_leg_synth(Plan &P, bool fp32, int nrhs)
+// Legendre synthesis of the prologue's records: every 64-pair group (live false), or the groups of
+// the current weights by class (live true)
+void launch_leg_synth(Plan &P, bool fp32, int nrhs, bool live)
 {
-    const int64_t fg_stride = (int64_t)P.nrings * (P.lmax + 1) * 2;
-    if (fp32) {
-        // near-polar ring groups in the difference form, the rest in the plain form
-        if (P.polar_groups) syn_launch<float, 1, 1, 1>(P, nrhs, fg_stride, 0, P.polar_groups);
-        syn_dispatch<float>(P, nrhs, fg_stride, P.polar_groups);
-    } else {
-        syn_dispatch<double>(P, nrhs, fg_stride, 0);
-    }
-}
-
-// adjoint workgroups over the 64-pair groups [g0, g1), ring blocks rb0 .. of the plan's adj_nrb
-template <typename T, int R, int W, int L, int F>
-static void adj_launch(Plan &P, int rhs, int g0, int g1, int rb0)
-{
-    const int nrbl = (int)cdiv(g1 - g0, W * R);
-    if (nrbl <= 0) return;
-    const int64_t fg_stride = (int64_t)P.nrings * (P.lmax + 1) * 2;
-    const void *coef = std::is_same<T, double>::value ? (const void *)P.d_coef64s
-                       : F                              ? (const void *)P.d_coef32d
-                                                        : (const void *)P.d_coef32s;
-    dim3 g((unsigned)(8 * nrbl * cdiv(P.lmax + 1, 8)));
-    k_leg_adj<T, R, W, L, F><<<g, 64 * W, 0, P.stream>>>(
-        (const cplx<T> *)P.d_FG + rhs * fg_stride, (const typename CoefT<T, F>::type *)coef, P.d_coef64s, P.d_ent,
-        P.d_entk,
-        P.d_entl, P.ng64, P.d_pair_z, (T *)P.d_part, P.d_wgstart, P.nalm, P.lmax, P.npairs, P.nrings, g0, g1, rb0,
-        nrbl, P.adj_nrb);
-}
-
-// supported adjoint shapes (ring pairs per lane, waves per workgroup, l-chunk)
-#define AKRA_ADJ_SHAPES(X) \
-    X(1, 1, 8) X(1, 2, 8) X(1, 4, 8) X(2, 2, 8) X(2, 4, 8) X(4, 2, 8) X(4, 4, 8) X(8, 1, 8) X(8, 2, 8) \
-    X(2, 4, 4) X(4, 2, 4) X(4, 4, 4) X(8, 1, 4) X(2, 1, 8) X(4, 1, 4) X(4, 1, 8)
-
-template <typename T>
-static void adj_dispatch(Plan &P, int rhs, int g0, int rb0)
-{
-    const int R = P.adj_R, W = P.adj_W, L = P.adj_L;
-#define AKRA_ADJ_CASE(r, w, l) \
-    if (R == r && W == w && L == l) return adj_launch<T, r, w, l, 0>(P, rhs, g0, P.ng64, rb0);
-    AKRA_ADJ_SHAPES(AKRA_ADJ_CASE)
-#undef AKRA_ADJ_CASE
-    adj_launch<T, 4, 4, 8, 0>(P, rhs, g0, P.ng64, rb0);
+    const GroupSet &G = live && P.skip_rings ? P.gs_live : P.gs_all;
+    if (G.npol[GCLS_BOTH] + G.nmain[GCLS_BOTH])
+        leg_synth_cls<GCLS_BOTH>(P, fp32, nrhs, G.list[GCLS_BOTH], G.npol[GCLS_BOTH], G.nmain[GCLS_BOTH]);
+    if (G.npol[GCLS_NORTH] + G.nmain[GCLS_NORTH])
+        leg_synth_cls<GCLS_NORTH>(P, fp32, nrhs, G.list[GCLS_NORTH], G.npol[GCLS_NORTH], G.nmain[GCLS_NORTH]);
+    if (G.npol[GCLS_SOUTH] + G.nmain[GCLS_SOUTH])
+        leg_synth_cls<GCLS_SOUTH>(P, fp32, nrhs, G.list[GCLS_SOUTH], G.npol[GCLS_SOUTH], G.nmain[GCLS_SOUTH]);
 }
 
 bool adj_shape_supported(int r, int w, int l)
@@ -2808,18 +1925,35 @@ bool adj_shape_supported(int r, int w, int l)
     return false;
 }
 
-void launch_leg_adj(Plan &P, bool fp32, int rhs)
+int adj_blocks_total(const Plan &P, bool live)
 {
-    if (fp32) {
-        // near-polar ring groups in the difference form (four groups per workgroup), the rest plain
-        if (P.polar_groups) adj_launch<float, 4, 1, 4, 1>(P, rhs, 0, P.polar_groups, 0);
-        adj_dispatch<float>(P, rhs, P.polar_groups, P.adj_nrb_polar);
-    } else {
-        // the same ring-block layout as the plan's FP32 applies (the epilogue sums adj_nrb slabs):
-        // in FP32 plans the near-polar groups form their own blocks here too
-        if (P.polar_groups) adj_launch<double, 4, 1, 4, 0>(P, rhs, 0, P.polar_groups, 0);
-        adj_dispatch<double>(P, rhs, P.polar_groups, P.adj_nrb_polar);
-    }
+    const GroupSet &G = live && P.skip_rings ? P.gs_live : P.gs_all;
+    int n = 0;
+    for (int c = 0; c < GCLS_N; ++c) n += adj_blocks(P, c, G.npol[c], G.nmain[c]);
+    return n;
+}
+
+// Legendre adjoint of d_FG (right-hand side rhs) into the partial sums, over every 64-pair group
+// (live false) or the groups of the current weights by class, reading only rings that carry weight
+// (live true).  The near-polar groups of FP32 plans form their own blocks of four in FP32 and in
+// FP64 applies alike; the epilogue sums the nrb_cur blocks written.
+void launch_leg_adj(Plan &P, bool fp32, int rhs, bool live)
+{
+    live = live && P.skip_rings;
+    const GroupSet &G = live ? P.gs_live : P.gs_all;
+    const uint8_t *lv = live ? P.d_ring_live : nullptr;
+    const int nrb = adj_blocks_total(P, live);
+    int rb = 0;
+    if (G.npol[GCLS_BOTH] + G.nmain[GCLS_BOTH])
+        rb += leg_adj_cls<GCLS_BOTH>(P, fp32, rhs, G.list[GCLS_BOTH], G.npol[GCLS_BOTH], G.nmain[GCLS_BOTH], lv, rb,
+                                     nrb);
+    if (G.npol[GCLS_NORTH] + G.nmain[GCLS_NORTH])
+        rb += leg_adj_cls<GCLS_NORTH>(P, fp32, rhs, G.list[GCLS_NORTH], G.npol[GCLS_NORTH], G.nmain[GCLS_NORTH], lv,
+                                      rb, nrb);
+    if (G.npol[GCLS_SOUTH] + G.nmain[GCLS_SOUTH])
+        rb += leg_adj_cls<GCLS_SOUTH>(P, fp32, rhs, G.list[GCLS_SOUTH], G.npol[GCLS_SOUTH], G.nmain[GCLS_SOUTH], lv,
+                                      rb, nrb);
+    P.nrb_cur = nrb;
 }
 
 int cg_red_blocks(const Plan &P) { return (int)std::min<int64_t>(CG_RED_BLOCKS, cdiv(P.nalm, 256)); }
@@ -2829,10 +1963,10 @@ void launch_epilogue(Plan &P, bool fp32, const double *kern, double lam, const d
 {
     const dim3 g(dot_red ? (unsigned)cg_red_blocks(P) : (unsigned)cdiv(P.nalm, 256));
     if (fp32)
-        k_epilogue<float><<<g, 256, 0, P.stream>>>((const float *)P.d_part, P.d_wgstart, P.adj_nrb, P.nalm, P.d_lof,
+        k_epilogue<float><<<g, 256, 0, P.stream>>>((const float *)P.d_part, P.d_wgstart, P.nrb_cur, P.nalm, P.d_lof,
                                                    P.lmax, kern, lam, xE, xB, outE, outB, P.proj, dot_red);
     else
-        k_epilogue<double><<<g, 256, 0, P.stream>>>((const double *)P.d_part, P.d_wgstart, P.adj_nrb, P.nalm,
+        k_epilogue<double><<<g, 256, 0, P.stream>>>((const double *)P.d_part, P.d_wgstart, P.nrb_cur, P.nalm,
                                                     P.d_lof, P.lmax, kern, lam, xE, xB, outE, outB, P.proj, dot_red);
 }
 
@@ -2869,46 +2003,48 @@ void launch_cg_beta_sum(Plan &P, const double *red, double *scal, double precond
     k_cg_beta_sum<<<1, 256, 0, P.stream>>>(red, cg_red_blocks(P), scal, precond);
 }
 
+// The ring kinds of a RingSet: RK_P2 whole power-of-two rings (LDS FFT), RK_BF whole-ring Bluestein,
+// RK_BL rings split into two half-length Bluestein transforms, RK_REG + q the register engine's
+// lists (see Plan::d_order_r)
 template <typename T, int MODE>
-static void ring_launch_t(Plan &P, const double *g1, const double *g2, double *o1, double *o2, const double *W,
-                          double *o3, const uint8_t *mask, const double *cdev,
-                          int nrhs)
+static void ring_launch_t(Plan &P, const RingSet &RS, const double *g1, const double *g2, double *o1, double *o2,
+                          const double *W, double *o3, const uint8_t *mask, const double *cdev, int nrhs)
 {
     const int64_t fg_stride = (int64_t)P.nrings * (P.lmax + 1) * 2;
     const void *tw = std::is_same<T, double>::value ? P.d_tw64 : P.d_tw32;
     const cplx<T> *bh = (const cplx<T> *)(std::is_same<T, double>::value ? P.d_bhat64 : P.d_bhat32);
-    if (P.n_p2) {
+    if (RS.n[RK_P2]) {
         // whole rings: N = 4 sub <= 4 nside <= 8192 = RF RFU (nside <= 2048 is enforced at plan creation)
         const size_t nmax = std::max((size_t)RF, 4 * (size_t)P.maxM_p2);  // RF: the short-ring fold
         size_t sm = sizeof(cplx<T>) * (nmax + nmax / 32);
-        k_ring_full<T, MODE><<<dim3(P.n_p2, nrhs), RF, sm, P.stream>>>(
-            (cplx<T> *)P.d_FG, fg_stride, g1, g2, o1, o2, P.npix, W, P.d_rings, P.d_order_p2, (const cplx<T> *)tw,
+        k_ring_full<T, MODE><<<dim3(RS.n[RK_P2], nrhs), RF, sm, P.stream>>>(
+            (cplx<T> *)P.d_FG, fg_stride, g1, g2, o1, o2, P.npix, W, P.d_rings, RS.order[RK_P2], (const cplx<T> *)tw,
             P.twn, P.lmax, P.omega, o3, mask, cdev);
     }
-    if (P.n_bf) {
+    if (RS.n[RK_BF]) {
         const size_t nmax = std::max((size_t)RF, (size_t)P.maxM_bf);  // RF: the short-ring fold
         size_t sm = sizeof(cplx<T>) * (nmax + nmax / 32);
-        k_ring_bfull<T, MODE><<<dim3(P.n_bf, nrhs), RF, sm, P.stream>>>(
-            (cplx<T> *)P.d_FG, fg_stride, g1, g2, o1, o2, P.npix, W, P.d_rings, P.d_order_bf, (const cplx<T> *)tw,
+        k_ring_bfull<T, MODE><<<dim3(RS.n[RK_BF], nrhs), RF, sm, P.stream>>>(
+            (cplx<T> *)P.d_FG, fg_stride, g1, g2, o1, o2, P.npix, W, P.d_rings, RS.order[RK_BF], (const cplx<T> *)tw,
             P.twn, P.lmax, P.omega, o3, mask, cdev, bh);
     }
-    if (P.n_bl) {
+    if (RS.n[RK_BL]) {
         size_t sm = sizeof(cplx<T>) * (size_t)(P.maxM_bl + P.maxM_bl / 32);
-        k_ring_b2<T, MODE><<<dim3(P.n_bl, nrhs), RF, sm, P.stream>>>(
-            (cplx<T> *)P.d_FG, fg_stride, g1, g2, o1, o2, P.npix, W, P.d_rings, P.d_order_bl, (const cplx<T> *)tw,
+        k_ring_b2<T, MODE><<<dim3(RS.n[RK_BL], nrhs), RF, sm, P.stream>>>(
+            (cplx<T> *)P.d_FG, fg_stride, g1, g2, o1, o2, P.npix, W, P.d_rings, RS.order[RK_BL], (const cplx<T> *)tw,
             P.twn, P.lmax, P.omega, o3, mask, cdev, bh);
     }
     // register engine: LDS of M + M / 32 components (FP64, one component at a time) or complex values (FP32)
     const cplx<T> *bhr = (const cplx<T> *)(std::is_same<T, double>::value ? P.d_bhatr64 : P.d_bhatr32);
     auto reg = [&](auto kern, int q, int M) {
-        if (!P.n_r[q]) return;
+        if (!RS.n[RK_REG + q]) return;
         const bool split_ring = q >= 4;  // KIND 2: one-component exchanges and a half-ring stash
         const size_t sm = ((std::is_same<T, double>::value || split_ring) ? sizeof(T) : sizeof(cplx<T>)) *
                               (size_t)(M + M / 32) +
                           (split_ring ? sizeof(cplx<T>) * (size_t)(M / 2) : 0);
-        kern<<<dim3(P.n_r[q], nrhs), M / 16, sm, P.stream>>>(
-            (cplx<T> *)P.d_FG, fg_stride, g1, g2, o1, o2, P.npix, W, P.d_rings, P.d_order_r[q], (const cplx<T> *)tw,
-            P.twn, P.lmax, P.omega, o3, mask, cdev, bhr);
+        kern<<<dim3(RS.n[RK_REG + q], nrhs), M / 16, sm, P.stream>>>(
+            (cplx<T> *)P.d_FG, fg_stride, g1, g2, o1, o2, P.npix, W, P.d_rings, RS.order[RK_REG + q],
+            (const cplx<T> *)tw, P.twn, P.lmax, P.omega, o3, mask, cdev, bhr);
     };
     reg(k_ring16<T, MODE, 13, 2>, 5, 8192);
     reg(k_ring16<T, MODE, 13, 0>, 1, 8192);
@@ -2967,24 +2103,26 @@ void launch_bhat(Plan &P, const int *Ls, const int *Ms, const int64_t *ofs, int 
                                                                               (float2 *)P.d_bhat32);
 }
 
+// every ring (live false), or the rings that carry weight in the current weights (live true)
 void launch_ring(Plan &P, bool fp32, int mode, const double *g1, const double *g2, double *o1, double *o2,
-                 const double *W, int nrhs)
+                 const double *W, int nrhs, bool live)
 {
+    const RingSet &RS = live && P.skip_rings ? P.rs_live : P.rs_all;
     if (fp32) {
-        if (mode == 0) ring_launch_t<float, 0>(P, g1, g2, o1, o2, W, nullptr, nullptr, nullptr, nrhs);
-        else if (mode == 1) ring_launch_t<float, 1>(P, g1, g2, o1, o2, W, nullptr, nullptr, nullptr, nrhs);
-        else ring_launch_t<float, 2>(P, g1, g2, o1, o2, W, nullptr, nullptr, nullptr, nrhs);
+        if (mode == 0) ring_launch_t<float, 0>(P, RS, g1, g2, o1, o2, W, nullptr, nullptr, nullptr, nrhs);
+        else if (mode == 1) ring_launch_t<float, 1>(P, RS, g1, g2, o1, o2, W, nullptr, nullptr, nullptr, nrhs);
+        else ring_launch_t<float, 2>(P, RS, g1, g2, o1, o2, W, nullptr, nullptr, nullptr, nrhs);
     } else {
-        if (mode == 0) ring_launch_t<double, 0>(P, g1, g2, o1, o2, W, nullptr, nullptr, nullptr, nrhs);
-        else if (mode == 1) ring_launch_t<double, 1>(P, g1, g2, o1, o2, W, nullptr, nullptr, nullptr, nrhs);
-        else ring_launch_t<double, 2>(P, g1, g2, o1, o2, W, nullptr, nullptr, nullptr, nrhs);
+        if (mode == 0) ring_launch_t<double, 0>(P, RS, g1, g2, o1, o2, W, nullptr, nullptr, nullptr, nrhs);
+        else if (mode == 1) ring_launch_t<double, 1>(P, RS, g1, g2, o1, o2, W, nullptr, nullptr, nullptr, nrhs);
+        else ring_launch_t<double, 2>(P, RS, g1, g2, o1, o2, W, nullptr, nullptr, nullptr, nrhs);
     }
 }
 
 void launch_ring_grad(Plan &P, const double *g1, const double *g2, double *q1, double *q2, const double *W,
                       double *dninv, const uint8_t *mask, const double *cdev)
 {
-    ring_launch_t<double, 3>(P, g1, g2, q1, q2, W, dninv, mask, cdev, 1);
+    ring_launch_t<double, 3>(P, P.rs_all, g1, g2, q1, q2, W, dninv, mask, cdev, 1);
 }
 
 // right-hand side of the backward solve: the upstream gradient on the stored (Re, Im) of the alm,
@@ -3012,6 +2150,23 @@ __global__ void k_scale_scalar(double *out, const double *in, double f) { *out =
 void launch_scale_scalar(Plan &P, double *out, const double *in, double f)
 {
     k_scale_scalar<<<1, 1, 0, P.stream>>>(out, in, f);
+}
+
+// one workgroup per ring: 1 when any of the nrhs weight maps has a nonzero weight on the ring
+__global__ __launch_bounds__(256) void k_ring_live(const double *__restrict__ W, const RingInfo *__restrict__ rings,
+                                                   int64_t npix, int nrhs, uint8_t *__restrict__ live)
+{
+    const RingInfo ri = rings[blockIdx.x];
+    int any = 0;
+    for (int r = 0; r < nrhs; ++r)
+        for (int j = threadIdx.x; j < ri.nphi; j += blockDim.x) any |= W[r * npix + ri.ofs + j] != 0.0;
+    any = __syncthreads_or(any);
+    if (threadIdx.x == 0) live[blockIdx.x] = any ? 1 : 0;
+}
+
+void launch_ring_live(Plan &P, int nrhs)
+{
+    k_ring_live<<<P.nrings, 256, 0, P.stream>>>(P.d_W, P.d_rings, P.npix, nrhs, P.d_ring_live);
 }
 
 void launch_weights(Plan &P, const double *ninv, const uint8_t *mask, int nrhs, int ncount)

@@ -244,6 +244,105 @@ static void default_kernel(int lmax, std::vector<double> &k)
     for (int l = 2; l <= lmax; ++l) k[l] = std::sqrt((double)(l - 1) * (l + 2) / ((double)l * (l + 1)));
 }
 
+// ---- rings and groups that carry weight -------------------------------------------------------
+// ints of the device list buffer: the ring lists of every kind, then GCLS_N + 1 group lists
+static size_t live_list_ints(const Plan &P) { return (size_t)RING_KINDS * P.nrings + (GCLS_N + 1) * (size_t)P.ng64; }
+// pinned bytes: the ring flags (padded to 16), then the staged lists
+static size_t live_stage_bytes(const Plan &P) { return (size_t)(P.nrings + 15) / 16 * 16 + 4 * live_list_ints(P); }
+
+// Evaluated (l, m, pair) triples of the Legendre kernels over the weighted group lists: a synthesis
+// wave of syn_R list entries (one for near-polar groups) and an adjoint workgroup of adj_R adj_W
+// entries (four near-polar) start at the earliest entry degree among their groups; every pair of
+// their groups steps to lmax.  Split into two-ring and one-ring classes; the last count is that of
+// the batched kernels (every weighted group from its own entry degree).
+static void compute_work_live(Plan &P)
+{
+    const GroupSet &G = P.gs_live;
+    const int lmax = P.lmax, ng = P.ng64, np = P.npairs;
+    std::vector<int> hl[GCLS_N];
+    const int *base = (const int *)(P.h_live + (P.nrings + 15) / 16 * 16) + (size_t)RING_KINDS * P.nrings;
+    for (int c = 0; c < GCLS_N; ++c) hl[c].assign(base + (size_t)c * ng, base + (size_t)c * ng + G.npol[c] + G.nmain[c]);
+    auto seg = [&](const int *e, const int *gl, int n, int gs) {
+        int64_t w = 0;
+        for (int b = 0; b < n; b += gs) {
+            int ls = ENT_SKIP;
+            int64_t pairs = 0;
+            for (int i = b; i < std::min(n, b + gs); ++i) {
+                ls = std::min(ls, e[gl[i]]);
+                pairs += std::min(64, np - 64 * gl[i]);
+            }
+            if (ls <= lmax) w += pairs * (lmax - ls + 1);
+        }
+        return w;
+    };
+    const int *any = base + (size_t)GCLS_N * ng;
+    const int nany = G.npol_any + G.nmain_any;
+    int64_t w[5] = {0, 0, 0, 0, 0};
+    for (int m = 0; m <= lmax; ++m) {
+        const int *e = P.h_entl.data() + (size_t)m * ng;
+        w[4] += seg(e, any, nany, 1);
+        for (int c = 0; c < GCLS_N; ++c) {
+            const int *gl = hl[c].data();
+            const int npol = G.npol[c], nmain = G.nmain[c];
+            const bool two = c == GCLS_BOTH;
+            const int64_t s = seg(e, gl, npol, 1) + seg(e, gl + npol, nmain, two ? P.syn_R : P.syn_R1);
+            const int64_t a = seg(e, gl, npol, 4) + seg(e, gl + npol, nmain, two ? P.adj_R * P.adj_W : P.adj_R1 * P.adj_W1);
+            w[c == GCLS_BOTH ? 0 : 1] += s;
+            w[c == GCLS_BOTH ? 2 : 3] += a;
+        }
+    }
+    for (int i = 0; i < 5; ++i) P.work_live[i] = w[i];
+}
+
+// From the ring flags in h_live: the ring lists of every kind and the group lists of every class,
+// staged after the flags and uploaded to d_live_lists (stream-ordered before the next launches);
+// rs_live and gs_live then describe them.
+static akra_status build_live_lists(Plan &P)
+{
+    const uint8_t *flag = P.h_live;
+    int *stage = (int *)(P.h_live + (P.nrings + 15) / 16 * 16);
+    for (int k = 0; k < RING_KINDS; ++k) {
+        int *o = stage + (size_t)k * P.nrings;
+        int n = 0;
+        for (int r : P.h_order[k])
+            if (flag[r]) o[n++] = r;
+        P.rs_live.order[k] = P.d_live_lists + (size_t)k * P.nrings;
+        P.rs_live.n[k] = n;
+    }
+    int *gbase = stage + (size_t)RING_KINDS * P.nrings;
+    int cnt[GCLS_N + 1] = {0, 0, 0, 0}, pol[GCLS_N + 1] = {0, 0, 0, 0};
+    for (int g = 0; g < P.ng64; ++g) {
+        bool n = false, s = false;
+        for (int p = 64 * g; p < std::min(P.npairs, 64 * g + 64); ++p) {
+            const int rs = P.nrings - 1 - p;
+            n = n || flag[p];
+            s = s || (rs != p && flag[rs]);
+        }
+        if (!n && !s) continue;
+        const int c = (n && s) ? GCLS_BOTH : n ? GCLS_NORTH : GCLS_SOUTH;
+        for (int cc : {c, (int)GCLS_N}) {
+            gbase[(size_t)cc * P.ng64 + cnt[cc]++] = g;
+            if (g < P.polar_groups) pol[cc]++;
+        }
+    }
+    GroupSet &G = P.gs_live;
+    for (int c = 0; c < GCLS_N; ++c) {
+        G.list[c] = P.d_live_lists + (size_t)RING_KINDS * P.nrings + (size_t)c * P.ng64;
+        G.npol[c] = pol[c];
+        G.nmain[c] = cnt[c] - pol[c];
+    }
+    G.list_any = P.d_live_lists + (size_t)RING_KINDS * P.nrings + (size_t)GCLS_N * P.ng64;
+    G.npol_any = pol[GCLS_N];
+    G.nmain_any = cnt[GCLS_N] - pol[GCLS_N];
+    AK_HIP(hipMemcpyAsync(P.d_live_lists, stage, live_list_ints(P) * sizeof(int), hipMemcpyHostToDevice, P.stream),
+           "hipMemcpyAsync");
+    P.live_gen++;
+    P.n_live_rings = 0;
+    for (int r = 0; r < P.nrings; ++r) P.n_live_rings += flag[r] != 0;
+    compute_work_live(P);
+    return AKRA_OK;
+}
+
 static void free_plan(Plan *P)
 {
     void *ptrs[] = {P->d_rings, P->d_pair_z, P->d_coef64, P->d_coef32, P->d_coef64s, P->d_coef32s, P->d_recu,
@@ -251,10 +350,12 @@ static void free_plan(Plan *P)
                     P->d_ent, P->d_entk, P->d_entl, P->d_wgstart, P->d_wgstart_b, P->d_coef32d, P->d_brec,
                     P->d_tw64, P->d_tw32, P->d_bhat64, P->d_bhat32, P->d_bhatr64, P->d_bhatr32, P->d_order_r[0], P->d_order_r[1],
                     P->d_order_r[2], P->d_order_r[3], P->d_order_r[4], P->d_order_r[5], P->d_lof, P->d_order_p2, P->d_order_bl, P->d_order_bf, P->d_FG, P->d_part, P->d_rec, P->d_W, P->d_kern, P->d_kuser, P->d_red, P->d_red_cg, P->d_scal, P->d_flag, P->d_x, P->d_r,
-                    P->d_p, P->d_w, P->d_b, P->d_xs, P->d_cmp, P->d_spec};
+                    P->d_p, P->d_w, P->d_b, P->d_xs, P->d_cmp, P->d_spec, P->d_gl_all, P->d_live_lists,
+                    P->d_ring_live};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     if (P->h_pin) (void)hipHostFree(P->h_pin);
+    if (P->h_live) (void)hipHostFree(P->h_live);
     for (auto &e : P->ev_pool) {
         (void)hipEventDestroy(e[0]);
         (void)hipEventDestroy(e[1]);
@@ -343,6 +444,10 @@ static akra_status create(int nside, int lmax, int nrhs, int prec, void *stream,
     std::stable_sort(bf.begin(), bf.end(), bysize);
     for (auto &v : rl) std::stable_sort(v.begin(), v.end(), bysize);
     for (int q = 0; q < 6; ++q) P->n_r[q] = (int)rl[q].size();
+    P->h_order[RK_P2] = p2;
+    P->h_order[RK_BF] = bf;
+    P->h_order[RK_BL] = bl;
+    for (int q = 0; q < 6; ++q) P->h_order[RK_REG + q] = rl[q];
     P->n_p2 = (int)p2.size();
     P->n_bl = (int)bl.size();
     P->n_bf = (int)bf.size();
@@ -417,6 +522,11 @@ static akra_status create(int nside, int lmax, int nrhs, int prec, void *stream,
     P->adj_R = caps[ci][0];
     P->adj_W = caps[ci][1];
     P->adj_nrb = P->adj_nrb_polar + (P->ng64 - P->polar_groups + P->adj_R * P->adj_W - 1) / (P->adj_R * P->adj_W);
+    P->syn_V1 = P->syn_V;
+    P->syn_R1 = P->syn_R;
+    P->adj_R1 = P->adj_R;
+    P->adj_W1 = P->adj_W;
+    P->adj_L1 = P->adj_L;
 
     akra_status st;
 #define AK_TRY(x)                \
@@ -460,6 +570,30 @@ static akra_status create(int nside, int lmax, int nrhs, int prec, void *stream,
         AK_TRY(upload((void **)&P->d_order_bf, bf.data(), bf.size() * sizeof(int), *P));
         for (int q = 0; q < 6; ++q)
             if (!rl[q].empty()) AK_TRY(upload((void **)&P->d_order_r[q], rl[q].data(), rl[q].size() * sizeof(int), *P));
+        P->rs_all.order[RK_P2] = P->d_order_p2;
+        P->rs_all.order[RK_BF] = P->d_order_bf;
+        P->rs_all.order[RK_BL] = P->d_order_bl;
+        for (int q = 0; q < 6; ++q) P->rs_all.order[RK_REG + q] = P->d_order_r[q];
+        for (int k = 0; k < RING_KINDS; ++k) P->rs_all.n[k] = (int)P->h_order[k].size();
+        // every group in one list (the transforms without weights), polar groups first
+        std::vector<int> ids(P->ng64);
+        for (int g = 0; g < P->ng64; ++g) ids[g] = g;
+        AK_TRY(upload((void **)&P->d_gl_all, ids.data(), ids.size() * sizeof(int), *P));
+        GroupSet &A = P->gs_all;
+        A.list[GCLS_BOTH] = A.list_any = P->d_gl_all;
+        A.npol[GCLS_BOTH] = A.npol_any = P->polar_groups;
+        A.nmain[GCLS_BOTH] = A.nmain_any = P->ng64 - P->polar_groups;
+        // until a weight set-up, the weighted sets are the full ones
+        P->rs_live = P->rs_all;
+        P->gs_live = P->gs_all;
+        AK_TRY(alloc((void **)&P->d_live_lists, live_list_ints(*P) * sizeof(int), *P));
+        AK_TRY(alloc((void **)&P->d_ring_live, (size_t)P->nrings, *P));
+        if (hipHostMalloc((void **)&P->h_live, live_stage_bytes(*P)) != hipSuccess) {
+            P->h_live = nullptr;
+            free_plan(P);
+            set_error("hipHostMalloc failed");
+            return AKRA_ERR_ALLOC;
+        }
     }
     // entry states of the recurrence (the seeds are only needed to build them)
     {
@@ -555,7 +689,10 @@ static akra_status create(int nside, int lmax, int nrhs, int prec, void *stream,
     // workspaces
     const size_t fg = (size_t)nrhs * P->nrings * (lmax + 1) * 2 * sizeof(double2);
     AK_TRY(alloc(&P->d_FG, fg, *P));
-    P->part_rb_cap = (size_t)std::max(P->adj_nrb, P->adj_nrb_polar + (P->npairs <= 1024 ? P->ng64 : (P->ng64 + 3) / 4));
+    // the class lists of a weighted apply split the groups in up to three polar and three main parts,
+    // each rounded up to whole blocks: at most LIVE_NRB_EXTRA blocks more than the unsplit layout
+    P->part_rb_cap = (size_t)std::max(P->adj_nrb, P->adj_nrb_polar + (P->npairs <= 1024 ? P->ng64 : (P->ng64 + 3) / 4)) +
+                     LIVE_NRB_EXTRA;
     if (prec == AKRA_FP32 && nrhs > 1) {
         // batched adjoint: blocks of four groups (polar blocks apart), 8 right-hand sides of FP32 slabs
         // ring blocks of bat_AW groups (polar blocks apart); room for the smallest supported bat_AW, 2
@@ -567,6 +704,11 @@ static akra_status create(int nside, int lmax, int nrhs, int prec, void *stream,
     AK_TRY(alloc(&P->d_part, P->part_rb_cap * P->nalm * 4 * sizeof(double), *P));
     AK_TRY(alloc((void **)&P->d_wgstart, P->part_rb_cap * (lmax + 1) * sizeof(int), *P));
     compute_work(*P);
+    // before any weight set-up every ring counts, in two-ring groups
+    P->n_live_rings = P->nrings;
+    P->work_live[0] = P->work[1];
+    P->work_live[2] = P->work[2];
+    P->work_live[4] = P->work_b;
     P->rec_stride = P->nalm + ALM_PAD;
     AK_TRY(alloc(&P->d_rec, (size_t)nrhs * P->rec_stride * 64, *P));
     if (prec == AKRA_FP32 && P->polar_groups > 0) {
@@ -646,11 +788,16 @@ static akra_status setup_weights(Plan &P, const double *ninv, const uint8_t *mas
         return AKRA_ERR_ARG;
     }
     launch_weights(P, ninv, mask, P.nrhs, ncount > 0 ? ncount : P.nrhs);
+    launch_ring_live(P, P.nrhs);
     akra_status st = check_launch("weights");
     if (st) return st;
     AK_HIP(hipMemcpyAsync(P.h_pin, P.d_scal + 8, sizeof(double) * 4 * P.nrhs, hipMemcpyDeviceToHost, P.stream),
            "hipMemcpyAsync");
+    AK_HIP(hipMemcpyAsync(P.h_live, P.d_ring_live, (size_t)P.nrings, hipMemcpyDeviceToHost, P.stream),
+           "hipMemcpyAsync");
     AK_HIP(hipStreamSynchronize(P.stream), "hipStreamSynchronize");
+    st = build_live_lists(P);
+    if (st) return st;
     lam_eff.resize(P.nrhs);
     pc.resize(P.nrhs);
     if (msum) msum->resize(P.nrhs);
@@ -755,13 +902,13 @@ static akra_status apply_H_timed(Plan &P, bool fp32, const double *kern_dev, dou
     launch_prologue(P, fp32, xE, xB, kern_dev, 1);
     stage_mark(P, 0, false);
     stage_mark(P, 1, true);
-    launch_leg_synth(P, fp32, 1);
+    launch_leg_synth(P, fp32, 1, true);
     stage_mark(P, 1, false);
     stage_mark(P, 2, true);
-    launch_ring(P, fp32, 2, nullptr, nullptr, nullptr, nullptr, P.d_W + (int64_t)rhs * P.npix, 1);
+    launch_ring(P, fp32, 2, nullptr, nullptr, nullptr, nullptr, P.d_W + (int64_t)rhs * P.npix, 1, true);
     stage_mark(P, 2, false);
     stage_mark(P, 3, true);
-    launch_leg_adj(P, fp32, 0);
+    launch_leg_adj(P, fp32, 0, true);
     stage_mark(P, 3, false);
     stage_mark(P, 4, true);
     launch_epilogue(P, fp32, kern_dev, lam, xE, xB, yE, yB, dot_red);
@@ -779,14 +926,14 @@ static akra_status apply_H_batched(Plan &P, const double *kern_dev, const double
                                    double *dot_red = nullptr)
 {
     stage_mark(P, 1, true);
-    launch_synth_batched(P, xE, xB, rstride, kern_dev);
+    launch_synth_batched(P, xE, xB, rstride, kern_dev, true);
     stage_mark(P, 1, false);
     stage_mark(P, 2, true);
-    launch_ring(P, true, 2, nullptr, nullptr, nullptr, nullptr, P.d_W, P.nrhs);
+    launch_ring(P, true, 2, nullptr, nullptr, nullptr, nullptr, P.d_W, P.nrhs, true);
     stage_mark(P, 2, false);
     for (int q = 0; q * 8 < P.nrhs; ++q) {
         stage_mark(P, 3, true);
-        launch_adj_batched(P, q);
+        launch_adj_batched(P, q, true);
         stage_mark(P, 3, false);
         for (int r = 8 * q; r < P.nrhs && r < 8 * q + 8; ++r) {
             const int64_t o = (int64_t)r * 2 * rstride;
@@ -877,9 +1024,11 @@ static akra_status cg_iterate(Plan &P, bool fp32)
 // launch shapes.  A recorded iteration is valid while these are unchanged.
 static void iter_key(const Plan &P, bool fp32, double *k)
 {
-    const double v[12] = {(double)fp32, (double)P.cg_rhs, (double)P.proj, P.cg_lam, P.cg_pc,
-                          (double)(uintptr_t)P.cg_kern, (double)P.syn_V, (double)P.syn_R, (double)P.adj_R,
-                          (double)P.adj_W, (double)P.adj_L, (double)P.adj_nrb};
+    const double v[ITER_KEY_N] = {(double)fp32, (double)P.cg_rhs, (double)P.proj, P.cg_lam, P.cg_pc,
+                                  (double)(uintptr_t)P.cg_kern, (double)P.syn_V, (double)P.syn_R, (double)P.adj_R,
+                                  (double)P.adj_W, (double)P.adj_L, (double)P.adj_nrb, (double)P.live_gen,
+                                  (double)P.syn_V1, (double)P.syn_R1, (double)P.adj_R1, (double)P.adj_W1,
+                                  (double)P.adj_L1};
     std::memcpy(k, v, sizeof v);
 }
 
@@ -936,7 +1085,7 @@ static akra_status record_iteration(Plan &P, bool fp32)
 static akra_status cg_step1(Plan &P, bool fp32)
 {
     if (P.timing || !P.use_graph) return cg_iterate(P, fp32);
-    double k[12];
+    double k[ITER_KEY_N];
     iter_key(P, fp32, k);
     if (!P.cg_graph || std::memcmp(k, P.cg_graph_key, sizeof k) != 0) {
         akra_status st = record_iteration(P, fp32);
@@ -1146,12 +1295,12 @@ akra_status akra_synth2(akra_plan plan, const double *almE, const double *almB, 
     }
     const bool fp32 = plan_fp32(P);
     if (fp32 && P.nrhs > 1) {
-        launch_synth_batched(P, almE, almB, P.nalm, nullptr);
+        launch_synth_batched(P, almE, almB, P.nalm, nullptr, false);
     } else {
         launch_prologue(P, fp32, almE, almB, nullptr, P.nrhs);
-        launch_leg_synth(P, fp32, P.nrhs);
+        launch_leg_synth(P, fp32, P.nrhs, false);
     }
-    launch_ring(P, fp32, 0, nullptr, nullptr, g1, g2, nullptr, P.nrhs);
+    launch_ring(P, fp32, 0, nullptr, nullptr, g1, g2, nullptr, P.nrhs, false);
     return check_launch("synth2");
 }
 
@@ -1164,9 +1313,9 @@ akra_status akra_adjoint2(akra_plan plan, const double *g1, const double *g2, do
         return AKRA_ERR_ARG;
     }
     const bool fp32 = plan_fp32(P);
-    launch_ring(P, fp32, 1, g1, g2, nullptr, nullptr, nullptr, P.nrhs);
+    launch_ring(P, fp32, 1, g1, g2, nullptr, nullptr, nullptr, P.nrhs, false);
     for (int r = 0; r < P.nrhs; ++r) {
-        launch_leg_adj(P, fp32, r);
+        launch_leg_adj(P, fp32, r, false);
         launch_epilogue(P, fp32, nullptr, 0.0, nullptr, nullptr, almE + (int64_t)r * 2 * P.nalm,
                         almB + (int64_t)r * 2 * P.nalm);
     }
@@ -1204,9 +1353,9 @@ static akra_status rhs_core(Plan &P, const double *g1, const double *g2, const d
     // W gamma_obs, adjoint ring stage in the plan precision would lose FP64 accuracy of b for the
     // refined solve: the right-hand side is always formed in FP64.
     (void)fp32;
-    launch_ring(P, false, 1, g1, g2, nullptr, nullptr, P.d_W, P.nrhs);
+    launch_ring(P, false, 1, g1, g2, nullptr, nullptr, P.d_W, P.nrhs, true);
     for (int r = 0; r < P.nrhs; ++r) {
-        launch_leg_adj(P, false, r);
+        launch_leg_adj(P, false, r, true);
         launch_epilogue(P, false, kd, 0.0, nullptr, nullptr, bE + (int64_t)r * 2 * P.nalm, bB + (int64_t)r * 2 * P.nalm);
     }
     return check_launch("rhs");
@@ -1241,8 +1390,8 @@ static akra_status cg_prepare(Plan &P, const double *g1, const double *g2, const
     P.cg_pc = pc[r];
     P.cg_rhs = r;
     if (g1) {
-        launch_ring(P, false, 1, g1 + r * P.npix, g2 + r * P.npix, nullptr, nullptr, P.d_W + r * P.npix, 1);
-        launch_leg_adj(P, false, 0);
+        launch_ring(P, false, 1, g1 + r * P.npix, g2 + r * P.npix, nullptr, nullptr, P.d_W + r * P.npix, 1, true);
+        launch_leg_adj(P, false, 0, true);
         launch_epilogue(P, false, kd, 0.0, nullptr, nullptr, P.d_b, P.d_b + 2 * P.nalm);
     } else {
         AK_HIP(hipMemcpyAsync(P.d_b, bE + off, sizeof(double2) * P.nalm, hipMemcpyDeviceToDevice, P.stream), "copy");
@@ -1293,8 +1442,8 @@ static akra_status solve_batched(Plan &P, const double *g1, const double *g2, co
     for (int r = 0; r < nr; ++r) {
         const int64_t off = (int64_t)r * 2 * na;
         if (g1) {
-            launch_ring(P, false, 1, g1 + r * P.npix, g2 + r * P.npix, nullptr, nullptr, P.d_W + r * P.npix, 1);
-            launch_leg_adj(P, false, 0);
+            launch_ring(P, false, 1, g1 + r * P.npix, g2 + r * P.npix, nullptr, nullptr, P.d_W + r * P.npix, 1, true);
+            launch_leg_adj(P, false, 0, true);
             launch_epilogue(P, false, kd, 0.0, nullptr, nullptr, V(P.d_b, r), V(P.d_b, r) + 2 * na);
         } else {
             AK_HIP(hipMemcpyAsync(V(P.d_b, r), bE + off, sizeof(double2) * na, hipMemcpyDeviceToDevice, P.stream), "copy");
@@ -1430,7 +1579,9 @@ static akra_status solve_batched(Plan &P, const double *g1, const double *g2, co
             key.push_back((double)(uintptr_t)kd);
             key.push_back((double)P.proj);
             key.push_back((double)nr);
-            for (int v : {P.syn_V, P.syn_R, P.adj_R, P.adj_W, P.adj_L, P.adj_nrb}) key.push_back((double)v);
+            for (int v : {P.syn_V, P.syn_R, P.adj_R, P.adj_W, P.adj_L, P.adj_nrb, P.live_gen, P.syn_V1, P.syn_R1,
+                          P.adj_R1, P.adj_W1, P.adj_L1})
+                key.push_back((double)v);
             for (int r = 0; r < nr; ++r) {
                 key.push_back(le[r]);
                 key.push_back(pc[r]);
@@ -1626,8 +1777,8 @@ akra_status akra_cg_solve_cond_b(akra_plan plan, const double *g1, const double 
         for (int r = 0; r < P.nrhs; ++r) {
             const int64_t off = (int64_t)r * 2 * na;
             // b of this right-hand side (both blocks) into d_b
-            launch_ring(P, false, 1, g1 + r * P.npix, g2 + r * P.npix, nullptr, nullptr, P.d_W + r * P.npix, 1);
-            launch_leg_adj(P, false, 0);
+            launch_ring(P, false, 1, g1 + r * P.npix, g2 + r * P.npix, nullptr, nullptr, P.d_W + r * P.npix, 1, true);
+            launch_leg_adj(P, false, 0, true);
             launch_epilogue(P, false, kd, 0.0, nullptr, nullptr, P.d_b, P.d_b + nc);
             // H (kE, 0) into d_w; the B block is H_BE kE (the regulariser term of a zero B is zero)
             AK_HIP(hipMemsetAsync(P.d_xs + nc, 0, sizeof(double2) * na, P.stream), "memset");
@@ -1705,11 +1856,11 @@ akra_status akra_cg_solve_vjp(akra_plan plan, const double *g1, const double *g2
         k_sum2_scaled<<<1, 1, 0, P.stream>>>(sc + 2, sc, sc + 1, ms[r] > 0 ? o.lambda / ms[r] : 0.0);
         // q = Y K u into the gradient maps
         launch_prologue(P, false, P.d_x, P.d_x + 2 * na, kd, 1);
-        launch_leg_synth(P, false, 1);
-        launch_ring(P, false, 0, nullptr, nullptr, dg1 + mo, dg2 + mo, nullptr, 1);
+        launch_leg_synth(P, false, 1, false);
+        launch_ring(P, false, 0, nullptr, nullptr, dg1 + mo, dg2 + mo, nullptr, 1, false);
         // Y K x, consumed per pixel together with q, g, W and the mask
         launch_prologue(P, false, xE + off, xB + off, kd, 1);
-        launch_leg_synth(P, false, 1);
+        launch_leg_synth(P, false, 1, false);
         launch_ring_grad(P, g1 + mo, g2 + mo, dg1 + mo, dg2 + mo, P.d_W + mo, dninv + mo, mask, sc + 2);
         st = check_launch("solve_vjp");
         if (st) return st;
@@ -1791,10 +1942,17 @@ akra_status akra_cg_state(akra_plan plan, double *rel_resid, int *iters, double 
     return AKRA_OK;
 }
 
-akra_status akra_plan_set_tuning(akra_plan plan, int syn_variant, int syn_rings, int adj_rings, int adj_waves,
-                                 int adj_chunk)
+// the largest adjoint ring-block count any weighted apply can reach with the two shapes: the
+// groups of every class under the smaller group count per block, plus the rounding of the split
+static int nrb_bound(const Plan &P, int gpw0, int gpw1)
 {
-    AK_PLAN();
+    const int gpw = std::min(gpw0, gpw1);
+    return P.adj_nrb_polar + (P.ng64 - P.polar_groups + gpw - 1) / gpw + LIVE_NRB_EXTRA;
+}
+
+static akra_status set_tuning_class(Plan &P, int one_sided, int syn_variant, int syn_rings, int adj_rings,
+                                    int adj_waves, int adj_chunk)
+{
     const bool sv = syn_variant == 0 || syn_variant == 1;
     const bool sr = syn_rings == 1 || syn_rings == 2 || syn_rings == 4;
     if (!sv || !sr || !adj_shape_supported(adj_rings, adj_waves, adj_chunk)) {
@@ -1802,18 +1960,56 @@ akra_status akra_plan_set_tuning(akra_plan plan, int syn_variant, int syn_rings,
         return AKRA_ERR_ARG;
     }
     const int gpw = adj_rings * adj_waves;
-    const int nrb = P.adj_nrb_polar + (P.ng64 - P.polar_groups + gpw - 1) / gpw;
-    if ((size_t)nrb > P.part_rb_cap) {
+    const int other = one_sided ? P.adj_R * P.adj_W : P.adj_R1 * P.adj_W1;
+    if ((size_t)nrb_bound(P, gpw, other) > P.part_rb_cap) {
         set_error("adjoint shape needs more ring blocks than the plan's partial-sum buffer holds");
         return AKRA_ERR_ARG;
     }
-    P.syn_V = syn_variant;
-    P.syn_R = syn_rings;
-    P.adj_R = adj_rings;
-    P.adj_W = adj_waves;
-    P.adj_L = adj_chunk;
-    P.adj_nrb = nrb;
+    if (one_sided) {
+        P.syn_V1 = syn_variant;
+        P.syn_R1 = syn_rings;
+        P.adj_R1 = adj_rings;
+        P.adj_W1 = adj_waves;
+        P.adj_L1 = adj_chunk;
+    } else {
+        P.syn_V = syn_variant;
+        P.syn_R = syn_rings;
+        P.adj_R = adj_rings;
+        P.adj_W = adj_waves;
+        P.adj_L = adj_chunk;
+        P.adj_nrb = P.adj_nrb_polar + (P.ng64 - P.polar_groups + gpw - 1) / gpw;
+    }
     compute_work(P);
+    if (P.live_gen) compute_work_live(P);  // the staged lists of the last weight set-up
+    return AKRA_OK;
+}
+
+akra_status akra_plan_set_tuning(akra_plan plan, int syn_variant, int syn_rings, int adj_rings, int adj_waves,
+                                 int adj_chunk)
+{
+    AK_PLAN();
+    return set_tuning_class(P, 0, syn_variant, syn_rings, adj_rings, adj_waves, adj_chunk);
+}
+
+akra_status akra_plan_set_tuning_one_sided(akra_plan plan, int syn_variant, int syn_rings, int adj_rings,
+                                           int adj_waves, int adj_chunk)
+{
+    AK_PLAN();
+    return set_tuning_class(P, 1, syn_variant, syn_rings, adj_rings, adj_waves, adj_chunk);
+}
+
+akra_status akra_plan_get_tuning_one_sided(akra_plan plan, int *out5)
+{
+    AK_PLAN();
+    if (!out5) {
+        set_error("null pointer argument");
+        return AKRA_ERR_ARG;
+    }
+    out5[0] = P.syn_V1;
+    out5[1] = P.syn_R1;
+    out5[2] = P.adj_R1;
+    out5[3] = P.adj_W1;
+    out5[4] = P.adj_L1;
     return AKRA_OK;
 }
 
@@ -1874,6 +2070,28 @@ akra_status akra_plan_work(akra_plan plan, int64_t *out3)
         return AKRA_ERR_ARG;
     }
     for (int i = 0; i < 3; ++i) out3[i] = P.work[i];
+    return AKRA_OK;
+}
+
+akra_status akra_plan_work_weighted(akra_plan plan, int64_t *out6)
+{
+    AK_PLAN();
+    int64_t *out5 = out6;
+    if (!out5) {
+        set_error("out6 is NULL");
+        return AKRA_ERR_ARG;
+    }
+    out5[0] = P.n_live_rings;
+    for (int i = 0; i < 5; ++i) out5[1 + i] = P.work_live[i];
+    return AKRA_OK;
+}
+
+akra_status akra_plan_set_skip_unweighted(akra_plan plan, int on)
+{
+    AK_PLAN();
+    AK_HIP(hipStreamSynchronize(P.stream), "sync");
+    P.skip_rings = on != 0;
+    drop_graph(P);  // recorded iterations hold the launch sets
     return AKRA_OK;
 }
 

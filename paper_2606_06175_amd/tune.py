@@ -3,7 +3,10 @@
 For one (Nside, lmax, precision) it times every supported synthesis variant / ring-pairs-per-lane
 choice and every adjoint (ring pairs per lane, waves per workgroup) shape with HIP events on the
 plan stream (stage times of PCG iterations on synthetic data), and stores the fastest in
-tuning.json next to this file.  For FP32 plans with several right-hand sides (--nrhs K > 1) it tunes
+tuning.json next to this file.  It does so twice: on a full sky, where every ring group carries
+weight on both of its rings, and on the southern hemisphere alone, where every group carries weight
+on its south rings only and runs the one-sided contraction; the second result is kept as the
+entry's "one_sided" shapes.  For FP32 plans with several right-hand sides (--nrhs K > 1) it tunes
 the batched matrix-core kernels instead: waves per workgroup of the synthesis and of the adjoint,
 timed over batched operator applies (synthesis, adjoint and the epilogues that add the adjoint's
 slabs), cached per (Nside, lmax, K).  Plan() applies the cached shapes automatically.
@@ -94,10 +97,37 @@ def _time_stage(plan, stage, steps):
     return ms / max(n, 1)
 
 
+def _sweep(plan, setter, base_syn, base_adj, steps, log, tag):
+    from .akra import AkraError
+    res = {"syn": {}, "adj": {}}
+    best_syn, best_t = base_syn, float("inf")
+    for v, r in SYN:
+        setter(v, r, *base_adj)
+        t = _time_stage(plan, "leg_synth", steps)
+        res["syn"]["%d,%d" % (v, r)] = t
+        log("  %s synth variant %d rings/lane %d: %.3f ms" % (tag, v, r, t))
+        if t < best_t:
+            best_syn, best_t = (v, r), t
+    best_adj, best_ta = base_adj, float("inf")
+    for r, w, c in ADJ:
+        try:
+            setter(best_syn[0], best_syn[1], r, w, c)
+        except AkraError:
+            continue
+        t = _time_stage(plan, "leg_adj", steps)
+        res["adj"]["%d,%d,%d" % (r, w, c)] = t
+        log("  %s adjoint rings/lane %d waves %d chunk %d: %.3f ms" % (tag, r, w, c, t))
+        if t < best_ta:
+            best_adj, best_ta = (r, w, c), t
+    setter(best_syn[0], best_syn[1], *best_adj)
+    return {"syn_variant": best_syn[0], "syn_rings": best_syn[1], "adj_rings": best_adj[0],
+            "adj_waves": best_adj[1], "adj_chunk": best_adj[2], "ms_syn": best_t, "ms_adj": best_ta, "sweep": res}
+
+
 def tune(nside, lmax, precision="fp64", steps=2, log=print):
     import torch
 
-    from .akra import AkraError, Plan
+    from .akra import Plan
     dev = torch.device("cuda", 0)
     plan = Plan(nside, lmax, precision=precision, device=dev, tuned=False)
     npix = 12 * nside * nside
@@ -105,32 +135,23 @@ def tune(nside, lmax, precision="fp64", steps=2, log=print):
     g1 = torch.randn(npix, generator=g, dtype=torch.float64).to(dev)
     g2 = torch.randn(npix, generator=g, dtype=torch.float64).to(dev)
     ninv = torch.ones(npix, dtype=torch.float64, device=dev)
+    # full sky: every group weighted on both sides
     mask = torch.ones(npix, dtype=torch.uint8, device=dev)
     plan.cg_start(g1, g2, ninv, mask)
     base = plan.get_tuning()
-    res = {"syn": {}, "adj": {}}
-    best_syn, best_t = (base[0], base[1]), float("inf")
-    for v, r in SYN:
-        plan.set_tuning(v, r, base[2], base[3], base[4])
-        t = _time_stage(plan, "leg_synth", steps)
-        res["syn"]["%d,%d" % (v, r)] = t
-        log("  synth variant %d rings/lane %d: %.3f ms" % (v, r, t))
-        if t < best_t:
-            best_syn, best_t = (v, r), t
-    best_adj, best_ta = (base[2], base[3], base[4]), float("inf")
-    for r, w, c in ADJ:
-        try:
-            plan.set_tuning(best_syn[0], best_syn[1], r, w, c)
-        except AkraError:
-            continue
-        t = _time_stage(plan, "leg_adj", steps)
-        res["adj"]["%d,%d,%d" % (r, w, c)] = t
-        log("  adjoint rings/lane %d waves %d chunk %d: %.3f ms" % (r, w, c, t))
-        if t < best_ta:
-            best_adj, best_ta = (r, w, c), t
+    entry = _sweep(plan, plan.set_tuning, (base[0], base[1]), (base[2], base[3], base[4]), steps, log, "two-sided")
+    # the southern hemisphere (z < 0, the equatorial ring excluded): every group weighted on its
+    # south rings only.  In RING order those are the pixels past the equatorial ring 2 Nside (4 Nside
+    # pixels centred on the middle of the map): npix / 2 + 2 Nside onwards.
+    south = torch.zeros(npix, dtype=torch.uint8, device=dev)
+    south[npix // 2 + 2 * nside:] = 1
+    plan.cg_start(g1, g2, ninv, south)
+    ww = plan.work_weighted()
+    assert ww["synth_two"] == 0 and ww["adjoint_two"] == 0, ww
+    one = _sweep(plan, plan.set_tuning_one_sided, (entry["syn_variant"], entry["syn_rings"]),
+                 (entry["adj_rings"], entry["adj_waves"], entry["adj_chunk"]), steps, log, "one-sided")
+    entry["one_sided"] = one
     plan.close()
-    entry = {"syn_variant": best_syn[0], "syn_rings": best_syn[1], "adj_rings": best_adj[0],
-             "adj_waves": best_adj[1], "adj_chunk": best_adj[2], "ms_syn": best_t, "ms_adj": best_ta, "sweep": res}
     return entry
 
 
@@ -159,7 +180,8 @@ def main():
     cache[k] = e
     with open(a.out, "w") as f:
         json.dump(cache, f, indent=1, sort_keys=True)
-    print(json.dumps({k: v for k, v in e.items() if k != "sweep"}), flush=True)
+    print(json.dumps({k: ({kk: vv for kk, vv in v.items() if kk != "sweep"} if isinstance(v, dict) else v)
+                      for k, v in e.items() if k != "sweep"}), flush=True)
     return 0
 
 
