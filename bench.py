@@ -46,27 +46,34 @@ def live_ring_bytes(nside, lmax, w, fg_bytes):
     return int(2 * fg_bytes * live.sum() * (lmax + 1) + 8 * ns[live].sum()), int(live.sum())
 
 
-# HBM bytes per launch of the dominant kernel from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE at this
+# HBM bytes per apply of the dominant stage from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE at this
 # workload, each scaled by the same counter's reading for a device copy of known size; valid only for
-# the kernel sources they were taken from (the SHA-256 of akra_kernels.hip followed by akra_fft.h is
-# checked at run time).
+# the kernel sources and launch shapes they were taken with (the SHA-256 of the Legendre sources and
+# the plan's two- and one-sided shapes are checked at run time).
 TRAFFIC = {
-    # profiles/k_leg_adj_nside2048_lmax4096_fp64.md: FETCH 2.4830e6 KiB x 2.0 + WRITE 3.1590e6 KiB x 1.0
-    "leg_adj": {"bytes": 8.320e9, "workload": (2048, 4096),
-                "kernels_sha256": "ec32163557c157b07159683aee914f0a4bb9c61b42fb7588ccf88ffa7915747d"},
+    # profiles/k_leg_adj_nside2048_lmax4096_fp64.md: two-sided k_leg_adj<double, 4, 1, 4, 0, 0>
+    # FETCH 4.8017e5 KiB x 2.0 + WRITE 8.5475e5 KiB, one-sided k_leg_adj<double, 8, 1, 8, 0, 2>
+    # FETCH 5.8220e5 KiB x 2.0 + WRITE 1.0903e6 KiB
+    "leg_adj": {"bytes": 4.167e9, "workload": (2048, 4096), "shapes": ((0, 1, 4, 1, 4), (1, 2, 8, 1, 8)),
+                "sources_sha256": "3fefb0c5a3eb180bd2db44d6b2348ea08d230d231bf279c0574168699ea55b4e"},
 }
+LEG_SOURCES = ("akra_leg.h", "akra_leg_both.hip", "akra_leg_north.hip", "akra_leg_south.hip", "akra_kernels.hip")
 
 
-def traffic(stage, nside, lmax):
+def legendre_sources_sha256():
     import hashlib
-    rec = TRAFFIC.get(stage)
-    if not rec or rec["workload"] != (nside, lmax):
-        return None
     h = hashlib.sha256()
-    for name in ("akra_kernels.hip", "akra_fft.h"):
+    for name in LEG_SOURCES:
         with open(os.path.join(ROOT, "paper_2606_06175_amd", "csrc", name), "rb") as f:
             h.update(f.read())
-    if h.hexdigest() != rec["kernels_sha256"]:
+    return h.hexdigest()
+
+
+def traffic(stage, nside, lmax, shapes):
+    rec = TRAFFIC.get(stage)
+    if not rec or rec["workload"] != (nside, lmax) or tuple(map(tuple, shapes)) != rec["shapes"]:
+        return None
+    if legendre_sources_sha256() != rec["sources_sha256"]:
         return None
     return rec["bytes"]
 
@@ -670,7 +677,8 @@ def main():
     roofline = {"bound": "alu", "kernel": "k_leg_adj" if dom == "leg_adj" else "k_leg_synth",
                 "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
                 "frac": achieved / peak,
-                "traffic": traffic(dom, nside, lmax) if args.precision == "fp64" else None,
+                "traffic": (traffic(dom, nside, lmax, (plan.get_tuning(), plan.get_tuning_one_sided()))
+                            if args.precision == "fp64" else None),
                 "algorithmic": "26 flop x %d triples of ring groups weighted on both sides + 18 flop x %d of groups "
                                "weighted on one side = %.4g flop per launch (all (l, m, ring-pair) triples T = %d; "
                                "groups without a weighted ring and the terms below each group's entry degree, where "

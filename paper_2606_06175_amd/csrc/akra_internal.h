@@ -172,6 +172,7 @@ struct Plan {
     int *d_live_lists = nullptr;  // [RING_KINDS][nrings] ring lists, then [GCLS_N + 1][ng64] group lists
     uint8_t *d_ring_live = nullptr;  // [nrings] 1: the ring carries weight in some right-hand side's W
     uint8_t *h_live = nullptr;       // pinned: the flags read back, then the lists staged for upload
+    std::vector<uint8_t> h_live_prev;  // the flags the current lists were built from
     int live_gen = 0;                // counts weight set-ups (recorded graphs hold the lists' sizes)
     bool skip_rings = true;          // weighted applies use the weighted sets (akra_plan_set_skip_unweighted)
     int n_live_rings = 0;            // rings that carry weight in the current weights
@@ -240,6 +241,11 @@ struct Plan {
     bool use_graph = true;
     bool capturing = false;  // recording the graph: host-side trace ranges are not emitted
     hipStream_t cap_stream = nullptr;
+    // a second stream at the default priority: independent launches of one stage (the Legendre
+    // classes, the ring-kernel kinds) run on it beside the plan stream, forked from and joined back
+    // to the plan stream with events, so that one launch fills the other's tail
+    hipStream_t side_stream = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     hipGraphExec_t cg_graph = nullptr;
     double cg_graph_key[ITER_KEY_N] = {};
     // the lockstep iteration of the batched solve, keyed by its by-value arguments and active set
@@ -289,6 +295,28 @@ struct StallWatch {
         return ++since >= window;
     }
 };
+
+// Runs side() with the plan's launches going to the side stream and main() on the plan stream,
+// the side stream forked from the plan stream before and joined to it after (stream-ordered, and
+// captured the same way into a recorded graph).  Without a side stream both run on the plan stream.
+// A failing event call leaves its error for the launch check that follows every stage.
+template <class A, class B> void fork_join(Plan &P, A &&side, B &&main)
+{
+    if (!P.side_stream) {
+        side();
+        main();
+        return;
+    }
+    (void)hipEventRecord(P.ev_fork, P.stream);
+    (void)hipStreamWaitEvent(P.side_stream, P.ev_fork, 0);
+    const hipStream_t s = P.stream;
+    P.stream = P.side_stream;
+    side();
+    P.stream = s;
+    main();
+    (void)hipEventRecord(P.ev_join, P.side_stream);
+    (void)hipStreamWaitEvent(P.stream, P.ev_join, 0);
+}
 
 // error handling
 void set_error(const std::string &msg);

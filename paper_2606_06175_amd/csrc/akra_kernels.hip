@@ -1908,12 +1908,22 @@ void launch_entry(Plan &P)
 void launch_leg_synth(Plan &P, bool fp32, int nrhs, bool live)
 {
     const GroupSet &G = live && P.skip_rings ? P.gs_live : P.gs_all;
-    if (G.npol[GCLS_BOTH] + G.nmain[GCLS_BOTH])
-        leg_synth_cls<GCLS_BOTH>(P, fp32, nrhs, G.list[GCLS_BOTH], G.npol[GCLS_BOTH], G.nmain[GCLS_BOTH]);
-    if (G.npol[GCLS_NORTH] + G.nmain[GCLS_NORTH])
-        leg_synth_cls<GCLS_NORTH>(P, fp32, nrhs, G.list[GCLS_NORTH], G.npol[GCLS_NORTH], G.nmain[GCLS_NORTH]);
-    if (G.npol[GCLS_SOUTH] + G.nmain[GCLS_SOUTH])
-        leg_synth_cls<GCLS_SOUTH>(P, fp32, nrhs, G.list[GCLS_SOUTH], G.npol[GCLS_SOUTH], G.nmain[GCLS_SOUTH]);
+    auto n = [&](int c) { return G.npol[c] + G.nmain[c]; };
+    auto two = [&]() {
+        if (n(GCLS_BOTH)) leg_synth_cls<GCLS_BOTH>(P, fp32, nrhs, G.list[GCLS_BOTH], G.npol[GCLS_BOTH], G.nmain[GCLS_BOTH]);
+    };
+    auto one = [&]() {
+        if (n(GCLS_NORTH))
+            leg_synth_cls<GCLS_NORTH>(P, fp32, nrhs, G.list[GCLS_NORTH], G.npol[GCLS_NORTH], G.nmain[GCLS_NORTH]);
+        if (n(GCLS_SOUTH))
+            leg_synth_cls<GCLS_SOUTH>(P, fp32, nrhs, G.list[GCLS_SOUTH], G.npol[GCLS_SOUTH], G.nmain[GCLS_SOUTH]);
+    };
+    // the classes write F of disjoint rings: the two-sided groups on the side stream
+    if (n(GCLS_BOTH) && n(GCLS_NORTH) + n(GCLS_SOUTH)) fork_join(P, two, one);
+    else {
+        two();
+        one();
+    }
 }
 
 bool adj_shape_supported(int r, int w, int l)
@@ -1943,16 +1953,27 @@ void launch_leg_adj(Plan &P, bool fp32, int rhs, bool live)
     const GroupSet &G = live ? P.gs_live : P.gs_all;
     const uint8_t *lv = live ? P.d_ring_live : nullptr;
     const int nrb = adj_blocks_total(P, live);
-    int rb = 0;
-    if (G.npol[GCLS_BOTH] + G.nmain[GCLS_BOTH])
-        rb += leg_adj_cls<GCLS_BOTH>(P, fp32, rhs, G.list[GCLS_BOTH], G.npol[GCLS_BOTH], G.nmain[GCLS_BOTH], lv, rb,
-                                     nrb);
-    if (G.npol[GCLS_NORTH] + G.nmain[GCLS_NORTH])
-        rb += leg_adj_cls<GCLS_NORTH>(P, fp32, rhs, G.list[GCLS_NORTH], G.npol[GCLS_NORTH], G.nmain[GCLS_NORTH], lv,
-                                      rb, nrb);
-    if (G.npol[GCLS_SOUTH] + G.nmain[GCLS_SOUTH])
-        rb += leg_adj_cls<GCLS_SOUTH>(P, fp32, rhs, G.list[GCLS_SOUTH], G.npol[GCLS_SOUTH], G.nmain[GCLS_SOUTH], lv,
-                                      rb, nrb);
+    auto n = [&](int c) { return G.npol[c] + G.nmain[c]; };
+    // ring blocks: the two-sided class first, then north, then south (the slabs are disjoint)
+    const int rb1 = adj_blocks(P, GCLS_BOTH, G.npol[GCLS_BOTH], G.nmain[GCLS_BOTH]);
+    const int rb2 = rb1 + adj_blocks(P, GCLS_NORTH, G.npol[GCLS_NORTH], G.nmain[GCLS_NORTH]);
+    auto two = [&]() {
+        if (n(GCLS_BOTH))
+            leg_adj_cls<GCLS_BOTH>(P, fp32, rhs, G.list[GCLS_BOTH], G.npol[GCLS_BOTH], G.nmain[GCLS_BOTH], lv, 0, nrb);
+    };
+    auto one = [&]() {
+        if (n(GCLS_NORTH))
+            leg_adj_cls<GCLS_NORTH>(P, fp32, rhs, G.list[GCLS_NORTH], G.npol[GCLS_NORTH], G.nmain[GCLS_NORTH], lv,
+                                    rb1, nrb);
+        if (n(GCLS_SOUTH))
+            leg_adj_cls<GCLS_SOUTH>(P, fp32, rhs, G.list[GCLS_SOUTH], G.npol[GCLS_SOUTH], G.nmain[GCLS_SOUTH], lv,
+                                    rb2, nrb);
+    };
+    if (n(GCLS_BOTH) && n(GCLS_NORTH) + n(GCLS_SOUTH)) fork_join(P, two, one);
+    else {
+        two();
+        one();
+    }
     P.nrb_cur = nrb;
 }
 
@@ -2046,12 +2067,18 @@ static void ring_launch_t(Plan &P, const RingSet &RS, const double *g1, const do
             (cplx<T> *)P.d_FG, fg_stride, g1, g2, o1, o2, P.npix, W, P.d_rings, RS.order[RK_REG + q],
             (const cplx<T> *)tw, P.twn, P.lmax, P.omega, o3, mask, cdev, bhr);
     };
-    reg(k_ring16<T, MODE, 13, 2>, 5, 8192);
-    reg(k_ring16<T, MODE, 13, 0>, 1, 8192);
-    reg(k_ring16<T, MODE, 13, 1>, 3, 8192);
-    reg(k_ring16<T, MODE, 12, 2>, 4, 4096);
-    reg(k_ring16<T, MODE, 12, 0>, 0, 4096);
-    reg(k_ring16<T, MODE, 12, 1>, 2, 4096);
+    // the kinds touch disjoint rings: the largest direct kind on the plan stream, the others beside it
+    auto side = [&]() {
+        reg(k_ring16<T, MODE, 13, 2>, 5, 8192);
+        reg(k_ring16<T, MODE, 13, 1>, 3, 8192);
+        reg(k_ring16<T, MODE, 12, 0>, 0, 4096);
+    };
+    auto main = [&]() {
+        reg(k_ring16<T, MODE, 13, 0>, 1, 8192);
+        reg(k_ring16<T, MODE, 12, 2>, 4, 4096);
+        reg(k_ring16<T, MODE, 12, 1>, 2, 4096);
+    };
+    fork_join(P, side, main);
 }
 
 // Spectra of the Bluestein chirps, one per distinct sub-transform length L (plan creation):

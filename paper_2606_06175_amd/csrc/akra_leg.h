@@ -638,7 +638,8 @@ __device__ __forceinline__ void adj_step(const C &c, const X (&x)[R], T (&c2)[R]
 // four waves.  Eight pairs per lane cannot fit three waves without spilling in the inner loop: no
 // target there.
 template <typename T, int R, int CLS = GCLS_BOTH> struct AdjWaves {
-    static constexpr int value = R > 4 ? 1 : (std::is_same<T, double>::value && CLS == GCLS_BOTH) ? 3 : 4;
+    static constexpr bool two = CLS == GCLS_BOTH, fp64 = std::is_same<T, double>::value;
+    static constexpr int value = R > 4 ? (two ? 1 : 2) : (fp64 && two) ? 3 : 4;
 };
 // LDS hand-over between the lanes of a workgroup.  A single-wave workgroup needs no s_barrier: the
 // LDS unit executes one wave's instructions in order, so a fence that keeps the compiler from moving

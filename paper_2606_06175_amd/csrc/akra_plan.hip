@@ -300,6 +300,11 @@ static void compute_work_live(Plan &P)
 static akra_status build_live_lists(Plan &P)
 {
     const uint8_t *flag = P.h_live;
+    // the same rings as at the last set-up: the lists on the device (and recorded graphs) still hold
+    if (P.live_gen && P.h_live_prev.size() == (size_t)P.nrings &&
+        std::memcmp(P.h_live_prev.data(), flag, (size_t)P.nrings) == 0)
+        return AKRA_OK;
+    P.h_live_prev.assign(flag, flag + P.nrings);
     int *stage = (int *)(P.h_live + (P.nrings + 15) / 16 * 16);
     for (int k = 0; k < RING_KINDS; ++k) {
         int *o = stage + (size_t)k * P.nrings;
@@ -363,6 +368,9 @@ static void free_plan(Plan *P)
     if (P->cg_graph) (void)hipGraphExecDestroy(P->cg_graph);
     if (P->cg_graph_b) (void)hipGraphExecDestroy(P->cg_graph_b);
     if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
+    if (P->side_stream) (void)hipStreamDestroy(P->side_stream);
+    if (P->ev_fork) (void)hipEventDestroy(P->ev_fork);
+    if (P->ev_join) (void)hipEventDestroy(P->ev_join);
     delete P;
 }
 
@@ -755,6 +763,13 @@ static akra_status create(int nside, int lmax, int nrhs, int prec, void *stream,
     AK_TRY(alloc((void **)&P->d_w, vb, *P));
     AK_TRY(alloc((void **)&P->d_b, vb, *P));
     AK_TRY(alloc((void **)&P->d_xs, vb, *P));
+    if (hipStreamCreateWithFlags(&P->side_stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming) != hipSuccess) {
+        free_plan(P);
+        set_error("stream or event creation failed");
+        return AKRA_ERR_HIP;
+    }
     if (hipHostMalloc((void **)&P->h_pin, 256 * sizeof(double)) != hipSuccess) {
         P->h_pin = nullptr;
         free_plan(P);
