@@ -254,10 +254,12 @@ akra_status akra_plan_set_graph(akra_plan plan, int on);
  *   syn_variant  0 two steps per trip, 1 four steps per trip with look-ahead loads
  *   syn_rings    ring pairs per lane of the synthesis (1, 2, 4)
  *   adj_rings, adj_waves, adj_chunk   ring pairs per lane, waves per workgroup and l-chunk of the
- *                adjoint: (1,1,8) (1,2,8) (1,4,8) (2,2,8) (2,4,8) (4,2,8) (4,4,8) (8,1,8) (8,2,8)
- *                (2,4,4) (4,2,4) (4,4,4) (8,1,4) (2,1,8) (4,1,4) (4,1,8).  A shape covering fewer ring
- *                pairs per workgroup than the plan's partial-sum buffer allows (at least 256 pairs
- *                per workgroup when Nside > 512) is rejected with AKRA_ERR_ARG.
+ *                adjoint: (R,1,8) and (R,1,4) for R = 1..8, and (1,2,8) (1,4,8) (2,2,8) (2,4,8)
+ *                (4,2,8) (4,4,8) (8,2,8) (2,4,4) (4,2,4) (4,4,4).  Single-wave shapes spread a list of
+ *                n 64-pair groups evenly over ceil(n / R) workgroups (at most R groups each, none
+ *                with an empty slot); the others take R W consecutive groups per workgroup.  A shape
+ *                covering fewer ring pairs per workgroup than the plan's partial-sum buffer allows
+ *                (at least 256 pairs per workgroup when Nside > 512) is rejected with AKRA_ERR_ARG.
  * akra_plan_get_tuning writes the five current values to out5 (HOST).
  * These shapes apply to every group of an unweighted transform and to the ring groups weighted on
  * both sides in weighted applies (see akra_plan_set_skip_unweighted); akra_plan_set_tuning_one_sided

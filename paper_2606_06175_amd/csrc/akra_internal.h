@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <array>
 #include <cstdint>
 #include <string>
@@ -415,5 +416,42 @@ hipError_t launch_pixelize(Plan &P, int64_t n, double R, double se2, double n_th
                            double *ninv, double *neff, uint8_t *mask);
 bool pow2(int n);
 bool adj_shape_supported(int r, int w, int l);
+
+// Workgroups of the adjoint over a list of n 64-pair groups with R groups per wave and W waves per
+// workgroup.  Workgroups of several waves take W R consecutive list entries each (the last one
+// possibly fewer, its empty slots computing zeros).  Single-wave workgroups spread the list evenly
+// instead, so that no slot is empty: q = ceil(n / R) workgroups, the first nA of RA = ceil(n / q)
+// groups, the others of RA - 1 (RA <= R, and the count of workgroups is the same).
+struct AdjSplit {
+    int q, RA, nA;
+};
+inline AdjSplit adj_split(int n, int R, int W)
+{
+    AdjSplit s{0, R, 0};
+    if (n <= 0) return s;
+    if (W > 1) {
+        s.q = (n + R * W - 1) / (R * W);
+        s.nA = s.q;
+        return s;
+    }
+    s.q = (n + R - 1) / R;
+    s.RA = (n + s.q - 1) / s.q;
+    s.nA = n - s.q * (s.RA - 1);
+    return s;
+}
+// first list entry and number of groups of workgroup b of a split (W as in adj_split)
+inline void adj_block(const AdjSplit &s, int n, int W, int b, int &first, int &count)
+{
+    if (W > 1) {
+        first = b * s.RA * W;
+        count = std::min(n - first, s.RA * W);
+    } else if (b < s.nA) {
+        first = b * s.RA;
+        count = s.RA;
+    } else {
+        first = s.nA * s.RA + (b - s.nA) * (s.RA - 1);
+        count = s.RA - 1;
+    }
+}
 
 }  // namespace akra

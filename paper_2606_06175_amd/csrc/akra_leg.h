@@ -678,33 +678,24 @@ template <int W> __device__ __forceinline__ void wg_lds_sync()
     }
 }
 
-// Adjoint over a list of 64-pair groups: workgroup b of the launch holds the groups glist[b W R ..
-// b W R + W R - 1] (wave w the R of them from w R), and writes ring block rb0 + b of the nrb blocks
-// of every m.  CLS selects the rings it reads (GCLS_BOTH, GCLS_NORTH, GCLS_SOUTH); a ring whose
-// flag in live is zero is read as G = 0 (live null: every ring is read).
+// The adjoint of one workgroup: m, its ring block rb, and its groups glist[lw .. lw + W R) (wave w
+// the R of them from lw + w R; entries at or past ngl hold nothing).  red: the workgroup's LDS.
 template <typename T, int R, int W, int L, int F, int CLS>
-__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(AdjWaves<T, R, CLS>::value))) void k_leg_adj(const cplx<T> *__restrict__ FG,
-                                                    const typename CoefT<T, F>::type *__restrict__ coef,
-                                                    const Coef64S *__restrict__ cs64,
-                                                    const Ent64 *__restrict__ ent, const int *__restrict__ entk,
-                                                    const int *__restrict__ entl, int ng64,
-                                                    const double *__restrict__ pair_z, T *__restrict__ part,
-                                                    int *__restrict__ wgstart, int64_t nalm, int lmax, int npairs,
-                                                    int nrings, const int *__restrict__ glist, int ngl,
-                                                    const uint8_t *__restrict__ live, int rb0, int nrbl, int nrb)
+__device__ __forceinline__ void adj_body(T *__restrict__ red, const cplx<T> *__restrict__ FG,
+                                         const typename CoefT<T, F>::type *__restrict__ coef,
+                                         const Coef64S *__restrict__ cs64, const Ent64 *__restrict__ ent,
+                                         const int *__restrict__ entk, const int *__restrict__ entl, int ng64,
+                                         const double *__restrict__ pair_z, T *__restrict__ part,
+                                         int *__restrict__ wgstart, int64_t nalm, int lmax, int npairs, int nrings,
+                                         const int *__restrict__ glist, int ngl, const uint8_t *__restrict__ live,
+                                         int nrb, int m, int rb, int lw)
 {
     // LDS columns (wave, l, c) of 64 lanes, padded to CS entries: the G threads that sum one column
     // read entries gi + G t of it, and with CS = 64 + G (mod 32 double-banks) the 64 threads of a
     // wave spread over the banks twice each, as do the lane-contiguous writes
     constexpr int GR = 16 * W / L, CS = 64 + GR;
-    __shared__ T red[W * L * 4 * CS];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    int m, rbl;
-    xcd_map((int)blockIdx.x, nrbl, m, rbl);
-    if (m > lmax) return;
-    const int rb = rb0 + rbl;
-    const int lw = rbl * W * R;  // first list entry of the workgroup
     const int l0 = m > 2 ? m : 2;
     const int64_t base = (int64_t)m * (2 * lmax + 1 - m) / 2;
     const auto *cf = coef + base;
@@ -869,6 +860,40 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(AdjWaves
     }
 }
 
+// Adjoint over a list of 64-pair groups: workgroup b of the launch writes ring block rb0 + b of the
+// nrb blocks of every m, from the groups adj_block gives it (glist[b W R ..] for W > 1; for W = 1
+// the first nA workgroups take R groups each and the others R - 1, so that no slot is empty).  CLS
+// selects the rings it reads (GCLS_BOTH, GCLS_NORTH, GCLS_SOUTH); a ring whose flag in live is zero
+// is read as G = 0 (live null: every ring is read).
+template <typename T, int R, int W, int L, int F, int CLS>
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(AdjWaves<T, R, CLS>::value))) void k_leg_adj(const cplx<T> *__restrict__ FG,
+                                                    const typename CoefT<T, F>::type *__restrict__ coef,
+                                                    const Coef64S *__restrict__ cs64,
+                                                    const Ent64 *__restrict__ ent, const int *__restrict__ entk,
+                                                    const int *__restrict__ entl, int ng64,
+                                                    const double *__restrict__ pair_z, T *__restrict__ part,
+                                                    int *__restrict__ wgstart, int64_t nalm, int lmax, int npairs,
+                                                    int nrings, const int *__restrict__ glist, int ngl,
+                                                    const uint8_t *__restrict__ live, int rb0, int nrbl, int nrb,
+                                                    int nA)
+{
+    constexpr int GR = 16 * W / L, CS = 64 + GR;
+    __shared__ T red[W * L * 4 * CS];
+    int m, rbl;
+    xcd_map((int)blockIdx.x, nrbl, m, rbl);
+    if (m > lmax) return;
+    if constexpr (W == 1 && R > 1) {
+        if (rbl >= nA) {
+            adj_body<T, R - 1, 1, L, F, CLS>(red, FG, coef, cs64, ent, entk, entl, ng64, pair_z, part, wgstart, nalm,
+                                             lmax, npairs, nrings, glist, ngl, live, nrb, m, rb0 + rbl,
+                                             nA * R + (rbl - nA) * (R - 1));
+            return;
+        }
+    }
+    adj_body<T, R, W, L, F, CLS>(red, FG, coef, cs64, ent, entk, entl, ng64, pair_z, part, wgstart, nalm, lmax,
+                                 npairs, nrings, glist, ngl, live, nrb, m, rb0 + rbl, rbl * W * R);
+}
+
 // ================================================================================================
 // launch helpers (host): the translation units akra_leg_both/north/south.hip instantiate
 // leg_synth_cls and leg_adj_cls for one class each
@@ -928,50 +953,71 @@ void leg_synth_cls(Plan &P, bool fp32, int nrhs, const int *list, int npol, int 
     }
 }
 
-// adjoint workgroups (W R list entries each) over glist[0 .. ngl), writing ring blocks rb0 ..
-// of the apply's nrb; returns the blocks written
+// adjoint workgroups over glist[0 .. ngl) as split by sp (adj_split with this R, or RA, and W),
+// writing ring blocks rb0 .. of the apply's nrb; returns the blocks written
 template <typename T, int R, int W, int L, int F, int CLS>
-int adj_launch(Plan &P, int rhs, const int *glist, int ngl, const uint8_t *live, int rb0, int nrb)
+int adj_launch(Plan &P, int rhs, const int *glist, int ngl, const AdjSplit &sp, const uint8_t *live, int rb0,
+               int nrb)
 {
-    const int nrbl = (int)cdiv(ngl, W * R);
-    if (nrbl <= 0) return 0;
+    if (sp.q <= 0) return 0;
     const int64_t fg_stride = (int64_t)P.nrings * (P.lmax + 1) * 2;
     const void *coef = std::is_same<T, double>::value ? (const void *)P.d_coef64s
                        : F                              ? (const void *)P.d_coef32d
                                                         : (const void *)P.d_coef32s;
-    dim3 g((unsigned)(8 * nrbl * xcd_slots(P.lmax)));
+    dim3 g((unsigned)(8 * sp.q * xcd_slots(P.lmax)));
     k_leg_adj<T, R, W, L, F, CLS><<<g, 64 * W, 0, P.stream>>>(
         (const cplx<T> *)P.d_FG + rhs * fg_stride, (const typename CoefT<T, F>::type *)coef, P.d_coef64s, P.d_ent,
         P.d_entk, P.d_entl, P.ng64, P.d_pair_z, (T *)P.d_part, P.d_wgstart, P.nalm, P.lmax, P.npairs, P.nrings, glist,
-        ngl, live, rb0, nrbl, nrb);
-    return nrbl;
+        ngl, live, rb0, sp.q, nrb, sp.nA);
+    return sp.q;
 }
 
-// supported adjoint shapes (ring pairs per lane, waves per workgroup, l-chunk)
-#define AKRA_ADJ_SHAPES(X) \
-    X(1, 1, 8) X(1, 2, 8) X(1, 4, 8) X(2, 2, 8) X(2, 4, 8) X(4, 2, 8) X(4, 4, 8) X(8, 1, 8) X(8, 2, 8) \
-    X(2, 4, 4) X(4, 2, 4) X(4, 4, 4) X(8, 1, 4) X(2, 1, 8) X(4, 1, 4) X(4, 1, 8)
+// single-wave workgroups of at most RMAX groups, spread evenly (adj_split): the kernel of RA = sp.RA
+// groups per workgroup, whose later workgroups take RA - 1
+template <typename T, int RMAX, int L, int F, int CLS>
+int adj_launch_even(Plan &P, int rhs, const int *glist, int ngl, const AdjSplit &sp, const uint8_t *live, int rb0,
+                    int nrb)
+{
+    if constexpr (RMAX > 1) {
+        if (sp.RA < RMAX) return adj_launch_even<T, RMAX - 1, L, F, CLS>(P, rhs, glist, ngl, sp, live, rb0, nrb);
+    }
+    return adj_launch<T, RMAX, 1, L, F, CLS>(P, rhs, glist, ngl, sp, live, rb0, nrb);
+}
+
+// supported adjoint shapes (ring pairs per lane, waves per workgroup, l-chunk); the single-wave ones
+// run through adj_launch_even
+#define AKRA_ADJ_SHAPES_W1(X)                                                                          \
+    X(1, 1, 8) X(2, 1, 8) X(3, 1, 8) X(4, 1, 8) X(5, 1, 8) X(6, 1, 8) X(7, 1, 8) X(8, 1, 8) X(1, 1, 4) X(2, 1, 4) \
+        X(3, 1, 4) X(4, 1, 4) X(5, 1, 4) X(6, 1, 4) X(7, 1, 4) X(8, 1, 4)
+#define AKRA_ADJ_SHAPES_WN(X) \
+    X(1, 2, 8) X(1, 4, 8) X(2, 2, 8) X(2, 4, 8) X(4, 2, 8) X(4, 4, 8) X(8, 2, 8) X(2, 4, 4) X(4, 2, 4) X(4, 4, 4)
+#define AKRA_ADJ_SHAPES(X) AKRA_ADJ_SHAPES_W1(X) AKRA_ADJ_SHAPES_WN(X)
 
 template <typename T, int CLS>
 int adj_dispatch(Plan &P, int rhs, const int *glist, int ngl, const uint8_t *live, int rb0, int nrb)
 {
     int R, W, L;
     adj_shape_of(P, CLS, R, W, L);
+    const AdjSplit sp = adj_split(ngl, R, W);
+    if (W == 1) {
+        if (L == 4) return adj_launch_even<T, 8, 4, 0, CLS>(P, rhs, glist, ngl, sp, live, rb0, nrb);
+        return adj_launch_even<T, 8, 8, 0, CLS>(P, rhs, glist, ngl, sp, live, rb0, nrb);
+    }
 #define AKRA_ADJ_CASE(r, w, l) \
-    if (R == r && W == w && L == l) return adj_launch<T, r, w, l, 0, CLS>(P, rhs, glist, ngl, live, rb0, nrb);
-    AKRA_ADJ_SHAPES(AKRA_ADJ_CASE)
+    if (R == r && W == w && L == l) return adj_launch<T, r, w, l, 0, CLS>(P, rhs, glist, ngl, sp, live, rb0, nrb);
+    AKRA_ADJ_SHAPES_WN(AKRA_ADJ_CASE)
 #undef AKRA_ADJ_CASE
-    return adj_launch<T, 4, 4, 8, 0, CLS>(P, rhs, glist, ngl, live, rb0, nrb);
+    return adj_launch<T, 4, 4, 8, 0, CLS>(P, rhs, glist, ngl, adj_split(ngl, 4, 4), live, rb0, nrb);
 }
 
 // ring blocks the adjoint of a class list of npol near-polar and nmain other groups writes: the
-// near-polar groups form blocks of four (difference form in FP32 plans; FP64 applies of such plans
-// keep the same layout), the others blocks of the class's tuned adj_R adj_W
+// near-polar groups form blocks of at most four (difference form in FP32 plans; FP64 applies of such
+// plans keep the same layout), the others blocks of the class's tuned adj_R adj_W
 inline int adj_blocks(const Plan &P, int cls, int npol, int nmain)
 {
     int R, W, L;
     adj_shape_of(P, cls, R, W, L);
-    return (int)(cdiv(npol, 4) + cdiv(nmain, R * W));
+    return adj_split(npol, 4, 1).q + adj_split(nmain, R, W).q;
 }
 
 // Legendre adjoint of right-hand side rhs over list[0 .. npol + nmain) of class CLS into ring blocks
@@ -980,12 +1026,13 @@ template <int CLS>
 int leg_adj_cls(Plan &P, bool fp32, int rhs, const int *list, int npol, int nmain, const uint8_t *live, int rb0,
                 int nrb)
 {
+    const AdjSplit pol = adj_split(npol, 4, 1);
     int n = 0;
     if (fp32) {
-        n += adj_launch<float, 4, 1, 4, 1, CLS>(P, rhs, list, npol, live, rb0, nrb);
+        n += adj_launch_even<float, 4, 4, 1, CLS>(P, rhs, list, npol, pol, live, rb0, nrb);
         n += adj_dispatch<float, CLS>(P, rhs, list + npol, nmain, live, rb0 + n, nrb);
     } else {
-        n += adj_launch<double, 4, 1, 4, 0, CLS>(P, rhs, list, npol, live, rb0, nrb);
+        n += adj_launch_even<double, 4, 4, 0, CLS>(P, rhs, list, npol, pol, live, rb0, nrb);
         n += adj_dispatch<double, CLS>(P, rhs, list + npol, nmain, live, rb0 + n, nrb);
     }
     return n;

@@ -209,11 +209,25 @@ static void compute_work(Plan &P)
         }
         return w;
     };
+    // adjoint workgroups over [g0, g1) as adj_split places them
+    auto seg_adj = [&](const int *e, int g0, int g1, int R, int W) {
+        const AdjSplit sp = adj_split(g1 - g0, R, W);
+        int64_t w = 0;
+        for (int b = 0; b < sp.q; ++b) {
+            int first, count;
+            adj_block(sp, g1 - g0, W, b, first, count);
+            const int a0 = g0 + first, a1 = a0 + count;
+            int ls = ENT_SKIP;
+            for (int g = a0; g < a1; ++g) ls = std::min(ls, e[g]);
+            if (ls <= lmax) w += pairs_in(a0, a1) * (lmax - ls + 1);
+        }
+        return w;
+    };
     for (int m = 0; m <= lmax; ++m) {
         all += (int64_t)np * (lmax - std::max(m, 2) + 1);
         const int *e = P.h_entl.data() + (size_t)m * ng;
         syn += seg(e, 0, gp, 1) + seg(e, gp, ng, P.syn_R);
-        adj += seg(e, 0, gp, 4) + seg(e, gp, ng, P.adj_R * P.adj_W);
+        adj += seg_adj(e, 0, gp, 4, 1) + seg_adj(e, gp, ng, P.adj_R, P.adj_W);
         bat += seg(e, 0, ng, 1);
     }
     P.work[0] = all;
@@ -275,6 +289,22 @@ static void compute_work_live(Plan &P)
         }
         return w;
     };
+    auto seg_adj = [&](const int *e, const int *gl, int n, int R, int W) {
+        const AdjSplit sp = adj_split(n, R, W);
+        int64_t w = 0;
+        for (int b = 0; b < sp.q; ++b) {
+            int first, count;
+            adj_block(sp, n, W, b, first, count);
+            int ls = ENT_SKIP;
+            int64_t pairs = 0;
+            for (int i = first; i < first + count; ++i) {
+                ls = std::min(ls, e[gl[i]]);
+                pairs += std::min(64, np - 64 * gl[i]);
+            }
+            if (ls <= lmax) w += pairs * (lmax - ls + 1);
+        }
+        return w;
+    };
     const int *any = base + (size_t)GCLS_N * ng;
     const int nany = G.npol_any + G.nmain_any;
     int64_t w[5] = {0, 0, 0, 0, 0};
@@ -286,7 +316,8 @@ static void compute_work_live(Plan &P)
             const int npol = G.npol[c], nmain = G.nmain[c];
             const bool two = c == GCLS_BOTH;
             const int64_t s = seg(e, gl, npol, 1) + seg(e, gl + npol, nmain, two ? P.syn_R : P.syn_R1);
-            const int64_t a = seg(e, gl, npol, 4) + seg(e, gl + npol, nmain, two ? P.adj_R * P.adj_W : P.adj_R1 * P.adj_W1);
+            const int64_t a = seg_adj(e, gl, npol, 4, 1) + seg_adj(e, gl + npol, nmain, two ? P.adj_R : P.adj_R1,
+                                                                 two ? P.adj_W : P.adj_W1);
             w[c == GCLS_BOTH ? 0 : 1] += s;
             w[c == GCLS_BOTH ? 2 : 3] += a;
         }

@@ -23,8 +23,8 @@ import sys
 
 CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning.json")
 SYN = [(v, r) for v in (0, 1) for r in (1, 2, 4)]
-ADJ = [(1, 1, 8), (1, 2, 8), (1, 4, 8), (2, 2, 8), (2, 4, 8), (4, 2, 8), (4, 4, 8), (8, 1, 8), (8, 2, 8),
-       (2, 4, 4), (4, 2, 4), (4, 4, 4), (8, 1, 4), (2, 1, 8), (4, 1, 4), (4, 1, 8)]
+ADJ = [(r, 1, c) for c in (8, 4) for r in range(1, 9)] + \
+      [(1, 2, 8), (1, 4, 8), (2, 2, 8), (2, 4, 8), (4, 2, 8), (4, 4, 8), (8, 2, 8), (2, 4, 4), (4, 2, 4), (4, 4, 4)]
 
 
 BATCHED = [(sw, aw) for sw in (1, 2, 4, 8) for aw in (2, 4, 8)]

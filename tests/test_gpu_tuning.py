@@ -9,8 +9,8 @@ from oracle.geometry import healpix_rings
 pytestmark = pytest.mark.gpu
 
 SYN = [(v, r) for v in (0, 1) for r in (1, 2, 4)]
-ADJ = [(1, 1, 8), (1, 2, 8), (1, 4, 8), (2, 2, 8), (2, 4, 8), (4, 2, 8), (4, 4, 8), (8, 1, 8), (8, 2, 8),
-       (2, 4, 4), (4, 2, 4), (4, 4, 4), (8, 1, 4), (2, 1, 8), (4, 1, 4), (4, 1, 8)]
+ADJ = [(r, 1, c) for c in (8, 4) for r in range(1, 9)] + \
+      [(1, 2, 8), (1, 4, 8), (2, 2, 8), (2, 4, 8), (4, 2, 8), (4, 4, 8), (8, 2, 8), (2, 4, 4), (4, 2, 4), (4, 4, 4)]
 
 
 def rel(a, b):
@@ -80,4 +80,55 @@ def test_all_batched_shapes_match_oracle():
         p.set_tuning_batched(3, 4)
     with pytest.raises(Exception):
         p.set_tuning_batched(4, 1)
+    p.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
+def test_single_wave_shapes_uneven_split(prec, tol):
+    # Single-wave adjoint workgroups spread a list of n groups as ceil(n / R) workgroups of R and
+    # R - 1 groups.  At Nside 400 (800 ring pairs: 13 groups, the last of 32 pairs) the full list and
+    # an 11-group list of groups weighted on their south rings only leave workgroups of both sizes for
+    # every R from 2 to 8: the unweighted adjoint and the weighted apply against the oracle.
+    import torch
+    from paper_2606_06175_amd import Plan
+    nside, lmax = 400, 128
+    dev = torch.device("cuda", 0)
+    rings = healpix_rings(nside)
+    o = Oracle(lmax, rings)
+    npairs = 2 * nside
+    # weight on the south rings of pairs 74..799 and the north rings of pairs 770..799: groups 1..11
+    # are weighted on one side, group 12 on both, group 0 on neither
+    w_ring = np.zeros(rings.nrings, bool)
+    for p in range(74, npairs):
+        w_ring[rings.nrings - 1 - p] = True
+    w_ring[770:npairs] = True
+    cls = []
+    for g in range(13):
+        ps = range(64 * g, min(npairs, 64 * g + 64))
+        n = any(w_ring[p] for p in ps)
+        s = any(w_ring[rings.nrings - 1 - p] for p in ps if rings.nrings - 1 - p != p)
+        cls.append("both" if n and s else "south" if s else "north" if n else "none")
+    assert cls.count("south") == 11 and cls.count("both") == 1
+    mask = np.zeros(o.rings.npix, np.uint8)
+    for r in np.flatnonzero(w_ring):
+        mask[rings.ofs[r]:rings.ofs[r] + rings.nphi[r]] = 1
+    ninv = np.random.default_rng(21).uniform(5.0, 60.0, o.rings.npix)
+    h1, h2 = wl.random_maps(o.rings.npix, 22)
+    rE, rB = o.adjoint(h1, h2)
+    x = np.stack([wl.random_alm(lmax, 23, lmin=0), wl.random_alm(lmax, 24, lmin=0)])
+    ref = o.apply_H(x, o.weights(ninv, mask), 0.02)
+    p = Plan(nside, lmax, precision=prec, device=dev, tuned=False)
+    th1, th2 = torch.from_numpy(h1).to(dev), torch.from_numpy(h2).to(dev)
+    tn, tm = torch.from_numpy(ninv).to(dev), torch.from_numpy(mask).to(dev)
+    tx = [torch.from_numpy(a).to(dev) for a in x]
+    for r, w, c in [s for s in ADJ if s[1] == 1]:
+        print("single-wave adjoint rings", r, "chunk", c, flush=True)
+        p.set_tuning(1, 2, r, 1, c)
+        cE, cB = p.adjoint2(th1, th2)
+        assert rel(np.stack([cE.cpu().numpy(), cB.cpu().numpy()]), np.stack([rE, rB])) < tol, (r, c)
+        p.set_tuning(1, 2, 4, 1, 8)
+        p.set_tuning_one_sided(1, 2, r, 1, c)
+        yE, yB = p.apply_H(tn, tm, tx[0], tx[1], 0.02)
+        assert rel(np.stack([yE.cpu().numpy(), yB.cpu().numpy()]), ref) < tol, (r, c)
+        assert p.work_weighted()["adjoint_one"] > 0
     p.close()
