@@ -24,13 +24,25 @@ template <> struct CoefB<1> { using type = Coef32D; };
 // Entry states: stored in FP64 as mant * 2^(512 k).  FP32 kernels re-express them in their own unit.
 // ------------------------------------------------------------------------------------------------
 // i0, i1: 1 / c_l and 1 / c_{l-1} at the entry degree l for the scaled plain form (mu = lambda / c);
-// the difference form and the unscaled plain form pass 1.
+// the difference form and the unscaled plain form pass 1.  refl = +-1 gives the state of the
+// reflected ring (theta -> pi - theta) instead: with s = refl = (-1)^(l+m) at the entry degree l,
+// +2lambda_l(pi - theta) = s -2lambda_l(theta) and +2lambda_{l-1}(pi - theta) = -s -2lambda_{l-1}(theta),
+// and the same with the spins exchanged.
 template <typename T, int F>
 __device__ __forceinline__ void load_entry(const Ent64 *__restrict__ ent, const int *__restrict__ entk, int64_t idx,
-                                           T &c2, T &p2, T &cm, T &pm, int &k, double i0 = 1.0, double i1 = 1.0)
+                                           T &c2, T &p2, T &cm, T &pm, int &k, double i0 = 1.0, double i1 = 1.0,
+                                           int refl = 0)
 {
     Ent64 e = ent[idx];
     const int k64 = entk[idx];
+    if (refl != 0) {
+        const double sg = (double)refl;
+        const Ent64 n = e;
+        e.c2 = sg * n.cm;
+        e.cm = sg * n.c2;
+        e.p2 = -sg * n.pm;
+        e.pm = -sg * n.p2;
+    }
     if constexpr (F == 0) {
         e.c2 *= i0;
         e.cm *= i0;
@@ -348,7 +360,9 @@ __device__ __forceinline__ void xcd_map(int b, int nbm, int &m, int &blk)
 // and those of the south ring (through the reflection, with the parity sign) are
 //   S-(u0), S-(u1) and S+(u2), S+(u3):
 // a one-ring class runs the four FMAs of its ring only.  acc[c] holds S+(u_c), acc[4 + c] S-(u_c).
-template <typename T, int R, bool MASK, int CLS, typename In, typename X>
+// DIRECT: a one-ring class whose recurrence runs on that ring itself (the south ring at its own
+// cos(theta)): the four sums of the north-ring formula, S+(u0), S+(u1), S-(u2), S-(u3), in acc[0..3].
+template <typename T, int R, bool MASK, int CLS, bool DIRECT = false, typename In, typename X>
 __device__ __forceinline__ void syn_step(const In &in, const X (&x)[R], T (&c2)[R], T (&p2)[R], T (&cm)[R],
                                          T (&pm)[R], const int (&k)[R], T (&acc)[8][R])
 {
@@ -357,6 +371,14 @@ __device__ __forceinline__ void syn_step(const In &in, const X (&x)[R], T (&c2)[
         T v2 = c2[j], vm = cm[j];
         if (MASK) {
             if (k[j] != 0) v2 = vm = (T)0;
+        }
+        if constexpr (DIRECT) {
+            acc[0][j] = fma(v2, in.u0, acc[0][j]);
+            acc[1][j] = fma(v2, in.u1, acc[1][j]);
+            acc[2][j] = fma(vm, in.u2, acc[2][j]);
+            acc[3][j] = fma(vm, in.u3, acc[3][j]);
+            rstep(in, x[j], c2[j], p2[j], cm[j], pm[j]);
+            continue;
         }
         if (CLS != GCLS_SOUTH) {
             acc[0][j] = fma(v2, in.u0, acc[0][j]);
@@ -430,15 +452,17 @@ __device__ __forceinline__ bool rescale_restart(T (&c2)[R], T (&p2)[R], T (&cm)[
 
 // Start of a slot j whose group enters later than the wave (its values are zero until then).
 // ct: the m's row of the scaled table (1 / c_l for the entry of the scaled plain form)
-template <typename T, int R, int F>
+// REFL: the slots run on the reflected (south) ring of their pair, m the order.
+template <typename T, int R, int F, bool REFL = false>
 __device__ __forceinline__ void inject(int l, const int (&e)[R], const int (&pr)[R], const Ent64 *__restrict__ ent,
                                        const int *__restrict__ entk, int64_t row, int npairs, T (&c2)[R], T (&p2)[R],
-                                       T (&cm)[R], T (&pm)[R], int (&k)[R], const_as<Coef64S> *ct)
+                                       T (&cm)[R], T (&pm)[R], int (&k)[R], const_as<Coef64S> *ct, int m = 0)
 {
+    const int refl = REFL ? (((l + m) & 1) ? -1 : 1) : 0;
 #pragma unroll
     for (int j = 0; j < R; ++j)
         if (e[j] == l && pr[j] < npairs)
-            load_entry<T, F>(ent, entk, row + pr[j], c2[j], p2[j], cm[j], pm[j], k[j], ct[l].ic, ct[l - 1].ic);
+            load_entry<T, F>(ent, entk, row + pr[j], c2[j], p2[j], cm[j], pm[j], k[j], ct[l].ic, ct[l - 1].ic, refl);
 }
 
 template <int R> __device__ __forceinline__ bool pending(int l, int lmax, const int (&e)[R])
@@ -475,6 +499,9 @@ __global__ __launch_bounds__(256) void k_leg_synth(const SynRec<T> *__restrict__
     const Coef32D *cfd = coefd + base;
     const_as<Coef64S> *ct = uniform_ptr(cs64 + base);
     const SynSrc<T, F> src(rec, recu, cfd);
+    // one-ring classes of the plain form run on their own ring (the south class from reflected entry
+    // states at the south ring's cos(theta)) and need no split of the sums by the parity of l + m
+    constexpr bool DIRECT = CLS != GCLS_BOTH && F == 0, REFL = DIRECT && CLS == GCLS_SOUTH;
     auto rload = [&](int i) {
         if constexpr (F == 0) return rec[i];
         else return src.at(i);
@@ -504,9 +531,10 @@ __global__ __launch_bounds__(256) void k_leg_synth(const SynRec<T> *__restrict__
         c2[j] = p2[j] = cm[j] = pm[j] = (T)0;
         k[j] = 0;
         if (p < npairs) {
-            setpos(x[j], pair_z[p]);
+            setpos(x[j], REFL ? -pair_z[p] : pair_z[p]);
             if (e[j] == ls && ls <= lmax)
-                load_entry<T, F>(ent, entk, row + p, c2[j], p2[j], cm[j], pm[j], k[j], ct[ls].ic, ct[ls - 1].ic);
+                load_entry<T, F>(ent, entk, row + p, c2[j], p2[j], cm[j], pm[j], k[j], ct[ls].ic, ct[ls - 1].ic,
+                                 REFL ? (((ls + m) & 1) ? -1 : 1) : 0);
         }
         neg |= (k[j] < 0);
 #pragma unroll
@@ -521,11 +549,12 @@ __global__ __launch_bounds__(256) void k_leg_synth(const SynRec<T> *__restrict__
     constexpr int S = V == 0 ? 2 : 4;
     int l = __builtin_amdgcn_readfirstlane(ls <= lmax ? ls : lmax + 1);
     SynSrc<T, F> rp(rec + l, F ? recu + l : nullptr, cfd + l);
+    T(&accB)[8][R] = DIRECT ? acc0 : acc1;  // sums of the second step of a pair of steps
     auto a0 = rp.at(0), a1 = rp.at(1), b0 = a0, b1 = a1;
     for (; l + S - 1 <= lmax; l += S, rp.adv(S)) {
         if (pend) {
             // a slot enters at its group's entry degree (entries are l0 + 8q, trips start at ls + S q)
-            inject<T, R, F>(l, e, pr, ent, entk, row, npairs, c2, p2, cm, pm, k, ct);
+            inject<T, R, F, REFL>(l, e, pr, ent, entk, row, npairs, c2, p2, cm, pm, k, ct, m);
             pend = pending<R>(l, lmax, e);
             bool ng = false;
 #pragma unroll
@@ -535,15 +564,15 @@ __global__ __launch_bounds__(256) void k_leg_synth(const SynRec<T> *__restrict__
         if constexpr (S == 4) {
             b0 = rp.at(2);
             b1 = rp.at(3);
-            syn_step<T, R, false, CLS>(a0, x, c2, p2, cm, pm, k, acc0);
-            syn_step<T, R, false, CLS>(a1, x, c2, p2, cm, pm, k, acc1);
+            syn_step<T, R, false, CLS, DIRECT>(a0, x, c2, p2, cm, pm, k, acc0);
+            syn_step<T, R, false, CLS, DIRECT>(a1, x, c2, p2, cm, pm, k, accB);
             a0 = rp.at(4);
             a1 = rp.at(5);
-            syn_step<T, R, false, CLS>(b0, x, c2, p2, cm, pm, k, acc0);
-            syn_step<T, R, false, CLS>(b1, x, c2, p2, cm, pm, k, acc1);
+            syn_step<T, R, false, CLS, DIRECT>(b0, x, c2, p2, cm, pm, k, acc0);
+            syn_step<T, R, false, CLS, DIRECT>(b1, x, c2, p2, cm, pm, k, accB);
         } else {
-            syn_step<T, R, false, CLS>(a0, x, c2, p2, cm, pm, k, acc0);
-            syn_step<T, R, false, CLS>(a1, x, c2, p2, cm, pm, k, acc1);
+            syn_step<T, R, false, CLS, DIRECT>(a0, x, c2, p2, cm, pm, k, acc0);
+            syn_step<T, R, false, CLS, DIRECT>(a1, x, c2, p2, cm, pm, k, accB);
             a0 = rp.at(2);
             a1 = rp.at(3);
         }
@@ -551,9 +580,9 @@ __global__ __launch_bounds__(256) void k_leg_synth(const SynRec<T> *__restrict__
     }
     // tail (fewer than S steps)
     for (int t = 0; l <= lmax; ++l, ++t) {
-        if (pend) inject<T, R, F>(l, e, pr, ent, entk, row, npairs, c2, p2, cm, pm, k, ct);
-        if (t & 1) syn_step<T, R, false, CLS>(rload(l), x, c2, p2, cm, pm, k, acc1);
-        else syn_step<T, R, false, CLS>(rload(l), x, c2, p2, cm, pm, k, acc0);
+        if (pend) inject<T, R, F, REFL>(l, e, pr, ent, entk, row, npairs, c2, p2, cm, pm, k, ct, m);
+        if (t & 1) syn_step<T, R, false, CLS, DIRECT>(rload(l), x, c2, p2, cm, pm, k, accB);
+        else syn_step<T, R, false, CLS, DIRECT>(rload(l), x, c2, p2, cm, pm, k, acc0);
     }
     // lanes that never left the scaled range contribute nothing
 #pragma unroll
@@ -568,6 +597,15 @@ __global__ __launch_bounds__(256) void k_leg_synth(const SynRec<T> *__restrict__
 #pragma unroll
     for (int j = 0; j < R; ++j) {
         if (pr[j] >= npairs) continue;
+        if constexpr (DIRECT) {
+            // F(m) = -(S+(u0), S+(u1)), F(-m) part = -(S-(u2), S-(u3)) on the ring the slot ran on
+            const int r = REFL ? nrings - 1 - pr[j] : pr[j];
+            if (REFL && r == pr[j]) continue;  // the equator ring belongs to the north side
+            cplx<T> *f = Fb + ((int64_t)r * (lmax + 1) + m) * 2;
+            f[0] = mk<T>(-acc0[0][j], -acc0[1][j]);
+            f[1] = mk<T>(-acc0[2][j], -acc0[3][j]);
+            continue;
+        }
         T E[8], O[8];
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
