@@ -167,6 +167,9 @@ struct Plan {
     // every ring and group (transforms without weights), and those of the current weights: the
     // lists of the weighted set are rebuilt at every weight set-up (setup_weights)
     RingSet rs_all, rs_live;
+    // the weighted rings of rs_live by the class of their 64-pair group: [0] groups weighted on both
+    // sides, [1] on one side (each kind's list holds the first class's rings, then the second's)
+    RingSet rs_cls[2];
     GroupSet gs_all, gs_live;
     std::vector<int> h_order[RING_KINDS];  // host copies of the rings of every kind
     int *d_gl_all = nullptr;      // [ng64] 0, 1, .., ng64 - 1
@@ -324,6 +327,9 @@ void set_error(const std::string &msg);
 akra_status hip_fail(hipError_t e, const char *what);
 
 // ---- kernel launchers (akra_kernels.hip) -------------------------------------------------------
+// the weighted apply's Legendre and ring stages (single right-hand side, W of the plan's weights) as
+// one chain per class of ring groups on two streams (requires the side stream and both classes)
+void launch_weighted_chains(Plan &P, bool fp32, const double *W);
 // prologue: records {a, b, g, 0, K_l x_E, K_l x_B} per (l, m) in the transform precision (Im(a_l0) dropped)
 void launch_prologue(Plan &P, bool fp32, const double *xE, const double *xB, const double *kern, int nrhs);
 // entry states of the recurrence from the seeds (plan build)

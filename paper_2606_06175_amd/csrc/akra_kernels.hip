@@ -2029,7 +2029,8 @@ void launch_cg_beta_sum(Plan &P, const double *red, double *scal, double precond
 // lists (see Plan::d_order_r)
 template <typename T, int MODE>
 static void ring_launch_t(Plan &P, const RingSet &RS, const double *g1, const double *g2, double *o1, double *o2,
-                          const double *W, double *o3, const uint8_t *mask, const double *cdev, int nrhs)
+                          const double *W, double *o3, const uint8_t *mask, const double *cdev, int nrhs,
+                          bool split = true)
 {
     const int64_t fg_stride = (int64_t)P.nrings * (P.lmax + 1) * 2;
     const void *tw = std::is_same<T, double>::value ? P.d_tw64 : P.d_tw32;
@@ -2068,6 +2069,7 @@ static void ring_launch_t(Plan &P, const RingSet &RS, const double *g1, const do
             (const cplx<T> *)tw, P.twn, P.lmax, P.omega, o3, mask, cdev, bhr);
     };
     // the kinds touch disjoint rings: the largest direct kind on the plan stream, the others beside it
+    // (split false: all on the plan stream)
     auto side = [&]() {
         reg(k_ring16<T, MODE, 13, 2>, 5, 8192);
         reg(k_ring16<T, MODE, 13, 1>, 3, 8192);
@@ -2078,7 +2080,12 @@ static void ring_launch_t(Plan &P, const RingSet &RS, const double *g1, const do
         reg(k_ring16<T, MODE, 12, 2>, 4, 4096);
         reg(k_ring16<T, MODE, 12, 1>, 2, 4096);
     };
-    fork_join(P, side, main);
+    if (split) {
+        fork_join(P, side, main);
+    } else {
+        side();
+        main();
+    }
 }
 
 // Spectra of the Bluestein chirps, one per distinct sub-transform length L (plan creation):
@@ -2144,6 +2151,45 @@ void launch_ring(Plan &P, bool fp32, int mode, const double *g1, const double *g
         else if (mode == 1) ring_launch_t<double, 1>(P, RS, g1, g2, o1, o2, W, nullptr, nullptr, nullptr, nrhs);
         else ring_launch_t<double, 2>(P, RS, g1, g2, o1, o2, W, nullptr, nullptr, nullptr, nrhs);
     }
+}
+
+// Two chains, one per class of ring groups, each running synthesis, ring stage and adjoint of its
+// class: the groups weighted on both sides on the side stream, those weighted on one side on the
+// plan stream.  A chain's rings are those of its groups, so the chains write F and G of disjoint
+// rings and partial sums of disjoint ring blocks; a chain's ring stage needs only its own
+// synthesis, and its adjoint only its own rings, so no stage waits for the other class.
+void launch_weighted_chains(Plan &P, bool fp32, const double *W)
+{
+    const GroupSet &G = P.gs_live;
+    const uint8_t *lv = P.d_ring_live;
+    const int nrb = adj_blocks_total(P, true);
+    const int rb1 = adj_blocks(P, GCLS_BOTH, G.npol[GCLS_BOTH], G.nmain[GCLS_BOTH]);
+    const int rb2 = rb1 + adj_blocks(P, GCLS_NORTH, G.npol[GCLS_NORTH], G.nmain[GCLS_NORTH]);
+    auto n = [&](int c) { return G.npol[c] + G.nmain[c]; };
+    auto ring = [&](const RingSet &RS) {
+        if (fp32) ring_launch_t<float, 2>(P, RS, nullptr, nullptr, nullptr, nullptr, W, nullptr, nullptr, nullptr, 1, false);
+        else ring_launch_t<double, 2>(P, RS, nullptr, nullptr, nullptr, nullptr, W, nullptr, nullptr, nullptr, 1, false);
+    };
+    auto two = [&]() {
+        leg_synth_cls<GCLS_BOTH>(P, fp32, 1, G.list[GCLS_BOTH], G.npol[GCLS_BOTH], G.nmain[GCLS_BOTH]);
+        ring(P.rs_cls[0]);
+        leg_adj_cls<GCLS_BOTH>(P, fp32, 0, G.list[GCLS_BOTH], G.npol[GCLS_BOTH], G.nmain[GCLS_BOTH], lv, 0, nrb);
+    };
+    auto one = [&]() {
+        if (n(GCLS_NORTH))
+            leg_synth_cls<GCLS_NORTH>(P, fp32, 1, G.list[GCLS_NORTH], G.npol[GCLS_NORTH], G.nmain[GCLS_NORTH]);
+        if (n(GCLS_SOUTH))
+            leg_synth_cls<GCLS_SOUTH>(P, fp32, 1, G.list[GCLS_SOUTH], G.npol[GCLS_SOUTH], G.nmain[GCLS_SOUTH]);
+        ring(P.rs_cls[1]);
+        if (n(GCLS_NORTH))
+            leg_adj_cls<GCLS_NORTH>(P, fp32, 0, G.list[GCLS_NORTH], G.npol[GCLS_NORTH], G.nmain[GCLS_NORTH], lv,
+                                    rb1, nrb);
+        if (n(GCLS_SOUTH))
+            leg_adj_cls<GCLS_SOUTH>(P, fp32, 0, G.list[GCLS_SOUTH], G.npol[GCLS_SOUTH], G.nmain[GCLS_SOUTH], lv,
+                                    rb2, nrb);
+    };
+    fork_join(P, two, one);
+    P.nrb_cur = nrb;
 }
 
 void launch_ring_grad(Plan &P, const double *g1, const double *g2, double *q1, double *q2, const double *W,

@@ -337,16 +337,8 @@ static akra_status build_live_lists(Plan &P)
         return AKRA_OK;
     P.h_live_prev.assign(flag, flag + P.nrings);
     int *stage = (int *)(P.h_live + (P.nrings + 15) / 16 * 16);
-    for (int k = 0; k < RING_KINDS; ++k) {
-        int *o = stage + (size_t)k * P.nrings;
-        int n = 0;
-        for (int r : P.h_order[k])
-            if (flag[r]) o[n++] = r;
-        P.rs_live.order[k] = P.d_live_lists + (size_t)k * P.nrings;
-        P.rs_live.n[k] = n;
-    }
-    int *gbase = stage + (size_t)RING_KINDS * P.nrings;
-    int cnt[GCLS_N + 1] = {0, 0, 0, 0}, pol[GCLS_N + 1] = {0, 0, 0, 0};
+    // class of every 64-pair group by the rings of its pairs that carry weight (-1: none)
+    std::vector<int> gcls(P.ng64, -1);
     for (int g = 0; g < P.ng64; ++g) {
         bool n = false, s = false;
         for (int p = 64 * g; p < std::min(P.npairs, 64 * g + 64); ++p) {
@@ -354,8 +346,32 @@ static akra_status build_live_lists(Plan &P)
             n = n || flag[p];
             s = s || (rs != p && flag[rs]);
         }
-        if (!n && !s) continue;
-        const int c = (n && s) ? GCLS_BOTH : n ? GCLS_NORTH : GCLS_SOUTH;
+        if (n || s) gcls[g] = (n && s) ? GCLS_BOTH : n ? GCLS_NORTH : GCLS_SOUTH;
+    }
+    // ring lists per kind: the weighted rings of two-sided groups, then those of one-sided groups
+    for (int k = 0; k < RING_KINDS; ++k) {
+        int *o = stage + (size_t)k * P.nrings;
+        int n = 0, n2 = 0;
+        for (int two = 1; two >= 0; --two) {
+            for (int r : P.h_order[k]) {
+                const int p = std::min(r, P.nrings - 1 - r);
+                if (flag[r] && (gcls[p / 64] == GCLS_BOTH) == (two == 1)) o[n++] = r;
+            }
+            if (two) n2 = n;
+        }
+        int *d = P.d_live_lists + (size_t)k * P.nrings;
+        P.rs_live.order[k] = d;
+        P.rs_live.n[k] = n;
+        P.rs_cls[0].order[k] = d;
+        P.rs_cls[0].n[k] = n2;
+        P.rs_cls[1].order[k] = d + n2;
+        P.rs_cls[1].n[k] = n - n2;
+    }
+    int *gbase = stage + (size_t)RING_KINDS * P.nrings;
+    int cnt[GCLS_N + 1] = {0, 0, 0, 0}, pol[GCLS_N + 1] = {0, 0, 0, 0};
+    for (int g = 0; g < P.ng64; ++g) {
+        if (gcls[g] < 0) continue;
+        const int c = gcls[g];
         for (int cc : {c, (int)GCLS_N}) {
             gbase[(size_t)cc * P.ng64 + cnt[cc]++] = g;
             if (g < P.polar_groups) pol[cc]++;
@@ -624,6 +640,7 @@ static akra_status create(int nside, int lmax, int nrhs, int prec, void *stream,
         A.nmain[GCLS_BOTH] = A.nmain_any = P->ng64 - P->polar_groups;
         // until a weight set-up, the weighted sets are the full ones
         P->rs_live = P->rs_all;
+        P->rs_cls[0] = P->rs_all;  // every group counts as two-sided
         P->gs_live = P->gs_all;
         AK_TRY(alloc((void **)&P->d_live_lists, live_list_ints(*P) * sizeof(int), *P));
         AK_TRY(alloc((void **)&P->d_ring_live, (size_t)P->nrings, *P));
@@ -947,6 +964,15 @@ static akra_status apply_H_timed(Plan &P, bool fp32, const double *kern_dev, dou
     stage_mark(P, 0, true);
     launch_prologue(P, fp32, xE, xB, kern_dev, 1);
     stage_mark(P, 0, false);
+    const GroupSet &G = P.gs_live;
+    const bool two = G.npol[GCLS_BOTH] + G.nmain[GCLS_BOTH] > 0,
+               one = G.npol[GCLS_NORTH] + G.nmain[GCLS_NORTH] + G.npol[GCLS_SOUTH] + G.nmain[GCLS_SOUTH] > 0;
+    if (!P.timing && P.skip_rings && P.side_stream && two && one) {
+        // untimed: one chain per class of ring groups (stage times need the staged order below)
+        launch_weighted_chains(P, fp32, P.d_W + (int64_t)rhs * P.npix);
+        launch_epilogue(P, fp32, kern_dev, lam, xE, xB, yE, yB, dot_red);
+        return check_launch("apply_H");
+    }
     stage_mark(P, 1, true);
     launch_leg_synth(P, fp32, 1, true);
     stage_mark(P, 1, false);

@@ -179,3 +179,28 @@ def test_solve_skip_matches_full(torch_dev, prec):
         out.append((x, info["iters"]))
     assert abs(out[0][1] - out[1][1]) <= 2
     assert rel(out[0][0], out[1][0]) < 1e-8
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_class_chains_match_staged_apply(torch_dev, prec):
+    # untimed weighted applies run one chain per class of ring groups on two streams, timed applies
+    # run the stages in order; the kernels and their inputs are the same, so H x agrees bit for bit,
+    # and both agree with the oracle
+    torch, dev = torch_dev
+    nside, lmax = 100, 400
+    o = Oracle(lmax, healpix_rings(nside))
+    mask, ninv = weights(nside, "south_cap", 13)
+    x = np.stack([wl.random_alm(lmax, 14, lmin=0), wl.random_alm(lmax, 15, lmin=0)])
+    p = _plan(nside, lmax, prec)
+    tn, tm = torch.from_numpy(ninv).to(dev), torch.from_numpy(mask).to(dev)
+    tx = [torch.from_numpy(a).to(dev) for a in x]
+    out = []
+    for timed in (False, True, False):
+        p.set_timing(timed)
+        yE, yB = p.apply_H(tn, tm, tx[0], tx[1], 0.02)
+        out.append(np.stack([yE.cpu().numpy(), yB.cpu().numpy()]))
+    p.set_timing(False)
+    ww = p.work_weighted()
+    assert ww["synth_two"] > 0 and ww["synth_one"] > 0, ww
+    assert np.array_equal(out[0], out[1]) and np.array_equal(out[0], out[2])
+    check_alm(out[0], o.apply_H(x, o.weights(ninv, mask), 0.02), lmax, TOL[prec])
