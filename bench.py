@@ -51,11 +51,11 @@ def live_ring_bytes(nside, lmax, w, fg_bytes):
 # the kernel sources and launch shapes they were taken with (the SHA-256 of the Legendre sources and
 # the plan's two- and one-sided shapes are checked at run time).
 TRAFFIC = {
-    # profiles/k_leg_adj_nside2048_lmax4096_fp64.md: two-sided k_leg_adj<double, 4, 1, 4, 0, 0>
-    # FETCH 4.8017e5 KiB x 2.0 + WRITE 8.5475e5 KiB, one-sided k_leg_adj<double, 8, 1, 8, 0, 2>
-    # FETCH 5.8220e5 KiB x 2.0 + WRITE 1.0903e6 KiB
-    "leg_adj": {"bytes": 4.167e9, "workload": (2048, 4096), "shapes": ((0, 1, 4, 1, 4), (1, 2, 8, 1, 8)),
-                "sources_sha256": "3fefb0c5a3eb180bd2db44d6b2348ea08d230d231bf279c0574168699ea55b4e"},
+    # profiles/k_leg_adj_nside2048_lmax4096_fp64.md: two-sided k_leg_adj<double, 4, 1, 8, 0, 0>
+    # FETCH 6.1298e5 KiB x 2.0 + WRITE 8.3224e5 KiB, one-sided k_leg_adj<double, 7, 1, 8, 0, 2>
+    # FETCH 5.8951e5 KiB x 2.0 + WRITE 9.8546e5 KiB
+    "leg_adj": {"bytes": 4.324e9, "workload": (2048, 4096), "shapes": ((0, 1, 5, 1, 8), (0, 2, 8, 1, 8)),
+                "sources_sha256": "fae7696407d471e9ff8841cabd1a2755f55cf6ea99827c504f447fee78049cde"},
 }
 LEG_SOURCES = ("akra_leg.h", "akra_leg_both.hip", "akra_leg_north.hip", "akra_leg_south.hip", "akra_kernels.hip")
 
@@ -689,6 +689,7 @@ def main():
     fg_bytes = 32 if args.precision == "fp64" else 16  # (Q, U) complex entry of F or G per (ring, m)
     ring_bytes, n_live = live_ring_bytes(nside, lmax, cfg["mask"] * cfg["ninv"][0], fg_bytes)
     assert n_live == ww["live_rings"], (n_live, ww["live_rings"])
+    roofline["evaluated_triples"] = ww  # per launch of each class (akra_plan_work_weighted)
     roofline["ring_algorithmic_bytes"] = ring_bytes
     roofline["ring_rings_with_weight"] = n_live
     roofline["ring_hbm_GBs"] = ring_bytes / (stages["ring"]["ms_avg"] * 1e-3) / 1e9
