@@ -690,6 +690,10 @@ def main():
     ring_bytes, n_live = live_ring_bytes(nside, lmax, cfg["mask"] * cfg["ninv"][0], fg_bytes)
     assert n_live == ww["live_rings"], (n_live, ww["live_rings"])
     roofline["evaluated_triples"] = ww  # per launch of each class (akra_plan_work_weighted)
+    # the sustained plain FMA rate of this device under load (akra_fma_rate), beside the published peak
+    from paper_2606_06175_amd.akra import fma_rate
+    roofline["fma_ceiling_TFLOPs"] = fma_rate(args.precision)
+    roofline["frac_of_fma_ceiling"] = roofline["achieved"] / roofline["fma_ceiling_TFLOPs"]
     roofline["ring_algorithmic_bytes"] = ring_bytes
     roofline["ring_rings_with_weight"] = n_live
     roofline["ring_hbm_GBs"] = ring_bytes / (stages["ring"]["ms_avg"] * 1e-3) / 1e9

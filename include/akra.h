@@ -330,6 +330,16 @@ akra_status akra_plan_set_skip_unweighted(akra_plan plan, int on);
 akra_status akra_plan_work_weighted(akra_plan plan, int64_t *out6);
 akra_status akra_plan_set_timing(akra_plan plan, int on);
 /*
+ * Sustained fused multiply-add rate of the current device in TFLOP/s, written to *tflops (HOST):
+ * 16 independent FMA chains per thread, 8 waves per SIMD on every compute unit, plain (not packed)
+ * FP32 or FP64 by precision (AKRA_FP32 / AKRA_FP64), the fastest of 12 back-to-back launches of a
+ * few ms each, timed with HIP events on a private stream.  It is the ceiling an ALU-bound kernel meets at the clock the device holds
+ * under that load, beside the published peak.  Allocates and frees a scratch buffer of 8 B per
+ * thread of the grid; synchronises its own stream only.  Errors: AKRA_ERR_ARG (null output,
+ * unknown precision), AKRA_ERR_HIP.
+ */
+akra_status akra_fma_rate(int precision, double *tflops);
+/*
  * Ring-stage kernel choice of plans created afterwards (process-wide, not thread-safe against
  * concurrent akra_plan_create).  A ring whose length N is not a power of two is transformed whole by
  * Bluestein when its convolution length (the power of two M >= 2N - 1) is at most maxm, else as two

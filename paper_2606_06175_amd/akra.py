@@ -82,6 +82,7 @@ def lib():
     L.akra_plan_set_tuning_one_sided.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                                  ctypes.c_int]
     L.akra_plan_get_tuning_one_sided.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
+    L.akra_fma_rate.argtypes = [ctypes.c_int, dp]
     L.akra_plan_set_tuning_batched.argtypes = [vp, ctypes.c_int, ctypes.c_int]
     L.akra_plan_get_tuning_batched.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
     L.akra_plan_work.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
@@ -123,7 +124,7 @@ def lib():
               "akra_plan_stage_times", "akra_plan_set_tuning", "akra_plan_get_tuning", "akra_plan_work",
               "akra_plan_set_tuning_batched", "akra_plan_get_tuning_batched",
               "akra_plan_work_batched", "akra_plan_work_weighted", "akra_plan_set_skip_unweighted",
-              "akra_plan_set_tuning_one_sided", "akra_plan_get_tuning_one_sided",
+              "akra_plan_set_tuning_one_sided", "akra_plan_get_tuning_one_sided", "akra_fma_rate",
               "akra_cg_solve_vjp", "akra_cg_solve_cond_b", "akra_set_ring_whole_maxm", "akra_set_ring_register_engine", "akra_unmasked_index",
               "akra_shuffle_shear", "akra_alm_spectra", "akra_alm_spectra_noalloc", "akra_noise_work_size", "akra_noise_spectra", "akra_ang2pix",
               "akra_pixelize_work_size", "akra_pixelize", "akra_flat_plan_create", "akra_flat_synth",
@@ -142,6 +143,13 @@ def _check(st):
 def set_ring_whole_maxm(maxm):
     """Ring-stage kernel choice of plans created afterwards (see akra_set_ring_whole_maxm)."""
     _check(lib().akra_set_ring_whole_maxm(int(maxm)))
+
+
+def fma_rate(precision="fp64"):
+    """Sustained plain FMA rate of the current device in TFLOP/s (akra_fma_rate)."""
+    v = ctypes.c_double()
+    _check(lib().akra_fma_rate(PRECISIONS[precision], ctypes.byref(v)))
+    return v.value
 
 
 def set_ring_register_engine(on):

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libakra.so")
 LIB_SAN = os.path.join(HERE, "libakra_san.so")
-SOURCES = ["akra_kernels.hip", "akra_leg_both.hip", "akra_leg_south.hip", "akra_leg_north.hip", "akra_plan.hip",
+SOURCES = ["akra_probe.hip", "akra_kernels.hip", "akra_leg_both.hip", "akra_leg_south.hip", "akra_leg_north.hip", "akra_plan.hip",
            "akra_spectra.hip", "akra_pixel.hip", "akra_flat.hip"]
 # Packed FP32 VALU forms are disabled for every HIP translation unit.
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-Wall",

@@ -107,3 +107,10 @@ def test_noalloc_spectra_rejects_bad_arguments_before_any_hip_call(L):
     pairs = (ctypes.c_int32 * 2)(0, 1)
     assert L.akra_alm_spectra_noalloc(8, x, 1, x, 1, pairs, 1, x, None) == akra.AKRA_ERR_ARG
     assert "out of range" in L.akra_last_error().decode()
+
+
+def test_fma_rate_rejects_bad_arguments_before_any_hip_call(L):
+    v = ctypes.c_double()
+    assert L.akra_fma_rate(2, ctypes.byref(v)) == akra.AKRA_ERR_ARG
+    assert "precision" in L.akra_last_error().decode()
+    assert L.akra_fma_rate(0, None) == akra.AKRA_ERR_ARG
