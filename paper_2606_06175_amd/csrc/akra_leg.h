@@ -679,6 +679,12 @@ template <typename T, int R, int CLS = GCLS_BOTH> struct AdjWaves {
     static constexpr bool two = CLS == GCLS_BOTH, fp64 = std::is_same<T, double>::value;
     static constexpr int value = R > 4 ? (two ? 1 : 2) : (fp64 && two) ? 3 : 4;
 };
+// Column reads the reduction of a chunk issues before it waits for them: each batch is one LDS
+// round trip.  The one-sided FP64 forms with 5 to 7 pairs per lane run at two waves per SIMD with
+// registers to spare for 16 values; the others keep 8.
+template <typename T, int R, int CLS> struct AdjBatch {
+    static constexpr int value = (std::is_same<T, double>::value && CLS != GCLS_BOTH && R >= 5 && R <= 7) ? 16 : 8;
+};
 // LDS hand-over between the lanes of a workgroup.  A single-wave workgroup needs no s_barrier: the
 // LDS unit executes one wave's instructions in order, so a fence that keeps the compiler from moving
 // LDS accesses across it suffices, and no full wait for outstanding LDS operations is forced.
@@ -852,8 +858,8 @@ __device__ __forceinline__ void adj_body(T *__restrict__ red, const cplx<T> *__r
         // column o (wave q / 64, lane q % 64) at compile-time offsets from its column base, all
         // reads first, adds them in four independent partial sums, then sums over the G adjacent
         // threads sharing the output with DPP lane moves
-        // (in batches of 8 reads, which bounds the registers they hold)
-        constexpr int NR = NT / G, BR = NR < 8 ? NR : 8;
+        // (in batches of AdjBatch reads, which bounds the registers they hold)
+        constexpr int NR = NT / G, BR = NR < AdjBatch<T, R, CLS>::value ? NR : AdjBatch<T, R, CLS>::value;
         static_assert(NR >= 4 && NR % BR == 0, "four partial sums");
         T ps[4];
 #pragma unroll
