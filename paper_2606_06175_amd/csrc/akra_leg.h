@@ -562,13 +562,22 @@ __global__ __launch_bounds__(256) void k_leg_synth(const SynRec<T> *__restrict__
             ramp = ramp || wave_any(ng);
         }
         if constexpr (S == 4) {
+            // Scalar loads return out of order, so the wait before a record's first use covers
+            // every load then in flight: each pair's loads are issued after the first step of the
+            // pair before it (the scheduling barriers keep them there) and have that pair's second
+            // step to arrive.
+            syn_step<T, R, false, CLS, DIRECT>(a0, x, c2, p2, cm, pm, k, acc0);
+            __builtin_amdgcn_sched_barrier(0);
             b0 = rp.at(2);
             b1 = rp.at(3);
-            syn_step<T, R, false, CLS, DIRECT>(a0, x, c2, p2, cm, pm, k, acc0);
+            __builtin_amdgcn_sched_barrier(0);
             syn_step<T, R, false, CLS, DIRECT>(a1, x, c2, p2, cm, pm, k, accB);
+            __builtin_amdgcn_sched_barrier(0);
+            syn_step<T, R, false, CLS, DIRECT>(b0, x, c2, p2, cm, pm, k, acc0);
+            __builtin_amdgcn_sched_barrier(0);
             a0 = rp.at(4);
             a1 = rp.at(5);
-            syn_step<T, R, false, CLS, DIRECT>(b0, x, c2, p2, cm, pm, k, acc0);
+            __builtin_amdgcn_sched_barrier(0);
             syn_step<T, R, false, CLS, DIRECT>(b1, x, c2, p2, cm, pm, k, accB);
         } else {
             syn_step<T, R, false, CLS, DIRECT>(a0, x, c2, p2, cm, pm, k, acc0);
