@@ -109,17 +109,26 @@ def _time_stages(plan, stages, steps):
     return sum(st[s][0] / max(st[s][1], 1) for s in stages)
 
 
+def pick_synth(syn_sweep, tol=0.01):
+    """The synthesis shape of a sweep {"v,r": ms}: among the shapes within tol of the fastest, the
+    one with the fewest ring pairs per lane (then the lower variant).  The tuning masks are not the
+    user's footprint: fewer pairs per lane keep the entry-degree spread of a wave small on any
+    footprint, so near-ties go to them."""
+    best = min(syn_sweep.values())
+    near = [tuple(map(int, k.split(","))) for k, t in syn_sweep.items() if t <= (1 + tol) * best]
+    v, r = min(near, key=lambda vr: (vr[1], vr[0]))
+    return (v, r), syn_sweep["%d,%d" % (v, r)]
+
+
 def _sweep(plan, setter, base_syn, base_adj, steps, log, tag):
     from .akra import AkraError
     res = {"syn": {}, "adj": {}}
-    best_syn, best_t = base_syn, float("inf")
     for v, r in SYN:
         setter(v, r, *base_adj)
         t = _time_stage(plan, "leg_synth", steps)
         res["syn"]["%d,%d" % (v, r)] = t
         log("  %s synth variant %d rings/lane %d: %.3f ms" % (tag, v, r, t))
-        if t < best_t:
-            best_syn, best_t = (v, r), t
+    best_syn, best_t = pick_synth(res["syn"])
     best_adj, best_ta = base_adj, float("inf")
     for r, w, c in ADJ:
         try:
