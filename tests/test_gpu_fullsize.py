@@ -118,6 +118,29 @@ def test_apply_H_symmetric_and_fp32_agrees(big):
         assert rel(a, b) < 1e-5
 
 
+def test_weighted_chains_match_full_transforms(big):
+    # On the benchmark footprint the weighted apply (rings and groups without weight skipped, one
+    # chain per class of ring groups on two streams) equals the apply over every ring and group,
+    # whose transforms the sampled tests above check against the oracle, up to the adjoint's
+    # rounding order.
+    torch, dev = big["torch"], big["dev"]
+    cfg = wl.make_config("C3", nside=NSIDE, lmax=LMAX)
+    mask = torch.from_numpy(cfg["mask"]).to(dev)
+    ninv = torch.from_numpy(cfg["ninv"][0]).to(dev)
+    x = [torch.from_numpy(a).to(dev) for a in (big["aE"], big["aB"])]
+    p = _plan("fp64")
+    yE, yB = p.apply_H(ninv, mask, x[0], x[1], 0.01)
+    ww = p.work_weighted()
+    print("weighted work", ww, flush=True)
+    assert ww["synth_two"] > 0 and ww["synth_one"] > 0 and ww["live_rings"] < big["rings"].nrings
+    p.set_skip_unweighted(False)
+    fE, fB = p.apply_H(ninv, mask, x[0], x[1], 0.01)
+    e = rel(torch.stack([yE, yB]).cpu().numpy(), torch.stack([fE, fB]).cpu().numpy())
+    print("weighted against full transforms: %.3e" % e, flush=True)
+    assert e < 1e-13
+    p.close()
+
+
 def test_spectra_and_shuffle_full_size(big):
     # spectra of two coefficient sets at sampled degrees (tile edges, lmax) and the unmasked list and
     # one shuffle of a seeded f_sky = 0.1 mask, bit for bit, at the benchmark size
