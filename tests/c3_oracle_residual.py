@@ -13,7 +13,7 @@ the oracle, gamma_obs and x, are the arrays the GPU used and returned.  One orac
 takes minutes on the host cores, too long for the test suite, so this is a script; it prints its
 progress per block of rings and writes its result as JSON.
 
-    python tests/c3_oracle_residual.py [--out gpurun_out/c3_oracle_residual.json] [--chunks 16]
+    python tests/c3_oracle_residual.py [--out c3_oracle_residual.json] [--chunks 16]
 """
 import argparse
 import json
@@ -130,7 +130,7 @@ def oracle_residuals(d, nchunk):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--out", default=os.path.join("gpurun_out", "c3_oracle_residual.json"))
+    ap.add_argument("--out", default="c3_oracle_residual.json")
     ap.add_argument("--chunks", type=int, default=16)
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--maxiter", type=int, default=3000)
