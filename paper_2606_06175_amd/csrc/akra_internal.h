@@ -250,6 +250,7 @@ struct Plan {
     // to the plan stream with events, so that one launch fills the other's tail
     hipStream_t side_stream = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    bool in_fork = false;  // inside a fork_join: a nested one runs its halves in order
     hipGraphExec_t cg_graph = nullptr;
     double cg_graph_key[ITER_KEY_N] = {};
     // the lockstep iteration of the batched solve, keyed by its by-value arguments and active set
@@ -302,15 +303,17 @@ struct StallWatch {
 
 // Runs side() with the plan's launches going to the side stream and main() on the plan stream,
 // the side stream forked from the plan stream before and joined to it after (stream-ordered, and
-// captured the same way into a recorded graph).  Without a side stream both run on the plan stream.
-// A failing event call leaves its error for the launch check that follows every stage.
+// captured the same way into a recorded graph).  Without a side stream, or nested inside another
+// fork_join, both run in order on the current stream.  A failing event call leaves its error for
+// the launch check that follows every stage.
 template <class A, class B> void fork_join(Plan &P, A &&side, B &&main)
 {
-    if (!P.side_stream) {
+    if (!P.side_stream || P.in_fork) {
         side();
         main();
         return;
     }
+    P.in_fork = true;
     (void)hipEventRecord(P.ev_fork, P.stream);
     (void)hipStreamWaitEvent(P.side_stream, P.ev_fork, 0);
     const hipStream_t s = P.stream;
@@ -320,6 +323,7 @@ template <class A, class B> void fork_join(Plan &P, A &&side, B &&main)
     main();
     (void)hipEventRecord(P.ev_join, P.side_stream);
     (void)hipStreamWaitEvent(P.stream, P.ev_join, 0);
+    P.in_fork = false;
 }
 
 // error handling

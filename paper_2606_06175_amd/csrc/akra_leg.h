@@ -996,9 +996,18 @@ void leg_synth_cls(Plan &P, bool fp32, int nrhs, const int *list, int npol, int 
     const int64_t fg_stride = (int64_t)P.nrings * (P.lmax + 1) * 2;
     const int V = syn_V_of(P, CLS);
     if (fp32) {
-        syn_launch<float, 1, 1, 1, CLS>(P, nrhs, fg_stride, list, npol);
-        if (V == 0) syn_dispatch_r<float, 0, CLS>(P, nrhs, fg_stride, list + npol, nmain);
-        else syn_dispatch_r<float, 1, CLS>(P, nrhs, fg_stride, list + npol, nmain);
+        // the near-polar and the other groups write F of disjoint rings: the near-polar launch (few
+        // waves, long recurrences) beside the main one
+        auto pol = [&]() { syn_launch<float, 1, 1, 1, CLS>(P, nrhs, fg_stride, list, npol); };
+        auto rest = [&]() {
+            if (V == 0) syn_dispatch_r<float, 0, CLS>(P, nrhs, fg_stride, list + npol, nmain);
+            else syn_dispatch_r<float, 1, CLS>(P, nrhs, fg_stride, list + npol, nmain);
+        };
+        if (npol > 0 && nmain > 0) fork_join(P, pol, rest);
+        else {
+            pol();
+            rest();
+        }
     } else if (V == 0) {
         syn_dispatch_r<double, 0, CLS>(P, nrhs, fg_stride, list, npol + nmain);
     } else {
@@ -1079,6 +1088,8 @@ template <int CLS>
 int leg_adj_cls(Plan &P, bool fp32, int rhs, const int *list, int npol, int nmain, const uint8_t *live, int rb0,
                 int nrb)
 {
+    // the near-polar blocks first, then the others (in order: side by side the two launches took
+    // longer than one after the other)
     const AdjSplit pol = adj_split(npol, 4, 1);
     int n = 0;
     if (fp32) {
