@@ -120,9 +120,6 @@ enum { RK_P2 = 0, RK_BF = 1, RK_BL = 2, RK_REG = 3, RING_KINDS = 9 };
 constexpr int LIVE_NRB_EXTRA = 4;
 // values keying a recorded PCG iteration (see iter_key)
 constexpr int ITER_KEY_N = 18;
-// near-polar groups per adjoint workgroup (single-wave, spread evenly): their recurrences are long
-// and few, so small workgroups keep more waves running
-constexpr int ADJ_POLAR_R = 1;
 struct RingSet {
     const int *order[RING_KINDS] = {};
     int n[RING_KINDS] = {};
@@ -197,8 +194,10 @@ struct Plan {
     int syn_R1 = 1, syn_V1 = 1, adj_R1 = 1, adj_W1 = 1, adj_L1 = 8;
     size_t part_rb_cap = 1;  // ring blocks the partial-sum buffer holds
     // FP32 plans: the 64-pair groups nearest the poles run the Legendre stages in the difference
-    // form; the adjoint covers them with adj_nrb_polar ring blocks of at most ADJ_POLAR_R groups
-    int polar_groups = 0, adj_nrb_polar = 0;
+    // form; the adjoint covers them with adj_nrb_polar single-wave ring blocks of at most adj_Rpol
+    // groups (spread evenly): 4, or 1 where blocks of four would leave the launch with too few waves
+    // for its long recurrences
+    int polar_groups = 0, adj_nrb_polar = 0, adj_Rpol = 4;
     // batched matrix-core kernels: waves (64-pair groups) per workgroup of the synthesis and the
     // adjoint; nrb_b adjoint ring blocks of bat_AW groups (the buffers hold those of bat_AW = 2)
     int bat_SW = 4, bat_AW = 4, nrb_b_cap = 0;

@@ -1945,7 +1945,7 @@ int adj_blocks_total(const Plan &P, bool live)
 
 // Legendre adjoint of d_FG (right-hand side rhs) into the partial sums, over every 64-pair group
 // (live false) or the groups of the current weights by class, reading only rings that carry weight
-// (live true).  The near-polar groups of FP32 plans form their own blocks of at most ADJ_POLAR_R in
+// (live true).  The near-polar groups of FP32 plans form their own blocks of at most adj_Rpol in
 // FP32 and in FP64 applies alike; the epilogue sums the nrb_cur blocks written.
 void launch_leg_adj(Plan &P, bool fp32, int rhs, bool live)
 {

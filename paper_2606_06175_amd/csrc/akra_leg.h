@@ -1073,13 +1073,13 @@ int adj_dispatch(Plan &P, int rhs, const int *glist, int ngl, const uint8_t *liv
 }
 
 // ring blocks the adjoint of a class list of npol near-polar and nmain other groups writes: the
-// near-polar groups form blocks of at most ADJ_POLAR_R (difference form in FP32 plans; FP64 applies
-// of such plans keep the same layout), the others blocks of the class's tuned adj_R adj_W
+// near-polar groups form blocks of at most adj_Rpol (difference form in FP32 plans; FP64 applies of
+// such plans keep the same layout), the others blocks of the class's tuned adj_R adj_W
 inline int adj_blocks(const Plan &P, int cls, int npol, int nmain)
 {
     int R, W, L;
     adj_shape_of(P, cls, R, W, L);
-    return adj_split(npol, ADJ_POLAR_R, 1).q + adj_split(nmain, R, W).q;
+    return adj_split(npol, P.adj_Rpol, 1).q + adj_split(nmain, R, W).q;
 }
 
 // Legendre adjoint of right-hand side rhs over list[0 .. npol + nmain) of class CLS into ring blocks
@@ -1090,13 +1090,13 @@ int leg_adj_cls(Plan &P, bool fp32, int rhs, const int *list, int npol, int nmai
 {
     // the near-polar blocks first, then the others (in order: side by side the two launches took
     // longer than one after the other)
-    const AdjSplit pol = adj_split(npol, ADJ_POLAR_R, 1);
+    const AdjSplit pol = adj_split(npol, P.adj_Rpol, 1);
     int n = 0;
     if (fp32) {
-        n += adj_launch_even<float, ADJ_POLAR_R, 4, 1, CLS>(P, rhs, list, npol, pol, live, rb0, nrb);
+        n += adj_launch_even<float, 4, 4, 1, CLS>(P, rhs, list, npol, pol, live, rb0, nrb);
         n += adj_dispatch<float, CLS>(P, rhs, list + npol, nmain, live, rb0 + n, nrb);
     } else {
-        n += adj_launch_even<double, ADJ_POLAR_R, 4, 0, CLS>(P, rhs, list, npol, pol, live, rb0, nrb);
+        n += adj_launch_even<double, 4, 4, 0, CLS>(P, rhs, list, npol, pol, live, rb0, nrb);
         n += adj_dispatch<double, CLS>(P, rhs, list + npol, nmain, live, rb0 + n, nrb);
     }
     return n;

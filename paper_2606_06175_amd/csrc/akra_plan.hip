@@ -227,7 +227,7 @@ static void compute_work(Plan &P)
         all += (int64_t)np * (lmax - std::max(m, 2) + 1);
         const int *e = P.h_entl.data() + (size_t)m * ng;
         syn += seg(e, 0, gp, 1) + seg(e, gp, ng, P.syn_R);
-        adj += seg_adj(e, 0, gp, ADJ_POLAR_R, 1) + seg_adj(e, gp, ng, P.adj_R, P.adj_W);
+        adj += seg_adj(e, 0, gp, P.adj_Rpol, 1) + seg_adj(e, gp, ng, P.adj_R, P.adj_W);
         bat += seg(e, 0, ng, 1);
     }
     P.work[0] = all;
@@ -316,7 +316,7 @@ static void compute_work_live(Plan &P)
             const int npol = G.npol[c], nmain = G.nmain[c];
             const bool two = c == GCLS_BOTH;
             const int64_t s = seg(e, gl, npol, 1) + seg(e, gl + npol, nmain, two ? P.syn_R : P.syn_R1);
-            const int64_t a = seg_adj(e, gl, npol, ADJ_POLAR_R, 1) + seg_adj(e, gl + npol, nmain, two ? P.adj_R : P.adj_R1,
+            const int64_t a = seg_adj(e, gl, npol, P.adj_Rpol, 1) + seg_adj(e, gl + npol, nmain, two ? P.adj_R : P.adj_R1,
                                                                  two ? P.adj_W : P.adj_W1);
             w[c == GCLS_BOTH ? 0 : 1] += s;
             w[c == GCLS_BOTH ? 2 : 3] += a;
@@ -561,7 +561,10 @@ static akra_status create(int nside, int lmax, int nrhs, int prec, void *stream,
         int g = 0;
         while (g < P->ng64 && std::acos(P->h_rings[64 * g].z) < theta_c) ++g;
         P->polar_groups = std::min(P->ng64, (g + 3) / 4 * 4);
-        P->adj_nrb_polar = (P->polar_groups + ADJ_POLAR_R - 1) / ADJ_POLAR_R;
+        // blocks of four need some 8192 waves (8 per SIMD) to fill the device; fewer, and each wave's
+        // long difference-form recurrence leaves the launch latency-bound: then one group per block
+        P->adj_Rpol = (int64_t)((P->polar_groups + 3) / 4) * (lmax + 1) >= 8192 ? 4 : 1;
+        P->adj_nrb_polar = (P->polar_groups + P->adj_Rpol - 1) / P->adj_Rpol;
     }
 
     // Legendre launch shapes

@@ -109,7 +109,7 @@ def _time_stages(plan, stages, steps):
     return sum(st[s][0] / max(st[s][1], 1) for s in stages)
 
 
-def pick_synth(syn_sweep, tol=0.01):
+def pick_synth(syn_sweep, tol=0.02):
     """The synthesis shape of a sweep {"v,r": ms}: among the shapes within tol of the fastest, the
     one with the fewest ring pairs per lane (then the lower variant).  The tuning masks are not the
     user's footprint: fewer pairs per lane keep the entry-degree spread of a wave small on any
