@@ -1653,7 +1653,7 @@ constexpr int ABL = 32;  // degrees per chunk: the rows of the MFMA
 constexpr int ABS = 33;  // LDS stride of one pair's 32 rows (bank-conflict-free writes)
 
 template <int F, int AW>
-__global__ __launch_bounds__(64 * AW) void k_leg_adj_b(const float2 *__restrict__ FG, int64_t fg_stride,
+__global__ __launch_bounds__(64 * AW) __attribute__((amdgpu_waves_per_eu(2))) void k_leg_adj_b(const float2 *__restrict__ FG, int64_t fg_stride,
                                                         const typename CoefB<F>::type *__restrict__ coef,
                                                         const Ent64 *__restrict__ ent, const int *__restrict__ entk,
                                                         const int *__restrict__ entl, int ng64,
@@ -1664,6 +1664,7 @@ __global__ __launch_bounds__(64 * AW) void k_leg_adj_b(const float2 *__restrict_
                                                         int nrbl, int nrb)
 {
     __shared__ float lam[AW][2][64 * ABS];  // per wave: lambda+ and lambda- of its 64 pairs x 32 rows
+    __shared__ float red[8 * AW * 64];      // the cross-wave sum, eight output registers at a time
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     int m, rbl;
@@ -1719,56 +1720,88 @@ __global__ __launch_bounds__(64 * AW) void k_leg_adj_b(const float2 *__restrict_
     const_as<C> *cp = uniform_ptr(coef + base);
     float *lp = &lam[wave][0][lane * ABS], *lmn = &lam[wave][1][lane * ABS];
     const float *ap = &lam[wave][0][(lane >> 5) * ABS + (lane & 31)], *am = &lam[wave][1][(lane >> 5) * ABS + (lane & 31)];
+    // the wave's recurrence covers the chunk starting at lx (zero before the wave's entry, for lanes
+    // still in the scaled range and past lmax)
+    auto is_active = [&](int lx) { return lx <= lmax && e <= lx + ABL - 1 && e <= lmax; };
+    // rows t8 .. t8 + 7 of the chunk at lx into the wave's LDS rows (entry degrees are l0 + 8 q and
+    // chunks start at l0 + 32 j, so an entry falls on a block of 8)
+    auto rows8 = [&](int lx, int t8, auto &&after) {
+        const int lb = lx + t8;
+        if (lb == e) {
+            if (valid) load_entry<float, F>(ent, entk, (int64_t)m * npairs + p, c2, p2, cm, pm, k);
+            ramp = wave_any(k < 0);
+        }
+        if (lb < e || lb > lmax) {
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                lp[t8 + t] = lmn[t8 + t] = 0.f;
+                after(t);
+            }
+            return;
+        }
+        C cc[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) cc[t] = ld_coef(cp + lb + t);  // padded past lmax
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const bool live = k == 0 && lb + t <= lmax;
+            lp[t8 + t] = live ? c2 : 0.f;
+            lmn[t8 + t] = live ? cm : 0.f;
+            rstep(cc[t], x, c2, p2, cm, pm);
+            after(t);
+            if (ramp && (t & 3) == 3) {
+                // every four steps (the growth over four steps stays far from overflow)
+                if (k < 0 && fmaxf(fabsf(c2), fabsf(cm)) > scale_hi<float>()) {
+                    const float d = scale_down<float>();
+                    c2 *= d;
+                    p2 *= d;
+                    cm *= d;
+                    pm *= d;
+                    k += 1;
+                }
+                ramp = wave_any(k < 0);
+            }
+        }
+    };
+    // Software pipeline over chunks: the A operands of chunk lc are read from LDS into registers, then
+    // the recurrence writes the rows of the next chunk into the same LDS rows while the matrix cores
+    // contract chunk lc (eight rows, then the sixteen products of eight pair-pairs).  A wave reads and
+    // writes only its own rows, and its LDS accesses run in program order, so the reads return the
+    // rows of chunk lc.
     const int lstart = l0 + ((ls - l0) / ABL) * ABL;
+    if (is_active(lstart)) {
+#pragma unroll
+        for (int t8 = 0; t8 < ABL; t8 += 8) rows8(lstart, t8, [](int) {});
+    }
     for (int lc = lstart; lc <= lmax; lc += ABL) {
-        // recurrence values of the chunk's rows (zero before the wave's entry, for lanes still in the
-        // scaled range and past lmax)
-        const bool active = e <= lc + ABL - 1 && e <= lmax;
+        const bool act = is_active(lc), actn = is_active(lc + ABL);
+        wg_lds_sync<1>();
+        float a[32], b[32];
+        if (act) {
+#pragma unroll
+            for (int kk = 0; kk < 32; ++kk) {
+                a[kk] = ap[2 * kk * ABS];
+                b[kk] = am[2 * kk * ABS];
+            }
+        }
+        wg_lds_sync<1>();
         v16f Dp, Dm;
 #pragma unroll
         for (int r = 0; r < 16; ++r) Dp[r] = Dm[r] = 0.f;
-        if (active) {
-            // rows in blocks of 8: entry degrees are l0 + 8 q and chunks start at l0 + 32 j
-            for (int t8 = 0; t8 < ABL; t8 += 8) {
-                const int lb = lc + t8;
-                if (lb == e) {
-                    if (valid) load_entry<float, F>(ent, entk, (int64_t)m * npairs + p, c2, p2, cm, pm, k);
-                    ramp = wave_any(k < 0);
-                }
-                if (lb < e || lb > lmax) {
+        // the products of pair-pair kk follow row kk % 8 of block kk / 8 of the next chunk
+        auto mm = [&](int kk) {
+            Dp = __builtin_amdgcn_mfma_f32_32x32x2f32(a[kk], Bp[kk], Dp, 0, 0, 0);
+            Dm = __builtin_amdgcn_mfma_f32_32x32x2f32(b[kk], Bm[kk], Dm, 0, 0, 0);
+        };
+        if (act && actn) {
 #pragma unroll
-                    for (int t = 0; t < 8; ++t) lp[t8 + t] = lmn[t8 + t] = 0.f;
-                    continue;
-                }
-                C cc[8];
+            for (int t8 = 0; t8 < ABL; t8 += 8) rows8(lc + ABL, t8, [&](int t) { mm(t8 + t); });
+        } else if (act) {
 #pragma unroll
-                for (int t = 0; t < 8; ++t) cc[t] = ld_coef(cp + lb + t);  // padded past lmax
+            for (int kk = 0; kk < 32; ++kk) mm(kk);
+        } else if (actn) {
 #pragma unroll
-                for (int t = 0; t < 8; ++t) {
-                    const bool live = k == 0 && lb + t <= lmax;
-                    lp[t8 + t] = live ? c2 : 0.f;
-                    lmn[t8 + t] = live ? cm : 0.f;
-                    rstep(cc[t], x, c2, p2, cm, pm);
-                    if (ramp && (t & 3) == 3) {
-                        // every four steps (the growth over four steps stays far from overflow)
-                        if (k < 0 && fmaxf(fabsf(c2), fabsf(cm)) > scale_hi<float>()) {
-                            const float d = scale_down<float>();
-                            c2 *= d;
-                            p2 *= d;
-                            cm *= d;
-                            pm *= d;
-                            k += 1;
-                        }
-                        ramp = wave_any(k < 0);
-                    }
-                }
-            }
-            wg_lds_sync<1>();  // the wave reads only its own rows
-#pragma unroll
-            for (int kk = 0; kk < 32; ++kk) {
-                Dp = __builtin_amdgcn_mfma_f32_32x32x2f32(ap[2 * kk * ABS], Bp[kk], Dp, 0, 0, 0);
-                Dm = __builtin_amdgcn_mfma_f32_32x32x2f32(am[2 * kk * ABS], Bm[kk], Dm, 0, 0, 0);
-            }
+            for (int t8 = 0; t8 < ABL; t8 += 8) rows8(lc + ABL, t8, [](int) {});
         }
         // D row of register r in lane l: 8 (r / 4) + 4 (l / 32) + r % 4, column l % 32
         float o[16];
@@ -1779,23 +1812,24 @@ __global__ __launch_bounds__(64 * AW) void k_leg_adj_b(const float2 *__restrict_
             const float t2 = dpp_mov<0x4E>(Dm[r]);  // D- of column j ^ 2
             o[r] = c < 2 ? fmaf(s, t2, Dp[r]) : fmaf(s, Dp[r], t2);
         }
-        // sum over the block's waves in LDS (the rows of lam are free once every wave has multiplied)
-        __syncthreads();
-        float *red = &lam[0][0][0];
+        // sum over the block's waves in LDS, eight registers at a time
 #pragma unroll
-        for (int r = 0; r < 16; ++r) red[(wave * 16 + r) * 64 + lane] = o[r];
-        __syncthreads();
+        for (int h = 0; h < 16; h += 8) {
+            __syncthreads();
 #pragma unroll
-        for (int u = 0; u < 16 / AW; ++u) {
-            const int r = wave * (16 / AW) + u;  // this thread's register index, lane as it was
-            float sum = 0.f;
+            for (int r8 = 0; r8 < 8; ++r8) red[(wave * 8 + r8) * 64 + lane] = o[h + r8];
+            __syncthreads();
 #pragma unroll
-            for (int w = 0; w < AW; ++w) sum += red[(w * 16 + r) * 64 + lane];
-            const int i = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3), l = lc + i;
-            if (l <= lmax && rhs < nrhs)
-                part[(((int64_t)(j >> 2) * nrb + rb) * nalm + base + l) * 4 + c] = sum;
+            for (int u = 0; u < 8 / AW; ++u) {
+                const int r = h + wave * (8 / AW) + u;  // this thread's register index, lane as it was
+                float sum = 0.f;
+#pragma unroll
+                for (int w = 0; w < AW; ++w) sum += red[(w * 8 + r - h) * 64 + lane];
+                const int i = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3), l = lc + i;
+                if (l <= lmax && rhs < nrhs)
+                    part[(((int64_t)(j >> 2) * nrb + rb) * nalm + base + l) * 4 + c] = sum;
+            }
         }
-        __syncthreads();
     }
 }
 
