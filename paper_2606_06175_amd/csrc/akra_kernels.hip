@@ -1560,7 +1560,12 @@ __global__ __launch_bounds__(64 * SW) __attribute__((amdgpu_waves_per_eu(2))) vo
     using C = typename CoefB<F>::type;
     const_as<C> *cp = uniform_ptr(coef + base);
     const float *bl = brec + base * (NBR * 4) + i;  // column i of the group's records
-    for (int l = ls; l <= lmax; l += 4) {
+    // four degrees from l: records and recurrence values, then the eight products.  RAMP: some lane is
+    // still in the scaled range (its values count as zero until its exponent reaches zero, and the
+    // exponents are checked once per four steps); once no lane is, none returns to it, and the loop
+    // without the selects and the checks takes over.
+    auto four = [&](int l, auto ramp_tag) {
+        constexpr bool RAMP = decltype(ramp_tag)::value;
         // B rows l + 2h (even offsets) and l + 1 + 2h (odd), zero past lmax
         const int re = l + 2 * h, ro = re + 1;
         const float be = re <= lmax ? bl[(int64_t)re * (NBR * 4)] : 0.f;
@@ -1568,7 +1573,7 @@ __global__ __launch_bounds__(64 * SW) __attribute__((amdgpu_waves_per_eu(2))) vo
         float v2[4], vm[4];
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-            const bool live = k == 0;
+            const bool live = !RAMP || k == 0;
             v2[t] = live ? c2 : 0.f;
             vm[t] = live ? cm : 0.f;
             rstep(ld_coef(cp + l + t), x, c2, p2, cm, pm);
@@ -1585,7 +1590,7 @@ __global__ __launch_bounds__(64 * SW) __attribute__((amdgpu_waves_per_eu(2))) vo
             Dme[s2] = __builtin_amdgcn_mfma_f32_32x32x2f32(vm[2 * s2], be, Dme[s2], 0, 0, 0);
             Dmo[s2] = __builtin_amdgcn_mfma_f32_32x32x2f32(vm[2 * s2 + 1], bo, Dmo[s2], 0, 0, 0);
         }
-        if (ramp) {
+        if constexpr (RAMP) {
             // once per four steps (the growth over four steps stays far from overflow)
             if (k < 0 && fmaxf(fabsf(c2), fabsf(cm)) > scale_hi<float>()) {
                 const float d = scale_down<float>();
@@ -1597,7 +1602,10 @@ __global__ __launch_bounds__(64 * SW) __attribute__((amdgpu_waves_per_eu(2))) vo
             }
             ramp = wave_any(k < 0);
         }
-    }
+    };
+    int l = ls;
+    for (; l <= lmax && ramp; l += 4) four(l, std::true_type{});
+    for (; l <= lmax; l += 4) four(l, std::false_type{});
     // F of the north and south ring of every (pair, rhs): quad sums over c, written by lane c = 0
     const bool odd0 = ((l0 + m) & 1) != 0;  // entries are l0 + 8 q: D2e holds degrees of parity l0 + m
     const int c = i & 3, rl = i >> 2, rhs = q * NBR + rl;
@@ -1742,6 +1750,17 @@ __global__ __launch_bounds__(64 * AW) __attribute__((amdgpu_waves_per_eu(2))) vo
         C cc[8];
 #pragma unroll
         for (int t = 0; t < 8; ++t) cc[t] = ld_coef(cp + lb + t);  // padded past lmax
+        if (!ramp && lb + 7 <= lmax) {
+            // every lane out of the scaled range and every row in range: no selects, no checks
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                lp[t8 + t] = c2;
+                lmn[t8 + t] = cm;
+                rstep(cc[t], x, c2, p2, cm, pm);
+                after(t);
+            }
+            return;
+        }
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
             const bool live = k == 0 && lb + t <= lmax;
