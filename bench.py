@@ -55,7 +55,7 @@ TRAFFIC = {
     # FETCH 6.1001e5 KiB x 2.0 + WRITE 8.3224e5 KiB, one-sided k_leg_adj<double, 7, 1, 8, 0, 2>
     # FETCH 6.0235e5 KiB x 2.0 + WRITE 9.8547e5 KiB (means of the two dispatches of each run)
     "leg_adj": {"bytes": 4.344e9, "workload": (2048, 4096), "shapes": ((0, 1, 5, 1, 8), (0, 2, 8, 1, 8)),
-                "sources_sha256": "8112968f7493e75a1a8f61ccc08a33fc29bff98e23d0ce2f429d32df9ee92599"},
+                "sources_sha256": "dad28f34f7f07a6d8186e7387dbe4b6f9f9c1495755f63a184261ce44d0388b1"},
 }
 LEG_SOURCES = ("akra_leg.h", "akra_leg_both.hip", "akra_leg_north.hip", "akra_leg_south.hip", "akra_kernels.hip")
 
