@@ -591,6 +591,9 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only time a plain device-to-device copy of MIB MiB (4 launches) and exit; the HBM "
                          "counters of that copy calibrate the counters of the operator's kernels")
+    ap.add_argument("--mfma-probe", action="store_true",
+                    help="print the sustained v_mfma_f32_32x32x2_f32 rate with 0, 4 or 8 pairs of FP32 FMAs "
+                         "between the products (akra_mfma_rate) and exit")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -610,6 +613,13 @@ def main():
     if args.lds_rings:
         from paper_2606_06175_amd import akra
         akra.set_ring_register_engine(False)
+    if args.mfma_probe:
+        from paper_2606_06175_amd.akra import mfma_rate
+        rows = [{"chains": k, "fma_pairs_between_products": v, "waves_per_simd": w,
+                 "TFLOPs": mfma_rate(k, v, w)}
+                for k, v, w in ((1, 0, 1), (2, 0, 1), (4, 0, 1), (4, 0, 2), (2, 4, 1), (2, 8, 1), (4, 4, 1), (4, 8, 2))]
+        print(json.dumps({"mfma_probe": "v_mfma_f32_32x32x2_f32", "peak": 157.3, "rows": rows}), flush=True)
+        return
     if args.copy_calibration:
         n = args.copy_calibration << 20
         src = torch.ones(n // 8, dtype=torch.float64, device=dev)

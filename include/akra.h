@@ -340,6 +340,18 @@ akra_status akra_plan_set_timing(akra_plan plan, int on);
  */
 akra_status akra_fma_rate(int precision, double *tflops);
 /*
+ * Sustained rate of the matrix-core product v_mfma_f32_32x32x2_f32 (4096 flop each) on the current
+ * device in TFLOP/s, written to *tflops (HOST): chains (1, 2 or 4) independent 32 x 32 FP32
+ * accumulators per wave, valu (0, 4 or 8) pairs of plain FP32 FMAs on two other chains of each lane
+ * after every product, waves (1 or 2) single-wave workgroups per SIMD on every compute unit; the
+ * fastest of 6 launches, timed with HIP events on a private stream.  The rate counts the products'
+ * flops only.  It measures how far VALU work between products slows the matrix cores, the bound of
+ * the batched Legendre kernels, whose recurrence is such work.  Allocates and frees a scratch buffer
+ * of 4 B per thread of the grid; synchronises its own stream only.  Errors: AKRA_ERR_ARG (null
+ * output, a value outside the lists), AKRA_ERR_HIP.
+ */
+akra_status akra_mfma_rate(int chains, int valu, int waves, double *tflops);
+/*
  * Ring-stage kernel choice of plans created afterwards (process-wide, not thread-safe against
  * concurrent akra_plan_create).  A ring whose length N is not a power of two is transformed whole by
  * Bluestein when its convolution length (the power of two M >= 2N - 1) is at most maxm, else as two

@@ -83,6 +83,7 @@ def lib():
                                                  ctypes.c_int]
     L.akra_plan_get_tuning_one_sided.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
     L.akra_fma_rate.argtypes = [ctypes.c_int, dp]
+    L.akra_mfma_rate.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, dp]
     L.akra_plan_set_tuning_batched.argtypes = [vp, ctypes.c_int, ctypes.c_int]
     L.akra_plan_get_tuning_batched.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
     L.akra_plan_work.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
@@ -124,7 +125,7 @@ def lib():
               "akra_plan_stage_times", "akra_plan_set_tuning", "akra_plan_get_tuning", "akra_plan_work",
               "akra_plan_set_tuning_batched", "akra_plan_get_tuning_batched",
               "akra_plan_work_batched", "akra_plan_work_weighted", "akra_plan_set_skip_unweighted",
-              "akra_plan_set_tuning_one_sided", "akra_plan_get_tuning_one_sided", "akra_fma_rate",
+              "akra_plan_set_tuning_one_sided", "akra_plan_get_tuning_one_sided", "akra_fma_rate", "akra_mfma_rate",
               "akra_cg_solve_vjp", "akra_cg_solve_cond_b", "akra_set_ring_whole_maxm", "akra_set_ring_register_engine", "akra_unmasked_index",
               "akra_shuffle_shear", "akra_alm_spectra", "akra_alm_spectra_noalloc", "akra_noise_work_size", "akra_noise_spectra", "akra_ang2pix",
               "akra_pixelize_work_size", "akra_pixelize", "akra_flat_plan_create", "akra_flat_synth",
@@ -149,6 +150,14 @@ def fma_rate(precision="fp64"):
     """Sustained plain FMA rate of the current device in TFLOP/s (akra_fma_rate)."""
     v = ctypes.c_double()
     _check(lib().akra_fma_rate(PRECISIONS[precision], ctypes.byref(v)))
+    return v.value
+
+
+def mfma_rate(chains=4, valu=0, waves=2):
+    """Sustained v_mfma_f32_32x32x2_f32 rate in TFLOP/s with valu pairs of FP32 FMAs between the
+    products (akra_mfma_rate)."""
+    v = ctypes.c_double()
+    _check(lib().akra_mfma_rate(int(chains), int(valu), int(waves), ctypes.byref(v)))
     return v.value
 
 

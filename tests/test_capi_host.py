@@ -114,3 +114,11 @@ def test_fma_rate_rejects_bad_arguments_before_any_hip_call(L):
     assert L.akra_fma_rate(2, ctypes.byref(v)) == akra.AKRA_ERR_ARG
     assert "precision" in L.akra_last_error().decode()
     assert L.akra_fma_rate(0, None) == akra.AKRA_ERR_ARG
+
+
+def test_mfma_rate_rejects_bad_arguments_before_any_hip_call(L):
+    v = ctypes.c_double()
+    for chains, valu, waves in ((3, 0, 1), (4, 2, 1), (4, 0, 3), (0, 0, 1)):
+        assert L.akra_mfma_rate(chains, valu, waves, ctypes.byref(v)) == akra.AKRA_ERR_ARG
+    assert "chains" in L.akra_last_error().decode()
+    assert L.akra_mfma_rate(4, 0, 2, None) == akra.AKRA_ERR_ARG
